@@ -1,0 +1,241 @@
+"""FP64 CPU oracle (test infrastructure only).
+
+Plain, slow reference for the Gaussian-splatting hot path; see the header of
+``gs_oracle.c`` for what each routine follows in the paper.  Only the tests,
+the smoke check and the benchmark's CPU-baseline leg may import this package.
+It shares no code with the HIP library and does not import it.
+
+Parity unpinned: none of the routines below; each is pinned by the
+``tests/test_oracle_*.py`` suite against closed forms, brute force or
+finite differences.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "gs_oracle.c")
+_LIB = os.path.join(_HERE, "libgs_oracle.so")
+_lib = None
+
+DEFAULT_MARGINS = (2e-5, 2e-5, 1e-5, 1e-5)  # dq, de, dT, ddom
+
+
+def build(force: bool = True) -> str:
+    """Compile the oracle with gcc (plain C, FP64, no contraction)."""
+    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+        tmp = _LIB + ".tmp"
+        subprocess.check_call(["gcc", "-O2", "-std=c11", "-ffp-contract=off", "-fno-fast-math",
+                               "-fPIC", "-shared", "-o", tmp, _SRC, "-lm", "-lpthread"])
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+            build()
+        _lib = ctypes.CDLL(_LIB)
+        _lib.oc_bin_f32.restype = ctypes.c_int64
+    return _lib
+
+
+def _p(a):
+    return None if a is None else a.ctypes.data_as(ctypes.c_void_p)
+
+
+def _f32(a):
+    return np.ascontiguousarray(a, np.float32)
+
+
+def _f64(a):
+    return np.ascontiguousarray(a, np.float64)
+
+
+def cam_row(cam) -> np.ndarray:
+    return np.ascontiguousarray(cam.as_row() if hasattr(cam, "as_row") else cam, np.float64)
+
+
+def sh_basis(degree: int, direction) -> np.ndarray:
+    d = _f64(direction)
+    Y = np.zeros((degree + 1) ** 2)
+    lib().oc_sh_basis(ctypes.c_int(degree), _p(d), _p(Y))
+    return Y
+
+
+def project(scene, cam, levels: bool = False) -> dict:
+    """FP64 projection of every Gaussian for one camera."""
+    n = scene.n
+    out = dict(mean2d=np.zeros((n, 2)), cov2d=np.zeros((n, 3)), conic=np.zeros((n, 3)),
+               depth=np.zeros(n), opacity=np.zeros(n), color=np.zeros((n, 3)),
+               radius=np.zeros(n, np.int32), visible=np.zeros(n, np.uint8))
+    L = 0
+    lo = lc = None
+    if levels and scene.qbound is not None:
+        L = (scene.lvl_opacity_logits.shape[0] if scene.lvl_opacity_logits is not None
+             else int(scene.qbound.max()))
+        out["lvl_opacity"] = lo = np.zeros((L, n))
+        out["lvl_color"] = lc = np.zeros((L, n, 3))
+    lvl_logits = None if scene.lvl_opacity_logits is None else _f64(scene.lvl_opacity_logits)
+    lvl_dc = None if scene.lvl_sh_dc is None else _f64(scene.lvl_sh_dc)
+    args = [_f64(scene.means), _f64(scene.log_scales), _f64(scene.quats),
+            _f64(scene.opacity_logits), _f64(scene.sh)]
+    crow = cam_row(cam)
+    lib().oc_project(ctypes.c_int(n), ctypes.c_int(scene.sh_degree), *[_p(a) for a in args],
+                     _p(crow), _p(out["mean2d"]), _p(out["cov2d"]), _p(out["conic"]),
+                     _p(out["depth"]), _p(out["opacity"]), _p(out["color"]), _p(out["radius"]),
+                     _p(out["visible"]), ctypes.c_int(L), _p(lvl_logits if L else None),
+                     _p(lvl_dc if L else None), _p(lo), _p(lc))
+    return out
+
+
+def bin_f32(mean2d, radius, depth, widths, heights, tile: int,
+            tile_level_lo=None, qbound=None) -> dict:
+    """Stage-wise binning on float32 inputs ([V][n] arrays)."""
+    mean2d = _f32(mean2d)
+    radius = np.ascontiguousarray(radius, np.int32)
+    depth = _f32(depth)
+    V = len(widths)
+    n = radius.size // V
+    widths = np.ascontiguousarray(widths, np.int32)
+    heights = np.ascontiguousarray(heights, np.int32)
+    tll = None if tile_level_lo is None else np.ascontiguousarray(tile_level_lo, np.uint8)
+    qb = None if qbound is None else np.ascontiguousarray(qbound, np.uint8)
+    hits = np.zeros(V * n, np.uint32)
+    total = lib().oc_bin_f32(V, n, _p(mean2d), _p(radius), _p(depth), _p(widths), _p(heights),
+                             tile, _p(tll), _p(qb), _p(hits), None, None, None, ctypes.c_int64(0))
+    tiles = int(sum(((w + tile - 1) // tile) * ((h + tile - 1) // tile)
+                    for w, h in zip(widths, heights)))
+    keys = np.zeros(max(total, 1), np.uint64)
+    vals = np.zeros(max(total, 1), np.uint32)
+    ranges = np.zeros((tiles, 2), np.uint32)
+    got = lib().oc_bin_f32(V, n, _p(mean2d), _p(radius), _p(depth), _p(widths), _p(heights),
+                           tile, _p(tll), _p(qb), _p(hits), _p(keys), _p(vals), _p(ranges),
+                           ctypes.c_int64(total))
+    assert got == total
+    return dict(hits=hits.reshape(V, n), keys=keys[:total], vals=vals[:total], ranges=ranges,
+                num_keys=int(total))
+
+
+def composite(proj: dict, W: int, H: int, bg=(0.0, 0.0, 0.0), pixels=None,
+              margins=DEFAULT_MARGINS, max_leaves: int = 64, nthreads: int = 0,
+              qbound=None, pix_lo=None, pix_w=None, levels: bool = False) -> dict:
+    """Per-pixel compositing (Eq. 1a) of projected splats given as float64
+    arrays (mean2d, conic, depth, opacity, color, radius).  ``pixels`` is an
+    (m, 2) array of (x, y) or None for the full image (returned as (H, W, 3))."""
+    n = proj["depth"].shape[0]
+    m2, cn, dp, op, cl = (_f64(proj[k]) for k in ("mean2d", "conic", "depth", "opacity", "color"))
+    rad = np.ascontiguousarray(proj["radius"], np.int32)
+    lo = lc = None
+    if levels:
+        lo = _f64(proj["lvl_opacity"]) if proj.get("lvl_opacity") is not None else None
+        lc = _f64(proj["lvl_color"]) if proj.get("lvl_color") is not None else None
+    px = None if pixels is None else np.ascontiguousarray(pixels, np.int32)
+    npx = W * H if px is None else px.shape[0]
+    out = dict(rgb=np.zeros((npx, 3)), rgb_min=np.zeros((npx, 3)), rgb_max=np.zeros((npx, 3)),
+               T=np.zeros(npx), last_id=np.zeros(npx, np.int32), dom_id=np.zeros(npx, np.int32),
+               amb=np.zeros(npx, np.int32), n_blend=np.zeros(npx, np.int32),
+               last_set=np.zeros((npx, 4), np.int32), dom_set=np.zeros((npx, 4), np.int32))
+    bgv = _f64(bg)
+    mg = _f64(margins)
+    qb = None if qbound is None else np.ascontiguousarray(qbound, np.uint8)
+    plo = None if pix_lo is None else np.ascontiguousarray(pix_lo, np.uint8)
+    pw = None if pix_w is None else _f64(pix_w)
+    lib().oc_composite(ctypes.c_int(n), _p(m2), _p(cn), _p(dp), _p(op), _p(cl), _p(rad),
+                       ctypes.c_int(W), ctypes.c_int(H), _p(bgv), _p(qb), _p(lo), _p(lc),
+                       _p(plo), _p(pw), ctypes.c_int(npx), _p(px), _p(mg),
+                       ctypes.c_int(max_leaves),
+                       _p(out["rgb"]), _p(out["rgb_min"]), _p(out["rgb_max"]), _p(out["T"]),
+                       _p(out["last_id"]), _p(out["dom_id"]), _p(out["amb"]), _p(out["n_blend"]),
+                       _p(out["last_set"]), _p(out["dom_set"]), ctypes.c_int(nthreads))
+    if px is None:
+        for k in ("rgb", "rgb_min", "rgb_max"):
+            out[k] = out[k].reshape(H, W, 3)
+        for k in ("T", "last_id", "dom_id", "amb", "n_blend"):
+            out[k] = out[k].reshape(H, W)
+        for k in ("last_set", "dom_set"):
+            out[k] = out[k].reshape(H, W, 4)
+    return out
+
+
+def render(scene, cam, bg=(0.0, 0.0, 0.0), pixels=None, **kw) -> dict:
+    """O1: full FP64 render (projection then compositing)."""
+    pr = project(scene, cam)
+    out = composite(pr, int(cam.width), int(cam.height), bg=bg, pixels=pixels, **kw)
+    out["proj"] = pr
+    return out
+
+
+def fovea(cam, fov, n_levels: int, tile: int, eps: float = 1e-3) -> dict:
+    W, H = int(cam.width), int(cam.height)
+    tiles = ((W + tile - 1) // tile) * ((H + tile - 1) // tile)
+    out = dict(pix_lo=np.zeros(W * H, np.uint8), pix_w=np.zeros(W * H), ecc=np.zeros(W * H),
+               pix_amb=np.zeros(W * H, np.uint8), tile_lo=np.zeros(tiles, np.uint8),
+               tile_hi=np.zeros(tiles, np.uint8), tile_amb=np.zeros(tiles, np.uint8))
+    crow = cam_row(cam)
+    frow = _f64(fov.as_row() if hasattr(fov, "as_row") else fov)
+    lib().oc_fovea(_p(crow), _p(frow), ctypes.c_int(n_levels), ctypes.c_int(tile),
+                   ctypes.c_double(eps), _p(out["pix_lo"]), _p(out["pix_w"]), _p(out["ecc"]),
+                   _p(out["pix_amb"]), _p(out["tile_lo"]), _p(out["tile_hi"]), _p(out["tile_amb"]))
+    return out
+
+
+def composite_bwd(proj: dict, W: int, H: int, dL_dimg, bg=(0.0, 0.0, 0.0)) -> dict:
+    """Reverse of the compositing: per-Gaussian d mean2d, d conic, d opacity,
+    d colour for dL/dI given as (3, H, W)."""
+    n = proj["depth"].shape[0]
+    m2, cn, dp, op, cl = (_f64(proj[k]) for k in ("mean2d", "conic", "depth", "opacity", "color"))
+    rad = np.ascontiguousarray(proj["radius"], np.int32)
+    g = _f64(dL_dimg)
+    out = dict(mean2d=np.zeros((n, 2)), conic=np.zeros((n, 3)), opacity=np.zeros(n),
+               color=np.zeros((n, 3)))
+    bgv = _f64(bg)
+    lib().oc_composite_bwd(ctypes.c_int(n), _p(m2), _p(cn), _p(dp), _p(op), _p(cl), _p(rad),
+                           ctypes.c_int(W), ctypes.c_int(H), _p(bgv), _p(g),
+                           _p(out["mean2d"]), _p(out["conic"]), _p(out["opacity"]),
+                           _p(out["color"]))
+    return out
+
+
+def project_bwd(scene, cam, g: dict, acc: dict | None = None) -> dict:
+    """Reverse of the projection for one camera; adds into ``acc``."""
+    n = scene.n
+    K = (scene.sh_degree + 1) ** 2
+    if acc is None:
+        acc = dict(means=np.zeros((n, 3)), log_scales=np.zeros((n, 3)), quats=np.zeros((n, 4)),
+                   opacity_logits=np.zeros(n), sh=np.zeros((n, K, 3)))
+    args = [_f64(scene.means), _f64(scene.log_scales), _f64(scene.quats),
+            _f64(scene.opacity_logits), _f64(scene.sh)]
+    crow = cam_row(cam)
+    gm, gc, go, gcl = (_f64(g[k]) for k in ("mean2d", "conic", "opacity", "color"))
+    lib().oc_project_bwd(ctypes.c_int(n), ctypes.c_int(scene.sh_degree), *[_p(a) for a in args],
+                         _p(crow), _p(gm), _p(gc), _p(go), _p(gcl),
+                         _p(acc["means"]), _p(acc["log_scales"]), _p(acc["quats"]),
+                         _p(acc["opacity_logits"]), _p(acc["sh"]))
+    return acc
+
+
+def reverse(scene, cams, dL_dimgs, bg=(0.0, 0.0, 0.0)) -> dict:
+    """O4: gradients of sum_v <dL_dimg_v, I_v> w.r.t. all parameters."""
+    acc = None
+    for cam, g in zip(cams, dL_dimgs):
+        pr = project(scene, cam)
+        gs = composite_bwd(pr, int(cam.width), int(cam.height), g, bg)
+        acc = project_bwd(scene, cam, gs, acc)
+    return acc
+
+
+def splats_to_proj(splats: dict) -> dict:
+    """Upcast float32 splat fields (as returned by the HIP path) to the float64
+    dict the compositing routines take."""
+    return dict(mean2d=_f64(splats["mean2d"]), conic=_f64(splats["conic"]),
+                depth=_f64(splats["depth"]), opacity=_f64(splats["opacity"]),
+                color=_f64(splats["color"]),
+                radius=np.ascontiguousarray(splats["radius"], np.int32),
+                lvl_opacity=None if splats.get("lvl_opacity") is None else _f64(splats["lvl_opacity"]),
+                lvl_color=None if splats.get("lvl_color") is None else _f64(splats["lvl_color"]))
