@@ -1,0 +1,269 @@
+/*
+ * gs.h -- C ABI of the MI355X (gfx950) Gaussian-splatting rasterizer.
+ *
+ * The library renders images from 3D Gaussian points in the three stages of
+ * the point-based neural rendering pipeline (Section 2.1): projection of each
+ * ellipsoid to a screen-space ellipse with a spherical-harmonic colour
+ * (Eq. 1b, 1c), per-tile depth sorting, and per-pixel front-to-back
+ * integration (Eq. 1a).  The foveated form (Section 4.1, 4.2) renders
+ * eccentricity rings from nested point subsets with per-level opacity and DC
+ * colour and blends the rings at their borders.
+ *
+ * Conventions shared by every entry point
+ *   - All arrays named "device" are device (HBM) pointers owned by the
+ *     caller; the library never allocates, frees or retains them.  Scratch
+ *     memory comes in through `workspace` (device, 256-byte aligned, at least
+ *     gs_workspace_bytes() bytes).  No entry point allocates device memory.
+ *   - `stream` is a hipStream_t (NULL = the default stream).  Every call only
+ *     enqueues work on it and returns; there is no host synchronisation, so
+ *     every call can be captured into a HIP graph.
+ *   - Arguments are validated on the host before anything is enqueued.  On
+ *     error a negative status is returned, nothing is enqueued, and
+ *     gs_last_error() returns a message (thread-local, valid until the next
+ *     call on the same thread).
+ *   - Views: `cams_host` and `cams_dev` hold the same `n_views` cameras, on
+ *     the host (read for validation and launch sizes) and on the device
+ *     (read by kernels).  Tiles of all views form one global tile space:
+ *     view v owns tiles [off_v, off_v + tx_v * ty_v), tx_v = ceil(W_v / T),
+ *     ty_v = ceil(H_v / T), off_v = sum of the tile counts of views < v;
+ *     tile (tx, ty) of view v is global tile off_v + ty * tx_v + tx.
+ *     Pixels likewise: view v owns pixels [P_v, P_v + W_v H_v), row-major.
+ *   - Images are planar float32: view v occupies 3 * W_v * H_v floats
+ *     starting at 3 * P_v, channel-major ([3][H_v][W_v]).
+ *   - Tile size T is 8, 16 or 32.
+ */
+#ifndef GS_H
+#define GS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+    GS_OK = 0,
+    GS_ERR_INVALID = -1,     /* bad argument (null pointer, size, alignment) */
+    GS_ERR_UNSUPPORTED = -2, /* valid but unsupported (SH degree > 3, tile size) */
+    GS_ERR_CAPACITY = -3,    /* workspace too small */
+    GS_ERR_HIP = -4          /* a HIP runtime call or launch failed */
+};
+
+/* Pinhole camera, OpenCV frame (x right, y down, z forward).  A world point x
+ * maps to camera space as R x + t (R row-major).  Pixel (i, j) is sampled at
+ * its integer coordinates; fx, fy in pixels; the projection Jacobian's
+ * tangent clamp uses tan(fov_x / 2) = width / (2 fx).  Points with camera
+ * depth <= near_z are culled.  Size 76 bytes, arrays tightly packed. */
+typedef struct gs_camera {
+    int32_t width, height;
+    float fx, fy, cx, cy;
+    float R[9];
+    float t[3];
+    float near_z;
+} gs_camera;
+
+/* Scene (Section 2.1 point parameters; Section 4.2 nested subsets).  All
+ * pointers are device pointers, float32, structure of arrays:
+ *   means [n][3], log_scales [n][3] (scale = exp), quats [n][4] as
+ *   (w, x, y, z) (normalised in the kernel), opacity_logits [n]
+ *   (opacity = sigmoid), sh [n][K][3] with K = (sh_degree + 1)^2.
+ * Foveated rendering only (NULL / 0 otherwise):
+ *   qbound [n] uint8 in 1..n_levels, the quality bound m: point i is used by
+ *   levels t <= m_i;  lvl_opacity_logits [n_levels][n] and
+ *   lvl_sh_dc [n_levels][n][3], the per-level versions of opacity and DC
+ *   colour (selective multi-versioning); NULL means every level shares the
+ *   base parameter. */
+typedef struct gs_scene {
+    int32_t n;
+    int32_t sh_degree;
+    const float *means;
+    const float *log_scales;
+    const float *quats;
+    const float *opacity_logits;
+    const float *sh;
+    const uint8_t *qbound;
+    int32_t n_levels;
+    const float *lvl_opacity_logits;
+    const float *lvl_sh_dc;
+} gs_scene;
+
+/* Projected splat, one per (view, point): 48 bytes.
+ *   mean_x, mean_y   screen position (pixels)
+ *   conic_a/b/c      inverse 2D covariance [[a, b], [b, c]]
+ *   opacity, r, g, b activated opacity and colour
+ *   depth            camera-space z
+ *   radius           ceil(3 sqrt(largest eigenvalue)), 0 if culled
+ *   tiles_touched    tiles of the clipped pixel rectangle
+ *                    [ceil(x - r), floor(x + r)] x [ceil(y - r), floor(y + r)],
+ *                    computed in float32 (Comp_i of Eq. 3 before filtering) */
+typedef struct gs_splat {
+    float mean_x, mean_y;
+    float conic_a, conic_b, conic_c;
+    float opacity;
+    float r, g, b;
+    float depth;
+    int32_t radius;
+    uint32_t tiles_touched;
+} gs_splat;
+
+/* Gradient of a loss with respect to a splat's screen-space quantities
+ * (48 bytes; the three pad floats are written as zero). */
+typedef struct gs_splat_grad {
+    float mean_x, mean_y;
+    float conic_a, conic_b, conic_c;
+    float opacity;
+    float r, g, b;
+    float pad[3];
+} gs_splat_grad;
+
+/* Foveation parameters of one eye (Section 4.1, Section 6): gaze pixel, the
+ * eccentricities (degrees) where rings 2..n_levels start, and the total width
+ * (degrees) of the blend band centred on each ring start. */
+typedef struct gs_fovea {
+    float gaze_x, gaze_y;
+    float ring_deg[3];
+    float band_deg;
+} gs_fovea;
+
+/* Message for the last non-zero status on this thread ("" if none). */
+const char *gs_last_error(void);
+
+/* ABI version (bumped on any layout change). */
+int gs_version(void);
+
+/* Host helper: total tiles and pixels of the global spaces. */
+int gs_tile_count(const gs_camera *cams_host, int n_views, int tile_size,
+                  int64_t *n_tiles, int64_t *n_pixels);
+
+/* Bytes of workspace needed by gs_bin_sort / gs_rasterize_* / gs_render_*
+ * for these views, n points and a key capacity. */
+size_t gs_workspace_bytes(const gs_camera *cams_host, int n_views, int32_t n,
+                          int tile_size, uint64_t key_capacity);
+
+/* Projection (Section 2.1 "Projection"; Eq. 1b, 1c).
+ * Writes splats [n_views][n] (device).  For each point and view: camera-space
+ * mean u = R mu + t; culled if u_z <= near_z; 2D covariance
+ * J R Sigma R^T J^T + 0.3 I with Sigma = Rot(q) diag(exp(2 log_scale))
+ * Rot(q)^T and J the perspective Jacobian (tangent clamped to 1.3x the half
+ * field of view); colour max(0, sum_k sh_k Y_k(dir) + 1/2) with Y the real
+ * orthonormal SH basis of the unit direction from the camera centre to mu.
+ * lvl_rgba (device, nullable) [n_views][n][n_levels][4]: per-level colour
+ * and opacity (rgb, opacity) when the scene has n_levels > 0. */
+int gs_project(const gs_scene *scene, const gs_camera *cams_host, const gs_camera *cams_dev,
+               int n_views, int tile_size, gs_splat *splats, float *lvl_rgba, void *stream);
+
+/* Tile binning and (tile, depth) sort (Section 2.1 "Sorting"; Section 4.2
+ * filtering).  For every view v and point i with a visible splat, one key per
+ * tile of its pixel rectangle (row-major), kept only if tile_level_lo is NULL
+ * or tile_level_lo[tile] <= qbound[i].  The list is sorted by
+ * (global tile, float32 depth bits), ties by (view, i).
+ * Outputs (device):
+ *   vals [key_capacity]        point index i of each sorted key
+ *   keys [key_capacity]        nullable; (global tile << 32) | depth bits
+ *   tile_ranges [n_tiles][2]   [begin, end) of each tile's run in vals
+ *   hits [n_views][n]          nullable; keys emitted per point (Comp_i)
+ *   num_keys [1] (uint64)      total keys required.  If it exceeds
+ *                              key_capacity the outputs are truncated and
+ *                              invalid; the caller re-runs with a larger
+ *                              capacity (read num_keys after synchronising).
+ * key_capacity must be < 2^32. */
+int gs_bin_sort(const gs_splat *splats, int32_t n, const gs_camera *cams_host,
+                const gs_camera *cams_dev, int n_views, int tile_size,
+                const uint8_t *tile_level_lo, const uint8_t *qbound,
+                uint32_t *vals, uint64_t *keys, uint64_t key_capacity,
+                uint32_t *tile_ranges, uint32_t *hits, uint64_t *num_keys,
+                void *workspace, size_t workspace_bytes, void *stream);
+
+/* Per-pixel front-to-back compositing (Eq. 1a) over each tile's sorted run.
+ * A point contributes to pixel p if its Mahalanobis distance d satisfies
+ * d^2 <= 9 and alpha = min(0.99, opacity exp(-d^2 / 2)) >= 1/255; before
+ * blending it, T' = T (1 - alpha) is formed and the pixel stops (without
+ * blending it) once T' < 1e-4.  Output I = sum T_i alpha_i c_i + T bg.
+ * Outputs (device): image (planar, see above), final_T [n_pixels],
+ * n_contrib [n_pixels] (1-based position in the tile run of the last blended
+ * point, 0 if none), dominated_px (nullable) [n_views][n]: number of pixels
+ * whose largest T_i alpha_i is point i's (Val_i of Eq. 3; first maximum in
+ * depth order).  bg is a host float[3] (NULL = black). */
+int gs_rasterize_fwd(const gs_splat *splats, int32_t n, const gs_camera *cams_host,
+                     const gs_camera *cams_dev, int n_views, int tile_size,
+                     const uint32_t *vals, const uint32_t *tile_ranges, const float *bg,
+                     float *image, float *final_T, uint32_t *n_contrib, uint32_t *dominated_px,
+                     void *workspace, size_t workspace_bytes, void *stream);
+
+/* Reverse of gs_rasterize_fwd: given dL/dimage (planar, device) and the
+ * forward's final_T and n_contrib, writes grads [n_views][n] (device,
+ * overwritten): the gradient of L with respect to each splat's mean, conic,
+ * opacity and colour.  The per-pixel decisions (extent, skip, stop, the alpha
+ * clamp) are held constant. */
+int gs_rasterize_bwd(const gs_splat *splats, int32_t n, const gs_camera *cams_host,
+                     const gs_camera *cams_dev, int n_views, int tile_size,
+                     const uint32_t *vals, const uint32_t *tile_ranges, const float *bg,
+                     const float *final_T, const uint32_t *n_contrib, const float *dL_dimage,
+                     gs_splat_grad *grads, void *workspace, size_t workspace_bytes,
+                     void *stream);
+
+/* Reverse of gs_project: from grads [n_views][n] to the scene parameters,
+ * summed over views.  Outputs (device, overwritten): d_means [n][3],
+ * d_log_scales [n][3], d_quats [n][4], d_opacity_logits [n], d_sh [n][K][3]. */
+int gs_project_bwd(const gs_scene *scene, const gs_camera *cams_host, const gs_camera *cams_dev,
+                   int n_views, const gs_splat *splats, const gs_splat_grad *grads,
+                   float *d_means, float *d_log_scales, float *d_quats,
+                   float *d_opacity_logits, float *d_sh, void *stream);
+
+/* Foveation tables (Section 4.1; ring layout of Section 6).  For every pixel
+ * of every eye: eccentricity = angle between the pinhole rays through the
+ * pixel and through the gaze pixel; lower level lo (1-based) and weight w of
+ * level lo + 1, a linear ramp across the band of total width band_deg centred
+ * on each ring start (w = 0 outside bands).  Per tile: the lowest and highest
+ * level with non-zero weight over its pixels.
+ * fov_host: n_eyes structs (host).  Outputs (device): pix_level [n_pixels]
+ * uint8, pix_weight [n_pixels] float, tile_level [n_tiles][2] uint8 (lo, hi).
+ * n_levels is 1..4. */
+int gs_fovea_prep(const gs_camera *cams_host, const gs_camera *cams_dev, const gs_fovea *fov_host,
+                  int n_eyes, int tile_size, int n_levels, uint8_t *pix_level, float *pix_weight,
+                  uint8_t *tile_level, void *stream);
+
+/* Foveated compositing (Section 4.1 blending, 4.2 filtering and
+ * multi-versioning).  Keys must come from gs_bin_sort with the tile table's
+ * lower levels as tile_level_lo.  Each pixel composites level lo and, if its
+ * weight is non-zero, level lo + 1; level t uses only points with
+ * qbound >= t and their level-t colour and opacity (lvl_rgba from
+ * gs_project); output (1 - w) I_lo + w I_(lo+1).  Same cut-offs as
+ * gs_rasterize_fwd, applied per level. */
+int gs_rasterize_foveated(const gs_splat *splats, const float *lvl_rgba, int32_t n,
+                          const uint8_t *qbound, int n_levels, const gs_camera *cams_host,
+                          const gs_camera *cams_dev, int n_eyes, int tile_size,
+                          const uint32_t *vals, const uint32_t *tile_ranges,
+                          const uint8_t *pix_level, const float *pix_weight, const float *bg,
+                          float *image, void *workspace, size_t workspace_bytes, void *stream);
+
+/* One-call foveated render of n_eyes views: fovea tables, projection with
+ * per-level versions, filtered binning and sort, foveated compositing.
+ * Intermediate buffers live in the workspace; size it with
+ * gs_render_workspace_bytes().  num_keys (device, uint64) receives the
+ * required key count as in gs_bin_sort (outputs are invalid if it exceeds
+ * key_capacity). */
+size_t gs_render_workspace_bytes(const gs_camera *cams_host, int n_views, int32_t n,
+                                 int n_levels, int tile_size, uint64_t key_capacity);
+int gs_render_foveated(const gs_scene *scene, const gs_camera *cams_host,
+                       const gs_camera *cams_dev, const gs_fovea *fov_host, int n_eyes,
+                       int tile_size, const float *bg, float *image, uint64_t key_capacity,
+                       uint64_t *num_keys, void *workspace, size_t workspace_bytes,
+                       void *stream);
+
+/* One-call plain render of n_views views: projection, binning and sort,
+ * compositing.  Same workspace rule as gs_render_foveated (n_levels = 0).
+ * splats, vals, tile_ranges, final_T, n_contrib are outputs kept for a
+ * backward pass (device; n_contrib/final_T [n_pixels], vals [key_capacity]). */
+int gs_render_fwd(const gs_scene *scene, const gs_camera *cams_host, const gs_camera *cams_dev,
+                  int n_views, int tile_size, const float *bg, gs_splat *splats,
+                  uint32_t *vals, uint32_t *tile_ranges, uint64_t key_capacity,
+                  uint64_t *num_keys, float *image, float *final_T, uint32_t *n_contrib,
+                  void *workspace, size_t workspace_bytes, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* GS_H */

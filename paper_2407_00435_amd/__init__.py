@@ -1,0 +1,14 @@
+"""MI355X (gfx950) Gaussian-splatting rasterizer: thin Python binding over the
+C ABI of ``libgsmi.so`` (see ``include/gs.h``).
+
+Every step of the render runs in the library's HIP kernels; this package only
+marshals torch device tensors into the C calls.  Importing it loads the
+library and fails loudly if it has not been built.
+"""
+from .binding import (  # noqa: F401
+    Cameras, SceneTensors, GsError, lib, lib_path,
+    gs_project, gs_bin_sort, gs_rasterize_fwd, gs_rasterize_bwd, gs_project_bwd,
+    gs_fovea_prep, gs_rasterize_foveated, gs_render_foveated, gs_render_fwd,
+    gs_workspace_bytes, gs_render_workspace_bytes, gs_tile_count, splat_fields,
+)
+from .render import GaussianRender, render  # noqa: F401

@@ -1,0 +1,378 @@
+"""ctypes binding of the C ABI in ``include/gs.h``.
+
+Argument marshalling only: torch tensors supply device pointers and the
+current HIP stream; every computation happens in ``libgsmi.so``.  Function
+names match the C entry points.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+lib_path = os.path.join(_HERE, "libgsmi.so")
+
+GS_OK, GS_ERR_INVALID, GS_ERR_UNSUPPORTED, GS_ERR_CAPACITY, GS_ERR_HIP = 0, -1, -2, -3, -4
+
+
+class GsError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"gs error {code}: {msg}")
+        self.code = code
+
+
+class GsCamera(ctypes.Structure):
+    _fields_ = [("width", ctypes.c_int32), ("height", ctypes.c_int32),
+                ("fx", ctypes.c_float), ("fy", ctypes.c_float),
+                ("cx", ctypes.c_float), ("cy", ctypes.c_float),
+                ("R", ctypes.c_float * 9), ("t", ctypes.c_float * 3),
+                ("near_z", ctypes.c_float)]
+
+
+class GsScene(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int32), ("sh_degree", ctypes.c_int32),
+                ("means", ctypes.c_void_p), ("log_scales", ctypes.c_void_p),
+                ("quats", ctypes.c_void_p), ("opacity_logits", ctypes.c_void_p),
+                ("sh", ctypes.c_void_p), ("qbound", ctypes.c_void_p),
+                ("n_levels", ctypes.c_int32),
+                ("lvl_opacity_logits", ctypes.c_void_p), ("lvl_sh_dc", ctypes.c_void_p)]
+
+
+class GsFovea(ctypes.Structure):
+    _fields_ = [("gaze_x", ctypes.c_float), ("gaze_y", ctypes.c_float),
+                ("ring_deg", ctypes.c_float * 3), ("band_deg", ctypes.c_float)]
+
+
+assert ctypes.sizeof(GsCamera) == 76
+assert ctypes.sizeof(GsFovea) == 24
+
+_lib = None
+_VP = ctypes.c_void_p
+_I = ctypes.c_int
+_I32 = ctypes.c_int32
+_U64 = ctypes.c_uint64
+_SZ = ctypes.c_size_t
+_PC = ctypes.POINTER(GsCamera)
+_PS = ctypes.POINTER(GsScene)
+_PF = ctypes.POINTER(GsFovea)
+
+_SIGS = {
+    "gs_last_error": ([], ctypes.c_char_p),
+    "gs_version": ([], _I),
+    "gs_tile_count": ([_PC, _I, _I, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64)], _I),
+    "gs_workspace_bytes": ([_PC, _I, _I32, _I, _U64], _SZ),
+    "gs_render_workspace_bytes": ([_PC, _I, _I32, _I, _I, _U64], _SZ),
+    "gs_project": ([_PS, _PC, _VP, _I, _I, _VP, _VP, _VP], _I),
+    "gs_bin_sort": ([_VP, _I32, _PC, _VP, _I, _I, _VP, _VP, _VP, _VP, _U64, _VP, _VP, _VP, _VP, _SZ,
+                     _VP], _I),
+    "gs_rasterize_fwd": ([_VP, _I32, _PC, _VP, _I, _I, _VP, _VP, _VP, _VP, _VP, _VP, _VP, _VP, _SZ,
+                          _VP], _I),
+    "gs_rasterize_bwd": ([_VP, _I32, _PC, _VP, _I, _I, _VP, _VP, _VP, _VP, _VP, _VP, _VP, _VP, _SZ,
+                          _VP], _I),
+    "gs_project_bwd": ([_PS, _PC, _VP, _I, _VP, _VP, _VP, _VP, _VP, _VP, _VP, _VP], _I),
+    "gs_fovea_prep": ([_PC, _VP, _PF, _I, _I, _I, _VP, _VP, _VP, _VP], _I),
+    "gs_rasterize_foveated": ([_VP, _VP, _I32, _VP, _I, _PC, _VP, _I, _I, _VP, _VP, _VP, _VP, _VP,
+                               _VP, _VP, _SZ, _VP], _I),
+    "gs_render_foveated": ([_PS, _PC, _VP, _PF, _I, _I, _VP, _VP, _U64, _VP, _VP, _SZ, _VP], _I),
+    "gs_render_fwd": ([_PS, _PC, _VP, _I, _I, _VP, _VP, _VP, _VP, _U64, _VP, _VP, _VP, _VP, _VP, _SZ,
+                       _VP], _I),
+}
+EXPORTED = tuple(_SIGS)
+
+
+def lib():
+    """Load libgsmi.so (raises if it has not been built: there is no fallback)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(lib_path):
+            raise RuntimeError(f"{lib_path} is missing; build it with "
+                               "paper_2407_00435_amd/build.py (hipcc, gfx950)")
+        L = ctypes.CDLL(lib_path)
+        for name, (args, res) in _SIGS.items():
+            fn = getattr(L, name)
+            fn.argtypes = args
+            fn.restype = res
+        _lib = L
+    return _lib
+
+
+def _check(code: int):
+    if code != GS_OK:
+        raise GsError(code, lib().gs_last_error().decode())
+
+
+def _ptr(t):
+    if t is None:
+        return None
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _stream():
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _dev():
+    return torch.device("cuda", torch.cuda.current_device())
+
+
+def _ws(nbytes: int):
+    t = torch.empty(max(int(nbytes), 256) + 256, dtype=torch.uint8, device=_dev())
+    off = (-t.data_ptr()) % 256
+    return t, ctypes.c_void_p(t.data_ptr() + off), int(nbytes)
+
+
+class Cameras:
+    """n_views cameras on the host (ctypes array) and the device (uint8 tensor)."""
+
+    def __init__(self, cams, device=None):
+        self.n = len(cams)
+        self.host = (GsCamera * self.n)()
+        for k, c in enumerate(cams):
+            row = c.as_row() if hasattr(c, "as_row") else np.asarray(c, np.float64)
+            h = self.host[k]
+            h.width, h.height = int(row[0]), int(row[1])
+            h.fx, h.fy, h.cx, h.cy = (float(x) for x in row[2:6])
+            for j in range(9):
+                h.R[j] = float(row[6 + j])
+            for j in range(3):
+                h.t[j] = float(row[15 + j])
+            h.near_z = float(row[18])
+        raw = bytes(self.host)
+        self.dev = torch.frombuffer(bytearray(raw), dtype=torch.uint8).to(device or _dev())
+        self.sizes = [(int(c.width), int(c.height)) for c in self.host]
+
+    @property
+    def hp(self):
+        return ctypes.cast(self.host, _PC)
+
+    @property
+    def dp(self):
+        return ctypes.c_void_p(self.dev.data_ptr())
+
+    def tiles(self, tile_size: int):
+        nt, npx = ctypes.c_int64(), ctypes.c_int64()
+        _check(lib().gs_tile_count(self.hp, self.n, tile_size, ctypes.byref(nt), ctypes.byref(npx)))
+        return int(nt.value), int(npx.value)
+
+
+class SceneTensors:
+    """Device copies of a scene's parameter arrays (float32, contiguous)."""
+
+    def __init__(self, scene=None, device=None, **tensors):
+        dev = device or _dev()
+        if scene is not None:
+            tensors = dict(means=scene.means, log_scales=scene.log_scales, quats=scene.quats,
+                           opacity_logits=scene.opacity_logits, sh=scene.sh,
+                           qbound=scene.qbound, lvl_opacity_logits=scene.lvl_opacity_logits,
+                           lvl_sh_dc=scene.lvl_sh_dc, sh_degree=scene.sh_degree)
+        self.sh_degree = int(tensors.pop("sh_degree"))
+        self.t = {}
+        for k, v in tensors.items():
+            if v is None:
+                self.t[k] = None
+                continue
+            if not torch.is_tensor(v):
+                v = torch.from_numpy(np.ascontiguousarray(v))
+            dt = torch.uint8 if k == "qbound" else torch.float32
+            self.t[k] = v.to(device=dev, dtype=dt).contiguous()
+        self.n = int(self.t["means"].shape[0])
+        self.n_levels = 0
+        if self.t.get("qbound") is not None:
+            if self.t.get("lvl_opacity_logits") is not None:
+                self.n_levels = int(self.t["lvl_opacity_logits"].shape[0])
+            elif self.t.get("lvl_sh_dc") is not None:
+                self.n_levels = int(self.t["lvl_sh_dc"].shape[0])
+            else:
+                self.n_levels = 4
+
+    def struct(self, levels: bool = True) -> GsScene:
+        g = self.t.get
+        s = GsScene()
+        s.n, s.sh_degree = self.n, self.sh_degree
+        s.means, s.log_scales, s.quats = (g("means").data_ptr(), g("log_scales").data_ptr(),
+                                          g("quats").data_ptr())
+        s.opacity_logits, s.sh = g("opacity_logits").data_ptr(), g("sh").data_ptr()
+        if levels and g("qbound") is not None:
+            s.qbound = g("qbound").data_ptr()
+            s.n_levels = self.n_levels
+            s.lvl_opacity_logits = g("lvl_opacity_logits").data_ptr() if g("lvl_opacity_logits") is not None else None
+            s.lvl_sh_dc = g("lvl_sh_dc").data_ptr() if g("lvl_sh_dc") is not None else None
+        return s
+
+
+def splat_fields(splats: torch.Tensor) -> dict:
+    """View a [V, n, 12] float32 splat tensor as named fields."""
+    f = splats
+    return dict(mean2d=f[..., 0:2], conic=f[..., 2:5], opacity=f[..., 5], color=f[..., 6:9],
+                depth=f[..., 9], radius=f[..., 10].view(torch.int32),
+                tiles_touched=f[..., 11].view(torch.int32))
+
+
+def gs_tile_count(cams: Cameras, tile_size: int):
+    return cams.tiles(tile_size)
+
+
+def gs_workspace_bytes(cams: Cameras, n: int, tile_size: int, key_capacity: int) -> int:
+    return int(lib().gs_workspace_bytes(cams.hp, cams.n, n, tile_size, key_capacity))
+
+
+def gs_render_workspace_bytes(cams: Cameras, n: int, n_levels: int, tile_size: int,
+                              key_capacity: int) -> int:
+    return int(lib().gs_render_workspace_bytes(cams.hp, cams.n, n, n_levels, tile_size, key_capacity))
+
+
+def gs_project(scene: SceneTensors, cams: Cameras, tile_size: int = 16, levels: bool = False):
+    """Projection; returns splats [V, n, 12] (and lvl_rgba [V, n, L, 4] if levels)."""
+    dev = scene.t["means"].device
+    splats = torch.empty((cams.n, scene.n, 12), dtype=torch.float32, device=dev)
+    lvl = None
+    if levels:
+        lvl = torch.empty((cams.n, scene.n, scene.n_levels, 4), dtype=torch.float32, device=dev)
+    st = scene.struct(levels=levels)
+    _check(lib().gs_project(ctypes.byref(st), cams.hp, cams.dp, cams.n, tile_size, _ptr(splats),
+                            _ptr(lvl), _stream()))
+    return (splats, lvl) if levels else splats
+
+
+def gs_bin_sort(splats: torch.Tensor, n: int, cams: Cameras, tile_size: int = 16,
+                tile_level_lo=None, qbound=None, key_capacity: int | None = None,
+                want_keys: bool = False, want_hits: bool = False):
+    """Binning + (tile, depth) sort.  key_capacity defaults to the sum of the
+    unfiltered rectangle tile counts (exact for the plain path, an upper bound
+    with the level filter); that default reads one scalar back from the device."""
+    dev = splats.device
+    n_tiles, _ = cams.tiles(tile_size)
+    if key_capacity is None:
+        key_capacity = int(splat_fields(splats)["tiles_touched"].to(torch.int64).sum().item())
+    cap = max(int(key_capacity), 1)
+    vals = torch.empty(cap, dtype=torch.int32, device=dev)
+    keys = torch.empty(cap, dtype=torch.int64, device=dev) if want_keys else None
+    ranges = torch.empty((n_tiles, 2), dtype=torch.int32, device=dev)
+    hits = torch.empty((cams.n, n), dtype=torch.int32, device=dev) if want_hits else None
+    num = torch.zeros(1, dtype=torch.int64, device=dev)
+    wsb = gs_workspace_bytes(cams, n, tile_size, cap)
+    ws_t, ws, wsn = _ws(wsb)
+    _check(lib().gs_bin_sort(_ptr(splats), n, cams.hp, cams.dp, cams.n, tile_size, _ptr(tile_level_lo),
+                             _ptr(qbound), _ptr(vals), _ptr(keys), cap, _ptr(ranges), _ptr(hits),
+                             _ptr(num), ws, wsn, _stream()))
+    return dict(vals=vals, keys=keys, ranges=ranges, hits=hits, num_keys=num, capacity=cap,
+                _ws=ws_t)
+
+
+def gs_rasterize_fwd(splats, n, cams: Cameras, tile_size, vals, ranges, bg=(0.0, 0.0, 0.0),
+                     want_dominated: bool = False):
+    dev = splats.device
+    _, n_px = cams.tiles(tile_size)
+    image = torch.empty(3 * n_px, dtype=torch.float32, device=dev)
+    final_T = torch.empty(n_px, dtype=torch.float32, device=dev)
+    n_contrib = torch.empty(n_px, dtype=torch.int32, device=dev)
+    dom = torch.empty((cams.n, n), dtype=torch.int32, device=dev) if want_dominated else None
+    bgc = (ctypes.c_float * 3)(*bg)
+    _check(lib().gs_rasterize_fwd(_ptr(splats), n, cams.hp, cams.dp, cams.n, tile_size, _ptr(vals),
+                                  _ptr(ranges), ctypes.cast(bgc, _VP), _ptr(image), _ptr(final_T),
+                                  _ptr(n_contrib), _ptr(dom), None, 0, _stream()))
+    return dict(image=image, final_T=final_T, n_contrib=n_contrib, dominated=dom)
+
+
+def gs_rasterize_bwd(splats, n, cams: Cameras, tile_size, vals, ranges, final_T, n_contrib,
+                     dL_dimage, bg=(0.0, 0.0, 0.0)):
+    grads = torch.empty((cams.n, n, 12), dtype=torch.float32, device=splats.device)
+    bgc = (ctypes.c_float * 3)(*bg)
+    _check(lib().gs_rasterize_bwd(_ptr(splats), n, cams.hp, cams.dp, cams.n, tile_size, _ptr(vals),
+                                  _ptr(ranges), ctypes.cast(bgc, _VP), _ptr(final_T), _ptr(n_contrib),
+                                  _ptr(dL_dimage.contiguous()), _ptr(grads), None, 0, _stream()))
+    return grads
+
+
+def gs_project_bwd(scene: SceneTensors, cams: Cameras, splats, grads):
+    t = scene.t
+    out = {k: torch.empty_like(t[k]) for k in ("means", "log_scales", "quats", "opacity_logits", "sh")}
+    st = scene.struct(levels=False)
+    _check(lib().gs_project_bwd(ctypes.byref(st), cams.hp, cams.dp, cams.n, _ptr(splats), _ptr(grads),
+                                _ptr(out["means"]), _ptr(out["log_scales"]), _ptr(out["quats"]),
+                                _ptr(out["opacity_logits"]), _ptr(out["sh"]), _stream()))
+    return out
+
+
+def _foveae(foveae):
+    arr = (GsFovea * len(foveae))()
+    for k, f in enumerate(foveae):
+        row = f.as_row() if hasattr(f, "as_row") else np.asarray(f, np.float64)
+        arr[k].gaze_x, arr[k].gaze_y = float(row[0]), float(row[1])
+        for j in range(3):
+            arr[k].ring_deg[j] = float(row[2 + j])
+        arr[k].band_deg = float(row[5])
+    return arr
+
+
+def gs_fovea_prep(cams: Cameras, foveae, tile_size: int = 16, n_levels: int = 4):
+    dev = cams.dev.device
+    n_tiles, n_px = cams.tiles(tile_size)
+    pl = torch.empty(n_px, dtype=torch.uint8, device=dev)
+    pw = torch.empty(n_px, dtype=torch.float32, device=dev)
+    tl = torch.empty((n_tiles, 2), dtype=torch.uint8, device=dev)
+    fa = _foveae(foveae)
+    _check(lib().gs_fovea_prep(cams.hp, cams.dp, ctypes.cast(fa, _PF), cams.n, tile_size, n_levels,
+                               _ptr(pl), _ptr(pw), _ptr(tl), _stream()))
+    return dict(pix_level=pl, pix_weight=pw, tile_level=tl)
+
+
+def gs_rasterize_foveated(splats, lvl_rgba, n, qbound, n_levels, cams: Cameras, tile_size, vals,
+                          ranges, pix_level, pix_weight, bg=(0.0, 0.0, 0.0)):
+    _, n_px = cams.tiles(tile_size)
+    image = torch.empty(3 * n_px, dtype=torch.float32, device=splats.device)
+    bgc = (ctypes.c_float * 3)(*bg)
+    _check(lib().gs_rasterize_foveated(_ptr(splats), _ptr(lvl_rgba), n, _ptr(qbound), n_levels, cams.hp,
+                                       cams.dp, cams.n, tile_size, _ptr(vals), _ptr(ranges),
+                                       _ptr(pix_level), _ptr(pix_weight), ctypes.cast(bgc, _VP),
+                                       _ptr(image), None, 0, _stream()))
+    return image
+
+
+def gs_render_foveated(scene: SceneTensors, cams: Cameras, foveae, tile_size: int = 16,
+                       bg=(0.0, 0.0, 0.0), key_capacity: int = 0, image=None, workspace=None):
+    """One-call foveated render; returns (image, num_keys tensor, workspace)."""
+    dev = scene.t["means"].device
+    _, n_px = cams.tiles(tile_size)
+    if image is None:
+        image = torch.empty(3 * n_px, dtype=torch.float32, device=dev)
+    num = torch.zeros(1, dtype=torch.int64, device=dev)
+    need = gs_render_workspace_bytes(cams, scene.n, scene.n_levels, tile_size, key_capacity)
+    if workspace is None or workspace[2] < need:
+        workspace = _ws(need)
+    fa = _foveae(foveae)
+    bgc = (ctypes.c_float * 3)(*bg)
+    st = scene.struct(levels=True)
+    _check(lib().gs_render_foveated(ctypes.byref(st), cams.hp, cams.dp, ctypes.cast(fa, _PF), cams.n,
+                                    tile_size, ctypes.cast(bgc, _VP), _ptr(image), key_capacity,
+                                    _ptr(num), workspace[1], workspace[2], _stream()))
+    return image, num, workspace
+
+
+def gs_render_fwd(scene: SceneTensors, cams: Cameras, tile_size: int = 16, bg=(0.0, 0.0, 0.0),
+                  key_capacity: int = 0, workspace=None):
+    dev = scene.t["means"].device
+    n_tiles, n_px = cams.tiles(tile_size)
+    cap = max(int(key_capacity), 1)
+    out = dict(splats=torch.empty((cams.n, scene.n, 12), dtype=torch.float32, device=dev),
+               vals=torch.empty(cap, dtype=torch.int32, device=dev),
+               ranges=torch.empty((n_tiles, 2), dtype=torch.int32, device=dev),
+               num_keys=torch.zeros(1, dtype=torch.int64, device=dev),
+               image=torch.empty(3 * n_px, dtype=torch.float32, device=dev),
+               final_T=torch.empty(n_px, dtype=torch.float32, device=dev),
+               n_contrib=torch.empty(n_px, dtype=torch.int32, device=dev))
+    need = gs_workspace_bytes(cams, scene.n, tile_size, cap)
+    if workspace is None or workspace[2] < need:
+        workspace = _ws(need)
+    bgc = (ctypes.c_float * 3)(*bg)
+    st = scene.struct(levels=False)
+    _check(lib().gs_render_fwd(ctypes.byref(st), cams.hp, cams.dp, cams.n, tile_size,
+                               ctypes.cast(bgc, _VP), _ptr(out["splats"]), _ptr(out["vals"]),
+                               _ptr(out["ranges"]), cap, _ptr(out["num_keys"]), _ptr(out["image"]),
+                               _ptr(out["final_T"]), _ptr(out["n_contrib"]), workspace[1], workspace[2],
+                               _stream()))
+    out["workspace"] = workspace
+    return out

@@ -1,0 +1,436 @@
+// C ABI of the library: argument checks, workspace layout and the
+// composition of the stages.  Every entry point only enqueues on the given
+// stream and never allocates device memory.
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <string>
+
+#include "common.hpp"
+#include "kernels.hpp"
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const char *fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof(buf), fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return code;
+}
+
+int ok()
+{
+    g_err.clear();
+    return GS_OK;
+}
+
+int hip_fail(hipError_t e, const char *where)
+{
+    return fail(GS_ERR_HIP, "%s: %s", where, hipGetErrorString(e));
+}
+
+bool aligned(const void *p, size_t a) { return ((uintptr_t)p % a) == 0; }
+
+bool tile_ok(int T) { return T == 8 || T == 16 || T == 32; }
+
+int check_cams(const gs_camera *ch, const gs_camera *cd, int V, int T, int64_t *tiles,
+               int64_t *pixels)
+{
+    if (V < 1) return fail(GS_ERR_INVALID, "n_views must be >= 1 (got %d)", V);
+    if (!ch || !cd) return fail(GS_ERR_INVALID, "camera arrays must not be NULL");
+    if (!tile_ok(T)) return fail(GS_ERR_UNSUPPORTED, "tile size %d not in {8, 16, 32}", T);
+    int64_t t = 0, p = 0;
+    for (int v = 0; v < V; ++v) {
+        const gs_camera &c = ch[v];
+        if (c.width <= 0 || c.height <= 0 || c.width > 65536 || c.height > 65536)
+            return fail(GS_ERR_INVALID, "camera %d: bad size %dx%d", v, c.width, c.height);
+        if (!(c.fx > 0.f) || !(c.fy > 0.f) || !std::isfinite(c.cx) || !std::isfinite(c.cy))
+            return fail(GS_ERR_INVALID, "camera %d: bad intrinsics", v);
+        t += (int64_t)((c.width + T - 1) / T) * ((c.height + T - 1) / T);
+        p += (int64_t)c.width * c.height;
+    }
+    if (t >= (1ll << 32)) return fail(GS_ERR_UNSUPPORTED, "too many tiles (%lld)", (long long)t);
+    if (tiles) *tiles = t;
+    if (pixels) *pixels = p;
+    return GS_OK;
+}
+
+int check_scene(const gs_scene *s, bool levels)
+{
+    if (!s) return fail(GS_ERR_INVALID, "scene is NULL");
+    if (s->n < 0) return fail(GS_ERR_INVALID, "n must be >= 0");
+    if (s->sh_degree < 0 || s->sh_degree > 3)
+        return fail(GS_ERR_UNSUPPORTED, "sh_degree %d not in 0..3", s->sh_degree);
+    if (s->n > 0 && (!s->means || !s->log_scales || !s->quats || !s->opacity_logits || !s->sh))
+        return fail(GS_ERR_INVALID, "scene parameter pointer is NULL");
+    if (!aligned(s->quats, 16)) return fail(GS_ERR_INVALID, "quats must be 16-byte aligned");
+    if ((s->sh_degree == 1 || s->sh_degree == 3) && !aligned(s->sh, 16))
+        return fail(GS_ERR_INVALID, "sh must be 16-byte aligned");
+    if (levels) {
+        if (s->n_levels < 1 || s->n_levels > 4)
+            return fail(GS_ERR_UNSUPPORTED, "n_levels %d not in 1..4", s->n_levels);
+        if (s->n > 0 && !s->qbound) return fail(GS_ERR_INVALID, "qbound is NULL");
+    }
+    return GS_OK;
+}
+
+int tile_bits_of(int64_t n_tiles)
+{
+    int b = 0;
+    while ((int64_t(1) << b) < n_tiles) ++b;
+    return b;
+}
+
+// ---------------------------------------------------------------------------
+// Workspace layout (256-byte aligned sub-buffers).
+struct Carve {
+    size_t off = 0;
+    char *base = nullptr;
+    template <class P>
+    P *take(size_t bytes)
+    {
+        off = (off + 255) & ~size_t(255);
+        P *p = base ? reinterpret_cast<P *>(base + off) : nullptr;
+        off += bytes;
+        return p;
+    }
+};
+
+void carve_bin(Carve &c, int64_t E, uint64_t cap, BinScratch &bs)
+{
+    bs.dkey_a = c.take<uint32_t>(4 * E);
+    bs.dval_a = c.take<uint32_t>(4 * E);
+    bs.dkey_b = c.take<uint32_t>(4 * E);
+    bs.dval_b = c.take<uint32_t>(4 * E);
+    bs.hits = c.take<uint32_t>(4 * E);
+    int64_t nb = (E + SCAN_THREADS * SCAN_ITEMS - 1) / (SCAN_THREADS * SCAN_ITEMS) + 1;
+    bs.block_sums = c.take<uint64_t>(8 * nb);
+    bs.tkey_a = c.take<uint32_t>(4 * cap);
+    bs.tkey_b = c.take<uint32_t>(4 * cap);
+    bs.tval_b = c.take<uint32_t>(4 * cap);
+    bs.counts = c.take<uint64_t>(8 * 4);
+    bs.rs.hist = c.take<uint32_t>(4 * 4 * 256);
+    uint64_t big = cap > (uint64_t)E ? cap : (uint64_t)E;
+    bs.rs.status = c.take<uint64_t>(8 * 256 * radix_max_parts(big ? big : 1));
+    bs.rs.tickets = c.take<uint32_t>(4 * 4);
+}
+
+struct RenderBufs {
+    gs_splat *splats;
+    float *lvl;
+    uint32_t *vals;
+    uint32_t *ranges;
+    uint8_t *pix_level;
+    float *pix_weight;
+    uint8_t *tile_level;
+    uint8_t *tile_lo;
+};
+
+void carve_render(Carve &c, int64_t E, int L, uint64_t cap, int64_t tiles, int64_t pixels,
+                  RenderBufs &rb)
+{
+    rb.splats = c.take<gs_splat>(sizeof(gs_splat) * E);
+    rb.lvl = L > 0 ? c.take<float>(16 * E * L) : nullptr;
+    rb.vals = c.take<uint32_t>(4 * cap);
+    rb.ranges = c.take<uint32_t>(8 * tiles);
+    rb.pix_level = L > 0 ? c.take<uint8_t>(pixels) : nullptr;
+    rb.pix_weight = L > 0 ? c.take<float>(4 * pixels) : nullptr;
+    rb.tile_level = L > 0 ? c.take<uint8_t>(2 * tiles) : nullptr;
+    rb.tile_lo = L > 0 ? c.take<uint8_t>(tiles) : nullptr;
+}
+
+size_t bin_bytes(int64_t E, uint64_t cap)
+{
+    Carve c;
+    BinScratch bs;
+    carve_bin(c, E, cap, bs);
+    return c.off + 256;
+}
+
+int check_ws(const void *ws, size_t have, size_t need)
+{
+    if (!ws) return fail(GS_ERR_INVALID, "workspace is NULL");
+    if (!aligned(ws, 256)) return fail(GS_ERR_INVALID, "workspace must be 256-byte aligned");
+    if (have < need)
+        return fail(GS_ERR_CAPACITY, "workspace too small: %zu bytes given, %zu needed", have, need);
+    return GS_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *gs_last_error(void) { return g_err.c_str(); }
+
+int gs_version(void) { return 1; }
+
+int gs_tile_count(const gs_camera *cams_host, int n_views, int tile_size, int64_t *n_tiles,
+                  int64_t *n_pixels)
+{
+    int r = check_cams(cams_host, cams_host, n_views, tile_size, n_tiles, n_pixels);
+    return r ? r : ok();
+}
+
+size_t gs_workspace_bytes(const gs_camera *cams_host, int n_views, int32_t n, int tile_size,
+                          uint64_t key_capacity)
+{
+    (void)cams_host;
+    (void)tile_size;
+    return bin_bytes((int64_t)n_views * (n > 0 ? n : 0), key_capacity);
+}
+
+size_t gs_render_workspace_bytes(const gs_camera *cams_host, int n_views, int32_t n, int n_levels,
+                                 int tile_size, uint64_t key_capacity)
+{
+    int64_t tiles = 0, pixels = 0;
+    if (check_cams(cams_host, cams_host, n_views, tile_size, &tiles, &pixels)) return 0;
+    int64_t E = (int64_t)n_views * (n > 0 ? n : 0);
+    Carve c;
+    BinScratch bs;
+    RenderBufs rb;
+    carve_render(c, E, n_levels, key_capacity, tiles, pixels, rb);
+    carve_bin(c, E, key_capacity, bs);
+    return c.off + 256;
+}
+
+int gs_project(const gs_scene *scene, const gs_camera *cams_host, const gs_camera *cams_dev,
+               int n_views, int tile_size, gs_splat *splats, float *lvl_rgba, void *stream)
+{
+    int r;
+    if ((r = check_scene(scene, false))) return r;
+    if ((r = check_cams(cams_host, cams_dev, n_views, tile_size, nullptr, nullptr))) return r;
+    if ((int64_t)n_views * scene->n >= (1ll << 32))
+        return fail(GS_ERR_UNSUPPORTED, "n_views * n must be < 2^32");
+    if (scene->n > 0 && !splats) return fail(GS_ERR_INVALID, "splats is NULL");
+    if (!aligned(splats, 16) || !aligned(lvl_rgba, 16))
+        return fail(GS_ERR_INVALID, "splats and lvl_rgba must be 16-byte aligned");
+    if (lvl_rgba && (scene->n_levels < 1 || scene->n_levels > 4))
+        return fail(GS_ERR_INVALID, "lvl_rgba given but n_levels = %d", scene->n_levels);
+    hipError_t e = launch_project(*scene, cams_dev, n_views, tile_size, splats, lvl_rgba,
+                                  (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(e, "gs_project");
+    return ok();
+}
+
+int gs_bin_sort(const gs_splat *splats, int32_t n, const gs_camera *cams_host,
+                const gs_camera *cams_dev, int n_views, int tile_size,
+                const uint8_t *tile_level_lo, const uint8_t *qbound, uint32_t *vals,
+                uint64_t *keys, uint64_t key_capacity, uint32_t *tile_ranges, uint32_t *hits,
+                uint64_t *num_keys, void *workspace, size_t workspace_bytes, void *stream)
+{
+    int r;
+    int64_t tiles = 0;
+    if ((r = check_cams(cams_host, cams_dev, n_views, tile_size, &tiles, nullptr))) return r;
+    if (n < 0) return fail(GS_ERR_INVALID, "n must be >= 0");
+    int64_t E = (int64_t)n_views * n;
+    if (E >= (1ll << 32)) return fail(GS_ERR_UNSUPPORTED, "n_views * n must be < 2^32");
+    if (key_capacity >= (1ull << 32)) return fail(GS_ERR_UNSUPPORTED, "key_capacity must be < 2^32");
+    if ((n > 0 && !splats) || !tile_ranges || !num_keys || (key_capacity > 0 && !vals))
+        return fail(GS_ERR_INVALID, "NULL output or input pointer");
+    if (!aligned(splats, 16)) return fail(GS_ERR_INVALID, "splats must be 16-byte aligned");
+    if ((tile_level_lo != nullptr) != (qbound != nullptr))
+        return fail(GS_ERR_INVALID, "tile_level_lo and qbound go together");
+    if ((r = check_ws(workspace, workspace_bytes, bin_bytes(E, key_capacity)))) return r;
+    Carve c;
+    c.base = (char *)workspace;
+    BinScratch bs;
+    carve_bin(c, E, key_capacity, bs);
+    hipError_t e = launch_bin_sort(splats, n, cams_dev, n_views, tiles, tile_bits_of(tiles), tile_size,
+                                   tile_level_lo, qbound, vals, keys, key_capacity, tile_ranges,
+                                   hits, num_keys, bs, (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(e, "gs_bin_sort");
+    return ok();
+}
+
+int gs_rasterize_fwd(const gs_splat *splats, int32_t n, const gs_camera *cams_host,
+                     const gs_camera *cams_dev, int n_views, int tile_size, const uint32_t *vals,
+                     const uint32_t *tile_ranges, const float *bg, float *image, float *final_T,
+                     uint32_t *n_contrib, uint32_t *dominated_px, void *workspace,
+                     size_t workspace_bytes, void *stream)
+{
+    (void)workspace;
+    (void)workspace_bytes;
+    int r;
+    int64_t tiles = 0;
+    if ((r = check_cams(cams_host, cams_dev, n_views, tile_size, &tiles, nullptr))) return r;
+    if (n < 0) return fail(GS_ERR_INVALID, "n must be >= 0");
+    if (!tile_ranges || !image || !final_T || !n_contrib || (n > 0 && (!splats || !vals)))
+        return fail(GS_ERR_INVALID, "NULL output or input pointer");
+    if (!aligned(splats, 16)) return fail(GS_ERR_INVALID, "splats must be 16-byte aligned");
+    const float zero[3] = {0.f, 0.f, 0.f};
+    hipError_t e = launch_raster_fwd(splats, n, cams_dev, n_views, tile_size, tiles, vals, tile_ranges,
+                                     bg ? bg : zero, image, final_T, n_contrib, dominated_px,
+                                     (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(e, "gs_rasterize_fwd");
+    return ok();
+}
+
+int gs_rasterize_bwd(const gs_splat *splats, int32_t n, const gs_camera *cams_host,
+                     const gs_camera *cams_dev, int n_views, int tile_size, const uint32_t *vals,
+                     const uint32_t *tile_ranges, const float *bg, const float *final_T,
+                     const uint32_t *n_contrib, const float *dL_dimage, gs_splat_grad *grads,
+                     void *workspace, size_t workspace_bytes, void *stream)
+{
+    (void)workspace;
+    (void)workspace_bytes;
+    int r;
+    int64_t tiles = 0;
+    if ((r = check_cams(cams_host, cams_dev, n_views, tile_size, &tiles, nullptr))) return r;
+    if (n < 0) return fail(GS_ERR_INVALID, "n must be >= 0");
+    if (!tile_ranges || !final_T || !n_contrib || !dL_dimage ||
+        (n > 0 && (!splats || !vals || !grads)))
+        return fail(GS_ERR_INVALID, "NULL output or input pointer");
+    if (!aligned(splats, 16)) return fail(GS_ERR_INVALID, "splats must be 16-byte aligned");
+    const float zero[3] = {0.f, 0.f, 0.f};
+    hipError_t e = launch_raster_bwd(splats, n, cams_dev, n_views, tile_size, tiles, vals, tile_ranges,
+                                     bg ? bg : zero, final_T, n_contrib, dL_dimage, grads,
+                                     (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(e, "gs_rasterize_bwd");
+    return ok();
+}
+
+int gs_project_bwd(const gs_scene *scene, const gs_camera *cams_host, const gs_camera *cams_dev,
+                   int n_views, const gs_splat *splats, const gs_splat_grad *grads, float *d_means,
+                   float *d_log_scales, float *d_quats, float *d_opacity_logits, float *d_sh,
+                   void *stream)
+{
+    int r;
+    if ((r = check_scene(scene, false))) return r;
+    if ((r = check_cams(cams_host, cams_dev, n_views, 16, nullptr, nullptr))) return r;
+    if (scene->n > 0 &&
+        (!splats || !grads || !d_means || !d_log_scales || !d_quats || !d_opacity_logits || !d_sh))
+        return fail(GS_ERR_INVALID, "NULL output or input pointer");
+    if (!aligned(d_quats, 16)) return fail(GS_ERR_INVALID, "d_quats must be 16-byte aligned");
+    if ((scene->sh_degree == 1 || scene->sh_degree == 3) && !aligned(d_sh, 16))
+        return fail(GS_ERR_INVALID, "d_sh must be 16-byte aligned");
+    hipError_t e = launch_project_bwd(*scene, cams_dev, n_views, splats, grads, d_means, d_log_scales,
+                                      d_quats, d_opacity_logits, d_sh, (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(e, "gs_project_bwd");
+    return ok();
+}
+
+int gs_fovea_prep(const gs_camera *cams_host, const gs_camera *cams_dev, const gs_fovea *fov_host,
+                  int n_eyes, int tile_size, int n_levels, uint8_t *pix_level, float *pix_weight,
+                  uint8_t *tile_level, void *stream)
+{
+    int r;
+    int64_t tiles = 0, pixels = 0;
+    if ((r = check_cams(cams_host, cams_dev, n_eyes, tile_size, &tiles, &pixels))) return r;
+    if (n_eyes > 8) return fail(GS_ERR_UNSUPPORTED, "at most 8 eyes (got %d)", n_eyes);
+    if (n_levels < 1 || n_levels > 4) return fail(GS_ERR_UNSUPPORTED, "n_levels %d not in 1..4", n_levels);
+    if (!fov_host || !pix_level || !pix_weight || !tile_level)
+        return fail(GS_ERR_INVALID, "NULL output or input pointer");
+    for (int i = 0; i < n_eyes; ++i) {
+        const gs_fovea &f = fov_host[i];
+        if (!(f.band_deg >= 0.f) || !std::isfinite(f.gaze_x) || !std::isfinite(f.gaze_y))
+            return fail(GS_ERR_INVALID, "eye %d: bad fovea parameters", i);
+        for (int j = 0; j + 1 < n_levels; ++j) {
+            if (j > 0 && !(f.ring_deg[j] - 0.5f * f.band_deg >= f.ring_deg[j - 1] + 0.5f * f.band_deg))
+                return fail(GS_ERR_INVALID, "eye %d: ring bands overlap or are unordered", i);
+        }
+        if (n_levels > 1 && f.band_deg > 0.f && !(f.ring_deg[0] - 0.5f * f.band_deg >= 0.f))
+            return fail(GS_ERR_INVALID, "eye %d: first band starts below 0 degrees", i);
+    }
+    hipError_t e = launch_fovea_prep(cams_dev, fov_host, n_eyes, tile_size, n_levels, pixels, tiles,
+                                     pix_level, pix_weight, tile_level, (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(e, "gs_fovea_prep");
+    return ok();
+}
+
+int gs_rasterize_foveated(const gs_splat *splats, const float *lvl_rgba, int32_t n,
+                          const uint8_t *qbound, int n_levels, const gs_camera *cams_host,
+                          const gs_camera *cams_dev, int n_eyes, int tile_size, const uint32_t *vals,
+                          const uint32_t *tile_ranges, const uint8_t *pix_level,
+                          const float *pix_weight, const float *bg, float *image, void *workspace,
+                          size_t workspace_bytes, void *stream)
+{
+    (void)workspace;
+    (void)workspace_bytes;
+    int r;
+    int64_t tiles = 0;
+    if ((r = check_cams(cams_host, cams_dev, n_eyes, tile_size, &tiles, nullptr))) return r;
+    if (n < 0) return fail(GS_ERR_INVALID, "n must be >= 0");
+    if (n_levels < 1 || n_levels > 4) return fail(GS_ERR_UNSUPPORTED, "n_levels %d not in 1..4", n_levels);
+    if (!tile_ranges || !pix_level || !pix_weight || !image ||
+        (n > 0 && (!splats || !lvl_rgba || !qbound || !vals)))
+        return fail(GS_ERR_INVALID, "NULL output or input pointer");
+    if (!aligned(splats, 16) || !aligned(lvl_rgba, 16))
+        return fail(GS_ERR_INVALID, "splats and lvl_rgba must be 16-byte aligned");
+    const float zero[3] = {0.f, 0.f, 0.f};
+    hipError_t e = launch_raster_fov(splats, lvl_rgba, n, qbound, n_levels, cams_dev, n_eyes, tile_size,
+                                     tiles, vals, tile_ranges, pix_level, pix_weight, bg ? bg : zero,
+                                     image, (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(e, "gs_rasterize_foveated");
+    return ok();
+}
+
+int gs_render_foveated(const gs_scene *scene, const gs_camera *cams_host, const gs_camera *cams_dev,
+                       const gs_fovea *fov_host, int n_eyes, int tile_size, const float *bg,
+                       float *image, uint64_t key_capacity, uint64_t *num_keys, void *workspace,
+                       size_t workspace_bytes, void *stream)
+{
+    int r;
+    int64_t tiles = 0, pixels = 0;
+    if ((r = check_scene(scene, true))) return r;
+    if ((r = check_cams(cams_host, cams_dev, n_eyes, tile_size, &tiles, &pixels))) return r;
+    if (n_eyes > 8) return fail(GS_ERR_UNSUPPORTED, "at most 8 eyes (got %d)", n_eyes);
+    if (key_capacity >= (1ull << 32)) return fail(GS_ERR_UNSUPPORTED, "key_capacity must be < 2^32");
+    if (!image || !num_keys || !fov_host) return fail(GS_ERR_INVALID, "NULL output or input pointer");
+    int64_t E = (int64_t)n_eyes * scene->n;
+    if (E >= (1ll << 32)) return fail(GS_ERR_UNSUPPORTED, "n_eyes * n must be < 2^32");
+    int L = scene->n_levels;
+    size_t need = gs_render_workspace_bytes(cams_host, n_eyes, scene->n, L, tile_size, key_capacity);
+    if ((r = check_ws(workspace, workspace_bytes, need))) return r;
+    Carve c;
+    c.base = (char *)workspace;
+    RenderBufs rb;
+    carve_render(c, E, L, key_capacity, tiles, pixels, rb);
+    BinScratch bs;
+    carve_bin(c, E, key_capacity, bs);
+    if ((r = gs_fovea_prep(cams_host, cams_dev, fov_host, n_eyes, tile_size, L, rb.pix_level,
+                           rb.pix_weight, rb.tile_level, stream)))
+        return r;
+    hipStream_t st = (hipStream_t)stream;
+    hipError_t e = launch_tile_levels_lo(rb.tile_level, tiles, rb.tile_lo, st);
+    if (e != hipSuccess) return hip_fail(e, "gs_render_foveated");
+    if ((r = gs_project(scene, cams_host, cams_dev, n_eyes, tile_size, rb.splats, rb.lvl, stream)))
+        return r;
+    e = launch_bin_sort(rb.splats, scene->n, cams_dev, n_eyes, tiles, tile_bits_of(tiles), tile_size,
+                        rb.tile_lo, scene->qbound, rb.vals, nullptr, key_capacity, rb.ranges, nullptr,
+                        num_keys, bs, st);
+    if (e != hipSuccess) return hip_fail(e, "gs_render_foveated (binning)");
+    const float zero[3] = {0.f, 0.f, 0.f};
+    e = launch_raster_fov(rb.splats, rb.lvl, scene->n, scene->qbound, L, cams_dev, n_eyes, tile_size,
+                          tiles, rb.vals, rb.ranges, rb.pix_level, rb.pix_weight, bg ? bg : zero, image,
+                          st);
+    if (e != hipSuccess) return hip_fail(e, "gs_render_foveated (compositing)");
+    return ok();
+}
+
+int gs_render_fwd(const gs_scene *scene, const gs_camera *cams_host, const gs_camera *cams_dev,
+                  int n_views, int tile_size, const float *bg, gs_splat *splats, uint32_t *vals,
+                  uint32_t *tile_ranges, uint64_t key_capacity, uint64_t *num_keys, float *image,
+                  float *final_T, uint32_t *n_contrib, void *workspace, size_t workspace_bytes,
+                  void *stream)
+{
+    int r;
+    int64_t tiles = 0;
+    if ((r = check_scene(scene, false))) return r;
+    if ((r = check_cams(cams_host, cams_dev, n_views, tile_size, &tiles, nullptr))) return r;
+    if ((r = gs_project(scene, cams_host, cams_dev, n_views, tile_size, splats, nullptr, stream)))
+        return r;
+    if ((r = gs_bin_sort(splats, scene->n, cams_host, cams_dev, n_views, tile_size, nullptr, nullptr,
+                         vals, nullptr, key_capacity, tile_ranges, nullptr, num_keys, workspace,
+                         workspace_bytes, stream)))
+        return r;
+    return gs_rasterize_fwd(splats, scene->n, cams_host, cams_dev, n_views, tile_size, vals, tile_ranges,
+                            bg, image, final_T, n_contrib, nullptr, workspace, workspace_bytes, stream);
+}
+
+}  // extern "C"

@@ -1,0 +1,71 @@
+// Host-side launchers of the gfx950 kernels (internal to the library).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "gs.h"
+
+// projection
+hipError_t launch_project(const gs_scene &sc, const gs_camera *cams_dev, int V, int T,
+                          gs_splat *out, float *lvl_rgba, hipStream_t st);
+hipError_t launch_project_bwd(const gs_scene &sc, const gs_camera *cams_dev, int V,
+                              const gs_splat *splats, const gs_splat_grad *grads, float *g_means,
+                              float *g_ls, float *g_q, float *g_logit, float *g_sh, hipStream_t st);
+
+// radix sort of (u32 key, u32 value) pairs, LSD over bits [0, bits)
+struct RadixScratch {
+    uint32_t *hist;     // [4][256] digit counts, then exclusive bases
+    uint64_t *status;   // [max_parts][256] lookback words
+    uint32_t *tickets;  // [4] partition tickets, one per pass
+};
+constexpr int RS_THREADS = 256;
+constexpr int RS_ITEMS = 16;
+constexpr int RS_PART = RS_THREADS * RS_ITEMS;
+inline uint64_t radix_max_parts(uint64_t cap) { return (cap + RS_PART - 1) / RS_PART; }
+inline int radix_passes(int bits) { return (bits + 7) / 8; }
+// Sorts count (device, clamped to cap) pairs.  Input in (ka, va); the result
+// is in (ka, va) if the number of passes is even, else in (kb, vb).
+hipError_t radix_sort_pairs(uint32_t *ka, uint32_t *va, uint32_t *kb, uint32_t *vb,
+                            const uint64_t *d_count, uint64_t cap, int bits,
+                            const RadixScratch &rs, hipStream_t st);
+
+// binning
+struct BinScratch {
+    uint32_t *dkey_a, *dval_a, *dkey_b, *dval_b;  // [E] depth sort ping-pong
+    uint32_t *hits;                               // [E]
+    uint64_t *block_sums;                         // [E / SCAN_ITEMS + 1]
+    uint32_t *tkey_a, *tkey_b, *tval_b;           // [cap] tile-key sort ping-pong
+    uint64_t *counts;                             // [3]: entries, keys, key capacity
+    RadixScratch rs;
+};
+constexpr int SCAN_THREADS = 256;
+constexpr int SCAN_ITEMS = 16;
+hipError_t launch_bin_sort(const gs_splat *splats, int n, const gs_camera *cams_dev, int V,
+                           int64_t n_tiles, int tile_bits, int T, const uint8_t *tile_level_lo,
+                           const uint8_t *qbound, uint32_t *vals, uint64_t *keys, uint64_t cap,
+                           uint32_t *ranges, uint32_t *hits_out, uint64_t *num_keys,
+                           const BinScratch &bs, hipStream_t st);
+
+// compositing
+hipError_t launch_raster_fwd(const gs_splat *splats, int n, const gs_camera *cams_dev, int V, int T,
+                             int64_t n_tiles, const uint32_t *vals, const uint32_t *ranges,
+                             const float bg[3], float *image, float *final_T, uint32_t *n_contrib,
+                             uint32_t *dominated, hipStream_t st);
+hipError_t launch_raster_bwd(const gs_splat *splats, int n, const gs_camera *cams_dev, int V, int T,
+                             int64_t n_tiles, const uint32_t *vals, const uint32_t *ranges,
+                             const float bg[3], const float *final_T, const uint32_t *n_contrib,
+                             const float *dL_dimage, gs_splat_grad *grads, hipStream_t st);
+hipError_t launch_fovea_prep(const gs_camera *cams_dev, const gs_fovea *fov_host, int n_eyes, int T,
+                             int n_levels, int64_t n_pixels, int64_t n_tiles, uint8_t *pix_level,
+                             float *pix_weight, uint8_t *tile_level, hipStream_t st);
+hipError_t launch_raster_fov(const gs_splat *splats, const float *lvl_rgba, int n,
+                             const uint8_t *qbound, int n_levels, const gs_camera *cams_dev, int V,
+                             int T, int64_t n_tiles, const uint32_t *vals, const uint32_t *ranges,
+                             const uint8_t *pix_level, const float *pix_weight, const float bg[3],
+                             float *image, hipStream_t st);
+
+// utilities
+hipError_t launch_fill_u32(uint32_t *p, uint32_t value, uint64_t count, hipStream_t st);
+hipError_t launch_tile_levels_lo(const uint8_t *tile_level, int64_t n_tiles, uint8_t *lo,
+                                 hipStream_t st);

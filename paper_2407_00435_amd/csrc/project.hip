@@ -1,0 +1,460 @@
+// Projection of 3D Gaussians to screen-space splats (Section 2.1, Eq. 1b/1c)
+// and its reverse.  One thread per Gaussian; the thread loops over the views,
+// so each Gaussian's parameters are read from HBM once for all views.
+#include "common.hpp"
+#include "kernels.hpp"
+
+namespace {
+
+struct Cov3 {
+    float xx, xy, xz, yy, yz, zz;
+};
+
+struct Rot {
+    float m[9];
+};
+
+__device__ __forceinline__ Rot quat_rot(float w, float x, float y, float z)
+{
+    float inv = rsqrtf(w * w + x * x + y * y + z * z);
+    w *= inv; x *= inv; y *= inv; z *= inv;
+    Rot R;
+    R.m[0] = 1.f - 2.f * (y * y + z * z); R.m[1] = 2.f * (x * y - w * z);       R.m[2] = 2.f * (x * z + w * y);
+    R.m[3] = 2.f * (x * y + w * z);       R.m[4] = 1.f - 2.f * (x * x + z * z); R.m[5] = 2.f * (y * z - w * x);
+    R.m[6] = 2.f * (x * z - w * y);       R.m[7] = 2.f * (y * z + w * x);       R.m[8] = 1.f - 2.f * (x * x + y * y);
+    return R;
+}
+
+// Sigma = Rot diag(s^2) Rot^T
+__device__ __forceinline__ Cov3 cov3d(const Rot &R, float s0, float s1, float s2)
+{
+    float a0 = s0 * s0, a1 = s1 * s1, a2 = s2 * s2;
+    const float *m = R.m;
+    Cov3 c;
+    c.xx = m[0] * m[0] * a0 + m[1] * m[1] * a1 + m[2] * m[2] * a2;
+    c.xy = m[0] * m[3] * a0 + m[1] * m[4] * a1 + m[2] * m[5] * a2;
+    c.xz = m[0] * m[6] * a0 + m[1] * m[7] * a1 + m[2] * m[8] * a2;
+    c.yy = m[3] * m[3] * a0 + m[4] * m[4] * a1 + m[5] * m[5] * a2;
+    c.yz = m[3] * m[6] * a0 + m[4] * m[7] * a1 + m[5] * m[8] * a2;
+    c.zz = m[6] * m[6] * a0 + m[7] * m[7] * a1 + m[8] * m[8] * a2;
+    return c;
+}
+
+struct CamF {
+    int W, H;
+    float fx, fy, cx, cy, near_z;
+    float R[9], t[3];
+    float pos[3];  // camera centre -R^T t
+    float limx, limy;
+};
+
+__device__ __forceinline__ CamF load_cam(const gs_camera *__restrict__ cams, int v)
+{
+    CamF c;
+    const gs_camera &g = cams[v];
+    c.W = g.width; c.H = g.height;
+    c.fx = g.fx; c.fy = g.fy; c.cx = g.cx; c.cy = g.cy; c.near_z = g.near_z;
+#pragma unroll
+    for (int k = 0; k < 9; ++k) c.R[k] = g.R[k];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) c.t[k] = g.t[k];
+#pragma unroll
+    for (int j = 0; j < 3; ++j) c.pos[j] = -(c.R[j] * c.t[0] + c.R[3 + j] * c.t[1] + c.R[6 + j] * c.t[2]);
+    c.limx = 1.3f * (0.5f * (float)c.W / c.fx);
+    c.limy = 1.3f * (0.5f * (float)c.H / c.fy);
+    return c;
+}
+
+// Load the (DEG+1)^2 x 3 SH coefficients of one Gaussian.
+template <int DEG>
+__device__ __forceinline__ void load_sh(const float *__restrict__ sh, int64_t i, float *c)
+{
+    constexpr int NC = (DEG + 1) * (DEG + 1) * 3;
+    const float *p = sh + i * NC;
+    if constexpr (NC % 4 == 0) {
+        const float4 *p4 = reinterpret_cast<const float4 *>(p);
+#pragma unroll
+        for (int k = 0; k < NC / 4; ++k) {
+            float4 q = p4[k];
+            c[4 * k] = q.x; c[4 * k + 1] = q.y; c[4 * k + 2] = q.z; c[4 * k + 3] = q.w;
+        }
+    } else {
+#pragma unroll
+        for (int k = 0; k < NC; ++k) c[k] = p[k];
+    }
+}
+
+__device__ __forceinline__ float sigmoidf(float x) { return 1.0f / (1.0f + __expf(-x)); }
+
+template <int DEG, bool LEVELS>
+__global__ void __launch_bounds__(256)
+k_project(const float *__restrict__ means, const float *__restrict__ log_scales,
+          const float *__restrict__ quats, const float *__restrict__ logits,
+          const float *__restrict__ sh, const float *__restrict__ lvl_logits,
+          const float *__restrict__ lvl_dc, int L, const gs_camera *__restrict__ cams, int V,
+          int T, int n, gs_splat *__restrict__ out, float4 *__restrict__ lvl_out)
+{
+    constexpr int K = (DEG + 1) * (DEG + 1);
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    float mx = means[3 * (int64_t)i], my = means[3 * (int64_t)i + 1], mz = means[3 * (int64_t)i + 2];
+    float4 q = reinterpret_cast<const float4 *>(quats)[i];
+    Rot Rq = quat_rot(q.x, q.y, q.z, q.w);
+    Cov3 S = cov3d(Rq, __expf(log_scales[3 * (int64_t)i]), __expf(log_scales[3 * (int64_t)i + 1]),
+                   __expf(log_scales[3 * (int64_t)i + 2]));
+    float opacity = sigmoidf(logits[i]);
+    float coef[K * 3];
+    load_sh<DEG>(sh, i, coef);
+    float lvl_op[4], lvl_dcv[4][3];
+    if (LEVELS) {
+        for (int t = 0; t < L; ++t) {
+            lvl_op[t] = lvl_logits ? sigmoidf(lvl_logits[(int64_t)t * n + i]) : opacity;
+            for (int ch = 0; ch < 3; ++ch)
+                lvl_dcv[t][ch] = lvl_dc ? lvl_dc[((int64_t)t * n + i) * 3 + ch] : coef[ch];
+        }
+    }
+    for (int v = 0; v < V; ++v) {
+        CamF c = load_cam(cams, v);
+        int64_t e = (int64_t)v * n + i;
+        float4 *o4 = reinterpret_cast<float4 *>(out + e);
+        float ux = c.R[0] * mx + c.R[1] * my + c.R[2] * mz + c.t[0];
+        float uy = c.R[3] * mx + c.R[4] * my + c.R[5] * mz + c.t[1];
+        float uz = c.R[6] * mx + c.R[7] * my + c.R[8] * mz + c.t[2];
+        bool ok = uz > c.near_z;
+        float a = 0.f, b = 0.f, cc = 0.f, det = 0.f;
+        if (ok) {
+            float iz = 1.0f / uz;
+            float tx = fminf(c.limx, fmaxf(-c.limx, ux * iz));
+            float ty = fminf(c.limy, fmaxf(-c.limy, uy * iz));
+            float j00 = c.fx * iz, j02 = -c.fx * tx * iz;
+            float j11 = c.fy * iz, j12 = -c.fy * ty * iz;
+            // T = J Rc (2x3)
+            float t00 = j00 * c.R[0] + j02 * c.R[6], t01 = j00 * c.R[1] + j02 * c.R[7],
+                  t02 = j00 * c.R[2] + j02 * c.R[8];
+            float t10 = j11 * c.R[3] + j12 * c.R[6], t11 = j11 * c.R[4] + j12 * c.R[7],
+                  t12 = j11 * c.R[5] + j12 * c.R[8];
+            // rows of T Sigma
+            float p0 = t00 * S.xx + t01 * S.xy + t02 * S.xz;
+            float p1 = t00 * S.xy + t01 * S.yy + t02 * S.yz;
+            float p2 = t00 * S.xz + t01 * S.yz + t02 * S.zz;
+            float r0 = t10 * S.xx + t11 * S.xy + t12 * S.xz;
+            float r1 = t10 * S.xy + t11 * S.yy + t12 * S.yz;
+            float r2 = t10 * S.xz + t11 * S.yz + t12 * S.zz;
+            a = p0 * t00 + p1 * t01 + p2 * t02 + 0.3f;
+            b = p0 * t10 + p1 * t11 + p2 * t12;
+            cc = r0 * t10 + r1 * t11 + r2 * t12 + 0.3f;
+            det = a * cc - b * b;
+            ok = det > 0.0f;
+        }
+        if (!ok) {
+            float4 z = make_float4(0.f, 0.f, 0.f, 0.f);
+            o4[0] = z;
+            o4[1] = z;
+            o4[2] = z;
+            if (LEVELS)
+                for (int t = 0; t < L; ++t) lvl_out[e * L + t] = z;
+            continue;
+        }
+        float idet = 1.0f / det;
+        float mid = 0.5f * (a + cc);
+        float lmax = mid + sqrtf(fmaxf(mid * mid - det, 0.0f));
+        int radius = (int)ceilf(3.0f * sqrtf(lmax));
+        float px = c.fx * ux / uz + c.cx;
+        float py = c.fy * uy / uz + c.cy;
+        TileRect rect;
+        uint32_t tiles = 0;
+        if (tile_rect(px, py, radius, c.W, c.H, T, rect))
+            tiles = (uint32_t)(rect.tx1 - rect.tx0 + 1) * (uint32_t)(rect.ty1 - rect.ty0 + 1);
+        // colour from the unit direction camera -> mean
+        float dx = mx - c.pos[0], dy = my - c.pos[1], dz = mz - c.pos[2];
+        float inv = rsqrtf(dx * dx + dy * dy + dz * dz);
+        dx *= inv; dy *= inv; dz *= inv;
+        float Y[K];
+        sh_basis<DEG>(dx, dy, dz, Y);
+        float rest[3];
+#pragma unroll
+        for (int ch = 0; ch < 3; ++ch) {
+            float s = 0.f;
+#pragma unroll
+            for (int k = 1; k < K; ++k) s += coef[3 * k + ch] * Y[k];
+            rest[ch] = s + 0.5f;
+        }
+        float col[3];
+#pragma unroll
+        for (int ch = 0; ch < 3; ++ch) col[ch] = fmaxf(0.0f, coef[ch] * SH_C0 + rest[ch]);
+        o4[0] = make_float4(px, py, cc * idet, -b * idet);
+        o4[1] = make_float4(a * idet, opacity, col[0], col[1]);
+        o4[2] = make_float4(col[2], uz, __int_as_float(radius), __uint_as_float(tiles));
+        if (LEVELS) {
+            for (int t = 0; t < L; ++t) {
+                lvl_out[e * L + t] = make_float4(fmaxf(0.0f, lvl_dcv[t][0] * SH_C0 + rest[0]),
+                                                 fmaxf(0.0f, lvl_dcv[t][1] * SH_C0 + rest[1]),
+                                                 fmaxf(0.0f, lvl_dcv[t][2] * SH_C0 + rest[2]),
+                                                 lvl_op[t]);
+            }
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Reverse of the projection.  For every view the forward quantities are
+// recomputed and the splat gradient is pushed back through
+//   conic = inverse(S'), S' = T Sigma T^T + 0.3 I, T = J Rc,
+//   J(u) with the clamped tangents, mean2d(u), u = Rc mu + t,
+//   Sigma = (Rq S)(Rq S)^T, Rq of the normalised quaternion,
+//   colour = max(0, sum sh Y(dir) + 1/2), opacity = sigmoid(logit).
+template <int DEG>
+__global__ void __launch_bounds__(256)
+k_project_bwd(const float *__restrict__ means, const float *__restrict__ log_scales,
+              const float *__restrict__ quats, const float *__restrict__ logits,
+              const float *__restrict__ sh, const gs_camera *__restrict__ cams, int V, int n,
+              const gs_splat *__restrict__ splats, const gs_splat_grad *__restrict__ grads,
+              float *__restrict__ g_means, float *__restrict__ g_ls, float *__restrict__ g_q,
+              float *__restrict__ g_logit, float *__restrict__ g_sh)
+{
+    constexpr int K = (DEG + 1) * (DEG + 1);
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    float mx = means[3 * (int64_t)i], my = means[3 * (int64_t)i + 1], mz = means[3 * (int64_t)i + 2];
+    float4 q4 = reinterpret_cast<const float4 *>(quats)[i];
+    float qn_inv = rsqrtf(q4.x * q4.x + q4.y * q4.y + q4.z * q4.z + q4.w * q4.w);
+    float qw = q4.x * qn_inv, qx = q4.y * qn_inv, qy = q4.z * qn_inv, qz = q4.w * qn_inv;
+    Rot Rq = quat_rot(q4.x, q4.y, q4.z, q4.w);
+    float s[3] = {__expf(log_scales[3 * (int64_t)i]), __expf(log_scales[3 * (int64_t)i + 1]),
+                  __expf(log_scales[3 * (int64_t)i + 2])};
+    // M = Rq diag(s); Sigma = M M^T
+    float M[9];
+#pragma unroll
+    for (int r = 0; r < 3; ++r)
+#pragma unroll
+        for (int k = 0; k < 3; ++k) M[r * 3 + k] = Rq.m[r * 3 + k] * s[k];
+    float Sg[9];
+#pragma unroll
+    for (int r = 0; r < 3; ++r)
+#pragma unroll
+        for (int k = 0; k < 3; ++k)
+            Sg[r * 3 + k] = M[r * 3] * M[k * 3] + M[r * 3 + 1] * M[k * 3 + 1] + M[r * 3 + 2] * M[k * 3 + 2];
+    float coef[K * 3];
+    load_sh<DEG>(sh, i, coef);
+    float opacity = sigmoidf(logits[i]);
+
+    float gm[3] = {0.f, 0.f, 0.f};
+    float dSig[9];
+#pragma unroll
+    for (int k = 0; k < 9; ++k) dSig[k] = 0.f;
+    float gsh[K * 3];
+#pragma unroll
+    for (int k = 0; k < K * 3; ++k) gsh[k] = 0.f;
+    float glogit = 0.f;
+
+    for (int v = 0; v < V; ++v) {
+        int64_t e = (int64_t)v * n + i;
+        const gs_splat &sp = splats[e];
+        if (sp.radius <= 0) continue;
+        const gs_splat_grad &g = grads[e];
+        CamF c = load_cam(cams, v);
+        float ux = c.R[0] * mx + c.R[1] * my + c.R[2] * mz + c.t[0];
+        float uy = c.R[3] * mx + c.R[4] * my + c.R[5] * mz + c.t[1];
+        float uz = c.R[6] * mx + c.R[7] * my + c.R[8] * mz + c.t[2];
+        // opacity
+        glogit += g.opacity * opacity * (1.0f - opacity);
+        // colour -> SH coefficients and direction
+        float ddx = mx - c.pos[0], ddy = my - c.pos[1], ddz = mz - c.pos[2];
+        float dist_inv = rsqrtf(ddx * ddx + ddy * ddy + ddz * ddz);
+        float dx = ddx * dist_inv, dy = ddy * dist_inv, dz = ddz * dist_inv;
+        float Y[K];
+        sh_basis<DEG>(dx, dy, dz, Y);
+        float gc[3] = {g.r, g.g, g.b};
+        float gdir[3] = {0.f, 0.f, 0.f};
+        float Yx[K], Yy[K], Yz[K];
+        if (DEG > 0) sh_basis_grad<DEG>(dx, dy, dz, Yx, Yy, Yz);
+#pragma unroll
+        for (int ch = 0; ch < 3; ++ch) {
+            float raw = 0.5f;
+#pragma unroll
+            for (int k = 0; k < K; ++k) raw += coef[3 * k + ch] * Y[k];
+            if (!(raw > 0.0f)) continue;
+#pragma unroll
+            for (int k = 0; k < K; ++k) {
+                gsh[3 * k + ch] += gc[ch] * Y[k];
+                if (DEG > 0) {
+                    gdir[0] += gc[ch] * coef[3 * k + ch] * Yx[k];
+                    gdir[1] += gc[ch] * coef[3 * k + ch] * Yy[k];
+                    gdir[2] += gc[ch] * coef[3 * k + ch] * Yz[k];
+                }
+            }
+        }
+        if (DEG > 0) {
+            float pr = dx * gdir[0] + dy * gdir[1] + dz * gdir[2];
+            gm[0] += (gdir[0] - dx * pr) * dist_inv;
+            gm[1] += (gdir[1] - dy * pr) * dist_inv;
+            gm[2] += (gdir[2] - dz * pr) * dist_inv;
+        }
+        // conic (A, B, C) -> S' = [[a, b], [b, cc]]
+        float A = sp.conic_a, B = sp.conic_b, C = sp.conic_c;
+        // dL/dS' = -M G M with G the symmetric gradient of [[A, B], [B, C]]
+        float GA = g.conic_a, GB = 0.5f * g.conic_b, GC = g.conic_c;
+        // M G
+        float mg00 = A * GA + B * GB, mg01 = A * GB + B * GC;
+        float mg10 = B * GA + C * GB, mg11 = B * GB + C * GC;
+        float dS00 = -(mg00 * A + mg01 * B);
+        float dS01 = -(mg00 * B + mg01 * C);
+        float dS11 = -(mg10 * B + mg11 * C);
+        // recompute T = J Rc
+        float iz = 1.0f / uz;
+        float rx = ux * iz, ry = uy * iz;
+        float tx = fminf(c.limx, fmaxf(-c.limx, rx));
+        float ty = fminf(c.limy, fmaxf(-c.limy, ry));
+        float j00 = c.fx * iz, j02 = -c.fx * tx * iz;
+        float j11 = c.fy * iz, j12 = -c.fy * ty * iz;
+        float T0[3] = {j00 * c.R[0] + j02 * c.R[6], j00 * c.R[1] + j02 * c.R[7], j00 * c.R[2] + j02 * c.R[8]};
+        float T1[3] = {j11 * c.R[3] + j12 * c.R[6], j11 * c.R[4] + j12 * c.R[7], j11 * c.R[5] + j12 * c.R[8]};
+        // dSigma += T^T dS T  (dS symmetric)
+#pragma unroll
+        for (int r = 0; r < 3; ++r)
+#pragma unroll
+            for (int k = 0; k < 3; ++k)
+                dSig[r * 3 + k] += T0[r] * (dS00 * T0[k] + dS01 * T1[k]) + T1[r] * (dS01 * T0[k] + dS11 * T1[k]);
+        // dT = 2 dS T Sigma
+        float TS0[3], TS1[3];
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            TS0[k] = T0[0] * Sg[k] + T0[1] * Sg[3 + k] + T0[2] * Sg[6 + k];
+            TS1[k] = T1[0] * Sg[k] + T1[1] * Sg[3 + k] + T1[2] * Sg[6 + k];
+        }
+        float dT0[3], dT1[3];
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            dT0[k] = 2.0f * (dS00 * TS0[k] + dS01 * TS1[k]);
+            dT1[k] = 2.0f * (dS01 * TS0[k] + dS11 * TS1[k]);
+        }
+        // dJ = dT Rc^T: J entries (0,0), (0,2), (1,1), (1,2)
+        float dJ00 = dT0[0] * c.R[0] + dT0[1] * c.R[1] + dT0[2] * c.R[2];
+        float dJ02 = dT0[0] * c.R[6] + dT0[1] * c.R[7] + dT0[2] * c.R[8];
+        float dJ11 = dT1[0] * c.R[3] + dT1[1] * c.R[4] + dT1[2] * c.R[5];
+        float dJ12 = dT1[0] * c.R[6] + dT1[1] * c.R[7] + dT1[2] * c.R[8];
+        float iz2 = iz * iz;
+        float gux = 0.f, guy = 0.f, guz = 0.f;
+        guz += -dJ00 * c.fx * iz2 - dJ11 * c.fy * iz2;
+        bool inx = rx > -c.limx && rx < c.limx;
+        bool iny = ry > -c.limy && ry < c.limy;
+        // J02 = -fx tx / z, tx = x / z when not clamped
+        if (inx) {
+            gux += dJ02 * (-c.fx * iz2);
+            guz += dJ02 * (2.0f * c.fx * ux * iz2 * iz);
+        } else {
+            guz += dJ02 * (c.fx * tx * iz2);
+        }
+        if (iny) {
+            guy += dJ12 * (-c.fy * iz2);
+            guz += dJ12 * (2.0f * c.fy * uy * iz2 * iz);
+        } else {
+            guz += dJ12 * (c.fy * ty * iz2);
+        }
+        // mean2d = (fx x / z + cx, fy y / z + cy)
+        gux += g.mean_x * c.fx * iz;
+        guy += g.mean_y * c.fy * iz;
+        guz += -(g.mean_x * c.fx * ux + g.mean_y * c.fy * uy) * iz2;
+        // u = Rc mu + t
+        gm[0] += c.R[0] * gux + c.R[3] * guy + c.R[6] * guz;
+        gm[1] += c.R[1] * gux + c.R[4] * guy + c.R[7] * guz;
+        gm[2] += c.R[2] * gux + c.R[5] * guy + c.R[8] * guz;
+    }
+    // Sigma = M M^T: dM = (dSig + dSig^T) M
+    float dM[9];
+#pragma unroll
+    for (int r = 0; r < 3; ++r)
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            float acc = 0.f;
+#pragma unroll
+            for (int l = 0; l < 3; ++l) acc += (dSig[r * 3 + l] + dSig[l * 3 + r]) * M[l * 3 + k];
+            dM[r * 3 + k] = acc;
+        }
+    // M = Rq diag(s)
+    float dR[9];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        float ds = dM[k] * Rq.m[k] + dM[3 + k] * Rq.m[3 + k] + dM[6 + k] * Rq.m[6 + k];
+        g_ls[3 * (int64_t)i + k] = ds * s[k];
+#pragma unroll
+        for (int r = 0; r < 3; ++r) dR[r * 3 + k] = dM[r * 3 + k] * s[k];
+    }
+    float w = qw, x = qx, y = qy, z = qz;
+    float dw = 2.f * (-z * dR[1] + y * dR[2] + z * dR[3] - x * dR[5] - y * dR[6] + x * dR[7]);
+    float dxq = 2.f * (y * dR[1] + z * dR[2] + y * dR[3] - 2.f * x * dR[4] - w * dR[5] + z * dR[6] +
+                       w * dR[7] - 2.f * x * dR[8]);
+    float dyq = 2.f * (-2.f * y * dR[0] + x * dR[1] + w * dR[2] + x * dR[3] + z * dR[5] - w * dR[6] +
+                       z * dR[7] - 2.f * y * dR[8]);
+    float dzq = 2.f * (-2.f * z * dR[0] - w * dR[1] + x * dR[2] + w * dR[3] - 2.f * z * dR[4] +
+                       y * dR[5] + x * dR[6] + y * dR[7]);
+    float pr = w * dw + x * dxq + y * dyq + z * dzq;
+    float4 gq = make_float4((dw - w * pr) * qn_inv, (dxq - x * pr) * qn_inv, (dyq - y * pr) * qn_inv,
+                            (dzq - z * pr) * qn_inv);
+    reinterpret_cast<float4 *>(g_q)[i] = gq;
+    g_means[3 * (int64_t)i] = gm[0];
+    g_means[3 * (int64_t)i + 1] = gm[1];
+    g_means[3 * (int64_t)i + 2] = gm[2];
+    g_logit[i] = glogit;
+    float *gs_out = g_sh + (int64_t)i * K * 3;
+    if constexpr ((K * 3) % 4 == 0) {
+        float4 *p4 = reinterpret_cast<float4 *>(gs_out);
+#pragma unroll
+        for (int k = 0; k < K * 3 / 4; ++k)
+            p4[k] = make_float4(gsh[4 * k], gsh[4 * k + 1], gsh[4 * k + 2], gsh[4 * k + 3]);
+    } else {
+#pragma unroll
+        for (int k = 0; k < K * 3; ++k) gs_out[k] = gsh[k];
+    }
+}
+
+}  // namespace
+
+hipError_t launch_project(const gs_scene &sc, const gs_camera *cams_dev, int V, int T,
+                          gs_splat *out, float *lvl_rgba, hipStream_t st)
+{
+    int n = sc.n;
+    if (n == 0) return hipSuccess;
+    dim3 grid((n + 255) / 256), block(256);
+    int L = sc.n_levels;
+    bool lv = lvl_rgba != nullptr && L > 0;
+    float4 *lo = reinterpret_cast<float4 *>(lvl_rgba);
+#define GS_PROJ(DEG)                                                                                   \
+    if (lv)                                                                                            \
+        hipLaunchKernelGGL((k_project<DEG, true>), grid, block, 0, st, sc.means, sc.log_scales,       \
+                           sc.quats, sc.opacity_logits, sc.sh, sc.lvl_opacity_logits, sc.lvl_sh_dc,  \
+                           L, cams_dev, V, T, n, out, lo);                                             \
+    else                                                                                               \
+        hipLaunchKernelGGL((k_project<DEG, false>), grid, block, 0, st, sc.means, sc.log_scales,      \
+                           sc.quats, sc.opacity_logits, sc.sh, nullptr, nullptr, 0, cams_dev, V, T,   \
+                           n, out, nullptr);
+    switch (sc.sh_degree) {
+    case 0: GS_PROJ(0); break;
+    case 1: GS_PROJ(1); break;
+    case 2: GS_PROJ(2); break;
+    default: GS_PROJ(3); break;
+    }
+#undef GS_PROJ
+    return hipGetLastError();
+}
+
+hipError_t launch_project_bwd(const gs_scene &sc, const gs_camera *cams_dev, int V,
+                              const gs_splat *splats, const gs_splat_grad *grads, float *g_means,
+                              float *g_ls, float *g_q, float *g_logit, float *g_sh, hipStream_t st)
+{
+    int n = sc.n;
+    if (n == 0) return hipSuccess;
+    dim3 grid((n + 255) / 256), block(256);
+#define GS_PB(DEG)                                                                                     \
+    hipLaunchKernelGGL((k_project_bwd<DEG>), grid, block, 0, st, sc.means, sc.log_scales, sc.quats,  \
+                       sc.opacity_logits, sc.sh, cams_dev, V, n, splats, grads, g_means, g_ls, g_q,   \
+                       g_logit, g_sh);
+    switch (sc.sh_degree) {
+    case 0: GS_PB(0); break;
+    case 1: GS_PB(1); break;
+    case 2: GS_PB(2); break;
+    default: GS_PB(3); break;
+    }
+#undef GS_PB
+    return hipGetLastError();
+}

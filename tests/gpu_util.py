@@ -1,0 +1,77 @@
+"""Helpers shared by the GPU parity tests (no renderer arithmetic here)."""
+from __future__ import annotations
+
+import numpy as np
+import pytest
+import torch
+
+IMG_TOL = 2e-4  # per-channel absolute image tolerance against the oracle
+
+
+def need_gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("needs an MI355X")
+
+
+def say(*a):
+    print("[case]", *a, flush=True)
+
+
+def splat_np(splats: torch.Tensor) -> dict:
+    """float32 splat tensor [V, n, 12] -> numpy fields (float32 / int32)."""
+    s = splats.detach().cpu().contiguous()
+    f = s.numpy()
+    i = s.view(torch.int32).numpy()
+    return dict(mean2d=f[..., 0:2].copy(), conic=f[..., 2:5].copy(), opacity=f[..., 5].copy(),
+                color=f[..., 6:9].copy(), depth=f[..., 9].copy(), radius=i[..., 10].copy(),
+                tiles_touched=i[..., 11].copy())
+
+
+def view_slice(sp: dict, v: int) -> dict:
+    return {k: a[v] for k, a in sp.items()}
+
+
+def image_views(img: torch.Tensor, sizes) -> list:
+    """Planar global image buffer -> list of (H, W, 3) numpy arrays."""
+    a = img.detach().cpu().numpy()
+    out, off = [], 0
+    for w, h in sizes:
+        out.append(a[off:off + 3 * w * h].reshape(3, h, w).transpose(1, 2, 0))
+        off += 3 * w * h
+    return out
+
+
+def pixel_views(buf: torch.Tensor, sizes) -> list:
+    a = buf.detach().cpu().numpy()
+    out, off = [], 0
+    for w, h in sizes:
+        out.append(a[off:off + w * h].reshape(h, w))
+        off += w * h
+    return out
+
+
+def check_envelope(gpu_rgb, ref: dict, tol=IMG_TOL, max_unresolved_frac=1e-4):
+    """GPU pixel values must lie within tol of the oracle's envelope over all
+    threshold-consistent branches.  Returns (max error vs primary branch,
+    #ambiguous pixels)."""
+    lo = ref["rgb_min"] - tol
+    hi = ref["rgb_max"] + tol
+    bad = (gpu_rgb < lo) | (gpu_rgb > hi)
+    unresolved = (ref["amb"] & 4) != 0
+    bad_px = bad.any(axis=-1) & ~unresolved
+    n_bad = int(bad_px.sum())
+    if n_bad:
+        idx = np.argwhere(bad_px)[:5]
+        detail = [(tuple(int(x) for x in ij), gpu_rgb[tuple(ij)].tolist(), ref["rgb"][tuple(ij)].tolist())
+                  for ij in idx]
+        raise AssertionError(f"{n_bad} pixels outside the oracle envelope (+-{tol}): {detail}")
+    assert unresolved.sum() <= max(1, max_unresolved_frac * unresolved.size)
+    amb = (ref["amb"] & 1) != 0
+    err = np.abs(gpu_rgb - ref["rgb"])
+    return float(err[~amb].max(initial=0.0)), int(amb.sum())
+
+
+def rel_l2(a, b):
+    a = np.asarray(a, np.float64).ravel()
+    b = np.asarray(b, np.float64).ravel()
+    return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-30))
