@@ -1,0 +1,302 @@
+#!/usr/bin/env python3
+"""Benchmark of the foveated stereo render on one MI355X.
+
+Workload: 1.5M clustered Gaussians with degree-3 SH, nested quality subsets
+(100/40/15/5 %) with per-level opacity and DC, two eyes at 1920x1080 with a
+shared gaze, four eccentricity rings with 3.5 degree blend bands, 16x16 tiles.
+One step = one pass of the whole path over both eyes: foveation tables,
+projection (with per-level versions), filtered binning and (tile, depth)
+sort, foveated compositing.  Inputs are resident in HBM before timing.
+
+Prints ONE JSON line (stdout).  Also reported, untimed in the headline:
+plain forward at 1280x720 / 500k, forward+backward at 1280x720 / 1M, the
+FP64 oracle's rate on the host (bounded sample), and the roofline of the
+dominant kernel (foveated compositing) from live HIP-event timings.
+"""
+from __future__ import annotations
+
+import argparse
+import ctypes
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "FPS & Mpix/s fwd, 1080p 1.5M Gaussians; fwd+bwd it/s; batched vs plain"
+# dense fp32 vector peak of MI355X (256 CUs, 2.4 GHz); see the design doc
+FP32_PEAK_TFLOPS = 157.3
+# algorithmic fp32 flops of one blended (pixel, point) pair (FMA = 2): offsets 2,
+# quadratic falloff 8, exp2 1, clamp 1, cut-off test 1, transmittance 2, stop
+# test 1, weight 1, colour 6
+FLOPS_PER_BLEND = 23
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+class Foveated:
+    """Preallocated buffers and stage calls for the foveated stereo render."""
+
+    def __init__(self, g, wl, tile=16):
+        import torch
+        self.g, self.torch, self.tile = g, torch, tile
+        self.S = g.SceneTensors(wl.scene)
+        self.C = g.Cameras(wl.cams)
+        self.fov = g.binding._foveae(wl.foveae)
+        self.L = self.S.n_levels
+        self.n = self.S.n
+        dev = self.S.t["means"].device
+        self.n_tiles, self.n_px = self.C.tiles(tile)
+        V = self.C.n
+        self.splats = torch.empty((V, self.n, 12), dtype=torch.float32, device=dev)
+        self.lvl = torch.empty((V, self.n, self.L, 4), dtype=torch.float32, device=dev)
+        self.pix_level = torch.empty(self.n_px, dtype=torch.uint8, device=dev)
+        self.pix_weight = torch.empty(self.n_px, dtype=torch.float32, device=dev)
+        self.tile_level = torch.empty((self.n_tiles, 2), dtype=torch.uint8, device=dev)
+        self.ranges = torch.empty((self.n_tiles, 2), dtype=torch.int32, device=dev)
+        self.num = torch.zeros(1, dtype=torch.int64, device=dev)
+        self.image = torch.empty(3 * self.n_px, dtype=torch.float32, device=dev)
+        self.scene_struct = self.S.struct(levels=True)
+        # key capacity: the unfiltered rectangle count bounds the filtered keys
+        self.project()
+        torch.cuda.synchronize()
+        tt = self.splats[..., 11].view(torch.int32).to(torch.int64).sum().item()
+        self.cap = int(tt)
+        self.vals = torch.empty(self.cap, dtype=torch.int32, device=dev)
+        nb = g.gs_workspace_bytes(self.C, self.n, tile, self.cap)
+        self.ws_t, self.ws, self.wsn = g.binding._ws(nb)
+        self.bg = (ctypes.c_float * 3)(0.0, 0.0, 0.0)
+        self.stream = g.binding._stream()
+
+    def fovea(self):
+        L, B, g = self.g.lib(), self.g.binding, self
+        B._check(L.gs_fovea_prep(g.C.hp, g.C.dp, ctypes.cast(g.fov, B._PF), g.C.n, g.tile, g.L,
+                                 B._ptr(g.pix_level), B._ptr(g.pix_weight), B._ptr(g.tile_level),
+                                 g.stream))
+
+    def project(self):
+        L, B = self.g.lib(), self.g.binding
+        B._check(L.gs_project(ctypes.byref(self.scene_struct), self.C.hp, self.C.dp, self.C.n, self.tile,
+                              B._ptr(self.splats), B._ptr(self.lvl), B._stream()))
+
+    def binsort(self):
+        L, B, g = self.g.lib(), self.g.binding, self
+        B._check(L.gs_bin_sort(B._ptr(g.splats), g.n, g.C.hp, g.C.dp, g.C.n, g.tile,
+                               B._ptr(g.tile_level), B._ptr(g.S.t["qbound"]), B._ptr(g.vals), None,
+                               g.cap, B._ptr(g.ranges), None, B._ptr(g.num), g.ws, g.wsn, g.stream))
+
+    def raster(self, stats=None):
+        L, B, g = self.g.lib(), self.g.binding, self
+        B._check(L.gs_rasterize_foveated(B._ptr(g.splats), B._ptr(g.lvl), g.n, B._ptr(g.S.t["qbound"]),
+                                         g.L, g.C.hp, g.C.dp, g.C.n, g.tile, B._ptr(g.vals),
+                                         B._ptr(g.ranges), B._ptr(g.pix_level), B._ptr(g.pix_weight),
+                                         ctypes.cast(g.bg, B._VP), B._ptr(g.image), B._ptr(stats), None,
+                                         0, g.stream))
+
+    STAGES = ("fovea", "project", "binsort", "raster")
+
+
+def time_foveated(fr, steps, warmup):
+    torch = fr.torch
+    for _ in range(warmup):
+        for s in fr.STAGES:
+            getattr(fr, s)()
+    torch.cuda.synchronize()
+    ev = [[torch.cuda.Event(enable_timing=True) for _ in range(len(fr.STAGES) + 1)]
+          for _ in range(steps)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(steps):
+        ev[k][0].record()
+        for j, s in enumerate(fr.STAGES):
+            getattr(fr, s)()
+            ev[k][j + 1].record()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    stage_ms = {s: sum(ev[k][j].elapsed_time(ev[k][j + 1]) for k in range(steps)) / steps
+                for j, s in enumerate(fr.STAGES)}
+    return wall, stage_ms
+
+
+def raster_stats(fr):
+    torch = fr.torch
+    st = torch.zeros(4, dtype=torch.int64, device=fr.image.device)
+    fr.raster(stats=st)
+    torch.cuda.synchronize()
+    return [int(x) for x in st.cpu().tolist()]
+
+
+def plain_fwd_rate(g, wl, steps, warmup, tile=16):
+    """Plain forward (projection, binning/sort, compositing) of one view."""
+    import torch
+    S, C = g.SceneTensors(wl.scene), g.Cameras(wl.cams)
+    splats = g.gs_project(S, C, tile)
+    cap = int(splats[..., 11].view(torch.int32).to(torch.int64).sum().item())
+    ws = None
+    for _ in range(warmup):
+        out = g.gs_render_fwd(S, C, tile, key_capacity=cap, workspace=ws)
+        ws = out["workspace"]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        out = g.gs_render_fwd(S, C, tile, key_capacity=cap, workspace=ws)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / steps
+    px = sum(w * h for w, h in C.sizes)
+    return dict(fps=1.0 / dt, mpix_s=px / dt / 1e6, ms=dt * 1e3, keys=int(out["num_keys"].item()))
+
+
+def fwd_bwd_rate(g, wl, steps, warmup, tile=16):
+    """Forward + backward (L1 loss against a target render) through autograd."""
+    import torch
+    S, C = g.SceneTensors(wl.scene), g.Cameras(wl.cams)
+    tgt_S = g.SceneTensors(wl.extra["target_scene"])
+    with torch.no_grad():
+        target = g.render(*(tgt_S.t[k] for k in ("means", "log_scales", "quats", "opacity_logits", "sh")),
+                          C, tgt_S.sh_degree, tile)
+    params = [S.t[k].clone().requires_grad_(True)
+              for k in ("means", "log_scales", "quats", "opacity_logits", "sh")]
+    splats = g.gs_project(S, C, tile)
+    cap = int(splats[..., 11].view(torch.int32).to(torch.int64).sum().item())
+
+    def it():
+        img = g.render(*params, C, S.sh_degree, tile, key_capacity=cap)
+        loss = (img - target).abs().mean()
+        loss.backward()
+        for p in params:
+            p.grad = None
+
+    for _ in range(warmup):
+        it()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        it()
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / steps
+    return dict(it_s=1.0 / dt, ms=dt * 1e3)
+
+
+def cpu_baseline(fr, wl, n_gauss_sample=12000, px_sample=(3000, 9000), threads=16):
+    """FP64 oracle on the host, on a bounded sample of the same workload:
+    projection (with the four level versions) of a random subset of the
+    Gaussians for both eyes, and per-pixel foveated compositing of random
+    pixels over the full projected splat set.  The per-Gaussian and per-pixel
+    costs are extrapolated to a whole stereo frame."""
+    import numpy as np
+    import oracle
+    threads = max(1, min(threads, os.cpu_count() or 1))
+    rng = np.random.default_rng(0)
+    sub = wl.scene.subset(rng.choice(wl.scene.n, n_gauss_sample, replace=False))
+    t0 = time.perf_counter()
+    for cam in wl.cams:
+        oracle.project(sub, cam, levels=True)
+    t_proj = (time.perf_counter() - t0) / (n_gauss_sample * len(wl.cams))
+    sp = fr.splats.cpu().numpy()
+    spi = fr.splats.cpu().view(fr.torch.int32).numpy()
+    lv = fr.lvl.cpu().numpy()
+    pl = fr.pix_level.cpu().numpy()
+    pw = fr.pix_weight.cpu().numpy().astype(np.float64)
+    per_px, fixed = [], []
+    off = 0
+    for v, cam in enumerate(wl.cams):
+        W, H = cam.width, cam.height
+        proj = dict(mean2d=sp[v, :, 0:2], conic=sp[v, :, 2:5], depth=sp[v, :, 9], opacity=sp[v, :, 5],
+                    color=sp[v, :, 6:9], radius=spi[v, :, 10],
+                    lvl_opacity=lv[v, :, :, 3].T.copy(), lvl_color=lv[v, :, :, 0:3].transpose(1, 0, 2).copy())
+        proj = oracle.splats_to_proj(proj)
+        ts = []
+        for k in px_sample:
+            pix = np.stack([rng.integers(0, W, k), rng.integers(0, H, k)], 1)
+            t0 = time.perf_counter()
+            oracle.composite(proj, W, H, qbound=wl.scene.qbound, pix_lo=pl[off:off + W * H],
+                             pix_w=pw[off:off + W * H], levels=True, pixels=pix, nthreads=threads)
+            ts.append(time.perf_counter() - t0)
+        a = (ts[1] - ts[0]) / (px_sample[1] - px_sample[0])
+        per_px.append(max(a, 0.0))
+        fixed.append(max(ts[0] - a * px_sample[0], 0.0))
+        off += W * H
+    frame = t_proj * wl.scene.n * len(wl.cams) + sum(
+        f + a * c.width * c.height for f, a, c in zip(fixed, per_px, wl.cams))
+    px = sum(c.width * c.height for c in wl.cams)
+    return dict(value=px / frame / 1e6, unit="Mpix/s", cores=threads, kind="oracle",
+                sample=(f"projection of {n_gauss_sample} random Gaussians x {len(wl.cams)} eyes x "
+                        f"(base + {wl.scene.lvl_opacity_logits.shape[0]} levels) single-threaded, and "
+                        f"foveated compositing of {px_sample[0]}+{px_sample[1]} random pixels per eye over "
+                        f"all projected splats; extrapolated to one full stereo frame "
+                        f"({frame:.1f} s/frame)"),
+                frame_s=frame)
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--tile", type=int, default=16)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-extras", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print("bench.py runs on exactly one GPU: this build has no multi-GPU path "
+              "(see DESIGN.md for how the render would shard).", file=sys.stderr)
+        sys.exit(2)
+    import torch
+
+    import paper_2407_00435_amd as g
+    import scenegen
+
+    torch.cuda.set_device(0)
+    log("generating the 1.5M-Gaussian foveated scene ...")
+    wl = scenegen.config3()
+    fr = Foveated(g, wl, args.tile)
+    log(f"key capacity {fr.cap}; warmup {args.warmup}, steps {args.steps}")
+    wall, stage_ms = time_foveated(fr, args.steps, args.warmup)
+    ms = wall / args.steps * 1e3
+    px = fr.n_px
+    keys = int(fr.num.item())
+    stats = raster_stats(fr)
+    t_r = stage_ms["raster"] * 1e-3
+    achieved = stats[0] * FLOPS_PER_BLEND / t_r / 1e12
+    line = {
+        "metric": METRIC,
+        "value": px / (wall / args.steps) / 1e6,
+        "unit": "Mpix/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "foveated stereo forward, 1.5M Gaussians SH3, 2 eyes 1920x1080, "
+                               "4 levels (100/40/15/5 %), 3.5 deg bands, 16x16 tiles",
+                   "gaussians": fr.n, "eyes": 2, "width": 1920, "height": 1080, "tile": args.tile,
+                   "levels": fr.L},
+        "fps": 1e3 / ms,
+        "stage_ms": stage_ms,
+        "keys": keys,
+        "raster_pairs": {"blended": stats[0], "evaluated": stats[1], "staged": stats[2], "kept": stats[3]},
+        "roofline": {"bound": "alu", "kernel": "k_raster_fov", "achieved": achieved,
+                     "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s", "frac": achieved / FP32_PEAK_TFLOPS,
+                     "traffic": None},
+    }
+    if not args.no_extras:
+        log("plain forward, 500k Gaussians, 1280x720 ...")
+        line["plain_fwd_720p_500k"] = plain_fwd_rate(g, scenegen.config2(), 20, 3)
+        log("forward+backward, 1M Gaussians, 1280x720 ...")
+        line["fwd_bwd_720p_1M"] = fwd_bwd_rate(g, scenegen.config4(), 10, 3)
+    if not args.no_cpu_baseline:
+        log("oracle on the host (bounded sample) ...")
+        line["cpu_baseline"] = cpu_baseline(fr, wl)
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -155,8 +155,9 @@ int gs_project(const gs_scene *scene, const gs_camera *cams_host, const gs_camer
 
 /* Tile binning and (tile, depth) sort (Section 2.1 "Sorting"; Section 4.2
  * filtering).  For every view v and point i with a visible splat, one key per
- * tile of its pixel rectangle (row-major), kept only if tile_level_lo is NULL
- * or tile_level_lo[tile] <= qbound[i].  The list is sorted by
+ * tile of its pixel rectangle (row-major), kept only if tile_level is NULL or
+ * tile_level[tile][0] <= qbound[i] (tile_level: the [n_tiles][2] uint8 table
+ * of gs_fovea_prep; its first column is the tile's lowest level).  The list is sorted by
  * (global tile, float32 depth bits), ties by (view, i).
  * Outputs (device):
  *   vals [key_capacity]        point index i of each sorted key
@@ -170,7 +171,7 @@ int gs_project(const gs_scene *scene, const gs_camera *cams_host, const gs_camer
  * key_capacity must be < 2^32. */
 int gs_bin_sort(const gs_splat *splats, int32_t n, const gs_camera *cams_host,
                 const gs_camera *cams_dev, int n_views, int tile_size,
-                const uint8_t *tile_level_lo, const uint8_t *qbound,
+                const uint8_t *tile_level, const uint8_t *qbound,
                 uint32_t *vals, uint64_t *keys, uint64_t key_capacity,
                 uint32_t *tile_ranges, uint32_t *hits, uint64_t *num_keys,
                 void *workspace, size_t workspace_bytes, void *stream);
@@ -184,12 +185,16 @@ int gs_bin_sort(const gs_splat *splats, int32_t n, const gs_camera *cams_host,
  * n_contrib [n_pixels] (1-based position in the tile run of the last blended
  * point, 0 if none), dominated_px (nullable) [n_views][n]: number of pixels
  * whose largest T_i alpha_i is point i's (Val_i of Eq. 3; first maximum in
- * depth order).  bg is a host float[3] (NULL = black). */
+ * depth order).  bg is a host float[3] (NULL = black).
+ * stats (device, nullable, uint64[4], accumulated, caller zeroes): blended
+ * (pixel, point) pairs, evaluated pairs, staged list entries and entries kept
+ * by the per-wave footprint test; a separate instrumented kernel runs when
+ * stats is non-NULL. */
 int gs_rasterize_fwd(const gs_splat *splats, int32_t n, const gs_camera *cams_host,
                      const gs_camera *cams_dev, int n_views, int tile_size,
                      const uint32_t *vals, const uint32_t *tile_ranges, const float *bg,
                      float *image, float *final_T, uint32_t *n_contrib, uint32_t *dominated_px,
-                     void *workspace, size_t workspace_bytes, void *stream);
+                     uint64_t *stats, void *workspace, size_t workspace_bytes, void *stream);
 
 /* Reverse of gs_rasterize_fwd: given dL/dimage (planar, device) and the
  * forward's final_T and n_contrib, writes grads [n_views][n] (device,
@@ -225,18 +230,21 @@ int gs_fovea_prep(const gs_camera *cams_host, const gs_camera *cams_dev, const g
                   uint8_t *tile_level, void *stream);
 
 /* Foveated compositing (Section 4.1 blending, 4.2 filtering and
- * multi-versioning).  Keys must come from gs_bin_sort with the tile table's
- * lower levels as tile_level_lo.  Each pixel composites level lo and, if its
+ * multi-versioning).  Keys must come from gs_bin_sort with the same tile
+ * level table (so each tile's run holds the points of its lowest level,
+ * the superset of its other levels).  Each pixel composites level lo and, if its
  * weight is non-zero, level lo + 1; level t uses only points with
  * qbound >= t and their level-t colour and opacity (lvl_rgba from
  * gs_project); output (1 - w) I_lo + w I_(lo+1).  Same cut-offs as
- * gs_rasterize_fwd, applied per level. */
+ * gs_rasterize_fwd, applied per level; stats as in gs_rasterize_fwd
+ * (blended pairs count each level's blend). */
 int gs_rasterize_foveated(const gs_splat *splats, const float *lvl_rgba, int32_t n,
                           const uint8_t *qbound, int n_levels, const gs_camera *cams_host,
                           const gs_camera *cams_dev, int n_eyes, int tile_size,
                           const uint32_t *vals, const uint32_t *tile_ranges,
                           const uint8_t *pix_level, const float *pix_weight, const float *bg,
-                          float *image, void *workspace, size_t workspace_bytes, void *stream);
+                          float *image, uint64_t *stats, void *workspace, size_t workspace_bytes,
+                          void *stream);
 
 /* One-call foveated render of n_eyes views: fovea tables, projection with
  * per-level versions, filtered binning and sort, foveated compositing.
@@ -261,6 +269,20 @@ int gs_render_fwd(const gs_scene *scene, const gs_camera *cams_host, const gs_ca
                   uint32_t *vals, uint32_t *tile_ranges, uint64_t key_capacity,
                   uint64_t *num_keys, float *image, float *final_T, uint32_t *n_contrib,
                   void *workspace, size_t workspace_bytes, void *stream);
+
+/* Process-wide tuning knob (not thread-safe against concurrent calls):
+ *   "radix_part": keys per sort workgroup, 4096, 8192 (default) or 16384.
+ * The GS_RADIX_PART environment variable sets the same default. */
+int gs_set_tuning(const char *name, int64_t value);
+
+/* Stable LSD radix sort of n (uint32 key, uint32 value) pairs by the low
+ * `bits` bits of the key (1..32) -- the sort of gs_bin_sort's depth and tile
+ * passes (Section 2.1 "Sorting").  keys, vals (device, [n]) are sorted in
+ * place; keys_tmp, vals_tmp (device, [n]) are scratch; equal keys keep their
+ * input order.  Key bits above `bits` must be zero.  n < 2^32. */
+size_t gs_sort_workspace_bytes(uint64_t n);
+int gs_sort_pairs(uint32_t *keys, uint32_t *vals, uint32_t *keys_tmp, uint32_t *vals_tmp,
+                  uint64_t n, int bits, void *workspace, size_t workspace_bytes, void *stream);
 
 #ifdef __cplusplus
 }

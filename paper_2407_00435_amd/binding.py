@@ -68,17 +68,20 @@ _SIGS = {
     "gs_project": ([_PS, _PC, _VP, _I, _I, _VP, _VP, _VP], _I),
     "gs_bin_sort": ([_VP, _I32, _PC, _VP, _I, _I, _VP, _VP, _VP, _VP, _U64, _VP, _VP, _VP, _VP, _SZ,
                      _VP], _I),
-    "gs_rasterize_fwd": ([_VP, _I32, _PC, _VP, _I, _I, _VP, _VP, _VP, _VP, _VP, _VP, _VP, _VP, _SZ,
-                          _VP], _I),
+    "gs_rasterize_fwd": ([_VP, _I32, _PC, _VP, _I, _I, _VP, _VP, _VP, _VP, _VP, _VP, _VP, _VP, _VP,
+                          _SZ, _VP], _I),
     "gs_rasterize_bwd": ([_VP, _I32, _PC, _VP, _I, _I, _VP, _VP, _VP, _VP, _VP, _VP, _VP, _VP, _SZ,
                           _VP], _I),
     "gs_project_bwd": ([_PS, _PC, _VP, _I, _VP, _VP, _VP, _VP, _VP, _VP, _VP, _VP], _I),
     "gs_fovea_prep": ([_PC, _VP, _PF, _I, _I, _I, _VP, _VP, _VP, _VP], _I),
     "gs_rasterize_foveated": ([_VP, _VP, _I32, _VP, _I, _PC, _VP, _I, _I, _VP, _VP, _VP, _VP, _VP,
-                               _VP, _VP, _SZ, _VP], _I),
+                               _VP, _VP, _VP, _SZ, _VP], _I),
     "gs_render_foveated": ([_PS, _PC, _VP, _PF, _I, _I, _VP, _VP, _U64, _VP, _VP, _SZ, _VP], _I),
     "gs_render_fwd": ([_PS, _PC, _VP, _I, _I, _VP, _VP, _VP, _VP, _U64, _VP, _VP, _VP, _VP, _VP, _SZ,
                        _VP], _I),
+    "gs_sort_workspace_bytes": ([_U64], _SZ),
+    "gs_set_tuning": ([ctypes.c_char_p, ctypes.c_int64], _I),
+    "gs_sort_pairs": ([_VP, _VP, _VP, _VP, _U64, _I, _VP, _SZ, _VP], _I),
 }
 EXPORTED = tuple(_SIGS)
 
@@ -238,7 +241,7 @@ def gs_project(scene: SceneTensors, cams: Cameras, tile_size: int = 16, levels: 
 
 
 def gs_bin_sort(splats: torch.Tensor, n: int, cams: Cameras, tile_size: int = 16,
-                tile_level_lo=None, qbound=None, key_capacity: int | None = None,
+                tile_level=None, qbound=None, key_capacity: int | None = None,
                 want_keys: bool = False, want_hits: bool = False):
     """Binning + (tile, depth) sort.  key_capacity defaults to the sum of the
     unfiltered rectangle tile counts (exact for the plain path, an upper bound
@@ -255,7 +258,7 @@ def gs_bin_sort(splats: torch.Tensor, n: int, cams: Cameras, tile_size: int = 16
     num = torch.zeros(1, dtype=torch.int64, device=dev)
     wsb = gs_workspace_bytes(cams, n, tile_size, cap)
     ws_t, ws, wsn = _ws(wsb)
-    _check(lib().gs_bin_sort(_ptr(splats), n, cams.hp, cams.dp, cams.n, tile_size, _ptr(tile_level_lo),
+    _check(lib().gs_bin_sort(_ptr(splats), n, cams.hp, cams.dp, cams.n, tile_size, _ptr(tile_level),
                              _ptr(qbound), _ptr(vals), _ptr(keys), cap, _ptr(ranges), _ptr(hits),
                              _ptr(num), ws, wsn, _stream()))
     return dict(vals=vals, keys=keys, ranges=ranges, hits=hits, num_keys=num, capacity=cap,
@@ -263,7 +266,7 @@ def gs_bin_sort(splats: torch.Tensor, n: int, cams: Cameras, tile_size: int = 16
 
 
 def gs_rasterize_fwd(splats, n, cams: Cameras, tile_size, vals, ranges, bg=(0.0, 0.0, 0.0),
-                     want_dominated: bool = False):
+                     want_dominated: bool = False, stats=None):
     dev = splats.device
     _, n_px = cams.tiles(tile_size)
     image = torch.empty(3 * n_px, dtype=torch.float32, device=dev)
@@ -273,7 +276,7 @@ def gs_rasterize_fwd(splats, n, cams: Cameras, tile_size, vals, ranges, bg=(0.0,
     bgc = (ctypes.c_float * 3)(*bg)
     _check(lib().gs_rasterize_fwd(_ptr(splats), n, cams.hp, cams.dp, cams.n, tile_size, _ptr(vals),
                                   _ptr(ranges), ctypes.cast(bgc, _VP), _ptr(image), _ptr(final_T),
-                                  _ptr(n_contrib), _ptr(dom), None, 0, _stream()))
+                                  _ptr(n_contrib), _ptr(dom), _ptr(stats), None, 0, _stream()))
     return dict(image=image, final_T=final_T, n_contrib=n_contrib, dominated=dom)
 
 
@@ -321,14 +324,15 @@ def gs_fovea_prep(cams: Cameras, foveae, tile_size: int = 16, n_levels: int = 4)
 
 
 def gs_rasterize_foveated(splats, lvl_rgba, n, qbound, n_levels, cams: Cameras, tile_size, vals,
-                          ranges, pix_level, pix_weight, bg=(0.0, 0.0, 0.0)):
+                          ranges, pix_level, pix_weight, bg=(0.0, 0.0, 0.0), stats=None, image=None):
     _, n_px = cams.tiles(tile_size)
-    image = torch.empty(3 * n_px, dtype=torch.float32, device=splats.device)
+    if image is None:
+        image = torch.empty(3 * n_px, dtype=torch.float32, device=splats.device)
     bgc = (ctypes.c_float * 3)(*bg)
     _check(lib().gs_rasterize_foveated(_ptr(splats), _ptr(lvl_rgba), n, _ptr(qbound), n_levels, cams.hp,
                                        cams.dp, cams.n, tile_size, _ptr(vals), _ptr(ranges),
                                        _ptr(pix_level), _ptr(pix_weight), ctypes.cast(bgc, _VP),
-                                       _ptr(image), None, 0, _stream()))
+                                       _ptr(image), _ptr(stats), None, 0, _stream()))
     return image
 
 
@@ -350,6 +354,22 @@ def gs_render_foveated(scene: SceneTensors, cams: Cameras, foveae, tile_size: in
                                     tile_size, ctypes.cast(bgc, _VP), _ptr(image), key_capacity,
                                     _ptr(num), workspace[1], workspace[2], _stream()))
     return image, num, workspace
+
+
+def gs_set_tuning(name: str, value: int):
+    _check(lib().gs_set_tuning(name.encode(), int(value)))
+
+
+def gs_sort_pairs(keys: torch.Tensor, vals: torch.Tensor, bits: int, workspace=None):
+    """Stable radix sort of int32 (uint32 bit pattern) keys and values, in place."""
+    n = keys.numel()
+    kt, vt = torch.empty_like(keys), torch.empty_like(vals)
+    need = int(lib().gs_sort_workspace_bytes(n))
+    if workspace is None or workspace[2] < need:
+        workspace = _ws(need)
+    _check(lib().gs_sort_pairs(_ptr(keys), _ptr(vals), _ptr(kt), _ptr(vt), n, bits, workspace[1],
+                               workspace[2], _stream()))
+    return workspace
 
 
 def gs_render_fwd(scene: SceneTensors, cams: Cameras, tile_size: int = 16, bg=(0.0, 0.0, 0.0),

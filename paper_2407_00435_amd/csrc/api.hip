@@ -102,19 +102,24 @@ struct Carve {
     }
 };
 
-void carve_bin(Carve &c, int64_t E, uint64_t cap, BinScratch &bs)
+void carve_bin(Carve &c, int64_t E, uint64_t cap, int64_t tiles, BinScratch &bs)
 {
     bs.dkey_a = c.take<uint32_t>(4 * E);
     bs.dval_a = c.take<uint32_t>(4 * E);
     bs.dkey_b = c.take<uint32_t>(4 * E);
     bs.dval_b = c.take<uint32_t>(4 * E);
     bs.hits = c.take<uint32_t>(4 * E);
+    bs.area = c.take<uint32_t>(4 * E);
+    bs.heavy_n = c.take<uint32_t>(4);
+    bs.heavy_e = c.take<uint32_t>(4 * E);
+    bs.heavy_off = c.take<uint64_t>(8 * E);
     int64_t nb = (E + SCAN_THREADS * SCAN_ITEMS - 1) / (SCAN_THREADS * SCAN_ITEMS) + 1;
     bs.block_sums = c.take<uint64_t>(8 * nb);
     bs.tkey_a = c.take<uint32_t>(4 * cap);
     bs.tkey_b = c.take<uint32_t>(4 * cap);
     bs.tval_b = c.take<uint32_t>(4 * cap);
     bs.counts = c.take<uint64_t>(8 * 4);
+    bs.sat = c.take<uint32_t>(4 * 4 * tiles);
     bs.rs.hist = c.take<uint32_t>(4 * 4 * 256);
     uint64_t big = cap > (uint64_t)E ? cap : (uint64_t)E;
     bs.rs.status = c.take<uint64_t>(8 * 256 * radix_max_parts(big ? big : 1));
@@ -129,7 +134,6 @@ struct RenderBufs {
     uint8_t *pix_level;
     float *pix_weight;
     uint8_t *tile_level;
-    uint8_t *tile_lo;
 };
 
 void carve_render(Carve &c, int64_t E, int L, uint64_t cap, int64_t tiles, int64_t pixels,
@@ -142,14 +146,13 @@ void carve_render(Carve &c, int64_t E, int L, uint64_t cap, int64_t tiles, int64
     rb.pix_level = L > 0 ? c.take<uint8_t>(pixels) : nullptr;
     rb.pix_weight = L > 0 ? c.take<float>(4 * pixels) : nullptr;
     rb.tile_level = L > 0 ? c.take<uint8_t>(2 * tiles) : nullptr;
-    rb.tile_lo = L > 0 ? c.take<uint8_t>(tiles) : nullptr;
 }
 
-size_t bin_bytes(int64_t E, uint64_t cap)
+size_t bin_bytes(int64_t E, uint64_t cap, int64_t tiles)
 {
     Carve c;
     BinScratch bs;
-    carve_bin(c, E, cap, bs);
+    carve_bin(c, E, cap, tiles, bs);
     return c.off + 256;
 }
 
@@ -180,9 +183,9 @@ int gs_tile_count(const gs_camera *cams_host, int n_views, int tile_size, int64_
 size_t gs_workspace_bytes(const gs_camera *cams_host, int n_views, int32_t n, int tile_size,
                           uint64_t key_capacity)
 {
-    (void)cams_host;
-    (void)tile_size;
-    return bin_bytes((int64_t)n_views * (n > 0 ? n : 0), key_capacity);
+    int64_t tiles = 0;
+    if (check_cams(cams_host, cams_host, n_views, tile_size, &tiles, nullptr)) return 0;
+    return bin_bytes((int64_t)n_views * (n > 0 ? n : 0), key_capacity, tiles);
 }
 
 size_t gs_render_workspace_bytes(const gs_camera *cams_host, int n_views, int32_t n, int n_levels,
@@ -195,7 +198,7 @@ size_t gs_render_workspace_bytes(const gs_camera *cams_host, int n_views, int32_
     BinScratch bs;
     RenderBufs rb;
     carve_render(c, E, n_levels, key_capacity, tiles, pixels, rb);
-    carve_bin(c, E, key_capacity, bs);
+    carve_bin(c, E, key_capacity, tiles, bs);
     return c.off + 256;
 }
 
@@ -220,7 +223,7 @@ int gs_project(const gs_scene *scene, const gs_camera *cams_host, const gs_camer
 
 int gs_bin_sort(const gs_splat *splats, int32_t n, const gs_camera *cams_host,
                 const gs_camera *cams_dev, int n_views, int tile_size,
-                const uint8_t *tile_level_lo, const uint8_t *qbound, uint32_t *vals,
+                const uint8_t *tile_level, const uint8_t *qbound, uint32_t *vals,
                 uint64_t *keys, uint64_t key_capacity, uint32_t *tile_ranges, uint32_t *hits,
                 uint64_t *num_keys, void *workspace, size_t workspace_bytes, void *stream)
 {
@@ -234,15 +237,15 @@ int gs_bin_sort(const gs_splat *splats, int32_t n, const gs_camera *cams_host,
     if ((n > 0 && !splats) || !tile_ranges || !num_keys || (key_capacity > 0 && !vals))
         return fail(GS_ERR_INVALID, "NULL output or input pointer");
     if (!aligned(splats, 16)) return fail(GS_ERR_INVALID, "splats must be 16-byte aligned");
-    if ((tile_level_lo != nullptr) != (qbound != nullptr))
-        return fail(GS_ERR_INVALID, "tile_level_lo and qbound go together");
-    if ((r = check_ws(workspace, workspace_bytes, bin_bytes(E, key_capacity)))) return r;
+    if ((tile_level != nullptr) != (qbound != nullptr))
+        return fail(GS_ERR_INVALID, "tile_level and qbound go together");
+    if ((r = check_ws(workspace, workspace_bytes, bin_bytes(E, key_capacity, tiles)))) return r;
     Carve c;
     c.base = (char *)workspace;
     BinScratch bs;
-    carve_bin(c, E, key_capacity, bs);
+    carve_bin(c, E, key_capacity, tiles, bs);
     hipError_t e = launch_bin_sort(splats, n, cams_dev, n_views, tiles, tile_bits_of(tiles), tile_size,
-                                   tile_level_lo, qbound, vals, keys, key_capacity, tile_ranges,
+                                   tile_level, qbound, 4, vals, keys, key_capacity, tile_ranges,
                                    hits, num_keys, bs, (hipStream_t)stream);
     if (e != hipSuccess) return hip_fail(e, "gs_bin_sort");
     return ok();
@@ -251,8 +254,8 @@ int gs_bin_sort(const gs_splat *splats, int32_t n, const gs_camera *cams_host,
 int gs_rasterize_fwd(const gs_splat *splats, int32_t n, const gs_camera *cams_host,
                      const gs_camera *cams_dev, int n_views, int tile_size, const uint32_t *vals,
                      const uint32_t *tile_ranges, const float *bg, float *image, float *final_T,
-                     uint32_t *n_contrib, uint32_t *dominated_px, void *workspace,
-                     size_t workspace_bytes, void *stream)
+                     uint32_t *n_contrib, uint32_t *dominated_px, uint64_t *stats,
+                     void *workspace, size_t workspace_bytes, void *stream)
 {
     (void)workspace;
     (void)workspace_bytes;
@@ -265,7 +268,7 @@ int gs_rasterize_fwd(const gs_splat *splats, int32_t n, const gs_camera *cams_ho
     if (!aligned(splats, 16)) return fail(GS_ERR_INVALID, "splats must be 16-byte aligned");
     const float zero[3] = {0.f, 0.f, 0.f};
     hipError_t e = launch_raster_fwd(splats, n, cams_dev, n_views, tile_size, tiles, vals, tile_ranges,
-                                     bg ? bg : zero, image, final_T, n_contrib, dominated_px,
+                                     bg ? bg : zero, image, final_T, n_contrib, dominated_px, stats,
                                      (hipStream_t)stream);
     if (e != hipSuccess) return hip_fail(e, "gs_rasterize_fwd");
     return ok();
@@ -347,8 +350,8 @@ int gs_rasterize_foveated(const gs_splat *splats, const float *lvl_rgba, int32_t
                           const uint8_t *qbound, int n_levels, const gs_camera *cams_host,
                           const gs_camera *cams_dev, int n_eyes, int tile_size, const uint32_t *vals,
                           const uint32_t *tile_ranges, const uint8_t *pix_level,
-                          const float *pix_weight, const float *bg, float *image, void *workspace,
-                          size_t workspace_bytes, void *stream)
+                          const float *pix_weight, const float *bg, float *image, uint64_t *stats,
+                          void *workspace, size_t workspace_bytes, void *stream)
 {
     (void)workspace;
     (void)workspace_bytes;
@@ -365,7 +368,7 @@ int gs_rasterize_foveated(const gs_splat *splats, const float *lvl_rgba, int32_t
     const float zero[3] = {0.f, 0.f, 0.f};
     hipError_t e = launch_raster_fov(splats, lvl_rgba, n, qbound, n_levels, cams_dev, n_eyes, tile_size,
                                      tiles, vals, tile_ranges, pix_level, pix_weight, bg ? bg : zero,
-                                     image, (hipStream_t)stream);
+                                     image, stats, (hipStream_t)stream);
     if (e != hipSuccess) return hip_fail(e, "gs_rasterize_foveated");
     return ok();
 }
@@ -392,23 +395,22 @@ int gs_render_foveated(const gs_scene *scene, const gs_camera *cams_host, const 
     RenderBufs rb;
     carve_render(c, E, L, key_capacity, tiles, pixels, rb);
     BinScratch bs;
-    carve_bin(c, E, key_capacity, bs);
+    carve_bin(c, E, key_capacity, tiles, bs);
     if ((r = gs_fovea_prep(cams_host, cams_dev, fov_host, n_eyes, tile_size, L, rb.pix_level,
                            rb.pix_weight, rb.tile_level, stream)))
         return r;
     hipStream_t st = (hipStream_t)stream;
-    hipError_t e = launch_tile_levels_lo(rb.tile_level, tiles, rb.tile_lo, st);
-    if (e != hipSuccess) return hip_fail(e, "gs_render_foveated");
+    hipError_t e;
     if ((r = gs_project(scene, cams_host, cams_dev, n_eyes, tile_size, rb.splats, rb.lvl, stream)))
         return r;
     e = launch_bin_sort(rb.splats, scene->n, cams_dev, n_eyes, tiles, tile_bits_of(tiles), tile_size,
-                        rb.tile_lo, scene->qbound, rb.vals, nullptr, key_capacity, rb.ranges, nullptr,
+                        rb.tile_level, scene->qbound, L, rb.vals, nullptr, key_capacity, rb.ranges, nullptr,
                         num_keys, bs, st);
     if (e != hipSuccess) return hip_fail(e, "gs_render_foveated (binning)");
     const float zero[3] = {0.f, 0.f, 0.f};
     e = launch_raster_fov(rb.splats, rb.lvl, scene->n, scene->qbound, L, cams_dev, n_eyes, tile_size,
                           tiles, rb.vals, rb.ranges, rb.pix_level, rb.pix_weight, bg ? bg : zero, image,
-                          st);
+                          nullptr, st);
     if (e != hipSuccess) return hip_fail(e, "gs_render_foveated (compositing)");
     return ok();
 }
@@ -430,7 +432,43 @@ int gs_render_fwd(const gs_scene *scene, const gs_camera *cams_host, const gs_ca
                          workspace_bytes, stream)))
         return r;
     return gs_rasterize_fwd(splats, scene->n, cams_host, cams_dev, n_views, tile_size, vals, tile_ranges,
-                            bg, image, final_T, n_contrib, nullptr, workspace, workspace_bytes, stream);
+                            bg, image, final_T, n_contrib, nullptr, nullptr, workspace, workspace_bytes,
+                            stream);
+}
+
+size_t gs_sort_workspace_bytes(uint64_t n) { return radix_sort_scratch_bytes(n); }
+
+int gs_set_tuning(const char *name, int64_t value)
+{
+    if (!name) return fail(GS_ERR_INVALID, "tuning name is NULL");
+    std::string k(name);
+    if (k == "radix_part") {
+        if (!radix_set_part((int)value))
+            return fail(GS_ERR_INVALID, "radix_part must be 4096, 8192 or 16384");
+        return ok();
+    }
+    return fail(GS_ERR_INVALID, "unknown tuning knob '%s'", name);
+}
+
+int gs_sort_pairs(uint32_t *keys, uint32_t *vals, uint32_t *keys_tmp, uint32_t *vals_tmp, uint64_t n,
+                  int bits, void *workspace, size_t workspace_bytes, void *stream)
+{
+    int r;
+    if (bits < 0 || bits > 32) return fail(GS_ERR_INVALID, "bits %d not in 0..32", bits);
+    if (n >= (1ull << 32)) return fail(GS_ERR_UNSUPPORTED, "n must be < 2^32");
+    if (n > 0 && (!keys || !vals || !keys_tmp || !vals_tmp))
+        return fail(GS_ERR_INVALID, "NULL key or value array");
+    if ((r = check_ws(workspace, workspace_bytes, radix_sort_scratch_bytes(n)))) return r;
+    if (n == 0 || bits == 0) return ok();
+    hipStream_t st = (hipStream_t)stream;
+    bool in_tmp = false;
+    hipError_t e = radix_sort_standalone(keys, vals, keys_tmp, vals_tmp, n, bits, workspace, &in_tmp, st);
+    if (e == hipSuccess && in_tmp) {
+        e = hipMemcpyAsync(keys, keys_tmp, 4 * n, hipMemcpyDeviceToDevice, st);
+        if (e == hipSuccess) e = hipMemcpyAsync(vals, vals_tmp, 4 * n, hipMemcpyDeviceToDevice, st);
+    }
+    if (e != hipSuccess) return hip_fail(e, "gs_sort_pairs");
+    return ok();
 }
 
 }  // extern "C"

@@ -19,10 +19,8 @@ struct RadixScratch {
     uint64_t *status;   // [max_parts][256] lookback words
     uint32_t *tickets;  // [4] partition tickets, one per pass
 };
-constexpr int RS_THREADS = 256;
-constexpr int RS_ITEMS = 16;
-constexpr int RS_PART = RS_THREADS * RS_ITEMS;
-inline uint64_t radix_max_parts(uint64_t cap) { return (cap + RS_PART - 1) / RS_PART; }
+// partitions the lookback status must hold for `cap` keys (smallest partition)
+uint64_t radix_max_parts(uint64_t cap);
 inline int radix_passes(int bits) { return (bits + 7) / 8; }
 // Sorts count (device, clamped to cap) pairs.  Input in (ka, va); the result
 // is in (ka, va) if the number of passes is even, else in (kb, vb).
@@ -30,20 +28,32 @@ hipError_t radix_sort_pairs(uint32_t *ka, uint32_t *va, uint32_t *kb, uint32_t *
                             const uint64_t *d_count, uint64_t cap, int bits,
                             const RadixScratch &rs, hipStream_t st);
 
+size_t radix_sort_scratch_bytes(uint64_t n);
+bool radix_set_part(int p);
+// sorts n pairs with its own scratch at ws; *in_tmp tells where the result is
+hipError_t radix_sort_standalone(uint32_t *keys, uint32_t *vals, uint32_t *kt, uint32_t *vt, uint64_t n,
+                                 int bits, void *ws, bool *in_tmp, hipStream_t st);
+
 // binning
 struct BinScratch {
     uint32_t *dkey_a, *dval_a, *dkey_b, *dval_b;  // [E] depth sort ping-pong
     uint32_t *hits;                               // [E]
+    uint32_t *area;                               // [E] unfiltered rectangle tiles
+    uint32_t *heavy_n;                            // [1] queued large rectangles
+    uint32_t *heavy_e;                            // [E]
+    uint64_t *heavy_off;                          // [E]
     uint64_t *block_sums;                         // [E / SCAN_ITEMS + 1]
     uint32_t *tkey_a, *tkey_b, *tval_b;           // [cap] tile-key sort ping-pong
     uint64_t *counts;                             // [3]: entries, keys, key capacity
+    uint32_t *sat;                                // [4][n_tiles] level summed-area tables
     RadixScratch rs;
 };
 constexpr int SCAN_THREADS = 256;
 constexpr int SCAN_ITEMS = 16;
 hipError_t launch_bin_sort(const gs_splat *splats, int n, const gs_camera *cams_dev, int V,
-                           int64_t n_tiles, int tile_bits, int T, const uint8_t *tile_level_lo,
-                           const uint8_t *qbound, uint32_t *vals, uint64_t *keys, uint64_t cap,
+                           int64_t n_tiles, int tile_bits, int T, const uint8_t *tile_level,
+                           const uint8_t *qbound, int n_levels, uint32_t *vals, uint64_t *keys,
+                           uint64_t cap,
                            uint32_t *ranges, uint32_t *hits_out, uint64_t *num_keys,
                            const BinScratch &bs, hipStream_t st);
 
@@ -51,7 +61,7 @@ hipError_t launch_bin_sort(const gs_splat *splats, int n, const gs_camera *cams_
 hipError_t launch_raster_fwd(const gs_splat *splats, int n, const gs_camera *cams_dev, int V, int T,
                              int64_t n_tiles, const uint32_t *vals, const uint32_t *ranges,
                              const float bg[3], float *image, float *final_T, uint32_t *n_contrib,
-                             uint32_t *dominated, hipStream_t st);
+                             uint32_t *dominated, uint64_t *stats, hipStream_t st);
 hipError_t launch_raster_bwd(const gs_splat *splats, int n, const gs_camera *cams_dev, int V, int T,
                              int64_t n_tiles, const uint32_t *vals, const uint32_t *ranges,
                              const float bg[3], const float *final_T, const uint32_t *n_contrib,
@@ -63,9 +73,7 @@ hipError_t launch_raster_fov(const gs_splat *splats, const float *lvl_rgba, int 
                              const uint8_t *qbound, int n_levels, const gs_camera *cams_dev, int V,
                              int T, int64_t n_tiles, const uint32_t *vals, const uint32_t *ranges,
                              const uint8_t *pix_level, const float *pix_weight, const float bg[3],
-                             float *image, hipStream_t st);
+                             float *image, uint64_t *stats, hipStream_t st);
 
 // utilities
 hipError_t launch_fill_u32(uint32_t *p, uint32_t value, uint64_t count, hipStream_t st);
-hipError_t launch_tile_levels_lo(const uint8_t *tile_level, int64_t n_tiles, uint8_t *lo,
-                                 hipStream_t st);

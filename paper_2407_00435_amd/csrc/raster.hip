@@ -100,13 +100,30 @@ __device__ __forceinline__ float qmax_of(float opacity)
 }
 
 // ---------------------------------------------------------------------------
-template <int T, bool DOM>
+// Optional statistics (STATS): [0] blended pairs, [1] evaluated (pixel,
+// splat) pairs, [2] staged records, [3] records kept by the cull.
+__device__ __forceinline__ void stats_add(unsigned long long *stats, float blended, float evaluated,
+                                          float staged, float kept)
+{
+    blended = wave_sum(blended);
+    evaluated = wave_sum(evaluated);
+    if (__lane_id() == 0) {
+        atomicAdd(stats + 0, (unsigned long long)blended);
+        atomicAdd(stats + 1, (unsigned long long)evaluated);
+        atomicAdd(stats + 2, (unsigned long long)staged);
+        atomicAdd(stats + 3, (unsigned long long)kept);
+    }
+}
+
+template <int T, bool DOM, bool STATS>
 __global__ void __launch_bounds__(T *T)
 k_raster_fwd(const gs_splat *__restrict__ splats, int n, const gs_camera *__restrict__ cams, int V,
              const uint32_t *__restrict__ vals, const uint32_t *__restrict__ ranges, float bg0,
              float bg1, float bg2, float *__restrict__ image, float *__restrict__ final_T,
-             uint32_t *__restrict__ n_contrib, uint32_t *__restrict__ dominated)
+             uint32_t *__restrict__ n_contrib, uint32_t *__restrict__ dominated,
+             unsigned long long *__restrict__ stats)
 {
+    float st_blend = 0.f, st_eval = 0.f, st_staged = 0.f, st_kept = 0.f;
     constexpr int WAVES = T * T / 64;
     constexpr int SUB = T / 8;
     __shared__ FwdRec s_rec[WAVES][64];
@@ -148,9 +165,14 @@ k_raster_fwd(const gs_splat *__restrict__ splats, int n, const gs_camera *__rest
         if (keep) s_rec[wave][__popcll(m & lanemask_lt())] = rec;
         wave_lds_sync();
         const int cnt = __popcll(m);
+        if (STATS) {
+            st_staged += (float)min(64u, end - c0);
+            st_kept += (float)cnt;
+        }
         for (int j = 0; j < cnt; ++j) {
             const float4 a = s_rec[wave][j].a, b = s_rec[wave][j].b;
             if (!done) {
+                if (STATS) st_eval += 1.0f;
                 const float e2 = pair_e2(a, b, fpx, fpy);
                 if (e2 >= b.z) {
                     const float alpha = fminf(GS_ALPHA_MAX, fast_exp2(e2));
@@ -160,6 +182,7 @@ k_raster_fwd(const gs_splat *__restrict__ splats, int n, const gs_camera *__rest
                     } else {
                         const float4 c = s_rec[wave][j].c;
                         const float w = alpha * Tr;
+                        if (STATS) st_blend += 1.0f;
                         C0 = fmaf(w, c.x, C0);
                         C1 = fmaf(w, c.y, C1);
                         C2 = fmaf(w, c.z, C2);
@@ -187,6 +210,7 @@ k_raster_fwd(const gs_splat *__restrict__ splats, int n, const gs_camera *__rest
         n_contrib[pix] = last;
         if (DOM && best_id >= 0) atomicAdd(dominated + (int64_t)vi.v * n + best_id, 1u);
     }
+    if (STATS) stats_add(stats, st_blend, st_eval, st_staged, st_kept);
 }
 
 // ---------------------------------------------------------------------------
@@ -201,14 +225,15 @@ struct FovRec {
     float4 lv[MAXL];
 };
 
-template <int T>
+template <int T, bool STATS>
 __global__ void __launch_bounds__(T *T)
 k_raster_fov(const gs_splat *__restrict__ splats, const float4 *__restrict__ lvl, int n,
              const uint8_t *__restrict__ qbound, int L, const gs_camera *__restrict__ cams, int V,
              const uint32_t *__restrict__ vals, const uint32_t *__restrict__ ranges,
              const uint8_t *__restrict__ pix_level, const float *__restrict__ pix_weight, float bg0,
-             float bg1, float bg2, float *__restrict__ image)
+             float bg1, float bg2, float *__restrict__ image, unsigned long long *__restrict__ stats)
 {
+    float st_blend = 0.f, st_eval = 0.f, st_staged = 0.f, st_kept = 0.f;
     constexpr int WAVES = T * T / 64;
     constexpr int SUB = T / 8;
     __shared__ FovRec s_rec[WAVES][64];
@@ -269,9 +294,14 @@ k_raster_fov(const gs_splat *__restrict__ splats, const float4 *__restrict__ lvl
         if (keep) s_rec[wave][__popcll(msk & lanemask_lt())] = rec;
         wave_lds_sync();
         const int cnt = __popcll(msk);
+        if (STATS) {
+            st_staged += (float)min(64u, end - c0);
+            st_kept += (float)cnt;
+        }
         for (int j = 0; j < cnt; ++j) {
             const float4 a = s_rec[wave][j].a, b = s_rec[wave][j].b;
             if (!(done_a && done_b)) {
+                if (STATS) st_eval += 1.0f;
                 const float p2 = pair_e2(a, b, fpx, fpy);  // b.y = 0: falloff only
                 const int m = (int)b.z;
                 if (p2 >= EXTENT_LOG2) {
@@ -285,6 +315,7 @@ k_raster_fov(const gs_splat *__restrict__ splats, const float4 *__restrict__ lvl
                                 done_a = true;
                             } else {
                                 const float w = alpha * Ta;
+                                if (STATS) st_blend += 1.0f;
                                 A0 = fmaf(w, lv.x, A0);
                                 A1 = fmaf(w, lv.y, A1);
                                 A2 = fmaf(w, lv.z, A2);
@@ -301,6 +332,7 @@ k_raster_fov(const gs_splat *__restrict__ splats, const float4 *__restrict__ lvl
                                 done_b = true;
                             } else {
                                 const float w = alpha * Tb;
+                                if (STATS) st_blend += 1.0f;
                                 B0 = fmaf(w, lv.x, B0);
                                 B1 = fmaf(w, lv.y, B1);
                                 B2 = fmaf(w, lv.z, B2);
@@ -328,6 +360,7 @@ k_raster_fov(const gs_splat *__restrict__ splats, const float4 *__restrict__ lvl
         img[plane] = ga;
         img[2 * plane] = ba;
     }
+    if (STATS) stats_add(stats, st_blend, st_eval, st_staged, st_kept);
 }
 
 // ---------------------------------------------------------------------------
@@ -551,20 +584,25 @@ k_fovea_tile(const gs_camera *__restrict__ cams, int V, int T, int64_t n_tiles,
 hipError_t launch_raster_fwd(const gs_splat *splats, int n, const gs_camera *cams_dev, int V, int T,
                              int64_t n_tiles, const uint32_t *vals, const uint32_t *ranges,
                              const float bg[3], float *image, float *final_T, uint32_t *n_contrib,
-                             uint32_t *dominated, hipStream_t st)
+                             uint32_t *dominated, uint64_t *stats, hipStream_t st)
 {
     if (n_tiles == 0) return hipSuccess;
     hipError_t e;
     if (dominated && (e = launch_fill_u32(dominated, 0u, (uint64_t)V * n, st)) != hipSuccess) return e;
+    unsigned long long *sp = reinterpret_cast<unsigned long long *>(stats);
 #define GS_RF(TS)                                                                                  \
-    if (dominated)                                                                                 \
-        hipLaunchKernelGGL((k_raster_fwd<TS, true>), dim3((unsigned)n_tiles), dim3(TS * TS), 0, st, \
-                           splats, n, cams_dev, V, vals, ranges, bg[0], bg[1], bg[2], image,       \
-                           final_T, n_contrib, dominated);                                         \
+    if (stats)                                                                                     \
+        hipLaunchKernelGGL((k_raster_fwd<TS, false, true>), dim3((unsigned)n_tiles), dim3(TS * TS), \
+                           0, st, splats, n, cams_dev, V, vals, ranges, bg[0], bg[1], bg[2], image, \
+                           final_T, n_contrib, dominated, sp);                                     \
+    else if (dominated)                                                                            \
+        hipLaunchKernelGGL((k_raster_fwd<TS, true, false>), dim3((unsigned)n_tiles), dim3(TS * TS), \
+                           0, st, splats, n, cams_dev, V, vals, ranges, bg[0], bg[1], bg[2], image, \
+                           final_T, n_contrib, dominated, sp);                                     \
     else                                                                                           \
-        hipLaunchKernelGGL((k_raster_fwd<TS, false>), dim3((unsigned)n_tiles), dim3(TS * TS), 0,   \
-                           st, splats, n, cams_dev, V, vals, ranges, bg[0], bg[1], bg[2], image,   \
-                           final_T, n_contrib, dominated);
+        hipLaunchKernelGGL((k_raster_fwd<TS, false, false>), dim3((unsigned)n_tiles),              \
+                           dim3(TS * TS), 0, st, splats, n, cams_dev, V, vals, ranges, bg[0],      \
+                           bg[1], bg[2], image, final_T, n_contrib, dominated, sp);
     switch (T) {
     case 8: GS_RF(8); break;
     case 16: GS_RF(16); break;
@@ -611,14 +649,20 @@ hipError_t launch_raster_fov(const gs_splat *splats, const float *lvl_rgba, int 
                              const uint8_t *qbound, int n_levels, const gs_camera *cams_dev, int V,
                              int T, int64_t n_tiles, const uint32_t *vals, const uint32_t *ranges,
                              const uint8_t *pix_level, const float *pix_weight, const float bg[3],
-                             float *image, hipStream_t st)
+                             float *image, uint64_t *stats, hipStream_t st)
 {
     if (n_tiles == 0) return hipSuccess;
     const float4 *lv = reinterpret_cast<const float4 *>(lvl_rgba);
+    unsigned long long *sp = reinterpret_cast<unsigned long long *>(stats);
 #define GS_RV(TS)                                                                                    \
-    hipLaunchKernelGGL((k_raster_fov<TS>), dim3((unsigned)n_tiles), dim3(TS * TS), 0, st, splats, lv, \
-                       n, qbound, n_levels, cams_dev, V, vals, ranges, pix_level, pix_weight, bg[0],  \
-                       bg[1], bg[2], image);
+    if (stats)                                                                                       \
+        hipLaunchKernelGGL((k_raster_fov<TS, true>), dim3((unsigned)n_tiles), dim3(TS * TS), 0, st,   \
+                           splats, lv, n, qbound, n_levels, cams_dev, V, vals, ranges, pix_level,    \
+                           pix_weight, bg[0], bg[1], bg[2], image, sp);                              \
+    else                                                                                             \
+        hipLaunchKernelGGL((k_raster_fov<TS, false>), dim3((unsigned)n_tiles), dim3(TS * TS), 0, st,  \
+                           splats, lv, n, qbound, n_levels, cams_dev, V, vals, ranges, pix_level,    \
+                           pix_weight, bg[0], bg[1], bg[2], image, sp);
     switch (T) {
     case 8: GS_RV(8); break;
     case 16: GS_RV(16); break;

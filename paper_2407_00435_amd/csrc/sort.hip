@@ -3,33 +3,42 @@
 // One histogram pass over the keys computes the digit counts of every pass;
 // then each pass is a single "onesweep" kernel: a workgroup takes the next
 // partition ticket from an atomic counter (so partitions are processed in
-// ticket order and every predecessor is already resident), ranks its 4096
-// keys stably with wave64 ballot matching, publishes its per-digit counts,
-// and resolves its global offsets by decoupled lookback over predecessor
+// ticket order and every predecessor is already resident), ranks its keys
+// stably with wave64 ballot matching, publishes its per-digit counts, and
+// resolves its global offsets by decoupled lookback over predecessor
 // partitions before scattering through LDS in coalesced runs.
+//
+// Digits are at most 8 bits wide and equal across passes (a 14-bit key sorts
+// in two 7-bit passes).  The partition size (keys per workgroup) trades the
+// length of the lookback chain against occupancy; it is 8192 by default and
+// can be set to 4096, 8192 or 16384 with the GS_RADIX_PART environment
+// variable or gs_set_tuning("radix_part", ...).
+#include <cstdlib>
+
 #include "common.hpp"
 #include "kernels.hpp"
 
 namespace {
 
-constexpr int RS_WAVES = RS_THREADS / 64;
 constexpr uint64_t FLAG_AGG = 1ull << 62;
 constexpr uint64_t FLAG_INC = 2ull << 62;
 constexpr uint64_t VAL_MASK = (1ull << 62) - 1;
+constexpr int MIN_PART = 4096;
 
 __global__ void __launch_bounds__(256)
 k_radix_hist(const uint32_t *__restrict__ keys, const uint64_t *__restrict__ d_count, uint64_t cap,
-             int passes, uint32_t *__restrict__ hist)
+             int passes, int dbits, uint32_t *__restrict__ hist)
 {
     __shared__ uint32_t sh[4][256];
     for (int j = threadIdx.x; j < 4 * 256; j += blockDim.x) (&sh[0][0])[j] = 0;
     __syncthreads();
     uint64_t count = *d_count;
     count = count < cap ? count : cap;
+    const uint32_t mask = (1u << dbits) - 1u;
     uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
     for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count; i += stride) {
         uint32_t k = keys[i];
-        for (int p = 0; p < passes; ++p) atomicAdd(&sh[p][(k >> (8 * p)) & 255u], 1u);
+        for (int p = 0; p < passes; ++p) atomicAdd(&sh[p][(k >> (dbits * p)) & mask], 1u);
     }
     __syncthreads();
     for (int j = threadIdx.x; j < passes * 256; j += blockDim.x) {
@@ -58,27 +67,30 @@ __global__ void __launch_bounds__(256) k_radix_prefix(uint32_t *__restrict__ his
 
 __global__ void __launch_bounds__(256)
 k_radix_clear(uint64_t *__restrict__ status, uint32_t *__restrict__ ticket,
-              const uint64_t *__restrict__ d_count, uint64_t cap)
+              const uint64_t *__restrict__ d_count, uint64_t cap, int part)
 {
     uint64_t count = *d_count;
     count = count < cap ? count : cap;
-    uint64_t words = ((count + RS_PART - 1) / RS_PART) * 256;
+    uint64_t words = ((count + part - 1) / part) * 256;
     uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
     for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < words; i += stride)
         status[i] = 0;
     if (blockIdx.x == 0 && threadIdx.x == 0) *ticket = 0;
 }
 
-__global__ void __launch_bounds__(RS_THREADS)
+template <int THREADS, int ITEMS>
+__global__ void __launch_bounds__(THREADS)
 k_radix_onesweep(const uint32_t *__restrict__ kin, const uint32_t *__restrict__ vin,
                  uint32_t *__restrict__ kout, uint32_t *__restrict__ vout,
-                 const uint64_t *__restrict__ d_count, uint64_t cap, int shift,
-                 const uint32_t *__restrict__ gbase, uint64_t *__restrict__ status,
+                 const uint64_t *__restrict__ d_count, uint64_t cap, int shift, uint32_t mask,
+                 int dbits, const uint32_t *__restrict__ gbase, uint64_t *__restrict__ status,
                  uint32_t *__restrict__ ticket)
 {
-    __shared__ uint32_t s_keys[RS_PART];
-    __shared__ uint32_t s_vals[RS_PART];
-    __shared__ uint32_t s_whist[RS_WAVES][256];
+    constexpr int WAVES = THREADS / 64;
+    constexpr int PART = THREADS * ITEMS;
+    __shared__ uint32_t s_keys[PART];
+    __shared__ uint32_t s_vals[PART];
+    __shared__ uint32_t s_whist[WAVES][256];
     __shared__ uint32_t s_bexcl[256];  // exclusive prefix over digits of the block counts
     __shared__ uint64_t s_dbase[256];  // global position of the digit's first key of this block
     __shared__ uint32_t s_part;
@@ -86,19 +98,19 @@ k_radix_onesweep(const uint32_t *__restrict__ kin, const uint32_t *__restrict__ 
     const int t = threadIdx.x;
     const int wave = t >> 6, lane = t & 63;
     if (t == 0) s_part = atomicAdd(ticket, 1u);
-    for (int j = t; j < RS_WAVES * 256; j += RS_THREADS) (&s_whist[0][0])[j] = 0;
+    for (int j = t; j < WAVES * 256; j += THREADS) (&s_whist[0][0])[j] = 0;
     __syncthreads();
     const uint64_t part = s_part;
     uint64_t count = *d_count;
     count = count < cap ? count : cap;
-    const uint64_t nparts = (count + RS_PART - 1) / RS_PART;
+    const uint64_t nparts = (count + PART - 1) / PART;
     if (part >= nparts) return;
 
-    const uint64_t pbase = part * RS_PART;
-    const uint64_t wbase = pbase + (uint64_t)wave * (RS_ITEMS * 64);
-    uint32_t k[RS_ITEMS], v[RS_ITEMS], rk[RS_ITEMS];
+    const uint64_t pbase = part * PART;
+    const uint64_t wbase = pbase + (uint64_t)wave * (ITEMS * 64);
+    uint32_t k[ITEMS], v[ITEMS], rk[ITEMS];
 #pragma unroll
-    for (int r = 0; r < RS_ITEMS; ++r) {
+    for (int r = 0; r < ITEMS; ++r) {
         uint64_t idx = wbase + (uint64_t)r * 64 + lane;
         bool ok = idx < count;
         k[r] = ok ? kin[idx] : 0xFFFFFFFFu;
@@ -107,13 +119,12 @@ k_radix_onesweep(const uint32_t *__restrict__ kin, const uint32_t *__restrict__ 
     const uint64_t lt = lanemask_lt();
     // stable rank within the wave: items in (round, lane) order
 #pragma unroll
-    for (int r = 0; r < RS_ITEMS; ++r) {
+    for (int r = 0; r < ITEMS; ++r) {
         uint64_t idx = wbase + (uint64_t)r * 64 + lane;
         bool ok = idx < count;
-        uint32_t d = (k[r] >> shift) & 255u;
+        uint32_t d = (k[r] >> shift) & mask;
         uint64_t peers = ballot64(ok);
-#pragma unroll
-        for (int b = 0; b < 8; ++b) {
+        for (int b = 0; b < dbits; ++b) {
             bool bit = (d >> b) & 1u;
             uint64_t bb = ballot64(bit);
             peers &= bit ? bb : ~bb;
@@ -126,76 +137,96 @@ k_radix_onesweep(const uint32_t *__restrict__ kin, const uint32_t *__restrict__ 
         wave_lds_sync();
     }
     __syncthreads();
-    // per digit: exclusive over waves, block total
+    // per digit (threads < 256): exclusive over waves, block total, lookback
+    const bool dig = t < 256;
     uint32_t total = 0;
-#pragma unroll
-    for (int w = 0; w < RS_WAVES; ++w) {
-        uint32_t c = s_whist[w][t];
-        s_whist[w][t] = total;
-        total += c;
-    }
-    // publish this partition's counts, then look back for the prefix
-    uint64_t *my = status + part * 256 + t;
-    if (part == 0) {
-        __hip_atomic_store(my, FLAG_INC | (uint64_t)total, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    } else {
-        __hip_atomic_store(my, FLAG_AGG | (uint64_t)total, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    }
     uint64_t prefix = 0;
-    if (part > 0) {
-        int64_t q = (int64_t)part - 1;
-        for (;;) {
-            uint64_t st = __hip_atomic_load(status + q * 256 + t, __ATOMIC_RELAXED,
-                                            __HIP_MEMORY_SCOPE_AGENT);
-            uint64_t flag = st & ~VAL_MASK;
-            if (flag == 0) {
-                __builtin_amdgcn_s_sleep(1);
-                continue;
-            }
-            prefix += st & VAL_MASK;
-            if (flag == FLAG_INC) break;
-            --q;
+    if (dig) {
+#pragma unroll
+        for (int w = 0; w < WAVES; ++w) {
+            uint32_t c = s_whist[w][t];
+            s_whist[w][t] = total;
+            total += c;
         }
-        __hip_atomic_store(my, FLAG_INC | (prefix + total), __ATOMIC_RELAXED,
-                           __HIP_MEMORY_SCOPE_AGENT);
+        uint64_t *my = status + part * 256 + t;
+        if (part == 0) {
+            __hip_atomic_store(my, FLAG_INC | (uint64_t)total, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        } else {
+            __hip_atomic_store(my, FLAG_AGG | (uint64_t)total, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
+        if (part > 0 && (uint32_t)t <= mask) {
+            int64_t q = (int64_t)part - 1;
+            for (;;) {
+                uint64_t st = __hip_atomic_load(status + q * 256 + t, __ATOMIC_RELAXED,
+                                                __HIP_MEMORY_SCOPE_AGENT);
+                uint64_t flag = st & ~VAL_MASK;
+                if (flag == 0) {
+                    __builtin_amdgcn_s_sleep(1);
+                    continue;
+                }
+                prefix += st & VAL_MASK;
+                if (flag == FLAG_INC) break;
+                --q;
+            }
+            __hip_atomic_store(my, FLAG_INC | (prefix + total), __ATOMIC_RELAXED,
+                               __HIP_MEMORY_SCOPE_AGENT);
+        }
+        s_bexcl[t] = total;
     }
+    __syncthreads();
     // block-local exclusive prefix over digits (Hillis-Steele in LDS)
-    s_bexcl[t] = total;
-    __syncthreads();
     for (int off = 1; off < 256; off <<= 1) {
-        uint32_t add = t >= off ? s_bexcl[t - off] : 0u;
+        uint32_t add = (dig && t >= off) ? s_bexcl[t - off] : 0u;
         __syncthreads();
-        s_bexcl[t] += add;
+        if (dig) s_bexcl[t] += add;
         __syncthreads();
     }
-    uint32_t bexcl = s_bexcl[t] - total;
+    uint32_t bexcl = dig ? s_bexcl[t] - total : 0u;
     __syncthreads();
-    s_bexcl[t] = bexcl;
-    s_dbase[t] = (uint64_t)gbase[t] + prefix;
+    if (dig) {
+        s_bexcl[t] = bexcl;
+        s_dbase[t] = (uint64_t)gbase[t] + prefix;
+    }
     __syncthreads();
     // scatter into LDS in digit order
 #pragma unroll
-    for (int r = 0; r < RS_ITEMS; ++r) {
+    for (int r = 0; r < ITEMS; ++r) {
         uint64_t idx = wbase + (uint64_t)r * 64 + lane;
         if (idx < count) {
-            uint32_t d = (k[r] >> shift) & 255u;
+            uint32_t d = (k[r] >> shift) & mask;
             uint32_t pos = s_bexcl[d] + s_whist[wave][d] + rk[r];
             s_keys[pos] = k[r];
             s_vals[pos] = v[r];
         }
     }
     __syncthreads();
-    uint32_t pcount = (uint32_t)((count - pbase) < (uint64_t)RS_PART ? (count - pbase) : RS_PART);
-    for (uint32_t j = t; j < pcount; j += RS_THREADS) {
+    uint32_t pcount = (uint32_t)((count - pbase) < (uint64_t)PART ? (count - pbase) : PART);
+    for (uint32_t j = t; j < pcount; j += THREADS) {
         uint32_t key = s_keys[j];
-        uint32_t d = (key >> shift) & 255u;
+        uint32_t d = (key >> shift) & mask;
         uint64_t dst = s_dbase[d] + (j - s_bexcl[d]);
         kout[dst] = key;
         vout[dst] = s_vals[j];
     }
 }
 
+__global__ void k_set_count(uint64_t *__restrict__ p, uint64_t value) { *p = value; }
+
+int g_part = 0;
+
+int part_size()
+{
+    if (g_part == 0) {
+        const char *s = std::getenv("GS_RADIX_PART");
+        int v = s ? std::atoi(s) : 8192;
+        g_part = (v == 4096 || v == 8192 || v == 16384) ? v : 8192;
+    }
+    return g_part;
+}
+
 }  // namespace
+
+uint64_t radix_max_parts(uint64_t cap) { return (cap + MIN_PART - 1) / MIN_PART; }
 
 hipError_t radix_sort_pairs(uint32_t *ka, uint32_t *va, uint32_t *kb, uint32_t *vb,
                             const uint64_t *d_count, uint64_t cap, int bits,
@@ -203,27 +234,67 @@ hipError_t radix_sort_pairs(uint32_t *ka, uint32_t *va, uint32_t *kb, uint32_t *
 {
     int passes = radix_passes(bits);
     if (passes == 0 || cap == 0) return hipSuccess;
+    // equal digit widths <= 8 bits: fewer buckets give longer runs per digit
+    const int dbits = (bits + passes - 1) / passes;
+    const uint32_t mask = (1u << dbits) - 1u;
     hipError_t e = launch_fill_u32(rs.hist, 0u, 4 * 256, st);
     if (e != hipSuccess) return e;
-    uint64_t max_parts = radix_max_parts(cap);
+    const int P = part_size();
+    const uint64_t parts = (cap + P - 1) / P;
     int hist_blocks = (int)((cap + 256 * 32 - 1) / (256 * 32));
     if (hist_blocks > 2048) hist_blocks = 2048;
     if (hist_blocks < 1) hist_blocks = 1;
     hipLaunchKernelGGL(k_radix_hist, dim3(hist_blocks), dim3(256), 0, st, ka, d_count, cap, passes,
-                       rs.hist);
+                       dbits, rs.hist);
     hipLaunchKernelGGL(k_radix_prefix, dim3(passes), dim3(256), 0, st, rs.hist);
     uint32_t *src_k = ka, *src_v = va, *dst_k = kb, *dst_v = vb;
-    int clear_blocks = (int)((max_parts * 256 + 255) / 256);
+    int clear_blocks = (int)((parts * 256 + 255) / 256);
     if (clear_blocks > 4096) clear_blocks = 4096;
     for (int p = 0; p < passes; ++p) {
         hipLaunchKernelGGL(k_radix_clear, dim3(clear_blocks), dim3(256), 0, st, rs.status,
-                           rs.tickets + p, d_count, cap);
-        hipLaunchKernelGGL(k_radix_onesweep, dim3((unsigned)max_parts), dim3(RS_THREADS), 0, st,
-                           src_k, src_v, dst_k, dst_v, d_count, cap, 8 * p, rs.hist + 256 * p,
-                           rs.status, rs.tickets + p);
+                           rs.tickets + p, d_count, cap, P);
+#define GS_OS(TH, IT)                                                                                \
+    hipLaunchKernelGGL((k_radix_onesweep<TH, IT>), dim3((unsigned)parts), dim3(TH), 0, st, src_k,  \
+                       src_v, dst_k, dst_v, d_count, cap, dbits * p, mask, dbits,                  \
+                       rs.hist + 256 * p, rs.status, rs.tickets + p)
+        if (P == 4096)
+            GS_OS(256, 16);
+        else if (P == 16384)
+            GS_OS(1024, 16);
+        else
+            GS_OS(512, 16);
+#undef GS_OS
         uint32_t *tk = src_k, *tv = src_v;
         src_k = dst_k; src_v = dst_v;
         dst_k = tk; dst_v = tv;
     }
     return hipGetLastError();
+}
+
+bool radix_set_part(int p)
+{
+    if (p != 4096 && p != 8192 && p != 16384) return false;
+    g_part = p;
+    return true;
+}
+
+size_t radix_sort_scratch_bytes(uint64_t n)
+{
+    // hist [4][256] u32 | tickets [4] u32 | count u64 | status [parts][256] u64
+    return 4 * 256 * 4 + 4 * 4 + 8 + 256 + 8 * 256 * radix_max_parts(n ? n : 1) + 256;
+}
+
+hipError_t radix_sort_standalone(uint32_t *keys, uint32_t *vals, uint32_t *kt, uint32_t *vt, uint64_t n,
+                                 int bits, void *ws, bool *in_tmp, hipStream_t st)
+{
+    char *base = (char *)ws;
+    RadixScratch rs;
+    rs.hist = (uint32_t *)base;
+    rs.tickets = (uint32_t *)(base + 4 * 256 * 4);
+    uint64_t *count = (uint64_t *)(base + 4 * 256 * 4 + 4 * 4 + 8);  // 8-byte aligned
+    rs.status = (uint64_t *)(base + 4 * 256 * 4 + 4 * 4 + 8 + 256);
+    rs.status = (uint64_t *)(((uintptr_t)rs.status + 255) & ~uintptr_t(255));
+    hipLaunchKernelGGL(k_set_count, dim3(1), dim3(1), 0, st, count, n);
+    *in_tmp = radix_passes(bits) % 2 == 1;
+    return radix_sort_pairs(keys, vals, kt, vt, count, n, bits, rs, st);
 }

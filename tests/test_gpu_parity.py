@@ -196,8 +196,7 @@ def _fr_case(g, sc, cams, fov, tile):
     S = g.SceneTensors(sc)
     t = g.gs_fovea_prep(C, fov, tile, 4)
     splats, lvl = g.gs_project(S, C, tile, levels=True)
-    tlo = t["tile_level"][:, 0].contiguous()
-    bs = g.gs_bin_sort(splats, sc.n, C, tile, tile_level_lo=tlo, qbound=S.t["qbound"],
+    bs = g.gs_bin_sort(splats, sc.n, C, tile, tile_level=t["tile_level"], qbound=S.t["qbound"],
                        want_keys=True, want_hits=True)
     img = g.gs_rasterize_foveated(splats, lvl, sc.n, S.t["qbound"], 4, C, tile, bs["vals"],
                                   bs["ranges"], t["pix_level"], t["pix_weight"])
