@@ -102,19 +102,24 @@ struct Carve {
     }
 };
 
-void carve_bin(Carve &c, int64_t E, uint64_t cap, int64_t tiles, BinScratch &bs)
+void carve_bin(Carve &c, int V, int64_t E, uint64_t cap, int64_t tiles, BinScratch &bs)
 {
     bs.dkey_a = c.take<uint32_t>(4 * E);
     bs.dval_a = c.take<uint32_t>(4 * E);
     bs.dkey_b = c.take<uint32_t>(4 * E);
     bs.dval_b = c.take<uint32_t>(4 * E);
     bs.hits = c.take<uint32_t>(4 * E);
-    bs.area = c.take<uint32_t>(4 * E);
-    bs.heavy_n = c.take<uint32_t>(4);
-    bs.heavy_e = c.take<uint32_t>(4 * E);
-    bs.heavy_off = c.take<uint64_t>(8 * E);
+    bs.rec = c.take<uint4>(16 * E);
+    bs.rec_s = c.take<uint4>(16 * E);
+    bs.hits_s = c.take<uint32_t>(4 * E);
+    bs.hpre = c.take<uint64_t>(8 * E);
+    bs.apre = c.take<uint64_t>(8 * E);
+    bs.slice = c.take<uint32_t>(4 * BIN_MAX_SLICES);
     int64_t nb = (E + SCAN_THREADS * SCAN_ITEMS - 1) / (SCAN_THREADS * SCAN_ITEMS) + 1;
     bs.block_sums = c.take<uint64_t>(8 * nb);
+    bs.block_sums2 = c.take<uint64_t>(8 * nb);
+    bs.block_vis = c.take<uint32_t>(4 * nb);
+    bs.vtab = c.take<int64_t>(16 * (int64_t)V);
     bs.tkey_a = c.take<uint32_t>(4 * cap);
     bs.tkey_b = c.take<uint32_t>(4 * cap);
     bs.tval_b = c.take<uint32_t>(4 * cap);
@@ -148,11 +153,11 @@ void carve_render(Carve &c, int64_t E, int L, uint64_t cap, int64_t tiles, int64
     rb.tile_level = L > 0 ? c.take<uint8_t>(2 * tiles) : nullptr;
 }
 
-size_t bin_bytes(int64_t E, uint64_t cap, int64_t tiles)
+size_t bin_bytes(int V_, int64_t E, uint64_t cap, int64_t tiles)
 {
     Carve c;
     BinScratch bs;
-    carve_bin(c, E, cap, tiles, bs);
+    carve_bin(c, V_, E, cap, tiles, bs);
     return c.off + 256;
 }
 
@@ -185,7 +190,7 @@ size_t gs_workspace_bytes(const gs_camera *cams_host, int n_views, int32_t n, in
 {
     int64_t tiles = 0;
     if (check_cams(cams_host, cams_host, n_views, tile_size, &tiles, nullptr)) return 0;
-    return bin_bytes((int64_t)n_views * (n > 0 ? n : 0), key_capacity, tiles);
+    return bin_bytes(n_views, (int64_t)n_views * (n > 0 ? n : 0), key_capacity, tiles);
 }
 
 size_t gs_render_workspace_bytes(const gs_camera *cams_host, int n_views, int32_t n, int n_levels,
@@ -198,7 +203,7 @@ size_t gs_render_workspace_bytes(const gs_camera *cams_host, int n_views, int32_
     BinScratch bs;
     RenderBufs rb;
     carve_render(c, E, n_levels, key_capacity, tiles, pixels, rb);
-    carve_bin(c, E, key_capacity, tiles, bs);
+    carve_bin(c, n_views, E, key_capacity, tiles, bs);
     return c.off + 256;
 }
 
@@ -239,12 +244,13 @@ int gs_bin_sort(const gs_splat *splats, int32_t n, const gs_camera *cams_host,
     if (!aligned(splats, 16)) return fail(GS_ERR_INVALID, "splats must be 16-byte aligned");
     if ((tile_level != nullptr) != (qbound != nullptr))
         return fail(GS_ERR_INVALID, "tile_level and qbound go together");
-    if ((r = check_ws(workspace, workspace_bytes, bin_bytes(E, key_capacity, tiles)))) return r;
+    if ((r = check_ws(workspace, workspace_bytes, bin_bytes(n_views, E, key_capacity, tiles)))) return r;
     Carve c;
     c.base = (char *)workspace;
     BinScratch bs;
-    carve_bin(c, E, key_capacity, tiles, bs);
-    hipError_t e = launch_bin_sort(splats, n, cams_dev, n_views, tiles, tile_bits_of(tiles), tile_size,
+    carve_bin(c, n_views, E, key_capacity, tiles, bs);
+    hipError_t e = launch_bin_sort(splats, n, cams_dev, cams_host, n_views, tiles, tile_bits_of(tiles),
+                                   tile_size,
                                    tile_level, qbound, 4, vals, keys, key_capacity, tile_ranges,
                                    hits, num_keys, bs, (hipStream_t)stream);
     if (e != hipSuccess) return hip_fail(e, "gs_bin_sort");
@@ -395,7 +401,7 @@ int gs_render_foveated(const gs_scene *scene, const gs_camera *cams_host, const 
     RenderBufs rb;
     carve_render(c, E, L, key_capacity, tiles, pixels, rb);
     BinScratch bs;
-    carve_bin(c, E, key_capacity, tiles, bs);
+    carve_bin(c, n_eyes, E, key_capacity, tiles, bs);
     if ((r = gs_fovea_prep(cams_host, cams_dev, fov_host, n_eyes, tile_size, L, rb.pix_level,
                            rb.pix_weight, rb.tile_level, stream)))
         return r;
@@ -403,7 +409,8 @@ int gs_render_foveated(const gs_scene *scene, const gs_camera *cams_host, const 
     hipError_t e;
     if ((r = gs_project(scene, cams_host, cams_dev, n_eyes, tile_size, rb.splats, rb.lvl, stream)))
         return r;
-    e = launch_bin_sort(rb.splats, scene->n, cams_dev, n_eyes, tiles, tile_bits_of(tiles), tile_size,
+    e = launch_bin_sort(rb.splats, scene->n, cams_dev, cams_host, n_eyes, tiles, tile_bits_of(tiles),
+                        tile_size,
                         rb.tile_level, scene->qbound, L, rb.vals, nullptr, key_capacity, rb.ranges, nullptr,
                         num_keys, bs, st);
     if (e != hipSuccess) return hip_fail(e, "gs_render_foveated (binning)");

@@ -22,11 +22,16 @@ struct RadixScratch {
 // partitions the lookback status must hold for `cap` keys (smallest partition)
 uint64_t radix_max_parts(uint64_t cap);
 inline int radix_passes(int bits) { return (bits + 7) / 8; }
+// digit width of each pass for a key of `bits` bits (equal widths, <= 8)
+int radix_digit_bits(int bits);
 // Sorts count (device, clamped to cap) pairs.  Input in (ka, va); the result
-// is in (ka, va) if the number of passes is even, else in (kb, vb).
+// is in (ka, va) if the number of passes is even, else in (kb, vb).  With
+// hist_ready the caller has accumulated the per-pass digit counts into
+// rs.hist ([pass][256], pass p = bits [p d, (p + 1) d) with d =
+// radix_digit_bits(bits)).
 hipError_t radix_sort_pairs(uint32_t *ka, uint32_t *va, uint32_t *kb, uint32_t *vb,
                             const uint64_t *d_count, uint64_t cap, int bits,
-                            const RadixScratch &rs, hipStream_t st);
+                            const RadixScratch &rs, hipStream_t st, bool hist_ready);
 
 size_t radix_sort_scratch_bytes(uint64_t n);
 bool radix_set_part(int p);
@@ -38,22 +43,26 @@ hipError_t radix_sort_standalone(uint32_t *keys, uint32_t *vals, uint32_t *kt, u
 struct BinScratch {
     uint32_t *dkey_a, *dval_a, *dkey_b, *dval_b;  // [E] depth sort ping-pong
     uint32_t *hits;                               // [E]
-    uint32_t *area;                               // [E] unfiltered rectangle tiles
-    uint32_t *heavy_n;                            // [1] queued large rectangles
-    uint32_t *heavy_e;                            // [E]
-    uint64_t *heavy_off;                          // [E]
-    uint64_t *block_sums;                         // [E / SCAN_ITEMS + 1]
+    uint4 *rec;                                   // [E] rectangle, count, quality bound (entries with keys)
+    uint4 *rec_s;                                 // [E] the same in depth order, tile-id form
+    uint32_t *hits_s;                             // [E] counts in depth order
+    uint64_t *hpre, *apre;                        // [E] key / rectangle-area offsets in depth order
+    uint32_t *slice;                              // [BIN_MAX_SLICES] first entry of each emission slice
+    uint32_t *block_vis;                          // [E / SCAN_ITEMS + 1] entries with keys per block
+    uint64_t *block_sums, *block_sums2;           // [E / SCAN_ITEMS + 1]
+    int64_t *vtab;                                // [2V] first tile and tiles_x of each view
     uint32_t *tkey_a, *tkey_b, *tval_b;           // [cap] tile-key sort ping-pong
-    uint64_t *counts;                             // [3]: entries, keys, key capacity
+    uint64_t *counts;                             // [4]: entries, keys, key capacity, rectangle area
     uint32_t *sat;                                // [4][n_tiles] level summed-area tables
     RadixScratch rs;
 };
 constexpr int SCAN_THREADS = 256;
+constexpr int64_t BIN_MAX_SLICES = 1 << 20;
 constexpr int SCAN_ITEMS = 16;
-hipError_t launch_bin_sort(const gs_splat *splats, int n, const gs_camera *cams_dev, int V,
-                           int64_t n_tiles, int tile_bits, int T, const uint8_t *tile_level,
-                           const uint8_t *qbound, int n_levels, uint32_t *vals, uint64_t *keys,
-                           uint64_t cap,
+hipError_t launch_bin_sort(const gs_splat *splats, int n, const gs_camera *cams_dev,
+                           const gs_camera *cams_host, int V, int64_t n_tiles, int tile_bits, int T,
+                           const uint8_t *tile_level, const uint8_t *qbound, int n_levels,
+                           uint32_t *vals, uint64_t *keys, uint64_t cap,
                            uint32_t *ranges, uint32_t *hits_out, uint64_t *num_keys,
                            const BinScratch &bs, hipStream_t st);
 

@@ -170,30 +170,26 @@ k_raster_fwd(const gs_splat *__restrict__ splats, int n, const gs_camera *__rest
             st_kept += (float)cnt;
         }
         for (int j = 0; j < cnt; ++j) {
-            const float4 a = s_rec[wave][j].a, b = s_rec[wave][j].b;
-            if (!done) {
-                if (STATS) st_eval += 1.0f;
-                const float e2 = pair_e2(a, b, fpx, fpy);
-                if (e2 >= b.z) {
-                    const float alpha = fminf(GS_ALPHA_MAX, fast_exp2(e2));
-                    const float Tn = fmaf(-alpha, Tr, Tr);
-                    if (Tn < GS_T_STOP) {
-                        done = true;
-                    } else {
-                        const float4 c = s_rec[wave][j].c;
-                        const float w = alpha * Tr;
-                        if (STATS) st_blend += 1.0f;
-                        C0 = fmaf(w, c.x, C0);
-                        C1 = fmaf(w, c.y, C1);
-                        C2 = fmaf(w, c.z, C2);
-                        Tr = Tn;
-                        last = __float_as_uint(b.w);
-                        if (DOM && w > best) {
-                            best = w;
-                            best_id = (int)__float_as_uint(c.w);
-                        }
-                    }
-                }
+            // branch-free: every lane evaluates, selects take the decisions
+            const float4 a = s_rec[wave][j].a, b = s_rec[wave][j].b, c = s_rec[wave][j].c;
+            if (STATS) st_eval += done ? 0.0f : 1.0f;
+            const float e2 = pair_e2(a, b, fpx, fpy);
+            const float alpha = fminf(GS_ALPHA_MAX, fast_exp2(e2));
+            const bool use = !done && e2 >= b.z;
+            const float Tn = fmaf(-alpha, Tr, Tr);
+            const bool stop = use && Tn < GS_T_STOP;
+            const bool blend = use && !stop;
+            const float w = blend ? alpha * Tr : 0.0f;
+            C0 = fmaf(w, c.x, C0);
+            C1 = fmaf(w, c.y, C1);
+            C2 = fmaf(w, c.z, C2);
+            Tr = blend ? Tn : Tr;
+            last = blend ? __float_as_uint(b.w) : last;
+            done = done || stop;
+            if (STATS) st_blend += blend ? 1.0f : 0.0f;
+            if (DOM && blend && w > best) {
+                best = w;
+                best_id = (int)__float_as_uint(c.w);
             }
             if ((j & 7) == 7 && ballot64(!done) == 0) break;
         }
@@ -261,6 +257,7 @@ k_raster_fov(const gs_splat *__restrict__ splats, const float4 *__restrict__ lvl
     // lowest level any pixel of the wave needs: splats bounded below it are skipped
     int wave_lo = inside ? lo : 255;
     for (int off = 32; off > 0; off >>= 1) wave_lo = min(wave_lo, __shfl_xor(wave_lo, off));
+    const bool any_two = ballot64(two) != 0;
 
     float Ta = 1.f, A0 = 0.f, A1 = 0.f, A2 = 0.f;
     float Tb = 1.f, B0 = 0.f, B1 = 0.f, B2 = 0.f;
@@ -282,7 +279,7 @@ k_raster_fov(const gs_splat *__restrict__ splats, const float4 *__restrict__ lvl
             const float4 *s4 = reinterpret_cast<const float4 *>(splats + vbase + id);
             const float4 s0 = s4[0], s1 = s4[1];
             rec.a = make_float4(s0.x, s0.y, NEG_HALF_LOG2E * s0.z, -GS_LOG2E * s0.w);
-            rec.b = make_float4(NEG_HALF_LOG2E * s1.x, 0.0f, (float)m, 0.0f);
+            rec.b = make_float4(NEG_HALF_LOG2E * s1.x, 0.0f, __int_as_float(m), 0.0f);
             const float4 *lp = lvl + (vbase + id) * L;
 #pragma unroll
             for (int t = 0; t < MAXL; ++t)
@@ -299,48 +296,42 @@ k_raster_fov(const gs_splat *__restrict__ splats, const float4 *__restrict__ lvl
             st_kept += (float)cnt;
         }
         for (int j = 0; j < cnt; ++j) {
+            // branch-free: every lane evaluates, selects take the decisions
             const float4 a = s_rec[wave][j].a, b = s_rec[wave][j].b;
-            if (!(done_a && done_b)) {
-                if (STATS) st_eval += 1.0f;
-                const float p2 = pair_e2(a, b, fpx, fpy);  // b.y = 0: falloff only
-                const int m = (int)b.z;
-                if (p2 >= EXTENT_LOG2) {
-                    const float G = fast_exp2(p2);
-                    if (!done_a && m >= lo) {
-                        const float4 lv = s_rec[wave][j].lv[lo - 1];
-                        const float alpha = fminf(GS_ALPHA_MAX, lv.w * G);
-                        if (alpha >= GS_ALPHA_MIN) {
-                            const float Tn = fmaf(-alpha, Ta, Ta);
-                            if (Tn < GS_T_STOP) {
-                                done_a = true;
-                            } else {
-                                const float w = alpha * Ta;
-                                if (STATS) st_blend += 1.0f;
-                                A0 = fmaf(w, lv.x, A0);
-                                A1 = fmaf(w, lv.y, A1);
-                                A2 = fmaf(w, lv.z, A2);
-                                Ta = Tn;
-                            }
-                        }
-                    }
-                    if (!done_b && m >= lo + 1) {
-                        const float4 lv = s_rec[wave][j].lv[lo];
-                        const float alpha = fminf(GS_ALPHA_MAX, lv.w * G);
-                        if (alpha >= GS_ALPHA_MIN) {
-                            const float Tn = fmaf(-alpha, Tb, Tb);
-                            if (Tn < GS_T_STOP) {
-                                done_b = true;
-                            } else {
-                                const float w = alpha * Tb;
-                                if (STATS) st_blend += 1.0f;
-                                B0 = fmaf(w, lv.x, B0);
-                                B1 = fmaf(w, lv.y, B1);
-                                B2 = fmaf(w, lv.z, B2);
-                                Tb = Tn;
-                            }
-                        }
-                    }
-                }
+            if (STATS) st_eval += (done_a && done_b) ? 0.0f : 1.0f;
+            const float p2 = pair_e2(a, b, fpx, fpy);  // b.y = 0: falloff only
+            const int m = __float_as_int(b.z);
+            const float G = fast_exp2(p2);
+            const bool incl = p2 >= EXTENT_LOG2;
+            {
+                const float4 lv = s_rec[wave][j].lv[lo - 1];
+                const float alpha = fminf(GS_ALPHA_MAX, lv.w * G);
+                const bool use = incl && !done_a && m >= lo && alpha >= GS_ALPHA_MIN;
+                const float Tn = fmaf(-alpha, Ta, Ta);
+                const bool stop = use && Tn < GS_T_STOP;
+                const bool blend = use && !stop;
+                const float w = blend ? alpha * Ta : 0.0f;
+                A0 = fmaf(w, lv.x, A0);
+                A1 = fmaf(w, lv.y, A1);
+                A2 = fmaf(w, lv.z, A2);
+                Ta = blend ? Tn : Ta;
+                done_a = done_a || stop;
+                if (STATS) st_blend += blend ? 1.0f : 0.0f;
+            }
+            if (any_two) {
+                const float4 lv = s_rec[wave][j].lv[lo < MAXL ? lo : MAXL - 1];
+                const float alpha = fminf(GS_ALPHA_MAX, lv.w * G);
+                const bool use = incl && !done_b && m >= lo + 1 && alpha >= GS_ALPHA_MIN;
+                const float Tn = fmaf(-alpha, Tb, Tb);
+                const bool stop = use && Tn < GS_T_STOP;
+                const bool blend = use && !stop;
+                const float w = blend ? alpha * Tb : 0.0f;
+                B0 = fmaf(w, lv.x, B0);
+                B1 = fmaf(w, lv.y, B1);
+                B2 = fmaf(w, lv.z, B2);
+                Tb = blend ? Tn : Tb;
+                done_b = done_b || stop;
+                if (STATS) st_blend += blend ? 1.0f : 0.0f;
             }
             if ((j & 7) == 7 && ballot64(!(done_a && done_b)) == 0) break;
         }

@@ -35,10 +35,21 @@ k_radix_hist(const uint32_t *__restrict__ keys, const uint64_t *__restrict__ d_c
     uint64_t count = *d_count;
     count = count < cap ? count : cap;
     const uint32_t mask = (1u << dbits) - 1u;
-    uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
-    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count; i += stride) {
-        uint32_t k = keys[i];
-        for (int p = 0; p < passes; ++p) atomicAdd(&sh[p][(k >> (dbits * p)) & mask], 1u);
+    // four keys per thread per step (16-byte loads)
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x * 4;
+    for (uint64_t i = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) * 4; i < count; i += stride) {
+        uint32_t k4[4];
+        const bool vec = i + 4 <= count && (reinterpret_cast<uintptr_t>(keys) & 15) == 0;
+        if (vec) {
+            const uint4 q = *reinterpret_cast<const uint4 *>(keys + i);
+            k4[0] = q.x; k4[1] = q.y; k4[2] = q.z; k4[3] = q.w;
+        }
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            if (i + j >= count) break;
+            const uint32_t k = vec ? k4[j] : keys[i + j];
+            for (int p = 0; p < passes; ++p) atomicAdd(&sh[p][(k >> (dbits * p)) & mask], 1u);
+        }
     }
     __syncthreads();
     for (int j = threadIdx.x; j < passes * 256; j += blockDim.x) {
@@ -228,24 +239,32 @@ int part_size()
 
 uint64_t radix_max_parts(uint64_t cap) { return (cap + MIN_PART - 1) / MIN_PART; }
 
+int radix_digit_bits(int bits)
+{
+    const int passes = radix_passes(bits);
+    return passes ? (bits + passes - 1) / passes : 0;
+}
+
 hipError_t radix_sort_pairs(uint32_t *ka, uint32_t *va, uint32_t *kb, uint32_t *vb,
                             const uint64_t *d_count, uint64_t cap, int bits,
-                            const RadixScratch &rs, hipStream_t st)
+                            const RadixScratch &rs, hipStream_t st, bool hist_ready)
 {
     int passes = radix_passes(bits);
     if (passes == 0 || cap == 0) return hipSuccess;
     // equal digit widths <= 8 bits: fewer buckets give longer runs per digit
-    const int dbits = (bits + passes - 1) / passes;
+    const int dbits = radix_digit_bits(bits);
     const uint32_t mask = (1u << dbits) - 1u;
-    hipError_t e = launch_fill_u32(rs.hist, 0u, 4 * 256, st);
-    if (e != hipSuccess) return e;
+    hipError_t e;
     const int P = part_size();
     const uint64_t parts = (cap + P - 1) / P;
-    int hist_blocks = (int)((cap + 256 * 32 - 1) / (256 * 32));
-    if (hist_blocks > 2048) hist_blocks = 2048;
-    if (hist_blocks < 1) hist_blocks = 1;
-    hipLaunchKernelGGL(k_radix_hist, dim3(hist_blocks), dim3(256), 0, st, ka, d_count, cap, passes,
-                       dbits, rs.hist);
+    if (!hist_ready) {
+        if ((e = launch_fill_u32(rs.hist, 0u, 4 * 256, st)) != hipSuccess) return e;
+        int hist_blocks = (int)((cap + 256 * 64 - 1) / (256 * 64));
+        if (hist_blocks > 2048) hist_blocks = 2048;
+        if (hist_blocks < 1) hist_blocks = 1;
+        hipLaunchKernelGGL(k_radix_hist, dim3(hist_blocks), dim3(256), 0, st, ka, d_count, cap, passes,
+                           dbits, rs.hist);
+    }
     hipLaunchKernelGGL(k_radix_prefix, dim3(passes), dim3(256), 0, st, rs.hist);
     uint32_t *src_k = ka, *src_v = va, *dst_k = kb, *dst_v = vb;
     int clear_blocks = (int)((parts * 256 + 255) / 256);
@@ -296,5 +315,5 @@ hipError_t radix_sort_standalone(uint32_t *keys, uint32_t *vals, uint32_t *kt, u
     rs.status = (uint64_t *)(((uintptr_t)rs.status + 255) & ~uintptr_t(255));
     hipLaunchKernelGGL(k_set_count, dim3(1), dim3(1), 0, st, count, n);
     *in_tmp = radix_passes(bits) % 2 == 1;
-    return radix_sort_pairs(keys, vals, kt, vt, count, n, bits, rs, st);
+    return radix_sort_pairs(keys, vals, kt, vt, count, n, bits, rs, st, false);
 }
