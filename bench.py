@@ -34,6 +34,44 @@ FP32_PEAK_TFLOPS = 157.3
 FLOPS_PER_BLEND = 23
 
 
+# HBM traffic of one k_raster_fov launch on this workload, from two
+# rocprofv3 --pmc passes (FETCH_SIZE, then WRITE_SIZE, KiB per dispatch,
+# averaged over the dispatches), each scaled by the ratio of known bytes to
+# the same counter on a plain device copy (bench.py --copy-probe).  Valid
+# only for the kernel sources they were taken on (sha256 below).
+TRAFFIC = {"kernel": "k_raster_fov", "fetch_kib": 389908.2, "write_kib": 56525.8, "fetch_scale": 1.9999,
+           "write_scale": 1.0,
+           "sha256": "520b7457e76008fc71a6856d6195a4f1f3b165c538ea61886326227913769bdb"}
+
+
+def kernel_sha():
+    import hashlib
+    h = hashlib.sha256()
+    for f in ("raster.hip", "common.hpp"):
+        with open(os.path.join(ROOT, "paper_2407_00435_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def traffic_bytes():
+    if not TRAFFIC or TRAFFIC["sha256"] != kernel_sha():
+        return None
+    return (TRAFFIC["fetch_kib"] * TRAFFIC["fetch_scale"] + TRAFFIC["write_kib"] * TRAFFIC["write_scale"]) * 1024
+
+
+def copy_probe(mib=1024, reps=5):
+    """Plain device copy of a known size, for scaling the memory counters."""
+    import torch
+    n = mib * (1 << 20) // 4
+    src = torch.ones(n, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    for _ in range(reps):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_probe_bytes_read": n * 4, "copy_probe_bytes_written": n * 4, "dispatches": reps}),
+          flush=True)
+
+
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
@@ -240,6 +278,8 @@ def main():
     ap.add_argument("--tile", type=int, default=16)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="only run a plain 1 GiB device copy (memory-counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py runs on exactly one GPU: this build has no multi-GPU path "
@@ -247,6 +287,9 @@ def main():
         sys.exit(2)
     import torch
 
+    if args.copy_probe:
+        copy_probe()
+        return
     import paper_2407_00435_amd as g
     import scenegen
 
@@ -285,7 +328,7 @@ def main():
         "raster_pairs": {"blended": stats[0], "evaluated": stats[1], "staged": stats[2], "kept": stats[3]},
         "roofline": {"bound": "alu", "kernel": "k_raster_fov", "achieved": achieved,
                      "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s", "frac": achieved / FP32_PEAK_TFLOPS,
-                     "traffic": None},
+                     "traffic": traffic_bytes()},
     }
     if not args.no_extras:
         log("plain forward, 500k Gaussians, 1280x720 ...")
