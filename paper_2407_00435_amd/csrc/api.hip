@@ -120,6 +120,7 @@ void carve_bin(Carve &c, int V, int64_t E, uint64_t cap, int64_t tiles, BinScrat
     bs.block_sums2 = c.take<uint64_t>(8 * nb);
     bs.block_vis = c.take<uint32_t>(4 * nb);
     bs.vtab = c.take<int64_t>(16 * (int64_t)V);
+    bs.bbox = c.take<int32_t>(64 * (int64_t)V);
     bs.tkey_a = c.take<uint32_t>(4 * cap);
     bs.tkey_b = c.take<uint32_t>(4 * cap);
     bs.tval_b = c.take<uint32_t>(4 * cap);

@@ -25,7 +25,7 @@
 
 namespace {
 
-constexpr int SAT_LDS_TILES = 40960;      // views up to this many tiles build their tables in LDS
+constexpr int SAT_LDS_TILES = 16384;      // views up to this many tiles build their tables in LDS (64 KB)
 constexpr uint64_t SLICE_MIN = 1024;       // rectangle tiles per emission task (at least)
 constexpr uint64_t MAX_SLICES = BIN_MAX_SLICES;  // emission tasks (at most)
 
@@ -63,26 +63,50 @@ k_view_table(const gs_camera *__restrict__ cams, int V, int T, int64_t *__restri
 // Summed-area table of [lower level of tile <= m] over each view's tile grid,
 // one table per level m = 1..L: sat[(m-1) * n_tiles + g] counts the tiles
 // (x', y') <= (x, y) of g's view.  One workgroup per (view, level), built in
-// LDS (dynamic size) when the view's grid fits, else in place in memory.
+// LDS (dynamic size) when the view's grid fits, else in place in memory:
+// row sums (a thread per row), then column sums (a thread per column).
+// Also the bounding box of those tiles, bbox[(v * L + m - 1) * 4 +
+// {x0, y0, x1, y1}] (x0 > x1 when there are none).
 __global__ void __launch_bounds__(256)
 k_level_sat(const gs_camera *__restrict__ cams, int V, int T, int L, int64_t n_tiles,
-            const uint8_t *__restrict__ tl, uint32_t *__restrict__ sat, int use_lds)
+            const uint8_t *__restrict__ tl, uint32_t *__restrict__ sat, int32_t *__restrict__ bbox, int use_lds)
 {
     extern __shared__ uint32_t s_sat[];
+    __shared__ int s_box[4];
     const int v = blockIdx.x / L, m = blockIdx.x % L + 1;
     const int64_t toff = view_tile_off(cams, v, T);
     const int tx = div_up(cams[v].width, T), ty = div_up(cams[v].height, T);
+    if (threadIdx.x == 0) {
+        s_box[0] = tx;
+        s_box[1] = ty;
+        s_box[2] = -1;
+        s_box[3] = -1;
+    }
+    __syncthreads();
     uint32_t *g = sat + (int64_t)(m - 1) * n_tiles + toff;
     uint32_t *s = use_lds ? s_sat : g;
     const uint8_t *lv = tl + 2 * toff;
     for (int y = threadIdx.x; y < ty; y += blockDim.x) {
         uint32_t run = 0;
+        int xl = tx, xr = -1;
         for (int x = 0; x < tx; ++x) {
-            run += lv[2 * ((int64_t)y * tx + x)] <= m;
+            const bool kept = lv[2 * ((int64_t)y * tx + x)] <= m;
+            run += kept;
+            if (kept) {
+                xl = x < xl ? x : xl;
+                xr = x;
+            }
             s[(int64_t)y * tx + x] = run;
+        }
+        if (xr >= 0) {
+            atomicMin(&s_box[0], xl);
+            atomicMin(&s_box[1], y);
+            atomicMax(&s_box[2], xr);
+            atomicMax(&s_box[3], y);
         }
     }
     __syncthreads();
+    if (threadIdx.x < 4) bbox[((int64_t)v * L + m - 1) * 4 + threadIdx.x] = s_box[threadIdx.x];
     for (int x = threadIdx.x; x < tx; x += blockDim.x) {
         uint32_t run = 0;
         for (int y = 0; y < ty; ++y) {
@@ -110,10 +134,12 @@ __device__ __forceinline__ uint32_t sat_rect(const uint32_t *__restrict__ s, int
 
 // 1. per-entry counts; culled / empty entries get 0.  Also the float32 depth
 //    bits (dkey_all), a per-block count of entries with keys and, for those
-//    entries, rec[e] = {x0 | y0 << 16, x1 | y1 << 16, count, quality bound}.
+//    entries, rec[e] = {x0 | y0 << 16, x1 | y1 << 16, count, quality bound}
+//    with the rectangle clipped to the bounding box of the tiles its level
+//    keeps (the kept tiles and their row-major order are unchanged).
 __global__ void __launch_bounds__(SCAN_THREADS)
 k_count(const gs_splat *__restrict__ splats, int n, const gs_camera *__restrict__ cams, int V, int T,
-        const int64_t *__restrict__ vtab, const uint32_t *__restrict__ sat, int L, int64_t n_tiles,
+        const int64_t *__restrict__ vtab, const uint32_t *__restrict__ sat, const int32_t *__restrict__ bbox, int L, int64_t n_tiles,
         const uint8_t *__restrict__ qbound, uint32_t *__restrict__ hits, uint4 *__restrict__ rec,
         uint32_t *__restrict__ dkey_all, uint32_t *__restrict__ hits_out, uint32_t *__restrict__ block_vis)
 {
@@ -140,9 +166,17 @@ k_count(const gs_splat *__restrict__ splats, int n, const gs_camera *__restrict_
             } else {
                 m = qbound[i];
                 if (m >= 1) {
+                    // kept tiles lie in the level's bounding box: clip to it
                     const int ml = m < L ? m : L;
-                    const uint32_t *s = sat + (int64_t)(ml - 1) * n_tiles + vtab[2 * v];
-                    cnt = sat_rect(s, (int)vtab[2 * v + 1], r.tx0, r.tx1, r.ty0, r.ty1);
+                    const int4 b = reinterpret_cast<const int4 *>(bbox)[(int64_t)v * L + ml - 1];
+                    r.tx0 = r.tx0 > b.x ? r.tx0 : b.x;
+                    r.ty0 = r.ty0 > b.y ? r.ty0 : b.y;
+                    r.tx1 = r.tx1 < b.z ? r.tx1 : b.z;
+                    r.ty1 = r.ty1 < b.w ? r.ty1 : b.w;
+                    if (r.tx0 <= r.tx1 && r.ty0 <= r.ty1) {
+                        const uint32_t *s = sat + (int64_t)(ml - 1) * n_tiles + vtab[2 * v];
+                        cnt = sat_rect(s, (int)vtab[2 * v + 1], r.tx0, r.tx1, r.ty0, r.ty1);
+                    }
                 }
             }
         }
@@ -391,38 +425,72 @@ __device__ __forceinline__ uint32_t sat_rel_rect(const uint32_t *__restrict__ s,
            sat_rel(s, q, dx0 - 1, dy0 - 1);
 }
 
+// Inclusive max-scan over the 64 lanes of a wave (values >= 0): row
+// shifts within each row of 16 lanes, then row broadcasts across rows.
+__device__ __forceinline__ uint32_t wave_incl_max(uint32_t x)
+{
+    x = max(x, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x111, 0xF, 0xF, true));  // row_shr:1
+    x = max(x, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x112, 0xF, 0xF, true));  // row_shr:2
+    x = max(x, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x114, 0xF, 0xF, true));  // row_shr:4
+    x = max(x, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x118, 0xF, 0xF, true));  // row_shr:8
+    x = max(x, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x142, 0xA, 0xF, false));  // row_bcast:15
+    x = max(x, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x143, 0xC, 0xF, false));  // row_bcast:31
+    return x;
+}
+
+// floor(l / w) and l mod w for l < w * 2^14, w >= 1 (reciprocal estimate,
+// one correction step: the quotient is below 2^14).
+__device__ __forceinline__ void divmod_small(uint32_t l, uint32_t w, uint32_t &q, uint32_t &rem)
+{
+    uint32_t qq = (uint32_t)((float)l * __builtin_amdgcn_rcpf((float)w));
+    int32_t rr = (int32_t)(l - qq * w);
+    if (rr < 0) {
+        --qq;
+        rr += (int32_t)w;
+    } else if (rr >= (int32_t)w) {
+        ++qq;
+        rr -= (int32_t)w;
+    }
+    q = qq;
+    rem = (uint32_t)rr;
+}
+
 // 4c. load-balanced emission.  The rectangles of the depth-sorted entries,
 // concatenated in row-major order, form one sequence of (entry, tile) items
 // whose kept tiles are exactly the key list in order.  Each wave takes slices
-// of that sequence, 64 items per step: lanes find their entry by a binary
-// search over the area offsets of the next 64 entries, test the tile level,
-// and kept keys are compacted with a ballot, so every store is coalesced.
+// of that sequence, 64 items per step: an entry that starts inside the step
+// marks its first item in a wave-private LDS row, a max-scan over the lanes
+// hands every item its entry, the tile level is tested, and kept keys are
+// compacted with a ballot, so every store is coalesced.
 __global__ void __launch_bounds__(256)
 k_emit(const uint4 *__restrict__ rec_s, const uint64_t *__restrict__ hpre, const uint64_t *__restrict__ apre,
        const uint32_t *__restrict__ slice, const uint64_t *__restrict__ counts, const uint8_t *__restrict__ tl,
        const uint32_t *__restrict__ sat, int L, int64_t n_tiles, uint64_t cap, uint32_t *__restrict__ tkey,
        uint32_t *__restrict__ tval)
 {
+    __shared__ uint32_t s_mark[4][64];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    s_mark[wave][lane] = 0;
+    wave_lds_sync();
     const uint64_t E = counts[0], A = counts[3];
     if (counts[1] == 0 || E == 0) return;  // no keys, or more than the capacity
     const uint64_t S = slice_len(A);
     const uint64_t n_slices = (A + S - 1) / S;
-    const int lane = threadIdx.x & 63;
     const uint64_t lt = lanemask_lt();
     const uint64_t waves = (uint64_t)gridDim.x * (blockDim.x / 64);
-    for (uint64_t sl = (uint64_t)blockIdx.x * (blockDim.x / 64) + (threadIdx.x >> 6); sl < n_slices; sl += waves) {
+    for (uint64_t sl = (uint64_t)blockIdx.x * (blockDim.x / 64) + wave; sl < n_slices; sl += waves) {
         const uint64_t a_beg = sl * S;
         const uint64_t a_end = a_beg + S < A ? a_beg + S : A;
         uint64_t r = slice[sl];
-        uint64_t base0 = a_beg - apre[r];  // items of entry r before the chunk
+        uint32_t base0 = (uint32_t)(a_beg - apre[r]);  // items of entry r before the step
         uint64_t o = hpre[r];
         {
             const SortedRec q = unpack_rec(rec_s[r]);
-            const uint32_t l = (uint32_t)base0;
             if (!tl) {
-                o += l;
+                o += base0;
             } else {
-                const uint32_t ly = l / q.w, lx = l - ly * q.w;
+                uint32_t ly, lx;
+                divmod_small(base0, q.w, ly, lx);
                 const uint32_t ml = q.m < (uint32_t)L ? q.m : (uint32_t)L;
                 const uint32_t *s = sat + (int64_t)(ml - 1) * n_tiles;
                 if (ly) o += sat_rel_rect(s, q, 0, (int)q.w - 1, 0, (int)ly - 1);
@@ -430,28 +498,27 @@ k_emit(const uint4 *__restrict__ rec_s, const uint64_t *__restrict__ hpre, const
             }
         }
         for (uint64_t c0 = a_beg; c0 < a_end; c0 += 64) {
-            // start of entry r + lane relative to the chunk (entry r itself: 0)
+            // entries r+1 .. r+63 that start inside this step mark their first item
             const uint64_t rj = r + lane;
-            uint32_t rel = 0xffffffffu;
-            if (lane == 0) {
-                rel = 0;
-            } else if (rj < E) {
+            if (lane > 0 && rj < E) {
                 const uint64_t d = apre[rj] - c0;
-                rel = d < 0xffffffffu ? (uint32_t)d : 0xffffffffu;
+                if (d < 64) s_mark[wave][d] = ((uint32_t)lane << 6) | (uint32_t)d;
             }
-            int k = 0;
-#pragma unroll
-            for (int step = 32; step > 0; step >>= 1) {
-                const uint32_t t = __shfl(rel, k + step);
-                if (t <= (uint32_t)lane) k += step;
-            }
-            const uint32_t rel_k = __shfl(rel, k);
+            wave_lds_sync();
+            const uint32_t mark = s_mark[wave][lane];
+            wave_lds_sync();
+            s_mark[wave][lane] = 0;
+            const uint32_t km = wave_incl_max(mark);
+            uint32_t k = km >> 6;
+            const uint32_t l = k == 0 ? base0 + (uint32_t)lane : (uint32_t)lane - (km & 63u);
+            uint64_t re = r + k;
+            re = re < E ? re : E - 1;
             const bool valid = c0 + lane < a_end;
-            const SortedRec q = unpack_rec(rec_s[r + k]);
-            const uint32_t l = k == 0 ? (uint32_t)base0 + lane : (uint32_t)lane - rel_k;
-            const uint32_t ly = l / q.w, lx = l - ly * q.w;
+            const SortedRec q = unpack_rec(rec_s[re]);
+            uint32_t ly, lx;
+            divmod_small(l, q.w, ly, lx);
             const uint32_t gid = q.gid0 + ly * q.tiles_x + lx;
-            const bool keep = valid && (!tl || tl[2 * (uint64_t)gid] <= q.m);
+            const bool keep = valid && (!tl || (gid < (uint64_t)n_tiles && tl[2 * (uint64_t)gid] <= q.m));
             const uint64_t bal = ballot64(keep);
             if (keep) {
                 const uint64_t pos = o + (uint32_t)__popcll(bal & lt);
@@ -461,9 +528,10 @@ k_emit(const uint4 *__restrict__ rec_s, const uint64_t *__restrict__ hpre, const
                 }
             }
             o += (uint32_t)__popcll(bal);
-            // the next chunk starts one item after lane 63's
-            const int k63 = __shfl(k, 63);
-            const uint32_t l63 = __shfl(l, 63), area63 = __shfl(q.w * q.h, 63);
+            // the next step starts one item after lane 63's
+            const uint32_t k63 = __builtin_amdgcn_readlane(k, 63);
+            const uint32_t l63 = __builtin_amdgcn_readlane(l, 63);
+            const uint32_t area63 = __builtin_amdgcn_readlane(q.w * q.h, 63);
             if (l63 + 1 < area63) {
                 r += k63;
                 base0 = l63 + 1;
@@ -471,6 +539,7 @@ k_emit(const uint4 *__restrict__ rec_s, const uint64_t *__restrict__ hpre, const
                 r += k63 + 1;
                 base0 = 0;
             }
+            wave_lds_sync();
         }
     }
 }
@@ -572,12 +641,12 @@ hipError_t launch_bin_sort(const gs_splat *splats, int n, const gs_camera *cams_
         }
         const int lds = max_view_tiles <= SAT_LDS_TILES;
         hipLaunchKernelGGL(k_level_sat, dim3(V * L), dim3(256), lds ? 4 * max_view_tiles : 0, st, cams_dev,
-                           V, T, L, n_tiles, tile_level, bs.sat, lds);
+                           V, T, L, n_tiles, tile_level, bs.sat, bs.bbox, lds);
     }
     const int64_t nb = (E + SCAN_THREADS * SCAN_ITEMS - 1) / (SCAN_THREADS * SCAN_ITEMS);
     // 1-2: counts, then stable compaction of entries with keys (depth digits counted)
     hipLaunchKernelGGL(k_count, dim3((unsigned)nb), dim3(SCAN_THREADS), 0, st, splats, n, cams_dev, V, T, bs.vtab,
-                       filt ? bs.sat : nullptr, L, n_tiles, qbound, bs.hits, bs.rec, bs.dkey_b, hits_out,
+                       filt ? bs.sat : nullptr, bs.bbox, L, n_tiles, qbound, bs.hits, bs.rec, bs.dkey_b, hits_out,
                        bs.block_vis);
     hipLaunchKernelGGL(k_scan_blocks, dim3(1), dim3(1024), 0, st, bs.block_sums, bs.block_vis, nb, bs.counts,
                        nullptr, nullptr);

@@ -54,6 +54,7 @@ struct BinScratch {
     uint32_t *tkey_a, *tkey_b, *tval_b;           // [cap] tile-key sort ping-pong
     uint64_t *counts;                             // [4]: entries, keys, key capacity, rectangle area
     uint32_t *sat;                                // [4][n_tiles] level summed-area tables
+    int32_t *bbox;                                // [V][4][4] bounding box of each level's kept tiles
     RadixScratch rs;
 };
 constexpr int SCAN_THREADS = 256;

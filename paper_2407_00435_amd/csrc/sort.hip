@@ -25,7 +25,12 @@ constexpr uint64_t FLAG_INC = 2ull << 62;
 constexpr uint64_t VAL_MASK = (1ull << 62) - 1;
 constexpr int MIN_PART = 4096;
 
-__global__ void __launch_bounds__(256)
+// Digit counts of every pass.  Each thread takes HIST_RUN consecutive keys
+// and adds runs of equal digits with one LDS atomic (key lists built in
+// depth order hold long runs of neighbouring tile ids).
+constexpr int HIST_RUN = 16;
+
+__global__ void __launch_bounds__(1024)
 k_radix_hist(const uint32_t *__restrict__ keys, const uint64_t *__restrict__ d_count, uint64_t cap,
              int passes, int dbits, uint32_t *__restrict__ hist)
 {
@@ -35,20 +40,40 @@ k_radix_hist(const uint32_t *__restrict__ keys, const uint64_t *__restrict__ d_c
     uint64_t count = *d_count;
     count = count < cap ? count : cap;
     const uint32_t mask = (1u << dbits) - 1u;
-    // four keys per thread per step (16-byte loads)
-    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x * 4;
-    for (uint64_t i = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) * 4; i < count; i += stride) {
-        uint32_t k4[4];
-        const bool vec = i + 4 <= count && (reinterpret_cast<uintptr_t>(keys) & 15) == 0;
-        if (vec) {
-            const uint4 q = *reinterpret_cast<const uint4 *>(keys + i);
-            k4[0] = q.x; k4[1] = q.y; k4[2] = q.z; k4[3] = q.w;
-        }
+    const bool vec_ok = (reinterpret_cast<uintptr_t>(keys) & 15) == 0;
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x * HIST_RUN;
+    for (uint64_t i = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) * HIST_RUN; i < count; i += stride) {
+        uint32_t k[HIST_RUN];
+        const uint32_t nk = count - i < (uint64_t)HIST_RUN ? (uint32_t)(count - i) : (uint32_t)HIST_RUN;
+        if (vec_ok && nk == HIST_RUN) {
 #pragma unroll
-        for (int j = 0; j < 4; ++j) {
-            if (i + j >= count) break;
-            const uint32_t k = vec ? k4[j] : keys[i + j];
-            for (int p = 0; p < passes; ++p) atomicAdd(&sh[p][(k >> (dbits * p)) & mask], 1u);
+            for (int q = 0; q < HIST_RUN / 4; ++q) {
+                const uint4 v = reinterpret_cast<const uint4 *>(keys + i)[q];
+                k[4 * q] = v.x;
+                k[4 * q + 1] = v.y;
+                k[4 * q + 2] = v.z;
+                k[4 * q + 3] = v.w;
+            }
+        } else {
+#pragma unroll
+            for (int j = 0; j < HIST_RUN; ++j) k[j] = j < (int)nk ? keys[i + j] : 0u;
+        }
+        for (int p = 0; p < passes; ++p) {
+            const int sh_p = dbits * p;
+            uint32_t prev = (k[0] >> sh_p) & mask, run = 1;
+#pragma unroll
+            for (int j = 1; j < HIST_RUN; ++j) {
+                if (j >= (int)nk) break;
+                const uint32_t d = (k[j] >> sh_p) & mask;
+                if (d == prev) {
+                    ++run;
+                } else {
+                    atomicAdd(&sh[p][prev], run);
+                    prev = d;
+                    run = 1;
+                }
+            }
+            atomicAdd(&sh[p][prev], run);
         }
     }
     __syncthreads();
@@ -259,10 +284,13 @@ hipError_t radix_sort_pairs(uint32_t *ka, uint32_t *va, uint32_t *kb, uint32_t *
     const uint64_t parts = (cap + P - 1) / P;
     if (!hist_ready) {
         if ((e = launch_fill_u32(rs.hist, 0u, 4 * 256, st)) != hipSuccess) return e;
-        int hist_blocks = (int)((cap + 256 * 64 - 1) / (256 * 64));
-        if (hist_blocks > 2048) hist_blocks = 2048;
+        // few large blocks: each adds its counts to the global histogram
+        // with one atomic per digit, and same-address atomics from
+        // thousands of blocks would serialise in L2
+        int hist_blocks = (int)((cap + 1024 * HIST_RUN * 4 - 1) / (1024 * HIST_RUN * 4));
+        if (hist_blocks > 256) hist_blocks = 256;
         if (hist_blocks < 1) hist_blocks = 1;
-        hipLaunchKernelGGL(k_radix_hist, dim3(hist_blocks), dim3(256), 0, st, ka, d_count, cap, passes,
+        hipLaunchKernelGGL(k_radix_hist, dim3(hist_blocks), dim3(1024), 0, st, ka, d_count, cap, passes,
                            dbits, rs.hist);
     }
     hipLaunchKernelGGL(k_radix_prefix, dim3(passes), dim3(256), 0, st, rs.hist);
