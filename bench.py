@@ -219,6 +219,57 @@ def fwd_bwd_rate(g, wl, steps, warmup, tile=16):
     return dict(it_s=1.0 / dt, ms=dt * 1e3)
 
 
+def batched_vs_plain(g, steps=3, log=None):
+    """3M Gaussians, 32 orbit views at mixed resolutions (forward + L1 loss +
+    backward) plus the foveated forward of two eyes, as one step.  Batched:
+    the autotuned schedule replayed from a recorded graph.  Plain: one view
+    per call (and one eye per call), run eagerly, tile 16."""
+    import torch
+    import scenegen
+    from paper_2407_00435_amd import autotune
+    from paper_2407_00435_amd.batched import BatchedStep
+
+    wl = scenegen.config5()
+    S = g.SceneTensors(wl.scene)
+    cams, eyes, fov = wl.cams, wl.extra["eyes"], wl.extra["eye_foveae"]
+    C = g.Cameras(cams)
+    tgt_S = g.SceneTensors(scenegen.perturbed(wl.scene, 1006))
+    sp = g.gs_project(tgt_S, C, 16)
+    cap = int(sp[..., 11].view(torch.int32).to(torch.int64).sum().item()) + 1024
+    del sp
+    target = g.gs_render_fwd(tgt_S, C, 16, key_capacity=cap)["image"].clone()
+    del tgt_S
+    torch.cuda.empty_cache()
+    px = sum(c.width * c.height for c in cams) + sum(c.width * c.height for c in eyes)
+    if log:
+        log(f"batched: autotuning ({len(cams)} views + {len(eyes)} eyes, {px / 1e6:.1f} Mpix) ...")
+    best, tried = autotune.tune(S, cams, target, eyes, fov, reps=2, log=log)
+    step = BatchedStep(S, cams, target, best["tile"], best["batch_views"], eyes, fov)
+    ms_b = autotune.time_step(step, steps)
+    keys_b = int(step.num_keys.sum().item())
+    ok_b = step.keys_ok()
+    del step
+    torch.cuda.empty_cache()
+    g.gs_set_tuning("radix_part", 8192)
+    plain = BatchedStep(S, cams, target, 16, 1, eyes, fov, eye_batch=1)
+    plain.step()
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(plain.stream)
+    for _ in range(steps):
+        plain._enqueue()
+    e1.record(plain.stream)
+    torch.cuda.synchronize()
+    ms_p = e0.elapsed_time(e1) / steps
+    ok_p = plain.keys_ok()
+    return dict(workload="3M Gaussians SH3; 32 orbit views (640x360..1920x1080) fwd + L1 + bwd; "
+                         "2 foveated 1080p eyes fwd",
+                megapixels=px / 1e6, batched_it_s=1e3 / ms_b, batched_ms=ms_b, plain_it_s=1e3 / ms_p,
+                plain_ms=ms_p, speedup=ms_p / ms_b, autotuned=best, keys=keys_b,
+                capacity_ok=bool(ok_b and ok_p),
+                tried=[dict(c, ms=round(m, 3)) for c, m in tried])
+
+
 def cpu_baseline(fr, wl, n_gauss_sample=12000, px_sample=(3000, 9000), threads=16):
     """FP64 oracle on the host, on a bounded sample of the same workload:
     projection (with the four level versions) of a random subset of the
@@ -335,6 +386,8 @@ def main():
         line["plain_fwd_720p_500k"] = plain_fwd_rate(g, scenegen.config2(), 20, 3)
         log("forward+backward, 1M Gaussians, 1280x720 ...")
         line["fwd_bwd_720p_1M"] = fwd_bwd_rate(g, scenegen.config4(), 10, 3)
+        log("batched vs plain, 3M Gaussians, 32 views + 2 eyes ...")
+        line["batched_vs_plain"] = batched_vs_plain(g, 3, log)
     if not args.no_cpu_baseline:
         log("oracle on the host (bounded sample) ...")
         line["cpu_baseline"] = cpu_baseline(fr, wl)

@@ -209,12 +209,14 @@ int gs_rasterize_bwd(const gs_splat *splats, int32_t n, const gs_camera *cams_ho
                      void *stream);
 
 /* Reverse of gs_project: from grads [n_views][n] to the scene parameters,
- * summed over views.  Outputs (device, overwritten): d_means [n][3],
- * d_log_scales [n][3], d_quats [n][4], d_opacity_logits [n], d_sh [n][K][3]. */
+ * summed over views.  Outputs (device): d_means [n][3], d_log_scales [n][3],
+ * d_quats [n][4], d_opacity_logits [n], d_sh [n][K][3]; overwritten when
+ * accumulate is 0, added to when it is 1 (views rendered by separate calls
+ * sum their gradients this way). */
 int gs_project_bwd(const gs_scene *scene, const gs_camera *cams_host, const gs_camera *cams_dev,
                    int n_views, const gs_splat *splats, const gs_splat_grad *grads,
                    float *d_means, float *d_log_scales, float *d_quats,
-                   float *d_opacity_logits, float *d_sh, void *stream);
+                   float *d_opacity_logits, float *d_sh, int accumulate, void *stream);
 
 /* Foveation tables (Section 4.1; ring layout of Section 6).  For every pixel
  * of every eye: eccentricity = angle between the pinhole rays through the
@@ -269,6 +271,34 @@ int gs_render_fwd(const gs_scene *scene, const gs_camera *cams_host, const gs_ca
                   uint32_t *vals, uint32_t *tile_ranges, uint64_t key_capacity,
                   uint64_t *num_keys, float *image, float *final_T, uint32_t *n_contrib,
                   void *workspace, size_t workspace_bytes, void *stream);
+
+/* L1 photometric loss, the training objective used with the reverse pass
+ * (Section 3 trains against captured images; the scale sets the mean):
+ * loss += scale * sum_k |image[k] - target[k]| and dL_dimage[k] =
+ * scale * sign(image[k] - target[k]) (0 where equal).  image, target,
+ * dL_dimage: device float [n]; loss: device float, added to (reset = 1
+ * zeroes it first).  The sum is taken in float32 with block partials added
+ * atomically, so its last bits depend on scheduling.  Launches kernels
+ * only, so it may be captured in a graph. */
+int gs_l1_grad(const float *image, const float *target, uint64_t n, float scale, float *dL_dimage,
+               float *loss, int reset, void *stream);
+
+/* Graph capture of a sequence of calls on one stream (every entry point
+ * above except gs_sort_pairs launches kernels only: no allocation, host
+ * synchronisation or host copies, so a fixed sequence of them on
+ * preallocated buffers can be recorded once and replayed).
+ * gs_graph_begin starts capture on `stream` (not the legacy default
+ * stream); the calls that follow on that stream are recorded, not run;
+ * gs_graph_end stops capture and instantiates the graph into *graph (owned
+ * by the caller, released with gs_graph_destroy).  gs_graph_launch replays
+ * it on a stream: pointers, sizes and host-side arguments (cameras, tile
+ * size, capacities) are those of the capture; the contents of device
+ * buffers are read afresh at each replay. */
+typedef struct gs_graph gs_graph;
+int gs_graph_begin(void *stream);
+int gs_graph_end(void *stream, gs_graph **graph);
+int gs_graph_launch(gs_graph *graph, void *stream);
+int gs_graph_destroy(gs_graph *graph);
 
 /* Process-wide tuning knob (not thread-safe against concurrent calls):
  *   "radix_part": keys per sort workgroup, 4096, 8192 (default) or 16384.

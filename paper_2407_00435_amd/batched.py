@@ -1,0 +1,159 @@
+"""Batched multi-view forward + backward, recorded once as a graph.
+
+One training step over a fixed camera set: projection, binning/sort and
+compositing of every view, the L1 loss against per-view targets, the
+compositing reverse and the projection reverse (gradients summed over
+views), plus the foveated forward of the two eyes.  Views are processed in
+sub-batches of ``batch_views`` consecutive views; within a sub-batch every
+stage is one library call over all its views (each Gaussian is read once
+for all of them, one global tile space, one sort, one compositing launch
+and one reverse launch).  ``batch_views = 1`` is the plain
+one-view-per-launch schedule (``eye_batch = 1`` likewise renders one eye
+per call).  All buffers are allocated up front, so the
+whole step is a fixed sequence of kernel launches on one stream and is
+captured with the library's graph calls and replayed.
+
+Torch only provides device memory and the stream; every step runs in the
+library's kernels.
+"""
+from __future__ import annotations
+
+import ctypes
+
+import torch
+
+from . import binding as B
+
+
+class BatchedStep:
+    def __init__(self, scene: B.SceneTensors, cams: list, target: torch.Tensor, tile_size: int = 16,
+                 batch_views: int | None = None, eyes: list | None = None, foveae: list | None = None,
+                 key_margin: float = 1.05, stream: torch.cuda.Stream | None = None,
+                 eye_batch: int | None = None):
+        dev = scene.t["means"].device
+        self.scene, self.tile = scene, tile_size
+        self.stream = stream or torch.cuda.Stream(device=dev)
+        V = len(cams)
+        bv = V if not batch_views else max(1, min(int(batch_views), V))
+        self.batch_views = bv
+        self.groups = []
+        px_off = 0
+        cap_max, n_px_max, tiles_max, ws_max = 1, 1, 1, 256
+        for a in range(0, V, bv):
+            C = B.Cameras(cams[a:a + bv], device=dev)
+            n_tiles, n_px = C.tiles(tile_size)
+            splats = B.gs_project(scene, C, tile_size)
+            cap = int(B.splat_fields(splats)["tiles_touched"].to(torch.int64).sum().item())
+            cap = max(int(cap * key_margin) + 1024, 1)
+            self.groups.append(dict(C=C, n_tiles=n_tiles, n_px=n_px, px_off=px_off, cap=cap))
+            px_off += n_px
+            cap_max, n_px_max, tiles_max = max(cap_max, cap), max(n_px_max, n_px), max(tiles_max, n_tiles)
+            ws_max = max(ws_max, B.gs_workspace_bytes(C, scene.n, tile_size, cap))
+            del splats
+        self.n_px = px_off
+        if target.numel() != 3 * self.n_px:
+            raise ValueError(f"target has {target.numel()} floats, the views need {3 * self.n_px}")
+        self.target = target.contiguous()
+        n, Vb = scene.n, bv
+        f32 = dict(dtype=torch.float32, device=dev)
+        i32 = dict(dtype=torch.int32, device=dev)
+        # per-sub-batch scratch, reused by every sub-batch
+        self.splats = torch.empty((Vb, n, 12), **f32)
+        self.sgrads = torch.empty((Vb, n, 12), **f32)
+        self.vals = torch.empty(cap_max, **i32)
+        self.ranges = torch.empty((tiles_max, 2), **i32)
+        self.num_keys = torch.zeros(len(self.groups), dtype=torch.int64, device=dev)
+        self.ws_t, self.ws, self.wsn = B._ws(ws_max)
+        # whole-step outputs
+        self.image = torch.empty(3 * self.n_px, **f32)
+        self.final_T = torch.empty(self.n_px, **f32)
+        self.n_contrib = torch.empty(self.n_px, **i32)
+        self.dL = torch.empty(3 * self.n_px, **f32)
+        self.loss = torch.zeros(1, **f32)
+        self.grads = {k: torch.empty_like(scene.t[k]) for k in B.PARAM_NAMES}
+        self.scale = 1.0 / (3 * self.n_px)
+        self.bg = (ctypes.c_float * 3)(0.0, 0.0, 0.0)
+        self.scene_struct = scene.struct(levels=False)
+        # foveated eyes (forward), in groups of eye_batch eyes per call
+        self.eye_groups = []
+        self.eye_image = None
+        if eyes:
+            if scene.n_levels == 0:
+                raise ValueError("foveated eyes need a scene with quality levels")
+            eb = len(eyes) if not eye_batch else max(1, min(int(eye_batch), len(eyes)))
+            e_off, e_ws = 0, 256
+            for a in range(0, len(eyes), eb):
+                E = B.Cameras(eyes[a:a + eb], device=dev)
+                _, e_px = E.tiles(tile_size)
+                probe = B.gs_project(scene, E, tile_size)
+                e_cap = int(B.splat_fields(probe)["tiles_touched"].to(torch.int64).sum().item()) + 1024
+                del probe
+                e_ws = max(e_ws, B.gs_render_workspace_bytes(E, scene.n, scene.n_levels, tile_size, e_cap))
+                self.eye_groups.append(dict(C=E, fov=B._foveae(foveae[a:a + eb]), cap=e_cap, px_off=e_off,
+                                            n_px=e_px))
+                e_off += e_px
+            self.eye_ws = B._ws(e_ws)
+            self.eye_image = torch.empty(3 * e_off, **f32)
+            self.eye_num = torch.zeros(len(self.eye_groups), dtype=torch.int64, device=dev)
+            self.eye_struct = scene.struct(levels=True)
+        self.graph = None
+
+    def _enqueue(self):
+        L, g = B.lib(), self
+        st = ctypes.c_void_p(self.stream.cuda_stream)
+        P = B._ptr
+        for k, grp in enumerate(self.groups):
+            C, o, npx = grp["C"], grp["px_off"], grp["n_px"]
+            img = self.image[3 * o:3 * (o + npx)]
+            fT = self.final_T[o:o + npx]
+            nc = self.n_contrib[o:o + npx]
+            dL = self.dL[3 * o:3 * (o + npx)]
+            tg = self.target[3 * o:3 * (o + npx)]
+            B._check(L.gs_render_fwd(ctypes.byref(self.scene_struct), C.hp, C.dp, C.n, g.tile,
+                                     ctypes.cast(g.bg, B._VP), P(g.splats), P(g.vals), P(g.ranges),
+                                     grp["cap"], P(g.num_keys[k:k + 1]), P(img), P(fT), P(nc), g.ws, g.wsn,
+                                     st))
+            B._check(L.gs_l1_grad(P(img), P(tg), 3 * npx, ctypes.c_float(g.scale), P(dL), P(g.loss),
+                                  1 if k == 0 else 0, st))
+            B._check(L.gs_rasterize_bwd(P(g.splats), g.scene.n, C.hp, C.dp, C.n, g.tile, P(g.vals),
+                                        P(g.ranges), ctypes.cast(g.bg, B._VP), P(fT), P(nc), P(dL),
+                                        P(g.sgrads), None, 0, st))
+            gr = g.grads
+            B._check(L.gs_project_bwd(ctypes.byref(self.scene_struct), C.hp, C.dp, C.n, P(g.splats),
+                                      P(g.sgrads), P(gr["means"]), P(gr["log_scales"]), P(gr["quats"]),
+                                      P(gr["opacity_logits"]), P(gr["sh"]), 1 if k > 0 else 0, st))
+        for k, e in enumerate(self.eye_groups):
+            o, npx = e["px_off"], e["n_px"]
+            B._check(L.gs_render_foveated(ctypes.byref(self.eye_struct), e["C"].hp, e["C"].dp,
+                                          ctypes.cast(e["fov"], B._PF), e["C"].n, g.tile,
+                                          ctypes.cast(g.bg, B._VP), P(self.eye_image[3 * o:3 * (o + npx)]),
+                                          e["cap"], P(self.eye_num[k:k + 1]), self.eye_ws[1], self.eye_ws[2],
+                                          st))
+
+    def step(self):
+        """Run one step eagerly on this object's stream."""
+        self.stream.wait_stream(torch.cuda.current_stream())
+        self._enqueue()
+        torch.cuda.current_stream().wait_stream(self.stream)
+
+    def capture(self):
+        """Record one step as a graph (nothing runs during the recording)."""
+        torch.cuda.synchronize()
+        with B.Graph.capture(self.stream) as cap:
+            self._enqueue()
+        self.graph = cap.graph
+        return self.graph
+
+    def replay(self):
+        self.stream.wait_stream(torch.cuda.current_stream())
+        self.graph.launch(self.stream)
+        torch.cuda.current_stream().wait_stream(self.stream)
+
+    def keys_ok(self):
+        """True if no sub-batch needed more keys than its capacity (reads back)."""
+        caps = torch.tensor([g["cap"] for g in self.groups], dtype=torch.int64)
+        ok = bool((self.num_keys.cpu() <= caps).all())
+        if self.eye_groups:
+            ecaps = torch.tensor([e["cap"] for e in self.eye_groups], dtype=torch.int64)
+            ok = ok and bool((self.eye_num.cpu() <= ecaps).all())
+        return ok

@@ -72,7 +72,7 @@ _SIGS = {
                           _SZ, _VP], _I),
     "gs_rasterize_bwd": ([_VP, _I32, _PC, _VP, _I, _I, _VP, _VP, _VP, _VP, _VP, _VP, _VP, _VP, _SZ,
                           _VP], _I),
-    "gs_project_bwd": ([_PS, _PC, _VP, _I, _VP, _VP, _VP, _VP, _VP, _VP, _VP, _VP], _I),
+    "gs_project_bwd": ([_PS, _PC, _VP, _I, _VP, _VP, _VP, _VP, _VP, _VP, _VP, _I, _VP], _I),
     "gs_fovea_prep": ([_PC, _VP, _PF, _I, _I, _I, _VP, _VP, _VP, _VP], _I),
     "gs_rasterize_foveated": ([_VP, _VP, _I32, _VP, _I, _PC, _VP, _I, _I, _VP, _VP, _VP, _VP, _VP,
                                _VP, _VP, _VP, _SZ, _VP], _I),
@@ -82,6 +82,11 @@ _SIGS = {
     "gs_sort_workspace_bytes": ([_U64], _SZ),
     "gs_set_tuning": ([ctypes.c_char_p, ctypes.c_int64], _I),
     "gs_sort_pairs": ([_VP, _VP, _VP, _VP, _U64, _I, _VP, _SZ, _VP], _I),
+    "gs_l1_grad": ([_VP, _VP, _U64, ctypes.c_float, _VP, _VP, _I, _VP], _I),
+    "gs_graph_begin": ([_VP], _I),
+    "gs_graph_end": ([_VP, ctypes.POINTER(_VP)], _I),
+    "gs_graph_launch": ([_VP, _VP], _I),
+    "gs_graph_destroy": ([_VP], _I),
 }
 EXPORTED = tuple(_SIGS)
 
@@ -290,14 +295,73 @@ def gs_rasterize_bwd(splats, n, cams: Cameras, tile_size, vals, ranges, final_T,
     return grads
 
 
-def gs_project_bwd(scene: SceneTensors, cams: Cameras, splats, grads):
+PARAM_NAMES = ("means", "log_scales", "quats", "opacity_logits", "sh")
+
+
+def gs_project_bwd(scene: SceneTensors, cams: Cameras, splats, grads, out=None, accumulate=False):
+    """Parameter gradients summed over the views; written into ``out`` (a dict
+    of tensors shaped like the parameters) when given, added to it if
+    ``accumulate``."""
     t = scene.t
-    out = {k: torch.empty_like(t[k]) for k in ("means", "log_scales", "quats", "opacity_logits", "sh")}
+    if out is None:
+        out = {k: torch.empty_like(t[k]) for k in PARAM_NAMES}
     st = scene.struct(levels=False)
     _check(lib().gs_project_bwd(ctypes.byref(st), cams.hp, cams.dp, cams.n, _ptr(splats), _ptr(grads),
                                 _ptr(out["means"]), _ptr(out["log_scales"]), _ptr(out["quats"]),
-                                _ptr(out["opacity_logits"]), _ptr(out["sh"]), _stream()))
+                                _ptr(out["opacity_logits"]), _ptr(out["sh"]), int(bool(accumulate)),
+                                _stream()))
     return out
+
+
+def gs_l1_grad(image, target, scale, dL_dimage, loss, reset=True):
+    """loss (+)= scale * sum|image - target|; dL_dimage = scale * sign(image - target)."""
+    _check(lib().gs_l1_grad(_ptr(image), _ptr(target), image.numel(), float(scale), _ptr(dL_dimage),
+                            _ptr(loss), int(bool(reset)), _stream()))
+
+
+class Graph:
+    """A recorded sequence of library calls on one stream, replayed with
+    ``launch``.  Record with ``with Graph.capture(stream) as g: ...``."""
+
+    def __init__(self, handle):
+        self._h = handle
+
+    @staticmethod
+    def capture(stream):
+        return _Capture(stream)
+
+    def launch(self, stream=None):
+        s = stream if stream is not None else torch.cuda.current_stream()
+        _check(lib().gs_graph_launch(self._h, ctypes.c_void_p(s.cuda_stream)))
+
+    def close(self):
+        if self._h:
+            _check(lib().gs_graph_destroy(self._h))
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class _Capture:
+    def __init__(self, stream):
+        self.stream = stream
+        self.graph = None
+
+    def __enter__(self):
+        _check(lib().gs_graph_begin(ctypes.c_void_p(self.stream.cuda_stream)))
+        return self
+
+    def __exit__(self, et, ev, tb):
+        h = ctypes.c_void_p()
+        rc = lib().gs_graph_end(ctypes.c_void_p(self.stream.cuda_stream), ctypes.byref(h))
+        if et is None:
+            _check(rc)
+            self.graph = Graph(h)
+        return False
 
 
 def _foveae(foveae):

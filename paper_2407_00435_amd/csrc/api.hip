@@ -8,6 +8,7 @@
 
 #include "common.hpp"
 #include "kernels.hpp"
+#include <new>
 
 namespace {
 
@@ -308,10 +309,11 @@ int gs_rasterize_bwd(const gs_splat *splats, int32_t n, const gs_camera *cams_ho
 int gs_project_bwd(const gs_scene *scene, const gs_camera *cams_host, const gs_camera *cams_dev,
                    int n_views, const gs_splat *splats, const gs_splat_grad *grads, float *d_means,
                    float *d_log_scales, float *d_quats, float *d_opacity_logits, float *d_sh,
-                   void *stream)
+                   int accumulate, void *stream)
 {
     int r;
     if ((r = check_scene(scene, false))) return r;
+    if (accumulate != 0 && accumulate != 1) return fail(GS_ERR_INVALID, "accumulate must be 0 or 1");
     if ((r = check_cams(cams_host, cams_dev, n_views, 16, nullptr, nullptr))) return r;
     if (scene->n > 0 &&
         (!splats || !grads || !d_means || !d_log_scales || !d_quats || !d_opacity_logits || !d_sh))
@@ -320,7 +322,7 @@ int gs_project_bwd(const gs_scene *scene, const gs_camera *cams_host, const gs_c
     if ((scene->sh_degree == 1 || scene->sh_degree == 3) && !aligned(d_sh, 16))
         return fail(GS_ERR_INVALID, "d_sh must be 16-byte aligned");
     hipError_t e = launch_project_bwd(*scene, cams_dev, n_views, splats, grads, d_means, d_log_scales,
-                                      d_quats, d_opacity_logits, d_sh, (hipStream_t)stream);
+                                      d_quats, d_opacity_logits, d_sh, accumulate, (hipStream_t)stream);
     if (e != hipSuccess) return hip_fail(e, "gs_project_bwd");
     return ok();
 }
@@ -445,6 +447,74 @@ int gs_render_fwd(const gs_scene *scene, const gs_camera *cams_host, const gs_ca
 }
 
 size_t gs_sort_workspace_bytes(uint64_t n) { return radix_sort_scratch_bytes(n); }
+
+int gs_l1_grad(const float *image, const float *target, uint64_t n, float scale, float *dL_dimage,
+               float *loss, int reset, void *stream)
+{
+    if (!loss || (n > 0 && (!image || !target || !dL_dimage)))
+        return fail(GS_ERR_INVALID, "NULL output or input pointer");
+    if (reset != 0 && reset != 1) return fail(GS_ERR_INVALID, "reset must be 0 or 1");
+    hipError_t e;
+    if (reset && (e = launch_fill_u32(reinterpret_cast<uint32_t *>(loss), 0u, 1, (hipStream_t)stream)) !=
+                     hipSuccess)
+        return hip_fail(e, "gs_l1_grad");
+    if ((e = launch_l1_grad(image, target, n, scale, dL_dimage, loss, (hipStream_t)stream)) != hipSuccess)
+        return hip_fail(e, "gs_l1_grad");
+    return ok();
+}
+
+struct gs_graph {
+    hipGraph_t graph;
+    hipGraphExec_t exec;
+};
+
+int gs_graph_begin(void *stream)
+{
+    if (!stream) return fail(GS_ERR_INVALID, "graph capture needs a non-default stream");
+    hipError_t e = hipStreamBeginCapture((hipStream_t)stream, hipStreamCaptureModeThreadLocal);
+    if (e != hipSuccess) return hip_fail(e, "gs_graph_begin");
+    return ok();
+}
+
+int gs_graph_end(void *stream, gs_graph **graph)
+{
+    if (!stream || !graph) return fail(GS_ERR_INVALID, "NULL stream or graph pointer");
+    *graph = nullptr;
+    hipGraph_t g = nullptr;
+    hipError_t e = hipStreamEndCapture((hipStream_t)stream, &g);
+    if (e != hipSuccess) return hip_fail(e, "gs_graph_end (capture)");
+    hipGraphExec_t x = nullptr;
+    e = hipGraphInstantiate(&x, g, nullptr, nullptr, 0);
+    if (e != hipSuccess) {
+        hipGraphDestroy(g);
+        return hip_fail(e, "gs_graph_end (instantiate)");
+    }
+    gs_graph *out = new (std::nothrow) gs_graph{g, x};
+    if (!out) {
+        hipGraphExecDestroy(x);
+        hipGraphDestroy(g);
+        return fail(GS_ERR_INVALID, "out of host memory");
+    }
+    *graph = out;
+    return ok();
+}
+
+int gs_graph_launch(gs_graph *graph, void *stream)
+{
+    if (!graph) return fail(GS_ERR_INVALID, "NULL graph");
+    hipError_t e = hipGraphLaunch(graph->exec, (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(e, "gs_graph_launch");
+    return ok();
+}
+
+int gs_graph_destroy(gs_graph *graph)
+{
+    if (!graph) return ok();
+    hipGraphExecDestroy(graph->exec);
+    hipGraphDestroy(graph->graph);
+    delete graph;
+    return ok();
+}
 
 int gs_set_tuning(const char *name, int64_t value)
 {

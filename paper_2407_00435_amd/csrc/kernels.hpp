@@ -11,7 +11,12 @@ hipError_t launch_project(const gs_scene &sc, const gs_camera *cams_dev, int V, 
                           gs_splat *out, float *lvl_rgba, hipStream_t st);
 hipError_t launch_project_bwd(const gs_scene &sc, const gs_camera *cams_dev, int V,
                               const gs_splat *splats, const gs_splat_grad *grads, float *g_means,
-                              float *g_ls, float *g_q, float *g_logit, float *g_sh, hipStream_t st);
+                              float *g_ls, float *g_q, float *g_logit, float *g_sh, int accumulate,
+                              hipStream_t st);
+
+// losses
+hipError_t launch_l1_grad(const float *image, const float *target, uint64_t n, float scale,
+                          float *dL_dimage, float *loss, hipStream_t st);
 
 // radix sort of (u32 key, u32 value) pairs, LSD over bits [0, bits)
 struct RadixScratch {

@@ -210,7 +210,7 @@ k_project_bwd(const float *__restrict__ means, const float *__restrict__ log_sca
               const float *__restrict__ sh, const gs_camera *__restrict__ cams, int V, int n,
               const gs_splat *__restrict__ splats, const gs_splat_grad *__restrict__ grads,
               float *__restrict__ g_means, float *__restrict__ g_ls, float *__restrict__ g_q,
-              float *__restrict__ g_logit, float *__restrict__ g_sh)
+              float *__restrict__ g_logit, float *__restrict__ g_sh, int acc)
 {
     constexpr int K = (DEG + 1) * (DEG + 1);
     int i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -376,7 +376,7 @@ k_project_bwd(const float *__restrict__ means, const float *__restrict__ log_sca
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
         float ds = dM[k] * Rq.m[k] + dM[3 + k] * Rq.m[3 + k] + dM[6 + k] * Rq.m[6 + k];
-        g_ls[3 * (int64_t)i + k] = ds * s[k];
+        g_ls[3 * (int64_t)i + k] = (acc ? g_ls[3 * (int64_t)i + k] : 0.f) + ds * s[k];
 #pragma unroll
         for (int r = 0; r < 3; ++r) dR[r * 3 + k] = dM[r * 3 + k] * s[k];
     }
@@ -391,6 +391,13 @@ k_project_bwd(const float *__restrict__ means, const float *__restrict__ log_sca
     float pr = w * dw + x * dxq + y * dyq + z * dzq;
     float4 gq = make_float4((dw - w * pr) * qn_inv, (dxq - x * pr) * qn_inv, (dyq - y * pr) * qn_inv,
                             (dzq - z * pr) * qn_inv);
+    if (acc) {
+        const float4 o = reinterpret_cast<const float4 *>(g_q)[i];
+        gq = make_float4(o.x + gq.x, o.y + gq.y, o.z + gq.z, o.w + gq.w);
+#pragma unroll
+        for (int k = 0; k < 3; ++k) gm[k] += g_means[3 * (int64_t)i + k];
+        glogit += g_logit[i];
+    }
     reinterpret_cast<float4 *>(g_q)[i] = gq;
     g_means[3 * (int64_t)i] = gm[0];
     g_means[3 * (int64_t)i + 1] = gm[1];
@@ -400,11 +407,17 @@ k_project_bwd(const float *__restrict__ means, const float *__restrict__ log_sca
     if constexpr ((K * 3) % 4 == 0) {
         float4 *p4 = reinterpret_cast<float4 *>(gs_out);
 #pragma unroll
-        for (int k = 0; k < K * 3 / 4; ++k)
-            p4[k] = make_float4(gsh[4 * k], gsh[4 * k + 1], gsh[4 * k + 2], gsh[4 * k + 3]);
+        for (int k = 0; k < K * 3 / 4; ++k) {
+            float4 v = make_float4(gsh[4 * k], gsh[4 * k + 1], gsh[4 * k + 2], gsh[4 * k + 3]);
+            if (acc) {
+                const float4 o = p4[k];
+                v = make_float4(o.x + v.x, o.y + v.y, o.z + v.z, o.w + v.w);
+            }
+            p4[k] = v;
+        }
     } else {
 #pragma unroll
-        for (int k = 0; k < K * 3; ++k) gs_out[k] = gsh[k];
+        for (int k = 0; k < K * 3; ++k) gs_out[k] = (acc ? gs_out[k] : 0.f) + gsh[k];
     }
 }
 
@@ -440,7 +453,8 @@ hipError_t launch_project(const gs_scene &sc, const gs_camera *cams_dev, int V, 
 
 hipError_t launch_project_bwd(const gs_scene &sc, const gs_camera *cams_dev, int V,
                               const gs_splat *splats, const gs_splat_grad *grads, float *g_means,
-                              float *g_ls, float *g_q, float *g_logit, float *g_sh, hipStream_t st)
+                              float *g_ls, float *g_q, float *g_logit, float *g_sh, int accumulate,
+                              hipStream_t st)
 {
     int n = sc.n;
     if (n == 0) return hipSuccess;
@@ -448,7 +462,7 @@ hipError_t launch_project_bwd(const gs_scene &sc, const gs_camera *cams_dev, int
 #define GS_PB(DEG)                                                                                     \
     hipLaunchKernelGGL((k_project_bwd<DEG>), grid, block, 0, st, sc.means, sc.log_scales, sc.quats,  \
                        sc.opacity_logits, sc.sh, cams_dev, V, n, splats, grads, g_means, g_ls, g_q,   \
-                       g_logit, g_sh);
+                       g_logit, g_sh, accumulate);
     switch (sc.sh_degree) {
     case 0: GS_PB(0); break;
     case 1: GS_PB(1); break;
