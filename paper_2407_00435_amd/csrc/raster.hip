@@ -359,12 +359,26 @@ k_raster_fov(const gs_splat *__restrict__ splats, const float4 *__restrict__ lvl
 // blended splat: T_i = T_(i+1) / (1 - alpha_i) starting from final_T, and the
 // light behind i (including the background) is accumulated on the way, so
 //   dL/dc_i = g alpha_i T_i,  dL/dalpha_i = sum_ch g (c_i T_i - B_i / (1 - alpha_i)).
-// Gradients of one splat are summed over the wave's 64 pixels with DPP
-// reductions before one float atomic per quantity.
+// The tile's list is walked in chunks of 64 positions by all its waves
+// together.  Gradients of one splat are summed over a wave's 64 pixels with
+// DPP reductions, then over the tile's waves in LDS, and leave the tile as
+// one float atomic per quantity per chunk: the global atomics, not the
+// arithmetic, bound this kernel.
 struct BwdRec {
     float4 a, b, c;   // forward record (identical decisions)
     float4 raw;       // conic A, B, C, opacity
 };
+
+// Sum over the 64 lanes of a wave, complete in lane 63 only: row sums, then
+// row broadcasts (lane 15 of row 0 into row 1 and of row 2 into row 3, then
+// lane 31 into row 3) -- six DPP adds, no lane reads.
+__device__ __forceinline__ float wave_total_63(float x)
+{
+    x = row_sum16(x);
+    x += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), 0x142, 0xA, 0xF, false));
+    x += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), 0x143, 0x8, 0xF, false));
+    return x;
+}
 
 template <int T>
 __global__ void __launch_bounds__(T *T)
@@ -376,7 +390,11 @@ k_raster_bwd(const gs_splat *__restrict__ splats, int n, const gs_camera *__rest
 {
     constexpr int WAVES = T * T / 64;
     constexpr int SUB = T / 8;
+    constexpr int NG = 9;  // mean x, y, conic A, B, C, opacity, colour r, g, b
     __shared__ BwdRec s_rec[WAVES][64];
+    __shared__ float s_grad[NG][64];
+    __shared__ uint32_t s_id[64];
+    __shared__ uint32_t s_maxnc;
     const int64_t gtile = blockIdx.x;
     const ViewInfo vi = view_of_tile(cams, V, T, gtile);
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
@@ -392,6 +410,8 @@ k_raster_bwd(const gs_splat *__restrict__ splats, int n, const gs_camera *__rest
     const int64_t pix = vi.pix_off + (int64_t)py * vi.W + px;
     const int64_t vbase = (int64_t)vi.v * n;
 
+    if (threadIdx.x == 0) s_maxnc = 0;
+    for (int q = threadIdx.x; q < NG * 64; q += T * T) (&s_grad[0][0])[q] = 0.f;
     uint32_t nc = 0;
     float Tr = 1.0f, g0 = 0.f, g1 = 0.f, g2 = 0.f;
     if (inside) {
@@ -407,93 +427,113 @@ k_raster_bwd(const gs_splat *__restrict__ splats, int n, const gs_camera *__rest
     float B0 = Tr * bg0, B1 = Tr * bg1, B2 = Tr * bg2;
     uint32_t maxnc = nc;
     for (int off = 32; off > 0; off >>= 1) maxnc = max(maxnc, (uint32_t)__shfl_xor((int)maxnc, off));
+    __syncthreads();
+    if (lane == 0) atomicMax(&s_maxnc, maxnc);
+    __syncthreads();
+    const uint32_t maxnc_tile = s_maxnc;
 
-    // walk chunks of 64 positions back to front: positions [p0, p1], 1-based
-    for (int64_t p1 = maxnc; p1 >= 1; p1 -= 64) {
+    // chunks of 64 positions back to front: positions [p0, p1], 1-based
+    for (int64_t p1 = maxnc_tile; p1 >= 1; p1 -= 64) {
         const int64_t p0 = p1 - 63 >= 1 ? p1 - 63 : 1;
-        const int64_t pos = p0 + lane;
-        bool keep = false;
-        // the record is fully defined on every lane before the cull decision
-        BwdRec rec;
-        rec.a = rec.b = rec.c = rec.raw = make_float4(0.f, 0.f, 0.f, 0.f);
-        if (pos <= p1) {
-            const uint32_t idx = start + (uint32_t)(pos - 1);
-            const uint32_t id = vals[idx];
-            const float4 *s4 = reinterpret_cast<const float4 *>(splats + vbase + id);
-            const float4 s0 = s4[0], s1 = s4[1], s2 = s4[2];
-            const FwdRec f = make_rec(s0, s1, s2, (uint32_t)pos, id);
-            rec.a = f.a;
-            rec.b = f.b;
-            rec.c = f.c;
-            rec.raw = make_float4(s0.z, s0.w, s1.x, s1.y);
-            keep = reaches_rect(s0.x, s0.y, s0.z, s0.w, s1.x, qmax_of(s1.y), rx0, rx1, ry0, ry1);
+        if (threadIdx.x < 64) {
+            const int64_t pos = p0 + threadIdx.x;
+            s_id[threadIdx.x] = pos <= p1 ? vals[start + (uint32_t)(pos - 1)] : 0u;
         }
-        const uint64_t msk = ballot64(keep);
-        if (keep) s_rec[wave][__popcll(msk & lanemask_lt())] = rec;
-        wave_lds_sync();
-        const int cnt = __popcll(msk);
-        for (int j = cnt - 1; j >= 0; --j) {
-            const float4 a = s_rec[wave][j].a, b = s_rec[wave][j].b;
-            const uint32_t ppos = __float_as_uint(b.w);
-            float gmx = 0.f, gmy = 0.f, gA = 0.f, gB = 0.f, gC = 0.f, gop = 0.f;
-            float gr = 0.f, gg = 0.f, gb = 0.f;
-            bool contrib = false;
-            if (ppos <= nc) {
-                const float e2 = pair_e2(a, b, fpx, fpy);
-                if (e2 >= b.z) {
-                    contrib = true;
-                    const float4 c = s_rec[wave][j].c, raw = s_rec[wave][j].raw;
-                    const float araw = fast_exp2(e2);
-                    const float alpha = fminf(GS_ALPHA_MAX, araw);
-                    const float oma = 1.0f - alpha;
-                    Tr = Tr / oma;
-                    const float wT = alpha * Tr;
-                    gr = g0 * wT;
-                    gg = g1 * wT;
-                    gb = g2 * wT;
-                    const float ioma = 1.0f / oma;
-                    const float dLda = g0 * (c.x * Tr - B0 * ioma) + g1 * (c.y * Tr - B1 * ioma) +
-                                       g2 * (c.z * Tr - B2 * ioma);
-                    B0 = fmaf(c.x, wT, B0);
-                    B1 = fmaf(c.y, wT, B1);
-                    B2 = fmaf(c.z, wT, B2);
-                    if (araw <= GS_ALPHA_MAX) {
-                        gop = dLda * alpha / raw.w;
-                        const float dLdq = -0.5f * alpha * dLda;
-                        const float dx = fpx - a.x, dy = fpy - a.y;
-                        gA = dLdq * dx * dx;
-                        gB = dLdq * 2.0f * dx * dy;
-                        gC = dLdq * dy * dy;
-                        gmx = -2.0f * dLdq * (raw.x * dx + raw.y * dy);
-                        gmy = -2.0f * dLdq * (raw.y * dx + raw.z * dy);
+        if ((uint32_t)p0 <= maxnc) {
+            const int64_t pos = p0 + lane;
+            bool keep = false;
+            // the record is fully defined on every lane before the cull decision
+            BwdRec rec;
+            rec.a = rec.b = rec.c = rec.raw = make_float4(0.f, 0.f, 0.f, 0.f);
+            if (pos <= p1 && pos <= (int64_t)maxnc) {
+                const uint32_t idx = start + (uint32_t)(pos - 1);
+                const uint32_t id = vals[idx];
+                const float4 *s4 = reinterpret_cast<const float4 *>(splats + vbase + id);
+                const float4 s0 = s4[0], s1 = s4[1], s2 = s4[2];
+                const FwdRec f = make_rec(s0, s1, s2, (uint32_t)pos, id);
+                rec.a = f.a;
+                rec.b = f.b;
+                rec.c = f.c;
+                rec.raw = make_float4(s0.z, s0.w, s1.x, s1.y);
+                keep = reaches_rect(s0.x, s0.y, s0.z, s0.w, s1.x, qmax_of(s1.y), rx0, rx1, ry0, ry1);
+            }
+            const uint64_t msk = ballot64(keep);
+            if (keep) s_rec[wave][__popcll(msk & lanemask_lt())] = rec;
+            wave_lds_sync();
+            const int cnt = __popcll(msk);
+            for (int j = cnt - 1; j >= 0; --j) {
+                const float4 a = s_rec[wave][j].a, b = s_rec[wave][j].b;
+                const uint32_t ppos = __float_as_uint(b.w);
+                float gmx = 0.f, gmy = 0.f, gA = 0.f, gB = 0.f, gC = 0.f, gop = 0.f;
+                float gr = 0.f, gg = 0.f, gb = 0.f;
+                bool contrib = false;
+                if (ppos <= nc) {
+                    const float e2 = pair_e2(a, b, fpx, fpy);
+                    if (e2 >= b.z) {
+                        contrib = true;
+                        const float4 c = s_rec[wave][j].c, raw = s_rec[wave][j].raw;
+                        const float araw = fast_exp2(e2);
+                        const float alpha = fminf(GS_ALPHA_MAX, araw);
+                        const float oma = 1.0f - alpha;
+                        const float ioma = __builtin_amdgcn_rcpf(oma);
+                        Tr = Tr * ioma;
+                        const float wT = alpha * Tr;
+                        gr = g0 * wT;
+                        gg = g1 * wT;
+                        gb = g2 * wT;
+                        const float dLda = g0 * (c.x * Tr - B0 * ioma) + g1 * (c.y * Tr - B1 * ioma) +
+                                           g2 * (c.z * Tr - B2 * ioma);
+                        B0 = fmaf(c.x, wT, B0);
+                        B1 = fmaf(c.y, wT, B1);
+                        B2 = fmaf(c.z, wT, B2);
+                        if (araw <= GS_ALPHA_MAX) {
+                            gop = dLda * alpha * __builtin_amdgcn_rcpf(raw.w);
+                            const float dLdq = -0.5f * alpha * dLda;
+                            const float dx = fpx - a.x, dy = fpy - a.y;
+                            gA = dLdq * dx * dx;
+                            gB = dLdq * 2.0f * dx * dy;
+                            gC = dLdq * dy * dy;
+                            gmx = -2.0f * dLdq * (raw.x * dx + raw.y * dy);
+                            gmy = -2.0f * dLdq * (raw.y * dx + raw.z * dy);
+                        }
+                    }
+                }
+                if (ballot64(contrib) != 0) {
+                    gmx = wave_total_63(gmx);
+                    gmy = wave_total_63(gmy);
+                    gA = wave_total_63(gA);
+                    gB = wave_total_63(gB);
+                    gC = wave_total_63(gC);
+                    gop = wave_total_63(gop);
+                    gr = wave_total_63(gr);
+                    gg = wave_total_63(gg);
+                    gb = wave_total_63(gb);
+                    if (lane == 63) {
+                        const int q = (int)(ppos - (uint32_t)p0);
+                        atomicAdd(&s_grad[0][q], gmx);
+                        atomicAdd(&s_grad[1][q], gmy);
+                        atomicAdd(&s_grad[2][q], gA);
+                        atomicAdd(&s_grad[3][q], gB);
+                        atomicAdd(&s_grad[4][q], gC);
+                        atomicAdd(&s_grad[5][q], gop);
+                        atomicAdd(&s_grad[6][q], gr);
+                        atomicAdd(&s_grad[7][q], gg);
+                        atomicAdd(&s_grad[8][q], gb);
                     }
                 }
             }
-            if (ballot64(contrib) != 0) {
-                gmx = wave_sum(gmx);
-                gmy = wave_sum(gmy);
-                gA = wave_sum(gA);
-                gB = wave_sum(gB);
-                gC = wave_sum(gC);
-                gop = wave_sum(gop);
-                gr = wave_sum(gr);
-                gg = wave_sum(gg);
-                gb = wave_sum(gb);
-                if (lane == 0) {
-                    float *gp = reinterpret_cast<float *>(grads + vbase + __float_as_uint(s_rec[wave][j].c.w));
-                    atomicAdd(gp + 0, gmx);
-                    atomicAdd(gp + 1, gmy);
-                    atomicAdd(gp + 2, gA);
-                    atomicAdd(gp + 3, gB);
-                    atomicAdd(gp + 4, gC);
-                    atomicAdd(gp + 5, gop);
-                    atomicAdd(gp + 6, gr);
-                    atomicAdd(gp + 7, gg);
-                    atomicAdd(gp + 8, gb);
-                }
+        }
+        __syncthreads();
+        // the tile's sums of this chunk leave with one atomic per quantity
+        for (int q = threadIdx.x; q < NG * 64; q += T * T) {
+            const int k = q >> 6, jj = q & 63;
+            const float v = s_grad[k][jj];
+            if (v != 0.f) {
+                atomicAdd(reinterpret_cast<float *>(grads + vbase + s_id[jj]) + k, v);
+                s_grad[k][jj] = 0.f;
             }
         }
-        wave_lds_sync();
+        __syncthreads();
     }
 }
 
