@@ -219,7 +219,7 @@ def fwd_bwd_rate(g, wl, steps, warmup, tile=16):
     return dict(it_s=1.0 / dt, ms=dt * 1e3)
 
 
-def batched_vs_plain(g, steps=3, log=None):
+def batched_vs_plain(g, steps=3, log=None, fixed=None, plain_too=True):
     """3M Gaussians, 32 orbit views at mixed resolutions (forward + L1 loss +
     backward) plus the foveated forward of two eyes, as one step.  Batched:
     the autotuned schedule replayed from a recorded graph.  Plain: one view
@@ -243,7 +243,11 @@ def batched_vs_plain(g, steps=3, log=None):
     px = sum(c.width * c.height for c in cams) + sum(c.width * c.height for c in eyes)
     if log:
         log(f"batched: autotuning ({len(cams)} views + {len(eyes)} eyes, {px / 1e6:.1f} Mpix) ...")
-    best, tried = autotune.tune(S, cams, target, eyes, fov, reps=2, log=log)
+    if fixed:
+        best, tried = dict(fixed), []
+        g.gs_set_tuning("radix_part", best["radix_part"])
+    else:
+        best, tried = autotune.tune(S, cams, target, eyes, fov, reps=2, log=log)
     step = BatchedStep(S, cams, target, best["tile"], best["batch_views"], eyes, fov)
     ms_b = autotune.time_step(step, steps)
     keys_b = int(step.num_keys.sum().item())
@@ -251,6 +255,8 @@ def batched_vs_plain(g, steps=3, log=None):
     del step
     torch.cuda.empty_cache()
     g.gs_set_tuning("radix_part", 8192)
+    if not plain_too:
+        return dict(batched_it_s=1e3 / ms_b, batched_ms=ms_b, config=best, keys=keys_b, capacity_ok=bool(ok_b))
     plain = BatchedStep(S, cams, target, 16, 1, eyes, fov, eye_batch=1)
     plain.step()
     torch.cuda.synchronize()
@@ -329,6 +335,11 @@ def main():
     ap.add_argument("--tile", type=int, default=16)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true")
+    ap.add_argument("--batched-only", action="store_true",
+                    help="only the batched step (3M Gaussians, 32 views + 2 eyes) at a fixed schedule: "
+                         "--tile, --batch-views, --radix-part; for profiling")
+    ap.add_argument("--batch-views", type=int, default=32)
+    ap.add_argument("--radix-part", type=int, default=16384)
     ap.add_argument("--copy-probe", action="store_true",
                     help="only run a plain 1 GiB device copy (memory-counter calibration)")
     args = ap.parse_args()
@@ -343,6 +354,12 @@ def main():
         return
     import paper_2407_00435_amd as g
     import scenegen
+
+    if args.batched_only:
+        r = batched_vs_plain(g, args.steps, log, fixed=dict(tile=args.tile, batch_views=args.batch_views,
+                                                             radix_part=args.radix_part), plain_too=False)
+        print(json.dumps(r), flush=True)
+        return
 
     torch.cuda.set_device(0)
     log("generating the 1.5M-Gaussian foveated scene ...")
