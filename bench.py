@@ -132,8 +132,8 @@ class Foveated:
         B._check(L.gs_rasterize_foveated(B._ptr(g.splats), B._ptr(g.lvl), g.n, B._ptr(g.S.t["qbound"]),
                                          g.L, g.C.hp, g.C.dp, g.C.n, g.tile, B._ptr(g.vals),
                                          B._ptr(g.ranges), B._ptr(g.pix_level), B._ptr(g.pix_weight),
-                                         ctypes.cast(g.bg, B._VP), B._ptr(g.image), B._ptr(stats), None,
-                                         0, g.stream))
+                                         ctypes.cast(g.bg, B._VP), B._ptr(g.image), B._ptr(stats), g.ws,
+                                         g.wsn, g.stream))
 
     STAGES = ("fovea", "project", "binsort", "raster")
 
@@ -246,6 +246,7 @@ def batched_vs_plain(g, steps=3, log=None, fixed=None, plain_too=True):
     if fixed:
         best, tried = dict(fixed), []
         g.gs_set_tuning("radix_part", best["radix_part"])
+        g.gs_set_tuning("raster_queue", best.get("raster_queue", 0))
     else:
         best, tried = autotune.tune(S, cams, target, eyes, fov, reps=2, log=log)
     step = BatchedStep(S, cams, target, best["tile"], best["batch_views"], eyes, fov)
@@ -255,6 +256,7 @@ def batched_vs_plain(g, steps=3, log=None, fixed=None, plain_too=True):
     del step
     torch.cuda.empty_cache()
     g.gs_set_tuning("radix_part", 8192)
+    g.gs_set_tuning("raster_queue", 0)
     if not plain_too:
         return dict(batched_it_s=1e3 / ms_b, batched_ms=ms_b, config=best, keys=keys_b, capacity_ok=bool(ok_b))
     plain = BatchedStep(S, cams, target, 16, 1, eyes, fov, eye_batch=1)
@@ -357,7 +359,8 @@ def main():
 
     if args.batched_only:
         r = batched_vs_plain(g, args.steps, log, fixed=dict(tile=args.tile, batch_views=args.batch_views,
-                                                             radix_part=args.radix_part), plain_too=False)
+                                                             radix_part=args.radix_part, raster_queue=0),
+                             plain_too=False)
         print(json.dumps(r), flush=True)
         return
 

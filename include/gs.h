@@ -302,6 +302,21 @@ int gs_graph_destroy(gs_graph *graph);
 
 /* Process-wide tuning knob (not thread-safe against concurrent calls):
  *   "radix_part": keys per sort workgroup, 4096, 8192 (default) or 16384.
+ *   "raster_queue": 0 (default): one workgroup per tile; 1: when the call
+ *                   has a workspace, the forward compositors run as a
+ *                   persistent grid whose workgroups pop tile tasks from a
+ *                   work queue.
+ *   "raster_heavy": with the queue and no split, tiles whose run is longer
+ *                   than this go first (default 0: tile order).
+ *   "raster_grab":  tasks a workgroup takes per pop (1..64, default 1).
+ *   "raster_split": 0 (default) or beta in 256..2^24: with the queue, tile
+ *                   runs longer than beta are cut into chunks of beta
+ *                   entries composited in parallel and merged front to back
+ *                   (chunks whose pixels reach the stop threshold are
+ *                   composited again from the running state, so the result
+ *                   is the sequential one up to float reassociation).
+ * Workspace sizes returned by gs_workspace_bytes / gs_render_workspace_bytes
+ * depend on these settings: size workspaces after setting them.
  * The GS_RADIX_PART environment variable sets the same default. */
 int gs_set_tuning(const char *name, int64_t value);
 

@@ -1,11 +1,13 @@
-"""Autotuner for the batched step: tile size, views per sub-batch and the
-sort's partition size.
+"""Autotuner for the batched step: tile size, views per sub-batch, the
+sort's partition size and the compositor's scheduling (one workgroup per
+tile or the persistent work queue).
 
 Candidates are measured, not modelled: each is built (buffers, a recorded
 graph), replayed a few times on the device, and timed with events on its
 stream.  The search is coordinate descent from (tile 16, all views in one
-sub-batch, partition 8192): first the tile size, then the sub-batch size at
-the best tile, then the partition size.  A candidate that does not fit in
+sub-batch, partition 8192, one workgroup per tile): first the tile size,
+then the sub-batch size at the best tile, then the partition size, then the
+persistent work-queue compositor.  A candidate that does not fit in
 device memory is skipped.  Results can be cached in a JSON file keyed by the
 workload's shape (point count, SH degree, view sizes, device name).
 """
@@ -60,6 +62,7 @@ def tune(scene, cams, target, eyes=None, foveae=None, tiles=(16, 32, 8), reps=3,
             if c == cfg:
                 return ms
         B.gs_set_tuning("radix_part", cfg["radix_part"])
+        B.gs_set_tuning("raster_queue", cfg["raster_queue"])
         step = None
         try:
             step = BatchedStep(scene, cams, target, cfg["tile"], cfg["batch_views"], eyes, foveae)
@@ -78,7 +81,7 @@ def tune(scene, cams, target, eyes=None, foveae=None, tiles=(16, 32, 8), reps=3,
             log(f"  {cfg}: {ms:.3f} ms")
         return ms
 
-    best = dict(tile=16, batch_views=V, radix_part=8192)
+    best = dict(tile=16, batch_views=V, radix_part=8192, raster_queue=0)
     best_ms = measure(best)
     for t in tiles:
         c = dict(best, tile=t)
@@ -90,11 +93,13 @@ def tune(scene, cams, target, eyes=None, foveae=None, tiles=(16, 32, 8), reps=3,
         ms = measure(c)
         if ms < best_ms:
             best, best_ms = c, ms
-    c = dict(best, radix_part=16384)
-    ms = measure(c)
-    if ms < best_ms:
-        best, best_ms = c, ms
+    for key, alt in (("radix_part", 16384), ("raster_queue", 1)):
+        c = dict(best, **{key: alt})
+        ms = measure(c)
+        if ms < best_ms:
+            best, best_ms = c, ms
     B.gs_set_tuning("radix_part", best["radix_part"])
+    B.gs_set_tuning("raster_queue", best["raster_queue"])
     best = dict(best, ms=best_ms)
     if cache_path:
         cache = {}

@@ -271,7 +271,10 @@ def gs_bin_sort(splats: torch.Tensor, n: int, cams: Cameras, tile_size: int = 16
 
 
 def gs_rasterize_fwd(splats, n, cams: Cameras, tile_size, vals, ranges, bg=(0.0, 0.0, 0.0),
-                     want_dominated: bool = False, stats=None):
+                     want_dominated: bool = False, stats=None, workspace=None):
+    """Forward compositing.  With ``workspace`` (a tuple from ``_ws``) the
+    library runs its persistent work-queue compositor; without, one
+    workgroup per tile."""
     dev = splats.device
     _, n_px = cams.tiles(tile_size)
     image = torch.empty(3 * n_px, dtype=torch.float32, device=dev)
@@ -279,9 +282,10 @@ def gs_rasterize_fwd(splats, n, cams: Cameras, tile_size, vals, ranges, bg=(0.0,
     n_contrib = torch.empty(n_px, dtype=torch.int32, device=dev)
     dom = torch.empty((cams.n, n), dtype=torch.int32, device=dev) if want_dominated else None
     bgc = (ctypes.c_float * 3)(*bg)
+    ws, wsn = (workspace[1], workspace[2]) if workspace is not None else (None, 0)
     _check(lib().gs_rasterize_fwd(_ptr(splats), n, cams.hp, cams.dp, cams.n, tile_size, _ptr(vals),
                                   _ptr(ranges), ctypes.cast(bgc, _VP), _ptr(image), _ptr(final_T),
-                                  _ptr(n_contrib), _ptr(dom), _ptr(stats), None, 0, _stream()))
+                                  _ptr(n_contrib), _ptr(dom), _ptr(stats), ws, wsn, _stream()))
     return dict(image=image, final_T=final_T, n_contrib=n_contrib, dominated=dom)
 
 
@@ -388,15 +392,17 @@ def gs_fovea_prep(cams: Cameras, foveae, tile_size: int = 16, n_levels: int = 4)
 
 
 def gs_rasterize_foveated(splats, lvl_rgba, n, qbound, n_levels, cams: Cameras, tile_size, vals,
-                          ranges, pix_level, pix_weight, bg=(0.0, 0.0, 0.0), stats=None, image=None):
+                          ranges, pix_level, pix_weight, bg=(0.0, 0.0, 0.0), stats=None, image=None,
+                          workspace=None):
     _, n_px = cams.tiles(tile_size)
     if image is None:
         image = torch.empty(3 * n_px, dtype=torch.float32, device=splats.device)
     bgc = (ctypes.c_float * 3)(*bg)
+    ws, wsn = (workspace[1], workspace[2]) if workspace is not None else (None, 0)
     _check(lib().gs_rasterize_foveated(_ptr(splats), _ptr(lvl_rgba), n, _ptr(qbound), n_levels, cams.hp,
                                        cams.dp, cams.n, tile_size, _ptr(vals), _ptr(ranges),
                                        _ptr(pix_level), _ptr(pix_weight), ctypes.cast(bgc, _VP),
-                                       _ptr(image), _ptr(stats), None, 0, _stream()))
+                                       _ptr(image), _ptr(stats), ws, wsn, _stream()))
     return image
 
 

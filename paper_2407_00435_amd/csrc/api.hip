@@ -155,6 +155,62 @@ void carve_render(Carve &c, int64_t E, int L, uint64_t cap, int64_t tiles, int64
     rb.tile_level = L > 0 ? c.take<uint8_t>(2 * tiles) : nullptr;
 }
 
+// Compositing work queue (see raster.hip): off by default -- on MI355X the
+// hardware dispatcher, one workgroup per tile in tile order, measured faster
+// than the persistent queue on the foveated stereo frame (0.63-0.67 ms
+// against 0.79 ms) -- and, when on, no split by default (tiles with the
+// longest runs saturate within their first chunks, so splitting composites
+// chunks that are then discarded).
+int g_raster_queue = 0;
+uint32_t g_raster_beta = 0;
+uint32_t g_raster_heavy = 0;
+uint32_t g_raster_grab = 1;
+
+// chunk partial per task: T*T pixels x 3 float4
+size_t queue_task_bytes(int T) { return 8 + 4 + (g_raster_beta ? (size_t)T * T * 48 : 0); }
+
+size_t queue_fixed_bytes(int64_t tiles) { return 256 + 8 * (size_t)tiles + 4 * 256; }
+
+// Workspace for the queue of a compositing call over `tiles` tiles and at
+// most `cap` keys (0 when the queue is switched off).
+size_t raster_queue_bytes(int64_t tiles, int T, uint64_t cap)
+{
+    if (!g_raster_queue) return 0;
+    return queue_fixed_bytes(tiles) + raster_queue_heavy_cap(tiles, T, cap, g_raster_beta) * queue_task_bytes(T);
+}
+
+// Lays the queue out in [base, base + bytes); the heavy-task capacity is what
+// fits (tiles that do not fit are queued unsplit).  False if the queue is off
+// or the space does not hold the fixed part.
+bool carve_queue(char *base, size_t bytes, int64_t tiles, int T, RasterQueueArgs &q)
+{
+    if (!g_raster_queue || !base) return false;
+    const size_t fixed = queue_fixed_bytes(tiles);
+    if (bytes < fixed) return false;
+    const size_t per = queue_task_bytes(T);
+    uint64_t hc = (bytes - fixed) / per;
+    if (hc > (1u << 30)) hc = 1u << 30;
+    for (;;) {
+        Carve c;
+        c.base = base;
+        q.counts = c.take<uint32_t>(16);
+        q.light = c.take<uint32_t>(8 * tiles);
+        q.heavy = c.take<uint32_t>(8 * hc);
+        q.merge_cnt = c.take<uint32_t>(4 * hc);
+        q.part = g_raster_beta ? c.take<float>((size_t)T * T * 48 * hc) : nullptr;
+        if (c.off <= bytes || hc == 0) break;
+        // alignment padding ate into the heavy part: shrink it
+        const uint64_t over = (c.off - bytes + per - 1) / per;
+        hc = hc > over ? hc - over : 0;
+    }
+    q.heavy_cap = (uint32_t)hc;
+    q.light_cap = (uint32_t)tiles;
+    q.beta = g_raster_beta;
+    q.heavy_min = g_raster_heavy;
+    q.grab = g_raster_grab;
+    return true;
+}
+
 size_t bin_bytes(int V_, int64_t E, uint64_t cap, int64_t tiles)
 {
     Carve c;
@@ -192,7 +248,8 @@ size_t gs_workspace_bytes(const gs_camera *cams_host, int n_views, int32_t n, in
 {
     int64_t tiles = 0;
     if (check_cams(cams_host, cams_host, n_views, tile_size, &tiles, nullptr)) return 0;
-    return bin_bytes(n_views, (int64_t)n_views * (n > 0 ? n : 0), key_capacity, tiles);
+    return bin_bytes(n_views, (int64_t)n_views * (n > 0 ? n : 0), key_capacity, tiles) + 256 +
+           raster_queue_bytes(tiles, tile_size, key_capacity);
 }
 
 size_t gs_render_workspace_bytes(const gs_camera *cams_host, int n_views, int32_t n, int n_levels,
@@ -206,7 +263,7 @@ size_t gs_render_workspace_bytes(const gs_camera *cams_host, int n_views, int32_
     RenderBufs rb;
     carve_render(c, E, n_levels, key_capacity, tiles, pixels, rb);
     carve_bin(c, n_views, E, key_capacity, tiles, bs);
-    return c.off + 256;
+    return c.off + 512 + raster_queue_bytes(tiles, tile_size, key_capacity);
 }
 
 int gs_project(const gs_scene *scene, const gs_camera *cams_host, const gs_camera *cams_dev,
@@ -265,8 +322,6 @@ int gs_rasterize_fwd(const gs_splat *splats, int32_t n, const gs_camera *cams_ho
                      uint32_t *n_contrib, uint32_t *dominated_px, uint64_t *stats,
                      void *workspace, size_t workspace_bytes, void *stream)
 {
-    (void)workspace;
-    (void)workspace_bytes;
     int r;
     int64_t tiles = 0;
     if ((r = check_cams(cams_host, cams_dev, n_views, tile_size, &tiles, nullptr))) return r;
@@ -274,10 +329,13 @@ int gs_rasterize_fwd(const gs_splat *splats, int32_t n, const gs_camera *cams_ho
     if (!tile_ranges || !image || !final_T || !n_contrib || (n > 0 && (!splats || !vals)))
         return fail(GS_ERR_INVALID, "NULL output or input pointer");
     if (!aligned(splats, 16)) return fail(GS_ERR_INVALID, "splats must be 16-byte aligned");
+    if (workspace && !aligned(workspace, 256)) return fail(GS_ERR_INVALID, "workspace must be 256-byte aligned");
+    RasterQueueArgs q;
+    const bool queued = carve_queue((char *)workspace, workspace_bytes, tiles, tile_size, q);
     const float zero[3] = {0.f, 0.f, 0.f};
     hipError_t e = launch_raster_fwd(splats, n, cams_dev, n_views, tile_size, tiles, vals, tile_ranges,
                                      bg ? bg : zero, image, final_T, n_contrib, dominated_px, stats,
-                                     (hipStream_t)stream);
+                                     queued ? &q : nullptr, (hipStream_t)stream);
     if (e != hipSuccess) return hip_fail(e, "gs_rasterize_fwd");
     return ok();
 }
@@ -362,8 +420,6 @@ int gs_rasterize_foveated(const gs_splat *splats, const float *lvl_rgba, int32_t
                           const float *pix_weight, const float *bg, float *image, uint64_t *stats,
                           void *workspace, size_t workspace_bytes, void *stream)
 {
-    (void)workspace;
-    (void)workspace_bytes;
     int r;
     int64_t tiles = 0;
     if ((r = check_cams(cams_host, cams_dev, n_eyes, tile_size, &tiles, nullptr))) return r;
@@ -374,10 +430,13 @@ int gs_rasterize_foveated(const gs_splat *splats, const float *lvl_rgba, int32_t
         return fail(GS_ERR_INVALID, "NULL output or input pointer");
     if (!aligned(splats, 16) || !aligned(lvl_rgba, 16))
         return fail(GS_ERR_INVALID, "splats and lvl_rgba must be 16-byte aligned");
+    if (workspace && !aligned(workspace, 256)) return fail(GS_ERR_INVALID, "workspace must be 256-byte aligned");
+    RasterQueueArgs q;
+    const bool queued = carve_queue((char *)workspace, workspace_bytes, tiles, tile_size, q);
     const float zero[3] = {0.f, 0.f, 0.f};
     hipError_t e = launch_raster_fov(splats, lvl_rgba, n, qbound, n_levels, cams_dev, n_eyes, tile_size,
                                      tiles, vals, tile_ranges, pix_level, pix_weight, bg ? bg : zero,
-                                     image, stats, (hipStream_t)stream);
+                                     image, stats, queued ? &q : nullptr, (hipStream_t)stream);
     if (e != hipSuccess) return hip_fail(e, "gs_rasterize_foveated");
     return ok();
 }
@@ -403,6 +462,7 @@ int gs_render_foveated(const gs_scene *scene, const gs_camera *cams_host, const 
     c.base = (char *)workspace;
     RenderBufs rb;
     carve_render(c, E, L, key_capacity, tiles, pixels, rb);
+    const size_t scratch_off = (c.off + 255) & ~size_t(255);  // binning scratch, then the compositing queue
     BinScratch bs;
     carve_bin(c, n_eyes, E, key_capacity, tiles, bs);
     if ((r = gs_fovea_prep(cams_host, cams_dev, fov_host, n_eyes, tile_size, L, rb.pix_level,
@@ -418,9 +478,12 @@ int gs_render_foveated(const gs_scene *scene, const gs_camera *cams_host, const 
                         num_keys, bs, st);
     if (e != hipSuccess) return hip_fail(e, "gs_render_foveated (binning)");
     const float zero[3] = {0.f, 0.f, 0.f};
+    RasterQueueArgs q;
+    const bool queued = carve_queue((char *)workspace + scratch_off, workspace_bytes - scratch_off, tiles,
+                                    tile_size, q);
     e = launch_raster_fov(rb.splats, rb.lvl, scene->n, scene->qbound, L, cams_dev, n_eyes, tile_size,
                           tiles, rb.vals, rb.ranges, rb.pix_level, rb.pix_weight, bg ? bg : zero, image,
-                          nullptr, st);
+                          nullptr, queued ? &q : nullptr, st);
     if (e != hipSuccess) return hip_fail(e, "gs_render_foveated (compositing)");
     return ok();
 }
@@ -520,6 +583,27 @@ int gs_set_tuning(const char *name, int64_t value)
 {
     if (!name) return fail(GS_ERR_INVALID, "tuning name is NULL");
     std::string k(name);
+    if (k == "raster_queue") {
+        if (value != 0 && value != 1) return fail(GS_ERR_INVALID, "raster_queue must be 0 or 1");
+        g_raster_queue = (int)value;
+        return ok();
+    }
+    if (k == "raster_grab") {
+        if (value < 1 || value > 64) return fail(GS_ERR_INVALID, "raster_grab must be in 1..64");
+        g_raster_grab = (uint32_t)value;
+        return ok();
+    }
+    if (k == "raster_heavy") {
+        if (value < 0 || value > (1ll << 31)) return fail(GS_ERR_INVALID, "raster_heavy must be in 0..2^31");
+        g_raster_heavy = (uint32_t)value;
+        return ok();
+    }
+    if (k == "raster_split") {
+        if (value != 0 && (value < 256 || value > (1 << 24)))
+            return fail(GS_ERR_INVALID, "raster_split must be 0 or in 256..2^24");
+        g_raster_beta = (uint32_t)value;
+        return ok();
+    }
     if (k == "radix_part") {
         if (!radix_set_part((int)value))
             return fail(GS_ERR_INVALID, "radix_part must be 4096, 8192 or 16384");

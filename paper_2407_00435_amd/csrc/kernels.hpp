@@ -73,10 +73,23 @@ hipError_t launch_bin_sort(const gs_splat *splats, int n, const gs_camera *cams_
                            const BinScratch &bs, hipStream_t st);
 
 // compositing
+// Work-queue scratch of the persistent compositors (carved from a workspace).
+struct RasterQueueArgs {
+    uint32_t *counts;     // [4]
+    uint32_t *heavy;      // [heavy_cap][2]
+    uint32_t *light;      // [light_cap][2]
+    uint32_t *merge_cnt;  // [heavy_cap]
+    float *part;          // [heavy_cap][64][12] when beta > 0
+    uint32_t heavy_cap, light_cap;
+    uint32_t beta;
+    uint32_t heavy_min;  // without splitting, runs longer than this go first (0: tile order)
+    uint32_t grab;       // consecutive tasks a workgroup takes per pop
+};
+uint64_t raster_queue_heavy_cap(int64_t n_tiles, int T, uint64_t cap, uint32_t beta);
 hipError_t launch_raster_fwd(const gs_splat *splats, int n, const gs_camera *cams_dev, int V, int T,
                              int64_t n_tiles, const uint32_t *vals, const uint32_t *ranges,
                              const float bg[3], float *image, float *final_T, uint32_t *n_contrib,
-                             uint32_t *dominated, uint64_t *stats, hipStream_t st);
+                             uint32_t *dominated, uint64_t *stats, const RasterQueueArgs *qa, hipStream_t st);
 hipError_t launch_raster_bwd(const gs_splat *splats, int n, const gs_camera *cams_dev, int V, int T,
                              int64_t n_tiles, const uint32_t *vals, const uint32_t *ranges,
                              const float bg[3], const float *final_T, const uint32_t *n_contrib,
@@ -88,7 +101,7 @@ hipError_t launch_raster_fov(const gs_splat *splats, const float *lvl_rgba, int 
                              const uint8_t *qbound, int n_levels, const gs_camera *cams_dev, int V,
                              int T, int64_t n_tiles, const uint32_t *vals, const uint32_t *ranges,
                              const uint8_t *pix_level, const float *pix_weight, const float bg[3],
-                             float *image, uint64_t *stats, hipStream_t st);
+                             float *image, uint64_t *stats, const RasterQueueArgs *qa, hipStream_t st);
 
 // utilities
 hipError_t launch_fill_u32(uint32_t *p, uint32_t value, uint64_t count, hipStream_t st);

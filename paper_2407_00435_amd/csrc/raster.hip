@@ -115,6 +115,136 @@ __device__ __forceinline__ void stats_add(unsigned long long *stats, float blend
     }
 }
 
+// Where a wave works: its 8x8 sub-block of a tile, its pixel, and the
+// sub-block rectangle clipped to the image (for the footprint cull).
+struct WaveCtx {
+    ViewInfo vi;
+    int px, py;
+    bool inside;
+    float fpx, fpy, rx0, rx1, ry0, ry1;
+    uint32_t start, end;  // the tile's run in the sorted list
+    int64_t pix;
+};
+
+template <int T>
+__device__ __forceinline__ WaveCtx wave_ctx(const gs_camera *__restrict__ cams, int V, int64_t gtile, int sub,
+                                            int lane, const uint32_t *__restrict__ ranges)
+{
+    constexpr int SUB = T / 8;
+    WaveCtx w;
+    w.vi = view_of_tile(cams, V, T, gtile);
+    const int64_t lt = gtile - w.vi.tile_off;
+    const int tx = (int)(lt % w.vi.tiles_x), ty = (int)(lt / w.vi.tiles_x);
+    const int sx0 = tx * T + (sub % SUB) * 8, sy0 = ty * T + (sub / SUB) * 8;
+    w.px = sx0 + (lane & 7);
+    w.py = sy0 + (lane >> 3);
+    w.inside = w.px < w.vi.W && w.py < w.vi.H;
+    w.fpx = (float)w.px;
+    w.fpy = (float)w.py;
+    w.rx0 = (float)sx0;
+    w.ry0 = (float)sy0;
+    w.rx1 = (float)min(sx0 + 7, w.vi.W - 1);
+    w.ry1 = (float)min(sy0 + 7, w.vi.H - 1);
+    w.start = ranges[2 * gtile];
+    w.end = ranges[2 * gtile + 1];
+    w.pix = w.vi.pix_off + (int64_t)w.py * w.vi.W + w.px;
+    return w;
+}
+
+// Per-pixel state of the plain compositor.
+struct FwdState {
+    float Tr, C0, C1, C2, best;
+    uint32_t last;
+    int best_id;
+    bool done;
+};
+
+__device__ __forceinline__ FwdState fwd_init(bool inside)
+{
+    FwdState s;
+    s.Tr = 1.0f;
+    s.C0 = s.C1 = s.C2 = 0.0f;
+    s.best = 0.0f;
+    s.last = 0;
+    s.best_id = -1;
+    s.done = !inside;
+    return s;
+}
+
+// Front-to-back over list positions [b, e) of the tile (absolute indices into
+// vals): 64 entries at a time are gathered, culled against the sub-block and
+// compacted into the wave's LDS slice, then composited.
+template <bool DOM, bool STATS>
+__device__ __forceinline__ void fwd_walk(const gs_splat *__restrict__ vsp, const uint32_t *__restrict__ vals,
+                                         const WaveCtx &w, uint32_t b, uint32_t e, FwdRec *__restrict__ srec,
+                                         FwdState &s, float *st)
+{
+    const int lane = __lane_id();
+    for (uint32_t c0 = b; c0 < e; c0 += 64) {
+        if (ballot64(!s.done) == 0) break;
+        const uint32_t idx = c0 + lane;
+        bool keep = false;
+        // the record is fully defined on every lane before the cull decision
+        FwdRec rec = zero_rec();
+        if (idx < e) {
+            const uint32_t id = vals[idx];
+            const float4 *s4 = reinterpret_cast<const float4 *>(vsp + id);
+            const float4 s0 = s4[0], s1 = s4[1], s2 = s4[2];
+            rec = make_rec(s0, s1, s2, idx - w.start + 1, id);
+            keep = reaches_rect(s0.x, s0.y, s0.z, s0.w, s1.x, qmax_of(s1.y), w.rx0, w.rx1, w.ry0, w.ry1);
+        }
+        const uint64_t m = ballot64(keep);
+        if (keep) srec[__popcll(m & lanemask_lt())] = rec;
+        wave_lds_sync();
+        const int cnt = __popcll(m);
+        if (STATS) {
+            st[2] += (float)min(64u, e - c0);
+            st[3] += (float)cnt;
+        }
+        for (int j = 0; j < cnt; ++j) {
+            // branch-free: every lane evaluates, selects take the decisions
+            const float4 a = srec[j].a, bb = srec[j].b, c = srec[j].c;
+            if (STATS) st[1] += s.done ? 0.0f : 1.0f;
+            const float e2 = pair_e2(a, bb, w.fpx, w.fpy);
+            const float alpha = fminf(GS_ALPHA_MAX, fast_exp2(e2));
+            const bool use = !s.done && e2 >= bb.z;
+            const float Tn = fmaf(-alpha, s.Tr, s.Tr);
+            const bool stop = use && Tn < GS_T_STOP;
+            const bool blend = use && !stop;
+            const float wt = blend ? alpha * s.Tr : 0.0f;
+            s.C0 = fmaf(wt, c.x, s.C0);
+            s.C1 = fmaf(wt, c.y, s.C1);
+            s.C2 = fmaf(wt, c.z, s.C2);
+            s.Tr = blend ? Tn : s.Tr;
+            s.last = blend ? __float_as_uint(bb.w) : s.last;
+            s.done = s.done || stop;
+            if (STATS) st[0] += blend ? 1.0f : 0.0f;
+            if (DOM && blend && wt > s.best) {
+                s.best = wt;
+                s.best_id = (int)__float_as_uint(c.w);
+            }
+            if ((j & 7) == 7 && ballot64(!s.done) == 0) break;
+        }
+        wave_lds_sync();
+    }
+}
+
+template <bool DOM>
+__device__ __forceinline__ void fwd_finish(const WaveCtx &w, const FwdState &s, int n, float bg0, float bg1,
+                                           float bg2, float *__restrict__ image, float *__restrict__ final_T,
+                                           uint32_t *__restrict__ n_contrib, uint32_t *__restrict__ dominated)
+{
+    if (!w.inside) return;
+    const int64_t plane = (int64_t)w.vi.W * w.vi.H;
+    float *img = image + 3 * w.vi.pix_off + (int64_t)w.py * w.vi.W + w.px;
+    img[0] = fmaf(s.Tr, bg0, s.C0);
+    img[plane] = fmaf(s.Tr, bg1, s.C1);
+    img[2 * plane] = fmaf(s.Tr, bg2, s.C2);
+    final_T[w.pix] = s.Tr;
+    n_contrib[w.pix] = s.last;
+    if (DOM && s.best_id >= 0) atomicAdd(dominated + (int64_t)w.vi.v * n + s.best_id, 1u);
+}
+
 template <int T, bool DOM, bool STATS>
 __global__ void __launch_bounds__(T *T)
 k_raster_fwd(const gs_splat *__restrict__ splats, int n, const gs_camera *__restrict__ cams, int V,
@@ -123,90 +253,15 @@ k_raster_fwd(const gs_splat *__restrict__ splats, int n, const gs_camera *__rest
              uint32_t *__restrict__ n_contrib, uint32_t *__restrict__ dominated,
              unsigned long long *__restrict__ stats)
 {
-    float st_blend = 0.f, st_eval = 0.f, st_staged = 0.f, st_kept = 0.f;
+    float st[4] = {0.f, 0.f, 0.f, 0.f};
     constexpr int WAVES = T * T / 64;
-    constexpr int SUB = T / 8;
     __shared__ FwdRec s_rec[WAVES][64];
-    const int64_t gtile = blockIdx.x;
-    const ViewInfo vi = view_of_tile(cams, V, T, gtile);
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const int64_t lt = gtile - vi.tile_off;
-    const int tx = (int)(lt % vi.tiles_x), ty = (int)(lt / vi.tiles_x);
-    const int sx0 = tx * T + (wave % SUB) * 8, sy0 = ty * T + (wave / SUB) * 8;
-    const int px = sx0 + (lane & 7), py = sy0 + (lane >> 3);
-    const bool inside = px < vi.W && py < vi.H;
-    const float fpx = (float)px, fpy = (float)py;
-    // the sub-block clipped to the image (empty sub-blocks skip all work)
-    const float rx0 = (float)sx0, ry0 = (float)sy0;
-    const float rx1 = (float)min(sx0 + 7, vi.W - 1), ry1 = (float)min(sy0 + 7, vi.H - 1);
-    const uint32_t start = ranges[2 * gtile], end = ranges[2 * gtile + 1];
-    const gs_splat *__restrict__ vsp = splats + (int64_t)vi.v * n;
-
-    float Tr = 1.0f, C0 = 0.f, C1 = 0.f, C2 = 0.f;
-    uint32_t last = 0;
-    float best = 0.0f;
-    int best_id = -1;
-    bool done = !inside;
-
-    for (uint32_t c0 = start; c0 < end; c0 += 64) {
-        if (ballot64(!done) == 0) break;
-        const uint32_t idx = c0 + lane;
-        bool keep = false;
-        // the record is fully defined on every lane before the cull decision
-        FwdRec rec = zero_rec();
-        if (idx < end) {
-            const uint32_t id = vals[idx];
-            const float4 *s4 = reinterpret_cast<const float4 *>(vsp + id);
-            const float4 s0 = s4[0], s1 = s4[1], s2 = s4[2];
-            rec = make_rec(s0, s1, s2, idx - start + 1, id);
-            keep = reaches_rect(s0.x, s0.y, s0.z, s0.w, s1.x, qmax_of(s1.y), rx0, rx1, ry0, ry1);
-        }
-        const uint64_t m = ballot64(keep);
-        if (keep) s_rec[wave][__popcll(m & lanemask_lt())] = rec;
-        wave_lds_sync();
-        const int cnt = __popcll(m);
-        if (STATS) {
-            st_staged += (float)min(64u, end - c0);
-            st_kept += (float)cnt;
-        }
-        for (int j = 0; j < cnt; ++j) {
-            // branch-free: every lane evaluates, selects take the decisions
-            const float4 a = s_rec[wave][j].a, b = s_rec[wave][j].b, c = s_rec[wave][j].c;
-            if (STATS) st_eval += done ? 0.0f : 1.0f;
-            const float e2 = pair_e2(a, b, fpx, fpy);
-            const float alpha = fminf(GS_ALPHA_MAX, fast_exp2(e2));
-            const bool use = !done && e2 >= b.z;
-            const float Tn = fmaf(-alpha, Tr, Tr);
-            const bool stop = use && Tn < GS_T_STOP;
-            const bool blend = use && !stop;
-            const float w = blend ? alpha * Tr : 0.0f;
-            C0 = fmaf(w, c.x, C0);
-            C1 = fmaf(w, c.y, C1);
-            C2 = fmaf(w, c.z, C2);
-            Tr = blend ? Tn : Tr;
-            last = blend ? __float_as_uint(b.w) : last;
-            done = done || stop;
-            if (STATS) st_blend += blend ? 1.0f : 0.0f;
-            if (DOM && blend && w > best) {
-                best = w;
-                best_id = (int)__float_as_uint(c.w);
-            }
-            if ((j & 7) == 7 && ballot64(!done) == 0) break;
-        }
-        wave_lds_sync();
-    }
-    if (inside) {
-        const int64_t pix = vi.pix_off + (int64_t)py * vi.W + px;
-        const int64_t plane = (int64_t)vi.W * vi.H;
-        float *img = image + 3 * vi.pix_off + (int64_t)py * vi.W + px;
-        img[0] = fmaf(Tr, bg0, C0);
-        img[plane] = fmaf(Tr, bg1, C1);
-        img[2 * plane] = fmaf(Tr, bg2, C2);
-        final_T[pix] = Tr;
-        n_contrib[pix] = last;
-        if (DOM && best_id >= 0) atomicAdd(dominated + (int64_t)vi.v * n + best_id, 1u);
-    }
-    if (STATS) stats_add(stats, st_blend, st_eval, st_staged, st_kept);
+    const WaveCtx w = wave_ctx<T>(cams, V, blockIdx.x, wave, lane, ranges);
+    FwdState s = fwd_init(w.inside);
+    fwd_walk<DOM, STATS>(splats + (int64_t)w.vi.v * n, vals, w, w.start, w.end, s_rec[wave], s, st);
+    fwd_finish<DOM>(w, s, n, bg0, bg1, bg2, image, final_T, n_contrib, dominated);
+    if (STATS) stats_add(stats, st[0], st[1], st[2], st[3]);
 }
 
 // ---------------------------------------------------------------------------
@@ -221,51 +276,58 @@ struct FovRec {
     float4 lv[MAXL];
 };
 
-template <int T, bool STATS>
-__global__ void __launch_bounds__(T *T)
-k_raster_fov(const gs_splat *__restrict__ splats, const float4 *__restrict__ lvl, int n,
-             const uint8_t *__restrict__ qbound, int L, const gs_camera *__restrict__ cams, int V,
-             const uint32_t *__restrict__ vals, const uint32_t *__restrict__ ranges,
-             const uint8_t *__restrict__ pix_level, const float *__restrict__ pix_weight, float bg0,
-             float bg1, float bg2, float *__restrict__ image, unsigned long long *__restrict__ stats)
+struct FovPix {
+    int lo;          // lower level of the pixel
+    float wup;       // weight of level lo + 1
+    bool two;        // the pixel blends two levels
+    int wave_lo;     // lowest level any pixel of the wave needs
+    bool any_two;    // some pixel of the wave blends two levels
+};
+
+__device__ __forceinline__ FovPix fov_pix(const WaveCtx &w, const uint8_t *__restrict__ pix_level,
+                                          const float *__restrict__ pix_weight)
 {
-    float st_blend = 0.f, st_eval = 0.f, st_staged = 0.f, st_kept = 0.f;
-    constexpr int WAVES = T * T / 64;
-    constexpr int SUB = T / 8;
-    __shared__ FovRec s_rec[WAVES][64];
-    const int64_t gtile = blockIdx.x;
-    const ViewInfo vi = view_of_tile(cams, V, T, gtile);
-    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const int64_t lt = gtile - vi.tile_off;
-    const int tx = (int)(lt % vi.tiles_x), ty = (int)(lt / vi.tiles_x);
-    const int sx0 = tx * T + (wave % SUB) * 8, sy0 = ty * T + (wave / SUB) * 8;
-    const int px = sx0 + (lane & 7), py = sy0 + (lane >> 3);
-    const bool inside = px < vi.W && py < vi.H;
-    const float fpx = (float)px, fpy = (float)py;
-    const float rx0 = (float)sx0, ry0 = (float)sy0;
-    const float rx1 = (float)min(sx0 + 7, vi.W - 1), ry1 = (float)min(sy0 + 7, vi.H - 1);
-    const uint32_t start = ranges[2 * gtile], end = ranges[2 * gtile + 1];
-    const int64_t pix = vi.pix_off + (int64_t)py * vi.W + px;
-
-    int lo = 1;
-    float wup = 0.0f;
-    if (inside) {
-        lo = pix_level[pix];
-        wup = pix_weight[pix];
+    FovPix f;
+    f.lo = 1;
+    f.wup = 0.0f;
+    if (w.inside) {
+        f.lo = pix_level[w.pix];
+        f.wup = pix_weight[w.pix];
     }
-    const bool two = wup > 0.0f;
-    // lowest level any pixel of the wave needs: splats bounded below it are skipped
-    int wave_lo = inside ? lo : 255;
-    for (int off = 32; off > 0; off >>= 1) wave_lo = min(wave_lo, __shfl_xor(wave_lo, off));
-    const bool any_two = ballot64(two) != 0;
+    f.two = f.wup > 0.0f;
+    int wl = w.inside ? f.lo : 255;
+    for (int off = 32; off > 0; off >>= 1) wl = min(wl, __shfl_xor(wl, off));
+    f.wave_lo = wl;
+    f.any_two = ballot64(f.two) != 0;
+    return f;
+}
 
-    float Ta = 1.f, A0 = 0.f, A1 = 0.f, A2 = 0.f;
-    float Tb = 1.f, B0 = 0.f, B1 = 0.f, B2 = 0.f;
-    bool done_a = !inside, done_b = !inside || !two;
-    const int64_t vbase = (int64_t)vi.v * n;
+struct FovState {
+    float Ta, A0, A1, A2, Tb, B0, B1, B2;
+    bool done_a, done_b;
+};
 
-    for (uint32_t c0 = start; c0 < end; c0 += 64) {
-        if (ballot64(!(done_a && done_b)) == 0) break;
+__device__ __forceinline__ FovState fov_init(bool inside, bool two)
+{
+    FovState s;
+    s.Ta = s.Tb = 1.0f;
+    s.A0 = s.A1 = s.A2 = s.B0 = s.B1 = s.B2 = 0.0f;
+    s.done_a = !inside;
+    s.done_b = !inside || !two;
+    return s;
+}
+
+template <bool STATS>
+__device__ __forceinline__ void fov_walk(const gs_splat *__restrict__ splats, const float4 *__restrict__ lvl,
+                                         int n, const uint8_t *__restrict__ qbound, int L,
+                                         const uint32_t *__restrict__ vals, const WaveCtx &w, const FovPix &f,
+                                         uint32_t b, uint32_t e, FovRec *__restrict__ srec, FovState &s,
+                                         float *st)
+{
+    const int lane = __lane_id();
+    const int64_t vbase = (int64_t)w.vi.v * n;
+    for (uint32_t c0 = b; c0 < e; c0 += 64) {
+        if (ballot64(!(s.done_a && s.done_b)) == 0) break;
         const uint32_t idx = c0 + lane;
         bool keep = false;
         // the record is fully defined on every lane before the cull decision
@@ -273,7 +335,7 @@ k_raster_fov(const gs_splat *__restrict__ splats, const float4 *__restrict__ lvl
         rec.a = rec.b = make_float4(0.f, 0.f, 0.f, 0.f);
 #pragma unroll
         for (int t = 0; t < MAXL; ++t) rec.lv[t] = make_float4(0.f, 0.f, 0.f, 0.f);
-        if (idx < end) {
+        if (idx < e) {
             const uint32_t id = vals[idx];
             const int m = qbound[id];
             const float4 *s4 = reinterpret_cast<const float4 *>(splats + vbase + id);
@@ -284,74 +346,408 @@ k_raster_fov(const gs_splat *__restrict__ splats, const float4 *__restrict__ lvl
 #pragma unroll
             for (int t = 0; t < MAXL; ++t)
                 if (t < L) rec.lv[t] = lp[t];
-            keep = m >= wave_lo &&
-                   reaches_rect(s0.x, s0.y, s0.z, s0.w, s1.x, 9.001f, rx0, rx1, ry0, ry1);
+            keep = m >= f.wave_lo &&
+                   reaches_rect(s0.x, s0.y, s0.z, s0.w, s1.x, 9.001f, w.rx0, w.rx1, w.ry0, w.ry1);
         }
         const uint64_t msk = ballot64(keep);
-        if (keep) s_rec[wave][__popcll(msk & lanemask_lt())] = rec;
+        if (keep) srec[__popcll(msk & lanemask_lt())] = rec;
         wave_lds_sync();
         const int cnt = __popcll(msk);
         if (STATS) {
-            st_staged += (float)min(64u, end - c0);
-            st_kept += (float)cnt;
+            st[2] += (float)min(64u, e - c0);
+            st[3] += (float)cnt;
         }
         for (int j = 0; j < cnt; ++j) {
             // branch-free: every lane evaluates, selects take the decisions
-            const float4 a = s_rec[wave][j].a, b = s_rec[wave][j].b;
-            if (STATS) st_eval += (done_a && done_b) ? 0.0f : 1.0f;
-            const float p2 = pair_e2(a, b, fpx, fpy);  // b.y = 0: falloff only
-            const int m = __float_as_int(b.z);
+            const float4 a = srec[j].a, bb = srec[j].b;
+            if (STATS) st[1] += (s.done_a && s.done_b) ? 0.0f : 1.0f;
+            const float p2 = pair_e2(a, bb, w.fpx, w.fpy);  // bb.y = 0: falloff only
+            const int m = __float_as_int(bb.z);
             const float G = fast_exp2(p2);
             const bool incl = p2 >= EXTENT_LOG2;
             {
-                const float4 lv = s_rec[wave][j].lv[lo - 1];
+                const float4 lv = srec[j].lv[f.lo - 1];
                 const float alpha = fminf(GS_ALPHA_MAX, lv.w * G);
-                const bool use = incl && !done_a && m >= lo && alpha >= GS_ALPHA_MIN;
-                const float Tn = fmaf(-alpha, Ta, Ta);
+                const bool use = incl && !s.done_a && m >= f.lo && alpha >= GS_ALPHA_MIN;
+                const float Tn = fmaf(-alpha, s.Ta, s.Ta);
                 const bool stop = use && Tn < GS_T_STOP;
                 const bool blend = use && !stop;
-                const float w = blend ? alpha * Ta : 0.0f;
-                A0 = fmaf(w, lv.x, A0);
-                A1 = fmaf(w, lv.y, A1);
-                A2 = fmaf(w, lv.z, A2);
-                Ta = blend ? Tn : Ta;
-                done_a = done_a || stop;
-                if (STATS) st_blend += blend ? 1.0f : 0.0f;
+                const float wt = blend ? alpha * s.Ta : 0.0f;
+                s.A0 = fmaf(wt, lv.x, s.A0);
+                s.A1 = fmaf(wt, lv.y, s.A1);
+                s.A2 = fmaf(wt, lv.z, s.A2);
+                s.Ta = blend ? Tn : s.Ta;
+                s.done_a = s.done_a || stop;
+                if (STATS) st[0] += blend ? 1.0f : 0.0f;
             }
-            if (any_two) {
-                const float4 lv = s_rec[wave][j].lv[lo < MAXL ? lo : MAXL - 1];
+            if (f.any_two) {
+                const float4 lv = srec[j].lv[f.lo < MAXL ? f.lo : MAXL - 1];
                 const float alpha = fminf(GS_ALPHA_MAX, lv.w * G);
-                const bool use = incl && !done_b && m >= lo + 1 && alpha >= GS_ALPHA_MIN;
-                const float Tn = fmaf(-alpha, Tb, Tb);
+                const bool use = incl && !s.done_b && m >= f.lo + 1 && alpha >= GS_ALPHA_MIN;
+                const float Tn = fmaf(-alpha, s.Tb, s.Tb);
                 const bool stop = use && Tn < GS_T_STOP;
                 const bool blend = use && !stop;
-                const float w = blend ? alpha * Tb : 0.0f;
-                B0 = fmaf(w, lv.x, B0);
-                B1 = fmaf(w, lv.y, B1);
-                B2 = fmaf(w, lv.z, B2);
-                Tb = blend ? Tn : Tb;
-                done_b = done_b || stop;
-                if (STATS) st_blend += blend ? 1.0f : 0.0f;
+                const float wt = blend ? alpha * s.Tb : 0.0f;
+                s.B0 = fmaf(wt, lv.x, s.B0);
+                s.B1 = fmaf(wt, lv.y, s.B1);
+                s.B2 = fmaf(wt, lv.z, s.B2);
+                s.Tb = blend ? Tn : s.Tb;
+                s.done_b = s.done_b || stop;
+                if (STATS) st[0] += blend ? 1.0f : 0.0f;
             }
-            if ((j & 7) == 7 && ballot64(!(done_a && done_b)) == 0) break;
+            if ((j & 7) == 7 && ballot64(!(s.done_a && s.done_b)) == 0) break;
         }
         wave_lds_sync();
     }
-    if (inside) {
-        const int64_t plane = (int64_t)vi.W * vi.H;
-        float *img = image + 3 * vi.pix_off + (int64_t)py * vi.W + px;
-        float ra = fmaf(Ta, bg0, A0), ga = fmaf(Ta, bg1, A1), ba = fmaf(Ta, bg2, A2);
-        if (two) {
-            float rb = fmaf(Tb, bg0, B0), gb = fmaf(Tb, bg1, B1), bb = fmaf(Tb, bg2, B2);
-            ra = (1.0f - wup) * ra + wup * rb;
-            ga = (1.0f - wup) * ga + wup * gb;
-            ba = (1.0f - wup) * ba + wup * bb;
-        }
-        img[0] = ra;
-        img[plane] = ga;
-        img[2 * plane] = ba;
+}
+
+__device__ __forceinline__ void fov_finish(const WaveCtx &w, const FovPix &f, const FovState &s, float bg0,
+                                           float bg1, float bg2, float *__restrict__ image)
+{
+    if (!w.inside) return;
+    const int64_t plane = (int64_t)w.vi.W * w.vi.H;
+    float *img = image + 3 * w.vi.pix_off + (int64_t)w.py * w.vi.W + w.px;
+    float ra = fmaf(s.Ta, bg0, s.A0), ga = fmaf(s.Ta, bg1, s.A1), ba = fmaf(s.Ta, bg2, s.A2);
+    if (f.two) {
+        float rb = fmaf(s.Tb, bg0, s.B0), gb = fmaf(s.Tb, bg1, s.B1), bb = fmaf(s.Tb, bg2, s.B2);
+        ra = (1.0f - f.wup) * ra + f.wup * rb;
+        ga = (1.0f - f.wup) * ga + f.wup * gb;
+        ba = (1.0f - f.wup) * ba + f.wup * bb;
     }
-    if (STATS) stats_add(stats, st_blend, st_eval, st_staged, st_kept);
+    img[0] = ra;
+    img[plane] = ga;
+    img[2 * plane] = ba;
+}
+
+template <int T, bool STATS>
+__global__ void __launch_bounds__(T *T)
+k_raster_fov(const gs_splat *__restrict__ splats, const float4 *__restrict__ lvl, int n,
+             const uint8_t *__restrict__ qbound, int L, const gs_camera *__restrict__ cams, int V,
+             const uint32_t *__restrict__ vals, const uint32_t *__restrict__ ranges,
+             const uint8_t *__restrict__ pix_level, const float *__restrict__ pix_weight, float bg0,
+             float bg1, float bg2, float *__restrict__ image, unsigned long long *__restrict__ stats)
+{
+    float st[4] = {0.f, 0.f, 0.f, 0.f};
+    constexpr int WAVES = T * T / 64;
+    __shared__ FovRec s_rec[WAVES][64];
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const WaveCtx w = wave_ctx<T>(cams, V, blockIdx.x, wave, lane, ranges);
+    const FovPix f = fov_pix(w, pix_level, pix_weight);
+    FovState s = fov_init(w.inside, f.two);
+    fov_walk<STATS>(splats, lvl, n, qbound, L, vals, w, f, w.start, w.end, s_rec[wave], s, st);
+    fov_finish(w, f, s, bg0, bg1, bg2, image);
+    if (STATS) stats_add(stats, st[0], st[1], st[2], st[3]);
+}
+
+// ---------------------------------------------------------------------------
+// Persistent work queue (load balance across tiles).  A task is a tile, or,
+// for a tile whose run is longer than the split length beta, one chunk of
+// beta entries of it; a workgroup takes one task at a time and its waves
+// cover the tile's 8x8 sub-blocks as in the one-workgroup-per-tile kernels
+// (so they share the gathered splats in cache).  Tasks of tiles with long
+// runs are queued first (longest work first); the workgroups of a persistent
+// grid pop tasks from one atomic counter until the queue is empty.  A chunk
+// composites its entries from T = 1 and stores (C, T, stopped) per pixel;
+// the workgroup that finishes a tile's last chunk merges the chunks front to
+// back with (C, T)_a + (C, T)_b = (C_a + T_a C_b, T_a T_b).  Where the running
+// T reaches the stop threshold inside a chunk (or the chunk stopped on its
+// own), the product would overshoot the sequential stop, so that chunk is
+// composited again for those pixels from the running state -- the
+// sequential result, up to float reassociation of the T products.
+struct RasterQueue {
+    uint32_t *counts;     // [4]: head, heavy tasks, light tasks, spare
+    uint2 *heavy;         // [heavy_cap] (tile, chunk)
+    uint2 *light;         // [light_cap]
+    uint32_t *merge_cnt;  // [heavy_cap] chunks finished, at each tile's first chunk
+    float4 *part;         // [heavy_cap][T*T][3] chunk partials (split only)
+    uint32_t heavy_cap, light_cap;
+    uint32_t beta;        // split length (0: no split)
+    uint32_t heavy_min;   // runs longer than this are queued first
+    uint32_t grab;        // tasks taken per pop
+    int64_t n_tiles;
+};
+
+__device__ __forceinline__ uint32_t n_chunks_of(uint32_t len, uint32_t beta)
+{
+    return (beta && len > beta) ? (len + beta - 1) / beta : 1u;
+}
+
+// One thread per tile; block-level aggregation of the queue reservations.
+__global__ void __launch_bounds__(256)
+k_build_queue(const uint32_t *__restrict__ ranges, int64_t n_tiles, RasterQueue q)
+{
+    __shared__ uint32_t s_h[4], s_l[4], s_bh, s_bl;
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    uint32_t nch = 1, nh = 0, nl = 0;
+    if (t < n_tiles) {
+        const uint32_t len = ranges[2 * t + 1] - ranges[2 * t];
+        nch = n_chunks_of(len, q.beta);
+        if (nch > 1 || len > q.heavy_min)
+            nh = nch;
+        else
+            nl = 1;
+    }
+    // exclusive prefix of nh and nl over the block
+    uint32_t ih = nh, il = nl;
+    for (int off = 1; off < 64; off <<= 1) {
+        const uint32_t a = __shfl_up(ih, off), b = __shfl_up(il, off);
+        if (lane >= off) {
+            ih += a;
+            il += b;
+        }
+    }
+    if (lane == 63) {
+        s_h[wave] = ih;
+        s_l[wave] = il;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        uint32_t th = 0, tl = 0;
+        for (int k = 0; k < 4; ++k) {
+            const uint32_t a = s_h[k], b = s_l[k];
+            s_h[k] = th;
+            s_l[k] = tl;
+            th += a;
+            tl += b;
+        }
+        s_bh = th ? atomicAdd(q.counts + 1, th) : 0u;
+        s_bl = tl ? atomicAdd(q.counts + 2, tl) : 0u;
+    }
+    __syncthreads();
+    if (t >= n_tiles) return;
+    if (nh) {
+        const uint32_t base = s_bh + s_h[wave] + ih - nh;
+        if (base + nh <= q.heavy_cap) {
+            for (uint32_t c = 0; c < nh; ++c) q.heavy[base + c] = make_uint2((uint32_t)t, c);
+            q.merge_cnt[base] = 0u;
+            return;
+        }
+        // no room among the heavy tasks: blank the reserved slots that exist
+        // and queue the tile unsplit with the light ones (which always fit)
+        for (uint32_t k = base; k < base + nh && k < q.heavy_cap; ++k) q.heavy[k] = make_uint2(0xFFFFFFFFu, 0u);
+        const uint32_t lb = atomicAdd(q.counts + 2, 1u);
+        if (lb < q.light_cap) q.light[lb] = make_uint2((uint32_t)t, 0u);
+        return;
+    }
+    const uint32_t base = s_bl + s_l[wave] + il - nl;
+    if (base < q.light_cap) q.light[base] = make_uint2((uint32_t)t, 0u);
+}
+
+// Pops the next task for the calling workgroup (uniform over the block).
+__device__ __forceinline__ uint32_t pop_task(uint32_t *head, uint32_t *s_slot, uint32_t grab)
+{
+    if (threadIdx.x == 0) *s_slot = atomicAdd(head, grab);
+    __syncthreads();
+    const uint32_t v = *s_slot;
+    __syncthreads();
+    return v;
+}
+
+// After a chunk's partials are stored: counts the chunk as finished and
+// returns true (uniform over the block) in the workgroup that finished last.
+__device__ __forceinline__ bool last_chunk(uint32_t *cnt, uint32_t nch, uint32_t *s_slot)
+{
+    __threadfence();
+    __syncthreads();
+    if (threadIdx.x == 0) *s_slot = atomicAdd(cnt, 1u);
+    __syncthreads();
+    const bool last = *s_slot == nch - 1;
+    __syncthreads();
+    if (last) __threadfence();
+    return last;
+}
+
+// One task of the plain compositor (every thread of the block calls it).
+template <int T, bool DOM>
+__device__ __forceinline__ void fwd_task(const gs_splat *__restrict__ splats, int n,
+                                         const gs_camera *__restrict__ cams, int V,
+                                         const uint32_t *__restrict__ vals, const uint32_t *__restrict__ ranges,
+                                         float bg0, float bg1, float bg2, float *__restrict__ image,
+                                         float *__restrict__ final_T, uint32_t *__restrict__ n_contrib,
+                                         uint32_t *__restrict__ dominated, const RasterQueue &q, uint32_t nh,
+                                         uint32_t it, FwdRec *__restrict__ srec, uint32_t *s_slot)
+{
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const uint2 task = it < nh ? q.heavy[it] : q.light[it - nh];
+    if ((int64_t)task.x >= q.n_tiles) return;
+    const uint32_t c = task.y;
+    const WaveCtx w = wave_ctx<T>(cams, V, task.x, wave, lane, ranges);
+    const gs_splat *vsp = splats + (int64_t)w.vi.v * n;
+    // tasks from the light list (including heavy tiles that did not fit
+    // among the heavy tasks) are never split
+    const uint32_t nch = it < nh ? n_chunks_of(w.end - w.start, q.beta) : 1u;
+    FwdState s = fwd_init(w.inside);
+    if (nch == 1) {
+        fwd_walk<DOM, false>(vsp, vals, w, w.start, w.end, srec, s, nullptr);
+        fwd_finish<DOM>(w, s, n, bg0, bg1, bg2, image, final_T, n_contrib, dominated);
+        return;
+    }
+    if (c >= nch || it - c + nch > nh) return;
+    const uint32_t b = w.start + c * q.beta, e = min(w.end, b + q.beta);
+    fwd_walk<DOM, false>(vsp, vals, w, b, e, srec, s, nullptr);
+    float4 *pp = q.part + ((int64_t)it * (T * T) + threadIdx.x) * 3;
+    pp[0] = make_float4(s.C0, s.C1, s.C2, s.Tr);
+    pp[1] = make_float4(__uint_as_float(s.last), s.best, __int_as_float(s.best_id),
+                        __uint_as_float(s.done ? 1u : 0u));
+    const uint32_t first = it - c;
+    if (!last_chunk(q.merge_cnt + first, nch, s_slot)) return;
+    // last chunk of this tile: merge front to back
+    FwdState m = fwd_init(w.inside);
+    for (uint32_t k = 0; k < nch; ++k) {
+        const float4 *pk = q.part + ((int64_t)(first + k) * (T * T) + threadIdx.x) * 3;
+        const float4 p0 = pk[0], p1 = pk[1];
+        const bool pdone = __float_as_uint(p1.w) != 0u;
+        const bool fix = !m.done && (pdone || m.Tr * p0.w < GS_T_STOP);
+        if (!m.done && !fix) {
+            m.C0 = fmaf(m.Tr, p0.x, m.C0);
+            m.C1 = fmaf(m.Tr, p0.y, m.C1);
+            m.C2 = fmaf(m.Tr, p0.z, m.C2);
+            const uint32_t pl = __float_as_uint(p1.x);
+            if (pl) m.last = pl;
+            if (DOM && __float_as_int(p1.z) >= 0 && m.Tr * p1.y > m.best) {
+                m.best = m.Tr * p1.y;
+                m.best_id = __float_as_int(p1.z);
+            }
+            m.Tr *= p0.w;
+        }
+        if (ballot64(fix) != 0) {
+            // composite this chunk again from the running state
+            FwdState r = m;
+            r.done = m.done || !fix;
+            const uint32_t kb = w.start + k * q.beta, ke = min(w.end, kb + q.beta);
+            fwd_walk<DOM, false>(vsp, vals, w, kb, ke, srec, r, nullptr);
+            if (fix) m = r;
+        }
+    }
+    fwd_finish<DOM>(w, m, n, bg0, bg1, bg2, image, final_T, n_contrib, dominated);
+}
+
+template <int T, bool DOM>
+__global__ void __launch_bounds__(T *T)
+k_raster_fwd_q(const gs_splat *__restrict__ splats, int n, const gs_camera *__restrict__ cams, int V,
+               const uint32_t *__restrict__ vals, const uint32_t *__restrict__ ranges, float bg0, float bg1,
+               float bg2, float *__restrict__ image, float *__restrict__ final_T,
+               uint32_t *__restrict__ n_contrib, uint32_t *__restrict__ dominated, RasterQueue q)
+{
+    constexpr int WAVES = T * T / 64;
+    __shared__ FwdRec s_rec[WAVES][64];
+    __shared__ uint32_t s_slot;
+    const uint32_t nh = min(q.counts[1], q.heavy_cap), total = nh + min(q.counts[2], q.light_cap);
+    // q.grab consecutive tasks per pop (neighbouring tiles share splats in cache)
+    uint32_t it = pop_task(q.counts, &s_slot, q.grab);
+    while (it < total) {
+        for (uint32_t k = 0; k < q.grab && it + k < total; ++k) {
+            fwd_task<T, DOM>(splats, n, cams, V, vals, ranges, bg0, bg1, bg2, image, final_T, n_contrib,
+                             dominated, q, nh, it + k, s_rec[threadIdx.x >> 6], &s_slot);
+            __syncthreads();
+        }
+        it = pop_task(q.counts, &s_slot, q.grab);
+    }
+}
+
+// One task of the foveated compositor (every thread of the block calls it).
+template <int T>
+__device__ __forceinline__ void fov_task(const gs_splat *__restrict__ splats, const float4 *__restrict__ lvl,
+                                         int n, const uint8_t *__restrict__ qbound, int L,
+                                         const gs_camera *__restrict__ cams, int V,
+                                         const uint32_t *__restrict__ vals, const uint32_t *__restrict__ ranges,
+                                         const uint8_t *__restrict__ pix_level,
+                                         const float *__restrict__ pix_weight, float bg0, float bg1, float bg2,
+                                         float *__restrict__ image, const RasterQueue &q, uint32_t nh,
+                                         uint32_t it, FovRec *__restrict__ srec, uint32_t *s_slot)
+{
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const uint2 task = it < nh ? q.heavy[it] : q.light[it - nh];
+    if ((int64_t)task.x >= q.n_tiles) return;
+    const uint32_t c = task.y;
+    const WaveCtx w = wave_ctx<T>(cams, V, task.x, wave, lane, ranges);
+    const FovPix f = fov_pix(w, pix_level, pix_weight);
+    // tasks from the light list (including heavy tiles that did not fit
+    // among the heavy tasks) are never split
+    const uint32_t nch = it < nh ? n_chunks_of(w.end - w.start, q.beta) : 1u;
+    FovState s = fov_init(w.inside, f.two);
+    if (nch == 1) {
+        fov_walk<false>(splats, lvl, n, qbound, L, vals, w, f, w.start, w.end, srec, s, nullptr);
+        fov_finish(w, f, s, bg0, bg1, bg2, image);
+        return;
+    }
+    if (c >= nch || it - c + nch > nh) return;
+    const uint32_t b = w.start + c * q.beta, e = min(w.end, b + q.beta);
+    fov_walk<false>(splats, lvl, n, qbound, L, vals, w, f, b, e, srec, s, nullptr);
+    float4 *pp = q.part + ((int64_t)it * (T * T) + threadIdx.x) * 3;
+    pp[0] = make_float4(s.A0, s.A1, s.A2, s.Ta);
+    pp[1] = make_float4(s.B0, s.B1, s.B2, s.Tb);
+    pp[2] = make_float4(__uint_as_float(s.done_a ? 1u : 0u), __uint_as_float(s.done_b ? 1u : 0u), 0.f, 0.f);
+    const uint32_t first = it - c;
+    if (!last_chunk(q.merge_cnt + first, nch, s_slot)) return;
+    // last chunk of this tile: merge front to back
+    FovState m = fov_init(w.inside, f.two);
+    for (uint32_t k = 0; k < nch; ++k) {
+        const float4 *pk = q.part + ((int64_t)(first + k) * (T * T) + threadIdx.x) * 3;
+        const float4 pa = pk[0], pb = pk[1], pf = pk[2];
+        const bool fix_a = !m.done_a && (__float_as_uint(pf.x) != 0u || m.Ta * pa.w < GS_T_STOP);
+        const bool fix_b = !m.done_b && (__float_as_uint(pf.y) != 0u || m.Tb * pb.w < GS_T_STOP);
+        if (!m.done_a && !fix_a) {
+            m.A0 = fmaf(m.Ta, pa.x, m.A0);
+            m.A1 = fmaf(m.Ta, pa.y, m.A1);
+            m.A2 = fmaf(m.Ta, pa.z, m.A2);
+            m.Ta *= pa.w;
+        }
+        if (!m.done_b && !fix_b) {
+            m.B0 = fmaf(m.Tb, pb.x, m.B0);
+            m.B1 = fmaf(m.Tb, pb.y, m.B1);
+            m.B2 = fmaf(m.Tb, pb.z, m.B2);
+            m.Tb *= pb.w;
+        }
+        if (ballot64(fix_a || fix_b) != 0) {
+            // composite this chunk again from the running state
+            FovState r = m;
+            r.done_a = m.done_a || !fix_a;
+            r.done_b = m.done_b || !fix_b;
+            const uint32_t kb = w.start + k * q.beta, ke = min(w.end, kb + q.beta);
+            fov_walk<false>(splats, lvl, n, qbound, L, vals, w, f, kb, ke, srec, r, nullptr);
+            if (fix_a) {
+                m.Ta = r.Ta;
+                m.A0 = r.A0;
+                m.A1 = r.A1;
+                m.A2 = r.A2;
+                m.done_a = r.done_a;
+            }
+            if (fix_b) {
+                m.Tb = r.Tb;
+                m.B0 = r.B0;
+                m.B1 = r.B1;
+                m.B2 = r.B2;
+                m.done_b = r.done_b;
+            }
+        }
+    }
+    fov_finish(w, f, m, bg0, bg1, bg2, image);
+}
+
+template <int T>
+__global__ void __launch_bounds__(T *T)
+k_raster_fov_q(const gs_splat *__restrict__ splats, const float4 *__restrict__ lvl, int n,
+               const uint8_t *__restrict__ qbound, int L, const gs_camera *__restrict__ cams, int V,
+               const uint32_t *__restrict__ vals, const uint32_t *__restrict__ ranges,
+               const uint8_t *__restrict__ pix_level, const float *__restrict__ pix_weight, float bg0, float bg1,
+               float bg2, float *__restrict__ image, RasterQueue q)
+{
+    constexpr int WAVES = T * T / 64;
+    __shared__ FovRec s_rec[WAVES][64];
+    __shared__ uint32_t s_slot;
+    const uint32_t nh = min(q.counts[1], q.heavy_cap), total = nh + min(q.counts[2], q.light_cap);
+    // q.grab consecutive tasks per pop (neighbouring tiles share splats in cache)
+    uint32_t it = pop_task(q.counts, &s_slot, q.grab);
+    while (it < total) {
+        for (uint32_t k = 0; k < q.grab && it + k < total; ++k) {
+            fov_task<T>(splats, lvl, n, qbound, L, cams, V, vals, ranges, pix_level, pix_weight, bg0, bg1, bg2,
+                        image, q, nh, it + k, s_rec[threadIdx.x >> 6], &s_slot);
+            __syncthreads();
+        }
+        it = pop_task(q.counts, &s_slot, q.grab);
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -612,15 +1008,87 @@ k_fovea_tile(const gs_camera *__restrict__ cams, int V, int T, int64_t n_tiles,
 
 }  // namespace
 
+namespace {
+
+// Persistent grid: resident workgroups of the kernel on every CU.
+template <class K>
+unsigned persistent_blocks(K kernel, int threads)
+{
+    int dev = 0, cus = 0, per_cu = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return 1024;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) cus = 256;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, threads, 0) != hipSuccess || per_cu < 1)
+        per_cu = 1;
+    return (unsigned)(cus * per_cu);
+}
+
+hipError_t build_queue(const uint32_t *ranges, int64_t n_tiles, int T, const RasterQueueArgs &qa, RasterQueue &q,
+                       hipStream_t st)
+{
+    q.counts = qa.counts;
+    q.heavy = reinterpret_cast<uint2 *>(qa.heavy);
+    q.light = reinterpret_cast<uint2 *>(qa.light);
+    q.merge_cnt = qa.merge_cnt;
+    q.part = reinterpret_cast<float4 *>(qa.part);
+    q.heavy_cap = qa.heavy_cap;
+    q.light_cap = qa.light_cap;
+    q.beta = qa.beta;
+    // split tiles are the heavy ones; without splitting, runs longer than
+    // heavy_min go first (0: plain tile order)
+    q.heavy_min = qa.beta ? qa.beta : (qa.heavy_min ? qa.heavy_min : 0xFFFFFFFFu);
+    q.grab = qa.grab ? qa.grab : 1;
+    q.n_tiles = n_tiles;
+    hipError_t e = launch_fill_u32(q.counts, 0u, 4, st);
+    if (e != hipSuccess) return e;
+    const unsigned blocks = (unsigned)((n_tiles + 255) / 256);
+    (void)T;
+    hipLaunchKernelGGL(k_build_queue, dim3(blocks), dim3(256), 0, st, ranges, n_tiles, q);
+    return hipGetLastError();
+}
+
+}  // namespace
+
+uint64_t raster_queue_heavy_cap(int64_t n_tiles, int T, uint64_t cap, uint32_t beta)
+{
+    (void)T;
+    return (uint64_t)n_tiles + (beta ? cap / beta + 1 : 0);
+}
+
 hipError_t launch_raster_fwd(const gs_splat *splats, int n, const gs_camera *cams_dev, int V, int T,
                              int64_t n_tiles, const uint32_t *vals, const uint32_t *ranges,
                              const float bg[3], float *image, float *final_T, uint32_t *n_contrib,
-                             uint32_t *dominated, uint64_t *stats, hipStream_t st)
+                             uint32_t *dominated, uint64_t *stats, const RasterQueueArgs *qa, hipStream_t st)
 {
     if (n_tiles == 0) return hipSuccess;
     hipError_t e;
     if (dominated && (e = launch_fill_u32(dominated, 0u, (uint64_t)V * n, st)) != hipSuccess) return e;
     unsigned long long *sp = reinterpret_cast<unsigned long long *>(stats);
+    if (qa && !stats) {
+        RasterQueue q;
+        if ((e = build_queue(ranges, n_tiles, T, *qa, q, st)) != hipSuccess) return e;
+#define GS_RQ(TS, DM)                                                                                  \
+    {                                                                                                  \
+        static unsigned blocks = 0;                                                                    \
+        if (!blocks) blocks = persistent_blocks(k_raster_fwd_q<TS, DM>, TS * TS);                     \
+        hipLaunchKernelGGL((k_raster_fwd_q<TS, DM>), dim3(blocks), dim3(TS * TS), 0, st, splats, n, cams_dev, \
+                           V, vals, ranges, bg[0], bg[1], bg[2], image, final_T, n_contrib, dominated, q); \
+    }
+        if (dominated) {
+            switch (T) {
+            case 8: GS_RQ(8, true); break;
+            case 16: GS_RQ(16, true); break;
+            default: GS_RQ(32, true); break;
+            }
+        } else {
+            switch (T) {
+            case 8: GS_RQ(8, false); break;
+            case 16: GS_RQ(16, false); break;
+            default: GS_RQ(32, false); break;
+            }
+        }
+#undef GS_RQ
+        return hipGetLastError();
+    }
 #define GS_RF(TS)                                                                                  \
     if (stats)                                                                                     \
         hipLaunchKernelGGL((k_raster_fwd<TS, false, true>), dim3((unsigned)n_tiles), dim3(TS * TS), \
@@ -680,11 +1148,31 @@ hipError_t launch_raster_fov(const gs_splat *splats, const float *lvl_rgba, int 
                              const uint8_t *qbound, int n_levels, const gs_camera *cams_dev, int V,
                              int T, int64_t n_tiles, const uint32_t *vals, const uint32_t *ranges,
                              const uint8_t *pix_level, const float *pix_weight, const float bg[3],
-                             float *image, uint64_t *stats, hipStream_t st)
+                             float *image, uint64_t *stats, const RasterQueueArgs *qa, hipStream_t st)
 {
     if (n_tiles == 0) return hipSuccess;
     const float4 *lv = reinterpret_cast<const float4 *>(lvl_rgba);
     unsigned long long *sp = reinterpret_cast<unsigned long long *>(stats);
+    if (qa && !stats) {
+        RasterQueue q;
+        hipError_t e;
+        if ((e = build_queue(ranges, n_tiles, T, *qa, q, st)) != hipSuccess) return e;
+#define GS_RQ(TS)                                                                                      \
+    {                                                                                                  \
+        static unsigned blocks = 0;                                                                    \
+        if (!blocks) blocks = persistent_blocks(k_raster_fov_q<TS>, TS * TS);                         \
+        hipLaunchKernelGGL((k_raster_fov_q<TS>), dim3(blocks), dim3(TS * TS), 0, st, splats, lv, n, qbound, \
+                           n_levels, cams_dev, V, vals, ranges, pix_level, pix_weight, bg[0], bg[1],    \
+                           bg[2], image, q);                                                           \
+    }
+        switch (T) {
+        case 8: GS_RQ(8); break;
+        case 16: GS_RQ(16); break;
+        default: GS_RQ(32); break;
+        }
+#undef GS_RQ
+        return hipGetLastError();
+    }
 #define GS_RV(TS)                                                                                    \
     if (stats)                                                                                       \
         hipLaunchKernelGGL((k_raster_fov<TS, true>), dim3((unsigned)n_tiles), dim3(TS * TS), 0, st,   \

@@ -156,10 +156,12 @@ def test_autotune_small():
     best, tried = autotune.tune(S, cams, target, eyes, fov, reps=2)
     assert best["tile"] in (8, 16, 32) and 1 <= best["batch_views"] <= len(cams)
     assert best["radix_part"] in (8192, 16384) and np.isfinite(best["ms"])
-    assert len(tried) >= 4
+    assert best["raster_queue"] in (0, 1)
+    assert len(tried) >= 5
     step = BatchedStep(S, cams, target, best["tile"], best["batch_views"], eyes, fov)
     step.step()
     ref = BatchedStep(S, cams, target, best["tile"], None, eyes, fov)
     ref.step()
     assert_same(snapshot(ref), snapshot(step))
     g.gs_set_tuning("radix_part", 8192)
+    g.gs_set_tuning("raster_queue", 0)
