@@ -239,3 +239,68 @@ def splats_to_proj(splats: dict) -> dict:
                 radius=np.ascontiguousarray(splats["radius"], np.int32),
                 lvl_opacity=None if splats.get("lvl_opacity") is None else _f64(splats["lvl_opacity"]),
                 lvl_color=None if splats.get("lvl_color") is None else _f64(splats["lvl_color"]))
+
+
+# ---------------------------------------------------------------------------
+# Efficiency-aware pruning (Section 3).  Plain numpy, written from the
+# definitions; the point of these is to be read against the paper.
+
+def ce_score(dominated, hits) -> np.ndarray:
+    """Computational efficiency of every point (Section 3.2, the CE equation):
+    CE_i = Val_i / Comp_i per view -- Val the pixels the point dominates,
+    Comp the tiles that intersect and use it -- and the final CE is the
+    maximum over the views (Section 3.2 prefers the maximum to the mean).
+    A view in which the point uses no tile contributes 0.  The ratio is
+    taken in float32 (correctly rounded division of exactly representable
+    counts), the precision the selection below orders by."""
+    dom = np.asarray(dominated, dtype=np.int64)
+    hit = np.asarray(hits, dtype=np.int64)
+    if dom.ndim == 1:
+        dom, hit = dom[None], hit[None]
+    V, n = dom.shape
+    out = np.zeros(n, dtype=np.float32)
+    for v in range(V):
+        used = hit[v] > 0
+        ratio = np.zeros(n, dtype=np.float32)
+        ratio[used] = dom[v, used].astype(np.float32) / hit[v, used].astype(np.float32)
+        out = np.maximum(out, ratio)
+    return out
+
+
+def select_lowest(ce, k: int):
+    """The k points with the lowest CE, removed first by the pruning step of
+    Section 3.4 (R = 10 % of the points per round there).  Ties in CE are
+    broken by the lower point index.  Returns (mask [n] uint8, indices [k]
+    ascending)."""
+    ce = np.asarray(ce, dtype=np.float32)
+    n = ce.shape[0]
+    k = max(0, min(int(k), n))
+    order = np.lexsort((np.arange(n), ce))  # by CE, then by index
+    chosen = np.sort(order[:k]).astype(np.uint32)
+    mask = np.zeros(n, dtype=np.uint8)
+    mask[chosen] = 1
+    return mask, chosen
+
+
+def weighted_scale(log_scales, hits, threshold: float, gamma: float = 1.0):
+    """Weighted Scale (Section 3.3): WS = (1/N) sum_i S_i G_i with
+    G_i = [U_i > T] (U_i - T), U_i the tiles point i is used in.  Readings:
+    S_i, the largest span of the point's ellipse, is three standard
+    deviations along its longest axis, 3 max_k exp(log_scale_ik); with a
+    batch of V views, U is taken per view and WS is averaged over the views.
+    Returns (gamma * WS, d(gamma * WS)/d log_scales) in float64; the
+    gradient flows through S only (G is a count), to the axis attaining the
+    maximum (the first one on ties)."""
+    ls = np.asarray(log_scales, dtype=np.float64).reshape(-1, 3)
+    U = np.asarray(hits, dtype=np.float64)
+    if U.ndim == 1:
+        U = U[None]
+    V, n = U.shape
+    sc = np.exp(ls)
+    axis = np.argmax(sc, axis=1)
+    S = 3.0 * sc[np.arange(n), axis]
+    G = np.where(U > threshold, U - threshold, 0.0).sum(axis=0)
+    ws = gamma * float((S * G).sum()) / (n * V)
+    grad = np.zeros_like(ls)
+    grad[np.arange(n), axis] = gamma * G * S / (n * V)
+    return ws, grad
