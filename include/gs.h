@@ -283,6 +283,39 @@ int gs_render_fwd(const gs_scene *scene, const gs_camera *cams_host, const gs_ca
 int gs_l1_grad(const float *image, const float *target, uint64_t n, float scale, float *dL_dimage,
                float *loss, int reset, void *stream);
 
+/* Computational efficiency of every point (Section 3.2, the CE equation):
+ * per view, Val / Comp with Val = the pixels the point dominates
+ * (dominated_px of gs_rasterize_fwd) and Comp = the tiles that intersect and
+ * use it (hits of gs_bin_sort, after the level filter when there is one);
+ * CE = the maximum over the views (0 for views where it uses no tile).  The
+ * ratio is a correctly rounded float32 division.  dominated, hits: device
+ * uint32 [n_views][n]; ce: device float [n]. */
+int gs_ce_score(const uint32_t *dominated, const uint32_t *hits, int32_t n, int n_views, float *ce,
+                void *stream);
+
+/* Selection of the k points with the lowest CE for removal (the pruning
+ * rounds of Section 3.4 remove R = 10 % per round): a radix select on the
+ * float bits (CE >= 0), ties broken by the lower index.  ce: device float
+ * [n] (non-negative, no NaN); mask: device uint8 [n], 1 for selected points;
+ * idx (nullable): device uint32 [k], the selected indices ascending.  k is
+ * clamped to [0, n].  Workspace: gs_select_workspace_bytes(n) bytes, 256-byte
+ * aligned (not needed when k = 0). */
+size_t gs_select_workspace_bytes(int32_t n);
+int gs_select_lowest(const float *ce, int32_t n, int32_t k, uint8_t *mask, uint32_t *idx, void *workspace,
+                     size_t workspace_bytes, void *stream);
+
+/* Weighted scale and its gradient (Section 3.3): ws = gamma / (N V) *
+ * sum_v sum_i S_i G_iv, S_i = 3 max_k exp(log_scales[i][k]) (three standard
+ * deviations along the longest axis), G_iv = [U > T] (U - T) with U =
+ * hits[v][i] (tiles the point is used in) and T = threshold.  The gradient
+ * with respect to log_scales flows through S to the longest axis (the first
+ * on ties); d_log_scales (nullable, device float [n][3]) is overwritten
+ * (accumulate = 0) or added to (1), e.g. on top of the render's gradient to
+ * form the composite loss of Section 3.3.  ws: device float, overwritten;
+ * summed in float32 with atomics (last bits depend on scheduling). */
+int gs_weighted_scale(const float *log_scales, const uint32_t *hits, int32_t n, int n_views, float threshold,
+                      float gamma, float *ws, float *d_log_scales, int accumulate, void *stream);
+
 /* Graph capture of a sequence of calls on one stream (every entry point
  * above except gs_sort_pairs launches kernels only: no allocation, host
  * synchronisation or host copies, so a fixed sequence of them on

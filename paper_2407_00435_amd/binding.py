@@ -83,6 +83,10 @@ _SIGS = {
     "gs_set_tuning": ([ctypes.c_char_p, ctypes.c_int64], _I),
     "gs_sort_pairs": ([_VP, _VP, _VP, _VP, _U64, _I, _VP, _SZ, _VP], _I),
     "gs_l1_grad": ([_VP, _VP, _U64, ctypes.c_float, _VP, _VP, _I, _VP], _I),
+    "gs_ce_score": ([_VP, _VP, _I32, _I, _VP, _VP], _I),
+    "gs_select_workspace_bytes": ([_I32], _SZ),
+    "gs_select_lowest": ([_VP, _I32, _I32, _VP, _VP, _VP, _SZ, _VP], _I),
+    "gs_weighted_scale": ([_VP, _VP, _I32, _I, ctypes.c_float, ctypes.c_float, _VP, _VP, _I, _VP], _I),
     "gs_graph_begin": ([_VP], _I),
     "gs_graph_end": ([_VP, ctypes.POINTER(_VP)], _I),
     "gs_graph_launch": ([_VP, _VP], _I),
@@ -321,6 +325,38 @@ def gs_l1_grad(image, target, scale, dL_dimage, loss, reset=True):
     """loss (+)= scale * sum|image - target|; dL_dimage = scale * sign(image - target)."""
     _check(lib().gs_l1_grad(_ptr(image), _ptr(target), image.numel(), float(scale), _ptr(dL_dimage),
                             _ptr(loss), int(bool(reset)), _stream()))
+
+
+def gs_ce_score(dominated, hits):
+    """CE per point from dominated [V, n] and hits [V, n] (int32/uint32 device tensors)."""
+    V, n = dominated.shape
+    ce = torch.empty(n, dtype=torch.float32, device=dominated.device)
+    _check(lib().gs_ce_score(_ptr(dominated.contiguous()), _ptr(hits.contiguous()), n, V, _ptr(ce), _stream()))
+    return ce
+
+
+def gs_select_lowest(ce, k: int, want_indices: bool = True):
+    """(mask uint8 [n], indices int32 [k] ascending) of the k lowest CE values."""
+    n = ce.numel()
+    kk = max(0, min(int(k), n))
+    mask = torch.empty(n, dtype=torch.uint8, device=ce.device)
+    idx = torch.empty(kk, dtype=torch.int32, device=ce.device) if want_indices else None
+    ws = _ws(int(lib().gs_select_workspace_bytes(n)))
+    _check(lib().gs_select_lowest(_ptr(ce.contiguous()), n, int(k), _ptr(mask), _ptr(idx) if kk else None, ws[1],
+                                  ws[2], _stream()))
+    return mask, idx
+
+
+def gs_weighted_scale(log_scales, hits, threshold: float, gamma: float = 1.0, d_log_scales=None,
+                      accumulate: bool = False):
+    """(gamma * WS as a 1-element device tensor, d/d log_scales)."""
+    V, n = hits.shape
+    ws = torch.empty(1, dtype=torch.float32, device=hits.device)
+    if d_log_scales is None:
+        d_log_scales = torch.empty((n, 3), dtype=torch.float32, device=hits.device)
+    _check(lib().gs_weighted_scale(_ptr(log_scales.contiguous()), _ptr(hits.contiguous()), n, V, float(threshold),
+                                   float(gamma), _ptr(ws), _ptr(d_log_scales), int(bool(accumulate)), _stream()))
+    return ws, d_log_scales
 
 
 class Graph:

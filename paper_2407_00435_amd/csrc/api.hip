@@ -526,6 +526,50 @@ int gs_l1_grad(const float *image, const float *target, uint64_t n, float scale,
     return ok();
 }
 
+int gs_ce_score(const uint32_t *dominated, const uint32_t *hits, int32_t n, int n_views, float *ce, void *stream)
+{
+    if (n < 0 || n_views < 1) return fail(GS_ERR_INVALID, "n must be >= 0 and n_views >= 1");
+    if ((int64_t)n * n_views >= (1ll << 32)) return fail(GS_ERR_UNSUPPORTED, "n_views * n must be < 2^32");
+    if (n > 0 && (!dominated || !hits || !ce)) return fail(GS_ERR_INVALID, "NULL output or input pointer");
+    hipError_t e = launch_ce_score(dominated, hits, n, n_views, ce, (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(e, "gs_ce_score");
+    return ok();
+}
+
+size_t gs_select_workspace_bytes(int32_t n) { return select_scratch_bytes(n > 0 ? n : 0) + 256; }
+
+int gs_select_lowest(const float *ce, int32_t n, int32_t k, uint8_t *mask, uint32_t *idx, void *workspace,
+                     size_t workspace_bytes, void *stream)
+{
+    int r;
+    if (n < 0) return fail(GS_ERR_INVALID, "n must be >= 0");
+    if (n > 0 && (!ce || !mask)) return fail(GS_ERR_INVALID, "NULL output or input pointer");
+    if (k < 0) k = 0;
+    if (k > n) k = n;
+    if (k == 0) {
+        hipError_t e = launch_fill_u8(mask, 0, n, (hipStream_t)stream);
+        if (e != hipSuccess) return hip_fail(e, "gs_select_lowest");
+        return ok();
+    }
+    if ((r = check_ws(workspace, workspace_bytes, gs_select_workspace_bytes(n)))) return r;
+    hipError_t e = launch_select_lowest(ce, n, k, mask, idx, workspace, (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(e, "gs_select_lowest");
+    return ok();
+}
+
+int gs_weighted_scale(const float *log_scales, const uint32_t *hits, int32_t n, int n_views, float threshold,
+                      float gamma, float *ws, float *d_log_scales, int accumulate, void *stream)
+{
+    if (n < 0 || n_views < 1) return fail(GS_ERR_INVALID, "n must be >= 0 and n_views >= 1");
+    if ((int64_t)n * n_views >= (1ll << 32)) return fail(GS_ERR_UNSUPPORTED, "n_views * n must be < 2^32");
+    if (!ws || (n > 0 && (!log_scales || !hits))) return fail(GS_ERR_INVALID, "NULL output or input pointer");
+    if (accumulate != 0 && accumulate != 1) return fail(GS_ERR_INVALID, "accumulate must be 0 or 1");
+    hipError_t e = launch_weighted_scale(log_scales, hits, n, n_views, threshold, gamma, ws, d_log_scales,
+                                         accumulate, (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(e, "gs_weighted_scale");
+    return ok();
+}
+
 struct gs_graph {
     hipGraph_t graph;
     hipGraphExec_t exec;

@@ -14,6 +14,16 @@ hipError_t launch_project_bwd(const gs_scene &sc, const gs_camera *cams_dev, int
                               float *g_ls, float *g_q, float *g_logit, float *g_sh, int accumulate,
                               hipStream_t st);
 
+// pruning metrics
+hipError_t launch_ce_score(const uint32_t *dominated, const uint32_t *hits, int n, int V, float *ce,
+                           hipStream_t st);
+size_t select_scratch_bytes(int n);
+hipError_t launch_fill_u8(uint8_t *p, uint8_t v, int n, hipStream_t st);
+hipError_t launch_select_lowest(const float *ce, int n, int k, uint8_t *mask, uint32_t *idx, void *scratch,
+                                hipStream_t st);
+hipError_t launch_weighted_scale(const float *log_scales, const uint32_t *hits, int n, int V, float thr,
+                                 float gamma, float *ws, float *d_log_scales, int accumulate, hipStream_t st);
+
 // losses
 hipError_t launch_l1_grad(const float *image, const float *target, uint64_t n, float scale,
                           float *dL_dimage, float *loss, hipStream_t st);

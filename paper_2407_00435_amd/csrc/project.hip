@@ -252,6 +252,11 @@ k_project_bwd(const float *__restrict__ means, const float *__restrict__ log_sca
         const gs_splat &sp = splats[e];
         if (sp.radius <= 0) continue;
         const gs_splat_grad &g = grads[e];
+        // a visible splat that no pixel blended (occluded, or outside every
+        // tile's stop point) has an all-zero gradient: nothing to push back
+        if (g.mean_x == 0.f && g.mean_y == 0.f && g.conic_a == 0.f && g.conic_b == 0.f && g.conic_c == 0.f &&
+            g.opacity == 0.f && g.r == 0.f && g.g == 0.f && g.b == 0.f)
+            continue;
         CamF c = load_cam(cams, v);
         float ux = c.R[0] * mx + c.R[1] * my + c.R[2] * mz + c.t[0];
         float uy = c.R[3] * mx + c.R[4] * my + c.R[5] * mz + c.t[1];
