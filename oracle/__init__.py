@@ -304,3 +304,81 @@ def weighted_scale(log_scales, hits, threshold: float, gamma: float = 1.0):
     grad = np.zeros_like(ls)
     grad[np.arange(n), axis] = gamma * G * S / (n * V)
     return ws, grad
+
+
+# ---------------------------------------------------------------------------
+# Reverse of the foveated render (Section 4.1 blending, Section 4.2 filtering
+# and selective multi-versioning), as a composition of the plain reverse.
+
+def level_scene(scene, t: int):
+    """Level t (1-based) of a foveated scene as a plain scene: the points
+    with quality bound m >= t (Section 4.2: a point takes part in level t iff
+    t <= m), with the level's opacity logit and DC colour (the non-DC SH
+    coefficients, position and shape are shared).  Returns (scene_t,
+    indices into the full scene)."""
+    idx = np.nonzero(np.asarray(scene.qbound) >= t)[0]
+    sub = scene.subset(idx)
+    if scene.lvl_opacity_logits is not None:
+        sub.opacity_logits = np.asarray(scene.lvl_opacity_logits[t - 1][idx], dtype=np.float64)
+    sub.sh = np.array(sub.sh, dtype=np.float64)
+    if scene.lvl_sh_dc is not None:
+        sub.sh[:, 0, :] = np.asarray(scene.lvl_sh_dc[t - 1][idx], dtype=np.float64)
+    return sub, idx
+
+
+def level_weights(pix_lo, pix_w, t: int) -> np.ndarray:
+    """Per-pixel weight of level t in the blended image: 1 - w at the pixel's
+    lower level and w at the next one (Section 4.1), 1 at the lower level
+    outside the bands."""
+    lo = np.asarray(pix_lo, dtype=np.int64)
+    w = np.asarray(pix_w, dtype=np.float64)
+    return np.where(lo == t, 1.0 - w, 0.0) + np.where((lo + 1 == t) & (w > 0), w, 0.0)
+
+
+def fr_reverse(scene, cams, tables, dL_dimgs, bg=(0.0, 0.0, 0.0)) -> dict:
+    """Gradients of sum_v <dL_v, I_v> for the foveated images I_v, with
+    tables[v] = (pix_lo [H*W], pix_w [H*W]).  The blended image is
+    sum_t weight_t(p) * (the plain render of level t's scene) at p, so the
+    gradient is the sum over levels of the plain reverse of level t's scene
+    under dL * weight_t, scattered back to the full scene: shared parameters
+    (means, log-scales, quaternions, non-DC SH) sum over levels; opacity
+    logits and DC go to the level versions when the scene has them (else to
+    the base).  Returns the five base arrays plus lvl_opacity_logits and
+    lvl_sh_dc (None when the scene shares the base)."""
+    n, K = scene.n, (scene.sh_degree + 1) ** 2
+    L = int(np.max(scene.qbound))
+    out = dict(means=np.zeros((n, 3)), log_scales=np.zeros((n, 3)), quats=np.zeros((n, 4)),
+               opacity_logits=np.zeros(n), sh=np.zeros((n, K, 3)),
+               lvl_opacity_logits=None if scene.lvl_opacity_logits is None
+               else np.zeros(np.asarray(scene.lvl_opacity_logits).shape),
+               lvl_sh_dc=None if scene.lvl_sh_dc is None else np.zeros(np.asarray(scene.lvl_sh_dc).shape))
+    for t in range(1, L + 1):
+        sub, idx = level_scene(scene, t)
+        if len(idx) == 0:
+            continue
+        dls = []
+        for cam, (lo, w), g in zip(cams, tables, dL_dimgs):
+            wt = level_weights(lo, w, t).reshape(int(cam.height), int(cam.width))
+            dls.append(np.asarray(g, dtype=np.float64) * wt[None])
+        gt = reverse(sub, cams, dls, bg)
+        for k in ("means", "log_scales", "quats"):
+            out[k][idx] += gt[k]
+        out["sh"][idx, 1:, :] += gt["sh"][:, 1:, :]
+        if out["lvl_sh_dc"] is not None:
+            out["lvl_sh_dc"][t - 1][idx] += gt["sh"][:, 0, :]
+        else:
+            out["sh"][idx, 0, :] += gt["sh"][:, 0, :]
+        if out["lvl_opacity_logits"] is not None:
+            out["lvl_opacity_logits"][t - 1][idx] += gt["opacity_logits"]
+        else:
+            out["opacity_logits"][idx] += gt["opacity_logits"]
+    return out
+
+
+def fr_render(scene, cam, pix_lo, pix_w, bg=(0.0, 0.0, 0.0)) -> np.ndarray:
+    """Foveated FP64 render (projection with the level versions, then the
+    per-level compositing and blend); (H, W, 3)."""
+    pr = project(scene, cam, levels=True)
+    out = composite(pr, int(cam.width), int(cam.height), bg=bg, qbound=scene.qbound, pix_lo=pix_lo,
+                    pix_w=np.asarray(pix_w, dtype=np.float64), levels=True, nthreads=1)
+    return out["rgb"]
