@@ -132,8 +132,8 @@ class Foveated:
         B._check(L.gs_rasterize_foveated(B._ptr(g.splats), B._ptr(g.lvl), g.n, B._ptr(g.S.t["qbound"]),
                                          g.L, g.C.hp, g.C.dp, g.C.n, g.tile, B._ptr(g.vals),
                                          B._ptr(g.ranges), B._ptr(g.pix_level), B._ptr(g.pix_weight),
-                                         ctypes.cast(g.bg, B._VP), B._ptr(g.image), B._ptr(stats), g.ws,
-                                         g.wsn, g.stream))
+                                         ctypes.cast(g.bg, B._VP), B._ptr(g.image), B._ptr(stats), None,
+                                         None, g.ws, g.wsn, g.stream))
 
     STAGES = ("fovea", "project", "binsort", "raster")
 

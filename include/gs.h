@@ -239,14 +239,52 @@ int gs_fovea_prep(const gs_camera *cams_host, const gs_camera *cams_dev, const g
  * qbound >= t and their level-t colour and opacity (lvl_rgba from
  * gs_project); output (1 - w) I_lo + w I_(lo+1).  Same cut-offs as
  * gs_rasterize_fwd, applied per level; stats as in gs_rasterize_fwd
- * (blended pairs count each level's blend). */
+ * (blended pairs count each level's blend).  final_T2 (float [n_pixels][2])
+ * and n_contrib2 (uint32 [n_pixels][2]), both nullable and given together,
+ * receive per pixel the final transmittance and the last blended run
+ * position of the two accumulators (levels lo and lo + 1): the start of
+ * gs_rasterize_foveated_bwd. */
 int gs_rasterize_foveated(const gs_splat *splats, const float *lvl_rgba, int32_t n,
                           const uint8_t *qbound, int n_levels, const gs_camera *cams_host,
                           const gs_camera *cams_dev, int n_eyes, int tile_size,
                           const uint32_t *vals, const uint32_t *tile_ranges,
                           const uint8_t *pix_level, const float *pix_weight, const float *bg,
-                          float *image, uint64_t *stats, void *workspace, size_t workspace_bytes,
-                          void *stream);
+                          float *image, uint64_t *stats, float *final_T2, uint32_t *n_contrib2,
+                          void *workspace, size_t workspace_bytes, void *stream);
+
+/* Reverse of gs_rasterize_foveated (the differentiable form of the blend of
+ * Section 4.1 with the per-level opacity and colour of Section 4.2): given
+ * dL/dimage and the forward's final_T2 / n_contrib2, each accumulator is
+ * walked back to front from its last blended splat with dL scaled by its
+ * blend weight.  Outputs (device, overwritten): grads [n_eyes][n]: the
+ * gradient with respect to each splat's mean and conic (summed over the
+ * levels; the opacity and colour fields are zero); lvl_grads [n_eyes][n]
+ * [n_levels][4]: per level, the gradient with respect to its colour (r, g,
+ * b) and opacity.  Decisions (extent, filter, skip, stop, clamp) are held
+ * constant. */
+int gs_rasterize_foveated_bwd(const gs_splat *splats, const float *lvl_rgba, int32_t n,
+                              const uint8_t *qbound, int n_levels, const gs_camera *cams_host,
+                              const gs_camera *cams_dev, int n_eyes, int tile_size,
+                              const uint32_t *vals, const uint32_t *tile_ranges,
+                              const uint8_t *pix_level, const float *pix_weight, const float *bg,
+                              const float *final_T2, const uint32_t *n_contrib2, const float *dL_dimage,
+                              gs_splat_grad *grads, float *lvl_grads, void *stream);
+
+/* Reverse of gs_project with the level versions (Section 4.2): from grads
+ * and lvl_grads of gs_rasterize_foveated_bwd to the scene parameters,
+ * summed over the eyes.  Level t's colour is max(0, DC_t Y_0 + sum_{k>=1}
+ * sh_k Y_k + 1/2) and its opacity sigmoid(lvl_opacity_logits[t]): the level
+ * DC and logit gradients go to d_lvl_sh_dc [n_levels][n][3] and
+ * d_lvl_opacity_logits [n_levels][n] (or, when the scene shares the base
+ * parameters, to the base DC and logit), the non-DC SH, position and shape
+ * gradients sum over the levels.  Outputs as in gs_project_bwd, plus the two
+ * level arrays (nullable when the scene has no level versions);
+ * accumulate = 1 adds to the outputs. */
+int gs_project_bwd_levels(const gs_scene *scene, const gs_camera *cams_host, const gs_camera *cams_dev,
+                          int n_views, const gs_splat *splats, const gs_splat_grad *grads,
+                          const float *lvl_grads, float *d_means, float *d_log_scales, float *d_quats,
+                          float *d_opacity_logits, float *d_sh, float *d_lvl_opacity_logits,
+                          float *d_lvl_sh_dc, int accumulate, void *stream);
 
 /* One-call foveated render of n_eyes views: fovea tables, projection with
  * per-level versions, filtered binning and sort, foveated compositing.

@@ -11,5 +11,6 @@ from .binding import (  # noqa: F401
     gs_fovea_prep, gs_rasterize_foveated, gs_render_foveated, gs_render_fwd,
     gs_workspace_bytes, gs_render_workspace_bytes, gs_tile_count, splat_fields, gs_sort_pairs, gs_set_tuning,
     gs_l1_grad, gs_ce_score, gs_select_lowest, gs_weighted_scale, Graph,
+    gs_rasterize_foveated_bwd, gs_project_bwd_levels,
 )
-from .render import GaussianRender, render  # noqa: F401
+from .render import GaussianRender, render, FoveatedRender, render_foveated  # noqa: F401

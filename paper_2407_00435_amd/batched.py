@@ -3,7 +3,10 @@
 One training step over a fixed camera set: projection, binning/sort and
 compositing of every view, the L1 loss against per-view targets, the
 compositing reverse and the projection reverse (gradients summed over
-views), plus the foveated forward of the two eyes.  Views are processed in
+views), plus the foveated eyes: forward only, or, given eye targets, forward,
+L1 loss and the foveated reverse into the base and per-level parameters
+(the loss is the mean over the views' pixels plus the mean over the eyes'
+pixels).  Views are processed in
 sub-batches of ``batch_views`` consecutive views; within a sub-batch every
 stage is one library call over all its views (each Gaussian is read once
 for all of them, one global tile space, one sort, one compositing launch
@@ -29,12 +32,12 @@ class BatchedStep:
     def __init__(self, scene: B.SceneTensors, cams: list, target: torch.Tensor, tile_size: int = 16,
                  batch_views: int | None = None, eyes: list | None = None, foveae: list | None = None,
                  key_margin: float = 1.05, stream: torch.cuda.Stream | None = None,
-                 eye_batch: int | None = None):
+                 eye_batch: int | None = None, eye_target: torch.Tensor | None = None):
         dev = scene.t["means"].device
         self.scene, self.tile = scene, tile_size
         self.stream = stream or torch.cuda.Stream(device=dev)
         V = len(cams)
-        bv = V if not batch_views else max(1, min(int(batch_views), V))
+        bv = max(1, V if not batch_views else min(int(batch_views), V))
         self.batch_views = bv
         self.groups = []
         px_off = 0
@@ -71,7 +74,7 @@ class BatchedStep:
         self.dL = torch.empty(3 * self.n_px, **f32)
         self.loss = torch.zeros(1, **f32)
         self.grads = {k: torch.empty_like(scene.t[k]) for k in B.PARAM_NAMES}
-        self.scale = 1.0 / (3 * self.n_px)
+        self.scale = 1.0 / (3 * self.n_px) if self.n_px else 0.0
         self.bg = (ctypes.c_float * 3)(0.0, 0.0, 0.0)
         self.scene_struct = scene.struct(levels=False)
         # foveated eyes (forward), in groups of eye_batch eyes per call
@@ -96,12 +99,76 @@ class BatchedStep:
             self.eye_image = torch.empty(3 * e_off, **f32)
             self.eye_num = torch.zeros(len(self.eye_groups), dtype=torch.int64, device=dev)
             self.eye_struct = scene.struct(levels=True)
+            self.eye_train = eye_target is not None
+            if self.eye_train:
+                if eye_target.numel() != 3 * e_off:
+                    raise ValueError(f"eye target has {eye_target.numel()} floats, the eyes need {3 * e_off}")
+                self.eye_target = eye_target.contiguous()
+                self.eye_dL = torch.empty(3 * e_off, **f32)
+                self.eye_scale = 1.0 / (3 * e_off)
+                L = scene.n_levels
+                eb_max = max(e["C"].n for e in self.eye_groups)
+                e_tiles = max(e["C"].tiles(tile_size)[0] for e in self.eye_groups)
+                e_cap = max(e["cap"] for e in self.eye_groups)
+                e_px_max = max(e["n_px"] for e in self.eye_groups)
+                self.eye_bufs = dict(
+                    pix_level=torch.empty(e_px_max, dtype=torch.uint8, device=dev),
+                    pix_weight=torch.empty(e_px_max, **f32),
+                    tile_level=torch.empty((e_tiles, 2), dtype=torch.uint8, device=dev),
+                    splats=torch.empty((eb_max, n, 12), **f32), lvl=torch.empty((eb_max, n, L, 4), **f32),
+                    vals=torch.empty(e_cap, **i32), ranges=torch.empty((e_tiles, 2), **i32),
+                    fT2=torch.empty((e_px_max, 2), **f32), nc2=torch.empty((e_px_max, 2), **i32),
+                    grads=torch.empty((eb_max, n, 12), **f32), lvl_grads=torch.empty((eb_max, n, L, 4), **f32))
+                self.eye_bin_ws = B._ws(max(B.gs_workspace_bytes(e["C"], n, tile_size, e["cap"])
+                                            for e in self.eye_groups))
+                for k in ("lvl_opacity_logits", "lvl_sh_dc"):
+                    self.grads[k] = torch.empty_like(scene.t[k]) if scene.t.get(k) is not None else None
+        else:
+            self.eye_train = False
         self.graph = None
 
     def _enqueue(self):
         L, g = B.lib(), self
         st = ctypes.c_void_p(self.stream.cuda_stream)
         P = B._ptr
+        gr = g.grads
+        first = True  # the first gradient writer overwrites, the others add
+        if self.eye_train:
+            # eyes first: their reverse is the only writer of the level arrays
+            eb = self.eye_bufs
+            nl = g.scene.n_levels
+            for k, e in enumerate(self.eye_groups):
+                C, o, npx = e["C"], e["px_off"], e["n_px"]
+                img = self.eye_image[3 * o:3 * (o + npx)]
+                dL = self.eye_dL[3 * o:3 * (o + npx)]
+                tg = self.eye_target[3 * o:3 * (o + npx)]
+                B._check(L.gs_fovea_prep(C.hp, C.dp, ctypes.cast(e["fov"], B._PF), C.n, g.tile, nl,
+                                         P(eb["pix_level"]), P(eb["pix_weight"]), P(eb["tile_level"]), st))
+                B._check(L.gs_project(ctypes.byref(self.eye_struct), C.hp, C.dp, C.n, g.tile, P(eb["splats"]),
+                                      P(eb["lvl"]), st))
+                B._check(L.gs_bin_sort(P(eb["splats"]), g.scene.n, C.hp, C.dp, C.n, g.tile, P(eb["tile_level"]),
+                                       P(g.scene.t["qbound"]), P(eb["vals"]), None, e["cap"], P(eb["ranges"]),
+                                       None, P(self.eye_num[k:k + 1]), self.eye_bin_ws[1], self.eye_bin_ws[2],
+                                       st))
+                B._check(L.gs_rasterize_foveated(P(eb["splats"]), P(eb["lvl"]), g.scene.n, P(g.scene.t["qbound"]),
+                                                 nl, C.hp, C.dp, C.n, g.tile, P(eb["vals"]), P(eb["ranges"]),
+                                                 P(eb["pix_level"]), P(eb["pix_weight"]),
+                                                 ctypes.cast(g.bg, B._VP), P(img), None, P(eb["fT2"]),
+                                                 P(eb["nc2"]), None, 0, st))
+                B._check(L.gs_l1_grad(P(img), P(tg), 3 * npx, ctypes.c_float(self.eye_scale), P(dL), P(g.loss),
+                                      1 if first else 0, st))
+                B._check(L.gs_rasterize_foveated_bwd(P(eb["splats"]), P(eb["lvl"]), g.scene.n,
+                                                     P(g.scene.t["qbound"]), nl, C.hp, C.dp, C.n, g.tile,
+                                                     P(eb["vals"]), P(eb["ranges"]), P(eb["pix_level"]),
+                                                     P(eb["pix_weight"]), ctypes.cast(g.bg, B._VP), P(eb["fT2"]),
+                                                     P(eb["nc2"]), P(dL), P(eb["grads"]), P(eb["lvl_grads"]), st))
+                B._check(L.gs_project_bwd_levels(ctypes.byref(self.eye_struct), C.hp, C.dp, C.n,
+                                                 P(eb["splats"]), P(eb["grads"]), P(eb["lvl_grads"]),
+                                                 P(gr["means"]), P(gr["log_scales"]), P(gr["quats"]),
+                                                 P(gr["opacity_logits"]), P(gr["sh"]),
+                                                 P(gr.get("lvl_opacity_logits")), P(gr.get("lvl_sh_dc")),
+                                                 0 if first else 1, st))
+                first = False
         for k, grp in enumerate(self.groups):
             C, o, npx = grp["C"], grp["px_off"], grp["n_px"]
             img = self.image[3 * o:3 * (o + npx)]
@@ -114,21 +181,22 @@ class BatchedStep:
                                      grp["cap"], P(g.num_keys[k:k + 1]), P(img), P(fT), P(nc), g.ws, g.wsn,
                                      st))
             B._check(L.gs_l1_grad(P(img), P(tg), 3 * npx, ctypes.c_float(g.scale), P(dL), P(g.loss),
-                                  1 if k == 0 else 0, st))
+                                  1 if first and k == 0 else 0, st))
             B._check(L.gs_rasterize_bwd(P(g.splats), g.scene.n, C.hp, C.dp, C.n, g.tile, P(g.vals),
                                         P(g.ranges), ctypes.cast(g.bg, B._VP), P(fT), P(nc), P(dL),
                                         P(g.sgrads), None, 0, st))
-            gr = g.grads
             B._check(L.gs_project_bwd(ctypes.byref(self.scene_struct), C.hp, C.dp, C.n, P(g.splats),
                                       P(g.sgrads), P(gr["means"]), P(gr["log_scales"]), P(gr["quats"]),
-                                      P(gr["opacity_logits"]), P(gr["sh"]), 1 if k > 0 else 0, st))
-        for k, e in enumerate(self.eye_groups):
-            o, npx = e["px_off"], e["n_px"]
-            B._check(L.gs_render_foveated(ctypes.byref(self.eye_struct), e["C"].hp, e["C"].dp,
-                                          ctypes.cast(e["fov"], B._PF), e["C"].n, g.tile,
-                                          ctypes.cast(g.bg, B._VP), P(self.eye_image[3 * o:3 * (o + npx)]),
-                                          e["cap"], P(self.eye_num[k:k + 1]), self.eye_ws[1], self.eye_ws[2],
-                                          st))
+                                      P(gr["opacity_logits"]), P(gr["sh"]), 0 if first else 1, st))
+            first = False
+        if not self.eye_train:
+            for k, e in enumerate(self.eye_groups):
+                o, npx = e["px_off"], e["n_px"]
+                B._check(L.gs_render_foveated(ctypes.byref(self.eye_struct), e["C"].hp, e["C"].dp,
+                                              ctypes.cast(e["fov"], B._PF), e["C"].n, g.tile,
+                                              ctypes.cast(g.bg, B._VP), P(self.eye_image[3 * o:3 * (o + npx)]),
+                                              e["cap"], P(self.eye_num[k:k + 1]), self.eye_ws[1], self.eye_ws[2],
+                                              st))
 
     def step(self):
         """Run one step eagerly on this object's stream."""

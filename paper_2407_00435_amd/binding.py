@@ -75,7 +75,11 @@ _SIGS = {
     "gs_project_bwd": ([_PS, _PC, _VP, _I, _VP, _VP, _VP, _VP, _VP, _VP, _VP, _I, _VP], _I),
     "gs_fovea_prep": ([_PC, _VP, _PF, _I, _I, _I, _VP, _VP, _VP, _VP], _I),
     "gs_rasterize_foveated": ([_VP, _VP, _I32, _VP, _I, _PC, _VP, _I, _I, _VP, _VP, _VP, _VP, _VP,
-                               _VP, _VP, _VP, _SZ, _VP], _I),
+                               _VP, _VP, _VP, _VP, _VP, _SZ, _VP], _I),
+    "gs_rasterize_foveated_bwd": ([_VP, _VP, _I32, _VP, _I, _PC, _VP, _I, _I, _VP, _VP, _VP, _VP, _VP,
+                                   _VP, _VP, _VP, _VP, _VP, _VP], _I),
+    "gs_project_bwd_levels": ([_PS, _PC, _VP, _I, _VP, _VP, _VP, _VP, _VP, _VP, _VP, _VP, _VP, _VP, _I,
+                               _VP], _I),
     "gs_render_foveated": ([_PS, _PC, _VP, _PF, _I, _I, _VP, _VP, _U64, _VP, _VP, _SZ, _VP], _I),
     "gs_render_fwd": ([_PS, _PC, _VP, _I, _I, _VP, _VP, _VP, _VP, _U64, _VP, _VP, _VP, _VP, _VP, _SZ,
                        _VP], _I),
@@ -429,17 +433,56 @@ def gs_fovea_prep(cams: Cameras, foveae, tile_size: int = 16, n_levels: int = 4)
 
 def gs_rasterize_foveated(splats, lvl_rgba, n, qbound, n_levels, cams: Cameras, tile_size, vals,
                           ranges, pix_level, pix_weight, bg=(0.0, 0.0, 0.0), stats=None, image=None,
-                          workspace=None):
+                          workspace=None, keep=None):
+    """Foveated compositing; returns the image.  ``keep`` = (final_T2, n_contrib2)
+    tensors ([n_pixels, 2] float32 / int32) receive the reverse pass's start."""
     _, n_px = cams.tiles(tile_size)
     if image is None:
         image = torch.empty(3 * n_px, dtype=torch.float32, device=splats.device)
     bgc = (ctypes.c_float * 3)(*bg)
     ws, wsn = (workspace[1], workspace[2]) if workspace is not None else (None, 0)
+    fT2, nc2 = keep if keep is not None else (None, None)
     _check(lib().gs_rasterize_foveated(_ptr(splats), _ptr(lvl_rgba), n, _ptr(qbound), n_levels, cams.hp,
                                        cams.dp, cams.n, tile_size, _ptr(vals), _ptr(ranges),
                                        _ptr(pix_level), _ptr(pix_weight), ctypes.cast(bgc, _VP),
-                                       _ptr(image), _ptr(stats), ws, wsn, _stream()))
+                                       _ptr(image), _ptr(stats), _ptr(fT2), _ptr(nc2), ws, wsn, _stream()))
     return image
+
+
+def gs_rasterize_foveated_bwd(splats, lvl_rgba, n, qbound, n_levels, cams: Cameras, tile_size, vals, ranges,
+                              pix_level, pix_weight, final_T2, n_contrib2, dL_dimage, bg=(0.0, 0.0, 0.0)):
+    """Reverse of the foveated compositing: (grads [V, n, 12], lvl_grads [V, n, L, 4])."""
+    dev = splats.device
+    grads = torch.empty((cams.n, n, 12), dtype=torch.float32, device=dev)
+    lvl_grads = torch.empty((cams.n, n, n_levels, 4), dtype=torch.float32, device=dev)
+    bgc = (ctypes.c_float * 3)(*bg)
+    _check(lib().gs_rasterize_foveated_bwd(_ptr(splats), _ptr(lvl_rgba), n, _ptr(qbound), n_levels, cams.hp,
+                                           cams.dp, cams.n, tile_size, _ptr(vals), _ptr(ranges), _ptr(pix_level),
+                                           _ptr(pix_weight), ctypes.cast(bgc, _VP), _ptr(final_T2),
+                                           _ptr(n_contrib2), _ptr(dL_dimage.contiguous()), _ptr(grads),
+                                           _ptr(lvl_grads), _stream()))
+    return grads, lvl_grads
+
+
+LEVEL_PARAM_NAMES = PARAM_NAMES + ("lvl_opacity_logits", "lvl_sh_dc")
+
+
+def gs_project_bwd_levels(scene: SceneTensors, cams: Cameras, splats, grads, lvl_grads, out=None,
+                          accumulate=False):
+    """Parameter gradients of the foveated render (base arrays plus the level
+    versions present in the scene), summed over the eyes."""
+    t = scene.t
+    if out is None:
+        out = {k: torch.empty_like(t[k]) for k in PARAM_NAMES}
+        for k in ("lvl_opacity_logits", "lvl_sh_dc"):
+            out[k] = torch.empty_like(t[k]) if t.get(k) is not None else None
+    st = scene.struct(levels=True)
+    _check(lib().gs_project_bwd_levels(ctypes.byref(st), cams.hp, cams.dp, cams.n, _ptr(splats), _ptr(grads),
+                                       _ptr(lvl_grads), _ptr(out["means"]), _ptr(out["log_scales"]),
+                                       _ptr(out["quats"]), _ptr(out["opacity_logits"]), _ptr(out["sh"]),
+                                       _ptr(out.get("lvl_opacity_logits")), _ptr(out.get("lvl_sh_dc")),
+                                       int(bool(accumulate)), _stream()))
+    return out
 
 
 def gs_render_foveated(scene: SceneTensors, cams: Cameras, foveae, tile_size: int = 16,

@@ -418,7 +418,8 @@ int gs_rasterize_foveated(const gs_splat *splats, const float *lvl_rgba, int32_t
                           const gs_camera *cams_dev, int n_eyes, int tile_size, const uint32_t *vals,
                           const uint32_t *tile_ranges, const uint8_t *pix_level,
                           const float *pix_weight, const float *bg, float *image, uint64_t *stats,
-                          void *workspace, size_t workspace_bytes, void *stream)
+                          float *final_T2, uint32_t *n_contrib2, void *workspace, size_t workspace_bytes,
+                          void *stream)
 {
     int r;
     int64_t tiles = 0;
@@ -434,10 +435,71 @@ int gs_rasterize_foveated(const gs_splat *splats, const float *lvl_rgba, int32_t
     RasterQueueArgs q;
     const bool queued = carve_queue((char *)workspace, workspace_bytes, tiles, tile_size, q);
     const float zero[3] = {0.f, 0.f, 0.f};
+    if ((final_T2 != nullptr) != (n_contrib2 != nullptr))
+        return fail(GS_ERR_INVALID, "final_T2 and n_contrib2 go together");
+    if (!aligned(final_T2, 8) || !aligned(n_contrib2, 8))
+        return fail(GS_ERR_INVALID, "final_T2 and n_contrib2 must be 8-byte aligned");
     hipError_t e = launch_raster_fov(splats, lvl_rgba, n, qbound, n_levels, cams_dev, n_eyes, tile_size,
                                      tiles, vals, tile_ranges, pix_level, pix_weight, bg ? bg : zero,
-                                     image, stats, queued ? &q : nullptr, (hipStream_t)stream);
+                                     image, stats, final_T2, n_contrib2, queued ? &q : nullptr, (hipStream_t)stream);
     if (e != hipSuccess) return hip_fail(e, "gs_rasterize_foveated");
+    return ok();
+}
+
+int gs_rasterize_foveated_bwd(const gs_splat *splats, const float *lvl_rgba, int32_t n, const uint8_t *qbound,
+                              int n_levels, const gs_camera *cams_host, const gs_camera *cams_dev, int n_eyes,
+                              int tile_size, const uint32_t *vals, const uint32_t *tile_ranges,
+                              const uint8_t *pix_level, const float *pix_weight, const float *bg,
+                              const float *final_T2, const uint32_t *n_contrib2, const float *dL_dimage,
+                              gs_splat_grad *grads, float *lvl_grads, void *stream)
+{
+    int r;
+    int64_t tiles = 0;
+    if ((r = check_cams(cams_host, cams_dev, n_eyes, tile_size, &tiles, nullptr))) return r;
+    if (n < 0) return fail(GS_ERR_INVALID, "n must be >= 0");
+    if (n_levels < 1 || n_levels > 4) return fail(GS_ERR_UNSUPPORTED, "n_levels %d not in 1..4", n_levels);
+    if (!tile_ranges || !pix_level || !pix_weight || !final_T2 || !n_contrib2 || !dL_dimage ||
+        (n > 0 && (!splats || !lvl_rgba || !qbound || !vals || !grads || !lvl_grads)))
+        return fail(GS_ERR_INVALID, "NULL output or input pointer");
+    if (!aligned(splats, 16) || !aligned(lvl_rgba, 16) || !aligned(lvl_grads, 16) || !aligned(grads, 16))
+        return fail(GS_ERR_INVALID, "splats, lvl_rgba, grads and lvl_grads must be 16-byte aligned");
+    if (!aligned(final_T2, 8) || !aligned(n_contrib2, 8))
+        return fail(GS_ERR_INVALID, "final_T2 and n_contrib2 must be 8-byte aligned");
+    const float zero[3] = {0.f, 0.f, 0.f};
+    hipError_t e = launch_raster_fov_bwd(splats, lvl_rgba, n, qbound, n_levels, cams_dev, n_eyes, tile_size, tiles,
+                                         vals, tile_ranges, pix_level, pix_weight, bg ? bg : zero, final_T2,
+                                         n_contrib2, dL_dimage, grads, lvl_grads, (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(e, "gs_rasterize_foveated_bwd");
+    return ok();
+}
+
+int gs_project_bwd_levels(const gs_scene *scene, const gs_camera *cams_host, const gs_camera *cams_dev,
+                          int n_views, const gs_splat *splats, const gs_splat_grad *grads, const float *lvl_grads,
+                          float *d_means, float *d_log_scales, float *d_quats, float *d_opacity_logits,
+                          float *d_sh, float *d_lvl_opacity_logits, float *d_lvl_sh_dc, int accumulate,
+                          void *stream)
+{
+    int r;
+    if ((r = check_scene(scene, true))) return r;
+    if ((r = check_cams(cams_host, cams_dev, n_views, 16, nullptr, nullptr))) return r;
+    if (accumulate != 0 && accumulate != 1) return fail(GS_ERR_INVALID, "accumulate must be 0 or 1");
+    if (scene->n_levels < 1 || scene->n_levels > 4)
+        return fail(GS_ERR_UNSUPPORTED, "n_levels %d not in 1..4", scene->n_levels);
+    if (scene->n > 0 && (!splats || !grads || !lvl_grads || !d_means || !d_log_scales || !d_quats ||
+                         !d_opacity_logits || !d_sh))
+        return fail(GS_ERR_INVALID, "NULL output or input pointer");
+    if (scene->lvl_opacity_logits && scene->n > 0 && !d_lvl_opacity_logits)
+        return fail(GS_ERR_INVALID, "the scene has level opacity logits: d_lvl_opacity_logits is needed");
+    if (scene->lvl_sh_dc && scene->n > 0 && !d_lvl_sh_dc)
+        return fail(GS_ERR_INVALID, "the scene has level DC colours: d_lvl_sh_dc is needed");
+    if (!aligned(d_quats, 16) || !aligned(lvl_grads, 16)) return fail(GS_ERR_INVALID, "d_quats and lvl_grads must be 16-byte aligned");
+    if ((scene->sh_degree == 1 || scene->sh_degree == 3) && !aligned(d_sh, 16))
+        return fail(GS_ERR_INVALID, "d_sh must be 16-byte aligned");
+    hipError_t e = launch_project_bwd(*scene, cams_dev, n_views, splats, grads, d_means, d_log_scales, d_quats,
+                                      d_opacity_logits, d_sh, accumulate, (hipStream_t)stream, lvl_grads,
+                                      scene->lvl_opacity_logits ? d_lvl_opacity_logits : nullptr,
+                                      scene->lvl_sh_dc ? d_lvl_sh_dc : nullptr);
+    if (e != hipSuccess) return hip_fail(e, "gs_project_bwd_levels");
     return ok();
 }
 
@@ -483,7 +545,7 @@ int gs_render_foveated(const gs_scene *scene, const gs_camera *cams_host, const 
                                     tile_size, q);
     e = launch_raster_fov(rb.splats, rb.lvl, scene->n, scene->qbound, L, cams_dev, n_eyes, tile_size,
                           tiles, rb.vals, rb.ranges, rb.pix_level, rb.pix_weight, bg ? bg : zero, image,
-                          nullptr, queued ? &q : nullptr, st);
+                          nullptr, nullptr, nullptr, queued ? &q : nullptr, st);
     if (e != hipSuccess) return hip_fail(e, "gs_render_foveated (compositing)");
     return ok();
 }

@@ -12,7 +12,8 @@ hipError_t launch_project(const gs_scene &sc, const gs_camera *cams_dev, int V, 
 hipError_t launch_project_bwd(const gs_scene &sc, const gs_camera *cams_dev, int V,
                               const gs_splat *splats, const gs_splat_grad *grads, float *g_means,
                               float *g_ls, float *g_q, float *g_logit, float *g_sh, int accumulate,
-                              hipStream_t st);
+                              hipStream_t st, const float *lvl_grads = nullptr, float *g_lvl_logit = nullptr,
+                              float *g_lvl_dc = nullptr);
 
 // pruning metrics
 hipError_t launch_ce_score(const uint32_t *dominated, const uint32_t *hits, int n, int V, float *ce,
@@ -104,6 +105,12 @@ hipError_t launch_raster_bwd(const gs_splat *splats, int n, const gs_camera *cam
                              int64_t n_tiles, const uint32_t *vals, const uint32_t *ranges,
                              const float bg[3], const float *final_T, const uint32_t *n_contrib,
                              const float *dL_dimage, gs_splat_grad *grads, hipStream_t st);
+hipError_t launch_raster_fov_bwd(const gs_splat *splats, const float *lvl_rgba, int n, const uint8_t *qbound,
+                                 int n_levels, const gs_camera *cams_dev, int V, int T, int64_t n_tiles,
+                                 const uint32_t *vals, const uint32_t *ranges, const uint8_t *pix_level,
+                                 const float *pix_weight, const float bg[3], const float *final_T2,
+                                 const uint32_t *n_contrib2, const float *dL_dimage, gs_splat_grad *grads,
+                                 float *lvl_grads, hipStream_t st);
 hipError_t launch_fovea_prep(const gs_camera *cams_dev, const gs_fovea *fov_host, int n_eyes, int T,
                              int n_levels, int64_t n_pixels, int64_t n_tiles, uint8_t *pix_level,
                              float *pix_weight, uint8_t *tile_level, hipStream_t st);
@@ -111,7 +118,8 @@ hipError_t launch_raster_fov(const gs_splat *splats, const float *lvl_rgba, int 
                              const uint8_t *qbound, int n_levels, const gs_camera *cams_dev, int V,
                              int T, int64_t n_tiles, const uint32_t *vals, const uint32_t *ranges,
                              const uint8_t *pix_level, const float *pix_weight, const float bg[3],
-                             float *image, uint64_t *stats, const RasterQueueArgs *qa, hipStream_t st);
+                             float *image, uint64_t *stats, float *final_T2, uint32_t *n_contrib2,
+                             const RasterQueueArgs *qa, hipStream_t st);
 
 // utilities
 hipError_t launch_fill_u32(uint32_t *p, uint32_t value, uint64_t count, hipStream_t st);

@@ -203,14 +203,21 @@ k_project(const float *__restrict__ means, const float *__restrict__ log_scales,
 //   J(u) with the clamped tangents, mean2d(u), u = Rc mu + t,
 //   Sigma = (Rq S)(Rq S)^T, Rq of the normalised quaternion,
 //   colour = max(0, sum sh Y(dir) + 1/2), opacity = sigmoid(logit).
-template <int DEG>
+// LEVELS: the splat gradient carries only mean and conic; colour and opacity
+// gradients come per level (lvl_g [V][n][L]: r, g, b, opacity) and go through
+// level t's colour max(0, DC_t Y_0 + sum_{k>=1} sh_k Y_k + 1/2) and opacity
+// sigmoid(logit_t) to the level DC / logit (or the base ones when the scene
+// shares them), the non-DC SH and the direction.
+template <int DEG, bool LEVELS>
 __global__ void __launch_bounds__(256)
 k_project_bwd(const float *__restrict__ means, const float *__restrict__ log_scales,
               const float *__restrict__ quats, const float *__restrict__ logits,
               const float *__restrict__ sh, const gs_camera *__restrict__ cams, int V, int n,
               const gs_splat *__restrict__ splats, const gs_splat_grad *__restrict__ grads,
               float *__restrict__ g_means, float *__restrict__ g_ls, float *__restrict__ g_q,
-              float *__restrict__ g_logit, float *__restrict__ g_sh, int acc)
+              float *__restrict__ g_logit, float *__restrict__ g_sh, int acc,
+              const float *__restrict__ lvl_logits, const float *__restrict__ lvl_dc, int L,
+              const float4 *__restrict__ lvl_g, float *__restrict__ g_lvl_logit, float *__restrict__ g_lvl_dc)
 {
     constexpr int K = (DEG + 1) * (DEG + 1);
     int i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -237,6 +244,25 @@ k_project_bwd(const float *__restrict__ means, const float *__restrict__ log_sca
     float coef[K * 3];
     load_sh<DEG>(sh, i, coef);
     float opacity = sigmoidf(logits[i]);
+    // level versions (LEVELS only)
+    constexpr int ML = LEVELS ? 4 : 1;
+    float lvl_op[ML], lvl_dcv[ML][3], g_lop[ML], g_ldc[ML][3];
+#pragma unroll
+    for (int t = 0; t < ML; ++t) {
+        lvl_op[t] = opacity;
+        g_lop[t] = 0.f;
+#pragma unroll
+        for (int ch = 0; ch < 3; ++ch) {
+            lvl_dcv[t][ch] = coef[ch];
+            g_ldc[t][ch] = 0.f;
+        }
+        if (LEVELS && t < L) {
+            if (lvl_logits) lvl_op[t] = sigmoidf(lvl_logits[(int64_t)t * n + i]);
+            if (lvl_dc)
+#pragma unroll
+                for (int ch = 0; ch < 3; ++ch) lvl_dcv[t][ch] = lvl_dc[((int64_t)t * n + i) * 3 + ch];
+        }
+    }
 
     float gm[3] = {0.f, 0.f, 0.f};
     float dSig[9];
@@ -254,38 +280,72 @@ k_project_bwd(const float *__restrict__ means, const float *__restrict__ log_sca
         const gs_splat_grad &g = grads[e];
         // a visible splat that no pixel blended (occluded, or outside every
         // tile's stop point) has an all-zero gradient: nothing to push back
-        if (g.mean_x == 0.f && g.mean_y == 0.f && g.conic_a == 0.f && g.conic_b == 0.f && g.conic_c == 0.f &&
-            g.opacity == 0.f && g.r == 0.f && g.g == 0.f && g.b == 0.f)
-            continue;
+        bool zero = g.mean_x == 0.f && g.mean_y == 0.f && g.conic_a == 0.f && g.conic_b == 0.f &&
+                    g.conic_c == 0.f && g.opacity == 0.f && g.r == 0.f && g.g == 0.f && g.b == 0.f;
+        float4 lg[ML];
+#pragma unroll
+        for (int t = 0; t < ML; ++t) {
+            lg[t] = make_float4(0.f, 0.f, 0.f, 0.f);
+            if (LEVELS && t < L) {
+                lg[t] = lvl_g[e * L + t];
+                zero = zero && lg[t].x == 0.f && lg[t].y == 0.f && lg[t].z == 0.f && lg[t].w == 0.f;
+            }
+        }
+        if (zero) continue;
         CamF c = load_cam(cams, v);
         float ux = c.R[0] * mx + c.R[1] * my + c.R[2] * mz + c.t[0];
         float uy = c.R[3] * mx + c.R[4] * my + c.R[5] * mz + c.t[1];
         float uz = c.R[6] * mx + c.R[7] * my + c.R[8] * mz + c.t[2];
         // opacity
-        glogit += g.opacity * opacity * (1.0f - opacity);
+        if (!LEVELS) {
+            glogit += g.opacity * opacity * (1.0f - opacity);
+        } else {
+#pragma unroll
+            for (int t = 0; t < ML; ++t)
+                if (t < L) {
+                    const float d = lg[t].w * lvl_op[t] * (1.0f - lvl_op[t]);
+                    if (lvl_logits)
+                        g_lop[t] += d;
+                    else
+                        glogit += d;
+                }
+        }
         // colour -> SH coefficients and direction
         float ddx = mx - c.pos[0], ddy = my - c.pos[1], ddz = mz - c.pos[2];
         float dist_inv = rsqrtf(ddx * ddx + ddy * ddy + ddz * ddz);
         float dx = ddx * dist_inv, dy = ddy * dist_inv, dz = ddz * dist_inv;
         float Y[K];
         sh_basis<DEG>(dx, dy, dz, Y);
-        float gc[3] = {g.r, g.g, g.b};
         float gdir[3] = {0.f, 0.f, 0.f};
         float Yx[K], Yy[K], Yz[K];
         if (DEG > 0) sh_basis_grad<DEG>(dx, dy, dz, Yx, Yy, Yz);
 #pragma unroll
-        for (int ch = 0; ch < 3; ++ch) {
-            float raw = 0.5f;
+        for (int t = 0; t < ML; ++t) {
+            if (LEVELS && t >= L) continue;
+            const float gc[3] = {LEVELS ? lg[t].x : g.r, LEVELS ? lg[t].y : g.g, LEVELS ? lg[t].z : g.b};
 #pragma unroll
-            for (int k = 0; k < K; ++k) raw += coef[3 * k + ch] * Y[k];
-            if (!(raw > 0.0f)) continue;
+            for (int ch = 0; ch < 3; ++ch) {
+                const float dc = LEVELS ? lvl_dcv[t][ch] : coef[ch];
+                float raw = 0.5f + dc * Y[0];
 #pragma unroll
-            for (int k = 0; k < K; ++k) {
-                gsh[3 * k + ch] += gc[ch] * Y[k];
+                for (int k = 1; k < K; ++k) raw += coef[3 * k + ch] * Y[k];
+                if (!(raw > 0.0f)) continue;
+                if (LEVELS && lvl_dc)
+                    g_ldc[t][ch] += gc[ch] * Y[0];
+                else
+                    gsh[ch] += gc[ch] * Y[0];
+#pragma unroll
+                for (int k = 1; k < K; ++k) gsh[3 * k + ch] += gc[ch] * Y[k];
                 if (DEG > 0) {
-                    gdir[0] += gc[ch] * coef[3 * k + ch] * Yx[k];
-                    gdir[1] += gc[ch] * coef[3 * k + ch] * Yy[k];
-                    gdir[2] += gc[ch] * coef[3 * k + ch] * Yz[k];
+                    gdir[0] += gc[ch] * dc * Yx[0];
+                    gdir[1] += gc[ch] * dc * Yy[0];
+                    gdir[2] += gc[ch] * dc * Yz[0];
+#pragma unroll
+                    for (int k = 1; k < K; ++k) {
+                        gdir[0] += gc[ch] * coef[3 * k + ch] * Yx[k];
+                        gdir[1] += gc[ch] * coef[3 * k + ch] * Yy[k];
+                        gdir[2] += gc[ch] * coef[3 * k + ch] * Yz[k];
+                    }
                 }
             }
         }
@@ -424,6 +484,21 @@ k_project_bwd(const float *__restrict__ means, const float *__restrict__ log_sca
 #pragma unroll
         for (int k = 0; k < K * 3; ++k) gs_out[k] = (acc ? gs_out[k] : 0.f) + gsh[k];
     }
+    if (LEVELS) {
+#pragma unroll
+        for (int t = 0; t < ML; ++t) {
+            if (t >= L) continue;
+            if (g_lvl_logit) {
+                float *p = g_lvl_logit + (int64_t)t * n + i;
+                *p = (acc ? *p : 0.f) + g_lop[t];
+            }
+            if (g_lvl_dc) {
+                float *p = g_lvl_dc + ((int64_t)t * n + i) * 3;
+#pragma unroll
+                for (int ch = 0; ch < 3; ++ch) p[ch] = (acc ? p[ch] : 0.f) + g_ldc[t][ch];
+            }
+        }
+    }
 }
 
 }  // namespace
@@ -459,15 +534,24 @@ hipError_t launch_project(const gs_scene &sc, const gs_camera *cams_dev, int V, 
 hipError_t launch_project_bwd(const gs_scene &sc, const gs_camera *cams_dev, int V,
                               const gs_splat *splats, const gs_splat_grad *grads, float *g_means,
                               float *g_ls, float *g_q, float *g_logit, float *g_sh, int accumulate,
-                              hipStream_t st)
+                              hipStream_t st, const float *lvl_grads, float *g_lvl_logit, float *g_lvl_dc)
 {
     int n = sc.n;
     if (n == 0) return hipSuccess;
     dim3 grid((n + 255) / 256), block(256);
+    const float4 *lg = reinterpret_cast<const float4 *>(lvl_grads);
+    const int L = sc.n_levels;
 #define GS_PB(DEG)                                                                                     \
-    hipLaunchKernelGGL((k_project_bwd<DEG>), grid, block, 0, st, sc.means, sc.log_scales, sc.quats,  \
-                       sc.opacity_logits, sc.sh, cams_dev, V, n, splats, grads, g_means, g_ls, g_q,   \
-                       g_logit, g_sh, accumulate);
+    if (lg)                                                                                            \
+        hipLaunchKernelGGL((k_project_bwd<DEG, true>), grid, block, 0, st, sc.means, sc.log_scales,   \
+                           sc.quats, sc.opacity_logits, sc.sh, cams_dev, V, n, splats, grads, g_means, \
+                           g_ls, g_q, g_logit, g_sh, accumulate, sc.lvl_opacity_logits, sc.lvl_sh_dc, L, \
+                           lg, g_lvl_logit, g_lvl_dc);                                                \
+    else                                                                                               \
+        hipLaunchKernelGGL((k_project_bwd<DEG, false>), grid, block, 0, st, sc.means, sc.log_scales,  \
+                           sc.quats, sc.opacity_logits, sc.sh, cams_dev, V, n, splats, grads, g_means, \
+                           g_ls, g_q, g_logit, g_sh, accumulate, nullptr, nullptr, 0, nullptr, nullptr, \
+                           nullptr);
     switch (sc.sh_degree) {
     case 0: GS_PB(0); break;
     case 1: GS_PB(1); break;

@@ -304,6 +304,7 @@ __device__ __forceinline__ FovPix fov_pix(const WaveCtx &w, const uint8_t *__res
 
 struct FovState {
     float Ta, A0, A1, A2, Tb, B0, B1, B2;
+    uint32_t last_a, last_b;  // 1-based run position of the last blended splat (kept on request)
     bool done_a, done_b;
 };
 
@@ -312,12 +313,13 @@ __device__ __forceinline__ FovState fov_init(bool inside, bool two)
     FovState s;
     s.Ta = s.Tb = 1.0f;
     s.A0 = s.A1 = s.A2 = s.B0 = s.B1 = s.B2 = 0.0f;
+    s.last_a = s.last_b = 0u;
     s.done_a = !inside;
     s.done_b = !inside || !two;
     return s;
 }
 
-template <bool STATS>
+template <bool STATS, bool KEEP = false>
 __device__ __forceinline__ void fov_walk(const gs_splat *__restrict__ splats, const float4 *__restrict__ lvl,
                                          int n, const uint8_t *__restrict__ qbound, int L,
                                          const uint32_t *__restrict__ vals, const WaveCtx &w, const FovPix &f,
@@ -341,7 +343,7 @@ __device__ __forceinline__ void fov_walk(const gs_splat *__restrict__ splats, co
             const float4 *s4 = reinterpret_cast<const float4 *>(splats + vbase + id);
             const float4 s0 = s4[0], s1 = s4[1];
             rec.a = make_float4(s0.x, s0.y, NEG_HALF_LOG2E * s0.z, -GS_LOG2E * s0.w);
-            rec.b = make_float4(NEG_HALF_LOG2E * s1.x, 0.0f, __int_as_float(m), 0.0f);
+            rec.b = make_float4(NEG_HALF_LOG2E * s1.x, 0.0f, __int_as_float(m), __uint_as_float(idx - w.start + 1));
             const float4 *lp = lvl + (vbase + id) * L;
 #pragma unroll
             for (int t = 0; t < MAXL; ++t)
@@ -377,6 +379,7 @@ __device__ __forceinline__ void fov_walk(const gs_splat *__restrict__ splats, co
                 s.A1 = fmaf(wt, lv.y, s.A1);
                 s.A2 = fmaf(wt, lv.z, s.A2);
                 s.Ta = blend ? Tn : s.Ta;
+                if (KEEP) s.last_a = blend ? __float_as_uint(bb.w) : s.last_a;
                 s.done_a = s.done_a || stop;
                 if (STATS) st[0] += blend ? 1.0f : 0.0f;
             }
@@ -392,6 +395,7 @@ __device__ __forceinline__ void fov_walk(const gs_splat *__restrict__ splats, co
                 s.B1 = fmaf(wt, lv.y, s.B1);
                 s.B2 = fmaf(wt, lv.z, s.B2);
                 s.Tb = blend ? Tn : s.Tb;
+                if (KEEP) s.last_b = blend ? __float_as_uint(bb.w) : s.last_b;
                 s.done_b = s.done_b || stop;
                 if (STATS) st[0] += blend ? 1.0f : 0.0f;
             }
@@ -409,23 +413,28 @@ __device__ __forceinline__ void fov_finish(const WaveCtx &w, const FovPix &f, co
     float *img = image + 3 * w.vi.pix_off + (int64_t)w.py * w.vi.W + w.px;
     float ra = fmaf(s.Ta, bg0, s.A0), ga = fmaf(s.Ta, bg1, s.A1), ba = fmaf(s.Ta, bg2, s.A2);
     if (f.two) {
-        float rb = fmaf(s.Tb, bg0, s.B0), gb = fmaf(s.Tb, bg1, s.B1), bb = fmaf(s.Tb, bg2, s.B2);
-        ra = (1.0f - f.wup) * ra + f.wup * rb;
-        ga = (1.0f - f.wup) * ga + f.wup * gb;
-        ba = (1.0f - f.wup) * ba + f.wup * bb;
+        // written out with fmaf so that every kernel sharing this epilogue
+        // rounds the blend identically (left to contraction, the compiler
+        // fuses a different product in different kernels)
+        const float rb = fmaf(s.Tb, bg0, s.B0), gb = fmaf(s.Tb, bg1, s.B1), bb = fmaf(s.Tb, bg2, s.B2);
+        const float wl = 1.0f - f.wup;
+        ra = fmaf(f.wup, rb, wl * ra);
+        ga = fmaf(f.wup, gb, wl * ga);
+        ba = fmaf(f.wup, bb, wl * ba);
     }
     img[0] = ra;
     img[plane] = ga;
     img[2 * plane] = ba;
 }
 
-template <int T, bool STATS>
+template <int T, bool STATS, bool KEEP>
 __global__ void __launch_bounds__(T *T)
 k_raster_fov(const gs_splat *__restrict__ splats, const float4 *__restrict__ lvl, int n,
              const uint8_t *__restrict__ qbound, int L, const gs_camera *__restrict__ cams, int V,
              const uint32_t *__restrict__ vals, const uint32_t *__restrict__ ranges,
              const uint8_t *__restrict__ pix_level, const float *__restrict__ pix_weight, float bg0,
-             float bg1, float bg2, float *__restrict__ image, unsigned long long *__restrict__ stats)
+             float bg1, float bg2, float *__restrict__ image, unsigned long long *__restrict__ stats,
+             float2 *__restrict__ final_T2, uint2 *__restrict__ n_contrib2)
 {
     float st[4] = {0.f, 0.f, 0.f, 0.f};
     constexpr int WAVES = T * T / 64;
@@ -434,8 +443,14 @@ k_raster_fov(const gs_splat *__restrict__ splats, const float4 *__restrict__ lvl
     const WaveCtx w = wave_ctx<T>(cams, V, blockIdx.x, wave, lane, ranges);
     const FovPix f = fov_pix(w, pix_level, pix_weight);
     FovState s = fov_init(w.inside, f.two);
-    fov_walk<STATS>(splats, lvl, n, qbound, L, vals, w, f, w.start, w.end, s_rec[wave], s, st);
+    fov_walk<STATS, KEEP>(splats, lvl, n, qbound, L, vals, w, f, w.start, w.end, s_rec[wave], s, st);
     fov_finish(w, f, s, bg0, bg1, bg2, image);
+    if (KEEP && w.inside) {
+        // the reverse pass starts from these: per accumulator, the final T and
+        // the last blended position
+        final_T2[w.pix] = make_float2(s.Ta, s.Tb);
+        n_contrib2[w.pix] = make_uint2(s.last_a, s.last_b);
+    }
     if (STATS) stats_add(stats, st[0], st[1], st[2], st[3]);
 }
 
@@ -934,6 +949,237 @@ k_raster_bwd(const gs_splat *__restrict__ splats, int n, const gs_camera *__rest
 }
 
 // ---------------------------------------------------------------------------
+// Reverse of the foveated compositing.  Per pixel, each accumulator (level lo
+// with weight 1 - w, level lo + 1 with weight w in a band) is walked back to
+// front from its last blended splat exactly as the plain reverse, with that
+// level's opacity and colour and the level filter.  Gradients with respect to
+// mean and conic are summed over the levels; colour and opacity gradients
+// are kept per level.  The tile's waves walk the list in chunks of 64
+// positions together and sum per splat in LDS before one atomic per quantity.
+struct FovBwdRec {
+    float4 a, b;      // mean x, mean y, qa, qb | qc, 0, quality bound, position
+    float4 raw;       // conic A, B, C, unused
+    float4 lv[MAXL];  // per level r, g, b, opacity
+};
+
+template <int T>
+__global__ void __launch_bounds__(T *T)
+k_raster_fov_bwd(const gs_splat *__restrict__ splats, const float4 *__restrict__ lvl, int n,
+                 const uint8_t *__restrict__ qbound, int L, const gs_camera *__restrict__ cams, int V,
+                 const uint32_t *__restrict__ vals, const uint32_t *__restrict__ ranges,
+                 const uint8_t *__restrict__ pix_level, const float *__restrict__ pix_weight, float bg0,
+                 float bg1, float bg2, const float2 *__restrict__ final_T2, const uint2 *__restrict__ n_contrib2,
+                 const float *__restrict__ dL_dimage, gs_splat_grad *__restrict__ grads,
+                 float4 *__restrict__ lvl_grads)
+{
+    constexpr int WAVES = T * T / 64;
+    constexpr int NG = 5 + 4 * MAXL;  // mean x, y, conic A, B, C; per level r, g, b, opacity
+    __shared__ FovBwdRec s_rec[WAVES][64];
+    __shared__ float s_grad[NG][64];
+    __shared__ uint32_t s_id[64];
+    __shared__ uint32_t s_maxnc;
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const WaveCtx w = wave_ctx<T>(cams, V, blockIdx.x, wave, lane, ranges);
+    const FovPix f = fov_pix(w, pix_level, pix_weight);
+    const int64_t vbase = (int64_t)w.vi.v * n;
+
+    if (threadIdx.x == 0) s_maxnc = 0;
+    for (int q = threadIdx.x; q < NG * 64; q += T * T) (&s_grad[0][0])[q] = 0.f;
+    uint32_t nca = 0, ncb = 0;
+    float Ta = 1.0f, Tb = 1.0f, g0 = 0.f, g1 = 0.f, g2 = 0.f;
+    if (w.inside) {
+        const float2 ft = final_T2[w.pix];
+        const uint2 nc = n_contrib2[w.pix];
+        Ta = ft.x;
+        Tb = ft.y;
+        nca = nc.x;
+        ncb = f.two ? nc.y : 0u;
+        const int64_t plane = (int64_t)w.vi.W * w.vi.H;
+        const float *gi = dL_dimage + 3 * w.vi.pix_off + (int64_t)w.py * w.vi.W + w.px;
+        g0 = gi[0];
+        g1 = gi[plane];
+        g2 = gi[2 * plane];
+    }
+    const float wa = f.two ? 1.0f - f.wup : 1.0f, wb = f.two ? f.wup : 0.0f;
+    const float ga0 = g0 * wa, ga1 = g1 * wa, ga2 = g2 * wa;
+    const float gb0 = g0 * wb, gb1 = g1 * wb, gb2 = g2 * wb;
+    // light from behind the current splat, starting with the background
+    float Ba0 = Ta * bg0, Ba1 = Ta * bg1, Ba2 = Ta * bg2;
+    float Bb0 = Tb * bg0, Bb1 = Tb * bg1, Bb2 = Tb * bg2;
+    const int lob = f.lo < MAXL ? f.lo : MAXL - 1;  // index of level lo + 1
+    int wave_hi = w.inside ? f.lo + (f.two ? 1 : 0) : 0;
+    uint32_t maxnc = max(nca, ncb);
+    for (int off = 32; off > 0; off >>= 1) {
+        maxnc = max(maxnc, (uint32_t)__shfl_xor((int)maxnc, off));
+        wave_hi = max(wave_hi, __shfl_xor(wave_hi, off));
+    }
+    __syncthreads();
+    if (lane == 0) atomicMax(&s_maxnc, maxnc);
+    __syncthreads();
+    const uint32_t maxnc_tile = s_maxnc;
+
+    for (int64_t p1 = maxnc_tile; p1 >= 1; p1 -= 64) {
+        const int64_t p0 = p1 - 63 >= 1 ? p1 - 63 : 1;
+        if (threadIdx.x < 64) {
+            const int64_t pos = p0 + threadIdx.x;
+            s_id[threadIdx.x] = pos <= p1 ? vals[w.start + (uint32_t)(pos - 1)] : 0u;
+        }
+        if ((uint32_t)p0 <= maxnc) {
+            const int64_t pos = p0 + lane;
+            bool keep = false;
+            // the record is fully defined on every lane before the cull decision
+            FovBwdRec rec;
+            rec.a = rec.b = rec.raw = make_float4(0.f, 0.f, 0.f, 0.f);
+#pragma unroll
+            for (int t = 0; t < MAXL; ++t) rec.lv[t] = make_float4(0.f, 0.f, 0.f, 0.f);
+            if (pos <= p1 && pos <= (int64_t)maxnc) {
+                const uint32_t id = vals[w.start + (uint32_t)(pos - 1)];
+                const int m = qbound[id];
+                const float4 *s4 = reinterpret_cast<const float4 *>(splats + vbase + id);
+                const float4 s0 = s4[0], s1 = s4[1];
+                rec.a = make_float4(s0.x, s0.y, NEG_HALF_LOG2E * s0.z, -GS_LOG2E * s0.w);
+                rec.b = make_float4(NEG_HALF_LOG2E * s1.x, 0.0f, __int_as_float(m), __uint_as_float((uint32_t)pos));
+                rec.raw = make_float4(s0.z, s0.w, s1.x, 0.0f);
+                const float4 *lp = lvl + (vbase + id) * L;
+#pragma unroll
+                for (int t = 0; t < MAXL; ++t)
+                    if (t < L) rec.lv[t] = lp[t];
+                keep = m >= f.wave_lo &&
+                       reaches_rect(s0.x, s0.y, s0.z, s0.w, s1.x, 9.001f, w.rx0, w.rx1, w.ry0, w.ry1);
+            }
+            const uint64_t msk = ballot64(keep);
+            if (keep) s_rec[wave][__popcll(msk & lanemask_lt())] = rec;
+            wave_lds_sync();
+            const int cnt = __popcll(msk);
+            for (int j = cnt - 1; j >= 0; --j) {
+                const float4 a = s_rec[wave][j].a, b = s_rec[wave][j].b;
+                const uint32_t ppos = __float_as_uint(b.w);
+                const int m = __float_as_int(b.z);
+                const float p2 = pair_e2(a, b, w.fpx, w.fpy);
+                const float G = fast_exp2(p2);
+                const bool incl = p2 >= EXTENT_LOG2;
+                const float4 raw = s_rec[wave][j].raw;
+                const float dx = w.fpx - a.x, dy = w.fpy - a.y;
+                float dLdq = 0.f;
+                float ca0 = 0.f, ca1 = 0.f, ca2 = 0.f, cao = 0.f;  // level lo: colour, opacity
+                float cb0 = 0.f, cb1 = 0.f, cb2 = 0.f, cbo = 0.f;  // level lo + 1
+                bool ca = false, cb = false;
+                {
+                    const float4 lv = s_rec[wave][j].lv[f.lo - 1];
+                    const float araw = lv.w * G;
+                    const float alpha = fminf(GS_ALPHA_MAX, araw);
+                    if (ppos <= nca && incl && m >= f.lo && alpha >= GS_ALPHA_MIN) {
+                        ca = true;
+                        const float oma = 1.0f - alpha;
+                        const float ioma = __builtin_amdgcn_rcpf(oma);
+                        Ta = Ta * ioma;
+                        const float wT = alpha * Ta;
+                        ca0 = ga0 * wT;
+                        ca1 = ga1 * wT;
+                        ca2 = ga2 * wT;
+                        const float dLda = ga0 * (lv.x * Ta - Ba0 * ioma) + ga1 * (lv.y * Ta - Ba1 * ioma) +
+                                           ga2 * (lv.z * Ta - Ba2 * ioma);
+                        Ba0 = fmaf(lv.x, wT, Ba0);
+                        Ba1 = fmaf(lv.y, wT, Ba1);
+                        Ba2 = fmaf(lv.z, wT, Ba2);
+                        if (araw <= GS_ALPHA_MAX) {
+                            cao = dLda * G;
+                            dLdq += -0.5f * alpha * dLda;
+                        }
+                    }
+                }
+                if (f.two) {
+                    const float4 lv = s_rec[wave][j].lv[lob];
+                    const float araw = lv.w * G;
+                    const float alpha = fminf(GS_ALPHA_MAX, araw);
+                    if (ppos <= ncb && incl && m >= f.lo + 1 && alpha >= GS_ALPHA_MIN) {
+                        cb = true;
+                        const float oma = 1.0f - alpha;
+                        const float ioma = __builtin_amdgcn_rcpf(oma);
+                        Tb = Tb * ioma;
+                        const float wT = alpha * Tb;
+                        cb0 = gb0 * wT;
+                        cb1 = gb1 * wT;
+                        cb2 = gb2 * wT;
+                        const float dLda = gb0 * (lv.x * Tb - Bb0 * ioma) + gb1 * (lv.y * Tb - Bb1 * ioma) +
+                                           gb2 * (lv.z * Tb - Bb2 * ioma);
+                        Bb0 = fmaf(lv.x, wT, Bb0);
+                        Bb1 = fmaf(lv.y, wT, Bb1);
+                        Bb2 = fmaf(lv.z, wT, Bb2);
+                        if (araw <= GS_ALPHA_MAX) {
+                            cbo = dLda * G;
+                            dLdq += -0.5f * alpha * dLda;
+                        }
+                    }
+                }
+                if (ballot64(ca || cb) == 0) continue;
+                const int q = (int)(ppos - (uint32_t)p0);
+                float gA = dLdq * dx * dx, gB = dLdq * 2.0f * dx * dy, gC = dLdq * dy * dy;
+                float gmx = -2.0f * dLdq * (raw.x * dx + raw.y * dy);
+                float gmy = -2.0f * dLdq * (raw.y * dx + raw.z * dy);
+                gmx = wave_total_63(gmx);
+                gmy = wave_total_63(gmy);
+                gA = wave_total_63(gA);
+                gB = wave_total_63(gB);
+                gC = wave_total_63(gC);
+                if (lane == 63) {
+                    atomicAdd(&s_grad[0][q], gmx);
+                    atomicAdd(&s_grad[1][q], gmy);
+                    atomicAdd(&s_grad[2][q], gA);
+                    atomicAdd(&s_grad[3][q], gB);
+                    atomicAdd(&s_grad[4][q], gC);
+                }
+                // per level: the lanes whose lower level (or next level) it is
+                for (int t = f.wave_lo; t <= wave_hi && t <= MAXL; ++t) {
+                    float v0 = 0.f, v1 = 0.f, v2 = 0.f, v3 = 0.f;
+                    if (ca && f.lo == t) {
+                        v0 += ca0;
+                        v1 += ca1;
+                        v2 += ca2;
+                        v3 += cao;
+                    }
+                    if (cb && f.lo + 1 == t) {
+                        v0 += cb0;
+                        v1 += cb1;
+                        v2 += cb2;
+                        v3 += cbo;
+                    }
+                    if (ballot64(v0 != 0.f || v1 != 0.f || v2 != 0.f || v3 != 0.f) == 0) continue;
+                    v0 = wave_total_63(v0);
+                    v1 = wave_total_63(v1);
+                    v2 = wave_total_63(v2);
+                    v3 = wave_total_63(v3);
+                    if (lane == 63) {
+                        const int k0 = 5 + 4 * (t - 1);
+                        atomicAdd(&s_grad[k0][q], v0);
+                        atomicAdd(&s_grad[k0 + 1][q], v1);
+                        atomicAdd(&s_grad[k0 + 2][q], v2);
+                        atomicAdd(&s_grad[k0 + 3][q], v3);
+                    }
+                }
+            }
+        }
+        __syncthreads();
+        // the tile's sums of this chunk leave with one atomic per quantity
+        for (int qq = threadIdx.x; qq < NG * 64; qq += T * T) {
+            const int k = qq >> 6, jj = qq & 63;
+            const float v = s_grad[k][jj];
+            if (v != 0.f) {
+                const int64_t e = vbase + s_id[jj];
+                if (k < 5) {
+                    atomicAdd(reinterpret_cast<float *>(grads + e) + k, v);
+                } else {
+                    const int t = (k - 5) >> 2, c = (k - 5) & 3;
+                    if (t < L) atomicAdd(reinterpret_cast<float *>(lvl_grads + e * L + t) + c, v);
+                }
+                s_grad[k][jj] = 0.f;
+            }
+        }
+        __syncthreads();
+    }
+}
+
+// ---------------------------------------------------------------------------
 // Foveation tables.
 struct FovArgs {
     gs_fovea f[8];
@@ -1131,6 +1377,34 @@ hipError_t launch_raster_bwd(const gs_splat *splats, int n, const gs_camera *cam
     return hipGetLastError();
 }
 
+hipError_t launch_raster_fov_bwd(const gs_splat *splats, const float *lvl_rgba, int n, const uint8_t *qbound,
+                                 int n_levels, const gs_camera *cams_dev, int V, int T, int64_t n_tiles,
+                                 const uint32_t *vals, const uint32_t *ranges, const uint8_t *pix_level,
+                                 const float *pix_weight, const float bg[3], const float *final_T2,
+                                 const uint32_t *n_contrib2, const float *dL_dimage, gs_splat_grad *grads,
+                                 float *lvl_grads, hipStream_t st)
+{
+    hipError_t e = launch_fill_u32(reinterpret_cast<uint32_t *>(grads), 0u, (uint64_t)V * n * 12, st);
+    if (e != hipSuccess) return e;
+    e = launch_fill_u32(reinterpret_cast<uint32_t *>(lvl_grads), 0u, (uint64_t)V * n * n_levels * 4, st);
+    if (e != hipSuccess || n_tiles == 0) return e;
+    const float4 *lv = reinterpret_cast<const float4 *>(lvl_rgba);
+    const float2 *fT2 = reinterpret_cast<const float2 *>(final_T2);
+    const uint2 *nc2 = reinterpret_cast<const uint2 *>(n_contrib2);
+    float4 *lg = reinterpret_cast<float4 *>(lvl_grads);
+#define GS_FB(TS)                                                                                      \
+    hipLaunchKernelGGL((k_raster_fov_bwd<TS>), dim3((unsigned)n_tiles), dim3(TS * TS), 0, st, splats, lv, n,   \
+                       qbound, n_levels, cams_dev, V, vals, ranges, pix_level, pix_weight, bg[0], bg[1], bg[2], \
+                       fT2, nc2, dL_dimage, grads, lg);
+    switch (T) {
+    case 8: GS_FB(8); break;
+    case 16: GS_FB(16); break;
+    default: GS_FB(32); break;
+    }
+#undef GS_FB
+    return hipGetLastError();
+}
+
 hipError_t launch_fovea_prep(const gs_camera *cams_dev, const gs_fovea *fov_host, int n_eyes, int T,
                              int n_levels, int64_t n_pixels, int64_t n_tiles, uint8_t *pix_level,
                              float *pix_weight, uint8_t *tile_level, hipStream_t st)
@@ -1148,11 +1422,28 @@ hipError_t launch_raster_fov(const gs_splat *splats, const float *lvl_rgba, int 
                              const uint8_t *qbound, int n_levels, const gs_camera *cams_dev, int V,
                              int T, int64_t n_tiles, const uint32_t *vals, const uint32_t *ranges,
                              const uint8_t *pix_level, const float *pix_weight, const float bg[3],
-                             float *image, uint64_t *stats, const RasterQueueArgs *qa, hipStream_t st)
+                             float *image, uint64_t *stats, float *final_T2, uint32_t *n_contrib2,
+                             const RasterQueueArgs *qa, hipStream_t st)
 {
     if (n_tiles == 0) return hipSuccess;
     const float4 *lv = reinterpret_cast<const float4 *>(lvl_rgba);
     unsigned long long *sp = reinterpret_cast<unsigned long long *>(stats);
+    float2 *fT2 = reinterpret_cast<float2 *>(final_T2);
+    uint2 *nc2 = reinterpret_cast<uint2 *>(n_contrib2);
+    if (fT2 && nc2) {
+        // the reverse pass needs per-accumulator state: one workgroup per tile
+#define GS_RK(TS)                                                                                    \
+    hipLaunchKernelGGL((k_raster_fov<TS, false, true>), dim3((unsigned)n_tiles), dim3(TS * TS), 0, st,    \
+                       splats, lv, n, qbound, n_levels, cams_dev, V, vals, ranges, pix_level, pix_weight,  \
+                       bg[0], bg[1], bg[2], image, sp, fT2, nc2);
+        switch (T) {
+        case 8: GS_RK(8); break;
+        case 16: GS_RK(16); break;
+        default: GS_RK(32); break;
+        }
+#undef GS_RK
+        return hipGetLastError();
+    }
     if (qa && !stats) {
         RasterQueue q;
         hipError_t e;
@@ -1175,13 +1466,13 @@ hipError_t launch_raster_fov(const gs_splat *splats, const float *lvl_rgba, int 
     }
 #define GS_RV(TS)                                                                                    \
     if (stats)                                                                                       \
-        hipLaunchKernelGGL((k_raster_fov<TS, true>), dim3((unsigned)n_tiles), dim3(TS * TS), 0, st,   \
+        hipLaunchKernelGGL((k_raster_fov<TS, true, false>), dim3((unsigned)n_tiles), dim3(TS * TS), 0, st, \
                            splats, lv, n, qbound, n_levels, cams_dev, V, vals, ranges, pix_level,    \
-                           pix_weight, bg[0], bg[1], bg[2], image, sp);                              \
+                           pix_weight, bg[0], bg[1], bg[2], image, sp, nullptr, nullptr);            \
     else                                                                                             \
-        hipLaunchKernelGGL((k_raster_fov<TS, false>), dim3((unsigned)n_tiles), dim3(TS * TS), 0, st,  \
+        hipLaunchKernelGGL((k_raster_fov<TS, false, false>), dim3((unsigned)n_tiles), dim3(TS * TS), 0, st, \
                            splats, lv, n, qbound, n_levels, cams_dev, V, vals, ranges, pix_level,    \
-                           pix_weight, bg[0], bg[1], bg[2], image, sp);
+                           pix_weight, bg[0], bg[1], bg[2], image, sp, nullptr, nullptr);
     switch (T) {
     case 8: GS_RV(8); break;
     case 16: GS_RV(16); break;

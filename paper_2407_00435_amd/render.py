@@ -44,3 +44,49 @@ def render(means, log_scales, quats, opacity_logits, sh, cams, sh_degree, tile_s
     (view v occupies 3 * W_v * H_v floats, channel-major)."""
     return GaussianRender.apply(means, log_scales, quats, opacity_logits, sh, cams, sh_degree,
                                 tile_size, tuple(bg), key_capacity)
+
+
+class FoveatedRender(torch.autograd.Function):
+    """Foveated render (Section 4.1 rings and blend, Section 4.2 filter and
+    level versions) with its reverse: gradients for the base parameters and
+    the per-level opacity logits and DC colours."""
+
+    @staticmethod
+    def forward(ctx, means, log_scales, quats, opacity_logits, sh, lvl_opacity_logits, lvl_sh_dc, qbound, cams,
+                foveae, sh_degree, tile_size, bg, key_capacity):
+        scene = B.SceneTensors(means=means.detach(), log_scales=log_scales.detach(), quats=quats.detach(),
+                               opacity_logits=opacity_logits.detach(), sh=sh.detach(), qbound=qbound,
+                               lvl_opacity_logits=lvl_opacity_logits.detach(), lvl_sh_dc=lvl_sh_dc.detach(),
+                               sh_degree=sh_degree)
+        L = scene.n_levels
+        t = B.gs_fovea_prep(cams, foveae, tile_size, L)
+        splats, lvl = B.gs_project(scene, cams, tile_size, levels=True)
+        bs = B.gs_bin_sort(splats, scene.n, cams, tile_size, tile_level=t["tile_level"], qbound=scene.t["qbound"],
+                           key_capacity=key_capacity)
+        _, n_px = cams.tiles(tile_size)
+        fT2 = torch.empty((n_px, 2), dtype=torch.float32, device=means.device)
+        nc2 = torch.empty((n_px, 2), dtype=torch.int32, device=means.device)
+        image = B.gs_rasterize_foveated(splats, lvl, scene.n, scene.t["qbound"], L, cams, tile_size, bs["vals"],
+                                        bs["ranges"], t["pix_level"], t["pix_weight"], bg, keep=(fT2, nc2))
+        ctx.scene, ctx.cams, ctx.tile, ctx.bg, ctx.tables = scene, cams, tile_size, bg, t
+        ctx.save_for_backward(splats, lvl, bs["vals"], bs["ranges"], fT2, nc2)
+        ctx.num_keys = bs["num_keys"]
+        return image
+
+    @staticmethod
+    def backward(ctx, dL_dimage):
+        splats, lvl, vals, ranges, fT2, nc2 = ctx.saved_tensors
+        sc, t = ctx.scene, ctx.tables
+        g, lg = B.gs_rasterize_foveated_bwd(splats, lvl, sc.n, sc.t["qbound"], sc.n_levels, ctx.cams, ctx.tile, vals,
+                                            ranges, t["pix_level"], t["pix_weight"], fT2, nc2,
+                                            dL_dimage.contiguous(), ctx.bg)
+        pg = B.gs_project_bwd_levels(sc, ctx.cams, splats, g, lg)
+        return (pg["means"], pg["log_scales"], pg["quats"], pg["opacity_logits"], pg["sh"],
+                pg["lvl_opacity_logits"], pg["lvl_sh_dc"], None, None, None, None, None, None, None)
+
+
+def render_foveated(means, log_scales, quats, opacity_logits, sh, lvl_opacity_logits, lvl_sh_dc, qbound, cams,
+                    foveae, sh_degree, tile_size=16, bg=(0.0, 0.0, 0.0), key_capacity=None):
+    """Foveated render of the eyes in ``cams`` (planar image buffer)."""
+    return FoveatedRender.apply(means, log_scales, quats, opacity_logits, sh, lvl_opacity_logits, lvl_sh_dc,
+                                qbound, cams, foveae, sh_degree, tile_size, tuple(bg), key_capacity)

@@ -51,7 +51,8 @@ def setup(g, n=3000, seed=21, fr=4):
 def snapshot(step):
     torch.cuda.synchronize()
     out = dict(image=step.image.clone(), final_T=step.final_T.clone(), n_contrib=step.n_contrib.clone(),
-               dL=step.dL.clone(), loss=step.loss.clone(), grads={k: v.clone() for k, v in step.grads.items()})
+               dL=step.dL.clone(), loss=step.loss.clone(),
+               grads={k: v.clone() for k, v in step.grads.items() if v is not None})
     if step.eye_image is not None:
         out["eyes"] = step.eye_image.clone()
     return out
@@ -165,3 +166,55 @@ def test_autotune_small():
     assert_same(snapshot(ref), snapshot(step))
     g.gs_set_tuning("radix_part", 8192)
     g.gs_set_tuning("raster_queue", 0)
+
+
+def eye_target(g, S, eyes, fov, seed=31):
+    C = g.Cameras(eyes)
+    _, n_px = C.tiles(16)
+    rng = np.random.default_rng(seed)
+    return torch.from_numpy(rng.uniform(0.0, 1.0, 3 * n_px).astype(np.float32)).cuda()
+
+
+def test_eye_training_matches_autograd():
+    """Eyes only: the step's foveated forward, L1 loss and reverse give the
+    gradients of the autograd foveated render under the same loss."""
+    g = gs()
+    from paper_2407_00435_amd.batched import BatchedStep
+    sc, S, cams, target, eyes, fov = setup(g, seed=33)
+    et = eye_target(g, S, eyes, fov)
+    step = BatchedStep(S, [], target[:0], 16, None, eyes, fov, eye_target=et)
+    step.step()
+    a = snapshot(step)
+    names = ("means", "log_scales", "quats", "opacity_logits", "sh", "lvl_opacity_logits", "lvl_sh_dc")
+    params = [S.t[k].clone().requires_grad_(True) for k in names]
+    img = g.render_foveated(*params, S.t["qbound"], g.Cameras(eyes), fov, sc.sh_degree, 16)
+    loss = (img - et).abs().mean()
+    loss.backward()
+    torch.cuda.synchronize()
+    assert torch.equal(img.detach(), a["eyes"])
+    assert abs(loss.item() - a["loss"].item()) <= 1e-5 * loss.item()
+    for p, k in zip(params, names):
+        assert rel_l2(p.grad.cpu().numpy(), a["grads"][k].cpu().numpy()) < 1e-5, k
+
+
+@pytest.mark.parametrize("bv", [None, 1])
+def test_views_and_eyes_training_graph(bv):
+    """Views and trained eyes in one step: per-view schedule = batched, and
+    graph replays = eager."""
+    g = gs()
+    from paper_2407_00435_amd.batched import BatchedStep
+    sc, S, cams, target, eyes, fov = setup(g, seed=35)
+    et = eye_target(g, S, eyes, fov, seed=36)
+    ref = BatchedStep(S, cams, target, 16, None, eyes, fov, eye_target=et)
+    ref.step()
+    a = snapshot(ref)
+    step = BatchedStep(S, cams, target, 16, bv, eyes, fov, eye_batch=bv, eye_target=et)
+    step.step()
+    assert_same(a, snapshot(step))
+    step.capture()
+    for _ in range(3):
+        torch.cuda.synchronize()
+        step.replay()
+        assert_same(a, snapshot(step))
+    assert step.keys_ok()
+    step.graph.close()
