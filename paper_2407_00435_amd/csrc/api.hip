@@ -81,13 +81,6 @@ int check_scene(const gs_scene *s, bool levels)
     return GS_OK;
 }
 
-int tile_bits_of(int64_t n_tiles)
-{
-    int b = 0;
-    while ((int64_t(1) << b) < n_tiles) ++b;
-    return b;
-}
-
 // ---------------------------------------------------------------------------
 // Workspace layout (256-byte aligned sub-buffers).
 struct Carve {
@@ -112,20 +105,26 @@ void carve_bin(Carve &c, int V, int64_t E, uint64_t cap, int64_t tiles, BinScrat
     bs.hits = c.take<uint32_t>(4 * E);
     bs.rec = c.take<uint4>(16 * E);
     bs.rec_s = c.take<uint4>(16 * E);
-    bs.hits_s = c.take<uint32_t>(4 * E);
-    bs.hpre = c.take<uint64_t>(8 * E);
-    bs.apre = c.take<uint64_t>(8 * E);
-    bs.slice = c.take<uint32_t>(4 * BIN_MAX_SLICES);
+    bs.cc_s = c.take<uint32_t>(4 * E);
     int64_t nb = (E + SCAN_THREADS * SCAN_ITEMS - 1) / (SCAN_THREADS * SCAN_ITEMS) + 1;
     bs.block_sums = c.take<uint64_t>(8 * nb);
     bs.block_sums2 = c.take<uint64_t>(8 * nb);
     bs.block_vis = c.take<uint32_t>(4 * nb);
     bs.vtab = c.take<int64_t>(16 * (int64_t)V);
+    bs.stab = c.take<int4>(16 * (int64_t)V);
     bs.bbox = c.take<int32_t>(64 * (int64_t)V);
     bs.tkey_a = c.take<uint32_t>(4 * cap);
     bs.tkey_b = c.take<uint32_t>(4 * cap);
     bs.tval_b = c.take<uint32_t>(4 * cap);
-    bs.counts = c.take<uint64_t>(8 * 4);
+    const uint64_t chunks = bin_max_chunks(cap, tiles);
+    bs.st_ranges = c.take<uint32_t>(8 * tiles);
+    bs.st_cls = c.take<uint8_t>(4 * tiles);
+    bs.chunk_off = c.take<uint32_t>(4 * (tiles + 1));
+    bs.chunk_st = c.take<uint32_t>(4 * chunks);
+    bs.ccnt = c.take<uint32_t>(4 * 64 * chunks);
+    bs.tot = c.take<uint32_t>(4 * tiles);
+    bs.tsum = c.take<uint64_t>(8 * (tiles / (SCAN_THREADS * SCAN_ITEMS) + 1));
+    bs.counts = c.take<uint64_t>(8 * 8);
     bs.sat = c.take<uint32_t>(4 * 4 * tiles);
     bs.rs.hist = c.take<uint32_t>(4 * 4 * 256);
     uint64_t big = cap > (uint64_t)E ? cap : (uint64_t)E;
@@ -308,7 +307,7 @@ int gs_bin_sort(const gs_splat *splats, int32_t n, const gs_camera *cams_host,
     c.base = (char *)workspace;
     BinScratch bs;
     carve_bin(c, n_views, E, key_capacity, tiles, bs);
-    hipError_t e = launch_bin_sort(splats, n, cams_dev, cams_host, n_views, tiles, tile_bits_of(tiles),
+    hipError_t e = launch_bin_sort(splats, n, cams_dev, cams_host, n_views, tiles,
                                    tile_size,
                                    tile_level, qbound, 4, vals, keys, key_capacity, tile_ranges,
                                    hits, num_keys, bs, (hipStream_t)stream);
@@ -534,7 +533,7 @@ int gs_render_foveated(const gs_scene *scene, const gs_camera *cams_host, const 
     hipError_t e;
     if ((r = gs_project(scene, cams_host, cams_dev, n_eyes, tile_size, rb.splats, rb.lvl, stream)))
         return r;
-    e = launch_bin_sort(rb.splats, scene->n, cams_dev, cams_host, n_eyes, tiles, tile_bits_of(tiles),
+    e = launch_bin_sort(rb.splats, scene->n, cams_dev, cams_host, n_eyes, tiles,
                         tile_size,
                         rb.tile_level, scene->qbound, L, rb.vals, nullptr, key_capacity, rb.ranges, nullptr,
                         num_keys, bs, st);

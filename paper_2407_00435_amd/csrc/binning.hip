@@ -9,16 +9,12 @@
 //   2. compact the entries that emit at least one key, in index order, and
 //      count their depth digits on the way;
 //   3. sort them by float32 depth bits (stable radix, 4 passes);
-//   4. gather the entry records in depth order, scan their counts and
-//      rectangle areas, and emit each entry's kept tile ids (row-major) at its
-//      offset -- the emitted list is in (depth, view, point) order.  The
-//      emission is load-balanced over the concatenated rectangles (fixed
-//      slices of tiles per wave, coalesced stores), so one huge rectangle
-//      costs no more than many small ones;
-//   5. a stable radix sort on the tile id alone (ceil(log2 tiles) bits)
-//      then yields (tile, depth, view, point) order;
-//   6. tile ranges from the boundaries of the sorted tile ids.
-// Sorting by depth first over the points (millions) and by tile over the
+//   4. gather the entry records in depth order and put the keys in
+//      (tile, depth, view, point) order with a two-level stable counting
+//      sort (super-tiles of 8 x 8 tiles, one wave lane per tile; see
+//      "Tile order" below), which writes every key once at its final
+//      position and yields the tile ranges from per-tile counts.
+// Sorting by depth over the points (millions) and counting per tile over the
 // keys (tens of millions) moves far fewer bytes than a 64-bit key sort.
 #include "common.hpp"
 #include "kernels.hpp"
@@ -26,8 +22,8 @@
 namespace {
 
 constexpr int SAT_LDS_TILES = 16384;      // views up to this many tiles build their tables in LDS (64 KB)
-constexpr uint64_t SLICE_MIN = 1024;       // rectangle tiles per emission task (at least)
-constexpr uint64_t MAX_SLICES = BIN_MAX_SLICES;  // emission tasks (at most)
+constexpr int ST = BIN_SUPER_TILE;        // super-tile side in tiles (ST * ST = wave size)
+constexpr uint32_t CHUNK = BIN_CHUNK;     // coarse pairs per chunk
 
 __global__ void k_set_u64(uint64_t *__restrict__ p, uint64_t value) { *p = value; }
 
@@ -46,17 +42,22 @@ __device__ __forceinline__ int64_t view_tile_off(const gs_camera *__restrict__ c
     return toff;
 }
 
-// Tile offset and grid width of every view: vtab[v] = {first tile, tiles_x}.
-__global__ void __launch_bounds__(256)
-k_view_table(const gs_camera *__restrict__ cams, int V, int T, int64_t *__restrict__ vtab)
+// Tile offset and grid width of every view: vtab[v] = {first tile, tiles_x};
+// stab[v] = {first super-tile, super-tiles per row, tiles_x, tiles_y}.
+__global__ void __launch_bounds__(64)
+k_view_table(const gs_camera *__restrict__ cams, int V, int T, int64_t *__restrict__ vtab, int4 *__restrict__ stab)
 {
     if (threadIdx.x != 0) return;
     int64_t toff = 0;
+    int soff = 0;
     for (int v = 0; v < V; ++v) {
         const int tx = div_up(cams[v].width, T), ty = div_up(cams[v].height, T);
+        const int sx = div_up(tx, ST), sy = div_up(ty, ST);
         vtab[2 * v] = toff;
         vtab[2 * v + 1] = tx;
+        stab[v] = make_int4(soff, sx, tx, ty);
         toff += (int64_t)tx * ty;
+        soff += sx * sy;
     }
 }
 
@@ -195,7 +196,8 @@ k_count(const gs_splat *__restrict__ splats, int n, const gs_camera *__restrict_
 }
 
 // Exclusive scan of nb block values in place (one workgroup); the total goes
-// to *total (and, if given, the keys-needed output with the capacity rule).
+// to *total, or 0 when cap_ptr is given and the total exceeds *cap_ptr (and,
+// if given, the unclamped total to *num_keys).
 __global__ void __launch_bounds__(1024)
 k_scan_blocks(uint64_t *__restrict__ block_sums, const uint32_t *__restrict__ block_u32, int64_t nb,
               uint64_t *__restrict__ total, const uint64_t *__restrict__ cap_ptr,
@@ -222,15 +224,11 @@ k_scan_blocks(uint64_t *__restrict__ block_sums, const uint32_t *__restrict__ bl
         run += x;
     }
     if (t == 1023) {
-        uint64_t tot = s[1023];
-        if (num_keys) {
-            // on overflow nothing downstream reads the (partial) key list: the
-            // sort and the ranges see zero keys; num_keys reports what is needed
-            *total = tot <= *cap_ptr ? tot : 0;
-            *num_keys = tot;
-        } else {
-            *total = tot;
-        }
+        const uint64_t tot = s[1023];
+        // with a capacity, a total above it reads as zero: on overflow nothing
+        // downstream reads the (partial) key list; num_keys reports what is needed
+        *total = (!cap_ptr || tot <= *cap_ptr) ? tot : 0;
+        if (num_keys) *num_keys = tot;
     }
 }
 
@@ -276,281 +274,539 @@ k_compact(const uint32_t *__restrict__ hits, const uint32_t *__restrict__ dkey_a
     }
 }
 
-// Depth-ordered entry record: x = first tile id of the rectangle,
-// y = w | h << 14 | (x0 == 0) << 28 | (y0 == 0) << 29, z = point index,
-// w = tiles_x << 8 | quality bound.
-struct SortedRec {
-    uint32_t gid0, w, h, tiles_x, m, i;
-    bool x0_zero, y0_zero;
-};
+// ---------------------------------------------------------------------------
+// Tile order by a two-level stable counting sort.  The tiles of each view are
+// grouped into super-tiles of ST x ST tiles, so that the 64 lanes of a wave
+// own the 64 tiles of one super-tile.
+//   a. every depth-ordered entry lists the super-tiles that hold at least one
+//      of its kept tiles (coarse pairs, in depth order), and a stable radix
+//      sort on the super-tile id groups them: each super-tile's run is in
+//      depth order;
+//   b. each run is cut into chunks of CHUNK entries, one wave per chunk: the
+//      lanes walk the chunk's entries in order and each counts the entries
+//      that keep its own tile;
+//   c. per tile, an exclusive scan of its counts over the chunks of its
+//      super-tile and, over all tiles in global tile order, of its totals
+//      (the tile ranges);
+//   d. the same walk again writes each kept (entry, tile) key at its tile's
+//      start + chunk prefix + running count: the (tile, depth, view, point)
+//      order, with every key written once at its final position.
 
-__device__ __forceinline__ SortedRec unpack_rec(uint4 q)
+// Class of every (super-tile, level): 0 if the level keeps none of the
+// super-tile's tiles, 1 if it keeps all of them, 2 otherwise.  One wave per
+// super-tile, lane = tile.
+__global__ void __launch_bounds__(256)
+k_st_class(const int64_t *__restrict__ vtab, const int4 *__restrict__ stab, int V, int64_t n_st, int L,
+           const uint8_t *__restrict__ tl, uint8_t *__restrict__ cls)
 {
-    SortedRec r;
-    r.gid0 = q.x;
-    r.w = q.y & 0x3fffu;
-    r.h = (q.y >> 14) & 0x3fffu;
-    r.x0_zero = (q.y >> 28) & 1u;
-    r.y0_zero = (q.y >> 29) & 1u;
-    r.i = q.z;
-    r.tiles_x = q.w >> 8;
-    r.m = q.w & 255u;
-    return r;
+    const int lane = threadIdx.x & 63;
+    const int64_t s = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (s >= n_st) return;
+    int v = 0;
+    while (v + 1 < V && stab[v + 1].x <= (int)s) ++v;
+    const int4 sb = stab[v];
+    const int sl = (int)s - sb.x, sy = sl / sb.y, sx = sl - sy * sb.y;
+    const int tx = sx * ST + lane % ST, ty = sy * ST + lane / ST;
+    const bool valid = tx < sb.z && ty < sb.w;
+    const uint32_t lvl = valid ? tl[2 * (vtab[2 * v] + (int64_t)ty * sb.z + tx)] : 255u;
+    const int nv = __popcll(ballot64(valid));
+    for (int m = 1; m <= L; ++m) {
+        const int nk = __popcll(ballot64(valid && lvl <= (uint32_t)m));
+        if (lane == 0) cls[s * 4 + m - 1] = (uint8_t)(nk == 0 ? 0 : (nk == nv ? 1 : 2));
+    }
 }
 
-// 4a. gather the records in depth order and sum counts and areas per block.
-__global__ void __launch_bounds__(SCAN_THREADS)
-k_gather(const uint32_t *__restrict__ order, const uint4 *__restrict__ rec, const uint64_t *__restrict__ d_count,
-         int n, const int64_t *__restrict__ vtab, uint4 *__restrict__ rec_s, uint32_t *__restrict__ hits_s,
-         uint64_t *__restrict__ bsum_h, uint64_t *__restrict__ bsum_a)
+// Super-tiles of the entry's view that its tile rectangle [x0, x1] x [y0, y1]
+// overlaps and that hold at least one of its kept tiles (with the level
+// filter: the class table, and a summed-area count over rectangle and
+// super-tile > 0 where the level keeps part of the super-tile), in row-major
+// order.  With EMIT, (super-tile id, r) pairs are written from position pos
+// on.  Returns their number.
+template <bool EMIT>
+__device__ __forceinline__ uint32_t coarse_walk(uint32_t rx, uint32_t ry, uint32_t m, int v, uint32_t r,
+                                                const int64_t *__restrict__ vtab, const int4 *__restrict__ stab,
+                                                const uint32_t *__restrict__ sat, const uint8_t *__restrict__ cls,
+                                                int L, int64_t n_tiles, uint32_t *__restrict__ ck,
+                                                uint32_t *__restrict__ cv, uint64_t pos)
 {
-    __shared__ uint64_t s_h[SCAN_THREADS / 64], s_a[SCAN_THREADS / 64];
+    const int x0 = (int)(rx & 0xffffu), y0 = (int)(rx >> 16), x1 = (int)(ry & 0xffffu), y1 = (int)(ry >> 16);
+    const int sx0 = x0 / ST, sx1 = x1 / ST, sy0 = y0 / ST, sy1 = y1 / ST;
+    const int4 sb = stab[v];
+    if (sx0 == sx1 && sy0 == sy1) {
+        // one super-tile: it holds all the entry's kept tiles (there is one)
+        if (EMIT) {
+            ck[pos] = (uint32_t)(sb.x + sy0 * sb.y + sx0);
+            cv[pos] = r;
+        }
+        return 1u;
+    }
+    const uint32_t *s = nullptr;
+    const int ml = (int)m < L ? (int)m : L;
+    if (sat) s = sat + (int64_t)(ml - 1) * n_tiles + vtab[2 * v];
+    uint32_t c = 0;
+    for (int sy = sy0; sy <= sy1; ++sy) {
+        const int by0 = y0 > sy * ST ? y0 : sy * ST, by1 = y1 < sy * ST + ST - 1 ? y1 : sy * ST + ST - 1;
+        for (int sx = sx0; sx <= sx1; ++sx) {
+            const uint32_t st_id = (uint32_t)(sb.x + sy * sb.y + sx);
+            bool keep = true;
+            if (s) {
+                const uint8_t k = cls[(uint64_t)st_id * 4 + ml - 1];
+                if (k == 2) {
+                    const int bx0 = x0 > sx * ST ? x0 : sx * ST;
+                    const int bx1 = x1 < sx * ST + ST - 1 ? x1 : sx * ST + ST - 1;
+                    keep = sat_rect(s, sb.z, bx0, bx1, by0, by1) != 0u;
+                } else {
+                    keep = k == 1;
+                }
+            }
+            if (keep) {
+                if (EMIT) {
+                    ck[pos + c] = st_id;
+                    cv[pos + c] = r;
+                }
+                ++c;
+            }
+        }
+    }
+    return c;
+}
+
+// Coarse pairs of an entry whose rectangle spans at most 2 x 2 super-tiles,
+// as a mask: bit dy * 2 + dx for super-tile (sx0 + dx, sy0 + dy).  Larger
+// spans have no mask (coarse_walk is run again to emit them).
+__device__ __forceinline__ uint32_t coarse_mask(uint32_t rx, uint32_t ry, uint32_t m, int v,
+                                                const int64_t *__restrict__ vtab, const int4 *__restrict__ stab,
+                                                const uint32_t *__restrict__ sat, const uint8_t *__restrict__ cls,
+                                                int L, int64_t n_tiles, uint32_t &count)
+{
+    const int x0 = (int)(rx & 0xffffu), y0 = (int)(rx >> 16), x1 = (int)(ry & 0xffffu), y1 = (int)(ry >> 16);
+    const int sx0 = x0 / ST, sx1 = x1 / ST, sy0 = y0 / ST, sy1 = y1 / ST;
+    if (sx1 - sx0 > 1 || sy1 - sy0 > 1) {
+        count = coarse_walk<false>(rx, ry, m, v, 0u, vtab, stab, sat, cls, L, n_tiles, nullptr, nullptr, 0);
+        return 0u;
+    }
+    if (sx0 == sx1 && sy0 == sy1) {
+        count = 1u;
+        return 1u;
+    }
+    const int4 sb = stab[v];
+    const int ml = (int)m < L ? (int)m : L;
+    const uint32_t *s = sat ? sat + (int64_t)(ml - 1) * n_tiles + vtab[2 * v] : nullptr;
+    uint32_t mask = 0;
+    for (int dy = 0; dy <= sy1 - sy0; ++dy) {
+        const int sy = sy0 + dy;
+        const int by0 = y0 > sy * ST ? y0 : sy * ST, by1 = y1 < sy * ST + ST - 1 ? y1 : sy * ST + ST - 1;
+        for (int dx = 0; dx <= sx1 - sx0; ++dx) {
+            const int sx = sx0 + dx;
+            bool keep = true;
+            if (s) {
+                const uint8_t k = cls[(uint64_t)(sb.x + sy * sb.y + sx) * 4 + ml - 1];
+                if (k == 2) {
+                    const int bx0 = x0 > sx * ST ? x0 : sx * ST;
+                    const int bx1 = x1 < sx * ST + ST - 1 ? x1 : sx * ST + ST - 1;
+                    keep = sat_rect(s, sb.z, bx0, bx1, by0, by1) != 0u;
+                } else {
+                    keep = k == 1;
+                }
+            }
+            mask |= keep ? 1u << (dy * 2 + dx) : 0u;
+        }
+    }
+    count = (uint32_t)__popc(mask);
+    return mask;
+}
+
+// 4a. gather the records in depth order: rec_s[r] = {x0 | y0 << 16,
+// x1 | y1 << 16, entry, view << 8 | quality bound}; cc_s[r] = its number of
+// coarse pairs | the coarse mask << 28; per-block sums of key counts and
+// coarse pairs.  A block takes SCAN_THREADS * SCAN_ITEMS entries with
+// GATHER_THREADS threads, each issuing its loads for all its entries first.
+constexpr int GATHER_THREADS = 1024;
+constexpr int GATHER_ITEMS = SCAN_THREADS * SCAN_ITEMS / GATHER_THREADS;
+__global__ void __launch_bounds__(GATHER_THREADS)
+k_gather(const uint32_t *__restrict__ order, const uint4 *__restrict__ rec, const uint64_t *__restrict__ d_count,
+         int n, const int64_t *__restrict__ vtab, const int4 *__restrict__ stab, const uint32_t *__restrict__ sat,
+         const uint8_t *__restrict__ cls, int L, int64_t n_tiles, uint4 *__restrict__ rec_s,
+         uint32_t *__restrict__ cc_s, uint64_t *__restrict__ bsum_h, uint64_t *__restrict__ bsum_c)
+{
+    __shared__ uint64_t s_h[GATHER_THREADS / 64], s_c[GATHER_THREADS / 64];
     const uint64_t E = *d_count;
-    const int64_t base = (int64_t)blockIdx.x * (SCAN_THREADS * SCAN_ITEMS);
-    uint64_t acc_h = 0, acc_a = 0;
-    for (int j = 0; j < SCAN_ITEMS; ++j) {
-        const int64_t r = base + (int64_t)j * SCAN_THREADS + threadIdx.x;
-        if ((uint64_t)r >= E) break;
-        const uint32_t e = order[r];
-        const uint4 q = rec[e];
-        const uint32_t v = e / (uint32_t)n;
-        const uint32_t i = e - v * (uint32_t)n;
-        const uint32_t x0 = q.x & 0xffffu, y0 = q.x >> 16, x1 = q.y & 0xffffu, y1 = q.y >> 16;
-        const uint32_t w = x1 - x0 + 1, h = y1 - y0 + 1;
-        const int64_t tx = vtab[2 * v + 1];
-        const uint32_t gid0 = (uint32_t)(vtab[2 * v] + (int64_t)y0 * tx + x0);
-        rec_s[r] = make_uint4(gid0, w | (h << 14) | ((uint32_t)(x0 == 0) << 28) | ((uint32_t)(y0 == 0) << 29), i,
-                              ((uint32_t)tx << 8) | q.w);
-        hits_s[r] = q.z;
-        acc_h += q.z;
-        acc_a += (uint64_t)w * h;
+    const int64_t base = (int64_t)blockIdx.x * (GATHER_THREADS * GATHER_ITEMS);
+    uint32_t e[GATHER_ITEMS];
+    uint4 q[GATHER_ITEMS];
+#pragma unroll
+    for (int j = 0; j < GATHER_ITEMS; ++j) {
+        const int64_t r = base + (int64_t)j * GATHER_THREADS + threadIdx.x;
+        e[j] = (uint64_t)r < E ? order[r] : 0xFFFFFFFFu;
+    }
+#pragma unroll
+    for (int j = 0; j < GATHER_ITEMS; ++j) q[j] = e[j] != 0xFFFFFFFFu ? rec[e[j]] : make_uint4(0u, 0u, 0u, 0u);
+    uint64_t acc_h = 0, acc_c = 0;
+#pragma unroll
+    for (int j = 0; j < GATHER_ITEMS; ++j) {
+        if (e[j] == 0xFFFFFFFFu) continue;
+        const int64_t r = base + (int64_t)j * GATHER_THREADS + threadIdx.x;
+        const int v = (int)(e[j] / (uint32_t)n);
+        const uint32_t m = q[j].w & 255u;
+        uint32_t cc;
+        const uint32_t mask = coarse_mask(q[j].x, q[j].y, m, v, vtab, stab, sat, cls, L, n_tiles, cc);
+        rec_s[r] = make_uint4(q[j].x, q[j].y, e[j], ((uint32_t)v << 8) | m);
+        cc_s[r] = cc | (mask << 28);
+        acc_h += q[j].z;
+        acc_c += cc;
     }
     for (int off = 32; off > 0; off >>= 1) {
         acc_h += __shfl_xor(acc_h, off);
-        acc_a += __shfl_xor(acc_a, off);
+        acc_c += __shfl_xor(acc_c, off);
     }
     if ((threadIdx.x & 63) == 0) {
         s_h[threadIdx.x >> 6] = acc_h;
-        s_a[threadIdx.x >> 6] = acc_a;
+        s_c[threadIdx.x >> 6] = acc_c;
     }
     __syncthreads();
     if (threadIdx.x == 0) {
-        uint64_t th = 0, ta = 0;
-        for (int w = 0; w < SCAN_THREADS / 64; ++w) {
+        uint64_t th = 0, tc = 0;
+        for (int w = 0; w < GATHER_THREADS / 64; ++w) {
             th += s_h[w];
-            ta += s_a[w];
+            tc += s_c[w];
         }
         bsum_h[blockIdx.x] = th;
-        bsum_a[blockIdx.x] = ta;
+        bsum_c[blockIdx.x] = tc;
     }
 }
 
-__device__ __forceinline__ uint64_t slice_len(uint64_t area_total)
+// 4b. coarse pairs of every depth-ordered entry at its scanned offset (from
+// the mask when there is one).
+__global__ void __launch_bounds__(GATHER_THREADS)
+k_coarse_emit(const uint4 *__restrict__ rec_s, const uint32_t *__restrict__ cc_s, const uint64_t *__restrict__ counts,
+              const uint64_t *__restrict__ boff, const int64_t *__restrict__ vtab, const int4 *__restrict__ stab,
+              const uint32_t *__restrict__ sat, const uint8_t *__restrict__ cls, int L, int64_t n_tiles,
+              uint32_t *__restrict__ ck, uint32_t *__restrict__ cv)
 {
-    uint64_t s = (area_total + MAX_SLICES - 1) / MAX_SLICES;
-    s = (s + 63) & ~uint64_t(63);
-    return s > SLICE_MIN ? s : SLICE_MIN;
-}
-
-// 4b. scan down-sweep: key offset and area offset of every sorted entry, and
-// the entry in which each emission slice of the area starts.
-__global__ void __launch_bounds__(SCAN_THREADS)
-k_scan_down(const uint4 *__restrict__ rec_s, const uint32_t *__restrict__ hits_s,
-            const uint64_t *__restrict__ counts, const uint64_t *__restrict__ boff_h,
-            const uint64_t *__restrict__ boff_a, uint64_t *__restrict__ hpre, uint64_t *__restrict__ apre,
-            uint32_t *__restrict__ slice)
-{
-    __shared__ uint64_t s_h[SCAN_THREADS / 64], s_a[SCAN_THREADS / 64];
+    constexpr int W = GATHER_THREADS / 64;
+    __shared__ uint32_t s_w[GATHER_ITEMS][W];
     const uint64_t E = counts[0];
-    const uint64_t S = slice_len(counts[3]);
+    if (counts[1] == 0) return;  // no keys, or more than the capacity
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const int64_t base = (int64_t)blockIdx.x * (SCAN_THREADS * SCAN_ITEMS);
+    const int64_t base = (int64_t)blockIdx.x * (GATHER_THREADS * GATHER_ITEMS);
     if ((uint64_t)base >= E) return;
-    uint64_t run_h = boff_h[blockIdx.x], run_a = boff_a[blockIdx.x];
-    for (int j = 0; j < SCAN_ITEMS; ++j) {
-        const int64_t r = base + (int64_t)j * SCAN_THREADS + threadIdx.x;
+    uint32_t c[GATHER_ITEMS], x[GATHER_ITEMS];
+    uint4 q[GATHER_ITEMS];
+#pragma unroll
+    for (int j = 0; j < GATHER_ITEMS; ++j) {
+        const int64_t r = base + (int64_t)j * GATHER_THREADS + threadIdx.x;
         const bool ok = (uint64_t)r < E;
-        uint64_t ch = 0, ca = 0;
-        if (ok) {
-            const uint32_t y = rec_s[r].y;
-            ch = hits_s[r];
-            ca = (uint64_t)(y & 0x3fffu) * ((y >> 14) & 0x3fffu);
-        }
-        uint64_t xh = ch, xa = ca;
+        c[j] = ok ? cc_s[r] : 0u;
+        q[j] = ok ? rec_s[r] : make_uint4(0u, 0u, 0u, 0u);
+    }
+#pragma unroll
+    for (int j = 0; j < GATHER_ITEMS; ++j) {
+        x[j] = c[j] & 0x0FFFFFFFu;
         for (int off = 1; off < 64; off <<= 1) {
-            const uint64_t yh = __shfl_up(xh, off), ya = __shfl_up(xa, off);
-            if (lane >= off) {
-                xh += yh;
-                xa += ya;
+            const uint32_t y = __shfl_up(x[j], off);
+            if (lane >= off) x[j] += y;
+        }
+        if (lane == 63) s_w[j][wave] = x[j];
+    }
+    __syncthreads();
+    uint64_t run = boff[blockIdx.x];
+#pragma unroll
+    for (int j = 0; j < GATHER_ITEMS; ++j) {
+        uint64_t pw = 0, tw = 0;
+        for (int w = 0; w < W; ++w) {
+            const uint32_t vw = s_w[j][w];
+            if (w < wave) pw += vw;
+            tw += vw;
+        }
+        const int64_t r = base + (int64_t)j * GATHER_THREADS + threadIdx.x;
+        const uint32_t cnt = c[j] & 0x0FFFFFFFu, mask = c[j] >> 28;
+        const uint64_t pos = run + pw + x[j] - cnt;
+        if (cnt) {
+            const int v = (int)(q[j].w >> 8);
+            if (mask) {
+                const int4 sb = stab[v];
+                const int sx0 = (int)(q[j].x & 0xffffu) / ST, sy0 = (int)(q[j].x >> 16) / ST;
+                uint32_t k = 0;
+                for (int bit = 0; bit < 4; ++bit) {
+                    if (!(mask & (1u << bit))) continue;
+                    ck[pos + k] = (uint32_t)(sb.x + (sy0 + (bit >> 1)) * sb.y + sx0 + (bit & 1));
+                    cv[pos + k] = (uint32_t)r;
+                    ++k;
+                }
+            } else {
+                coarse_walk<true>(q[j].x, q[j].y, q[j].w & 255u, v, (uint32_t)r, vtab, stab, sat, cls, L, n_tiles,
+                                  ck, cv, pos);
             }
         }
-        if (lane == 63) {
-            s_h[wave] = xh;
-            s_a[wave] = xa;
-        }
-        __syncthreads();
-        uint64_t ph = 0, pa = 0, th = 0, ta = 0;
-        for (int w = 0; w < SCAN_THREADS / 64; ++w) {
-            const uint64_t vh = s_h[w], va = s_a[w];
-            if (w < wave) {
-                ph += vh;
-                pa += va;
-            }
-            th += vh;
-            ta += va;
-        }
-        __syncthreads();
-        if (ok) {
-            const uint64_t a0 = run_a + pa + xa - ca;
-            hpre[r] = run_h + ph + xh - ch;
-            apre[r] = a0;
-            for (uint64_t k = (a0 + S - 1) / S; k * S < a0 + ca; ++k) slice[k] = (uint32_t)r;
-        }
-        run_h += th;
-        run_a += ta;
+        run += tw;
     }
 }
 
-// Value of a level summed-area table at (x0 + dx, y0 + dy) of a rectangle.
-__device__ __forceinline__ uint32_t sat_rel(const uint32_t *__restrict__ s, const SortedRec &q, int dx, int dy)
+// Chunks of every super-tile's run: chunk_off[s] = first chunk of s
+// (chunk_off[n_st] = their number, also in *n_chunks), chunk_st[c] = its
+// super-tile.  One workgroup; each thread takes consecutive super-tiles.
+__global__ void __launch_bounds__(1024)
+k_chunk_table(const uint32_t *__restrict__ st_ranges, int64_t n_st, uint32_t *__restrict__ chunk_off,
+              uint32_t *__restrict__ chunk_st, uint64_t *__restrict__ n_chunks)
 {
-    if ((dx < 0 && q.x0_zero) || (dy < 0 && q.y0_zero)) return 0u;
-    return s[(int64_t)q.gid0 + (int64_t)dy * q.tiles_x + dx];
-}
-
-__device__ __forceinline__ uint32_t sat_rel_rect(const uint32_t *__restrict__ s, const SortedRec &q, int dx0,
-                                                 int dx1, int dy0, int dy1)
-{
-    return sat_rel(s, q, dx1, dy1) - sat_rel(s, q, dx0 - 1, dy1) - sat_rel(s, q, dx1, dy0 - 1) +
-           sat_rel(s, q, dx0 - 1, dy0 - 1);
-}
-
-// Inclusive max-scan over the 64 lanes of a wave (values >= 0): row
-// shifts within each row of 16 lanes, then row broadcasts across rows.
-__device__ __forceinline__ uint32_t wave_incl_max(uint32_t x)
-{
-    x = max(x, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x111, 0xF, 0xF, true));  // row_shr:1
-    x = max(x, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x112, 0xF, 0xF, true));  // row_shr:2
-    x = max(x, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x114, 0xF, 0xF, true));  // row_shr:4
-    x = max(x, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x118, 0xF, 0xF, true));  // row_shr:8
-    x = max(x, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x142, 0xA, 0xF, false));  // row_bcast:15
-    x = max(x, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x143, 0xC, 0xF, false));  // row_bcast:31
-    return x;
-}
-
-// floor(l / w) and l mod w for l < w * 2^14, w >= 1 (reciprocal estimate,
-// one correction step: the quotient is below 2^14).
-__device__ __forceinline__ void divmod_small(uint32_t l, uint32_t w, uint32_t &q, uint32_t &rem)
-{
-    uint32_t qq = (uint32_t)((float)l * __builtin_amdgcn_rcpf((float)w));
-    int32_t rr = (int32_t)(l - qq * w);
-    if (rr < 0) {
-        --qq;
-        rr += (int32_t)w;
-    } else if (rr >= (int32_t)w) {
-        ++qq;
-        rr -= (int32_t)w;
+    __shared__ uint32_t s[1024];
+    const int t = threadIdx.x;
+    const int64_t per = (n_st + 1023) / 1024;
+    const int64_t b0 = t * per < n_st ? t * per : n_st, b1 = b0 + per < n_st ? b0 + per : n_st;
+    uint32_t local = 0;
+    for (int64_t q = b0; q < b1; ++q) local += (st_ranges[2 * q + 1] - st_ranges[2 * q] + CHUNK - 1) / CHUNK;
+    s[t] = local;
+    __syncthreads();
+    for (int off = 1; off < 1024; off <<= 1) {
+        const uint32_t add = t >= off ? s[t - off] : 0u;
+        __syncthreads();
+        s[t] += add;
+        __syncthreads();
     }
-    q = qq;
-    rem = (uint32_t)rr;
+    uint32_t run = s[t] - local;
+    for (int64_t q = b0; q < b1; ++q) {
+        const uint32_t k = (st_ranges[2 * q + 1] - st_ranges[2 * q] + CHUNK - 1) / CHUNK;
+        chunk_off[q] = run;
+        for (uint32_t j = 0; j < k; ++j) chunk_st[run + j] = (uint32_t)q;
+        run += k;
+    }
+    if (t == 1023) {
+        chunk_off[n_st] = s[1023];
+        *n_chunks = s[1023];
+    }
 }
 
-// 4c. load-balanced emission.  The rectangles of the depth-sorted entries,
-// concatenated in row-major order, form one sequence of (entry, tile) items
-// whose kept tiles are exactly the key list in order.  Each wave takes slices
-// of that sequence, 64 items per step: an entry that starts inside the step
-// marks its first item in a wave-private LDS row, a max-scan over the lanes
-// hands every item its entry, the tile level is tested, and kept keys are
-// compacted with a ballot, so every store is coalesced.
+// View of a super-tile: the last view whose first super-tile is <= s.
+__device__ __forceinline__ int view_of_st(const int4 *__restrict__ stab, int V, int s)
+{
+    int lo = 0, hi = V - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (stab[mid].x <= s)
+            lo = mid;
+        else
+            hi = mid - 1;
+    }
+    return lo;
+}
+
+// 4c/4e. One wave per chunk of a super-tile's run.  Lane j of batch q holds
+// entry b + 64 q + j of the chunk; the wave visits the tiles of the super-tile
+// that the chunk's rectangles reach (row-major) and tests all the chunk's
+// entries against each at once.  COUNT: ccnt[c][l] = entries of the chunk
+// that keep tile l of the super-tile.  WRITE: the kept entries' point
+// indices (and optional 64-bit keys), compacted by ballot, at the tile's
+// start + the chunk's exclusive prefix (ccnt after k_col_scan): a tile's
+// keys of one batch are one contiguous store.
+constexpr int NB = CHUNK / 64;  // batches of 64 entries per chunk
+template <bool WRITE>
 __global__ void __launch_bounds__(256)
-k_emit(const uint4 *__restrict__ rec_s, const uint64_t *__restrict__ hpre, const uint64_t *__restrict__ apre,
-       const uint32_t *__restrict__ slice, const uint64_t *__restrict__ counts, const uint8_t *__restrict__ tl,
-       const uint32_t *__restrict__ sat, int L, int64_t n_tiles, uint64_t cap, uint32_t *__restrict__ tkey,
-       uint32_t *__restrict__ tval)
+k_tile_pass(const uint32_t *__restrict__ cv, const uint32_t *__restrict__ st_ranges,
+            const uint32_t *__restrict__ chunk_off, const uint32_t *__restrict__ chunk_st,
+            const uint64_t *__restrict__ counts, const uint4 *__restrict__ rec_s, const int64_t *__restrict__ vtab,
+            const int4 *__restrict__ stab, int V, int n, const uint8_t *__restrict__ tl, uint32_t *__restrict__ ccnt,
+            const uint32_t *__restrict__ ranges, uint32_t *__restrict__ vals, uint64_t *__restrict__ keys,
+            const gs_splat *__restrict__ splats)
 {
-    __shared__ uint32_t s_mark[4][64];
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    s_mark[wave][lane] = 0;
-    wave_lds_sync();
-    const uint64_t E = counts[0], A = counts[3];
-    if (counts[1] == 0 || E == 0) return;  // no keys, or more than the capacity
-    const uint64_t S = slice_len(A);
-    const uint64_t n_slices = (A + S - 1) / S;
+    // per-tile level and output position of the wave's super-tile, read
+    // back with uniform LDS loads inside the tile loop (a register loaded
+    // from memory would make every iteration wait for the stores before it)
+    __shared__ uint32_t s_lvl[4][64], s_pos[4][64];
+    if (counts[1] == 0) return;  // no keys, or more than the capacity
+    const uint64_t nc = counts[4];
+    const int lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
     const uint64_t lt = lanemask_lt();
     const uint64_t waves = (uint64_t)gridDim.x * (blockDim.x / 64);
-    for (uint64_t sl = (uint64_t)blockIdx.x * (blockDim.x / 64) + wave; sl < n_slices; sl += waves) {
-        const uint64_t a_beg = sl * S;
-        const uint64_t a_end = a_beg + S < A ? a_beg + S : A;
-        uint64_t r = slice[sl];
-        uint32_t base0 = (uint32_t)(a_beg - apre[r]);  // items of entry r before the step
-        uint64_t o = hpre[r];
+    for (uint64_t c = (uint64_t)blockIdx.x * (blockDim.x / 64) + wave; c < nc; c += waves) {
+        const uint32_t s = chunk_st[c];
+        const uint32_t k = (uint32_t)c - chunk_off[s];
+        const uint32_t b = st_ranges[2 * s] + k * CHUNK;
+        const uint32_t e_end = st_ranges[2 * s + 1] < b + CHUNK ? st_ranges[2 * s + 1] : b + CHUNK;
+        const int v = view_of_st(stab, V, (int)s);
+        const int4 sb = stab[v];
+        const int sl = (int)s - sb.x, sy = sl / sb.y, sx = sl - sy * sb.y;
+        const int bx = sx * ST, by = sy * ST;
+        const int64_t toff = vtab[2 * v];
         {
-            const SortedRec q = unpack_rec(rec_s[r]);
-            if (!tl) {
-                o += base0;
-            } else {
-                uint32_t ly, lx;
-                divmod_small(base0, q.w, ly, lx);
-                const uint32_t ml = q.m < (uint32_t)L ? q.m : (uint32_t)L;
-                const uint32_t *s = sat + (int64_t)(ml - 1) * n_tiles;
-                if (ly) o += sat_rel_rect(s, q, 0, (int)q.w - 1, 0, (int)ly - 1);
-                if (lx) o += sat_rel_rect(s, q, 0, (int)lx - 1, (int)ly, (int)ly);
+            const int mtx = bx + lane % ST, mty = by + lane / ST;
+            const bool mvalid = mtx < sb.z && mty < sb.w;
+            const int64_t mg = toff + (int64_t)mty * sb.z + mtx;
+            s_lvl[wave][lane] = (tl && mvalid) ? (uint32_t)tl[2 * mg] : 0u;
+            if (WRITE) s_pos[wave][lane] = mvalid ? ranges[2 * mg] + ccnt[c * 64 + lane] : 0u;
+        }
+        // the chunk's entries and the bounding box of their rectangles
+        int x0[NB], x1[NB], y0[NB], y1[NB];
+        uint32_t mw[NB], ez[NB];
+        int ux0 = 0x7fff, uy0 = 0x7fff, ux1 = -1, uy1 = -1;
+#pragma unroll
+        for (int q = 0; q < NB; ++q) {
+            const uint32_t j = b + 64u * q + (uint32_t)lane;
+            x0[q] = y0[q] = 0x7fff;
+            x1[q] = y1[q] = -1;
+            mw[q] = ez[q] = 0u;
+            if (j < e_end) {
+                const uint4 R = rec_s[cv[j]];
+                x0[q] = (int)(R.x & 0xffffu);
+                y0[q] = (int)(R.x >> 16);
+                x1[q] = (int)(R.y & 0xffffu);
+                y1[q] = (int)(R.y >> 16);
+                ez[q] = R.z;
+                mw[q] = R.w & 255u;
+                ux0 = min(ux0, x0[q]);
+                uy0 = min(uy0, y0[q]);
+                ux1 = max(ux1, x1[q]);
+                uy1 = max(uy1, y1[q]);
             }
         }
-        for (uint64_t c0 = a_beg; c0 < a_end; c0 += 64) {
-            // entries r+1 .. r+63 that start inside this step mark their first item
-            const uint64_t rj = r + lane;
-            if (lane > 0 && rj < E) {
-                const uint64_t d = apre[rj] - c0;
-                if (d < 64) s_mark[wave][d] = ((uint32_t)lane << 6) | (uint32_t)d;
-            }
-            wave_lds_sync();
-            const uint32_t mark = s_mark[wave][lane];
-            wave_lds_sync();
-            s_mark[wave][lane] = 0;
-            const uint32_t km = wave_incl_max(mark);
-            uint32_t k = km >> 6;
-            const uint32_t l = k == 0 ? base0 + (uint32_t)lane : (uint32_t)lane - (km & 63u);
-            uint64_t re = r + k;
-            re = re < E ? re : E - 1;
-            const bool valid = c0 + lane < a_end;
-            const SortedRec q = unpack_rec(rec_s[re]);
-            uint32_t ly, lx;
-            divmod_small(l, q.w, ly, lx);
-            const uint32_t gid = q.gid0 + ly * q.tiles_x + lx;
-            const bool keep = valid && (!tl || (gid < (uint64_t)n_tiles && tl[2 * (uint64_t)gid] <= q.m));
-            const uint64_t bal = ballot64(keep);
-            if (keep) {
-                const uint64_t pos = o + (uint32_t)__popcll(bal & lt);
-                if (pos < cap) {
-                    tkey[pos] = gid;
-                    tval[pos] = q.i;
+        for (int off = 32; off > 0; off >>= 1) {
+            ux0 = min(ux0, __shfl_xor(ux0, off));
+            uy0 = min(uy0, __shfl_xor(uy0, off));
+            ux1 = max(ux1, __shfl_xor(ux1, off));
+            uy1 = max(uy1, __shfl_xor(uy1, off));
+        }
+        ux0 = __builtin_amdgcn_readfirstlane(max(ux0, bx));
+        uy0 = __builtin_amdgcn_readfirstlane(max(uy0, by));
+        ux1 = __builtin_amdgcn_readfirstlane(min(ux1, min(bx + ST - 1, sb.z - 1)));
+        uy1 = __builtin_amdgcn_readfirstlane(min(uy1, min(by + ST - 1, sb.w - 1)));
+        const uint32_t vbase = (uint32_t)v * (uint32_t)n;
+        wave_lds_sync();
+        uint32_t mcnt = 0;
+        for (int ty = uy0; ty <= uy1; ++ty) {
+            uint64_t ym[NB];
+#pragma unroll
+            for (int q = 0; q < NB; ++q) ym[q] = ballot64((y0[q] <= ty) & (ty <= y1[q]));
+            for (int tx = ux0; tx <= ux1; ++tx) {
+                const int l = (ty - by) * ST + (tx - bx);
+                const uint32_t lvl = (uint32_t)__builtin_amdgcn_readfirstlane((int)s_lvl[wave][l]);
+                uint32_t pos = 0;
+                if (WRITE) pos = (uint32_t)__builtin_amdgcn_readfirstlane((int)s_pos[wave][l]);
+                uint32_t tot = 0;
+#pragma unroll
+                for (int q = 0; q < NB; ++q) {
+                    const uint64_t bal = ballot64((x0[q] <= tx) & (tx <= x1[q]) & (lvl <= mw[q])) & ym[q];
+                    if (WRITE && bal) {
+                        if ((bal >> lane) & 1u) {
+                            const uint32_t at = pos + (uint32_t)__popcll(bal & lt);
+                            vals[at] = ez[q] - vbase;
+                            if (keys)
+                                keys[at] = ((uint64_t)(toff + (int64_t)ty * sb.z + tx) << 32) |
+                                           __float_as_uint(splats[ez[q]].depth);
+                        }
+                        pos += (uint32_t)__popcll(bal);
+                    }
+                    if (!WRITE) tot += (uint32_t)__popcll(bal);
                 }
+                if (!WRITE) mcnt = lane == l ? tot : mcnt;
             }
-            o += (uint32_t)__popcll(bal);
-            // the next step starts one item after lane 63's
-            const uint32_t k63 = __builtin_amdgcn_readlane(k, 63);
-            const uint32_t l63 = __builtin_amdgcn_readlane(l, 63);
-            const uint32_t area63 = __builtin_amdgcn_readlane(q.w * q.h, 63);
-            if (l63 + 1 < area63) {
-                r += k63;
-                base0 = l63 + 1;
-            } else {
-                r += k63 + 1;
-                base0 = 0;
-            }
-            wave_lds_sync();
         }
+        if (!WRITE) ccnt[c * 64 + lane] = mcnt;
+        // the next chunk rewrites the wave's LDS rows
+        wave_lds_sync();
     }
 }
 
-// 6. tile ranges: four sorted ids per thread; a boundary between k - 1 and k
-// closes one tile's run and opens the next.
-__global__ void __launch_bounds__(256)
-k_ranges(const uint32_t *__restrict__ tkey, const uint64_t *__restrict__ counts, uint64_t cap,
-         int64_t n_tiles, uint32_t *__restrict__ ranges)
+// 4d. per super-tile and lane (tile): exclusive prefix of the chunk counts
+// in place, and the tile's total.  COL_WAVES waves split the chunks.
+constexpr int COL_WAVES = 16;
+__global__ void __launch_bounds__(COL_WAVES * 64)
+k_col_scan(const uint32_t *__restrict__ chunk_off, const int64_t *__restrict__ vtab, const int4 *__restrict__ stab,
+           int V, uint32_t *__restrict__ ccnt, uint32_t *__restrict__ tot)
 {
-    uint64_t count = counts[1];
+    __shared__ uint32_t s_part[COL_WAVES][64];
+    const uint32_t s = blockIdx.x;
+    const uint32_t c0 = chunk_off[s], nch = chunk_off[s + 1] - c0;
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const uint32_t per = (nch + COL_WAVES - 1) / COL_WAVES;
+    const uint32_t a = c0 + (wave * per < nch ? wave * per : nch);
+    const uint32_t z = c0 + ((wave + 1) * per < nch ? (wave + 1) * per : nch);
+    uint32_t sum = 0;
+    for (uint32_t c = a; c < z; ++c) sum += ccnt[(uint64_t)c * 64 + lane];
+    s_part[wave][lane] = sum;
+    __syncthreads();
+    uint32_t run = 0, total = 0;
+    for (int w = 0; w < COL_WAVES; ++w) {
+        const uint32_t x = s_part[w][lane];
+        if (w < wave) run += x;
+        total += x;
+    }
+    for (uint32_t c = a; c < z; ++c) {
+        const uint32_t x = ccnt[(uint64_t)c * 64 + lane];
+        ccnt[(uint64_t)c * 64 + lane] = run;
+        run += x;
+    }
+    if (wave == 0) {
+        const int v = view_of_st(stab, V, (int)s);
+        const int4 sb = stab[v];
+        const int sl = (int)s - sb.x, sy = sl / sb.y, sx = sl - sy * sb.y;
+        const int tx = sx * ST + lane % ST, ty = sy * ST + lane / ST;
+        if (tx < sb.z && ty < sb.w) tot[vtab[2 * v] + (int64_t)ty * sb.z + tx] = total;
+    }
+}
+
+// Block sums of the per-tile totals (blocks of SCAN_THREADS * SCAN_ITEMS tiles).
+__global__ void __launch_bounds__(SCAN_THREADS)
+k_tile_reduce(const uint32_t *__restrict__ tot, int64_t n_tiles, uint64_t *__restrict__ bsum)
+{
+    __shared__ uint64_t s_w[SCAN_THREADS / 64];
+    const int64_t base = (int64_t)blockIdx.x * (SCAN_THREADS * SCAN_ITEMS);
+    uint64_t acc = 0;
+    for (int j = 0; j < SCAN_ITEMS; ++j) {
+        const int64_t g = base + (int64_t)j * SCAN_THREADS + threadIdx.x;
+        if (g < n_tiles) acc += tot[g];
+    }
+    for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off);
+    if ((threadIdx.x & 63) == 0) s_w[threadIdx.x >> 6] = acc;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        uint64_t t = 0;
+        for (int w = 0; w < SCAN_THREADS / 64; ++w) t += s_w[w];
+        bsum[blockIdx.x] = t;
+    }
+}
+
+// 4d. tile ranges from the totals: thread t of a block takes SCAN_ITEMS
+// consecutive tiles; an empty tile gets (0, 0).
+__global__ void __launch_bounds__(SCAN_THREADS)
+k_tile_ranges(const uint32_t *__restrict__ tot, int64_t n_tiles, const uint64_t *__restrict__ boff,
+              const uint64_t *__restrict__ counts, uint32_t *__restrict__ ranges)
+{
+    __shared__ uint64_t s_w[SCAN_THREADS / 64];
+    if (counts[1] == 0) return;  // ranges stay zero
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int64_t g0 = (int64_t)blockIdx.x * (SCAN_THREADS * SCAN_ITEMS) + (int64_t)threadIdx.x * SCAN_ITEMS;
+    uint32_t t[SCAN_ITEMS];
+    uint64_t local = 0;
+#pragma unroll
+    for (int j = 0; j < SCAN_ITEMS; ++j) {
+        t[j] = g0 + j < n_tiles ? tot[g0 + j] : 0u;
+        local += t[j];
+    }
+    uint64_t x = local;
+    for (int off = 1; off < 64; off <<= 1) {
+        const uint64_t y = __shfl_up(x, off);
+        if (lane >= off) x += y;
+    }
+    if (lane == 63) s_w[wave] = x;
+    __syncthreads();
+    uint64_t run = boff[blockIdx.x] + x - local;
+    for (int w = 0; w < wave; ++w) run += s_w[w];
+#pragma unroll
+    for (int j = 0; j < SCAN_ITEMS; ++j) {
+        if (g0 + j < n_tiles)
+            reinterpret_cast<uint2 *>(ranges)[g0 + j] =
+                t[j] ? make_uint2((uint32_t)run, (uint32_t)(run + t[j])) : make_uint2(0u, 0u);
+        run += t[j];
+    }
+}
+
+// Super-tile ranges: four sorted ids per thread; a boundary between k - 1
+// and k closes one run and opens the next.
+__global__ void __launch_bounds__(256)
+k_ranges(const uint32_t *__restrict__ tkey, const uint64_t *__restrict__ d_count, uint64_t cap, int64_t n_ids,
+         uint32_t *__restrict__ ranges)
+{
+    uint64_t count = *d_count;
     count = count < cap ? count : cap;
     const uint64_t stride = (uint64_t)gridDim.x * blockDim.x * 4;
     for (uint64_t k0 = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) * 4; k0 < count; k0 += stride) {
@@ -568,32 +824,14 @@ k_ranges(const uint32_t *__restrict__ tkey, const uint64_t *__restrict__ counts,
             const uint64_t k = k0 + j;
             if (k >= count) break;
             if (t[j + 1] != t[j]) {
-                if (t[j + 1] < n_tiles) ranges[2 * (uint64_t)t[j + 1]] = (uint32_t)k;
-                if (k > 0 && t[j] < n_tiles) ranges[2 * (uint64_t)t[j] + 1] = (uint32_t)k;
+                if (t[j + 1] < n_ids) ranges[2 * (uint64_t)t[j + 1]] = (uint32_t)k;
+                if (k > 0 && t[j] < n_ids) ranges[2 * (uint64_t)t[j] + 1] = (uint32_t)k;
             }
         }
         if (k0 + 4 >= count) {
             const uint32_t last = t[count - k0];
-            if (last < n_tiles) ranges[2 * (uint64_t)last + 1] = (uint32_t)count;
+            if (last < n_ids) ranges[2 * (uint64_t)last + 1] = (uint32_t)count;
         }
-    }
-}
-
-__global__ void __launch_bounds__(256)
-k_keys64(const uint32_t *__restrict__ tkey, const uint32_t *__restrict__ vals,
-         const uint64_t *__restrict__ counts, uint64_t cap, const gs_splat *__restrict__ splats,
-         int n, const gs_camera *__restrict__ cams, int V, int T, int64_t n_tiles,
-         uint64_t *__restrict__ keys)
-{
-    uint64_t count = counts[1];
-    count = count < cap ? count : cap;
-    uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
-    for (uint64_t k = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; k < count; k += stride) {
-        uint32_t t = tkey[k];
-        if (t >= n_tiles) continue;
-        ViewInfo vi = view_of_tile(cams, V, T, t);
-        float d = splats[(int64_t)vi.v * n + vals[k]].depth;
-        keys[k] = ((uint64_t)t << 32) | __float_as_uint(d);
     }
 }
 
@@ -616,7 +854,7 @@ hipError_t launch_fill_u32(uint32_t *p, uint32_t value, uint64_t count, hipStrea
 }
 
 hipError_t launch_bin_sort(const gs_splat *splats, int n, const gs_camera *cams_dev,
-                           const gs_camera *cams_host, int V, int64_t n_tiles, int tile_bits, int T,
+                           const gs_camera *cams_host, int V, int64_t n_tiles, int T,
                            const uint8_t *tile_level, const uint8_t *qbound, int n_levels,
                            uint32_t *vals, uint64_t *keys, uint64_t cap, uint32_t *ranges,
                            uint32_t *hits_out, uint64_t *num_keys, const BinScratch &bs,
@@ -632,22 +870,27 @@ hipError_t launch_bin_sort(const gs_splat *splats, int n, const gs_camera *cams_
     }
     const bool filt = tile_level != nullptr;
     const int L = n_levels < 1 ? 1 : (n_levels > 4 ? 4 : n_levels);
-    hipLaunchKernelGGL(k_view_table, dim3(1), dim3(64), 0, st, cams_dev, V, T, bs.vtab);
+    int64_t n_st = 0;
+    int max_view_tiles = 0;
+    for (int v = 0; v < V; ++v) {
+        const int tx = (cams_host[v].width + T - 1) / T, ty = (cams_host[v].height + T - 1) / T;
+        n_st += (int64_t)((tx + ST - 1) / ST) * ((ty + ST - 1) / ST);
+        max_view_tiles = tx * ty > max_view_tiles ? tx * ty : max_view_tiles;
+    }
+    hipLaunchKernelGGL(k_view_table, dim3(1), dim3(64), 0, st, cams_dev, V, T, bs.vtab, bs.stab);
     if (filt) {
-        int max_view_tiles = 0;
-        for (int v = 0; v < V; ++v) {
-            int t = ((cams_host[v].width + T - 1) / T) * ((cams_host[v].height + T - 1) / T);
-            max_view_tiles = t > max_view_tiles ? t : max_view_tiles;
-        }
         const int lds = max_view_tiles <= SAT_LDS_TILES;
         hipLaunchKernelGGL(k_level_sat, dim3(V * L), dim3(256), lds ? 4 * max_view_tiles : 0, st, cams_dev,
                            V, T, L, n_tiles, tile_level, bs.sat, bs.bbox, lds);
     }
+    const uint32_t *sat = filt ? bs.sat : nullptr;
+    if (filt)
+        hipLaunchKernelGGL(k_st_class, dim3((unsigned)((n_st + 3) / 4)), dim3(256), 0, st, bs.vtab, bs.stab, V, n_st,
+                           L, tile_level, bs.st_cls);
     const int64_t nb = (E + SCAN_THREADS * SCAN_ITEMS - 1) / (SCAN_THREADS * SCAN_ITEMS);
     // 1-2: counts, then stable compaction of entries with keys (depth digits counted)
     hipLaunchKernelGGL(k_count, dim3((unsigned)nb), dim3(SCAN_THREADS), 0, st, splats, n, cams_dev, V, T, bs.vtab,
-                       filt ? bs.sat : nullptr, bs.bbox, L, n_tiles, qbound, bs.hits, bs.rec, bs.dkey_b, hits_out,
-                       bs.block_vis);
+                       sat, bs.bbox, L, n_tiles, qbound, bs.hits, bs.rec, bs.dkey_b, hits_out, bs.block_vis);
     hipLaunchKernelGGL(k_scan_blocks, dim3(1), dim3(1024), 0, st, bs.block_sums, bs.block_vis, nb, bs.counts,
                        nullptr, nullptr);
     if ((err = launch_fill_u32(bs.rs.hist, 0u, 4 * 256, st)) != hipSuccess) return err;
@@ -657,32 +900,44 @@ hipError_t launch_bin_sort(const gs_splat *splats, int n, const gs_camera *cams_
     if ((err = radix_sort_pairs(bs.dkey_a, bs.dval_a, bs.dkey_b, bs.dval_b, bs.counts, (uint64_t)E, 32, bs.rs, st,
                                 true)) != hipSuccess)
         return err;
-    // 4: records in depth order, scans of counts and areas, emission
-    hipLaunchKernelGGL(k_gather, dim3((unsigned)nb), dim3(SCAN_THREADS), 0, st, bs.dval_a, bs.rec, bs.counts, n,
-                       bs.vtab, bs.rec_s, bs.hits_s, bs.block_sums, bs.block_sums2);
+    // 4a: records in depth order; totals of keys (capacity rule) and coarse pairs
+    hipLaunchKernelGGL(k_gather, dim3((unsigned)nb), dim3(GATHER_THREADS), 0, st, bs.dval_a, bs.rec, bs.counts, n,
+                       bs.vtab, bs.stab, sat, bs.st_cls, L, n_tiles, bs.rec_s, bs.cc_s, bs.block_sums, bs.block_sums2);
     hipLaunchKernelGGL(k_scan_blocks, dim3(1), dim3(1024), 0, st, bs.block_sums, nullptr, nb, bs.counts + 1,
                        bs.counts + 2, num_keys);
+    // coarse pairs <= keys, so a coarse total above the key total means overflow
     hipLaunchKernelGGL(k_scan_blocks, dim3(1), dim3(1024), 0, st, bs.block_sums2, nullptr, nb, bs.counts + 3,
-                       nullptr, nullptr);
-    hipLaunchKernelGGL(k_scan_down, dim3((unsigned)nb), dim3(SCAN_THREADS), 0, st, bs.rec_s, bs.hits_s, bs.counts,
-                       bs.block_sums, bs.block_sums2, bs.hpre, bs.apre, bs.slice);
-    const int passes = radix_passes(tile_bits);
-    // emission goes to the buffer from which an even/odd number of passes
-    // ends in the caller's vals
-    uint32_t *ek = bs.tkey_a, *ev = (passes % 2 == 0) ? vals : bs.tval_b;
-    uint32_t *ok = bs.tkey_b, *ov = (passes % 2 == 0) ? bs.tval_b : vals;
-    hipLaunchKernelGGL(k_emit, dim3(2048), dim3(256), 0, st, bs.rec_s, bs.hpre, bs.apre, bs.slice, bs.counts,
-                       tile_level, filt ? bs.sat : nullptr, L, n_tiles, cap, ek, ev);
-    // 5: tile sort
-    if ((err = radix_sort_pairs(ek, ev, ok, ov, bs.counts + 1, cap, tile_bits, bs.rs, st, false)) !=
-        hipSuccess)
+                       bs.counts + 1, nullptr);
+    // 4b: coarse pairs, stably sorted by super-tile; the sorted values end in tval_b
+    int st_bits = 1;
+    while ((int64_t(1) << st_bits) < n_st) ++st_bits;
+    const bool even = radix_passes(st_bits) % 2 == 0;
+    uint32_t *ka = bs.tkey_a, *va = even ? bs.tval_b : vals, *kb = bs.tkey_b, *vb = even ? vals : bs.tval_b;
+    hipLaunchKernelGGL(k_coarse_emit, dim3((unsigned)nb), dim3(GATHER_THREADS), 0, st, bs.rec_s, bs.cc_s, bs.counts,
+                       bs.block_sums2, bs.vtab, bs.stab, sat, bs.st_cls, L, n_tiles, ka, va);
+    if ((err = radix_sort_pairs(ka, va, kb, vb, bs.counts + 3, cap, st_bits, bs.rs, st, false)) != hipSuccess)
         return err;
-    const uint32_t *sorted_t = (passes % 2 == 0) ? ek : ok;
-    // 6: ranges
-    hipLaunchKernelGGL(k_ranges, dim3(grid_for(cap, 256 * 16, 8192)), dim3(256), 0, st, sorted_t, bs.counts,
-                       cap, n_tiles, ranges);
-    if (keys)
-        hipLaunchKernelGGL(k_keys64, dim3(grid_for(cap, 256 * 8, 8192)), dim3(256), 0, st, sorted_t, vals,
-                           bs.counts, cap, splats, n, cams_dev, V, T, n_tiles, keys);
+    const uint32_t *sk = even ? ka : kb;
+    if ((err = launch_fill_u32(bs.st_ranges, 0u, 2 * (uint64_t)n_st, st)) != hipSuccess) return err;
+    hipLaunchKernelGGL(k_ranges, dim3(grid_for(cap, 256 * 16, 8192)), dim3(256), 0, st, sk, bs.counts + 3, cap,
+                       n_st, bs.st_ranges);
+    hipLaunchKernelGGL(k_chunk_table, dim3(1), dim3(1024), 0, st, bs.st_ranges, n_st, bs.chunk_off, bs.chunk_st,
+                       bs.counts + 4);
+    // 4c-4e: per-tile counts, their scans (tile ranges), keys at their final positions
+    const int pass_blocks = grid_for(bin_max_chunks(cap, n_tiles), 4, 2048);
+    hipLaunchKernelGGL((k_tile_pass<false>), dim3(pass_blocks), dim3(256), 0, st, bs.tval_b, bs.st_ranges,
+                       bs.chunk_off, bs.chunk_st, bs.counts, bs.rec_s, bs.vtab, bs.stab, V, n, tile_level, bs.ccnt,
+                       ranges, vals, keys, splats);
+    hipLaunchKernelGGL(k_col_scan, dim3((unsigned)n_st), dim3(COL_WAVES * 64), 0, st, bs.chunk_off, bs.vtab, bs.stab, V,
+                       bs.ccnt, bs.tot);
+    const int64_t nbt = (n_tiles + SCAN_THREADS * SCAN_ITEMS - 1) / (SCAN_THREADS * SCAN_ITEMS);
+    hipLaunchKernelGGL(k_tile_reduce, dim3((unsigned)nbt), dim3(SCAN_THREADS), 0, st, bs.tot, n_tiles, bs.tsum);
+    hipLaunchKernelGGL(k_scan_blocks, dim3(1), dim3(1024), 0, st, bs.tsum, nullptr, nbt, bs.counts + 5, nullptr,
+                       nullptr);
+    hipLaunchKernelGGL(k_tile_ranges, dim3((unsigned)nbt), dim3(SCAN_THREADS), 0, st, bs.tot, n_tiles, bs.tsum,
+                       bs.counts, ranges);
+    hipLaunchKernelGGL((k_tile_pass<true>), dim3(pass_blocks), dim3(256), 0, st, bs.tval_b, bs.st_ranges,
+                       bs.chunk_off, bs.chunk_st, bs.counts, bs.rec_s, bs.vtab, bs.stab, V, n, tile_level, bs.ccnt,
+                       ranges, vals, keys, splats);
     return hipGetLastError();
 }

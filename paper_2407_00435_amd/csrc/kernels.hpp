@@ -56,28 +56,39 @@ hipError_t radix_sort_standalone(uint32_t *keys, uint32_t *vals, uint32_t *kt, u
                                  int bits, void *ws, bool *in_tmp, hipStream_t st);
 
 // binning
+constexpr int SCAN_THREADS = 256;
+constexpr int SCAN_ITEMS = 16;
+constexpr int BIN_SUPER_TILE = 8;   // super-tile side in tiles (one wave lane per tile)
+constexpr uint32_t BIN_CHUNK = 256; // coarse pairs per chunk of the per-tile counting passes
+// chunks of the counting passes: each super-tile's run of coarse pairs (at
+// most the keys) is cut into chunks of BIN_CHUNK, and there are at most
+// n_tiles super-tiles
+inline uint64_t bin_max_chunks(uint64_t cap, int64_t n_tiles) { return cap / BIN_CHUNK + (uint64_t)n_tiles + 1; }
 struct BinScratch {
     uint32_t *dkey_a, *dval_a, *dkey_b, *dval_b;  // [E] depth sort ping-pong
     uint32_t *hits;                               // [E]
     uint4 *rec;                                   // [E] rectangle, count, quality bound (entries with keys)
-    uint4 *rec_s;                                 // [E] the same in depth order, tile-id form
-    uint32_t *hits_s;                             // [E] counts in depth order
-    uint64_t *hpre, *apre;                        // [E] key / rectangle-area offsets in depth order
-    uint32_t *slice;                              // [BIN_MAX_SLICES] first entry of each emission slice
+    uint4 *rec_s;                                 // [E] rectangle, entry, view and quality bound in depth order
+    uint32_t *cc_s;                               // [E] coarse pairs of each entry in depth order
     uint32_t *block_vis;                          // [E / SCAN_ITEMS + 1] entries with keys per block
     uint64_t *block_sums, *block_sums2;           // [E / SCAN_ITEMS + 1]
     int64_t *vtab;                                // [2V] first tile and tiles_x of each view
-    uint32_t *tkey_a, *tkey_b, *tval_b;           // [cap] tile-key sort ping-pong
-    uint64_t *counts;                             // [4]: entries, keys, key capacity, rectangle area
+    int4 *stab;                                   // [V] first super-tile, super-tiles per row, tiles_x, tiles_y
+    uint32_t *tkey_a, *tkey_b, *tval_b;           // [cap] coarse-pair sort ping-pong
+    uint32_t *st_ranges;                          // [n_tiles][2] run of each super-tile in the sorted pairs
+    uint8_t *st_cls;                              // [n_tiles][4] per super-tile and level: keeps none/all/part
+    uint32_t *chunk_off;                          // [n_tiles + 1] first chunk of each super-tile
+    uint32_t *chunk_st;                           // [bin_max_chunks] super-tile of each chunk
+    uint32_t *ccnt;                               // [bin_max_chunks][64] per-chunk tile counts, then prefixes
+    uint32_t *tot;                                // [n_tiles] keys per tile
+    uint64_t *tsum;                               // [n_tiles / SCAN_ITEMS + 1] block sums of tot
+    uint64_t *counts;                             // [8]: entries, keys, capacity, coarse pairs, chunks, keys
     uint32_t *sat;                                // [4][n_tiles] level summed-area tables
     int32_t *bbox;                                // [V][4][4] bounding box of each level's kept tiles
     RadixScratch rs;
 };
-constexpr int SCAN_THREADS = 256;
-constexpr int64_t BIN_MAX_SLICES = 1 << 20;
-constexpr int SCAN_ITEMS = 16;
 hipError_t launch_bin_sort(const gs_splat *splats, int n, const gs_camera *cams_dev,
-                           const gs_camera *cams_host, int V, int64_t n_tiles, int tile_bits, int T,
+                           const gs_camera *cams_host, int V, int64_t n_tiles, int T,
                            const uint8_t *tile_level, const uint8_t *qbound, int n_levels,
                            uint32_t *vals, uint64_t *keys, uint64_t cap,
                            uint32_t *ranges, uint32_t *hits_out, uint64_t *num_keys,

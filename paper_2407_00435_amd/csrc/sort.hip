@@ -6,7 +6,9 @@
 // ticket order and every predecessor is already resident), ranks its keys
 // stably with wave64 ballot matching, publishes its per-digit counts, and
 // resolves its global offsets by decoupled lookback over predecessor
-// partitions before scattering through LDS in coalesced runs.
+// partitions before scattering through LDS in coalesced runs.  The grid is
+// persistent: a workgroup takes tickets until the partitions run out, so
+// every partition it waits on belongs to a workgroup that is already running.
 //
 // Digits are at most 8 bits wide and equal across passes (a 14-bit key sorts
 // in two 7-bit passes).  The partition size (keys per workgroup) trades the
@@ -24,6 +26,7 @@ constexpr uint64_t FLAG_AGG = 1ull << 62;
 constexpr uint64_t FLAG_INC = 2ull << 62;
 constexpr uint64_t VAL_MASK = (1ull << 62) - 1;
 constexpr int MIN_PART = 4096;
+constexpr uint64_t SWEEP_BLOCKS = 1024;  // persistent onesweep workgroups (at most)
 
 // Digit counts of every pass.  Each thread takes HIST_RUN consecutive keys
 // and adds runs of equal digits with one LDS atomic (key lists built in
@@ -133,116 +136,121 @@ k_radix_onesweep(const uint32_t *__restrict__ kin, const uint32_t *__restrict__ 
 
     const int t = threadIdx.x;
     const int wave = t >> 6, lane = t & 63;
-    if (t == 0) s_part = atomicAdd(ticket, 1u);
-    for (int j = t; j < WAVES * 256; j += THREADS) (&s_whist[0][0])[j] = 0;
-    __syncthreads();
-    const uint64_t part = s_part;
     uint64_t count = *d_count;
     count = count < cap ? count : cap;
     const uint64_t nparts = (count + PART - 1) / PART;
-    if (part >= nparts) return;
+    // persistent: partitions are taken in ticket order until none is left
+    for (;;) {
+        if (t == 0) s_part = atomicAdd(ticket, 1u);
+        for (int j = t; j < WAVES * 256; j += THREADS) (&s_whist[0][0])[j] = 0;
+        __syncthreads();
+        const uint64_t part = s_part;
+        if (part >= nparts) return;
 
-    const uint64_t pbase = part * PART;
-    const uint64_t wbase = pbase + (uint64_t)wave * (ITEMS * 64);
-    uint32_t k[ITEMS], v[ITEMS], rk[ITEMS];
+        const uint64_t pbase = part * PART;
+        const uint64_t wbase = pbase + (uint64_t)wave * (ITEMS * 64);
+        uint32_t k[ITEMS], v[ITEMS], rk[ITEMS];
 #pragma unroll
-    for (int r = 0; r < ITEMS; ++r) {
-        uint64_t idx = wbase + (uint64_t)r * 64 + lane;
-        bool ok = idx < count;
-        k[r] = ok ? kin[idx] : 0xFFFFFFFFu;
-        v[r] = ok ? vin[idx] : 0u;
-    }
-    const uint64_t lt = lanemask_lt();
-    // stable rank within the wave: items in (round, lane) order
+        for (int r = 0; r < ITEMS; ++r) {
+            uint64_t idx = wbase + (uint64_t)r * 64 + lane;
+            bool ok = idx < count;
+            k[r] = ok ? kin[idx] : 0xFFFFFFFFu;
+            v[r] = ok ? vin[idx] : 0u;
+        }
+        const uint64_t lt = lanemask_lt();
+        // stable rank within the wave: items in (round, lane) order
 #pragma unroll
-    for (int r = 0; r < ITEMS; ++r) {
-        uint64_t idx = wbase + (uint64_t)r * 64 + lane;
-        bool ok = idx < count;
-        uint32_t d = (k[r] >> shift) & mask;
-        uint64_t peers = ballot64(ok);
-        for (int b = 0; b < dbits; ++b) {
-            bool bit = (d >> b) & 1u;
-            uint64_t bb = ballot64(bit);
-            peers &= bit ? bb : ~bb;
-        }
-        uint32_t before = (uint32_t)__popcll(peers & lt);
-        uint32_t prev = s_whist[wave][d];
-        rk[r] = prev + before;
-        wave_lds_sync();
-        if (ok && before == 0) s_whist[wave][d] = prev + (uint32_t)__popcll(peers);
-        wave_lds_sync();
-    }
-    __syncthreads();
-    // per digit (threads < 256): exclusive over waves, block total, lookback
-    const bool dig = t < 256;
-    uint32_t total = 0;
-    uint64_t prefix = 0;
-    if (dig) {
-#pragma unroll
-        for (int w = 0; w < WAVES; ++w) {
-            uint32_t c = s_whist[w][t];
-            s_whist[w][t] = total;
-            total += c;
-        }
-        uint64_t *my = status + part * 256 + t;
-        if (part == 0) {
-            __hip_atomic_store(my, FLAG_INC | (uint64_t)total, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        } else {
-            __hip_atomic_store(my, FLAG_AGG | (uint64_t)total, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        }
-        if (part > 0 && (uint32_t)t <= mask) {
-            int64_t q = (int64_t)part - 1;
-            for (;;) {
-                uint64_t st = __hip_atomic_load(status + q * 256 + t, __ATOMIC_RELAXED,
-                                                __HIP_MEMORY_SCOPE_AGENT);
-                uint64_t flag = st & ~VAL_MASK;
-                if (flag == 0) {
-                    __builtin_amdgcn_s_sleep(1);
-                    continue;
-                }
-                prefix += st & VAL_MASK;
-                if (flag == FLAG_INC) break;
-                --q;
-            }
-            __hip_atomic_store(my, FLAG_INC | (prefix + total), __ATOMIC_RELAXED,
-                               __HIP_MEMORY_SCOPE_AGENT);
-        }
-        s_bexcl[t] = total;
-    }
-    __syncthreads();
-    // block-local exclusive prefix over digits (Hillis-Steele in LDS)
-    for (int off = 1; off < 256; off <<= 1) {
-        uint32_t add = (dig && t >= off) ? s_bexcl[t - off] : 0u;
-        __syncthreads();
-        if (dig) s_bexcl[t] += add;
-        __syncthreads();
-    }
-    uint32_t bexcl = dig ? s_bexcl[t] - total : 0u;
-    __syncthreads();
-    if (dig) {
-        s_bexcl[t] = bexcl;
-        s_dbase[t] = (uint64_t)gbase[t] + prefix;
-    }
-    __syncthreads();
-    // scatter into LDS in digit order
-#pragma unroll
-    for (int r = 0; r < ITEMS; ++r) {
-        uint64_t idx = wbase + (uint64_t)r * 64 + lane;
-        if (idx < count) {
+        for (int r = 0; r < ITEMS; ++r) {
+            uint64_t idx = wbase + (uint64_t)r * 64 + lane;
+            bool ok = idx < count;
             uint32_t d = (k[r] >> shift) & mask;
-            uint32_t pos = s_bexcl[d] + s_whist[wave][d] + rk[r];
-            s_keys[pos] = k[r];
-            s_vals[pos] = v[r];
+            uint64_t peers = ballot64(ok);
+            for (int b = 0; b < dbits; ++b) {
+                bool bit = (d >> b) & 1u;
+                uint64_t bb = ballot64(bit);
+                peers &= bit ? bb : ~bb;
+            }
+            uint32_t before = (uint32_t)__popcll(peers & lt);
+            uint32_t prev = s_whist[wave][d];
+            rk[r] = prev + before;
+            wave_lds_sync();
+            if (ok && before == 0) s_whist[wave][d] = prev + (uint32_t)__popcll(peers);
+            wave_lds_sync();
         }
-    }
-    __syncthreads();
-    uint32_t pcount = (uint32_t)((count - pbase) < (uint64_t)PART ? (count - pbase) : PART);
-    for (uint32_t j = t; j < pcount; j += THREADS) {
-        uint32_t key = s_keys[j];
-        uint32_t d = (key >> shift) & mask;
-        uint64_t dst = s_dbase[d] + (j - s_bexcl[d]);
-        kout[dst] = key;
-        vout[dst] = s_vals[j];
+        __syncthreads();
+        // per digit (threads < 256): exclusive over waves, block total, lookback
+        const bool dig = t < 256;
+        uint32_t total = 0;
+        uint64_t prefix = 0;
+        if (dig) {
+#pragma unroll
+            for (int w = 0; w < WAVES; ++w) {
+                uint32_t c = s_whist[w][t];
+                s_whist[w][t] = total;
+                total += c;
+            }
+            uint64_t *my = status + part * 256 + t;
+            if (part == 0) {
+                __hip_atomic_store(my, FLAG_INC | (uint64_t)total, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            } else {
+                __hip_atomic_store(my, FLAG_AGG | (uint64_t)total, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            }
+            if (part > 0 && (uint32_t)t <= mask) {
+                int64_t q = (int64_t)part - 1;
+                for (;;) {
+                    uint64_t st = __hip_atomic_load(status + q * 256 + t, __ATOMIC_RELAXED,
+                                                    __HIP_MEMORY_SCOPE_AGENT);
+                    uint64_t flag = st & ~VAL_MASK;
+                    if (flag == 0) {
+                        __builtin_amdgcn_s_sleep(1);
+                        continue;
+                    }
+                    prefix += st & VAL_MASK;
+                    if (flag == FLAG_INC) break;
+                    --q;
+                }
+                __hip_atomic_store(my, FLAG_INC | (prefix + total), __ATOMIC_RELAXED,
+                                   __HIP_MEMORY_SCOPE_AGENT);
+            }
+            s_bexcl[t] = total;
+        }
+        __syncthreads();
+        // block-local exclusive prefix over digits (Hillis-Steele in LDS)
+        for (int off = 1; off < 256; off <<= 1) {
+            uint32_t add = (dig && t >= off) ? s_bexcl[t - off] : 0u;
+            __syncthreads();
+            if (dig) s_bexcl[t] += add;
+            __syncthreads();
+        }
+        uint32_t bexcl = dig ? s_bexcl[t] - total : 0u;
+        __syncthreads();
+        if (dig) {
+            s_bexcl[t] = bexcl;
+            s_dbase[t] = (uint64_t)gbase[t] + prefix;
+        }
+        __syncthreads();
+        // scatter into LDS in digit order
+#pragma unroll
+        for (int r = 0; r < ITEMS; ++r) {
+            uint64_t idx = wbase + (uint64_t)r * 64 + lane;
+            if (idx < count) {
+                uint32_t d = (k[r] >> shift) & mask;
+                uint32_t pos = s_bexcl[d] + s_whist[wave][d] + rk[r];
+                s_keys[pos] = k[r];
+                s_vals[pos] = v[r];
+            }
+        }
+        __syncthreads();
+        uint32_t pcount = (uint32_t)((count - pbase) < (uint64_t)PART ? (count - pbase) : PART);
+        for (uint32_t j = t; j < pcount; j += THREADS) {
+            uint32_t key = s_keys[j];
+            uint32_t d = (key >> shift) & mask;
+            uint64_t dst = s_dbase[d] + (j - s_bexcl[d]);
+            kout[dst] = key;
+            vout[dst] = s_vals[j];
+        }
+        // the next partition reuses every LDS array
+        __syncthreads();
     }
 }
 
@@ -295,13 +303,17 @@ hipError_t radix_sort_pairs(uint32_t *ka, uint32_t *va, uint32_t *kb, uint32_t *
     }
     hipLaunchKernelGGL(k_radix_prefix, dim3(passes), dim3(256), 0, st, rs.hist);
     uint32_t *src_k = ka, *src_v = va, *dst_k = kb, *dst_v = vb;
+    // the grid is sized for the capacity; a persistent grid of at most
+    // SWEEP_BLOCKS workgroups keeps the cost of an over-sized capacity
+    // (workgroups that start only to find no partition) bounded
+    const unsigned sweep_blocks = (unsigned)(parts < SWEEP_BLOCKS ? parts : SWEEP_BLOCKS);
     int clear_blocks = (int)((parts * 256 + 255) / 256);
     if (clear_blocks > 4096) clear_blocks = 4096;
     for (int p = 0; p < passes; ++p) {
         hipLaunchKernelGGL(k_radix_clear, dim3(clear_blocks), dim3(256), 0, st, rs.status,
                            rs.tickets + p, d_count, cap, P);
 #define GS_OS(TH, IT)                                                                                \
-    hipLaunchKernelGGL((k_radix_onesweep<TH, IT>), dim3((unsigned)parts), dim3(TH), 0, st, src_k,  \
+    hipLaunchKernelGGL((k_radix_onesweep<TH, IT>), dim3(sweep_blocks), dim3(TH), 0, st, src_k,     \
                        src_v, dst_k, dst_v, d_count, cap, dbits * p, mask, dbits,                  \
                        rs.hist + 256 * p, rs.status, rs.tickets + p)
         if (P == 4096)
