@@ -121,7 +121,7 @@ void carve_bin(Carve &c, int V, int64_t E, uint64_t cap, int64_t tiles, BinScrat
     bs.st_cls = c.take<uint8_t>(4 * tiles);
     bs.chunk_off = c.take<uint32_t>(4 * (tiles + 1));
     bs.chunk_st = c.take<uint32_t>(4 * chunks);
-    bs.ccnt = c.take<uint32_t>(4 * 64 * chunks);
+    bs.ccnt = c.take<uint32_t>(4 * BIN_SUPER_TILE * BIN_SUPER_TILE * chunks);
     bs.tot = c.take<uint32_t>(4 * tiles);
     bs.tsum = c.take<uint64_t>(8 * (tiles / (SCAN_THREADS * SCAN_ITEMS) + 1));
     bs.counts = c.take<uint64_t>(8 * 8);

@@ -22,7 +22,9 @@
 namespace {
 
 constexpr int SAT_LDS_TILES = 16384;      // views up to this many tiles build their tables in LDS (64 KB)
-constexpr int ST = BIN_SUPER_TILE;        // super-tile side in tiles (ST * ST = wave size)
+constexpr int ST = BIN_SUPER_TILE;        // super-tile side in tiles
+constexpr int TST = ST * ST;              // tiles per super-tile (<= wave size)
+constexpr int MS = 4;                     // coarse masks cover spans of up to MS x MS super-tiles
 constexpr uint32_t CHUNK = BIN_CHUNK;     // coarse pairs per chunk
 
 __global__ void k_set_u64(uint64_t *__restrict__ p, uint64_t value) { *p = value; }
@@ -307,7 +309,7 @@ k_st_class(const int64_t *__restrict__ vtab, const int4 *__restrict__ stab, int 
     const int4 sb = stab[v];
     const int sl = (int)s - sb.x, sy = sl / sb.y, sx = sl - sy * sb.y;
     const int tx = sx * ST + lane % ST, ty = sy * ST + lane / ST;
-    const bool valid = tx < sb.z && ty < sb.w;
+    const bool valid = lane < TST && tx < sb.z && ty < sb.w;
     const uint32_t lvl = valid ? tl[2 * (vtab[2 * v] + (int64_t)ty * sb.z + tx)] : 255u;
     const int nv = __popcll(ballot64(valid));
     for (int m = 1; m <= L; ++m) {
@@ -371,24 +373,22 @@ __device__ __forceinline__ uint32_t coarse_walk(uint32_t rx, uint32_t ry, uint32
     return c;
 }
 
-// Coarse pairs of an entry whose rectangle spans at most 2 x 2 super-tiles,
-// as a mask: bit dy * 2 + dx for super-tile (sx0 + dx, sy0 + dy).  Larger
-// spans have no mask (coarse_walk is run again to emit them).
-__device__ __forceinline__ uint32_t coarse_mask(uint32_t rx, uint32_t ry, uint32_t m, int v,
+// Coarse pairs of an entry whose rectangle spans at most MS x MS super-tiles,
+// as a mask: bit dy * MS + dx for super-tile (sx0 + dx, sy0 + dy).  Larger
+// spans have no mask (coarse_walk is run again to emit them).  Encoded count:
+// bit 31 set -> mask in bits 0..15 and count in bits 16..20; else the count.
+__device__ __forceinline__ uint32_t cc_count(uint32_t cc) { return (cc >> 31) ? (cc >> 16) & 31u : cc; }
+
+__device__ __forceinline__ uint32_t coarse_code(uint32_t rx, uint32_t ry, uint32_t m, int v,
                                                 const int64_t *__restrict__ vtab, const int4 *__restrict__ stab,
                                                 const uint32_t *__restrict__ sat, const uint8_t *__restrict__ cls,
-                                                int L, int64_t n_tiles, uint32_t &count)
+                                                int L, int64_t n_tiles)
 {
     const int x0 = (int)(rx & 0xffffu), y0 = (int)(rx >> 16), x1 = (int)(ry & 0xffffu), y1 = (int)(ry >> 16);
     const int sx0 = x0 / ST, sx1 = x1 / ST, sy0 = y0 / ST, sy1 = y1 / ST;
-    if (sx1 - sx0 > 1 || sy1 - sy0 > 1) {
-        count = coarse_walk<false>(rx, ry, m, v, 0u, vtab, stab, sat, cls, L, n_tiles, nullptr, nullptr, 0);
-        return 0u;
-    }
-    if (sx0 == sx1 && sy0 == sy1) {
-        count = 1u;
-        return 1u;
-    }
+    if (sx1 - sx0 >= MS || sy1 - sy0 >= MS)
+        return coarse_walk<false>(rx, ry, m, v, 0u, vtab, stab, sat, cls, L, n_tiles, nullptr, nullptr, 0);
+    if (sx0 == sx1 && sy0 == sy1) return 0x80000000u | (1u << 16) | 1u;
     const int4 sb = stab[v];
     const int ml = (int)m < L ? (int)m : L;
     const uint32_t *s = sat ? sat + (int64_t)(ml - 1) * n_tiles + vtab[2 * v] : nullptr;
@@ -409,16 +409,15 @@ __device__ __forceinline__ uint32_t coarse_mask(uint32_t rx, uint32_t ry, uint32
                     keep = k == 1;
                 }
             }
-            mask |= keep ? 1u << (dy * 2 + dx) : 0u;
+            mask |= keep ? 1u << (dy * MS + dx) : 0u;
         }
     }
-    count = (uint32_t)__popc(mask);
-    return mask;
+    return 0x80000000u | ((uint32_t)__popc(mask) << 16) | mask;
 }
 
 // 4a. gather the records in depth order: rec_s[r] = {x0 | y0 << 16,
-// x1 | y1 << 16, entry, view << 8 | quality bound}; cc_s[r] = its number of
-// coarse pairs | the coarse mask << 28; per-block sums of key counts and
+// x1 | y1 << 16, entry, view << 8 | quality bound}; cc_s[r] = its coarse
+// pairs (count, or count and mask, as coarse_code); per-block sums of key counts and
 // coarse pairs.  A block takes SCAN_THREADS * SCAN_ITEMS entries with
 // GATHER_THREADS threads, each issuing its loads for all its entries first.
 constexpr int GATHER_THREADS = 1024;
@@ -448,12 +447,11 @@ k_gather(const uint32_t *__restrict__ order, const uint4 *__restrict__ rec, cons
         const int64_t r = base + (int64_t)j * GATHER_THREADS + threadIdx.x;
         const int v = (int)(e[j] / (uint32_t)n);
         const uint32_t m = q[j].w & 255u;
-        uint32_t cc;
-        const uint32_t mask = coarse_mask(q[j].x, q[j].y, m, v, vtab, stab, sat, cls, L, n_tiles, cc);
+        const uint32_t code = coarse_code(q[j].x, q[j].y, m, v, vtab, stab, sat, cls, L, n_tiles);
         rec_s[r] = make_uint4(q[j].x, q[j].y, e[j], ((uint32_t)v << 8) | m);
-        cc_s[r] = cc | (mask << 28);
+        cc_s[r] = code;
         acc_h += q[j].z;
-        acc_c += cc;
+        acc_c += cc_count(code);
     }
     for (int off = 32; off > 0; off >>= 1) {
         acc_h += __shfl_xor(acc_h, off);
@@ -501,7 +499,7 @@ k_coarse_emit(const uint4 *__restrict__ rec_s, const uint32_t *__restrict__ cc_s
     }
 #pragma unroll
     for (int j = 0; j < GATHER_ITEMS; ++j) {
-        x[j] = c[j] & 0x0FFFFFFFu;
+        x[j] = cc_count(c[j]);
         for (int off = 1; off < 64; off <<= 1) {
             const uint32_t y = __shfl_up(x[j], off);
             if (lane >= off) x[j] += y;
@@ -519,17 +517,18 @@ k_coarse_emit(const uint4 *__restrict__ rec_s, const uint32_t *__restrict__ cc_s
             tw += vw;
         }
         const int64_t r = base + (int64_t)j * GATHER_THREADS + threadIdx.x;
-        const uint32_t cnt = c[j] & 0x0FFFFFFFu, mask = c[j] >> 28;
+        const uint32_t cnt = cc_count(c[j]);
         const uint64_t pos = run + pw + x[j] - cnt;
         if (cnt) {
             const int v = (int)(q[j].w >> 8);
-            if (mask) {
+            if (c[j] >> 31) {
                 const int4 sb = stab[v];
                 const int sx0 = (int)(q[j].x & 0xffffu) / ST, sy0 = (int)(q[j].x >> 16) / ST;
-                uint32_t k = 0;
-                for (int bit = 0; bit < 4; ++bit) {
-                    if (!(mask & (1u << bit))) continue;
-                    ck[pos + k] = (uint32_t)(sb.x + (sy0 + (bit >> 1)) * sb.y + sx0 + (bit & 1));
+                uint32_t mask = c[j] & 0xffffu, k = 0;
+                while (mask) {
+                    const int bit = __ffs(mask) - 1;
+                    mask &= mask - 1u;
+                    ck[pos + k] = (uint32_t)(sb.x + (sy0 + bit / MS) * sb.y + sx0 + bit % MS);
                     cv[pos + k] = (uint32_t)r;
                     ++k;
                 }
@@ -591,14 +590,23 @@ __device__ __forceinline__ int view_of_st(const int4 *__restrict__ stab, int V, 
 }
 
 // 4c/4e. One wave per chunk of a super-tile's run.  Lane j of batch q holds
-// entry b + 64 q + j of the chunk; the wave visits the tiles of the super-tile
-// that the chunk's rectangles reach (row-major) and tests all the chunk's
-// entries against each at once.  COUNT: ccnt[c][l] = entries of the chunk
-// that keep tile l of the super-tile.  WRITE: the kept entries' point
-// indices (and optional 64-bit keys), compacted by ballot, at the tile's
-// start + the chunk's exclusive prefix (ccnt after k_col_scan): a tile's
-// keys of one batch are one contiguous store.
+// entry b + 64 q + j of the chunk as a mask of the super-tile's tiles it keeps
+// (bit l = tile (l % ST, l / ST): inside its rectangle and, with the level
+// filter, of lower level <= its quality bound).  The wave visits the tiles
+// in the union of the masks; per tile and batch a ballot of the mask bits
+// gives the covering entries in order.  COUNT: ccnt[c][l] = entries of the
+// chunk that keep tile l.  WRITE: their point indices (and optional 64-bit
+// keys), ranked by mbcnt, at the tile's start + the chunk's exclusive prefix
+// (ccnt after k_col_scan) + the running count: a tile's keys of one batch
+// are one contiguous store.
 constexpr int NB = CHUNK / 64;  // batches of 64 entries per chunk
+// bit y * ST of every row y < ST: spreads an ST-bit row mask over all rows
+__host__ __device__ constexpr uint64_t row_spread()
+{
+    uint64_t r = 0;
+    for (int y = 0; y < ST; ++y) r |= 1ull << (y * ST);
+    return r;
+}
 template <bool WRITE>
 __global__ void __launch_bounds__(256)
 k_tile_pass(const uint32_t *__restrict__ cv, const uint32_t *__restrict__ st_ranges,
@@ -608,15 +616,14 @@ k_tile_pass(const uint32_t *__restrict__ cv, const uint32_t *__restrict__ st_ran
             const uint32_t *__restrict__ ranges, uint32_t *__restrict__ vals, uint64_t *__restrict__ keys,
             const gs_splat *__restrict__ splats)
 {
-    // per-tile level and output position of the wave's super-tile, read
-    // back with uniform LDS loads inside the tile loop (a register loaded
-    // from memory would make every iteration wait for the stores before it)
-    __shared__ uint32_t s_lvl[4][64], s_pos[4][64];
+    // output position of each tile of the wave's super-tile, read back with
+    // uniform LDS loads inside the tile loop (a register loaded from memory
+    // would make every iteration wait for the stores before it)
+    __shared__ uint32_t s_pos[4][TST];
     if (counts[1] == 0) return;  // no keys, or more than the capacity
     const uint64_t nc = counts[4];
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
-    const uint64_t lt = lanemask_lt();
     const uint64_t waves = (uint64_t)gridDim.x * (blockDim.x / 64);
     for (uint64_t c = (uint64_t)blockIdx.x * (blockDim.x / 64) + wave; c < nc; c += waves) {
         const uint32_t s = chunk_st[c];
@@ -628,69 +635,81 @@ k_tile_pass(const uint32_t *__restrict__ cv, const uint32_t *__restrict__ st_ran
         const int sl = (int)s - sb.x, sy = sl / sb.y, sx = sl - sy * sb.y;
         const int bx = sx * ST, by = sy * ST;
         const int64_t toff = vtab[2 * v];
+        // per level m: the super-tile's tiles whose lower level is <= m
+        uint64_t lvm1 = ~0ull, lvm2 = ~0ull, lvm3 = ~0ull, lvm4 = ~0ull;
         {
             const int mtx = bx + lane % ST, mty = by + lane / ST;
-            const bool mvalid = mtx < sb.z && mty < sb.w;
+            const bool mvalid = lane < TST && mtx < sb.z && mty < sb.w;
             const int64_t mg = toff + (int64_t)mty * sb.z + mtx;
-            s_lvl[wave][lane] = (tl && mvalid) ? (uint32_t)tl[2 * mg] : 0u;
-            if (WRITE) s_pos[wave][lane] = mvalid ? ranges[2 * mg] + ccnt[c * 64 + lane] : 0u;
+            if (tl) {
+                const uint32_t lvl = mvalid ? (uint32_t)tl[2 * mg] : 255u;
+                lvm1 = __builtin_amdgcn_ballot_w64(lvl <= 1u);
+                lvm2 = __builtin_amdgcn_ballot_w64(lvl <= 2u);
+                lvm3 = __builtin_amdgcn_ballot_w64(lvl <= 3u);
+                lvm4 = __builtin_amdgcn_ballot_w64(lvl <= 4u);
+            }
+            if (WRITE && lane < TST) s_pos[wave][lane] = mvalid ? ranges[2 * mg] + ccnt[c * TST + lane] : 0u;
         }
-        // the chunk's entries and the bounding box of their rectangles
-        int x0[NB], x1[NB], y0[NB], y1[NB];
-        uint32_t mw[NB], ez[NB];
-        int ux0 = 0x7fff, uy0 = 0x7fff, ux1 = -1, uy1 = -1;
+        // the chunk's entries as tile masks, and their union
+        uint32_t mlo[NB], mhi[NB], ez[NB];
+        uint64_t uni = 0;
 #pragma unroll
         for (int q = 0; q < NB; ++q) {
             const uint32_t j = b + 64u * q + (uint32_t)lane;
-            x0[q] = y0[q] = 0x7fff;
-            x1[q] = y1[q] = -1;
-            mw[q] = ez[q] = 0u;
+            uint64_t tm = 0;
+            ez[q] = 0u;
             if (j < e_end) {
                 const uint4 R = rec_s[cv[j]];
-                x0[q] = (int)(R.x & 0xffffu);
-                y0[q] = (int)(R.x >> 16);
-                x1[q] = (int)(R.y & 0xffffu);
-                y1[q] = (int)(R.y >> 16);
+                const int cx0 = max((int)(R.x & 0xffffu) - bx, 0), cx1 = min((int)(R.y & 0xffffu) - bx, ST - 1);
+                const int cy0 = max((int)(R.x >> 16) - by, 0), cy1 = min((int)(R.y >> 16) - by, ST - 1);
+                if (cx0 <= cx1 && cy0 <= cy1) {
+                    const uint64_t cols = (2ull << cx1) - (1ull << cx0);
+                    const int hb = (cy1 + 1) * ST;
+                    const uint64_t rows = (hb >= 64 ? ~0ull : (1ull << hb) - 1ull) & ~((1ull << (cy0 * ST)) - 1ull);
+                    tm = cols * row_spread() & rows;
+                    const uint32_t m = R.w & 255u;
+                    tm &= m >= 4u ? lvm4 : (m == 3u ? lvm3 : (m == 2u ? lvm2 : lvm1));
+                }
                 ez[q] = R.z;
-                mw[q] = R.w & 255u;
-                ux0 = min(ux0, x0[q]);
-                uy0 = min(uy0, y0[q]);
-                ux1 = max(ux1, x1[q]);
-                uy1 = max(uy1, y1[q]);
             }
+            mlo[q] = (uint32_t)tm;
+            mhi[q] = (uint32_t)(tm >> 32);
+            uni |= tm;
         }
+        uint32_t ulo = (uint32_t)uni, uhi = (uint32_t)(uni >> 32);
         for (int off = 32; off > 0; off >>= 1) {
-            ux0 = min(ux0, __shfl_xor(ux0, off));
-            uy0 = min(uy0, __shfl_xor(uy0, off));
-            ux1 = max(ux1, __shfl_xor(ux1, off));
-            uy1 = max(uy1, __shfl_xor(uy1, off));
+            ulo |= (uint32_t)__shfl_xor((int)ulo, off);
+            uhi |= (uint32_t)__shfl_xor((int)uhi, off);
         }
-        ux0 = __builtin_amdgcn_readfirstlane(max(ux0, bx));
-        uy0 = __builtin_amdgcn_readfirstlane(max(uy0, by));
-        ux1 = __builtin_amdgcn_readfirstlane(min(ux1, min(bx + ST - 1, sb.z - 1)));
-        uy1 = __builtin_amdgcn_readfirstlane(min(uy1, min(by + ST - 1, sb.w - 1)));
+        ulo = (uint32_t)__builtin_amdgcn_readfirstlane((int)ulo);
+        uhi = (uint32_t)__builtin_amdgcn_readfirstlane((int)uhi);
+        const uint32_t nq = (e_end - b + 63u) / 64u;
         const uint32_t vbase = (uint32_t)v * (uint32_t)n;
         wave_lds_sync();
         uint32_t mcnt = 0;
-        for (int ty = uy0; ty <= uy1; ++ty) {
-            uint64_t ym[NB];
 #pragma unroll
-            for (int q = 0; q < NB; ++q) ym[q] = ballot64((y0[q] <= ty) & (ty <= y1[q]));
-            for (int tx = ux0; tx <= ux1; ++tx) {
-                const int l = (ty - by) * ST + (tx - bx);
-                const uint32_t lvl = (uint32_t)__builtin_amdgcn_readfirstlane((int)s_lvl[wave][l]);
+        for (int half = 0; half < 2; ++half) {
+            uint32_t um = half ? uhi : ulo;
+            while (um) {
+                const int l32 = __builtin_ctz(um);
+                um &= um - 1u;
+                const int l = half * 32 + l32;
                 uint32_t pos = 0;
                 if (WRITE) pos = (uint32_t)__builtin_amdgcn_readfirstlane((int)s_pos[wave][l]);
                 uint32_t tot = 0;
 #pragma unroll
                 for (int q = 0; q < NB; ++q) {
-                    const uint64_t bal = ballot64((x0[q] <= tx) & (tx <= x1[q]) & (lvl <= mw[q])) & ym[q];
+                    if ((uint32_t)q >= nq) break;
+                    const bool cov = (((half ? mhi[q] : mlo[q]) >> l32) & 1u) != 0u;
+                    const uint64_t bal = __builtin_amdgcn_ballot_w64(cov);
                     if (WRITE && bal) {
-                        if ((bal >> lane) & 1u) {
-                            const uint32_t at = pos + (uint32_t)__popcll(bal & lt);
+                        if (cov) {
+                            const uint32_t at = pos + __builtin_amdgcn_mbcnt_hi(
+                                                          (uint32_t)(bal >> 32),
+                                                          __builtin_amdgcn_mbcnt_lo((uint32_t)bal, 0u));
                             vals[at] = ez[q] - vbase;
                             if (keys)
-                                keys[at] = ((uint64_t)(toff + (int64_t)ty * sb.z + tx) << 32) |
+                                keys[at] = ((uint64_t)(toff + (int64_t)(by + l / ST) * sb.z + bx + l % ST) << 32) |
                                            __float_as_uint(splats[ez[q]].depth);
                         }
                         pos += (uint32_t)__popcll(bal);
@@ -700,8 +719,8 @@ k_tile_pass(const uint32_t *__restrict__ cv, const uint32_t *__restrict__ st_ran
                 if (!WRITE) mcnt = lane == l ? tot : mcnt;
             }
         }
-        if (!WRITE) ccnt[c * 64 + lane] = mcnt;
-        // the next chunk rewrites the wave's LDS rows
+        if (!WRITE && lane < TST) ccnt[c * TST + lane] = mcnt;
+        // the next chunk rewrites the wave's LDS row
         wave_lds_sync();
     }
 }
@@ -714,6 +733,7 @@ k_col_scan(const uint32_t *__restrict__ chunk_off, const int64_t *__restrict__ v
            int V, uint32_t *__restrict__ ccnt, uint32_t *__restrict__ tot)
 {
     __shared__ uint32_t s_part[COL_WAVES][64];
+    const bool tile_lane = (threadIdx.x & 63) < TST;
     const uint32_t s = blockIdx.x;
     const uint32_t c0 = chunk_off[s], nch = chunk_off[s + 1] - c0;
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
@@ -721,7 +741,8 @@ k_col_scan(const uint32_t *__restrict__ chunk_off, const int64_t *__restrict__ v
     const uint32_t a = c0 + (wave * per < nch ? wave * per : nch);
     const uint32_t z = c0 + ((wave + 1) * per < nch ? (wave + 1) * per : nch);
     uint32_t sum = 0;
-    for (uint32_t c = a; c < z; ++c) sum += ccnt[(uint64_t)c * 64 + lane];
+    if (tile_lane)
+        for (uint32_t c = a; c < z; ++c) sum += ccnt[(uint64_t)c * TST + lane];
     s_part[wave][lane] = sum;
     __syncthreads();
     uint32_t run = 0, total = 0;
@@ -730,12 +751,14 @@ k_col_scan(const uint32_t *__restrict__ chunk_off, const int64_t *__restrict__ v
         if (w < wave) run += x;
         total += x;
     }
-    for (uint32_t c = a; c < z; ++c) {
-        const uint32_t x = ccnt[(uint64_t)c * 64 + lane];
-        ccnt[(uint64_t)c * 64 + lane] = run;
-        run += x;
+    if (tile_lane) {
+        for (uint32_t c = a; c < z; ++c) {
+            const uint32_t x = ccnt[(uint64_t)c * TST + lane];
+            ccnt[(uint64_t)c * TST + lane] = run;
+            run += x;
+        }
     }
-    if (wave == 0) {
+    if (wave == 0 && tile_lane) {
         const int v = view_of_st(stab, V, (int)s);
         const int4 sb = stab[v];
         const int sl = (int)s - sb.x, sy = sl / sb.y, sx = sl - sy * sb.y;

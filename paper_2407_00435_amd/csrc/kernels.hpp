@@ -58,7 +58,7 @@ hipError_t radix_sort_standalone(uint32_t *keys, uint32_t *vals, uint32_t *kt, u
 // binning
 constexpr int SCAN_THREADS = 256;
 constexpr int SCAN_ITEMS = 16;
-constexpr int BIN_SUPER_TILE = 8;   // super-tile side in tiles (one wave lane per tile)
+constexpr int BIN_SUPER_TILE = 8;   // super-tile side in tiles (BIN_SUPER_TILE^2 <= 64)
 constexpr uint32_t BIN_CHUNK = 256; // coarse pairs per chunk of the per-tile counting passes
 // chunks of the counting passes: each super-tile's run of coarse pairs (at
 // most the keys) is cut into chunks of BIN_CHUNK, and there are at most
@@ -79,7 +79,7 @@ struct BinScratch {
     uint8_t *st_cls;                              // [n_tiles][4] per super-tile and level: keeps none/all/part
     uint32_t *chunk_off;                          // [n_tiles + 1] first chunk of each super-tile
     uint32_t *chunk_st;                           // [bin_max_chunks] super-tile of each chunk
-    uint32_t *ccnt;                               // [bin_max_chunks][64] per-chunk tile counts, then prefixes
+    uint32_t *ccnt;                               // [bin_max_chunks][BIN_SUPER_TILE^2] per-chunk tile counts, then prefixes
     uint32_t *tot;                                // [n_tiles] keys per tile
     uint64_t *tsum;                               // [n_tiles / SCAN_ITEMS + 1] block sums of tot
     uint64_t *counts;                             // [8]: entries, keys, capacity, coarse pairs, chunks, keys
