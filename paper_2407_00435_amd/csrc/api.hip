@@ -115,12 +115,13 @@ void carve_bin(Carve &c, int V, int64_t E, uint64_t cap, int64_t tiles, BinScrat
     bs.bbox = c.take<int32_t>(64 * (int64_t)V);
     bs.tkey_a = c.take<uint32_t>(4 * cap);
     bs.tkey_b = c.take<uint32_t>(4 * cap);
-    bs.tval_b = c.take<uint32_t>(4 * cap);
+    bs.cpay_a = c.take<uint2>(8 * cap);
+    bs.cpay_b = c.take<uint2>(8 * cap);
     const uint64_t chunks = bin_max_chunks(cap, tiles);
     bs.st_ranges = c.take<uint32_t>(8 * tiles);
     bs.st_cls = c.take<uint8_t>(4 * tiles);
     bs.chunk_off = c.take<uint32_t>(4 * (tiles + 1));
-    bs.chunk_st = c.take<uint32_t>(4 * chunks);
+    bs.chunk = c.take<uint4>(16 * chunks);
     bs.ccnt = c.take<uint32_t>(4 * BIN_SUPER_TILE * BIN_SUPER_TILE * chunks);
     bs.tot = c.take<uint32_t>(4 * tiles);
     bs.tsum = c.take<uint64_t>(8 * (tiles / (SCAN_THREADS * SCAN_ITEMS) + 1));

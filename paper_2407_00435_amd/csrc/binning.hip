@@ -140,7 +140,9 @@ __device__ __forceinline__ uint32_t sat_rect(const uint32_t *__restrict__ s, int
 //    entries, rec[e] = {x0 | y0 << 16, x1 | y1 << 16, count, quality bound}
 //    with the rectangle clipped to the bounding box of the tiles its level
 //    keeps (the kept tiles and their row-major order are unchanged).
-__global__ void __launch_bounds__(SCAN_THREADS)
+constexpr int COUNT_THREADS = 1024;
+constexpr int COUNT_ITEMS = SCAN_THREADS * SCAN_ITEMS / COUNT_THREADS;
+__global__ void __launch_bounds__(COUNT_THREADS)
 k_count(const gs_splat *__restrict__ splats, int n, const gs_camera *__restrict__ cams, int V, int T,
         const int64_t *__restrict__ vtab, const uint32_t *__restrict__ sat, const int32_t *__restrict__ bbox, int L, int64_t n_tiles,
         const uint8_t *__restrict__ qbound, uint32_t *__restrict__ hits, uint4 *__restrict__ rec,
@@ -150,20 +152,30 @@ k_count(const gs_splat *__restrict__ splats, int n, const gs_camera *__restrict_
     if (threadIdx.x == 0) s_cnt = 0;
     __syncthreads();
     const int64_t E = (int64_t)V * n;
-    const int64_t base = (int64_t)blockIdx.x * (SCAN_THREADS * SCAN_ITEMS);
+    const int64_t base = (int64_t)blockIdx.x * (COUNT_THREADS * COUNT_ITEMS);
+    // the splat fields of every item first (mean, radius, depth), then the work
+    float4 a[COUNT_ITEMS], c[COUNT_ITEMS];
+#pragma unroll
+    for (int j = 0; j < COUNT_ITEMS; ++j) {
+        const int64_t e = base + (int64_t)j * COUNT_THREADS + threadIdx.x;
+        if (e < E) {
+            const float4 *s4 = reinterpret_cast<const float4 *>(splats + e);
+            a[j] = s4[0];
+            c[j] = s4[2];
+        }
+    }
     uint32_t vis = 0;
-    for (int j = 0; j < SCAN_ITEMS; ++j) {
-        const int64_t e = base + (int64_t)j * SCAN_THREADS + threadIdx.x;
+#pragma unroll
+    for (int j = 0; j < COUNT_ITEMS; ++j) {
+        const int64_t e = base + (int64_t)j * COUNT_THREADS + threadIdx.x;
         if (e >= E) break;
         const int v = (int)(e / n);
         const int i = (int)(e - (int64_t)v * n);
         const int W = cams[v].width, H = cams[v].height;
-        const float4 *s4 = reinterpret_cast<const float4 *>(splats + e);
-        const float4 a = s4[0], c = s4[2];
         TileRect r;
         uint32_t cnt = 0;
         int m = 255;
-        if (tile_rect(a.x, a.y, __float_as_int(c.z), W, H, T, r)) {
+        if (tile_rect(a[j].x, a[j].y, __float_as_int(c[j].z), W, H, T, r)) {
             if (!sat) {
                 cnt = (uint32_t)(r.tx1 - r.tx0 + 1) * (uint32_t)(r.ty1 - r.ty0 + 1);
             } else {
@@ -188,7 +200,7 @@ k_count(const gs_splat *__restrict__ splats, int n, const gs_camera *__restrict_
             rec[e] = make_uint4((uint32_t)r.tx0 | ((uint32_t)r.ty0 << 16), (uint32_t)r.tx1 | ((uint32_t)r.ty1 << 16),
                                 cnt, (uint32_t)m);
         if (hits_out) hits_out[e] = cnt;
-        dkey_all[e] = __float_as_uint(c.y);
+        dkey_all[e] = __float_as_uint(c[j].y);
         vis += cnt > 0;
     }
     for (int off = 32; off > 0; off >>= 1) vis += __shfl_xor(vis, off);
@@ -235,32 +247,39 @@ k_scan_blocks(uint64_t *__restrict__ block_sums, const uint32_t *__restrict__ bl
 }
 
 // 2. stable compaction of the entries with keys, counting depth digits.
-__global__ void __launch_bounds__(SCAN_THREADS)
+__global__ void __launch_bounds__(COUNT_THREADS)
 k_compact(const uint32_t *__restrict__ hits, const uint32_t *__restrict__ dkey_all, int64_t E,
           const uint64_t *__restrict__ block_off, uint32_t *__restrict__ dkey,
           uint32_t *__restrict__ dval, uint32_t *__restrict__ hist)
 {
-    __shared__ uint32_t s_w[SCAN_THREADS / 64];
+    constexpr int W = COUNT_THREADS / 64;
+    __shared__ uint32_t s_w[COUNT_ITEMS][W];
     __shared__ uint32_t s_h[4][256];
-    for (int q = threadIdx.x; q < 4 * 256; q += SCAN_THREADS) (&s_h[0][0])[q] = 0;
+    for (int q = threadIdx.x; q < 4 * 256; q += COUNT_THREADS) (&s_h[0][0])[q] = 0;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const int64_t base = (int64_t)blockIdx.x * (SCAN_THREADS * SCAN_ITEMS);
-    uint64_t run = block_off[blockIdx.x];
+    const int64_t base = (int64_t)blockIdx.x * (COUNT_THREADS * COUNT_ITEMS);
+    bool vis[COUNT_ITEMS];
+    uint64_t bal[COUNT_ITEMS];
+#pragma unroll
+    for (int j = 0; j < COUNT_ITEMS; ++j) {
+        const int64_t e = base + (int64_t)j * COUNT_THREADS + threadIdx.x;
+        vis[j] = e < E && hits[e] > 0;
+        bal[j] = ballot64(vis[j]);
+        if (lane == 0) s_w[j][wave] = (uint32_t)__popcll(bal[j]);
+    }
     __syncthreads();
-    for (int j = 0; j < SCAN_ITEMS; ++j) {
-        const int64_t e = base + (int64_t)j * SCAN_THREADS + threadIdx.x;
-        const bool vis = e < E && hits[e] > 0;
-        const uint64_t bal = ballot64(vis);
-        if (lane == 0) s_w[wave] = (uint32_t)__popcll(bal);
-        __syncthreads();
+    uint64_t run = block_off[blockIdx.x];
+#pragma unroll
+    for (int j = 0; j < COUNT_ITEMS; ++j) {
         uint32_t wpre = 0, tot = 0;
-        for (int w = 0; w < SCAN_THREADS / 64; ++w) {
-            const uint32_t c = s_w[w];
+        for (int w = 0; w < W; ++w) {
+            const uint32_t c = s_w[j][w];
             if (w < wave) wpre += c;
             tot += c;
         }
-        if (vis) {
-            const uint64_t pos = run + wpre + (uint32_t)__popcll(bal & lanemask_lt());
+        if (vis[j]) {
+            const int64_t e = base + (int64_t)j * COUNT_THREADS + threadIdx.x;
+            const uint64_t pos = run + wpre + (uint32_t)__popcll(bal[j] & lanemask_lt());
             const uint32_t k = dkey_all[e];
             dkey[pos] = k;
             dval[pos] = (uint32_t)e;
@@ -268,9 +287,9 @@ k_compact(const uint32_t *__restrict__ hits, const uint32_t *__restrict__ dkey_a
             for (int p = 0; p < 4; ++p) atomicAdd(&s_h[p][(k >> (8 * p)) & 255u], 1u);
         }
         run += tot;
-        __syncthreads();
     }
-    for (int q = threadIdx.x; q < 4 * 256; q += SCAN_THREADS) {
+    __syncthreads();
+    for (int q = threadIdx.x; q < 4 * 256; q += COUNT_THREADS) {
         const uint32_t c = (&s_h[0][0])[q];
         if (c) atomicAdd(&hist[q], c);
     }
@@ -318,18 +337,30 @@ k_st_class(const int64_t *__restrict__ vtab, const int4 *__restrict__ stab, int 
     }
 }
 
+// Payload of a coarse pair: the entry (view * n + point) and, relative to
+// super-tile (sx, sy), its clipped tile rectangle (4 bits per bound) with the
+// quality bound in bits 16..23.
+__device__ __forceinline__ uint2 coarse_payload(uint32_t rx, uint32_t ry, uint32_t m, uint32_t e, int sx, int sy)
+{
+    const int x0 = (int)(rx & 0xffffu) - sx * ST, y0 = (int)(rx >> 16) - sy * ST;
+    const int x1 = (int)(ry & 0xffffu) - sx * ST, y1 = (int)(ry >> 16) - sy * ST;
+    const uint32_t cx0 = (uint32_t)max(x0, 0), cy0 = (uint32_t)max(y0, 0);
+    const uint32_t cx1 = (uint32_t)min(x1, ST - 1), cy1 = (uint32_t)min(y1, ST - 1);
+    return make_uint2(e, cx0 | (cy0 << 4) | (cx1 << 8) | (cy1 << 12) | (m << 16));
+}
+
 // Super-tiles of the entry's view that its tile rectangle [x0, x1] x [y0, y1]
 // overlaps and that hold at least one of its kept tiles (with the level
 // filter: the class table, and a summed-area count over rectangle and
 // super-tile > 0 where the level keeps part of the super-tile), in row-major
-// order.  With EMIT, (super-tile id, r) pairs are written from position pos
-// on.  Returns their number.
+// order.  With EMIT, (super-tile id, payload) pairs of entry e are written
+// from position pos on.  Returns their number.
 template <bool EMIT>
-__device__ __forceinline__ uint32_t coarse_walk(uint32_t rx, uint32_t ry, uint32_t m, int v, uint32_t r,
+__device__ __forceinline__ uint32_t coarse_walk(uint32_t rx, uint32_t ry, uint32_t m, int v, uint32_t e,
                                                 const int64_t *__restrict__ vtab, const int4 *__restrict__ stab,
                                                 const uint32_t *__restrict__ sat, const uint8_t *__restrict__ cls,
                                                 int L, int64_t n_tiles, uint32_t *__restrict__ ck,
-                                                uint32_t *__restrict__ cv, uint64_t pos)
+                                                uint2 *__restrict__ cp, uint64_t pos)
 {
     const int x0 = (int)(rx & 0xffffu), y0 = (int)(rx >> 16), x1 = (int)(ry & 0xffffu), y1 = (int)(ry >> 16);
     const int sx0 = x0 / ST, sx1 = x1 / ST, sy0 = y0 / ST, sy1 = y1 / ST;
@@ -338,7 +369,7 @@ __device__ __forceinline__ uint32_t coarse_walk(uint32_t rx, uint32_t ry, uint32
         // one super-tile: it holds all the entry's kept tiles (there is one)
         if (EMIT) {
             ck[pos] = (uint32_t)(sb.x + sy0 * sb.y + sx0);
-            cv[pos] = r;
+            cp[pos] = coarse_payload(rx, ry, m, e, sx0, sy0);
         }
         return 1u;
     }
@@ -364,7 +395,7 @@ __device__ __forceinline__ uint32_t coarse_walk(uint32_t rx, uint32_t ry, uint32
             if (keep) {
                 if (EMIT) {
                     ck[pos + c] = st_id;
-                    cv[pos + c] = r;
+                    cp[pos + c] = coarse_payload(rx, ry, m, e, sx, sy);
                 }
                 ++c;
             }
@@ -479,7 +510,7 @@ __global__ void __launch_bounds__(GATHER_THREADS)
 k_coarse_emit(const uint4 *__restrict__ rec_s, const uint32_t *__restrict__ cc_s, const uint64_t *__restrict__ counts,
               const uint64_t *__restrict__ boff, const int64_t *__restrict__ vtab, const int4 *__restrict__ stab,
               const uint32_t *__restrict__ sat, const uint8_t *__restrict__ cls, int L, int64_t n_tiles,
-              uint32_t *__restrict__ ck, uint32_t *__restrict__ cv)
+              uint32_t *__restrict__ ck, uint2 *__restrict__ cp)
 {
     constexpr int W = GATHER_THREADS / 64;
     __shared__ uint32_t s_w[GATHER_ITEMS][W];
@@ -528,13 +559,14 @@ k_coarse_emit(const uint4 *__restrict__ rec_s, const uint32_t *__restrict__ cc_s
                 while (mask) {
                     const int bit = __ffs(mask) - 1;
                     mask &= mask - 1u;
-                    ck[pos + k] = (uint32_t)(sb.x + (sy0 + bit / MS) * sb.y + sx0 + bit % MS);
-                    cv[pos + k] = (uint32_t)r;
+                    const int sx = sx0 + bit % MS, sy = sy0 + bit / MS;
+                    ck[pos + k] = (uint32_t)(sb.x + sy * sb.y + sx);
+                    cp[pos + k] = coarse_payload(q[j].x, q[j].y, q[j].w & 255u, q[j].z, sx, sy);
                     ++k;
                 }
             } else {
-                coarse_walk<true>(q[j].x, q[j].y, q[j].w & 255u, v, (uint32_t)r, vtab, stab, sat, cls, L, n_tiles,
-                                  ck, cv, pos);
+                coarse_walk<true>(q[j].x, q[j].y, q[j].w & 255u, v, q[j].z, vtab, stab, sat, cls, L, n_tiles, ck,
+                                  cp, pos);
             }
         }
         run += tw;
@@ -542,11 +574,11 @@ k_coarse_emit(const uint4 *__restrict__ rec_s, const uint32_t *__restrict__ cc_s
 }
 
 // Chunks of every super-tile's run: chunk_off[s] = first chunk of s
-// (chunk_off[n_st] = their number, also in *n_chunks), chunk_st[c] = its
-// super-tile.  One workgroup; each thread takes consecutive super-tiles.
+// (chunk_off[n_st] = their number, also in *n_chunks).  One workgroup; each
+// thread takes consecutive super-tiles.
 __global__ void __launch_bounds__(1024)
 k_chunk_table(const uint32_t *__restrict__ st_ranges, int64_t n_st, uint32_t *__restrict__ chunk_off,
-              uint32_t *__restrict__ chunk_st, uint64_t *__restrict__ n_chunks)
+              uint64_t *__restrict__ n_chunks)
 {
     __shared__ uint32_t s[1024];
     const int t = threadIdx.x;
@@ -564,10 +596,8 @@ k_chunk_table(const uint32_t *__restrict__ st_ranges, int64_t n_st, uint32_t *__
     }
     uint32_t run = s[t] - local;
     for (int64_t q = b0; q < b1; ++q) {
-        const uint32_t k = (st_ranges[2 * q + 1] - st_ranges[2 * q] + CHUNK - 1) / CHUNK;
         chunk_off[q] = run;
-        for (uint32_t j = 0; j < k; ++j) chunk_st[run + j] = (uint32_t)q;
-        run += k;
+        run += (st_ranges[2 * q + 1] - st_ranges[2 * q] + CHUNK - 1) / CHUNK;
     }
     if (t == 1023) {
         chunk_off[n_st] = s[1023];
@@ -587,6 +617,23 @@ __device__ __forceinline__ int view_of_st(const int4 *__restrict__ stab, int V, 
             hi = mid - 1;
     }
     return lo;
+}
+
+// Chunk records: chunk[c] = {first pair, end pair, super-tile, view}.  One
+// workgroup per super-tile.
+__global__ void __launch_bounds__(256)
+k_chunk_fill(const uint32_t *__restrict__ st_ranges, const uint32_t *__restrict__ chunk_off,
+             const int4 *__restrict__ stab, int V, uint4 *__restrict__ chunk)
+{
+    const uint32_t s = blockIdx.x;
+    const uint32_t c0 = chunk_off[s], nch = chunk_off[s + 1] - c0;
+    if (nch == 0) return;
+    const uint32_t b0 = st_ranges[2 * s], e0 = st_ranges[2 * s + 1];
+    const uint32_t v = (uint32_t)view_of_st(stab, V, (int)s);
+    for (uint32_t t = threadIdx.x; t < nch; t += blockDim.x) {
+        const uint32_t b = b0 + t * CHUNK;
+        chunk[c0 + t] = make_uint4(b, e0 < b + CHUNK ? e0 : b + CHUNK, s, v);
+    }
 }
 
 // 4c/4e. One wave per chunk of a super-tile's run.  Lane j of batch q holds
@@ -609,9 +656,8 @@ __host__ __device__ constexpr uint64_t row_spread()
 }
 template <bool WRITE>
 __global__ void __launch_bounds__(256)
-k_tile_pass(const uint32_t *__restrict__ cv, const uint32_t *__restrict__ st_ranges,
-            const uint32_t *__restrict__ chunk_off, const uint32_t *__restrict__ chunk_st,
-            const uint64_t *__restrict__ counts, const uint4 *__restrict__ rec_s, const int64_t *__restrict__ vtab,
+k_tile_pass(const uint2 *__restrict__ cp, const uint4 *__restrict__ chunk, const uint64_t *__restrict__ counts,
+            const int64_t *__restrict__ vtab,
             const int4 *__restrict__ stab, int V, int n, const uint8_t *__restrict__ tl, uint32_t *__restrict__ ccnt,
             const uint32_t *__restrict__ ranges, uint32_t *__restrict__ vals, uint64_t *__restrict__ keys,
             const gs_splat *__restrict__ splats)
@@ -626,11 +672,16 @@ k_tile_pass(const uint32_t *__restrict__ cv, const uint32_t *__restrict__ st_ran
     const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
     const uint64_t waves = (uint64_t)gridDim.x * (blockDim.x / 64);
     for (uint64_t c = (uint64_t)blockIdx.x * (blockDim.x / 64) + wave; c < nc; c += waves) {
-        const uint32_t s = chunk_st[c];
-        const uint32_t k = (uint32_t)c - chunk_off[s];
-        const uint32_t b = st_ranges[2 * s] + k * CHUNK;
-        const uint32_t e_end = st_ranges[2 * s + 1] < b + CHUNK ? st_ranges[2 * s + 1] : b + CHUNK;
-        const int v = view_of_st(stab, V, (int)s);
+        const uint4 ch = chunk[c];
+        const uint32_t b = ch.x, e_end = ch.y, s = ch.z;
+        const int v = (int)ch.w;
+        // the chunk's pair payloads early: they do not depend on the view
+        uint2 pj[NB];
+#pragma unroll
+        for (int q = 0; q < NB; ++q) {
+            const uint32_t j = b + 64u * q + (uint32_t)lane;
+            pj[q] = j < e_end ? cp[j] : make_uint2(0u, 0xFFFFFFFFu);
+        }
         const int4 sb = stab[v];
         const int sl = (int)s - sb.x, sy = sl / sb.y, sx = sl - sy * sb.y;
         const int bx = sx * ST, by = sy * ST;
@@ -655,22 +706,19 @@ k_tile_pass(const uint32_t *__restrict__ cv, const uint32_t *__restrict__ st_ran
         uint64_t uni = 0;
 #pragma unroll
         for (int q = 0; q < NB; ++q) {
-            const uint32_t j = b + 64u * q + (uint32_t)lane;
             uint64_t tm = 0;
             ez[q] = 0u;
-            if (j < e_end) {
-                const uint4 R = rec_s[cv[j]];
-                const int cx0 = max((int)(R.x & 0xffffu) - bx, 0), cx1 = min((int)(R.y & 0xffffu) - bx, ST - 1);
-                const int cy0 = max((int)(R.x >> 16) - by, 0), cy1 = min((int)(R.y >> 16) - by, ST - 1);
-                if (cx0 <= cx1 && cy0 <= cy1) {
-                    const uint64_t cols = (2ull << cx1) - (1ull << cx0);
-                    const int hb = (cy1 + 1) * ST;
-                    const uint64_t rows = (hb >= 64 ? ~0ull : (1ull << hb) - 1ull) & ~((1ull << (cy0 * ST)) - 1ull);
-                    tm = cols * row_spread() & rows;
-                    const uint32_t m = R.w & 255u;
-                    tm &= m >= 4u ? lvm4 : (m == 3u ? lvm3 : (m == 2u ? lvm2 : lvm1));
-                }
-                ez[q] = R.z;
+            if (pj[q].y != 0xFFFFFFFFu) {
+                const uint32_t w = pj[q].y;
+                const int cx0 = (int)(w & 15u), cy0 = (int)((w >> 4) & 15u);
+                const int cx1 = (int)((w >> 8) & 15u), cy1 = (int)((w >> 12) & 15u);
+                const uint64_t cols = (2ull << cx1) - (1ull << cx0);
+                const int hb = (cy1 + 1) * ST;
+                const uint64_t rows = (hb >= 64 ? ~0ull : (1ull << hb) - 1ull) & ~((1ull << (cy0 * ST)) - 1ull);
+                tm = cols * row_spread() & rows;
+                const uint32_t m = (w >> 16) & 255u;
+                tm &= m >= 4u ? lvm4 : (m == 3u ? lvm3 : (m == 2u ? lvm2 : lvm1));
+                ez[q] = pj[q].x;
             }
             mlo[q] = (uint32_t)tm;
             mhi[q] = (uint32_t)(tm >> 32);
@@ -912,12 +960,12 @@ hipError_t launch_bin_sort(const gs_splat *splats, int n, const gs_camera *cams_
                            L, tile_level, bs.st_cls);
     const int64_t nb = (E + SCAN_THREADS * SCAN_ITEMS - 1) / (SCAN_THREADS * SCAN_ITEMS);
     // 1-2: counts, then stable compaction of entries with keys (depth digits counted)
-    hipLaunchKernelGGL(k_count, dim3((unsigned)nb), dim3(SCAN_THREADS), 0, st, splats, n, cams_dev, V, T, bs.vtab,
+    hipLaunchKernelGGL(k_count, dim3((unsigned)nb), dim3(COUNT_THREADS), 0, st, splats, n, cams_dev, V, T, bs.vtab,
                        sat, bs.bbox, L, n_tiles, qbound, bs.hits, bs.rec, bs.dkey_b, hits_out, bs.block_vis);
     hipLaunchKernelGGL(k_scan_blocks, dim3(1), dim3(1024), 0, st, bs.block_sums, bs.block_vis, nb, bs.counts,
                        nullptr, nullptr);
     if ((err = launch_fill_u32(bs.rs.hist, 0u, 4 * 256, st)) != hipSuccess) return err;
-    hipLaunchKernelGGL(k_compact, dim3((unsigned)nb), dim3(SCAN_THREADS), 0, st, bs.hits, bs.dkey_b, E,
+    hipLaunchKernelGGL(k_compact, dim3((unsigned)nb), dim3(COUNT_THREADS), 0, st, bs.hits, bs.dkey_b, E,
                        bs.block_sums, bs.dkey_a, bs.dval_a, bs.rs.hist);
     // 3: depth sort of the entries with keys (4 x 8-bit passes), result back in (dkey_a, dval_a)
     if ((err = radix_sort_pairs(bs.dkey_a, bs.dval_a, bs.dkey_b, bs.dval_b, bs.counts, (uint64_t)E, 32, bs.rs, st,
@@ -931,25 +979,26 @@ hipError_t launch_bin_sort(const gs_splat *splats, int n, const gs_camera *cams_
     // coarse pairs <= keys, so a coarse total above the key total means overflow
     hipLaunchKernelGGL(k_scan_blocks, dim3(1), dim3(1024), 0, st, bs.block_sums2, nullptr, nb, bs.counts + 3,
                        bs.counts + 1, nullptr);
-    // 4b: coarse pairs, stably sorted by super-tile; the sorted values end in tval_b
+    // 4b: coarse pairs with their payloads, stably sorted by super-tile
     int st_bits = 1;
     while ((int64_t(1) << st_bits) < n_st) ++st_bits;
     const bool even = radix_passes(st_bits) % 2 == 0;
-    uint32_t *ka = bs.tkey_a, *va = even ? bs.tval_b : vals, *kb = bs.tkey_b, *vb = even ? vals : bs.tval_b;
     hipLaunchKernelGGL(k_coarse_emit, dim3((unsigned)nb), dim3(GATHER_THREADS), 0, st, bs.rec_s, bs.cc_s, bs.counts,
-                       bs.block_sums2, bs.vtab, bs.stab, sat, bs.st_cls, L, n_tiles, ka, va);
-    if ((err = radix_sort_pairs(ka, va, kb, vb, bs.counts + 3, cap, st_bits, bs.rs, st, false)) != hipSuccess)
+                       bs.block_sums2, bs.vtab, bs.stab, sat, bs.st_cls, L, n_tiles, bs.tkey_a, bs.cpay_a);
+    if ((err = radix_sort_pairs_v2(bs.tkey_a, bs.cpay_a, bs.tkey_b, bs.cpay_b, bs.counts + 3, cap, st_bits, bs.rs,
+                                   st)) != hipSuccess)
         return err;
-    const uint32_t *sk = even ? ka : kb;
+    const uint32_t *sk = even ? bs.tkey_a : bs.tkey_b;
+    const uint2 *sp = even ? bs.cpay_a : bs.cpay_b;
     if ((err = launch_fill_u32(bs.st_ranges, 0u, 2 * (uint64_t)n_st, st)) != hipSuccess) return err;
     hipLaunchKernelGGL(k_ranges, dim3(grid_for(cap, 256 * 16, 8192)), dim3(256), 0, st, sk, bs.counts + 3, cap,
                        n_st, bs.st_ranges);
-    hipLaunchKernelGGL(k_chunk_table, dim3(1), dim3(1024), 0, st, bs.st_ranges, n_st, bs.chunk_off, bs.chunk_st,
-                       bs.counts + 4);
+    hipLaunchKernelGGL(k_chunk_table, dim3(1), dim3(1024), 0, st, bs.st_ranges, n_st, bs.chunk_off, bs.counts + 4);
+    hipLaunchKernelGGL(k_chunk_fill, dim3((unsigned)n_st), dim3(256), 0, st, bs.st_ranges, bs.chunk_off, bs.stab, V,
+                       bs.chunk);
     // 4c-4e: per-tile counts, their scans (tile ranges), keys at their final positions
     const int pass_blocks = grid_for(bin_max_chunks(cap, n_tiles), 4, 2048);
-    hipLaunchKernelGGL((k_tile_pass<false>), dim3(pass_blocks), dim3(256), 0, st, bs.tval_b, bs.st_ranges,
-                       bs.chunk_off, bs.chunk_st, bs.counts, bs.rec_s, bs.vtab, bs.stab, V, n, tile_level, bs.ccnt,
+    hipLaunchKernelGGL((k_tile_pass<false>), dim3(pass_blocks), dim3(256), 0, st, sp, bs.chunk, bs.counts, bs.vtab, bs.stab, V, n, tile_level, bs.ccnt,
                        ranges, vals, keys, splats);
     hipLaunchKernelGGL(k_col_scan, dim3((unsigned)n_st), dim3(COL_WAVES * 64), 0, st, bs.chunk_off, bs.vtab, bs.stab, V,
                        bs.ccnt, bs.tot);
@@ -959,8 +1008,7 @@ hipError_t launch_bin_sort(const gs_splat *splats, int n, const gs_camera *cams_
                        nullptr);
     hipLaunchKernelGGL(k_tile_ranges, dim3((unsigned)nbt), dim3(SCAN_THREADS), 0, st, bs.tot, n_tiles, bs.tsum,
                        bs.counts, ranges);
-    hipLaunchKernelGGL((k_tile_pass<true>), dim3(pass_blocks), dim3(256), 0, st, bs.tval_b, bs.st_ranges,
-                       bs.chunk_off, bs.chunk_st, bs.counts, bs.rec_s, bs.vtab, bs.stab, V, n, tile_level, bs.ccnt,
+    hipLaunchKernelGGL((k_tile_pass<true>), dim3(pass_blocks), dim3(256), 0, st, sp, bs.chunk, bs.counts, bs.vtab, bs.stab, V, n, tile_level, bs.ccnt,
                        ranges, vals, keys, splats);
     return hipGetLastError();
 }

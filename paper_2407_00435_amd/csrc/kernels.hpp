@@ -49,6 +49,10 @@ hipError_t radix_sort_pairs(uint32_t *ka, uint32_t *va, uint32_t *kb, uint32_t *
                             const uint64_t *d_count, uint64_t cap, int bits,
                             const RadixScratch &rs, hipStream_t st, bool hist_ready);
 
+// The same with 8-byte values (partitions of at most 8192 keys).
+hipError_t radix_sort_pairs_v2(uint32_t *ka, uint2 *va, uint32_t *kb, uint2 *vb, const uint64_t *d_count,
+                               uint64_t cap, int bits, const RadixScratch &rs, hipStream_t st);
+
 size_t radix_sort_scratch_bytes(uint64_t n);
 bool radix_set_part(int p);
 // sorts n pairs with its own scratch at ws; *in_tmp tells where the result is
@@ -74,11 +78,12 @@ struct BinScratch {
     uint64_t *block_sums, *block_sums2;           // [E / SCAN_ITEMS + 1]
     int64_t *vtab;                                // [2V] first tile and tiles_x of each view
     int4 *stab;                                   // [V] first super-tile, super-tiles per row, tiles_x, tiles_y
-    uint32_t *tkey_a, *tkey_b, *tval_b;           // [cap] coarse-pair sort ping-pong
+    uint32_t *tkey_a, *tkey_b;                    // [cap] coarse-pair sort keys (super-tile ids), ping-pong
+    uint2 *cpay_a, *cpay_b;                       // [cap] coarse-pair payloads, ping-pong
     uint32_t *st_ranges;                          // [n_tiles][2] run of each super-tile in the sorted pairs
     uint8_t *st_cls;                              // [n_tiles][4] per super-tile and level: keeps none/all/part
     uint32_t *chunk_off;                          // [n_tiles + 1] first chunk of each super-tile
-    uint32_t *chunk_st;                           // [bin_max_chunks] super-tile of each chunk
+    uint4 *chunk;                                 // [bin_max_chunks] first pair, end pair, super-tile, view
     uint32_t *ccnt;                               // [bin_max_chunks][BIN_SUPER_TILE^2] per-chunk tile counts, then prefixes
     uint32_t *tot;                                // [n_tiles] keys per tile
     uint64_t *tsum;                               // [n_tiles / SCAN_ITEMS + 1] block sums of tot

@@ -117,10 +117,10 @@ k_radix_clear(uint64_t *__restrict__ status, uint32_t *__restrict__ ticket,
     if (blockIdx.x == 0 && threadIdx.x == 0) *ticket = 0;
 }
 
-template <int THREADS, int ITEMS>
+template <int THREADS, int ITEMS, typename VT>
 __global__ void __launch_bounds__(THREADS)
-k_radix_onesweep(const uint32_t *__restrict__ kin, const uint32_t *__restrict__ vin,
-                 uint32_t *__restrict__ kout, uint32_t *__restrict__ vout,
+k_radix_onesweep(const uint32_t *__restrict__ kin, const VT *__restrict__ vin,
+                 uint32_t *__restrict__ kout, VT *__restrict__ vout,
                  const uint64_t *__restrict__ d_count, uint64_t cap, int shift, uint32_t mask,
                  int dbits, const uint32_t *__restrict__ gbase, uint64_t *__restrict__ status,
                  uint32_t *__restrict__ ticket)
@@ -128,7 +128,7 @@ k_radix_onesweep(const uint32_t *__restrict__ kin, const uint32_t *__restrict__ 
     constexpr int WAVES = THREADS / 64;
     constexpr int PART = THREADS * ITEMS;
     __shared__ uint32_t s_keys[PART];
-    __shared__ uint32_t s_vals[PART];
+    __shared__ VT s_vals[PART];
     __shared__ uint32_t s_whist[WAVES][256];
     __shared__ uint32_t s_bexcl[256];  // exclusive prefix over digits of the block counts
     __shared__ uint64_t s_dbase[256];  // global position of the digit's first key of this block
@@ -149,13 +149,14 @@ k_radix_onesweep(const uint32_t *__restrict__ kin, const uint32_t *__restrict__ 
 
         const uint64_t pbase = part * PART;
         const uint64_t wbase = pbase + (uint64_t)wave * (ITEMS * 64);
-        uint32_t k[ITEMS], v[ITEMS], rk[ITEMS];
+        uint32_t k[ITEMS], rk[ITEMS];
+        VT v[ITEMS];
 #pragma unroll
         for (int r = 0; r < ITEMS; ++r) {
             uint64_t idx = wbase + (uint64_t)r * 64 + lane;
             bool ok = idx < count;
             k[r] = ok ? kin[idx] : 0xFFFFFFFFu;
-            v[r] = ok ? vin[idx] : 0u;
+            v[r] = ok ? vin[idx] : VT{};
         }
         const uint64_t lt = lanemask_lt();
         // stable rank within the wave: items in (round, lane) order
@@ -278,7 +279,8 @@ int radix_digit_bits(int bits)
     return passes ? (bits + passes - 1) / passes : 0;
 }
 
-hipError_t radix_sort_pairs(uint32_t *ka, uint32_t *va, uint32_t *kb, uint32_t *vb,
+template <typename VT>
+static hipError_t sort_pairs_impl(uint32_t *ka, VT *va, uint32_t *kb, VT *vb,
                             const uint64_t *d_count, uint64_t cap, int bits,
                             const RadixScratch &rs, hipStream_t st, bool hist_ready)
 {
@@ -288,7 +290,8 @@ hipError_t radix_sort_pairs(uint32_t *ka, uint32_t *va, uint32_t *kb, uint32_t *
     const int dbits = radix_digit_bits(bits);
     const uint32_t mask = (1u << dbits) - 1u;
     hipError_t e;
-    const int P = part_size();
+    // 8-byte values: partitions of at most 8192 keys (the LDS holds keys and values)
+    const int P = sizeof(VT) > 4 && part_size() > 8192 ? 8192 : part_size();
     const uint64_t parts = (cap + P - 1) / P;
     if (!hist_ready) {
         if ((e = launch_fill_u32(rs.hist, 0u, 4 * 256, st)) != hipSuccess) return e;
@@ -302,7 +305,8 @@ hipError_t radix_sort_pairs(uint32_t *ka, uint32_t *va, uint32_t *kb, uint32_t *
                            dbits, rs.hist);
     }
     hipLaunchKernelGGL(k_radix_prefix, dim3(passes), dim3(256), 0, st, rs.hist);
-    uint32_t *src_k = ka, *src_v = va, *dst_k = kb, *dst_v = vb;
+    uint32_t *src_k = ka, *dst_k = kb;
+    VT *src_v = va, *dst_v = vb;
     // the grid is sized for the capacity; a persistent grid of at most
     // SWEEP_BLOCKS workgroups keeps the cost of an over-sized capacity
     // (workgroups that start only to find no partition) bounded
@@ -313,21 +317,36 @@ hipError_t radix_sort_pairs(uint32_t *ka, uint32_t *va, uint32_t *kb, uint32_t *
         hipLaunchKernelGGL(k_radix_clear, dim3(clear_blocks), dim3(256), 0, st, rs.status,
                            rs.tickets + p, d_count, cap, P);
 #define GS_OS(TH, IT)                                                                                \
-    hipLaunchKernelGGL((k_radix_onesweep<TH, IT>), dim3(sweep_blocks), dim3(TH), 0, st, src_k,     \
+    hipLaunchKernelGGL((k_radix_onesweep<TH, IT, VT>), dim3(sweep_blocks), dim3(TH), 0, st, src_k,     \
                        src_v, dst_k, dst_v, d_count, cap, dbits * p, mask, dbits,                  \
                        rs.hist + 256 * p, rs.status, rs.tickets + p)
-        if (P == 4096)
+        if (P == 4096) {
             GS_OS(256, 16);
-        else if (P == 16384)
-            GS_OS(1024, 16);
-        else
+        } else if (P == 16384) {
+            if constexpr (sizeof(VT) == 4) GS_OS(1024, 16);
+        } else {
             GS_OS(512, 16);
+        }
 #undef GS_OS
-        uint32_t *tk = src_k, *tv = src_v;
+        uint32_t *tk = src_k;
+        VT *tv = src_v;
         src_k = dst_k; src_v = dst_v;
         dst_k = tk; dst_v = tv;
     }
     return hipGetLastError();
+}
+
+hipError_t radix_sort_pairs(uint32_t *ka, uint32_t *va, uint32_t *kb, uint32_t *vb,
+                            const uint64_t *d_count, uint64_t cap, int bits,
+                            const RadixScratch &rs, hipStream_t st, bool hist_ready)
+{
+    return sort_pairs_impl<uint32_t>(ka, va, kb, vb, d_count, cap, bits, rs, st, hist_ready);
+}
+
+hipError_t radix_sort_pairs_v2(uint32_t *ka, uint2 *va, uint32_t *kb, uint2 *vb, const uint64_t *d_count,
+                               uint64_t cap, int bits, const RadixScratch &rs, hipStream_t st)
+{
+    return sort_pairs_impl<uint2>(ka, va, kb, vb, d_count, cap, bits, rs, st, false);
 }
 
 bool radix_set_part(int p)
