@@ -771,10 +771,9 @@ k_raster_fov_q(const gs_splat *__restrict__ splats, const float4 *__restrict__ l
 // light behind i (including the background) is accumulated on the way, so
 //   dL/dc_i = g alpha_i T_i,  dL/dalpha_i = sum_ch g (c_i T_i - B_i / (1 - alpha_i)).
 // The tile's list is walked in chunks of 64 positions by all its waves
-// together.  Gradients of one splat are summed over a wave's 64 pixels with
-// DPP reductions, then over the tile's waves in LDS, and leave the tile as
-// one float atomic per quantity per chunk: the global atomics, not the
-// arithmetic, bound this kernel.
+// together.  Gradients of one splat are summed over each 16-lane row of a
+// wave with DPP reduce-scatters, then over rows and the tile's waves in LDS,
+// and leave the tile as one float atomic per quantity per chunk.
 struct BwdRec {
     float4 a, b, c;   // forward record (identical decisions)
     float4 raw;       // conic A, B, C, opacity
@@ -910,27 +909,14 @@ k_raster_bwd(const gs_splat *__restrict__ splats, int n, const gs_camera *__rest
                     }
                 }
                 if (ballot64(contrib) != 0) {
-                    gmx = wave_total_63(gmx);
-                    gmy = wave_total_63(gmy);
-                    gA = wave_total_63(gA);
-                    gB = wave_total_63(gB);
-                    gC = wave_total_63(gC);
-                    gop = wave_total_63(gop);
-                    gr = wave_total_63(gr);
-                    gg = wave_total_63(gg);
-                    gb = wave_total_63(gb);
-                    if (lane == 63) {
-                        const int q = (int)(ppos - (uint32_t)p0);
-                        atomicAdd(&s_grad[0][q], gmx);
-                        atomicAdd(&s_grad[1][q], gmy);
-                        atomicAdd(&s_grad[2][q], gA);
-                        atomicAdd(&s_grad[3][q], gB);
-                        atomicAdd(&s_grad[4][q], gC);
-                        atomicAdd(&s_grad[5][q], gop);
-                        atomicAdd(&s_grad[6][q], gr);
-                        atomicAdd(&s_grad[7][q], gg);
-                        atomicAdd(&s_grad[8][q], gb);
-                    }
+                    // eight quantities by a reduce-scatter over each row (one
+                    // LDS atomic per quantity and row), the ninth by a row sum
+                    const float v8[8] = {gmx, gmy, gA, gB, gC, gop, gr, gg};
+                    const float part = row_scatter_sum8(v8, lane);
+                    const float pb = row_sum16(gb);
+                    const int q = (int)(ppos - (uint32_t)p0);
+                    if ((lane & 8) == 0) atomicAdd(&s_grad[scatter_q(lane)][q], part);
+                    if ((lane & 15) == 15) atomicAdd(&s_grad[8][q], pb);
                 }
             }
         }
