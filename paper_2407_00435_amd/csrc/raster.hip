@@ -776,7 +776,6 @@ k_raster_fov_q(const gs_splat *__restrict__ splats, const float4 *__restrict__ l
 // and leave the tile as one float atomic per quantity per chunk.
 struct BwdRec {
     float4 a, b, c;   // forward record (identical decisions)
-    float4 raw;       // conic A, B, C, opacity
 };
 
 // Sum over the 64 lanes of a wave, complete in lane 63 only: row sums, then
@@ -800,7 +799,7 @@ k_raster_bwd(const gs_splat *__restrict__ splats, int n, const gs_camera *__rest
 {
     constexpr int WAVES = T * T / 64;
     constexpr int SUB = T / 8;
-    constexpr int NG = 9;  // mean x, y, conic A, B, C, opacity, colour r, g, b
+    constexpr int NG = 9;  // sums of w, w dx, w dy, w dx^2, w dx dy, w dy^2, colour r, g, b
     __shared__ BwdRec s_rec[WAVES][64];
     __shared__ float s_grad[NG][64];
     __shared__ uint32_t s_id[64];
@@ -854,7 +853,7 @@ k_raster_bwd(const gs_splat *__restrict__ splats, int n, const gs_camera *__rest
             bool keep = false;
             // the record is fully defined on every lane before the cull decision
             BwdRec rec;
-            rec.a = rec.b = rec.c = rec.raw = make_float4(0.f, 0.f, 0.f, 0.f);
+            rec.a = rec.b = rec.c = make_float4(0.f, 0.f, 0.f, 0.f);
             if (pos <= p1 && pos <= (int64_t)maxnc) {
                 const uint32_t idx = start + (uint32_t)(pos - 1);
                 const uint32_t id = vals[idx];
@@ -864,7 +863,6 @@ k_raster_bwd(const gs_splat *__restrict__ splats, int n, const gs_camera *__rest
                 rec.a = f.a;
                 rec.b = f.b;
                 rec.c = f.c;
-                rec.raw = make_float4(s0.z, s0.w, s1.x, s1.y);
                 keep = reaches_rect(s0.x, s0.y, s0.z, s0.w, s1.x, qmax_of(s1.y), rx0, rx1, ry0, ry1);
             }
             const uint64_t msk = ballot64(keep);
@@ -874,44 +872,34 @@ k_raster_bwd(const gs_splat *__restrict__ splats, int n, const gs_camera *__rest
             for (int j = cnt - 1; j >= 0; --j) {
                 const float4 a = s_rec[wave][j].a, b = s_rec[wave][j].b;
                 const uint32_t ppos = __float_as_uint(b.w);
-                float gmx = 0.f, gmy = 0.f, gA = 0.f, gB = 0.f, gC = 0.f, gop = 0.f;
-                float gr = 0.f, gg = 0.f, gb = 0.f;
-                bool contrib = false;
-                if (ppos <= nc) {
-                    const float e2 = pair_e2(a, b, fpx, fpy);
-                    if (e2 >= b.z) {
-                        contrib = true;
-                        const float4 c = s_rec[wave][j].c, raw = s_rec[wave][j].raw;
-                        const float araw = fast_exp2(e2);
-                        const float alpha = fminf(GS_ALPHA_MAX, araw);
-                        const float oma = 1.0f - alpha;
-                        const float ioma = __builtin_amdgcn_rcpf(oma);
-                        Tr = Tr * ioma;
-                        const float wT = alpha * Tr;
-                        gr = g0 * wT;
-                        gg = g1 * wT;
-                        gb = g2 * wT;
-                        const float dLda = g0 * (c.x * Tr - B0 * ioma) + g1 * (c.y * Tr - B1 * ioma) +
-                                           g2 * (c.z * Tr - B2 * ioma);
-                        B0 = fmaf(c.x, wT, B0);
-                        B1 = fmaf(c.y, wT, B1);
-                        B2 = fmaf(c.z, wT, B2);
-                        if (araw <= GS_ALPHA_MAX) {
-                            gop = dLda * alpha * __builtin_amdgcn_rcpf(raw.w);
-                            const float dLdq = -0.5f * alpha * dLda;
-                            const float dx = fpx - a.x, dy = fpy - a.y;
-                            gA = dLdq * dx * dx;
-                            gB = dLdq * 2.0f * dx * dy;
-                            gC = dLdq * dy * dy;
-                            gmx = -2.0f * dLdq * (raw.x * dx + raw.y * dy);
-                            gmy = -2.0f * dLdq * (raw.y * dx + raw.z * dy);
-                        }
-                    }
-                }
-                if (ballot64(contrib) != 0) {
+                // per pixel only w = alpha dL/dalpha and its moments in
+                // (dx, dy); the conic, mean and opacity gradients are linear
+                // in their sums (applied once per splat at the flush).
+                // Branch-free: every lane evaluates, selects take the
+                // decisions of the forward pass.
+                const float e2 = pair_e2(a, b, fpx, fpy);
+                const bool contrib = ppos <= nc && e2 >= b.z;
+                const float4 c = s_rec[wave][j].c;
+                const float araw = fast_exp2(e2);
+                const float alpha = fminf(GS_ALPHA_MAX, araw);
+                const float ioma = __builtin_amdgcn_rcpf(1.0f - alpha);
+                const float Tn = Tr * ioma;
+                const float wT = contrib ? alpha * Tn : 0.f;
+                const float dLda = g0 * fmaf(c.x, Tn, -B0 * ioma) + g1 * fmaf(c.y, Tn, -B1 * ioma) +
+                                   g2 * fmaf(c.z, Tn, -B2 * ioma);
+                const float gr = g0 * wT, gg = g1 * wT, gb = g2 * wT;
+                B0 = fmaf(c.x, wT, B0);
+                B1 = fmaf(c.y, wT, B1);
+                B2 = fmaf(c.z, wT, B2);
+                Tr = contrib ? Tn : Tr;
+                const float w = (contrib && araw <= GS_ALPHA_MAX) ? alpha * dLda : 0.f;
+                const float dx = fpx - a.x, dy = fpy - a.y;
+                const float wdx = w * dx, wdy = w * dy;
+                const float wdx2 = wdx * dx, wdxdy = wdx * dy, wdy2 = wdy * dy;
+                if (__builtin_amdgcn_ballot_w64(contrib) != 0) {
                     // eight quantities by a reduce-scatter over each row (one
                     // LDS atomic per quantity and row), the ninth by a row sum
-                    const float v8[8] = {gmx, gmy, gA, gB, gC, gop, gr, gg};
+                    const float v8[8] = {w, wdx, wdy, wdx2, wdxdy, wdy2, gr, gg};
                     const float part = row_scatter_sum8(v8, lane);
                     const float pb = row_sum16(gb);
                     const int q = (int)(ppos - (uint32_t)p0);
@@ -921,13 +909,39 @@ k_raster_bwd(const gs_splat *__restrict__ splats, int n, const gs_camera *__rest
             }
         }
         __syncthreads();
-        // the tile's sums of this chunk leave with one atomic per quantity
-        for (int q = threadIdx.x; q < NG * 64; q += T * T) {
-            const int k = q >> 6, jj = q & 63;
-            const float v = s_grad[k][jj];
-            if (v != 0.f) {
-                atomicAdd(reinterpret_cast<float *>(grads + vbase + s_id[jj]) + k, v);
+        // the tile's sums of this chunk leave with one atomic per quantity:
+        // with q = the Mahalanobis form and dL/dq = -w / 2,
+        //   dL/dmean = (A S_wdx + B S_wdy, B S_wdx + C S_wdy),
+        //   dL/d(A, B, C) = (-S_wdx2 / 2, -S_wdxdy, -S_wdy2 / 2),
+        //   dL/dopacity = S_w / opacity
+        if (threadIdx.x < 64) {
+            const int jj = threadIdx.x;
+            float S[NG];
+            bool any = false;
+#pragma unroll
+            for (int k = 0; k < NG; ++k) {
+                S[k] = s_grad[k][jj];
                 s_grad[k][jj] = 0.f;
+                any = any || S[k] != 0.f;
+            }
+            if (any) {
+                const gs_splat *sp = splats + vbase + s_id[jj];
+                const float4 s0 = reinterpret_cast<const float4 *>(sp)[0];
+                const float4 s1 = reinterpret_cast<const float4 *>(sp)[1];
+                float out[NG];
+                out[0] = fmaf(s0.z, S[1], s0.w * S[2]);
+                out[1] = fmaf(s0.w, S[1], s1.x * S[2]);
+                out[2] = -0.5f * S[3];
+                out[3] = -S[4];
+                out[4] = -0.5f * S[5];
+                out[5] = S[0] * __builtin_amdgcn_rcpf(s1.y);
+                out[6] = S[6];
+                out[7] = S[7];
+                out[8] = S[8];
+                float *gp = reinterpret_cast<float *>(grads + vbase + s_id[jj]);
+#pragma unroll
+                for (int k = 0; k < NG; ++k)
+                    if (out[k] != 0.f) atomicAdd(gp + k, out[k]);
             }
         }
         __syncthreads();
