@@ -407,7 +407,7 @@ int gs_fovea_prep(const gs_camera *cams_host, const gs_camera *cams_dev, const g
         if (n_levels > 1 && f.band_deg > 0.f && !(f.ring_deg[0] - 0.5f * f.band_deg >= 0.f))
             return fail(GS_ERR_INVALID, "eye %d: first band starts below 0 degrees", i);
     }
-    hipError_t e = launch_fovea_prep(cams_dev, fov_host, n_eyes, tile_size, n_levels, pixels, tiles,
+    hipError_t e = launch_fovea_prep(cams_host, cams_dev, fov_host, n_eyes, tile_size, n_levels, pixels, tiles,
                                      pix_level, pix_weight, tile_level, (hipStream_t)stream);
     if (e != hipSuccess) return hip_fail(e, "gs_fovea_prep");
     return ok();

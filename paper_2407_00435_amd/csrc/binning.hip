@@ -89,19 +89,25 @@ k_level_sat(const gs_camera *__restrict__ cams, int V, int T, int L, int64_t n_t
     uint32_t *g = sat + (int64_t)(m - 1) * n_tiles + toff;
     uint32_t *s = use_lds ? s_sat : g;
     const uint8_t *lv = tl + 2 * toff;
-    for (int y = threadIdx.x; y < ty; y += blockDim.x) {
+    // row sums: a wave per row, 64 columns per step (ballot prefix counts)
+    const int lane = threadIdx.x & 63, waves = blockDim.x / 64;
+    for (int y = threadIdx.x >> 6; y < ty; y += waves) {
         uint32_t run = 0;
         int xl = tx, xr = -1;
-        for (int x = 0; x < tx; ++x) {
-            const bool kept = lv[2 * ((int64_t)y * tx + x)] <= m;
-            run += kept;
-            if (kept) {
-                xl = x < xl ? x : xl;
-                xr = x;
+        for (int x0 = 0; x0 < tx; x0 += 64) {
+            const int x = x0 + lane;
+            const bool kept = x < tx && lv[2 * ((int64_t)y * tx + x)] <= m;
+            const uint64_t bal = __builtin_amdgcn_ballot_w64(kept);
+            const uint32_t below = __builtin_amdgcn_mbcnt_hi((uint32_t)(bal >> 32),
+                                                             __builtin_amdgcn_mbcnt_lo((uint32_t)bal, 0u));
+            if (x < tx) s[(int64_t)y * tx + x] = run + below + (kept ? 1u : 0u);
+            run += (uint32_t)__popcll(bal);
+            if (bal) {
+                xl = min(xl, x0 + __ffsll((unsigned long long)bal) - 1);
+                xr = max(xr, x0 + 63 - __clzll((long long)bal));
             }
-            s[(int64_t)y * tx + x] = run;
         }
-        if (xr >= 0) {
+        if (xr >= 0 && lane == 0) {
             atomicMin(&s_box[0], xl);
             atomicMin(&s_box[1], y);
             atomicMax(&s_box[2], xr);

@@ -127,9 +127,9 @@ hipError_t launch_raster_fov_bwd(const gs_splat *splats, const float *lvl_rgba, 
                                  const float *pix_weight, const float bg[3], const float *final_T2,
                                  const uint32_t *n_contrib2, const float *dL_dimage, gs_splat_grad *grads,
                                  float *lvl_grads, hipStream_t st);
-hipError_t launch_fovea_prep(const gs_camera *cams_dev, const gs_fovea *fov_host, int n_eyes, int T,
-                             int n_levels, int64_t n_pixels, int64_t n_tiles, uint8_t *pix_level,
-                             float *pix_weight, uint8_t *tile_level, hipStream_t st);
+hipError_t launch_fovea_prep(const gs_camera *cams_host, const gs_camera *cams_dev, const gs_fovea *fov_host,
+                             int n_eyes, int T, int n_levels, int64_t n_pixels, int64_t n_tiles,
+                             uint8_t *pix_level, float *pix_weight, uint8_t *tile_level, hipStream_t st);
 hipError_t launch_raster_fov(const gs_splat *splats, const float *lvl_rgba, int n,
                              const uint8_t *qbound, int n_levels, const gs_camera *cams_dev, int V,
                              int T, int64_t n_tiles, const uint32_t *vals, const uint32_t *ranges,

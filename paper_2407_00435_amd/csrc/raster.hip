@@ -265,15 +265,18 @@ k_raster_fwd(const gs_splat *__restrict__ splats, int n, const gs_camera *__rest
 }
 
 // ---------------------------------------------------------------------------
-// Foveated compositing.  Record: geometry (mean, qa, qb | qc, quality bound,
-// unused, unused) and per level (r, g, b, opacity).  Each pixel runs the
+// Foveated compositing.  Record: geometry (mean, qa, qb | qc, point index,
+// quality bound, list position) and (r, g, b, opacity) of the two levels the
+// wave's pixels use (wave_lo and wave_lo + 1).  Each pixel runs the
 // accumulator of its lower level and, if blended, of the next one; level t
 // takes a splat only if its quality bound is >= t and uses that level's
-// opacity and colour.
+// opacity and colour.  An 8 x 8 block needs more than two levels only when
+// ring bands are closer than the block; such a wave reads the level data
+// from memory instead.
 constexpr int MAXL = 4;
 struct FovRec {
     float4 a, b;
-    float4 lv[MAXL];
+    float4 lv[2];
 };
 
 struct FovPix {
@@ -282,6 +285,7 @@ struct FovPix {
     bool two;        // the pixel blends two levels
     int wave_lo;     // lowest level any pixel of the wave needs
     bool any_two;    // some pixel of the wave blends two levels
+    bool wide;       // the wave's pixels need more than two levels
 };
 
 __device__ __forceinline__ FovPix fov_pix(const WaveCtx &w, const uint8_t *__restrict__ pix_level,
@@ -297,8 +301,11 @@ __device__ __forceinline__ FovPix fov_pix(const WaveCtx &w, const uint8_t *__res
     f.two = f.wup > 0.0f;
     int wl = w.inside ? f.lo : 255;
     for (int off = 32; off > 0; off >>= 1) wl = min(wl, __shfl_xor(wl, off));
+    int wh = w.inside ? f.lo + (f.two ? 1 : 0) : 0;
+    for (int off = 32; off > 0; off >>= 1) wh = max(wh, __shfl_xor(wh, off));
     f.wave_lo = wl;
     f.any_two = ballot64(f.two) != 0;
+    f.wide = wh - wl >= 2;
     return f;
 }
 
@@ -319,8 +326,8 @@ __device__ __forceinline__ FovState fov_init(bool inside, bool two)
     return s;
 }
 
-template <bool STATS, bool KEEP = false>
-__device__ __forceinline__ void fov_walk(const gs_splat *__restrict__ splats, const float4 *__restrict__ lvl,
+template <bool STATS, bool KEEP, bool WIDE>
+__device__ __forceinline__ void fov_walk_impl(const gs_splat *__restrict__ splats, const float4 *__restrict__ lvl,
                                          int n, const uint8_t *__restrict__ qbound, int L,
                                          const uint32_t *__restrict__ vals, const WaveCtx &w, const FovPix &f,
                                          uint32_t b, uint32_t e, FovRec *__restrict__ srec, FovState &s,
@@ -334,20 +341,20 @@ __device__ __forceinline__ void fov_walk(const gs_splat *__restrict__ splats, co
         bool keep = false;
         // the record is fully defined on every lane before the cull decision
         FovRec rec;
-        rec.a = rec.b = make_float4(0.f, 0.f, 0.f, 0.f);
-#pragma unroll
-        for (int t = 0; t < MAXL; ++t) rec.lv[t] = make_float4(0.f, 0.f, 0.f, 0.f);
+        rec.a = rec.b = rec.lv[0] = rec.lv[1] = make_float4(0.f, 0.f, 0.f, 0.f);
         if (idx < e) {
             const uint32_t id = vals[idx];
             const int m = qbound[id];
             const float4 *s4 = reinterpret_cast<const float4 *>(splats + vbase + id);
             const float4 s0 = s4[0], s1 = s4[1];
             rec.a = make_float4(s0.x, s0.y, NEG_HALF_LOG2E * s0.z, -GS_LOG2E * s0.w);
-            rec.b = make_float4(NEG_HALF_LOG2E * s1.x, 0.0f, __int_as_float(m), __uint_as_float(idx - w.start + 1));
-            const float4 *lp = lvl + (vbase + id) * L;
-#pragma unroll
-            for (int t = 0; t < MAXL; ++t)
-                if (t < L) rec.lv[t] = lp[t];
+            rec.b = make_float4(NEG_HALF_LOG2E * s1.x, __uint_as_float(id), __int_as_float(m),
+                                __uint_as_float(idx - w.start + 1));
+            if (!WIDE) {
+                const float4 *lp = lvl + (vbase + id) * L;
+                rec.lv[0] = lp[min(max(f.wave_lo - 1, 0), L - 1)];
+                rec.lv[1] = lp[min(f.wave_lo, L - 1)];
+            }
             keep = m >= f.wave_lo &&
                    reaches_rect(s0.x, s0.y, s0.z, s0.w, s1.x, 9.001f, w.rx0, w.rx1, w.ry0, w.ry1);
         }
@@ -363,12 +370,22 @@ __device__ __forceinline__ void fov_walk(const gs_splat *__restrict__ splats, co
             // branch-free: every lane evaluates, selects take the decisions
             const float4 a = srec[j].a, bb = srec[j].b;
             if (STATS) st[1] += (s.done_a && s.done_b) ? 0.0f : 1.0f;
-            const float p2 = pair_e2(a, bb, w.fpx, w.fpy);  // bb.y = 0: falloff only
+            const float p2 = pair_e2(a, make_float4(bb.x, 0.f, 0.f, 0.f), w.fpx, w.fpy);  // falloff only
             const int m = __float_as_int(bb.z);
             const float G = fast_exp2(p2);
             const bool incl = p2 >= EXTENT_LOG2;
+            float4 lva, lvb;
+            if (!WIDE) {
+                // 0 or 1 inside the image; pixels outside (level 1, done) are clamped
+                lva = srec[j].lv[min(max(f.lo - f.wave_lo, 0), 1)];
+                lvb = srec[j].lv[1];
+            } else {
+                const float4 *lp = lvl + (vbase + __float_as_uint(bb.y)) * L;
+                lva = lp[f.lo - 1];
+                lvb = lp[f.lo < L ? f.lo : L - 1];
+            }
             {
-                const float4 lv = srec[j].lv[f.lo - 1];
+                const float4 lv = lva;
                 const float alpha = fminf(GS_ALPHA_MAX, lv.w * G);
                 const bool use = incl && !s.done_a && m >= f.lo && alpha >= GS_ALPHA_MIN;
                 const float Tn = fmaf(-alpha, s.Ta, s.Ta);
@@ -384,7 +401,7 @@ __device__ __forceinline__ void fov_walk(const gs_splat *__restrict__ splats, co
                 if (STATS) st[0] += blend ? 1.0f : 0.0f;
             }
             if (f.any_two) {
-                const float4 lv = srec[j].lv[f.lo < MAXL ? f.lo : MAXL - 1];
+                const float4 lv = lvb;
                 const float alpha = fminf(GS_ALPHA_MAX, lv.w * G);
                 const bool use = incl && !s.done_b && m >= f.lo + 1 && alpha >= GS_ALPHA_MIN;
                 const float Tn = fmaf(-alpha, s.Tb, s.Tb);
@@ -403,6 +420,22 @@ __device__ __forceinline__ void fov_walk(const gs_splat *__restrict__ splats, co
         }
         wave_lds_sync();
     }
+}
+
+// The two-level records serve every wave whose pixels need at most two
+// levels; the rest read level data from memory (separate instantiations keep
+// memory loads out of the common loop).
+template <bool STATS, bool KEEP = false>
+__device__ __forceinline__ void fov_walk(const gs_splat *__restrict__ splats, const float4 *__restrict__ lvl,
+                                         int n, const uint8_t *__restrict__ qbound, int L,
+                                         const uint32_t *__restrict__ vals, const WaveCtx &w, const FovPix &f,
+                                         uint32_t b, uint32_t e, FovRec *__restrict__ srec, FovState &s,
+                                         float *st)
+{
+    if (f.wide)
+        fov_walk_impl<STATS, KEEP, true>(splats, lvl, n, qbound, L, vals, w, f, b, e, srec, s, st);
+    else
+        fov_walk_impl<STATS, KEEP, false>(splats, lvl, n, qbound, L, vals, w, f, b, e, srec, s, st);
 }
 
 __device__ __forceinline__ void fov_finish(const WaveCtx &w, const FovPix &f, const FovState &s, float bg0,
@@ -1185,29 +1218,35 @@ struct FovArgs {
     gs_fovea f[8];
 };
 
-__global__ void __launch_bounds__(256)
-k_fovea_pix(const gs_camera *__restrict__ cams, int V, int T, int L, int64_t n_pixels, FovArgs fa,
-            uint8_t *__restrict__ pix_level, float *__restrict__ pix_weight)
+// Block rows walk the image rows (rows of all views stacked), 256 pixels of
+// a row per block: no per-pixel index division, per-view constants once.
+__device__ __forceinline__ void fovea_pixel(const gs_camera *__restrict__ cams, int V, int L, const FovArgs &fa,
+                                            int grow, int x, uint8_t *__restrict__ pix_level,
+                                            float *__restrict__ pix_weight)
 {
-    int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (p >= n_pixels) return;
-    const ViewInfo vi = view_of_pixel(cams, V, T, p);
-    const gs_camera &c = cams[vi.v];
-    const gs_fovea f = fa.f[vi.v];
-    int64_t lp = p - vi.pix_off;
-    int x = (int)(lp % vi.W), y = (int)(lp / vi.W);
-    float rx = ((float)x - c.cx) / c.fx, ry = ((float)y - c.cy) / c.fy;
-    float gx = (f.gaze_x - c.cx) / c.fx, gy = (f.gaze_y - c.cy) / c.fy;
+    int row = grow, v = 0;
+    int64_t poff = 0;
+    while (v + 1 < V && row >= cams[v].height) {
+        row -= cams[v].height;
+        poff += (int64_t)cams[v].width * cams[v].height;
+        ++v;
+    }
+    const gs_camera &c = cams[v];
+    if (x >= c.width || row >= c.height) return;
+    const gs_fovea f = fa.f[v];
+    const float ifx = 1.0f / c.fx, ify = 1.0f / c.fy;
+    const float rx = ((float)x - c.cx) * ifx, ry = ((float)row - c.cy) * ify;
+    const float gx = (f.gaze_x - c.cx) * ifx, gy = (f.gaze_y - c.cy) * ify;
     // angle between (rx, ry, 1) and (gx, gy, 1)
-    float cx_ = ry - gy, cy_ = gx - rx, cz_ = rx * gy - ry * gx;
-    float cn = sqrtf(cx_ * cx_ + cy_ * cy_ + cz_ * cz_);
-    float dt = rx * gx + ry * gy + 1.0f;
-    float ecc = atan2f(cn, dt) * 57.29577951308232f;
+    const float cx_ = ry - gy, cy_ = gx - rx, cz_ = rx * gy - ry * gx;
+    const float cn = sqrtf(cx_ * cx_ + cy_ * cy_ + cz_ * cz_);
+    const float dt = rx * gx + ry * gy + 1.0f;
+    const float ecc = atan2f(cn, dt) * 57.29577951308232f;
     int lo = 1;
     float w = 0.0f;
-    float hb = 0.5f * f.band_deg;
+    const float hb = 0.5f * f.band_deg;
     for (int j = 0; j < L - 1; ++j) {
-        float e0 = f.ring_deg[j] - hb, e1 = f.ring_deg[j] + hb;
+        const float e0 = f.ring_deg[j] - hb, e1 = f.ring_deg[j] + hb;
         if (ecc < e0) break;
         if (ecc < e1) {
             lo = j + 1;
@@ -1216,8 +1255,17 @@ k_fovea_pix(const gs_camera *__restrict__ cams, int V, int T, int L, int64_t n_p
         }
         lo = j + 2;
     }
+    const int64_t p = poff + (int64_t)row * c.width + x;
     pix_level[p] = (uint8_t)lo;
     pix_weight[p] = w;
+}
+
+__global__ void __launch_bounds__(256)
+k_fovea_pix(const gs_camera *__restrict__ cams, int V, int L, int rows, FovArgs fa, uint8_t *__restrict__ pix_level,
+            float *__restrict__ pix_weight)
+{
+    const int x = blockIdx.x * blockDim.x + threadIdx.x;
+    for (int r = blockIdx.y; r < rows; r += gridDim.y) fovea_pixel(cams, V, L, fa, r, x, pix_level, pix_weight);
 }
 
 // one wave per tile: lowest and highest level with non-zero weight
@@ -1405,14 +1453,24 @@ hipError_t launch_raster_fov_bwd(const gs_splat *splats, const float *lvl_rgba, 
     return hipGetLastError();
 }
 
-hipError_t launch_fovea_prep(const gs_camera *cams_dev, const gs_fovea *fov_host, int n_eyes, int T,
-                             int n_levels, int64_t n_pixels, int64_t n_tiles, uint8_t *pix_level,
-                             float *pix_weight, uint8_t *tile_level, hipStream_t st)
+hipError_t launch_fovea_prep(const gs_camera *cams_host, const gs_camera *cams_dev, const gs_fovea *fov_host,
+                             int n_eyes, int T, int n_levels, int64_t n_pixels, int64_t n_tiles,
+                             uint8_t *pix_level, float *pix_weight, uint8_t *tile_level, hipStream_t st)
 {
     FovArgs fa;
     for (int i = 0; i < 8; ++i) fa.f[i] = fov_host[i < n_eyes ? i : 0];
-    hipLaunchKernelGGL(k_fovea_pix, dim3((unsigned)((n_pixels + 255) / 256)), dim3(256), 0, st,
-                       cams_dev, n_eyes, T, n_levels, n_pixels, fa, pix_level, pix_weight);
+    int max_w = 0, rows = 0;
+    for (int v = 0; v < n_eyes; ++v) {
+        max_w = cams_host[v].width > max_w ? cams_host[v].width : max_w;
+        rows += cams_host[v].height;
+    }
+    (void)n_pixels;
+    if (rows > 0 && max_w > 0) {
+        // about eight rows per block: a block's setup is longer than one row's work
+        const int gy = (rows + 7) / 8 < 65535 ? (rows + 7) / 8 : 65535;
+        hipLaunchKernelGGL(k_fovea_pix, dim3((unsigned)((max_w + 255) / 256), (unsigned)gy), dim3(256), 0, st,
+                           cams_dev, n_eyes, n_levels, rows, fa, pix_level, pix_weight);
+    }
     hipLaunchKernelGGL(k_fovea_tile, dim3((unsigned)((n_tiles + 3) / 4)), dim3(256), 0, st, cams_dev,
                        n_eyes, T, n_tiles, pix_level, pix_weight, tile_level);
     return hipGetLastError();

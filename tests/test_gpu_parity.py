@@ -204,14 +204,28 @@ def _fr_case(g, sc, cams, fov, tile):
     return C, S, t, splats, lvl, bs, img
 
 
-@pytest.mark.parametrize("tile", [8, 16])
-def test_foveated_matches_oracle(tile):
+def _max_block_span(pl, pw):
+    """Largest number of levels the pixels of one 8 x 8 block use."""
+    hi = pl.astype(np.int32) + (pw > 0)
+    H, W = pl.shape
+    span = 0
+    for y in range(0, H, 8):
+        for x in range(0, W, 8):
+            span = max(span, int(hi[y:y + 8, x:x + 8].max() - pl[y:y + 8, x:x + 8].min()) + 1)
+    return span
+
+
+# the last case puts rings 2 degrees (about 6 pixels) apart: 8 x 8 blocks then
+# need up to four levels, the compositor's path for blocks wider than two
+@pytest.mark.parametrize("tile,rings,band", [(8, (12.0, 24.0, 33.0), 3.5), (16, (12.0, 24.0, 33.0), 3.5),
+                                             (16, (10.0, 12.0, 14.0), 1.0)])
+def test_foveated_matches_oracle(tile, rings, band):
     g = gs()
     sc = scene_small(seed=51, n=4000, fr=4)
     cams = [scenegen.pinhole(300, 170, scenegen.FR_FOV_DEG, t=(0.03, 0.0, 2.0)),
             scenegen.pinhole(300, 170, scenegen.FR_FOV_DEG, t=(-0.03, 0.0, 2.0))]
-    fov = [scenegen.Fovea(160.0, 80.0, rings_deg=(12.0, 24.0, 33.0), band_deg=3.5)] * 2
-    say("foveated", tile)
+    fov = [scenegen.Fovea(160.0, 80.0, rings_deg=rings, band_deg=band)] * 2
+    say("foveated", tile, rings, band)
     C, S, t, splats, lvl, bs, img = _fr_case(g, sc, cams, fov, tile)
     sp = splat_np(splats)
     lvn = lvl.cpu().numpy()
@@ -230,6 +244,8 @@ def test_foveated_matches_oracle(tile):
     imgs = image_views(img, sizes)
     pl = pixel_views(t["pix_level"], sizes)
     pw = pixel_views(t["pix_weight"], sizes)
+    spans = [_max_block_span(pl[v], pw[v]) for v in range(len(cams))]
+    assert (max(spans) == 2) if band > 2.0 else (max(spans) >= 3), spans
     for v, cam in enumerate(cams):
         proj = oracle.splats_to_proj(view_slice(sp, v))
         proj["lvl_opacity"] = lvn[v, :, :, 3].T.astype(np.float64).copy()
