@@ -275,8 +275,8 @@ k_project_bwd(const float *__restrict__ means, const float *__restrict__ log_sca
 
     for (int v = 0; v < V; ++v) {
         int64_t e = (int64_t)v * n + i;
-        const gs_splat &sp = splats[e];
-        if (sp.radius <= 0) continue;
+        // splats culled by the forward carry no gradient: the zero test
+        // below skips them without reading the forward's records
         const gs_splat_grad &g = grads[e];
         // a visible splat that no pixel blended (occluded, or outside every
         // tile's stop point) has an all-zero gradient: nothing to push back
@@ -296,6 +296,28 @@ k_project_bwd(const float *__restrict__ means, const float *__restrict__ log_sca
         float ux = c.R[0] * mx + c.R[1] * my + c.R[2] * mz + c.t[0];
         float uy = c.R[3] * mx + c.R[4] * my + c.R[5] * mz + c.t[1];
         float uz = c.R[6] * mx + c.R[7] * my + c.R[8] * mz + c.t[2];
+        if (!(uz > c.near_z)) continue;  // the forward's near cull
+        // T = J Rc, T Sigma and the conic, as the forward computes them
+        const float iz = 1.0f / uz;
+        const float rx = ux * iz, ry = uy * iz;
+        const float tx = fminf(c.limx, fmaxf(-c.limx, rx));
+        const float ty = fminf(c.limy, fmaxf(-c.limy, ry));
+        const float j00 = c.fx * iz, j02 = -c.fx * tx * iz;
+        const float j11 = c.fy * iz, j12 = -c.fy * ty * iz;
+        const float T0[3] = {j00 * c.R[0] + j02 * c.R[6], j00 * c.R[1] + j02 * c.R[7], j00 * c.R[2] + j02 * c.R[8]};
+        const float T1[3] = {j11 * c.R[3] + j12 * c.R[6], j11 * c.R[4] + j12 * c.R[7], j11 * c.R[5] + j12 * c.R[8]};
+        float TS0[3], TS1[3];
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            TS0[k] = T0[0] * Sg[k] + T0[1] * Sg[3 + k] + T0[2] * Sg[6 + k];
+            TS1[k] = T1[0] * Sg[k] + T1[1] * Sg[3 + k] + T1[2] * Sg[6 + k];
+        }
+        const float ca = TS0[0] * T0[0] + TS0[1] * T0[1] + TS0[2] * T0[2] + 0.3f;
+        const float cb = TS0[0] * T1[0] + TS0[1] * T1[1] + TS0[2] * T1[2];
+        const float cc_ = TS1[0] * T1[0] + TS1[1] * T1[1] + TS1[2] * T1[2] + 0.3f;
+        const float cdet = ca * cc_ - cb * cb;
+        if (!(cdet > 0.0f)) continue;  // the forward's degenerate-covariance cull
+        const float cidet = 1.0f / cdet;
         // opacity
         if (!LEVELS) {
             glogit += g.opacity * opacity * (1.0f - opacity);
@@ -356,7 +378,7 @@ k_project_bwd(const float *__restrict__ means, const float *__restrict__ log_sca
             gm[2] += (gdir[2] - dz * pr) * dist_inv;
         }
         // conic (A, B, C) -> S' = [[a, b], [b, cc]]
-        float A = sp.conic_a, B = sp.conic_b, C = sp.conic_c;
+        const float A = cc_ * cidet, B = -cb * cidet, C = ca * cidet;
         // dL/dS' = -M G M with G the symmetric gradient of [[A, B], [B, C]]
         float GA = g.conic_a, GB = 0.5f * g.conic_b, GC = g.conic_c;
         // M G
@@ -365,15 +387,6 @@ k_project_bwd(const float *__restrict__ means, const float *__restrict__ log_sca
         float dS00 = -(mg00 * A + mg01 * B);
         float dS01 = -(mg00 * B + mg01 * C);
         float dS11 = -(mg10 * B + mg11 * C);
-        // recompute T = J Rc
-        float iz = 1.0f / uz;
-        float rx = ux * iz, ry = uy * iz;
-        float tx = fminf(c.limx, fmaxf(-c.limx, rx));
-        float ty = fminf(c.limy, fmaxf(-c.limy, ry));
-        float j00 = c.fx * iz, j02 = -c.fx * tx * iz;
-        float j11 = c.fy * iz, j12 = -c.fy * ty * iz;
-        float T0[3] = {j00 * c.R[0] + j02 * c.R[6], j00 * c.R[1] + j02 * c.R[7], j00 * c.R[2] + j02 * c.R[8]};
-        float T1[3] = {j11 * c.R[3] + j12 * c.R[6], j11 * c.R[4] + j12 * c.R[7], j11 * c.R[5] + j12 * c.R[8]};
         // dSigma += T^T dS T  (dS symmetric)
 #pragma unroll
         for (int r = 0; r < 3; ++r)
@@ -381,12 +394,6 @@ k_project_bwd(const float *__restrict__ means, const float *__restrict__ log_sca
             for (int k = 0; k < 3; ++k)
                 dSig[r * 3 + k] += T0[r] * (dS00 * T0[k] + dS01 * T1[k]) + T1[r] * (dS01 * T0[k] + dS11 * T1[k]);
         // dT = 2 dS T Sigma
-        float TS0[3], TS1[3];
-#pragma unroll
-        for (int k = 0; k < 3; ++k) {
-            TS0[k] = T0[0] * Sg[k] + T0[1] * Sg[3 + k] + T0[2] * Sg[6 + k];
-            TS1[k] = T1[0] * Sg[k] + T1[1] * Sg[3 + k] + T1[2] * Sg[6 + k];
-        }
         float dT0[3], dT1[3];
 #pragma unroll
         for (int k = 0; k < 3; ++k) {
