@@ -39,9 +39,9 @@ FLOPS_PER_BLEND = 23
 # averaged over the dispatches), each scaled by the ratio of known bytes to
 # the same counter on a plain device copy (bench.py --copy-probe).  Valid
 # only for the kernel sources they were taken on (sha256 below).
-TRAFFIC = {"kernel": "k_raster_fov", "fetch_kib": 392352.6, "write_kib": 56503.8, "fetch_scale": 1.9999,
+TRAFFIC = {"kernel": "k_raster_fov", "fetch_kib": 562906.1, "write_kib": 57112.4, "fetch_scale": 1.9999,
            "write_scale": 1.0,
-           "sha256": "d20d75c2022537c4104e8a711bfce21377eef5255330a549d599865dbe3fd1b4"}
+           "sha256": "c3500cb0952d3f289d0846e751c970082c9860bbcbfc37c3c0270b6bcf46d280"}
 
 
 def kernel_sha():

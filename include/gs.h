@@ -212,7 +212,10 @@ int gs_rasterize_bwd(const gs_splat *splats, int32_t n, const gs_camera *cams_ho
  * summed over views.  Outputs (device): d_means [n][3], d_log_scales [n][3],
  * d_quats [n][4], d_opacity_logits [n], d_sh [n][K][3]; overwritten when
  * accumulate is 0, added to when it is 1 (views rendered by separate calls
- * sum their gradients this way). */
+ * sum their gradients this way).  The projection is recomputed from the
+ * scene; splats (the forward's output) is accepted for interface symmetry and
+ * not read.  A (view, point) whose gradient record is all zero, or that the
+ * forward culls (near plane, degenerate covariance), contributes nothing. */
 int gs_project_bwd(const gs_scene *scene, const gs_camera *cams_host, const gs_camera *cams_dev,
                    int n_views, const gs_splat *splats, const gs_splat_grad *grads,
                    float *d_means, float *d_log_scales, float *d_quats,

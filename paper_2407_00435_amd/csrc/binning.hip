@@ -1004,7 +1004,8 @@ hipError_t launch_bin_sort(const gs_splat *splats, int n, const gs_camera *cams_
                        bs.chunk);
     // 4c-4e: per-tile counts, their scans (tile ranges), keys at their final positions
     const int pass_blocks = grid_for(bin_max_chunks(cap, n_tiles), 4, 2048);
-    hipLaunchKernelGGL((k_tile_pass<false>), dim3(pass_blocks), dim3(256), 0, st, sp, bs.chunk, bs.counts, bs.vtab, bs.stab, V, n, tile_level, bs.ccnt,
+    hipLaunchKernelGGL((k_tile_pass<false>), dim3(pass_blocks), dim3(256), 0, st, sp, bs.chunk, bs.counts, bs.vtab,
+                       bs.stab, V, n, tile_level, bs.ccnt,
                        ranges, vals, keys, splats);
     hipLaunchKernelGGL(k_col_scan, dim3((unsigned)n_st), dim3(COL_WAVES * 64), 0, st, bs.chunk_off, bs.vtab, bs.stab, V,
                        bs.ccnt, bs.tot);
@@ -1014,7 +1015,8 @@ hipError_t launch_bin_sort(const gs_splat *splats, int n, const gs_camera *cams_
                        nullptr);
     hipLaunchKernelGGL(k_tile_ranges, dim3((unsigned)nbt), dim3(SCAN_THREADS), 0, st, bs.tot, n_tiles, bs.tsum,
                        bs.counts, ranges);
-    hipLaunchKernelGGL((k_tile_pass<true>), dim3(pass_blocks), dim3(256), 0, st, sp, bs.chunk, bs.counts, bs.vtab, bs.stab, V, n, tile_level, bs.ccnt,
+    hipLaunchKernelGGL((k_tile_pass<true>), dim3(pass_blocks), dim3(256), 0, st, sp, bs.chunk, bs.counts, bs.vtab,
+                       bs.stab, V, n, tile_level, bs.ccnt,
                        ranges, vals, keys, splats);
     return hipGetLastError();
 }
