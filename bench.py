@@ -329,6 +329,59 @@ def cpu_baseline(fr, wl, n_gauss_sample=12000, px_sample=(3000, 9000), threads=1
                 frame_s=frame)
 
 
+def hbm_bandwidth(g, fr, stage_ms, reps=10):
+    """Achieved HBM bandwidth of the projection and of the radix sort, against a
+    plain device copy on the same GPU (the achievable reference) and the
+    published 8 TB/s.  Projection bytes are algorithmic: per Gaussian 236 B of
+    SH3 parameters + 65 B of level data read, per (Gaussian, eye) 48 B of splat +
+    4 x 16 B of level colour/opacity written.  Sort bytes: one 4 B key read for
+    the histogram, then per 8-bit pass an 8 B (key, value) read and write."""
+    import torch
+    B = g.binding
+    src = torch.ones(256 << 20, dtype=torch.float32, device="cuda")  # 1 GiB
+    dst = torch.empty_like(src)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    e0.record()
+    for _ in range(reps):
+        dst.copy_(src)
+    e1.record()
+    torch.cuda.synchronize()
+    copy_gbs = 2 * src.numel() * 4 * reps / (e0.elapsed_time(e1) * 1e-3) / 1e9
+    del src, dst
+    out = {"copy_gbs": copy_gbs, "peak_gbs": 8000.0}
+    eyes = fr.C.n
+    proj_bytes = fr.n * (236 + 65) + fr.n * eyes * (48 + 4 * 16)
+    gbs = proj_bytes / (stage_ms["project"] * 1e-3) / 1e9
+    out["project"] = {"bytes": proj_bytes, "gbs": gbs, "frac_of_copy": gbs / copy_gbs, "frac_of_peak": gbs / 8000.0}
+    L = B.lib()
+    for label, count in (("sort_2.9M", int(fr.n * eyes * 0.955)), ("sort_64M", 64 << 20)):
+        gen = torch.Generator(device="cuda").manual_seed(7)
+        k0 = torch.randint(0, 2 ** 31 - 1, (count,), dtype=torch.int32, device="cuda", generator=gen)
+        v0 = torch.arange(count, dtype=torch.int32, device="cuda")
+        k, v, kt, vt = k0.clone(), v0.clone(), torch.empty_like(k0), torch.empty_like(v0)
+        ws = B._ws(int(L.gs_sort_workspace_bytes(count)))
+        t = 0.0
+        for r in range(reps + 1):
+            k.copy_(k0)
+            v.copy_(v0)
+            e0.record()
+            B._check(L.gs_sort_pairs(B._ptr(k), B._ptr(v), B._ptr(kt), B._ptr(vt), count, 32, ws[1], ws[2],
+                                     B._stream()))
+            e1.record()
+            torch.cuda.synchronize()
+            if r:
+                t += e0.elapsed_time(e1) * 1e-3
+        t /= reps
+        nbytes = count * (4 + 4 * 16)
+        gbs = nbytes / t / 1e9
+        out[label] = {"keys": count, "bits": 32, "ms": t * 1e3, "bytes": nbytes, "gbs": gbs,
+                      "frac_of_copy": gbs / copy_gbs, "frac_of_peak": gbs / 8000.0}
+        del k0, v0, k, v, kt, vt, ws
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -402,6 +455,8 @@ def main():
                      "traffic": traffic_bytes()},
     }
     if not args.no_extras:
+        log("HBM bandwidth of projection and sort ...")
+        line["hbm"] = hbm_bandwidth(g, fr, stage_ms)
         log("plain forward, 500k Gaussians, 1280x720 ...")
         line["plain_fwd_720p_500k"] = plain_fwd_rate(g, scenegen.config2(), 20, 3)
         log("forward+backward, 1M Gaussians, 1280x720 ...")
