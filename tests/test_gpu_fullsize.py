@@ -10,7 +10,9 @@ bands) against the FP64 oracle's per-pixel compositing.  Config 2 (the plain
 forward: 500k Gaussians, 1280x720) is checked the same way.  Config 5 (3M
 Gaussians, 32 views + 2 eyes) checks that the batched schedule the bench
 times gives the one-view-per-call schedule's results: images bit for bit,
-gradients to float32 reassociation (1e-4 relative L2).
+gradients within the run-to-run spread of float atomics.  Config 4 (1M
+Gaussians, forward + backward through autograd) checks sampled pixels and
+that autograd equals the reverse passes called one by one.
 """
 import numpy as np
 import pytest
@@ -197,3 +199,53 @@ def test_config5_batched_equals_one_view_per_call():
     for k, e in errs.items():
         assert e <= 4.0 * noise[k] + 1e-5, k
         assert e < 1e-3, k
+
+
+def test_config4_forward_backward_full_size():
+    """The bench's autograd step at full size: sampled pixels against the
+    oracle, and the autograd gradients equal to the reverse passes called one
+    by one through the C ABI (the per-pixel reverse is checked against the
+    oracle and FP64 finite differences on the subcase the workload prescribes,
+    in the parity tests)."""
+    g = gs()
+    say("config 4 full size: autograd forward + backward")
+    wl = scenegen.config4()
+    S, C = g.SceneTensors(wl.scene), g.Cameras(wl.cams)
+    T = 16
+    tgt_S = g.SceneTensors(wl.extra["target_scene"])
+    names = ("means", "log_scales", "quats", "opacity_logits", "sh")
+    with torch.no_grad():
+        target = g.render(*(tgt_S.t[k] for k in names), C, tgt_S.sh_degree, T)
+    params = [S.t[k].clone().requires_grad_(True) for k in names]
+    splats = g.gs_project(S, C, T)
+    cap = int(splats[..., 11].view(torch.int32).to(torch.int64).sum().item())
+    img = g.render(*params, C, S.sh_degree, T, key_capacity=cap)
+    loss = (img - target).abs().mean()
+    loss.backward()
+    torch.cuda.synchronize()
+    for p, k in zip(params, names):
+        assert torch.isfinite(p.grad).all(), k
+    cam = wl.cams[0]
+    W, H = cam.width, cam.height
+    # forward: sampled pixels against the oracle
+    out = g.gs_render_fwd(S, C, T, key_capacity=cap)
+    torch.cuda.synchronize()
+    assert torch.equal(out["image"], img.detach())
+    sp = splat_np(out["splats"])
+    rng = np.random.default_rng(4)
+    pix = sample_pixels(rng, W, H, T, out["ranges"].cpu().numpy().view(np.uint32), (W + T - 1) // T,
+                        n_random=2000)
+    ref = oracle.composite(oracle.splats_to_proj(view_slice(sp, 0)), W, H, pixels=pix, nthreads=16)
+    gpu = img.detach().cpu().numpy().reshape(3, H, W)[:, pix[:, 1], pix[:, 0]].T
+    err, namb = check_envelope(gpu, ref, max_unresolved_frac=1e-3)
+    say(f"config 4: forward max err {err:.3g}, ambiguous {namb}")
+    # reverse: the same chain called stage by stage
+    dL = (torch.sign(img.detach() - target) / img.numel()).contiguous()
+    grads = g.gs_rasterize_bwd(out["splats"], S.n, C, T, out["vals"], out["ranges"], out["final_T"],
+                               out["n_contrib"], dL)
+    pg = g.gs_project_bwd(S, C, out["splats"], grads)
+    torch.cuda.synchronize()
+    errs = {k: rel_l2(p.grad.cpu().numpy(), pg[k].cpu().numpy()) for p, k in zip(params, names)}
+    say("config 4: autograd vs staged calls " + ", ".join(f"{k} {e:.2e}" for k, e in errs.items()))
+    for k, e in errs.items():
+        assert e < 1e-4, k
