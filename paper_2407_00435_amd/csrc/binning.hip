@@ -27,8 +27,6 @@ constexpr int TST = ST * ST;              // tiles per super-tile (<= wave size)
 constexpr int MS = 4;                     // coarse masks cover spans of up to MS x MS super-tiles
 constexpr uint32_t CHUNK = BIN_CHUNK;     // coarse pairs per chunk
 
-__global__ void k_set_u64(uint64_t *__restrict__ p, uint64_t value) { *p = value; }
-
 __global__ void __launch_bounds__(256)
 k_fill_u32(uint32_t *__restrict__ p, uint32_t value, uint64_t count)
 {
@@ -44,12 +42,23 @@ __device__ __forceinline__ int64_t view_tile_off(const gs_camera *__restrict__ c
     return toff;
 }
 
-// Tile offset and grid width of every view: vtab[v] = {first tile, tiles_x};
-// stab[v] = {first super-tile, super-tiles per row, tiles_x, tiles_y}.
-__global__ void __launch_bounds__(64)
-k_view_table(const gs_camera *__restrict__ cams, int V, int T, int64_t *__restrict__ vtab, int4 *__restrict__ stab)
+// Set-up of one binning call: the tile offset and grid width of every view,
+// vtab[v] = {first tile, tiles_x}, stab[v] = {first super-tile, super-tiles
+// per row, tiles_x, tiles_y}; the key capacity in *cap_out; zeroed tile and
+// super-tile ranges (a tile without keys keeps (0, 0)); and, when given,
+// *num_keys = 0 (no entries at all).
+__global__ void __launch_bounds__(256)
+k_bin_setup(const gs_camera *__restrict__ cams, int V, int T, int64_t *__restrict__ vtab, int4 *__restrict__ stab,
+            uint64_t *__restrict__ cap_out, uint64_t cap, uint32_t *__restrict__ ranges, int64_t n_tiles,
+            uint32_t *__restrict__ st_ranges, int64_t n_st, uint64_t *__restrict__ num_keys)
 {
-    if (threadIdx.x != 0) return;
+    const uint64_t i0 = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    for (uint64_t i = i0; i < 2 * (uint64_t)n_tiles; i += stride) ranges[i] = 0;
+    for (uint64_t i = i0; i < 2 * (uint64_t)n_st; i += stride) st_ranges[i] = 0;
+    if (i0 != 0) return;
+    *cap_out = cap;
+    if (num_keys) *num_keys = 0;
     int64_t toff = 0;
     int soff = 0;
     for (int v = 0; v < V; ++v) {
@@ -215,20 +224,18 @@ k_count(const gs_splat *__restrict__ splats, int n, const gs_camera *__restrict_
     if (threadIdx.x == 0) block_vis[blockIdx.x] = s_cnt;
 }
 
-// Exclusive scan of nb block values in place (one workgroup); the total goes
-// to *total, or 0 when cap_ptr is given and the total exceeds *cap_ptr (and,
-// if given, the unclamped total to *num_keys).
-__global__ void __launch_bounds__(1024)
-k_scan_blocks(uint64_t *__restrict__ block_sums, const uint32_t *__restrict__ block_u32, int64_t nb,
-              uint64_t *__restrict__ total, const uint64_t *__restrict__ cap_ptr,
-              uint64_t *__restrict__ num_keys)
+// Exclusive scan of nb block values in place by one workgroup of 1024
+// threads (block_u32, when given, holds the values as u32); returns the
+// total to every thread.
+__device__ uint64_t scan_blocks_body(uint64_t *__restrict__ s, uint64_t *__restrict__ block_sums,
+                                     const uint32_t *__restrict__ block_u32, int64_t nb)
 {
-    __shared__ uint64_t s[1024];
-    int t = threadIdx.x;
-    int64_t per = (nb + 1023) / 1024;
-    int64_t b0 = t * per, b1 = b0 + per < nb ? b0 + per : nb;
+    const int t = threadIdx.x;
+    const int64_t per = (nb + 1023) / 1024;
+    const int64_t b0 = t * per, b1 = b0 + per < nb ? b0 + per : nb;
     uint64_t local = 0;
     for (int64_t b = b0; b < b1; ++b) local += block_u32 ? block_u32[b] : block_sums[b];
+    __syncthreads();  // s may still be read by a previous scan
     s[t] = local;
     __syncthreads();
     for (int off = 1; off < 1024; off <<= 1) {
@@ -243,12 +250,38 @@ k_scan_blocks(uint64_t *__restrict__ block_sums, const uint32_t *__restrict__ bl
         block_sums[b] = run;
         run += x;
     }
-    if (t == 1023) {
-        const uint64_t tot = s[1023];
-        // with a capacity, a total above it reads as zero: on overflow nothing
-        // downstream reads the (partial) key list; num_keys reports what is needed
-        *total = (!cap_ptr || tot <= *cap_ptr) ? tot : 0;
-        if (num_keys) *num_keys = tot;
+    return s[1023];
+}
+
+// Exclusive scan of nb block values in place (one workgroup); the total goes
+// to *total.
+__global__ void __launch_bounds__(1024)
+k_scan_blocks(uint64_t *__restrict__ block_sums, const uint32_t *__restrict__ block_u32, int64_t nb,
+              uint64_t *__restrict__ total)
+{
+    __shared__ uint64_t s[1024];
+    const uint64_t tot = scan_blocks_body(s, block_sums, block_u32, nb);
+    if (threadIdx.x == 1023) *total = tot;
+}
+
+// The two scans after the gather, in one workgroup: block key counts (total
+// to *keys_total, or 0 when it exceeds *cap_ptr; the unclamped total to
+// *num_keys) and block coarse-pair counts (total to *pairs_total, or 0 when
+// the key total was 0: coarse pairs never outnumber keys, so this is the
+// overflow case).  On overflow nothing downstream reads the partial lists.
+__global__ void __launch_bounds__(1024)
+k_scan_pair(uint64_t *__restrict__ key_sums, uint64_t *__restrict__ pair_sums, int64_t nb,
+            uint64_t *__restrict__ keys_total, const uint64_t *__restrict__ cap_ptr,
+            uint64_t *__restrict__ num_keys, uint64_t *__restrict__ pairs_total)
+{
+    __shared__ uint64_t s[1024];
+    const uint64_t kt = scan_blocks_body(s, key_sums, nullptr, nb);
+    const uint64_t kc = kt <= *cap_ptr ? kt : 0;
+    const uint64_t pt = scan_blocks_body(s, pair_sums, nullptr, nb);
+    if (threadIdx.x == 1023) {
+        *keys_total = kc;
+        if (num_keys) *num_keys = kt;
+        *pairs_total = pt <= kc ? pt : 0;
     }
 }
 
@@ -579,12 +612,29 @@ k_coarse_emit(const uint4 *__restrict__ rec_s, const uint32_t *__restrict__ cc_s
     }
 }
 
+// View of a super-tile: the last view whose first super-tile is <= s.
+__device__ __forceinline__ int view_of_st(const int4 *__restrict__ stab, int V, int s)
+{
+    int lo = 0, hi = V - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (stab[mid].x <= s)
+            lo = mid;
+        else
+            hi = mid - 1;
+    }
+    return lo;
+}
+
 // Chunks of every super-tile's run: chunk_off[s] = first chunk of s
 // (chunk_off[n_st] = their number, also in *n_chunks).  One workgroup; each
-// thread takes consecutive super-tiles.
+// thread takes consecutive super-tiles.  With FILL (n_st <= 1024, one
+// super-tile per thread) the same workgroup also writes the chunk records,
+// chunk[c] = {first pair, end pair, super-tile, view}, a wave per super-tile.
+template <bool FILL>
 __global__ void __launch_bounds__(1024)
 k_chunk_table(const uint32_t *__restrict__ st_ranges, int64_t n_st, uint32_t *__restrict__ chunk_off,
-              uint64_t *__restrict__ n_chunks)
+              uint64_t *__restrict__ n_chunks, const int4 *__restrict__ stab, int V, uint4 *__restrict__ chunk)
 {
     __shared__ uint32_t s[1024];
     const int t = threadIdx.x;
@@ -609,20 +659,20 @@ k_chunk_table(const uint32_t *__restrict__ st_ranges, int64_t n_st, uint32_t *__
         chunk_off[n_st] = s[1023];
         *n_chunks = s[1023];
     }
-}
-
-// View of a super-tile: the last view whose first super-tile is <= s.
-__device__ __forceinline__ int view_of_st(const int4 *__restrict__ stab, int V, int s)
-{
-    int lo = 0, hi = V - 1;
-    while (lo < hi) {
-        const int mid = (lo + hi + 1) >> 1;
-        if (stab[mid].x <= s)
-            lo = mid;
-        else
-            hi = mid - 1;
+    if constexpr (FILL) {
+        // s[q] is the inclusive chunk prefix of super-tile q (per == 1)
+        const int wave = t >> 6, lane = t & 63;
+        for (int64_t q = wave; q < n_st; q += 1024 / 64) {
+            const uint32_t c1 = s[q], c0 = q > 0 ? s[q - 1] : 0u;
+            if (c1 == c0) continue;
+            const uint32_t bq = st_ranges[2 * q], eq = st_ranges[2 * q + 1];
+            const uint32_t v = (uint32_t)view_of_st(stab, V, (int)q);
+            for (uint32_t c = c0 + lane; c < c1; c += 64) {
+                const uint32_t bb = bq + (c - c0) * CHUNK;
+                chunk[c] = make_uint4(bb, eq < bb + CHUNK ? eq : bb + CHUNK, (uint32_t)q, v);
+            }
+        }
     }
-    return lo;
 }
 
 // Chunk records: chunk[c] = {first pair, end pair, super-tile, view}.  One
@@ -877,6 +927,53 @@ k_tile_ranges(const uint32_t *__restrict__ tot, int64_t n_tiles, const uint64_t 
     }
 }
 
+// 4d in one workgroup (grids of up to TILE_SCAN1_MAX tiles): tile ranges
+// from the totals, SCAN_ITEMS consecutive tiles per thread, segment after
+// segment with a running carry; an empty tile gets (0, 0).
+constexpr int TS1_THREADS = 1024;
+constexpr int64_t TILE_SCAN1_MAX = 4 * TS1_THREADS * SCAN_ITEMS;
+__global__ void __launch_bounds__(TS1_THREADS)
+k_tile_scan1(const uint32_t *__restrict__ tot, int64_t n_tiles, const uint64_t *__restrict__ counts,
+             uint32_t *__restrict__ ranges)
+{
+    __shared__ uint64_t s_w[TS1_THREADS / 64];
+    if (counts[1] == 0) return;  // ranges stay zero
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    uint64_t carry = 0;
+    for (int64_t seg = 0; seg < n_tiles; seg += TS1_THREADS * SCAN_ITEMS) {
+        const int64_t g0 = seg + (int64_t)threadIdx.x * SCAN_ITEMS;
+        uint32_t t[SCAN_ITEMS];
+        uint64_t local = 0;
+#pragma unroll
+        for (int j = 0; j < SCAN_ITEMS; ++j) {
+            t[j] = g0 + j < n_tiles ? tot[g0 + j] : 0u;
+            local += t[j];
+        }
+        uint64_t x = local;
+        for (int off = 1; off < 64; off <<= 1) {
+            const uint64_t y = __shfl_up(x, off);
+            if (lane >= off) x += y;
+        }
+        if (lane == 63) s_w[wave] = x;
+        __syncthreads();
+        uint64_t run = carry + x - local, segtot = 0;
+        for (int w = 0; w < TS1_THREADS / 64; ++w) {
+            const uint64_t sw = s_w[w];
+            run += w < wave ? sw : 0;
+            segtot += sw;
+        }
+#pragma unroll
+        for (int j = 0; j < SCAN_ITEMS; ++j) {
+            if (g0 + j < n_tiles)
+                reinterpret_cast<uint2 *>(ranges)[g0 + j] =
+                    t[j] ? make_uint2((uint32_t)run, (uint32_t)(run + t[j])) : make_uint2(0u, 0u);
+            run += t[j];
+        }
+        carry += segtot;
+        __syncthreads();  // s_w is rewritten by the next segment
+    }
+}
+
 // Super-tile ranges: four sorted ids per thread; a boundary between k - 1
 // and k closes one run and opens the next.
 __global__ void __launch_bounds__(256)
@@ -939,14 +1036,6 @@ hipError_t launch_bin_sort(const gs_splat *splats, int n, const gs_camera *cams_
 {
     const int64_t E = (int64_t)V * n;
     hipError_t err;
-    hipLaunchKernelGGL(k_set_u64, dim3(1), dim3(1), 0, st, bs.counts + 2, cap);
-    if ((err = launch_fill_u32(ranges, 0u, 2 * (uint64_t)n_tiles, st)) != hipSuccess) return err;
-    if (E == 0) {
-        hipLaunchKernelGGL(k_set_u64, dim3(1), dim3(1), 0, st, num_keys, (uint64_t)0);
-        return hipGetLastError();
-    }
-    const bool filt = tile_level != nullptr;
-    const int L = n_levels < 1 ? 1 : (n_levels > 4 ? 4 : n_levels);
     int64_t n_st = 0;
     int max_view_tiles = 0;
     for (int v = 0; v < V; ++v) {
@@ -954,7 +1043,12 @@ hipError_t launch_bin_sort(const gs_splat *splats, int n, const gs_camera *cams_
         n_st += (int64_t)((tx + ST - 1) / ST) * ((ty + ST - 1) / ST);
         max_view_tiles = tx * ty > max_view_tiles ? tx * ty : max_view_tiles;
     }
-    hipLaunchKernelGGL(k_view_table, dim3(1), dim3(64), 0, st, cams_dev, V, T, bs.vtab, bs.stab);
+    hipLaunchKernelGGL(k_bin_setup, dim3(grid_for(2 * (uint64_t)(n_tiles > n_st ? n_tiles : n_st), 256 * 4, 256)),
+                       dim3(256), 0, st, cams_dev, V, T, bs.vtab, bs.stab, bs.counts + 2, cap, ranges, n_tiles,
+                       bs.st_ranges, n_st, E == 0 ? num_keys : nullptr);
+    if (E == 0) return hipGetLastError();
+    const bool filt = tile_level != nullptr;
+    const int L = n_levels < 1 ? 1 : (n_levels > 4 ? 4 : n_levels);
     if (filt) {
         const int lds = max_view_tiles <= SAT_LDS_TILES;
         hipLaunchKernelGGL(k_level_sat, dim3(V * L), dim3(256), lds ? 4 * max_view_tiles : 0, st, cams_dev,
@@ -968,9 +1062,8 @@ hipError_t launch_bin_sort(const gs_splat *splats, int n, const gs_camera *cams_
     // 1-2: counts, then stable compaction of entries with keys (depth digits counted)
     hipLaunchKernelGGL(k_count, dim3((unsigned)nb), dim3(COUNT_THREADS), 0, st, splats, n, cams_dev, V, T, bs.vtab,
                        sat, bs.bbox, L, n_tiles, qbound, bs.hits, bs.rec, bs.dkey_b, hits_out, bs.block_vis);
-    hipLaunchKernelGGL(k_scan_blocks, dim3(1), dim3(1024), 0, st, bs.block_sums, bs.block_vis, nb, bs.counts,
-                       nullptr, nullptr);
-    if ((err = launch_fill_u32(bs.rs.hist, 0u, 4 * 256, st)) != hipSuccess) return err;
+    hipLaunchKernelGGL(k_scan_blocks, dim3(1), dim3(1024), 0, st, bs.block_sums, bs.block_vis, nb, bs.counts);
+    if ((err = radix_sort_prepare(bs.rs, bs.counts, (uint64_t)E, 4, st)) != hipSuccess) return err;
     hipLaunchKernelGGL(k_compact, dim3((unsigned)nb), dim3(COUNT_THREADS), 0, st, bs.hits, bs.dkey_b, E,
                        bs.block_sums, bs.dkey_a, bs.dval_a, bs.rs.hist);
     // 3: depth sort of the entries with keys (4 x 8-bit passes), result back in (dkey_a, dval_a)
@@ -980,11 +1073,8 @@ hipError_t launch_bin_sort(const gs_splat *splats, int n, const gs_camera *cams_
     // 4a: records in depth order; totals of keys (capacity rule) and coarse pairs
     hipLaunchKernelGGL(k_gather, dim3((unsigned)nb), dim3(GATHER_THREADS), 0, st, bs.dval_a, bs.rec, bs.counts, n,
                        bs.vtab, bs.stab, sat, bs.st_cls, L, n_tiles, bs.rec_s, bs.cc_s, bs.block_sums, bs.block_sums2);
-    hipLaunchKernelGGL(k_scan_blocks, dim3(1), dim3(1024), 0, st, bs.block_sums, nullptr, nb, bs.counts + 1,
-                       bs.counts + 2, num_keys);
-    // coarse pairs <= keys, so a coarse total above the key total means overflow
-    hipLaunchKernelGGL(k_scan_blocks, dim3(1), dim3(1024), 0, st, bs.block_sums2, nullptr, nb, bs.counts + 3,
-                       bs.counts + 1, nullptr);
+    hipLaunchKernelGGL(k_scan_pair, dim3(1), dim3(1024), 0, st, bs.block_sums, bs.block_sums2, nb, bs.counts + 1,
+                       bs.counts + 2, num_keys, bs.counts + 3);
     // 4b: coarse pairs with their payloads, stably sorted by super-tile
     int st_bits = 1;
     while ((int64_t(1) << st_bits) < n_st) ++st_bits;
@@ -996,12 +1086,17 @@ hipError_t launch_bin_sort(const gs_splat *splats, int n, const gs_camera *cams_
         return err;
     const uint32_t *sk = even ? bs.tkey_a : bs.tkey_b;
     const uint2 *sp = even ? bs.cpay_a : bs.cpay_b;
-    if ((err = launch_fill_u32(bs.st_ranges, 0u, 2 * (uint64_t)n_st, st)) != hipSuccess) return err;
     hipLaunchKernelGGL(k_ranges, dim3(grid_for(cap, 256 * 16, 8192)), dim3(256), 0, st, sk, bs.counts + 3, cap,
                        n_st, bs.st_ranges);
-    hipLaunchKernelGGL(k_chunk_table, dim3(1), dim3(1024), 0, st, bs.st_ranges, n_st, bs.chunk_off, bs.counts + 4);
-    hipLaunchKernelGGL(k_chunk_fill, dim3((unsigned)n_st), dim3(256), 0, st, bs.st_ranges, bs.chunk_off, bs.stab, V,
-                       bs.chunk);
+    if (n_st <= 1024) {
+        hipLaunchKernelGGL(k_chunk_table<true>, dim3(1), dim3(1024), 0, st, bs.st_ranges, n_st, bs.chunk_off,
+                           bs.counts + 4, bs.stab, V, bs.chunk);
+    } else {
+        hipLaunchKernelGGL(k_chunk_table<false>, dim3(1), dim3(1024), 0, st, bs.st_ranges, n_st, bs.chunk_off,
+                           bs.counts + 4, bs.stab, V, bs.chunk);
+        hipLaunchKernelGGL(k_chunk_fill, dim3((unsigned)n_st), dim3(256), 0, st, bs.st_ranges, bs.chunk_off, bs.stab,
+                           V, bs.chunk);
+    }
     // 4c-4e: per-tile counts, their scans (tile ranges), keys at their final positions
     const int pass_blocks = grid_for(bin_max_chunks(cap, n_tiles), 4, 2048);
     hipLaunchKernelGGL((k_tile_pass<false>), dim3(pass_blocks), dim3(256), 0, st, sp, bs.chunk, bs.counts, bs.vtab,
@@ -1009,12 +1104,15 @@ hipError_t launch_bin_sort(const gs_splat *splats, int n, const gs_camera *cams_
                        ranges, vals, keys, splats);
     hipLaunchKernelGGL(k_col_scan, dim3((unsigned)n_st), dim3(COL_WAVES * 64), 0, st, bs.chunk_off, bs.vtab, bs.stab, V,
                        bs.ccnt, bs.tot);
-    const int64_t nbt = (n_tiles + SCAN_THREADS * SCAN_ITEMS - 1) / (SCAN_THREADS * SCAN_ITEMS);
-    hipLaunchKernelGGL(k_tile_reduce, dim3((unsigned)nbt), dim3(SCAN_THREADS), 0, st, bs.tot, n_tiles, bs.tsum);
-    hipLaunchKernelGGL(k_scan_blocks, dim3(1), dim3(1024), 0, st, bs.tsum, nullptr, nbt, bs.counts + 5, nullptr,
-                       nullptr);
-    hipLaunchKernelGGL(k_tile_ranges, dim3((unsigned)nbt), dim3(SCAN_THREADS), 0, st, bs.tot, n_tiles, bs.tsum,
-                       bs.counts, ranges);
+    if (n_tiles <= TILE_SCAN1_MAX) {
+        hipLaunchKernelGGL(k_tile_scan1, dim3(1), dim3(TS1_THREADS), 0, st, bs.tot, n_tiles, bs.counts, ranges);
+    } else {
+        const int64_t nbt = (n_tiles + SCAN_THREADS * SCAN_ITEMS - 1) / (SCAN_THREADS * SCAN_ITEMS);
+        hipLaunchKernelGGL(k_tile_reduce, dim3((unsigned)nbt), dim3(SCAN_THREADS), 0, st, bs.tot, n_tiles, bs.tsum);
+        hipLaunchKernelGGL(k_scan_blocks, dim3(1), dim3(1024), 0, st, bs.tsum, nullptr, nbt, bs.counts + 5);
+        hipLaunchKernelGGL(k_tile_ranges, dim3((unsigned)nbt), dim3(SCAN_THREADS), 0, st, bs.tot, n_tiles, bs.tsum,
+                           bs.counts, ranges);
+    }
     hipLaunchKernelGGL((k_tile_pass<true>), dim3(pass_blocks), dim3(256), 0, st, sp, bs.chunk, bs.counts, bs.vtab,
                        bs.stab, V, n, tile_level, bs.ccnt,
                        ranges, vals, keys, splats);

@@ -32,8 +32,9 @@ hipError_t launch_l1_grad(const float *image, const float *target, uint64_t n, f
 // radix sort of (u32 key, u32 value) pairs, LSD over bits [0, bits)
 struct RadixScratch {
     uint32_t *hist;     // [4][256] digit counts, then exclusive bases
-    uint64_t *status;   // [max_parts][256] lookback words
+    uint64_t *status;   // [2][status_words] lookback words, two buffers
     uint32_t *tickets;  // [4] partition tickets, one per pass
+    uint64_t status_words;  // words per buffer: 256 per partition
 };
 // partitions the lookback status must hold for `cap` keys (smallest partition)
 uint64_t radix_max_parts(uint64_t cap);
@@ -53,6 +54,11 @@ hipError_t radix_sort_pairs(uint32_t *ka, uint32_t *va, uint32_t *kb, uint32_t *
 hipError_t radix_sort_pairs_v2(uint32_t *ka, uint2 *va, uint32_t *kb, uint2 *vb, const uint64_t *d_count,
                                uint64_t cap, int bits, const RadixScratch &rs, hipStream_t st);
 
+// zeroes the digit counts, tickets and first-pass lookback words of a sort
+// of min(*d_count, cap) pairs with vbytes-byte values; a caller that builds
+// the digit counts itself (hist_ready) calls it first
+hipError_t radix_sort_prepare(const RadixScratch &rs, const uint64_t *d_count, uint64_t cap, int vbytes,
+                              hipStream_t st);
 size_t radix_sort_scratch_bytes(uint64_t n);
 bool radix_set_part(int p);
 // sorts n pairs with its own scratch at ws; *in_tmp tells where the result is

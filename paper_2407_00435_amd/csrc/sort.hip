@@ -86,35 +86,21 @@ k_radix_hist(const uint32_t *__restrict__ keys, const uint64_t *__restrict__ d_c
     }
 }
 
-// exclusive prefix over the 256 digits of each pass (one block per pass)
-__global__ void __launch_bounds__(256) k_radix_prefix(uint32_t *__restrict__ hist)
-{
-    __shared__ uint32_t s[256];
-    uint32_t *h = hist + blockIdx.x * 256;
-    int t = threadIdx.x;
-    uint32_t v = h[t];
-    s[t] = v;
-    __syncthreads();
-    for (int off = 1; off < 256; off <<= 1) {
-        uint32_t add = t >= off ? s[t - off] : 0u;
-        __syncthreads();
-        s[t] += add;
-        __syncthreads();
-    }
-    h[t] = s[t] - v;
-}
-
+// Prepares one sort: zeroes the digit counts and the partition tickets of
+// every pass, and the lookback words of the first pass's partitions (the
+// key count read on the device).  Each pass clears the words of the next.
 __global__ void __launch_bounds__(256)
-k_radix_clear(uint64_t *__restrict__ status, uint32_t *__restrict__ ticket,
-              const uint64_t *__restrict__ d_count, uint64_t cap, int part)
+k_radix_init(uint32_t *__restrict__ hist, uint32_t *__restrict__ tickets, uint64_t *__restrict__ status,
+             const uint64_t *__restrict__ d_count, uint64_t cap, int part)
 {
     uint64_t count = *d_count;
     count = count < cap ? count : cap;
-    uint64_t words = ((count + part - 1) / part) * 256;
-    uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
-    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < words; i += stride)
-        status[i] = 0;
-    if (blockIdx.x == 0 && threadIdx.x == 0) *ticket = 0;
+    const uint64_t words = ((count + part - 1) / part) * 256;
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    const uint64_t i0 = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    for (uint64_t i = i0; i < words; i += stride) status[i] = 0;
+    for (uint64_t i = i0; i < 4 * 256; i += stride) hist[i] = 0;
+    if (i0 < 4) tickets[i0] = 0;
 }
 
 template <int THREADS, int ITEMS, typename VT>
@@ -122,8 +108,8 @@ __global__ void __launch_bounds__(THREADS)
 k_radix_onesweep(const uint32_t *__restrict__ kin, const VT *__restrict__ vin,
                  uint32_t *__restrict__ kout, VT *__restrict__ vout,
                  const uint64_t *__restrict__ d_count, uint64_t cap, int shift, uint32_t mask,
-                 int dbits, const uint32_t *__restrict__ gbase, uint64_t *__restrict__ status,
-                 uint32_t *__restrict__ ticket)
+                 int dbits, const uint32_t *__restrict__ dcount, uint64_t *__restrict__ status,
+                 uint64_t *__restrict__ status_next, uint32_t *__restrict__ ticket)
 {
     constexpr int WAVES = THREADS / 64;
     constexpr int PART = THREADS * ITEMS;
@@ -132,10 +118,29 @@ k_radix_onesweep(const uint32_t *__restrict__ kin, const VT *__restrict__ vin,
     __shared__ uint32_t s_whist[WAVES][256];
     __shared__ uint32_t s_bexcl[256];  // exclusive prefix over digits of the block counts
     __shared__ uint64_t s_dbase[256];  // global position of the digit's first key of this block
+    __shared__ uint32_t s_gbase[256];  // exclusive prefix of this pass's digit counts
+    __shared__ uint32_t s_wsum[4];
     __shared__ uint32_t s_part;
 
     const int t = threadIdx.x;
     const int wave = t >> 6, lane = t & 63;
+    // digit bases of the pass, once per workgroup (waves 0-3 take 64 digits each)
+    uint32_t dc = 0, dx = 0;
+    if (t < 256) {
+        dc = dcount[t];
+        dx = dc;
+        for (int off = 1; off < 64; off <<= 1) {
+            const uint32_t y = __shfl_up(dx, off);
+            if (lane >= off) dx += y;
+        }
+        if (lane == 63) s_wsum[wave] = dx;
+    }
+    __syncthreads();
+    if (t < 256) {
+        uint32_t add = 0;
+        for (int w = 0; w < wave; ++w) add += s_wsum[w];
+        s_gbase[t] = add + dx - dc;
+    }
     uint64_t count = *d_count;
     count = count < cap ? count : cap;
     const uint64_t nparts = (count + PART - 1) / PART;
@@ -146,6 +151,8 @@ k_radix_onesweep(const uint32_t *__restrict__ kin, const VT *__restrict__ vin,
         __syncthreads();
         const uint64_t part = s_part;
         if (part >= nparts) return;
+        // the next pass finds its partition's lookback words cleared
+        if (status_next && t < 256) status_next[part * 256 + t] = 0;
 
         const uint64_t pbase = part * PART;
         const uint64_t wbase = pbase + (uint64_t)wave * (ITEMS * 64);
@@ -227,7 +234,7 @@ k_radix_onesweep(const uint32_t *__restrict__ kin, const VT *__restrict__ vin,
         __syncthreads();
         if (dig) {
             s_bexcl[t] = bexcl;
-            s_dbase[t] = (uint64_t)gbase[t] + prefix;
+            s_dbase[t] = (uint64_t)s_gbase[t] + prefix;
         }
         __syncthreads();
         // scatter into LDS in digit order
@@ -279,6 +286,23 @@ int radix_digit_bits(int bits)
     return passes ? (bits + passes - 1) / passes : 0;
 }
 
+// partition size of a sort with values of vbytes bytes (the LDS holds keys
+// and values: 8-byte values take partitions of at most 8192 keys)
+static int part_for(int vbytes) { return vbytes > 4 && part_size() > 8192 ? 8192 : part_size(); }
+
+hipError_t radix_sort_prepare(const RadixScratch &rs, const uint64_t *d_count, uint64_t cap, int vbytes,
+                              hipStream_t st)
+{
+    const int P = part_for(vbytes);
+    const uint64_t words = ((cap + P - 1) / P) * 256;
+    if (words > rs.status_words) return hipErrorInvalidValue;
+    uint64_t blocks = (words + 255) / 256;
+    blocks = blocks < 1 ? 1 : (blocks > 1024 ? 1024 : blocks);
+    hipLaunchKernelGGL(k_radix_init, dim3((unsigned)blocks), dim3(256), 0, st, rs.hist, rs.tickets, rs.status,
+                       d_count, cap, P);
+    return hipGetLastError();
+}
+
 template <typename VT>
 static hipError_t sort_pairs_impl(uint32_t *ka, VT *va, uint32_t *kb, VT *vb,
                             const uint64_t *d_count, uint64_t cap, int bits,
@@ -290,11 +314,10 @@ static hipError_t sort_pairs_impl(uint32_t *ka, VT *va, uint32_t *kb, VT *vb,
     const int dbits = radix_digit_bits(bits);
     const uint32_t mask = (1u << dbits) - 1u;
     hipError_t e;
-    // 8-byte values: partitions of at most 8192 keys (the LDS holds keys and values)
-    const int P = sizeof(VT) > 4 && part_size() > 8192 ? 8192 : part_size();
+    const int P = part_for((int)sizeof(VT));
     const uint64_t parts = (cap + P - 1) / P;
     if (!hist_ready) {
-        if ((e = launch_fill_u32(rs.hist, 0u, 4 * 256, st)) != hipSuccess) return e;
+        if ((e = radix_sort_prepare(rs, d_count, cap, (int)sizeof(VT), st)) != hipSuccess) return e;
         // few large blocks: each adds its counts to the global histogram
         // with one atomic per digit, and same-address atomics from
         // thousands of blocks would serialise in L2
@@ -304,22 +327,21 @@ static hipError_t sort_pairs_impl(uint32_t *ka, VT *va, uint32_t *kb, VT *vb,
         hipLaunchKernelGGL(k_radix_hist, dim3(hist_blocks), dim3(1024), 0, st, ka, d_count, cap, passes,
                            dbits, rs.hist);
     }
-    hipLaunchKernelGGL(k_radix_prefix, dim3(passes), dim3(256), 0, st, rs.hist);
     uint32_t *src_k = ka, *dst_k = kb;
     VT *src_v = va, *dst_v = vb;
-    // the grid is sized for the capacity; a persistent grid of at most
-    // SWEEP_BLOCKS workgroups keeps the cost of an over-sized capacity
-    // (workgroups that start only to find no partition) bounded
+    // a persistent grid of at most SWEEP_BLOCKS workgroups keeps the cost
+    // of an over-sized capacity (workgroups that start only to find no
+    // partition) bounded
     const unsigned sweep_blocks = (unsigned)(parts < SWEEP_BLOCKS ? parts : SWEEP_BLOCKS);
-    int clear_blocks = (int)((parts * 256 + 255) / 256);
-    if (clear_blocks > 4096) clear_blocks = 4096;
     for (int p = 0; p < passes; ++p) {
-        hipLaunchKernelGGL(k_radix_clear, dim3(clear_blocks), dim3(256), 0, st, rs.status,
-                           rs.tickets + p, d_count, cap, P);
+        // lookback words alternate between two buffers; pass p clears the
+        // buffer of pass p + 1 as it goes
+        uint64_t *cur = rs.status + (p & 1) * rs.status_words;
+        uint64_t *next = p + 1 < passes ? rs.status + ((p + 1) & 1) * rs.status_words : nullptr;
 #define GS_OS(TH, IT)                                                                                \
     hipLaunchKernelGGL((k_radix_onesweep<TH, IT, VT>), dim3(sweep_blocks), dim3(TH), 0, st, src_k,     \
                        src_v, dst_k, dst_v, d_count, cap, dbits * p, mask, dbits,                  \
-                       rs.hist + 256 * p, rs.status, rs.tickets + p)
+                       rs.hist + 256 * p, cur, next, rs.tickets + p)
         if (P == 4096) {
             GS_OS(256, 16);
         } else if (P == 16384) {
@@ -358,8 +380,8 @@ bool radix_set_part(int p)
 
 size_t radix_sort_scratch_bytes(uint64_t n)
 {
-    // hist [4][256] u32 | tickets [4] u32 | count u64 | status [parts][256] u64
-    return 4 * 256 * 4 + 4 * 4 + 8 + 256 + 8 * 256 * radix_max_parts(n ? n : 1) + 256;
+    // hist [4][256] u32 | tickets [4] u32 | count u64 | status [2][parts][256] u64
+    return 4 * 256 * 4 + 4 * 4 + 8 + 256 + 2 * 8 * 256 * radix_max_parts(n ? n : 1) + 256;
 }
 
 hipError_t radix_sort_standalone(uint32_t *keys, uint32_t *vals, uint32_t *kt, uint32_t *vt, uint64_t n,
@@ -372,6 +394,7 @@ hipError_t radix_sort_standalone(uint32_t *keys, uint32_t *vals, uint32_t *kt, u
     uint64_t *count = (uint64_t *)(base + 4 * 256 * 4 + 4 * 4 + 8);  // 8-byte aligned
     rs.status = (uint64_t *)(base + 4 * 256 * 4 + 4 * 4 + 8 + 256);
     rs.status = (uint64_t *)(((uintptr_t)rs.status + 255) & ~uintptr_t(255));
+    rs.status_words = 256 * radix_max_parts(n ? n : 1);
     hipLaunchKernelGGL(k_set_count, dim3(1), dim3(1), 0, st, count, n);
     *in_tmp = radix_passes(bits) % 2 == 1;
     return radix_sort_pairs(keys, vals, kt, vt, count, n, bits, rs, st, false);
