@@ -21,7 +21,7 @@
 
 namespace {
 
-constexpr int SAT_LDS_TILES = 16384;      // views up to this many tiles build their tables in LDS (64 KB)
+constexpr int SAT_LDS_TILES = 16384;      // views up to this many tiles build their tables in LDS (80 KB)
 constexpr int ST = BIN_SUPER_TILE;        // super-tile side in tiles
 constexpr int TST = ST * ST;              // tiles per super-tile (<= wave size)
 constexpr int MS = 4;                     // coarse masks cover spans of up to MS x MS super-tiles
@@ -75,11 +75,12 @@ k_bin_setup(const gs_camera *__restrict__ cams, int V, int T, int64_t *__restric
 // Summed-area table of [lower level of tile <= m] over each view's tile grid,
 // one table per level m = 1..L: sat[(m-1) * n_tiles + g] counts the tiles
 // (x', y') <= (x, y) of g's view.  One workgroup per (view, level), built in
-// LDS (dynamic size) when the view's grid fits, else in place in memory:
-// row sums (a thread per row), then column sums (a thread per column).
+// LDS (dynamic size, with the tiles' lower levels staged beside it) when the
+// view's grid fits, else in place in memory: row sums (a wave per row), then
+// column sums (a wave per column).
 // Also the bounding box of those tiles, bbox[(v * L + m - 1) * 4 +
 // {x0, y0, x1, y1}] (x0 > x1 when there are none).
-__global__ void __launch_bounds__(256)
+__global__ void __launch_bounds__(1024)
 k_level_sat(const gs_camera *__restrict__ cams, int V, int T, int L, int64_t n_tiles,
             const uint8_t *__restrict__ tl, uint32_t *__restrict__ sat, int32_t *__restrict__ bbox, int use_lds)
 {
@@ -88,28 +89,48 @@ k_level_sat(const gs_camera *__restrict__ cams, int V, int T, int L, int64_t n_t
     const int v = blockIdx.x / L, m = blockIdx.x % L + 1;
     const int64_t toff = view_tile_off(cams, v, T);
     const int tx = div_up(cams[v].width, T), ty = div_up(cams[v].height, T);
+    const int nt = tx * ty;
     if (threadIdx.x == 0) {
         s_box[0] = tx;
         s_box[1] = ty;
         s_box[2] = -1;
         s_box[3] = -1;
     }
-    __syncthreads();
     uint32_t *g = sat + (int64_t)(m - 1) * n_tiles + toff;
     uint32_t *s = use_lds ? s_sat : g;
-    const uint8_t *lv = tl + 2 * toff;
+    const uint16_t *lv = reinterpret_cast<const uint16_t *>(tl + 2 * toff);  // {lower, upper} level per tile
+    // in LDS mode the lower levels are staged first, every load in flight at once
+    uint8_t *s_lv = reinterpret_cast<uint8_t *>(s_sat + nt);
+    if (use_lds) {
+        constexpr int U = 8;
+        for (int k0 = threadIdx.x; k0 < nt; k0 += U * blockDim.x) {
+            uint16_t r[U];
+#pragma unroll
+            for (int j = 0; j < U; ++j) {
+                const int k = k0 + j * blockDim.x;
+                r[j] = k < nt ? lv[k] : (uint16_t)0;
+            }
+#pragma unroll
+            for (int j = 0; j < U; ++j) {
+                const int k = k0 + j * blockDim.x;
+                if (k < nt) s_lv[k] = (uint8_t)(r[j] & 0xff);
+            }
+        }
+    }
+    __syncthreads();
     // row sums: a wave per row, 64 columns per step (ballot prefix counts)
-    const int lane = threadIdx.x & 63, waves = blockDim.x / 64;
-    for (int y = threadIdx.x >> 6; y < ty; y += waves) {
+    const int lane = threadIdx.x & 63, waves = blockDim.x / 64, wave = threadIdx.x >> 6;
+    for (int y = wave; y < ty; y += waves) {
         uint32_t run = 0;
         int xl = tx, xr = -1;
         for (int x0 = 0; x0 < tx; x0 += 64) {
             const int x = x0 + lane;
-            const bool kept = x < tx && lv[2 * ((int64_t)y * tx + x)] <= m;
+            const int k = y * tx + x;
+            const bool kept = x < tx && (use_lds ? (int)s_lv[k] : (int)(lv[k] & 0xff)) <= m;
             const uint64_t bal = __builtin_amdgcn_ballot_w64(kept);
             const uint32_t below = __builtin_amdgcn_mbcnt_hi((uint32_t)(bal >> 32),
                                                              __builtin_amdgcn_mbcnt_lo((uint32_t)bal, 0u));
-            if (x < tx) s[(int64_t)y * tx + x] = run + below + (kept ? 1u : 0u);
+            if (x < tx) s[k] = run + below + (kept ? 1u : 0u);
             run += (uint32_t)__popcll(bal);
             if (bal) {
                 xl = min(xl, x0 + __ffsll((unsigned long long)bal) - 1);
@@ -125,16 +146,23 @@ k_level_sat(const gs_camera *__restrict__ cams, int V, int T, int L, int64_t n_t
     }
     __syncthreads();
     if (threadIdx.x < 4) bbox[((int64_t)v * L + m - 1) * 4 + threadIdx.x] = s_box[threadIdx.x];
-    for (int x = threadIdx.x; x < tx; x += blockDim.x) {
+    // column sums: a wave per column, 64 rows per step (wave prefix sums)
+    for (int x = wave; x < tx; x += waves) {
         uint32_t run = 0;
-        for (int y = 0; y < ty; ++y) {
-            run += s[(int64_t)y * tx + x];
-            s[(int64_t)y * tx + x] = run;
+        for (int y0 = 0; y0 < ty; y0 += 64) {
+            const int y = y0 + lane;
+            uint32_t c = y < ty ? s[(int64_t)y * tx + x] : 0u;
+            for (int off = 1; off < 64; off <<= 1) {
+                const uint32_t u = __shfl_up(c, off);
+                if (lane >= off) c += u;
+            }
+            if (y < ty) s[(int64_t)y * tx + x] = run + c;
+            run += __shfl(c, 63);
         }
     }
     if (use_lds) {
         __syncthreads();
-        for (int64_t k = threadIdx.x; k < (int64_t)tx * ty; k += blockDim.x) g[k] = s[k];
+        for (int64_t k = threadIdx.x; k < nt; k += blockDim.x) g[k] = s[k];
     }
 }
 
@@ -1051,7 +1079,7 @@ hipError_t launch_bin_sort(const gs_splat *splats, int n, const gs_camera *cams_
     const int L = n_levels < 1 ? 1 : (n_levels > 4 ? 4 : n_levels);
     if (filt) {
         const int lds = max_view_tiles <= SAT_LDS_TILES;
-        hipLaunchKernelGGL(k_level_sat, dim3(V * L), dim3(256), lds ? 4 * max_view_tiles : 0, st, cams_dev,
+        hipLaunchKernelGGL(k_level_sat, dim3(V * L), dim3(1024), lds ? 5 * max_view_tiles + 16 : 0, st, cams_dev,
                            V, T, L, n_tiles, tile_level, bs.sat, bs.bbox, lds);
     }
     const uint32_t *sat = filt ? bs.sat : nullptr;

@@ -359,64 +359,77 @@ __device__ __forceinline__ void fov_walk_impl(const gs_splat *__restrict__ splat
                    reaches_rect(s0.x, s0.y, s0.z, s0.w, s1.x, 9.001f, w.rx0, w.rx1, w.ry0, w.ry1);
         }
         const uint64_t msk = ballot64(keep);
-        if (keep) srec[__popcll(msk & lanemask_lt())] = rec;
-        wave_lds_sync();
         const int cnt = __popcll(msk);
+        // the list is padded to a multiple of 4 with null records (opacity 0,
+        // level -1: no pixel uses them) so that the loop below runs in groups
+        // of 4 with one exit test per group
+        const int cnt4 = (cnt + 3) & ~3;
+        if (keep) srec[__popcll(msk & lanemask_lt())] = rec;
+        if (lane >= cnt && lane < cnt4) {
+            FovRec z;
+            z.a = z.lv[0] = z.lv[1] = make_float4(0.f, 0.f, 0.f, 0.f);
+            z.b = make_float4(0.f, 0.f, __int_as_float(-1), 0.f);
+            srec[lane] = z;
+        }
+        wave_lds_sync();
         if (STATS) {
             st[2] += (float)min(64u, e - c0);
             st[3] += (float)cnt;
         }
-        for (int j = 0; j < cnt; ++j) {
-            // branch-free: every lane evaluates, selects take the decisions
-            const float4 a = srec[j].a, bb = srec[j].b;
-            if (STATS) st[1] += (s.done_a && s.done_b) ? 0.0f : 1.0f;
-            const float p2 = pair_e2(a, make_float4(bb.x, 0.f, 0.f, 0.f), w.fpx, w.fpy);  // falloff only
-            const int m = __float_as_int(bb.z);
-            const float G = fast_exp2(p2);
-            const bool incl = p2 >= EXTENT_LOG2;
-            float4 lva, lvb;
-            if (!WIDE) {
-                // 0 or 1 inside the image; pixels outside (level 1, done) are clamped
-                lva = srec[j].lv[min(max(f.lo - f.wave_lo, 0), 1)];
-                lvb = srec[j].lv[1];
-            } else {
-                const float4 *lp = lvl + (vbase + __float_as_uint(bb.y)) * L;
-                lva = lp[f.lo - 1];
-                lvb = lp[f.lo < L ? f.lo : L - 1];
+        for (int j0 = 0; j0 < cnt4; j0 += 4) {
+#pragma unroll
+            for (int j = j0; j < j0 + 4; ++j) {
+                // branch-free: every lane evaluates, selects take the decisions
+                const float4 a = srec[j].a, bb = srec[j].b;
+                if (STATS) st[1] += (j >= cnt || (s.done_a && s.done_b)) ? 0.0f : 1.0f;
+                const float p2 = pair_e2(a, make_float4(bb.x, 0.f, 0.f, 0.f), w.fpx, w.fpy);  // falloff only
+                const int m = __float_as_int(bb.z);
+                const float G = fast_exp2(p2);
+                const bool incl = p2 >= EXTENT_LOG2;
+                float4 lva, lvb;
+                if (!WIDE) {
+                    // 0 or 1 inside the image; pixels outside (level 1, done) are clamped
+                    lva = srec[j].lv[min(max(f.lo - f.wave_lo, 0), 1)];
+                    lvb = srec[j].lv[1];
+                } else {
+                    const float4 *lp = lvl + (vbase + __float_as_uint(bb.y)) * L;
+                    lva = lp[f.lo - 1];
+                    lvb = lp[f.lo < L ? f.lo : L - 1];
+                }
+                {
+                    const float4 lv = lva;
+                    const float alpha = fminf(GS_ALPHA_MAX, lv.w * G);
+                    const bool use = incl && !s.done_a && m >= f.lo && alpha >= GS_ALPHA_MIN;
+                    const float Tn = fmaf(-alpha, s.Ta, s.Ta);
+                    const bool stop = use && Tn < GS_T_STOP;
+                    const bool blend = use && !stop;
+                    const float wt = blend ? alpha * s.Ta : 0.0f;
+                    s.A0 = fmaf(wt, lv.x, s.A0);
+                    s.A1 = fmaf(wt, lv.y, s.A1);
+                    s.A2 = fmaf(wt, lv.z, s.A2);
+                    s.Ta = blend ? Tn : s.Ta;
+                    if (KEEP) s.last_a = blend ? __float_as_uint(bb.w) : s.last_a;
+                    s.done_a = s.done_a || stop;
+                    if (STATS) st[0] += blend ? 1.0f : 0.0f;
+                }
+                if (f.any_two) {
+                    const float4 lv = lvb;
+                    const float alpha = fminf(GS_ALPHA_MAX, lv.w * G);
+                    const bool use = incl && !s.done_b && m >= f.lo + 1 && alpha >= GS_ALPHA_MIN;
+                    const float Tn = fmaf(-alpha, s.Tb, s.Tb);
+                    const bool stop = use && Tn < GS_T_STOP;
+                    const bool blend = use && !stop;
+                    const float wt = blend ? alpha * s.Tb : 0.0f;
+                    s.B0 = fmaf(wt, lv.x, s.B0);
+                    s.B1 = fmaf(wt, lv.y, s.B1);
+                    s.B2 = fmaf(wt, lv.z, s.B2);
+                    s.Tb = blend ? Tn : s.Tb;
+                    if (KEEP) s.last_b = blend ? __float_as_uint(bb.w) : s.last_b;
+                    s.done_b = s.done_b || stop;
+                    if (STATS) st[0] += blend ? 1.0f : 0.0f;
+                }
             }
-            {
-                const float4 lv = lva;
-                const float alpha = fminf(GS_ALPHA_MAX, lv.w * G);
-                const bool use = incl && !s.done_a && m >= f.lo && alpha >= GS_ALPHA_MIN;
-                const float Tn = fmaf(-alpha, s.Ta, s.Ta);
-                const bool stop = use && Tn < GS_T_STOP;
-                const bool blend = use && !stop;
-                const float wt = blend ? alpha * s.Ta : 0.0f;
-                s.A0 = fmaf(wt, lv.x, s.A0);
-                s.A1 = fmaf(wt, lv.y, s.A1);
-                s.A2 = fmaf(wt, lv.z, s.A2);
-                s.Ta = blend ? Tn : s.Ta;
-                if (KEEP) s.last_a = blend ? __float_as_uint(bb.w) : s.last_a;
-                s.done_a = s.done_a || stop;
-                if (STATS) st[0] += blend ? 1.0f : 0.0f;
-            }
-            if (f.any_two) {
-                const float4 lv = lvb;
-                const float alpha = fminf(GS_ALPHA_MAX, lv.w * G);
-                const bool use = incl && !s.done_b && m >= f.lo + 1 && alpha >= GS_ALPHA_MIN;
-                const float Tn = fmaf(-alpha, s.Tb, s.Tb);
-                const bool stop = use && Tn < GS_T_STOP;
-                const bool blend = use && !stop;
-                const float wt = blend ? alpha * s.Tb : 0.0f;
-                s.B0 = fmaf(wt, lv.x, s.B0);
-                s.B1 = fmaf(wt, lv.y, s.B1);
-                s.B2 = fmaf(wt, lv.z, s.B2);
-                s.Tb = blend ? Tn : s.Tb;
-                if (KEEP) s.last_b = blend ? __float_as_uint(bb.w) : s.last_b;
-                s.done_b = s.done_b || stop;
-                if (STATS) st[0] += blend ? 1.0f : 0.0f;
-            }
-            if ((j & 7) == 7 && ballot64(!(s.done_a && s.done_b)) == 0) break;
+            if (ballot64(!(s.done_a && s.done_b)) == 0) break;
         }
         wave_lds_sync();
     }
@@ -1218,32 +1231,23 @@ struct FovArgs {
     gs_fovea f[8];
 };
 
-// Block rows walk the image rows (rows of all views stacked), 256 pixels of
-// a row per block: no per-pixel index division, per-view constants once.
-__device__ __forceinline__ void fovea_pixel(const gs_camera *__restrict__ cams, int V, int L, const FovArgs &fa,
-                                            int grow, int x, uint8_t *__restrict__ pix_level,
-                                            float *__restrict__ pix_weight)
+// Level and blend weight of pixel (x, y) of a view: the eccentricity is the
+// angle between the pixel's ray and the gaze ray (through the gaze pixel);
+// the level is the first ring the pixel lies inside, and within a ring's
+// blend band the weight of the next level rises linearly from 0 to 1.
+__device__ __forceinline__ void fovea_level(const gs_camera &c, const gs_fovea &f, int L, int x, int y, int &lo,
+                                            float &w)
 {
-    int row = grow, v = 0;
-    int64_t poff = 0;
-    while (v + 1 < V && row >= cams[v].height) {
-        row -= cams[v].height;
-        poff += (int64_t)cams[v].width * cams[v].height;
-        ++v;
-    }
-    const gs_camera &c = cams[v];
-    if (x >= c.width || row >= c.height) return;
-    const gs_fovea f = fa.f[v];
     const float ifx = 1.0f / c.fx, ify = 1.0f / c.fy;
-    const float rx = ((float)x - c.cx) * ifx, ry = ((float)row - c.cy) * ify;
+    const float rx = ((float)x - c.cx) * ifx, ry = ((float)y - c.cy) * ify;
     const float gx = (f.gaze_x - c.cx) * ifx, gy = (f.gaze_y - c.cy) * ify;
     // angle between (rx, ry, 1) and (gx, gy, 1)
     const float cx_ = ry - gy, cy_ = gx - rx, cz_ = rx * gy - ry * gx;
     const float cn = sqrtf(cx_ * cx_ + cy_ * cy_ + cz_ * cz_);
     const float dt = rx * gx + ry * gy + 1.0f;
     const float ecc = atan2f(cn, dt) * 57.29577951308232f;
-    int lo = 1;
-    float w = 0.0f;
+    lo = 1;
+    w = 0.0f;
     const float hb = 0.5f * f.band_deg;
     for (int j = 0; j < L - 1; ++j) {
         const float e0 = f.ring_deg[j] - hb, e1 = f.ring_deg[j] + hb;
@@ -1255,46 +1259,49 @@ __device__ __forceinline__ void fovea_pixel(const gs_camera *__restrict__ cams, 
         }
         lo = j + 2;
     }
-    const int64_t p = poff + (int64_t)row * c.width + x;
-    pix_level[p] = (uint8_t)lo;
-    pix_weight[p] = w;
 }
 
-__global__ void __launch_bounds__(256)
-k_fovea_pix(const gs_camera *__restrict__ cams, int V, int L, int rows, FovArgs fa, uint8_t *__restrict__ pix_level,
-            float *__restrict__ pix_weight)
+// One workgroup per tile, a thread per pixel: the pixel's level and weight,
+// and the tile's lowest level and highest level with non-zero weight
+// (tile_level[2 g], tile_level[2 g + 1]).
+template <int T>
+__global__ void __launch_bounds__(T * T)
+k_fovea_prep(const gs_camera *__restrict__ cams, int V, int L, FovArgs fa, uint8_t *__restrict__ pix_level,
+             float *__restrict__ pix_weight, uint8_t *__restrict__ tile_level)
 {
-    const int x = blockIdx.x * blockDim.x + threadIdx.x;
-    for (int r = blockIdx.y; r < rows; r += gridDim.y) fovea_pixel(cams, V, L, fa, r, x, pix_level, pix_weight);
-}
-
-// one wave per tile: lowest and highest level with non-zero weight
-__global__ void __launch_bounds__(256)
-k_fovea_tile(const gs_camera *__restrict__ cams, int V, int T, int64_t n_tiles,
-             const uint8_t *__restrict__ pix_level, const float *__restrict__ pix_weight,
-             uint8_t *__restrict__ tile_level)
-{
-    int64_t gt = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
-    int lane = threadIdx.x & 63;
-    if (gt >= n_tiles) return;
+    constexpr int WAVES = (T * T + 63) / 64;
+    __shared__ int s_lo[WAVES], s_hi[WAVES];
+    const int64_t gt = blockIdx.x;
     const ViewInfo vi = view_of_tile(cams, V, T, gt);
-    int64_t lt = gt - vi.tile_off;
-    int tx = (int)(lt % vi.tiles_x), ty = (int)(lt / vi.tiles_x);
+    const int64_t lt = gt - vi.tile_off;
+    const int tx = (int)(lt % vi.tiles_x), ty = (int)(lt / vi.tiles_x);
+    const int x = tx * T + (int)(threadIdx.x % T), y = ty * T + (int)(threadIdx.x / T);
     int lo = 255, hi = 0;
-    for (int k = lane; k < T * T; k += 64) {
-        int x = tx * T + (k % T), y = ty * T + (k / T);
-        if (x < vi.W && y < vi.H) {
-            int64_t p = vi.pix_off + (int64_t)y * vi.W + x;
-            int l = pix_level[p];
-            lo = min(lo, l);
-            hi = max(hi, l + (pix_weight[p] > 0.0f ? 1 : 0));
-        }
+    if (x < vi.W && y < vi.H) {
+        int l;
+        float w;
+        fovea_level(cams[vi.v], fa.f[vi.v], L, x, y, l, w);
+        const int64_t p = vi.pix_off + (int64_t)y * vi.W + x;
+        pix_level[p] = (uint8_t)l;
+        pix_weight[p] = w;
+        lo = l;
+        hi = l + (w > 0.0f ? 1 : 0);
     }
     for (int off = 32; off > 0; off >>= 1) {
         lo = min(lo, __shfl_xor(lo, off));
         hi = max(hi, __shfl_xor(hi, off));
     }
-    if (lane == 0) {
+    const int wave = threadIdx.x >> 6;
+    if ((threadIdx.x & 63) == 0) {
+        s_lo[wave] = lo;
+        s_hi[wave] = hi;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int q = 1; q < WAVES; ++q) {
+            lo = min(lo, s_lo[q]);
+            hi = max(hi, s_hi[q]);
+        }
         tile_level[2 * gt] = (uint8_t)lo;
         tile_level[2 * gt + 1] = (uint8_t)hi;
     }
@@ -1457,22 +1464,20 @@ hipError_t launch_fovea_prep(const gs_camera *cams_host, const gs_camera *cams_d
                              int n_eyes, int T, int n_levels, int64_t n_pixels, int64_t n_tiles,
                              uint8_t *pix_level, float *pix_weight, uint8_t *tile_level, hipStream_t st)
 {
+    (void)cams_host;
+    (void)n_pixels;
+    if (n_tiles == 0) return hipSuccess;
     FovArgs fa;
     for (int i = 0; i < 8; ++i) fa.f[i] = fov_host[i < n_eyes ? i : 0];
-    int max_w = 0, rows = 0;
-    for (int v = 0; v < n_eyes; ++v) {
-        max_w = cams_host[v].width > max_w ? cams_host[v].width : max_w;
-        rows += cams_host[v].height;
+#define GS_FP(TS)                                                                                      \
+    hipLaunchKernelGGL((k_fovea_prep<TS>), dim3((unsigned)n_tiles), dim3(TS * TS), 0, st, cams_dev, n_eyes,  \
+                       n_levels, fa, pix_level, pix_weight, tile_level)
+    switch (T) {
+    case 8: GS_FP(8); break;
+    case 16: GS_FP(16); break;
+    default: GS_FP(32); break;
     }
-    (void)n_pixels;
-    if (rows > 0 && max_w > 0) {
-        // about eight rows per block: a block's setup is longer than one row's work
-        const int gy = (rows + 7) / 8 < 65535 ? (rows + 7) / 8 : 65535;
-        hipLaunchKernelGGL(k_fovea_pix, dim3((unsigned)((max_w + 255) / 256), (unsigned)gy), dim3(256), 0, st,
-                           cams_dev, n_eyes, n_levels, rows, fa, pix_level, pix_weight);
-    }
-    hipLaunchKernelGGL(k_fovea_tile, dim3((unsigned)((n_tiles + 3) / 4)), dim3(256), 0, st, cams_dev,
-                       n_eyes, T, n_tiles, pix_level, pix_weight, tile_level);
+#undef GS_FP
     return hipGetLastError();
 }
 
