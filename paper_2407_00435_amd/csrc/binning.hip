@@ -35,6 +35,32 @@ k_fill_u32(uint32_t *__restrict__ p, uint32_t value, uint64_t count)
         p[i] = value;
 }
 
+// Inclusive prefix sum over the 64 lanes of a wave: shifts by 1, 2, 4 and 8
+// inside each 16-lane row, then lane 15 of rows 0 and 2 into rows 1 and 3,
+// then lane 31 into rows 2 and 3 -- six DPP adds, no round trip through LDS.
+__device__ __forceinline__ uint32_t wave_incl_scan(uint32_t x)
+{
+    x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x111, 0xF, 0xF, false);  // row_shr:1
+    x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x112, 0xF, 0xF, false);  // row_shr:2
+    x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x114, 0xF, 0xF, false);  // row_shr:4
+    x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x118, 0xF, 0xF, false);  // row_shr:8
+    x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x142, 0xA, 0xF, false);  // row_bcast:15
+    x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x143, 0xC, 0xF, false);  // row_bcast:31
+    return x;
+}
+
+// Bitwise OR over the 64 lanes of a wave, in every lane: DPP ORs inside each
+// 16-lane row (complete in lane 15 of the row), then the four row results.
+__device__ __forceinline__ uint32_t wave_or(uint32_t x)
+{
+    x |= (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x111, 0xF, 0xF, false);  // row_shr:1
+    x |= (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x112, 0xF, 0xF, false);  // row_shr:2
+    x |= (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x114, 0xF, 0xF, false);  // row_shr:4
+    x |= (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x118, 0xF, 0xF, false);  // row_shr:8
+    return (uint32_t)(__builtin_amdgcn_readlane((int)x, 15) | __builtin_amdgcn_readlane((int)x, 31) |
+                      __builtin_amdgcn_readlane((int)x, 47) | __builtin_amdgcn_readlane((int)x, 63));
+}
+
 __device__ __forceinline__ int64_t view_tile_off(const gs_camera *__restrict__ cams, int v, int T)
 {
     int64_t toff = 0;
@@ -151,11 +177,7 @@ k_level_sat(const gs_camera *__restrict__ cams, int V, int T, int L, int64_t n_t
         uint32_t run = 0;
         for (int y0 = 0; y0 < ty; y0 += 64) {
             const int y = y0 + lane;
-            uint32_t c = y < ty ? s[(int64_t)y * tx + x] : 0u;
-            for (int off = 1; off < 64; off <<= 1) {
-                const uint32_t u = __shfl_up(c, off);
-                if (lane >= off) c += u;
-            }
+            const uint32_t c = wave_incl_scan(y < ty ? s[(int64_t)y * tx + x] : 0u);
             if (y < ty) s[(int64_t)y * tx + x] = run + c;
             run += __shfl(c, 63);
         }
@@ -597,11 +619,7 @@ k_coarse_emit(const uint4 *__restrict__ rec_s, const uint32_t *__restrict__ cc_s
     }
 #pragma unroll
     for (int j = 0; j < GATHER_ITEMS; ++j) {
-        x[j] = cc_count(c[j]);
-        for (int off = 1; off < 64; off <<= 1) {
-            const uint32_t y = __shfl_up(x[j], off);
-            if (lane >= off) x[j] += y;
-        }
+        x[j] = wave_incl_scan(cc_count(c[j]));
         if (lane == 63) s_w[j][wave] = x[j];
     }
     __syncthreads();
@@ -808,13 +826,7 @@ k_tile_pass(const uint2 *__restrict__ cp, const uint4 *__restrict__ chunk, const
             mhi[q] = (uint32_t)(tm >> 32);
             uni |= tm;
         }
-        uint32_t ulo = (uint32_t)uni, uhi = (uint32_t)(uni >> 32);
-        for (int off = 32; off > 0; off >>= 1) {
-            ulo |= (uint32_t)__shfl_xor((int)ulo, off);
-            uhi |= (uint32_t)__shfl_xor((int)uhi, off);
-        }
-        ulo = (uint32_t)__builtin_amdgcn_readfirstlane((int)ulo);
-        uhi = (uint32_t)__builtin_amdgcn_readfirstlane((int)uhi);
+        const uint32_t ulo = wave_or((uint32_t)uni), uhi = wave_or((uint32_t)(uni >> 32));
         const uint32_t nq = (e_end - b + 63u) / 64u;
         const uint32_t vbase = (uint32_t)v * (uint32_t)n;
         wave_lds_sync();
@@ -956,46 +968,48 @@ k_tile_ranges(const uint32_t *__restrict__ tot, int64_t n_tiles, const uint64_t 
 }
 
 // 4d in one workgroup (grids of up to TILE_SCAN1_MAX tiles): tile ranges
-// from the totals, SCAN_ITEMS consecutive tiles per thread, segment after
-// segment with a running carry; an empty tile gets (0, 0).
+// from the totals.  Segment after segment (with a running carry), wave w
+// takes 1024 consecutive tiles as SCAN_ITEMS rows of 64, lane l of row j
+// holding tile 64 j + l (coalesced loads and stores); the rows are scanned
+// in order by wave prefix sums.  An empty tile gets (0, 0).
 constexpr int TS1_THREADS = 1024;
 constexpr int64_t TILE_SCAN1_MAX = 4 * TS1_THREADS * SCAN_ITEMS;
 __global__ void __launch_bounds__(TS1_THREADS)
 k_tile_scan1(const uint32_t *__restrict__ tot, int64_t n_tiles, const uint64_t *__restrict__ counts,
              uint32_t *__restrict__ ranges)
 {
-    __shared__ uint64_t s_w[TS1_THREADS / 64];
+    constexpr int WAVES = TS1_THREADS / 64;
+    __shared__ uint64_t s_w[WAVES];
     if (counts[1] == 0) return;  // ranges stay zero
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     uint64_t carry = 0;
     for (int64_t seg = 0; seg < n_tiles; seg += TS1_THREADS * SCAN_ITEMS) {
-        const int64_t g0 = seg + (int64_t)threadIdx.x * SCAN_ITEMS;
+        const int64_t g0 = seg + (int64_t)wave * (64 * SCAN_ITEMS) + lane;
         uint32_t t[SCAN_ITEMS];
-        uint64_t local = 0;
+        uint32_t local = 0;
 #pragma unroll
         for (int j = 0; j < SCAN_ITEMS; ++j) {
-            t[j] = g0 + j < n_tiles ? tot[g0 + j] : 0u;
+            t[j] = g0 + 64 * j < n_tiles ? tot[g0 + 64 * j] : 0u;
             local += t[j];
         }
-        uint64_t x = local;
-        for (int off = 1; off < 64; off <<= 1) {
-            const uint64_t y = __shfl_up(x, off);
-            if (lane >= off) x += y;
-        }
-        if (lane == 63) s_w[wave] = x;
+        uint64_t wt = local;
+        for (int off = 32; off > 0; off >>= 1) wt += __shfl_xor(wt, off);
+        if (lane == 0) s_w[wave] = wt;
         __syncthreads();
-        uint64_t run = carry + x - local, segtot = 0;
-        for (int w = 0; w < TS1_THREADS / 64; ++w) {
+        uint64_t run = carry, segtot = 0;
+        for (int w = 0; w < WAVES; ++w) {
             const uint64_t sw = s_w[w];
             run += w < wave ? sw : 0;
             segtot += sw;
         }
 #pragma unroll
         for (int j = 0; j < SCAN_ITEMS; ++j) {
-            if (g0 + j < n_tiles)
-                reinterpret_cast<uint2 *>(ranges)[g0 + j] =
-                    t[j] ? make_uint2((uint32_t)run, (uint32_t)(run + t[j])) : make_uint2(0u, 0u);
-            run += t[j];
+            const uint32_t x = wave_incl_scan(t[j]);
+            const uint64_t b0 = run + x - t[j];
+            if (g0 + 64 * j < n_tiles)
+                reinterpret_cast<uint2 *>(ranges)[g0 + 64 * j] =
+                    t[j] ? make_uint2((uint32_t)b0, (uint32_t)(b0 + t[j])) : make_uint2(0u, 0u);
+            run += __shfl(x, 63);
         }
         carry += segtot;
         __syncthreads();  // s_w is rewritten by the next segment

@@ -194,36 +194,48 @@ __device__ __forceinline__ void fwd_walk(const gs_splat *__restrict__ vsp, const
             keep = reaches_rect(s0.x, s0.y, s0.z, s0.w, s1.x, qmax_of(s1.y), w.rx0, w.rx1, w.ry0, w.ry1);
         }
         const uint64_t m = ballot64(keep);
-        if (keep) srec[__popcll(m & lanemask_lt())] = rec;
-        wave_lds_sync();
         const int cnt = __popcll(m);
+        // padded to a multiple of 4 with null records (an infinite alpha
+        // threshold: no pixel uses them): the loop runs in groups of 4 with
+        // one exit test per group
+        const int cnt4 = (cnt + 3) & ~3;
+        if (keep) srec[__popcll(m & lanemask_lt())] = rec;
+        if (lane >= cnt && lane < cnt4) {
+            FwdRec z = zero_rec();
+            z.b.z = __builtin_inff();
+            srec[lane] = z;
+        }
+        wave_lds_sync();
         if (STATS) {
             st[2] += (float)min(64u, e - c0);
             st[3] += (float)cnt;
         }
-        for (int j = 0; j < cnt; ++j) {
-            // branch-free: every lane evaluates, selects take the decisions
-            const float4 a = srec[j].a, bb = srec[j].b, c = srec[j].c;
-            if (STATS) st[1] += s.done ? 0.0f : 1.0f;
-            const float e2 = pair_e2(a, bb, w.fpx, w.fpy);
-            const float alpha = fminf(GS_ALPHA_MAX, fast_exp2(e2));
-            const bool use = !s.done && e2 >= bb.z;
-            const float Tn = fmaf(-alpha, s.Tr, s.Tr);
-            const bool stop = use && Tn < GS_T_STOP;
-            const bool blend = use && !stop;
-            const float wt = blend ? alpha * s.Tr : 0.0f;
-            s.C0 = fmaf(wt, c.x, s.C0);
-            s.C1 = fmaf(wt, c.y, s.C1);
-            s.C2 = fmaf(wt, c.z, s.C2);
-            s.Tr = blend ? Tn : s.Tr;
-            s.last = blend ? __float_as_uint(bb.w) : s.last;
-            s.done = s.done || stop;
-            if (STATS) st[0] += blend ? 1.0f : 0.0f;
-            if (DOM && blend && wt > s.best) {
-                s.best = wt;
-                s.best_id = (int)__float_as_uint(c.w);
+        for (int j0 = 0; j0 < cnt4; j0 += 4) {
+#pragma unroll
+            for (int j = j0; j < j0 + 4; ++j) {
+                // branch-free: every lane evaluates, selects take the decisions
+                const float4 a = srec[j].a, bb = srec[j].b, c = srec[j].c;
+                if (STATS) st[1] += (j >= cnt || s.done) ? 0.0f : 1.0f;
+                const float e2 = pair_e2(a, bb, w.fpx, w.fpy);
+                const float alpha = fminf(GS_ALPHA_MAX, fast_exp2(e2));
+                const bool use = !s.done && e2 >= bb.z;
+                const float Tn = fmaf(-alpha, s.Tr, s.Tr);
+                const bool stop = use && Tn < GS_T_STOP;
+                const bool blend = use && !stop;
+                const float wt = blend ? alpha * s.Tr : 0.0f;
+                s.C0 = fmaf(wt, c.x, s.C0);
+                s.C1 = fmaf(wt, c.y, s.C1);
+                s.C2 = fmaf(wt, c.z, s.C2);
+                s.Tr = blend ? Tn : s.Tr;
+                s.last = blend ? __float_as_uint(bb.w) : s.last;
+                s.done = s.done || stop;
+                if (STATS) st[0] += blend ? 1.0f : 0.0f;
+                if (DOM && blend && wt > s.best) {
+                    s.best = wt;
+                    s.best_id = (int)__float_as_uint(c.w);
+                }
             }
-            if ((j & 7) == 7 && ballot64(!s.done) == 0) break;
+            if (ballot64(!s.done) == 0) break;
         }
         wave_lds_sync();
     }
@@ -912,45 +924,57 @@ k_raster_bwd(const gs_splat *__restrict__ splats, int n, const gs_camera *__rest
                 keep = reaches_rect(s0.x, s0.y, s0.z, s0.w, s1.x, qmax_of(s1.y), rx0, rx1, ry0, ry1);
             }
             const uint64_t msk = ballot64(keep);
-            if (keep) s_rec[wave][__popcll(msk & lanemask_lt())] = rec;
-            wave_lds_sync();
             const int cnt = __popcll(msk);
-            for (int j = cnt - 1; j >= 0; --j) {
-                const float4 a = s_rec[wave][j].a, b = s_rec[wave][j].b;
-                const uint32_t ppos = __float_as_uint(b.w);
-                // per pixel only w = alpha dL/dalpha and its moments in
-                // (dx, dy); the conic, mean and opacity gradients are linear
-                // in their sums (applied once per splat at the flush).
-                // Branch-free: every lane evaluates, selects take the
-                // decisions of the forward pass.
-                const float e2 = pair_e2(a, b, fpx, fpy);
-                const bool contrib = ppos <= nc && e2 >= b.z;
-                const float4 c = s_rec[wave][j].c;
-                const float araw = fast_exp2(e2);
-                const float alpha = fminf(GS_ALPHA_MAX, araw);
-                const float ioma = __builtin_amdgcn_rcpf(1.0f - alpha);
-                const float Tn = Tr * ioma;
-                const float wT = contrib ? alpha * Tn : 0.f;
-                const float dLda = g0 * fmaf(c.x, Tn, -B0 * ioma) + g1 * fmaf(c.y, Tn, -B1 * ioma) +
-                                   g2 * fmaf(c.z, Tn, -B2 * ioma);
-                const float gr = g0 * wT, gg = g1 * wT, gb = g2 * wT;
-                B0 = fmaf(c.x, wT, B0);
-                B1 = fmaf(c.y, wT, B1);
-                B2 = fmaf(c.z, wT, B2);
-                Tr = contrib ? Tn : Tr;
-                const float w = (contrib && araw <= GS_ALPHA_MAX) ? alpha * dLda : 0.f;
-                const float dx = fpx - a.x, dy = fpy - a.y;
-                const float wdx = w * dx, wdy = w * dy;
-                const float wdx2 = wdx * dx, wdxdy = wdx * dy, wdy2 = wdy * dy;
-                if (__builtin_amdgcn_ballot_w64(contrib) != 0) {
-                    // eight quantities by a reduce-scatter over each row (one
-                    // LDS atomic per quantity and row), the ninth by a row sum
-                    const float v8[8] = {w, wdx, wdy, wdx2, wdxdy, wdy2, gr, gg};
-                    const float part = row_scatter_sum8(v8, lane);
-                    const float pb = row_sum16(gb);
-                    const int q = (int)(ppos - (uint32_t)p0);
-                    if ((lane & 8) == 0) atomicAdd(&s_grad[scatter_q(lane)][q], part);
-                    if ((lane & 15) == 15) atomicAdd(&s_grad[8][q], pb);
+            // padded to a multiple of 4 with null records (an infinite alpha
+            // threshold: no pixel takes them), walked back to front in groups of 4
+            const int cnt4 = (cnt + 3) & ~3;
+            if (keep) s_rec[wave][__popcll(msk & lanemask_lt())] = rec;
+            if (lane >= cnt && lane < cnt4) {
+                BwdRec z;
+                z.a = z.b = z.c = make_float4(0.f, 0.f, 0.f, 0.f);
+                z.b.z = __builtin_inff();
+                s_rec[wave][lane] = z;
+            }
+            wave_lds_sync();
+            for (int j0 = cnt4 - 4; j0 >= 0; j0 -= 4) {
+#pragma unroll
+                for (int j = j0 + 3; j >= j0; --j) {
+                    const float4 a = s_rec[wave][j].a, b = s_rec[wave][j].b;
+                    const uint32_t ppos = __float_as_uint(b.w);
+                    // per pixel only w = alpha dL/dalpha and its moments in
+                    // (dx, dy); the conic, mean and opacity gradients are linear
+                    // in their sums (applied once per splat at the flush).
+                    // Branch-free: every lane evaluates, selects take the
+                    // decisions of the forward pass.
+                    const float e2 = pair_e2(a, b, fpx, fpy);
+                    const bool contrib = ppos <= nc && e2 >= b.z;
+                    const float4 c = s_rec[wave][j].c;
+                    const float araw = fast_exp2(e2);
+                    const float alpha = fminf(GS_ALPHA_MAX, araw);
+                    const float ioma = __builtin_amdgcn_rcpf(1.0f - alpha);
+                    const float Tn = Tr * ioma;
+                    const float wT = contrib ? alpha * Tn : 0.f;
+                    const float dLda = g0 * fmaf(c.x, Tn, -B0 * ioma) + g1 * fmaf(c.y, Tn, -B1 * ioma) +
+                                       g2 * fmaf(c.z, Tn, -B2 * ioma);
+                    const float gr = g0 * wT, gg = g1 * wT, gb = g2 * wT;
+                    B0 = fmaf(c.x, wT, B0);
+                    B1 = fmaf(c.y, wT, B1);
+                    B2 = fmaf(c.z, wT, B2);
+                    Tr = contrib ? Tn : Tr;
+                    const float w = (contrib && araw <= GS_ALPHA_MAX) ? alpha * dLda : 0.f;
+                    const float dx = fpx - a.x, dy = fpy - a.y;
+                    const float wdx = w * dx, wdy = w * dy;
+                    const float wdx2 = wdx * dx, wdxdy = wdx * dy, wdy2 = wdy * dy;
+                    if (__builtin_amdgcn_ballot_w64(contrib) != 0) {
+                        // eight quantities by a reduce-scatter over each row (one
+                        // LDS atomic per quantity and row), the ninth by a row sum
+                        const float v8[8] = {w, wdx, wdy, wdx2, wdxdy, wdy2, gr, gg};
+                        const float part = row_scatter_sum8(v8, lane);
+                        const float pb = row_sum16(gb);
+                        const int q = (int)(ppos - (uint32_t)p0);
+                        if ((lane & 8) == 0) atomicAdd(&s_grad[scatter_q(lane)][q], part);
+                        if ((lane & 15) == 15) atomicAdd(&s_grad[8][q], pb);
+                    }
                 }
             }
         }
