@@ -362,13 +362,21 @@ __device__ __forceinline__ void fov_walk_impl(const gs_splat *__restrict__ splat
             rec.a = make_float4(s0.x, s0.y, NEG_HALF_LOG2E * s0.z, -GS_LOG2E * s0.w);
             rec.b = make_float4(NEG_HALF_LOG2E * s1.x, __uint_as_float(id), __int_as_float(m),
                                 __uint_as_float(idx - w.start + 1));
+            float qcull = 9.001f;
             if (!WIDE) {
                 const float4 *lp = lvl + (vbase + id) * L;
                 rec.lv[0] = lp[min(max(f.wave_lo - 1, 0), L - 1)];
                 rec.lv[1] = lp[min(f.wave_lo, L - 1)];
+                // level wave_lo + 1 above the splat's quality bound: zero
+                // opacity, which no alpha test passes (so the loop needs no
+                // level test)
+                if (m < f.wave_lo + 1) rec.lv[1].w = 0.0f;
+                // no pixel of the wave blends the splat where opacity * G
+                // stays below the alpha floor
+                qcull = qmax_of(fmaxf(rec.lv[0].w, rec.lv[1].w));
             }
             keep = m >= f.wave_lo &&
-                   reaches_rect(s0.x, s0.y, s0.z, s0.w, s1.x, 9.001f, w.rx0, w.rx1, w.ry0, w.ry1);
+                   reaches_rect(s0.x, s0.y, s0.z, s0.w, s1.x, qcull, w.rx0, w.rx1, w.ry0, w.ry1);
         }
         const uint64_t msk = ballot64(keep);
         const int cnt = __popcll(msk);
@@ -411,7 +419,7 @@ __device__ __forceinline__ void fov_walk_impl(const gs_splat *__restrict__ splat
                 {
                     const float4 lv = lva;
                     const float alpha = fminf(GS_ALPHA_MAX, lv.w * G);
-                    const bool use = incl && !s.done_a && m >= f.lo && alpha >= GS_ALPHA_MIN;
+                    const bool use = incl && !s.done_a && (!WIDE || m >= f.lo) && alpha >= GS_ALPHA_MIN;
                     const float Tn = fmaf(-alpha, s.Ta, s.Ta);
                     const bool stop = use && Tn < GS_T_STOP;
                     const bool blend = use && !stop;
@@ -427,7 +435,7 @@ __device__ __forceinline__ void fov_walk_impl(const gs_splat *__restrict__ splat
                 if (f.any_two) {
                     const float4 lv = lvb;
                     const float alpha = fminf(GS_ALPHA_MAX, lv.w * G);
-                    const bool use = incl && !s.done_b && m >= f.lo + 1 && alpha >= GS_ALPHA_MIN;
+                    const bool use = incl && !s.done_b && (!WIDE || m >= f.lo + 1) && alpha >= GS_ALPHA_MIN;
                     const float Tn = fmaf(-alpha, s.Tb, s.Tb);
                     const bool stop = use && Tn < GS_T_STOP;
                     const bool blend = use && !stop;
@@ -890,8 +898,9 @@ k_raster_bwd(const gs_splat *__restrict__ splats, int n, const gs_camera *__rest
         g1 = gi[plane];
         g2 = gi[2 * plane];
     }
-    // light from behind the current splat, starting with the background
-    float B0 = Tr * bg0, B1 = Tr * bg1, B2 = Tr * bg2;
+    // light from behind the current splat enters dL/dalpha only as
+    // sum_ch g_ch B_ch: that one sum is carried, starting with the background
+    float gB = Tr * fmaf(g0, bg0, fmaf(g1, bg1, g2 * bg2));
     uint32_t maxnc = nc;
     for (int off = 32; off > 0; off >>= 1) maxnc = max(maxnc, (uint32_t)__shfl_xor((int)maxnc, off));
     __syncthreads();
@@ -954,12 +963,10 @@ k_raster_bwd(const gs_splat *__restrict__ splats, int n, const gs_camera *__rest
                     const float ioma = __builtin_amdgcn_rcpf(1.0f - alpha);
                     const float Tn = Tr * ioma;
                     const float wT = contrib ? alpha * Tn : 0.f;
-                    const float dLda = g0 * fmaf(c.x, Tn, -B0 * ioma) + g1 * fmaf(c.y, Tn, -B1 * ioma) +
-                                       g2 * fmaf(c.z, Tn, -B2 * ioma);
+                    const float gc = fmaf(g0, c.x, fmaf(g1, c.y, g2 * c.z));
+                    const float dLda = fmaf(gc, Tn, -gB * ioma);
                     const float gr = g0 * wT, gg = g1 * wT, gb = g2 * wT;
-                    B0 = fmaf(c.x, wT, B0);
-                    B1 = fmaf(c.y, wT, B1);
-                    B2 = fmaf(c.z, wT, B2);
+                    gB = fmaf(gc, wT, gB);
                     Tr = contrib ? Tn : Tr;
                     const float w = (contrib && araw <= GS_ALPHA_MAX) ? alpha * dLda : 0.f;
                     const float dx = fpx - a.x, dy = fpy - a.y;
