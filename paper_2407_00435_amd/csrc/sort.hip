@@ -128,11 +128,7 @@ k_radix_onesweep(const uint32_t *__restrict__ kin, const VT *__restrict__ vin,
     uint32_t dc = 0, dx = 0;
     if (t < 256) {
         dc = dcount[t];
-        dx = dc;
-        for (int off = 1; off < 64; off <<= 1) {
-            const uint32_t y = __shfl_up(dx, off);
-            if (lane >= off) dx += y;
-        }
+        dx = wave_incl_scan(dc);
         if (lane == 63) s_wsum[wave] = dx;
     }
     __syncthreads();
@@ -188,7 +184,7 @@ k_radix_onesweep(const uint32_t *__restrict__ kin, const VT *__restrict__ vin,
         __syncthreads();
         // per digit (threads < 256): exclusive over waves, block total, lookback
         const bool dig = t < 256;
-        uint32_t total = 0;
+        uint32_t total = 0, inc = 0;
         uint64_t prefix = 0;
         if (dig) {
 #pragma unroll
@@ -220,20 +216,16 @@ k_radix_onesweep(const uint32_t *__restrict__ kin, const VT *__restrict__ vin,
                 __hip_atomic_store(my, FLAG_INC | (prefix + total), __ATOMIC_RELAXED,
                                    __HIP_MEMORY_SCOPE_AGENT);
             }
-            s_bexcl[t] = total;
+            // block-local prefix over the digits: a wave scan in each of
+            // waves 0-3, then the totals of the waves before
+            inc = wave_incl_scan(total);
+            if (lane == 63) s_wsum[wave] = inc;
         }
-        __syncthreads();
-        // block-local exclusive prefix over digits (Hillis-Steele in LDS)
-        for (int off = 1; off < 256; off <<= 1) {
-            uint32_t add = (dig && t >= off) ? s_bexcl[t - off] : 0u;
-            __syncthreads();
-            if (dig) s_bexcl[t] += add;
-            __syncthreads();
-        }
-        uint32_t bexcl = dig ? s_bexcl[t] - total : 0u;
         __syncthreads();
         if (dig) {
-            s_bexcl[t] = bexcl;
+            uint32_t add = 0;
+            for (int w = 0; w < wave; ++w) add += s_wsum[w];
+            s_bexcl[t] = add + inc - total;
             s_dbase[t] = (uint64_t)s_gbase[t] + prefix;
         }
         __syncthreads();
