@@ -129,7 +129,7 @@ void carve_bin(Carve &c, int V, int64_t E, uint64_t cap, int64_t tiles, BinScrat
     bs.sat = c.take<uint32_t>(4 * 4 * tiles);
     bs.rs.hist = c.take<uint32_t>(4 * 4 * 256);
     uint64_t big = cap > (uint64_t)E ? cap : (uint64_t)E;
-    bs.rs.status_words = 256 * radix_max_parts(big ? big : 1);
+    bs.rs.status_words = radix_status_words(big);
     bs.rs.status = c.take<uint64_t>(2 * 8 * bs.rs.status_words);
     bs.rs.tickets = c.take<uint32_t>(4 * 4);
 }

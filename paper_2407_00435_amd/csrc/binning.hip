@@ -1091,7 +1091,7 @@ hipError_t launch_bin_sort(const gs_splat *splats, int n, const gs_camera *cams_
     hipLaunchKernelGGL(k_count, dim3((unsigned)nb), dim3(COUNT_THREADS), 0, st, splats, n, cams_dev, V, T, bs.vtab,
                        sat, bs.bbox, L, n_tiles, qbound, bs.hits, bs.rec, bs.dkey_b, hits_out, bs.block_vis);
     hipLaunchKernelGGL(k_scan_blocks, dim3(1), dim3(1024), 0, st, bs.block_sums, bs.block_vis, nb, bs.counts);
-    if ((err = radix_sort_prepare(bs.rs, bs.counts, (uint64_t)E, 4, st)) != hipSuccess) return err;
+    if ((err = radix_sort_prepare(bs.rs, bs.counts, (uint64_t)E, 4, 32, st)) != hipSuccess) return err;
     hipLaunchKernelGGL(k_compact, dim3((unsigned)nb), dim3(COUNT_THREADS), 0, st, bs.hits, bs.dkey_b, E,
                        bs.block_sums, bs.dkey_a, bs.dval_a, bs.rs.hist);
     // 3: depth sort of the entries with keys (4 x 8-bit passes), result back in (dkey_a, dval_a)
@@ -1106,7 +1106,7 @@ hipError_t launch_bin_sort(const gs_splat *splats, int n, const gs_camera *cams_
     // 4b: coarse pairs with their payloads, stably sorted by super-tile
     int st_bits = 1;
     while ((int64_t(1) << st_bits) < n_st) ++st_bits;
-    const bool even = radix_passes(st_bits) % 2 == 0;
+    const bool even = radix_pass_count(st_bits, 8) % 2 == 0;
     hipLaunchKernelGGL(k_coarse_emit, dim3((unsigned)nb), dim3(GATHER_THREADS), 0, st, bs.rec_s, bs.cc_s, bs.counts,
                        bs.block_sums2, bs.vtab, bs.stab, sat, bs.st_cls, L, n_tiles, bs.tkey_a, bs.cpay_a);
     if ((err = radix_sort_pairs_v2(bs.tkey_a, bs.cpay_a, bs.tkey_b, bs.cpay_b, bs.counts + 3, cap, st_bits, bs.rs,

@@ -34,18 +34,23 @@ struct RadixScratch {
     uint32_t *hist;     // [4][256] digit counts, then exclusive bases
     uint64_t *status;   // [2][status_words] lookback words, two buffers
     uint32_t *tickets;  // [4] partition tickets, one per pass
-    uint64_t status_words;  // words per buffer: 256 per partition
+    uint64_t status_words;  // words per buffer (radix_status_words)
 };
 // partitions the lookback status must hold for `cap` keys (smallest partition)
 uint64_t radix_max_parts(uint64_t cap);
+// lookback words per buffer for sorts of up to `cap` keys (any radix)
+uint64_t radix_status_words(uint64_t cap);
+// passes a sort of `bits`-bit keys with vbytes-byte values runs (its result
+// is in the second buffer pair when odd)
+int radix_pass_count(int bits, int vbytes);
 inline int radix_passes(int bits) { return (bits + 7) / 8; }
 // digit width of each pass for a key of `bits` bits (equal widths, <= 8)
 int radix_digit_bits(int bits);
 // Sorts count (device, clamped to cap) pairs.  Input in (ka, va); the result
-// is in (ka, va) if the number of passes is even, else in (kb, vb).  With
-// hist_ready the caller has accumulated the per-pass digit counts into
-// rs.hist ([pass][256], pass p = bits [p d, (p + 1) d) with d =
-// radix_digit_bits(bits)).
+// is in (ka, va) if radix_pass_count(bits, value bytes) is even, else in (kb,
+// vb).  With hist_ready (keys of more than 9 bits) the caller has called
+// radix_sort_prepare and accumulated the per-pass digit counts into rs.hist
+// ([pass][256], pass p = bits [p d, (p + 1) d) with d = radix_digit_bits(bits)).
 hipError_t radix_sort_pairs(uint32_t *ka, uint32_t *va, uint32_t *kb, uint32_t *vb,
                             const uint64_t *d_count, uint64_t cap, int bits,
                             const RadixScratch &rs, hipStream_t st, bool hist_ready);
@@ -57,7 +62,7 @@ hipError_t radix_sort_pairs_v2(uint32_t *ka, uint2 *va, uint32_t *kb, uint2 *vb,
 // zeroes the digit counts, tickets and first-pass lookback words of a sort
 // of min(*d_count, cap) pairs with vbytes-byte values; a caller that builds
 // the digit counts itself (hist_ready) calls it first
-hipError_t radix_sort_prepare(const RadixScratch &rs, const uint64_t *d_count, uint64_t cap, int vbytes,
+hipError_t radix_sort_prepare(const RadixScratch &rs, const uint64_t *d_count, uint64_t cap, int vbytes, int bits,
                               hipStream_t st);
 size_t radix_sort_scratch_bytes(uint64_t n);
 bool radix_set_part(int p);

@@ -35,10 +35,11 @@ constexpr int HIST_RUN = 16;
 
 __global__ void __launch_bounds__(1024)
 k_radix_hist(const uint32_t *__restrict__ keys, const uint64_t *__restrict__ d_count, uint64_t cap,
-             int passes, int dbits, uint32_t *__restrict__ hist)
+             int passes, int dbits, int radix, uint32_t *__restrict__ hist)
 {
-    __shared__ uint32_t sh[4][256];
-    for (int j = threadIdx.x; j < 4 * 256; j += blockDim.x) (&sh[0][0])[j] = 0;
+    // counts of pass p at sh[p * radix + digit] (radix 256, or 512 for one 9-bit pass)
+    __shared__ uint32_t sh[4 * 256];
+    for (int j = threadIdx.x; j < 4 * 256; j += blockDim.x) sh[j] = 0;
     __syncthreads();
     uint64_t count = *d_count;
     count = count < cap ? count : cap;
@@ -71,17 +72,17 @@ k_radix_hist(const uint32_t *__restrict__ keys, const uint64_t *__restrict__ d_c
                 if (d == prev) {
                     ++run;
                 } else {
-                    atomicAdd(&sh[p][prev], run);
+                    atomicAdd(&sh[p * radix + prev], run);
                     prev = d;
                     run = 1;
                 }
             }
-            atomicAdd(&sh[p][prev], run);
+            atomicAdd(&sh[p * radix + prev], run);
         }
     }
     __syncthreads();
-    for (int j = threadIdx.x; j < passes * 256; j += blockDim.x) {
-        uint32_t c = (&sh[0][0])[j];
+    for (int j = threadIdx.x; j < passes * radix; j += blockDim.x) {
+        uint32_t c = sh[j];
         if (c) atomicAdd(&hist[j], c);
     }
 }
@@ -91,11 +92,11 @@ k_radix_hist(const uint32_t *__restrict__ keys, const uint64_t *__restrict__ d_c
 // key count read on the device).  Each pass clears the words of the next.
 __global__ void __launch_bounds__(256)
 k_radix_init(uint32_t *__restrict__ hist, uint32_t *__restrict__ tickets, uint64_t *__restrict__ status,
-             const uint64_t *__restrict__ d_count, uint64_t cap, int part)
+             const uint64_t *__restrict__ d_count, uint64_t cap, int part, int radix)
 {
     uint64_t count = *d_count;
     count = count < cap ? count : cap;
-    const uint64_t words = ((count + part - 1) / part) * 256;
+    const uint64_t words = ((count + part - 1) / part) * radix;
     const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
     const uint64_t i0 = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
     for (uint64_t i = i0; i < words; i += stride) status[i] = 0;
@@ -103,7 +104,7 @@ k_radix_init(uint32_t *__restrict__ hist, uint32_t *__restrict__ tickets, uint64
     if (i0 < 4) tickets[i0] = 0;
 }
 
-template <int THREADS, int ITEMS, typename VT>
+template <int THREADS, int ITEMS, typename VT, int RB>
 __global__ void __launch_bounds__(THREADS)
 k_radix_onesweep(const uint32_t *__restrict__ kin, const VT *__restrict__ vin,
                  uint32_t *__restrict__ kout, VT *__restrict__ vout,
@@ -113,26 +114,29 @@ k_radix_onesweep(const uint32_t *__restrict__ kin, const VT *__restrict__ vin,
 {
     constexpr int WAVES = THREADS / 64;
     constexpr int PART = THREADS * ITEMS;
+    constexpr int R = 1 << RB;  // digits of the pass, one thread each
+    static_assert(R <= THREADS, "a thread per digit");
     __shared__ uint32_t s_keys[PART];
     __shared__ VT s_vals[PART];
-    __shared__ uint32_t s_whist[WAVES][256];
-    __shared__ uint32_t s_bexcl[256];  // exclusive prefix over digits of the block counts
-    __shared__ uint64_t s_dbase[256];  // global position of the digit's first key of this block
-    __shared__ uint32_t s_gbase[256];  // exclusive prefix of this pass's digit counts
-    __shared__ uint32_t s_wsum[4];
+    __shared__ uint32_t s_whist[WAVES][R];
+    __shared__ uint32_t s_bexcl[R];  // exclusive prefix over digits of the block counts
+    __shared__ uint64_t s_dbase[R];  // global position of the digit's first key of this block
+    __shared__ uint32_t s_gbase[R];  // exclusive prefix of this pass's digit counts
+    __shared__ uint32_t s_wsum[R / 64];
     __shared__ uint32_t s_part;
 
     const int t = threadIdx.x;
     const int wave = t >> 6, lane = t & 63;
-    // digit bases of the pass, once per workgroup (waves 0-3 take 64 digits each)
+    // digit bases of the pass, once per workgroup (the first R / 64 waves
+    // take 64 digits each)
     uint32_t dc = 0, dx = 0;
-    if (t < 256) {
+    if (t < R) {
         dc = dcount[t];
         dx = wave_incl_scan(dc);
         if (lane == 63) s_wsum[wave] = dx;
     }
     __syncthreads();
-    if (t < 256) {
+    if (t < R) {
         uint32_t add = 0;
         for (int w = 0; w < wave; ++w) add += s_wsum[w];
         s_gbase[t] = add + dx - dc;
@@ -143,12 +147,12 @@ k_radix_onesweep(const uint32_t *__restrict__ kin, const VT *__restrict__ vin,
     // persistent: partitions are taken in ticket order until none is left
     for (;;) {
         if (t == 0) s_part = atomicAdd(ticket, 1u);
-        for (int j = t; j < WAVES * 256; j += THREADS) (&s_whist[0][0])[j] = 0;
+        for (int j = t; j < WAVES * R; j += THREADS) (&s_whist[0][0])[j] = 0;
         __syncthreads();
         const uint64_t part = s_part;
         if (part >= nparts) return;
         // the next pass finds its partition's lookback words cleared
-        if (status_next && t < 256) status_next[part * 256 + t] = 0;
+        if (status_next && t < R) status_next[part * R + t] = 0;
 
         const uint64_t pbase = part * PART;
         const uint64_t wbase = pbase + (uint64_t)wave * (ITEMS * 64);
@@ -182,8 +186,8 @@ k_radix_onesweep(const uint32_t *__restrict__ kin, const VT *__restrict__ vin,
             wave_lds_sync();
         }
         __syncthreads();
-        // per digit (threads < 256): exclusive over waves, block total, lookback
-        const bool dig = t < 256;
+        // per digit (threads < R): exclusive over waves, block total, lookback
+        const bool dig = t < R;
         uint32_t total = 0, inc = 0;
         uint64_t prefix = 0;
         if (dig) {
@@ -193,7 +197,7 @@ k_radix_onesweep(const uint32_t *__restrict__ kin, const VT *__restrict__ vin,
                 s_whist[w][t] = total;
                 total += c;
             }
-            uint64_t *my = status + part * 256 + t;
+            uint64_t *my = status + part * R + t;
             if (part == 0) {
                 __hip_atomic_store(my, FLAG_INC | (uint64_t)total, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             } else {
@@ -202,7 +206,7 @@ k_radix_onesweep(const uint32_t *__restrict__ kin, const VT *__restrict__ vin,
             if (part > 0 && (uint32_t)t <= mask) {
                 int64_t q = (int64_t)part - 1;
                 for (;;) {
-                    uint64_t st = __hip_atomic_load(status + q * 256 + t, __ATOMIC_RELAXED,
+                    uint64_t st = __hip_atomic_load(status + q * R + t, __ATOMIC_RELAXED,
                                                     __HIP_MEMORY_SCOPE_AGENT);
                     uint64_t flag = st & ~VAL_MASK;
                     if (flag == 0) {
@@ -217,7 +221,7 @@ k_radix_onesweep(const uint32_t *__restrict__ kin, const VT *__restrict__ vin,
                                    __HIP_MEMORY_SCOPE_AGENT);
             }
             // block-local prefix over the digits: a wave scan in each of
-            // waves 0-3, then the totals of the waves before
+            // the first R / 64 waves, then the totals of the waves before
             inc = wave_incl_scan(total);
             if (lane == 63) s_wsum[wave] = inc;
         }
@@ -272,6 +276,9 @@ int part_size()
 
 uint64_t radix_max_parts(uint64_t cap) { return (cap + MIN_PART - 1) / MIN_PART; }
 
+// 256 words per partition of 4096 keys also hold 512 per partition of 8192
+uint64_t radix_status_words(uint64_t cap) { return 256 * (radix_max_parts(cap ? cap : 1) + 1); }
+
 int radix_digit_bits(int bits)
 {
     const int passes = radix_passes(bits);
@@ -282,16 +289,26 @@ int radix_digit_bits(int bits)
 // and values: 8-byte values take partitions of at most 8192 keys)
 static int part_for(int vbytes) { return vbytes > 4 && part_size() > 8192 ? 8192 : part_size(); }
 
-hipError_t radix_sort_prepare(const RadixScratch &rs, const uint64_t *d_count, uint64_t cap, int vbytes,
+// A 9-bit key sorts in one pass of 512 digits where the workgroup has a
+// thread per digit (512 threads: partitions of 8192 keys).
+static bool one_wide_pass(int bits, int P) { return bits == 9 && P == 8192; }
+
+int radix_pass_count(int bits, int vbytes)
+{
+    return one_wide_pass(bits, part_for(vbytes)) ? 1 : radix_passes(bits);
+}
+
+hipError_t radix_sort_prepare(const RadixScratch &rs, const uint64_t *d_count, uint64_t cap, int vbytes, int bits,
                               hipStream_t st)
 {
     const int P = part_for(vbytes);
-    const uint64_t words = ((cap + P - 1) / P) * 256;
+    const int R = one_wide_pass(bits, P) ? 512 : 256;
+    const uint64_t words = ((cap + P - 1) / P) * R;
     if (words > rs.status_words) return hipErrorInvalidValue;
     uint64_t blocks = (words + 255) / 256;
     blocks = blocks < 1 ? 1 : (blocks > 1024 ? 1024 : blocks);
     hipLaunchKernelGGL(k_radix_init, dim3((unsigned)blocks), dim3(256), 0, st, rs.hist, rs.tickets, rs.status,
-                       d_count, cap, P);
+                       d_count, cap, P, R);
     return hipGetLastError();
 }
 
@@ -300,16 +317,19 @@ static hipError_t sort_pairs_impl(uint32_t *ka, VT *va, uint32_t *kb, VT *vb,
                             const uint64_t *d_count, uint64_t cap, int bits,
                             const RadixScratch &rs, hipStream_t st, bool hist_ready)
 {
-    int passes = radix_passes(bits);
-    if (passes == 0 || cap == 0) return hipSuccess;
-    // equal digit widths <= 8 bits: fewer buckets give longer runs per digit
-    const int dbits = radix_digit_bits(bits);
+    if (radix_passes(bits) == 0 || cap == 0) return hipSuccess;
+    const int P = part_for((int)sizeof(VT));
+    const bool wide = one_wide_pass(bits, P);
+    const int passes = wide ? 1 : radix_passes(bits);
+    // equal digit widths <= 8 bits (fewer buckets give longer runs per
+    // digit), or one 9-bit digit
+    const int dbits = wide ? 9 : radix_digit_bits(bits);
+    const int R = wide ? 512 : 256;
     const uint32_t mask = (1u << dbits) - 1u;
     hipError_t e;
-    const int P = part_for((int)sizeof(VT));
     const uint64_t parts = (cap + P - 1) / P;
     if (!hist_ready) {
-        if ((e = radix_sort_prepare(rs, d_count, cap, (int)sizeof(VT), st)) != hipSuccess) return e;
+        if ((e = radix_sort_prepare(rs, d_count, cap, (int)sizeof(VT), bits, st)) != hipSuccess) return e;
         // few large blocks: each adds its counts to the global histogram
         // with one atomic per digit, and same-address atomics from
         // thousands of blocks would serialise in L2
@@ -317,7 +337,7 @@ static hipError_t sort_pairs_impl(uint32_t *ka, VT *va, uint32_t *kb, VT *vb,
         if (hist_blocks > 256) hist_blocks = 256;
         if (hist_blocks < 1) hist_blocks = 1;
         hipLaunchKernelGGL(k_radix_hist, dim3(hist_blocks), dim3(1024), 0, st, ka, d_count, cap, passes,
-                           dbits, rs.hist);
+                           dbits, R, rs.hist);
     }
     uint32_t *src_k = ka, *dst_k = kb;
     VT *src_v = va, *dst_v = vb;
@@ -330,16 +350,18 @@ static hipError_t sort_pairs_impl(uint32_t *ka, VT *va, uint32_t *kb, VT *vb,
         // buffer of pass p + 1 as it goes
         uint64_t *cur = rs.status + (p & 1) * rs.status_words;
         uint64_t *next = p + 1 < passes ? rs.status + ((p + 1) & 1) * rs.status_words : nullptr;
-#define GS_OS(TH, IT)                                                                                \
-    hipLaunchKernelGGL((k_radix_onesweep<TH, IT, VT>), dim3(sweep_blocks), dim3(TH), 0, st, src_k,     \
+#define GS_OS(TH, IT, RB)                                                                            \
+    hipLaunchKernelGGL((k_radix_onesweep<TH, IT, VT, RB>), dim3(sweep_blocks), dim3(TH), 0, st, src_k, \
                        src_v, dst_k, dst_v, d_count, cap, dbits * p, mask, dbits,                  \
-                       rs.hist + 256 * p, cur, next, rs.tickets + p)
-        if (P == 4096) {
-            GS_OS(256, 16);
+                       rs.hist + R * p, cur, next, rs.tickets + p)
+        if (wide) {
+            GS_OS(512, 16, 9);
+        } else if (P == 4096) {
+            GS_OS(256, 16, 8);
         } else if (P == 16384) {
-            if constexpr (sizeof(VT) == 4) GS_OS(1024, 16);
+            if constexpr (sizeof(VT) == 4) GS_OS(1024, 16, 8);
         } else {
-            GS_OS(512, 16);
+            GS_OS(512, 16, 8);
         }
 #undef GS_OS
         uint32_t *tk = src_k;
@@ -372,8 +394,8 @@ bool radix_set_part(int p)
 
 size_t radix_sort_scratch_bytes(uint64_t n)
 {
-    // hist [4][256] u32 | tickets [4] u32 | count u64 | status [2][parts][256] u64
-    return 4 * 256 * 4 + 4 * 4 + 8 + 256 + 2 * 8 * 256 * radix_max_parts(n ? n : 1) + 256;
+    // hist [4][256] u32 | tickets [4] u32 | count u64 | status [2][status words] u64
+    return 4 * 256 * 4 + 4 * 4 + 8 + 256 + 2 * 8 * radix_status_words(n) + 256;
 }
 
 hipError_t radix_sort_standalone(uint32_t *keys, uint32_t *vals, uint32_t *kt, uint32_t *vt, uint64_t n,
@@ -386,8 +408,8 @@ hipError_t radix_sort_standalone(uint32_t *keys, uint32_t *vals, uint32_t *kt, u
     uint64_t *count = (uint64_t *)(base + 4 * 256 * 4 + 4 * 4 + 8);  // 8-byte aligned
     rs.status = (uint64_t *)(base + 4 * 256 * 4 + 4 * 4 + 8 + 256);
     rs.status = (uint64_t *)(((uintptr_t)rs.status + 255) & ~uintptr_t(255));
-    rs.status_words = 256 * radix_max_parts(n ? n : 1);
+    rs.status_words = radix_status_words(n);
     hipLaunchKernelGGL(k_set_count, dim3(1), dim3(1), 0, st, count, n);
-    *in_tmp = radix_passes(bits) % 2 == 1;
+    *in_tmp = radix_pass_count(bits, 4) % 2 == 1;
     return radix_sort_pairs(keys, vals, kt, vt, count, n, bits, rs, st, false);
 }

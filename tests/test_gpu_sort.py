@@ -1,7 +1,7 @@
 """The radix sort used for the depth and tile passes (Section 2.1 "Sorting"):
 bit-exact against numpy's stable sort for every partition size, with
 ragged sizes (not multiples of a partition) and the digit widths the tile
-keys use."""
+keys use (9 bits: one pass of 512 digits with 8192-key partitions)."""
 import numpy as np
 import pytest
 import torch
@@ -12,14 +12,15 @@ pytestmark = pytest.mark.gpu
 
 
 @pytest.mark.parametrize("part", [4096, 8192, 16384])
-@pytest.mark.parametrize("bits,n", [(7, 1000), (14, 333_333), (18, 1_234_567), (32, 777_777), (32, 1)])
+@pytest.mark.parametrize("bits,n", [(7, 1000), (9, 500_001), (9, 8192), (14, 333_333), (18, 1_234_567),
+                                    (32, 777_777), (32, 1)])
 def test_sort_pairs_bit_exact(part, bits, n):
     need_gpu()
     import paper_2407_00435_amd as g
     say("sort", part, bits, n)
     g.gs_set_tuning("radix_part", part)
     rng = np.random.default_rng(bits * 1000 + n)
-    if bits == 14:
+    if bits in (9, 14):
         # tile ids with heavy skew: a few tiles hold most keys
         keys = np.minimum(rng.zipf(1.3, n), (1 << bits) - 1).astype(np.uint32)
     else:
