@@ -412,16 +412,34 @@ k_st_class(const int64_t *__restrict__ vtab, const int4 *__restrict__ stab, int 
     }
 }
 
-// Payload of a coarse pair: the entry (view * n + point) and, relative to
-// super-tile (sx, sy), its clipped tile rectangle (4 bits per bound) with the
-// quality bound in bits 16..23.
-__device__ __forceinline__ uint2 coarse_payload(uint32_t rx, uint32_t ry, uint32_t m, uint32_t e, int sx, int sy)
+// What a coarse pair carries besides its entry (view * n + point): relative
+// to super-tile (sx, sy), the entry's clipped tile rectangle (3 bits per
+// bound) and min(quality bound, 4) (3 bits; the tile pass tells no higher
+// bound apart), 15 bits.  With super-tile ids below 2^ST_ID_BITS they ride
+// in the sort key above the id (PACKED: key = id | info << ST_ID_BITS, 4-byte
+// value e); else the value is (e, info).
+constexpr int ST_ID_BITS = 17;
+static_assert(ST == 8, "3 bits per bound");
+__device__ __forceinline__ uint32_t coarse_info(uint32_t rx, uint32_t ry, uint32_t m, int sx, int sy)
 {
     const int x0 = (int)(rx & 0xffffu) - sx * ST, y0 = (int)(rx >> 16) - sy * ST;
     const int x1 = (int)(ry & 0xffffu) - sx * ST, y1 = (int)(ry >> 16) - sy * ST;
     const uint32_t cx0 = (uint32_t)max(x0, 0), cy0 = (uint32_t)max(y0, 0);
     const uint32_t cx1 = (uint32_t)min(x1, ST - 1), cy1 = (uint32_t)min(y1, ST - 1);
-    return make_uint2(e, cx0 | (cy0 << 4) | (cx1 << 8) | (cy1 << 12) | (m << 16));
+    return cx0 | (cy0 << 3) | (cx1 << 6) | (cy1 << 9) | (min(m, 4u) << 12);
+}
+
+template <bool PACKED>
+__device__ __forceinline__ void coarse_put(uint32_t *__restrict__ ck, void *__restrict__ cv, uint64_t pos,
+                                           uint32_t st_id, uint32_t info, uint32_t e)
+{
+    if (PACKED) {
+        ck[pos] = st_id | (info << ST_ID_BITS);
+        reinterpret_cast<uint32_t *>(cv)[pos] = e;
+    } else {
+        ck[pos] = st_id;
+        reinterpret_cast<uint2 *>(cv)[pos] = make_uint2(e, info);
+    }
 }
 
 // Super-tiles of the entry's view that its tile rectangle [x0, x1] x [y0, y1]
@@ -430,22 +448,20 @@ __device__ __forceinline__ uint2 coarse_payload(uint32_t rx, uint32_t ry, uint32
 // super-tile > 0 where the level keeps part of the super-tile), in row-major
 // order.  With EMIT, (super-tile id, payload) pairs of entry e are written
 // from position pos on.  Returns their number.
-template <bool EMIT>
+template <bool EMIT, bool PACKED = false>
 __device__ __forceinline__ uint32_t coarse_walk(uint32_t rx, uint32_t ry, uint32_t m, int v, uint32_t e,
                                                 const int64_t *__restrict__ vtab, const int4 *__restrict__ stab,
                                                 const uint32_t *__restrict__ sat, const uint8_t *__restrict__ cls,
                                                 int L, int64_t n_tiles, uint32_t *__restrict__ ck,
-                                                uint2 *__restrict__ cp, uint64_t pos)
+                                                void *__restrict__ cv, uint64_t pos)
 {
     const int x0 = (int)(rx & 0xffffu), y0 = (int)(rx >> 16), x1 = (int)(ry & 0xffffu), y1 = (int)(ry >> 16);
     const int sx0 = x0 / ST, sx1 = x1 / ST, sy0 = y0 / ST, sy1 = y1 / ST;
     const int4 sb = stab[v];
     if (sx0 == sx1 && sy0 == sy1) {
         // one super-tile: it holds all the entry's kept tiles (there is one)
-        if (EMIT) {
-            ck[pos] = (uint32_t)(sb.x + sy0 * sb.y + sx0);
-            cp[pos] = coarse_payload(rx, ry, m, e, sx0, sy0);
-        }
+        if (EMIT)
+            coarse_put<PACKED>(ck, cv, pos, (uint32_t)(sb.x + sy0 * sb.y + sx0), coarse_info(rx, ry, m, sx0, sy0), e);
         return 1u;
     }
     const uint32_t *s = nullptr;
@@ -468,10 +484,7 @@ __device__ __forceinline__ uint32_t coarse_walk(uint32_t rx, uint32_t ry, uint32
                 }
             }
             if (keep) {
-                if (EMIT) {
-                    ck[pos + c] = st_id;
-                    cp[pos + c] = coarse_payload(rx, ry, m, e, sx, sy);
-                }
+                if (EMIT) coarse_put<PACKED>(ck, cv, pos + c, st_id, coarse_info(rx, ry, m, sx, sy), e);
                 ++c;
             }
         }
@@ -581,11 +594,12 @@ k_gather(const uint32_t *__restrict__ order, const uint4 *__restrict__ rec, cons
 
 // 4b. coarse pairs of every depth-ordered entry at its scanned offset (from
 // the mask when there is one).
+template <bool PACKED>
 __global__ void __launch_bounds__(GATHER_THREADS)
 k_coarse_emit(const uint4 *__restrict__ rec_s, const uint32_t *__restrict__ cc_s, const uint64_t *__restrict__ counts,
               const uint64_t *__restrict__ boff, const int64_t *__restrict__ vtab, const int4 *__restrict__ stab,
               const uint32_t *__restrict__ sat, const uint8_t *__restrict__ cls, int L, int64_t n_tiles,
-              uint32_t *__restrict__ ck, uint2 *__restrict__ cp)
+              uint32_t *__restrict__ ck, void *__restrict__ cv)
 {
     constexpr int W = GATHER_THREADS / 64;
     __shared__ uint32_t s_w[GATHER_ITEMS][W];
@@ -631,13 +645,13 @@ k_coarse_emit(const uint4 *__restrict__ rec_s, const uint32_t *__restrict__ cc_s
                     const int bit = __ffs(mask) - 1;
                     mask &= mask - 1u;
                     const int sx = sx0 + bit % MS, sy = sy0 + bit / MS;
-                    ck[pos + k] = (uint32_t)(sb.x + sy * sb.y + sx);
-                    cp[pos + k] = coarse_payload(q[j].x, q[j].y, q[j].w & 255u, q[j].z, sx, sy);
+                    coarse_put<PACKED>(ck, cv, pos + k, (uint32_t)(sb.x + sy * sb.y + sx),
+                                       coarse_info(q[j].x, q[j].y, q[j].w & 255u, sx, sy), q[j].z);
                     ++k;
                 }
             } else {
-                coarse_walk<true>(q[j].x, q[j].y, q[j].w & 255u, v, q[j].z, vtab, stab, sat, cls, L, n_tiles, ck,
-                                  cp, pos);
+                coarse_walk<true, PACKED>(q[j].x, q[j].y, q[j].w & 255u, v, q[j].z, vtab, stab, sat, cls, L,
+                                          n_tiles, ck, cv, pos);
             }
         }
         run += tw;
@@ -742,9 +756,10 @@ __host__ __device__ constexpr uint64_t row_spread()
     for (int y = 0; y < ST; ++y) r |= 1ull << (y * ST);
     return r;
 }
-template <bool WRITE>
+template <bool WRITE, bool PACKED>
 __global__ void __launch_bounds__(256)
-k_tile_pass(const uint2 *__restrict__ cp, const uint4 *__restrict__ chunk, const uint64_t *__restrict__ counts,
+k_tile_pass(const uint32_t *__restrict__ ck, const void *__restrict__ cv, const uint4 *__restrict__ chunk,
+            const uint64_t *__restrict__ counts,
             const int64_t *__restrict__ vtab,
             const int4 *__restrict__ stab, int V, int n, const uint8_t *__restrict__ tl, uint32_t *__restrict__ ccnt,
             const uint32_t *__restrict__ ranges, uint32_t *__restrict__ vals, uint64_t *__restrict__ keys,
@@ -763,12 +778,19 @@ k_tile_pass(const uint2 *__restrict__ cp, const uint4 *__restrict__ chunk, const
         const uint4 ch = chunk[c];
         const uint32_t b = ch.x, e_end = ch.y, s = ch.z;
         const int v = (int)ch.w;
-        // the chunk's pair payloads early: they do not depend on the view
+        // the chunk's pairs early (entry, info): they do not depend on the view
         uint2 pj[NB];
 #pragma unroll
         for (int q = 0; q < NB; ++q) {
             const uint32_t j = b + 64u * q + (uint32_t)lane;
-            pj[q] = j < e_end ? cp[j] : make_uint2(0u, 0xFFFFFFFFu);
+            if (j < e_end) {
+                if (PACKED)
+                    pj[q] = make_uint2(reinterpret_cast<const uint32_t *>(cv)[j], ck[j] >> ST_ID_BITS);
+                else
+                    pj[q] = reinterpret_cast<const uint2 *>(cv)[j];
+            } else {
+                pj[q] = make_uint2(0u, 0xFFFFFFFFu);  // no entry (info never has bit 31)
+            }
         }
         const int4 sb = stab[v];
         const int sl = (int)s - sb.x, sy = sl / sb.y, sx = sl - sy * sb.y;
@@ -798,13 +820,13 @@ k_tile_pass(const uint2 *__restrict__ cp, const uint4 *__restrict__ chunk, const
             ez[q] = 0u;
             if (pj[q].y != 0xFFFFFFFFu) {
                 const uint32_t w = pj[q].y;
-                const int cx0 = (int)(w & 15u), cy0 = (int)((w >> 4) & 15u);
-                const int cx1 = (int)((w >> 8) & 15u), cy1 = (int)((w >> 12) & 15u);
+                const int cx0 = (int)(w & 7u), cy0 = (int)((w >> 3) & 7u);
+                const int cx1 = (int)((w >> 6) & 7u), cy1 = (int)((w >> 9) & 7u);
                 const uint64_t cols = (2ull << cx1) - (1ull << cx0);
                 const int hb = (cy1 + 1) * ST;
                 const uint64_t rows = (hb >= 64 ? ~0ull : (1ull << hb) - 1ull) & ~((1ull << (cy0 * ST)) - 1ull);
                 tm = cols * row_spread() & rows;
-                const uint32_t m = (w >> 16) & 255u;
+                const uint32_t m = w >> 12;
                 tm &= m >= 4u ? lvm4 : (m == 3u ? lvm3 : (m == 2u ? lvm2 : lvm1));
                 ez[q] = pj[q].x;
             }
@@ -1002,10 +1024,11 @@ k_tile_scan1(const uint32_t *__restrict__ tot, int64_t n_tiles, const uint64_t *
     }
 }
 
-// Super-tile ranges: four sorted ids per thread; a boundary between k - 1
-// and k closes one run and opens the next.
+// Super-tile ranges: four sorted ids (the key bits under id_mask) per
+// thread; a boundary between k - 1 and k closes one run and opens the next.
 __global__ void __launch_bounds__(256)
-k_ranges(const uint32_t *__restrict__ tkey, const uint64_t *__restrict__ d_count, uint64_t cap, int64_t n_ids,
+k_ranges(const uint32_t *__restrict__ tkey, uint32_t id_mask, const uint64_t *__restrict__ d_count, uint64_t cap,
+         int64_t n_ids,
          uint32_t *__restrict__ ranges)
 {
     uint64_t count = *d_count;
@@ -1013,13 +1036,13 @@ k_ranges(const uint32_t *__restrict__ tkey, const uint64_t *__restrict__ d_count
     const uint64_t stride = (uint64_t)gridDim.x * blockDim.x * 4;
     for (uint64_t k0 = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) * 4; k0 < count; k0 += stride) {
         uint32_t t[5];
-        t[0] = k0 == 0 ? 0xFFFFFFFFu : tkey[k0 - 1];
+        t[0] = k0 == 0 ? 0xFFFFFFFFu : tkey[k0 - 1] & id_mask;
         if (k0 + 4 <= count) {
             const uint4 q = *reinterpret_cast<const uint4 *>(tkey + k0);
-            t[1] = q.x; t[2] = q.y; t[3] = q.z; t[4] = q.w;
+            t[1] = q.x & id_mask; t[2] = q.y & id_mask; t[3] = q.z & id_mask; t[4] = q.w & id_mask;
         } else {
 #pragma unroll
-            for (int j = 0; j < 4; ++j) t[j + 1] = k0 + j < count ? tkey[k0 + j] : 0xFFFFFFFFu;
+            for (int j = 0; j < 4; ++j) t[j + 1] = k0 + j < count ? tkey[k0 + j] & id_mask : 0xFFFFFFFFu;
         }
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
@@ -1106,16 +1129,30 @@ hipError_t launch_bin_sort(const gs_splat *splats, int n, const gs_camera *cams_
     // 4b: coarse pairs with their payloads, stably sorted by super-tile
     int st_bits = 1;
     while ((int64_t(1) << st_bits) < n_st) ++st_bits;
-    const bool even = radix_pass_count(st_bits, 8) % 2 == 0;
-    hipLaunchKernelGGL(k_coarse_emit, dim3((unsigned)nb), dim3(GATHER_THREADS), 0, st, bs.rec_s, bs.cc_s, bs.counts,
-                       bs.block_sums2, bs.vtab, bs.stab, sat, bs.st_cls, L, n_tiles, bs.tkey_a, bs.cpay_a);
-    if ((err = radix_sort_pairs_v2(bs.tkey_a, bs.cpay_a, bs.tkey_b, bs.cpay_b, bs.counts + 3, cap, st_bits, bs.rs,
-                                   st)) != hipSuccess)
-        return err;
+    // the pair's info rides in the sort key when the super-tile ids leave room
+    const bool packed = st_bits <= ST_ID_BITS;
+    const bool even = radix_pass_count(st_bits, packed ? 4 : 8) % 2 == 0;
+    if (packed) {
+        hipLaunchKernelGGL(k_coarse_emit<true>, dim3((unsigned)nb), dim3(GATHER_THREADS), 0, st, bs.rec_s, bs.cc_s,
+                           bs.counts, bs.block_sums2, bs.vtab, bs.stab, sat, bs.st_cls, L, n_tiles, bs.tkey_a,
+                           (void *)bs.cpay_a);
+        if ((err = radix_sort_pairs(bs.tkey_a, reinterpret_cast<uint32_t *>(bs.cpay_a), bs.tkey_b,
+                                    reinterpret_cast<uint32_t *>(bs.cpay_b), bs.counts + 3, cap, st_bits, bs.rs, st,
+                                    false)) != hipSuccess)
+            return err;
+    } else {
+        hipLaunchKernelGGL(k_coarse_emit<false>, dim3((unsigned)nb), dim3(GATHER_THREADS), 0, st, bs.rec_s, bs.cc_s,
+                           bs.counts, bs.block_sums2, bs.vtab, bs.stab, sat, bs.st_cls, L, n_tiles, bs.tkey_a,
+                           (void *)bs.cpay_a);
+        if ((err = radix_sort_pairs_v2(bs.tkey_a, bs.cpay_a, bs.tkey_b, bs.cpay_b, bs.counts + 3, cap, st_bits, bs.rs,
+                                       st)) != hipSuccess)
+            return err;
+    }
     const uint32_t *sk = even ? bs.tkey_a : bs.tkey_b;
-    const uint2 *sp = even ? bs.cpay_a : bs.cpay_b;
-    hipLaunchKernelGGL(k_ranges, dim3(grid_for(cap, 256 * 16, 8192)), dim3(256), 0, st, sk, bs.counts + 3, cap,
-                       n_st, bs.st_ranges);
+    const void *sv = even ? (const void *)bs.cpay_a : (const void *)bs.cpay_b;
+    const uint32_t id_mask = packed ? (1u << ST_ID_BITS) - 1u : 0xFFFFFFFFu;
+    hipLaunchKernelGGL(k_ranges, dim3(grid_for(cap, 256 * 16, 8192)), dim3(256), 0, st, sk, id_mask, bs.counts + 3,
+                       cap, n_st, bs.st_ranges);
     if (n_st <= 1024) {
         hipLaunchKernelGGL(k_chunk_table<true>, dim3(1), dim3(1024), 0, st, bs.st_ranges, n_st, bs.chunk_off,
                            bs.counts + 4, bs.stab, V, bs.chunk);
@@ -1127,9 +1164,13 @@ hipError_t launch_bin_sort(const gs_splat *splats, int n, const gs_camera *cams_
     }
     // 4c-4e: per-tile counts, their scans (tile ranges), keys at their final positions
     const int pass_blocks = grid_for(bin_max_chunks(cap, n_tiles), 4, 2048);
-    hipLaunchKernelGGL((k_tile_pass<false>), dim3(pass_blocks), dim3(256), 0, st, sp, bs.chunk, bs.counts, bs.vtab,
-                       bs.stab, V, n, tile_level, bs.ccnt,
-                       ranges, vals, keys, splats);
+#define GS_TP(W, PK)                                                                                       \
+    hipLaunchKernelGGL((k_tile_pass<W, PK>), dim3(pass_blocks), dim3(256), 0, st, sk, sv, bs.chunk, bs.counts, \
+                       bs.vtab, bs.stab, V, n, tile_level, bs.ccnt, ranges, vals, keys, splats)
+    if (packed)
+        GS_TP(false, true);
+    else
+        GS_TP(false, false);
     hipLaunchKernelGGL(k_col_scan, dim3((unsigned)n_st), dim3(COL_WAVES * 64), 0, st, bs.chunk_off, bs.vtab, bs.stab, V,
                        bs.ccnt, bs.tot);
     if (n_tiles <= TILE_SCAN1_MAX) {
@@ -1141,8 +1182,10 @@ hipError_t launch_bin_sort(const gs_splat *splats, int n, const gs_camera *cams_
         hipLaunchKernelGGL(k_tile_ranges, dim3((unsigned)nbt), dim3(SCAN_THREADS), 0, st, bs.tot, n_tiles, bs.tsum,
                            bs.counts, ranges);
     }
-    hipLaunchKernelGGL((k_tile_pass<true>), dim3(pass_blocks), dim3(256), 0, st, sp, bs.chunk, bs.counts, bs.vtab,
-                       bs.stab, V, n, tile_level, bs.ccnt,
-                       ranges, vals, keys, splats);
+    if (packed)
+        GS_TP(true, true);
+    else
+        GS_TP(true, false);
+#undef GS_TP
     return hipGetLastError();
 }
