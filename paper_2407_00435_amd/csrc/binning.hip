@@ -756,7 +756,7 @@ __host__ __device__ constexpr uint64_t row_spread()
     for (int y = 0; y < ST; ++y) r |= 1ull << (y * ST);
     return r;
 }
-template <bool WRITE, bool PACKED>
+template <bool WRITE, bool PACKED, bool KEYS>
 __global__ void __launch_bounds__(256)
 k_tile_pass(const uint32_t *__restrict__ ck, const void *__restrict__ cv, const uint4 *__restrict__ chunk,
             const uint64_t *__restrict__ counts,
@@ -835,10 +835,12 @@ k_tile_pass(const uint32_t *__restrict__ ck, const void *__restrict__ cv, const 
             uni |= tm;
         }
         const uint32_t ulo = wave_or((uint32_t)uni), uhi = wave_or((uint32_t)(uni >> 32));
-        const uint32_t nq = (e_end - b + 63u) / 64u;
         const uint32_t vbase = (uint32_t)v * (uint32_t)n;
         wave_lds_sync();
         uint32_t mcnt = 0;
+        // batches past the chunk's end hold empty masks: their ballots are
+        // zero, so no batch needs a bounds test; a batch's store is skipped by
+        // the empty exec mask
 #pragma unroll
         for (int half = 0; half < 2; ++half) {
             uint32_t um = half ? uhi : ulo;
@@ -851,22 +853,22 @@ k_tile_pass(const uint32_t *__restrict__ ck, const void *__restrict__ cv, const 
                 uint32_t tot = 0;
 #pragma unroll
                 for (int q = 0; q < NB; ++q) {
-                    if ((uint32_t)q >= nq) break;
                     const bool cov = (((half ? mhi[q] : mlo[q]) >> l32) & 1u) != 0u;
                     const uint64_t bal = __builtin_amdgcn_ballot_w64(cov);
-                    if (WRITE && bal) {
+                    if (WRITE) {
                         if (cov) {
                             const uint32_t at = pos + __builtin_amdgcn_mbcnt_hi(
                                                           (uint32_t)(bal >> 32),
                                                           __builtin_amdgcn_mbcnt_lo((uint32_t)bal, 0u));
                             vals[at] = ez[q] - vbase;
-                            if (keys)
+                            if (KEYS)
                                 keys[at] = ((uint64_t)(toff + (int64_t)(by + l / ST) * sb.z + bx + l % ST) << 32) |
                                            __float_as_uint(splats[ez[q]].depth);
                         }
                         pos += (uint32_t)__popcll(bal);
+                    } else {
+                        tot += (uint32_t)__popcll(bal);
                     }
-                    if (!WRITE) tot += (uint32_t)__popcll(bal);
                 }
                 if (!WRITE) mcnt = lane == l ? tot : mcnt;
             }
@@ -1164,13 +1166,13 @@ hipError_t launch_bin_sort(const gs_splat *splats, int n, const gs_camera *cams_
     }
     // 4c-4e: per-tile counts, their scans (tile ranges), keys at their final positions
     const int pass_blocks = grid_for(bin_max_chunks(cap, n_tiles), 4, 2048);
-#define GS_TP(W, PK)                                                                                       \
-    hipLaunchKernelGGL((k_tile_pass<W, PK>), dim3(pass_blocks), dim3(256), 0, st, sk, sv, bs.chunk, bs.counts, \
-                       bs.vtab, bs.stab, V, n, tile_level, bs.ccnt, ranges, vals, keys, splats)
+#define GS_TP(W, PK, KY)                                                                                   \
+    hipLaunchKernelGGL((k_tile_pass<W, PK, KY>), dim3(pass_blocks), dim3(256), 0, st, sk, sv, bs.chunk,         \
+                       bs.counts, bs.vtab, bs.stab, V, n, tile_level, bs.ccnt, ranges, vals, keys, splats)
     if (packed)
-        GS_TP(false, true);
+        GS_TP(false, true, false);
     else
-        GS_TP(false, false);
+        GS_TP(false, false, false);
     hipLaunchKernelGGL(k_col_scan, dim3((unsigned)n_st), dim3(COL_WAVES * 64), 0, st, bs.chunk_off, bs.vtab, bs.stab, V,
                        bs.ccnt, bs.tot);
     if (n_tiles <= TILE_SCAN1_MAX) {
@@ -1182,10 +1184,17 @@ hipError_t launch_bin_sort(const gs_splat *splats, int n, const gs_camera *cams_
         hipLaunchKernelGGL(k_tile_ranges, dim3((unsigned)nbt), dim3(SCAN_THREADS), 0, st, bs.tot, n_tiles, bs.tsum,
                            bs.counts, ranges);
     }
-    if (packed)
-        GS_TP(true, true);
-    else
-        GS_TP(true, false);
+    if (packed) {
+        if (keys)
+            GS_TP(true, true, true);
+        else
+            GS_TP(true, true, false);
+    } else {
+        if (keys)
+            GS_TP(true, false, true);
+        else
+            GS_TP(true, false, false);
+    }
 #undef GS_TP
     return hipGetLastError();
 }
