@@ -855,6 +855,16 @@ __device__ __forceinline__ float wave_total_63(float x)
     return x;
 }
 
+// Sum over each octet of lanes (8 k .. 8 k + 7), in every lane of the octet:
+// quad exchanges, then the half-row mirror (lane i <-> 7 - i within 8).
+__device__ __forceinline__ float octet_sum(float x)
+{
+    x += dpp_f<0xB1>(x);   // quad_perm [1,0,3,2]
+    x += dpp_f<0x4E>(x);   // quad_perm [2,3,0,1]
+    x += dpp_f<0x141>(x);  // row_half_mirror
+    return x;
+}
+
 template <int T>
 __global__ void __launch_bounds__(T *T)
 k_raster_bwd(const gs_splat *__restrict__ splats, int n, const gs_camera *__restrict__ cams, int V,
@@ -867,6 +877,7 @@ k_raster_bwd(const gs_splat *__restrict__ splats, int n, const gs_camera *__rest
     constexpr int SUB = T / 8;
     constexpr int NG = 9;  // sums of w, w dx, w dy, w dx^2, w dx dy, w dy^2, colour r, g, b
     __shared__ BwdRec s_rec[WAVES][64];
+    __shared__ float2 s_m[WAVES][8][64];  // (w, alpha T) of 8 records x 64 pixels per wave
     __shared__ float s_grad[NG][64];
     __shared__ uint32_t s_id[64];
     __shared__ uint32_t s_maxnc;
@@ -901,6 +912,16 @@ k_raster_bwd(const gs_splat *__restrict__ splats, int n, const gs_camera *__rest
     // light from behind the current splat enters dL/dalpha only as
     // sum_ch g_ch B_ch: that one sum is carried, starting with the background
     float gB = Tr * fmaf(g0, bg0, fmaf(g1, bg1, g2 * bg2));
+    // dL/dimage of the 8 pixels of row (lane & 7) of the wave's block, for
+    // the per-record row sums
+    float grow0[8], grow1[8], grow2[8];
+#pragma unroll
+    for (int x = 0; x < 8; ++x) {
+        const int src = 8 * (lane & 7) + x;
+        grow0[x] = __shfl(g0, src);
+        grow1[x] = __shfl(g1, src);
+        grow2[x] = __shfl(g2, src);
+    }
     uint32_t maxnc = nc;
     for (int off = 32; off > 0; off >>= 1) maxnc = max(maxnc, (uint32_t)__shfl_xor((int)maxnc, off));
     __syncthreads();
@@ -934,27 +955,27 @@ k_raster_bwd(const gs_splat *__restrict__ splats, int n, const gs_camera *__rest
             }
             const uint64_t msk = ballot64(keep);
             const int cnt = __popcll(msk);
-            // padded to a multiple of 4 with null records (an infinite alpha
-            // threshold: no pixel takes them), walked back to front in groups of 4
-            const int cnt4 = (cnt + 3) & ~3;
+            // padded to a multiple of 8 with null records (an infinite alpha
+            // threshold: no pixel takes them), walked back to front in groups of 8
+            const int cnt8 = (cnt + 7) & ~7;
             if (keep) s_rec[wave][__popcll(msk & lanemask_lt())] = rec;
-            if (lane >= cnt && lane < cnt4) {
+            if (lane >= cnt && lane < cnt8) {
                 BwdRec z;
                 z.a = z.b = z.c = make_float4(0.f, 0.f, 0.f, 0.f);
                 z.b.z = __builtin_inff();
                 s_rec[wave][lane] = z;
             }
             wave_lds_sync();
-            for (int j0 = cnt4 - 4; j0 >= 0; j0 -= 4) {
-#pragma unroll
-                for (int j = j0 + 3; j >= j0; --j) {
+            for (int j0 = cnt8 - 8; j0 >= 0; j0 -= 8) {
+                // (1) lanes are pixels: per record w = alpha dL/dalpha and the
+                // blend weight alpha T into the wave's LDS block.  Branch-free:
+                // every lane evaluates, selects take the forward's decisions.
+                bool any = false;
+#pragma unroll 2
+                for (int r = 7; r >= 0; --r) {
+                    const int j = j0 + r;
                     const float4 a = s_rec[wave][j].a, b = s_rec[wave][j].b;
                     const uint32_t ppos = __float_as_uint(b.w);
-                    // per pixel only w = alpha dL/dalpha and its moments in
-                    // (dx, dy); the conic, mean and opacity gradients are linear
-                    // in their sums (applied once per splat at the flush).
-                    // Branch-free: every lane evaluates, selects take the
-                    // decisions of the forward pass.
                     const float e2 = pair_e2(a, b, fpx, fpy);
                     const bool contrib = ppos <= nc && e2 >= b.z;
                     const float4 c = s_rec[wave][j].c;
@@ -965,24 +986,50 @@ k_raster_bwd(const gs_splat *__restrict__ splats, int n, const gs_camera *__rest
                     const float wT = contrib ? alpha * Tn : 0.f;
                     const float gc = fmaf(g0, c.x, fmaf(g1, c.y, g2 * c.z));
                     const float dLda = fmaf(gc, Tn, -gB * ioma);
-                    const float gr = g0 * wT, gg = g1 * wT, gb = g2 * wT;
                     gB = fmaf(gc, wT, gB);
                     Tr = contrib ? Tn : Tr;
                     const float w = (contrib && araw <= GS_ALPHA_MAX) ? alpha * dLda : 0.f;
-                    const float dx = fpx - a.x, dy = fpy - a.y;
-                    const float wdx = w * dx, wdy = w * dy;
-                    const float wdx2 = wdx * dx, wdxdy = wdx * dy, wdy2 = wdy * dy;
-                    if (__builtin_amdgcn_ballot_w64(contrib) != 0) {
-                        // eight quantities by a reduce-scatter over each row (one
-                        // LDS atomic per quantity and row), the ninth by a row sum
-                        const float v8[8] = {w, wdx, wdy, wdx2, wdxdy, wdy2, gr, gg};
-                        const float part = row_scatter_sum8(v8, lane);
-                        const float pb = row_sum16(gb);
-                        const int q = (int)(ppos - (uint32_t)p0);
-                        if ((lane & 8) == 0) atomicAdd(&s_grad[scatter_q(lane)][q], part);
-                        if ((lane & 15) == 15) atomicAdd(&s_grad[8][q], pb);
+                    s_m[wave][r][lane] = make_float2(w, wT);
+                    any = any || contrib;
+                }
+                if (ballot64(any) == 0) continue;  // none of the 8 reaches the wave's pixels
+                wave_lds_sync();
+                // (2) lane 8 r + y sums record j0 + r over pixel row y in
+                // registers (w and its moments in (dx, dy); colour as g alpha
+                // T), then the 8 rows of a record add up by DPP within the
+                // lane octet, and one lane per record adds the nine sums to
+                // the tile's slots of the record's list position
+                {
+                    const int r = lane >> 3, y = lane & 7;
+                    const float4 a = s_rec[wave][j0 + r].a;
+                    const float dy = (ry0 + (float)y) - a.y;
+                    float S[NG];
+#pragma unroll
+                    for (int k = 0; k < NG; ++k) S[k] = 0.f;
+#pragma unroll
+                    for (int x = 0; x < 8; ++x) {
+                        const float2 m = s_m[wave][r][8 * y + x];
+                        const float dx = (rx0 + (float)x) - a.x;
+                        const float wdx = m.x * dx, wdy = m.x * dy;
+                        S[0] += m.x;
+                        S[1] += wdx;
+                        S[2] += wdy;
+                        S[3] = fmaf(wdx, dx, S[3]);
+                        S[4] = fmaf(wdx, dy, S[4]);
+                        S[5] = fmaf(wdy, dy, S[5]);
+                        S[6] = fmaf(grow0[x], m.y, S[6]);
+                        S[7] = fmaf(grow1[x], m.y, S[7]);
+                        S[8] = fmaf(grow2[x], m.y, S[8]);
+                    }
+#pragma unroll
+                    for (int k = 0; k < NG; ++k) S[k] = octet_sum(S[k]);
+                    if (y == 0 && j0 + r < cnt) {
+                        const int q = (int)(__float_as_uint(s_rec[wave][j0 + r].b.w) - (uint32_t)p0);
+#pragma unroll
+                        for (int k = 0; k < NG; ++k) atomicAdd(&s_grad[k][q], S[k]);
                     }
                 }
+                wave_lds_sync();  // the next group rewrites the wave's LDS block
             }
         }
         __syncthreads();
