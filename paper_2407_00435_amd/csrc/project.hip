@@ -273,15 +273,43 @@ k_project_bwd(const float *__restrict__ means, const float *__restrict__ log_sca
     for (int k = 0; k < K * 3; ++k) gsh[k] = 0.f;
     float glogit = 0.f;
 
+    // the SH coefficients are complete before the view loop: their waits
+    // would otherwise sit inside it and also wait for the next view's loads
+#pragma unroll
+    for (int k = 0; k < K * 3; ++k) __asm__ volatile("" ::"v"(coef[k]));
+    // the view's 48-byte gradient record as three vector loads, the next
+    // view's issued before this view's work (one thread walks all views)
+    const float4 *g4 = reinterpret_cast<const float4 *>(grads);
+    float4 ga = make_float4(0.f, 0.f, 0.f, 0.f), gb = ga, gc3 = ga;
+    if (V > 0) {
+        ga = g4[3 * (int64_t)i];
+        gb = g4[3 * (int64_t)i + 1];
+        gc3 = g4[3 * (int64_t)i + 2];
+    }
+    // (and so is the first view's record, for the same reason)
+    __asm__ volatile("" ::"v"(ga.x), "v"(ga.y), "v"(ga.z), "v"(ga.w), "v"(gb.x), "v"(gb.y), "v"(gb.z), "v"(gb.w),
+                     "v"(gc3.x));
     for (int v = 0; v < V; ++v) {
         int64_t e = (int64_t)v * n + i;
-        // splats culled by the forward carry no gradient: the zero test
-        // below skips them without reading the forward's records
-        const gs_splat_grad &g = grads[e];
-        // a visible splat that no pixel blended (occluded, or outside every
-        // tile's stop point) has an all-zero gradient: nothing to push back
-        bool zero = g.mean_x == 0.f && g.mean_y == 0.f && g.conic_a == 0.f && g.conic_b == 0.f &&
-                    g.conic_c == 0.f && g.opacity == 0.f && g.r == 0.f && g.g == 0.f && g.b == 0.f;
+        gs_splat_grad g;
+        g.mean_x = ga.x; g.mean_y = ga.y; g.conic_a = ga.z; g.conic_b = ga.w;
+        g.conic_c = gb.x; g.opacity = gb.y; g.r = gb.z; g.g = gb.w;
+        g.b = gc3.x;
+        if (v + 1 < V) {
+            const int64_t en = e + n;
+            ga = g4[3 * en];
+            gb = g4[3 * en + 1];
+            gc3 = g4[3 * en + 2];
+        }
+        // keeps the next view's loads here, ahead of this view's work (the
+        // scheduler would otherwise sink them to the end of the iteration)
+        __asm__ volatile("" ::: "memory");
+        // splats culled by the forward carry no gradient, and a visible
+        // splat that no pixel blended (occluded, or outside every tile's
+        // stop point) has an all-zero gradient: nothing to push back (the
+        // forward's records are not read)
+        bool zero = (g.mean_x == 0.f) & (g.mean_y == 0.f) & (g.conic_a == 0.f) & (g.conic_b == 0.f) &
+                    (g.conic_c == 0.f) & (g.opacity == 0.f) & (g.r == 0.f) & (g.g == 0.f) & (g.b == 0.f);
         float4 lg[ML];
 #pragma unroll
         for (int t = 0; t < ML; ++t) {
