@@ -107,10 +107,33 @@ k_project(const float *__restrict__ means, const float *__restrict__ log_scales,
     load_sh<DEG>(sh, i, coef);
     float lvl_op[4], lvl_dcv[4][3];
     if (LEVELS) {
-        for (int t = 0; t < L; ++t) {
-            lvl_op[t] = lvl_logits ? sigmoidf(lvl_logits[(int64_t)t * n + i]) : opacity;
-            for (int ch = 0; ch < 3; ++ch)
-                lvl_dcv[t][ch] = lvl_dc ? lvl_dc[((int64_t)t * n + i) * 3 + ch] : coef[ch];
+        // every level's loads first, unconditional (levels past L read level
+        // L - 1, which is in bounds) so that they are in flight together,
+        // then their use
+        float raw[4], rdc[4][3];
+        const bool hl = lvl_logits != nullptr, hd = lvl_dc != nullptr;
+        if (hl && hd) {
+#pragma unroll
+            for (int t = 0; t < 4; ++t) {
+                const int64_t tl = (int64_t)min(t, L - 1) * n + i;
+                raw[t] = lvl_logits[tl];
+#pragma unroll
+                for (int ch = 0; ch < 3; ++ch) rdc[t][ch] = lvl_dc[tl * 3 + ch];
+            }
+        } else {
+#pragma unroll
+            for (int t = 0; t < 4; ++t) {
+                const int64_t tl = (int64_t)min(t, L - 1) * n + i;
+                raw[t] = hl ? lvl_logits[tl] : 0.f;
+#pragma unroll
+                for (int ch = 0; ch < 3; ++ch) rdc[t][ch] = hd ? lvl_dc[tl * 3 + ch] : 0.f;
+            }
+        }
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+            lvl_op[t] = (hl && t < L) ? sigmoidf(raw[t]) : opacity;
+#pragma unroll
+            for (int ch = 0; ch < 3; ++ch) lvl_dcv[t][ch] = (hd && t < L) ? rdc[t][ch] : coef[ch];
         }
     }
     for (int v = 0; v < V; ++v) {
@@ -473,10 +496,16 @@ k_project_bwd(const float *__restrict__ means, const float *__restrict__ log_sca
         }
     // M = Rq diag(s)
     float dR[9];
+    float ols[3] = {0.f, 0.f, 0.f};
+    if (acc) {
+        ols[0] = g_ls[3 * (int64_t)i];
+        ols[1] = g_ls[3 * (int64_t)i + 1];
+        ols[2] = g_ls[3 * (int64_t)i + 2];
+    }
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
         float ds = dM[k] * Rq.m[k] + dM[3 + k] * Rq.m[3 + k] + dM[6 + k] * Rq.m[6 + k];
-        g_ls[3 * (int64_t)i + k] = (acc ? g_ls[3 * (int64_t)i + k] : 0.f) + ds * s[k];
+        g_ls[3 * (int64_t)i + k] = ols[k] + ds * s[k];
 #pragma unroll
         for (int r = 0; r < 3; ++r) dR[r * 3 + k] = dM[r * 3 + k] * s[k];
     }
@@ -491,12 +520,17 @@ k_project_bwd(const float *__restrict__ means, const float *__restrict__ log_sca
     float pr = w * dw + x * dxq + y * dyq + z * dzq;
     float4 gq = make_float4((dw - w * pr) * qn_inv, (dxq - x * pr) * qn_inv, (dyq - y * pr) * qn_inv,
                             (dzq - z * pr) * qn_inv);
+    // accumulating: the old values are read in batches (one wait per batch,
+    // not one round trip per value)
     if (acc) {
         const float4 o = reinterpret_cast<const float4 *>(g_q)[i];
+        const float om0 = g_means[3 * (int64_t)i], om1 = g_means[3 * (int64_t)i + 1];
+        const float om2 = g_means[3 * (int64_t)i + 2], ol = g_logit[i];
         gq = make_float4(o.x + gq.x, o.y + gq.y, o.z + gq.z, o.w + gq.w);
-#pragma unroll
-        for (int k = 0; k < 3; ++k) gm[k] += g_means[3 * (int64_t)i + k];
-        glogit += g_logit[i];
+        gm[0] += om0;
+        gm[1] += om1;
+        gm[2] += om2;
+        glogit += ol;
     }
     reinterpret_cast<float4 *>(g_q)[i] = gq;
     g_means[3 * (int64_t)i] = gm[0];
@@ -506,14 +540,20 @@ k_project_bwd(const float *__restrict__ means, const float *__restrict__ log_sca
     float *gs_out = g_sh + (int64_t)i * K * 3;
     if constexpr ((K * 3) % 4 == 0) {
         float4 *p4 = reinterpret_cast<float4 *>(gs_out);
+        constexpr int N4 = K * 3 / 4;
 #pragma unroll
-        for (int k = 0; k < K * 3 / 4; ++k) {
-            float4 v = make_float4(gsh[4 * k], gsh[4 * k + 1], gsh[4 * k + 2], gsh[4 * k + 3]);
-            if (acc) {
-                const float4 o = p4[k];
-                v = make_float4(o.x + v.x, o.y + v.y, o.z + v.z, o.w + v.w);
+        for (int k0 = 0; k0 < N4; k0 += 4) {
+            float4 o[4];
+#pragma unroll
+            for (int j = 0; j < 4; ++j)
+                o[j] = (acc && k0 + j < N4) ? p4[k0 + j] : make_float4(0.f, 0.f, 0.f, 0.f);
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const int k = k0 + j;
+                if (k < N4)
+                    p4[k] = make_float4(o[j].x + gsh[4 * k], o[j].y + gsh[4 * k + 1], o[j].z + gsh[4 * k + 2],
+                                        o[j].w + gsh[4 * k + 3]);
             }
-            p4[k] = v;
         }
     } else {
 #pragma unroll
