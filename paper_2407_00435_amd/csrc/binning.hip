@@ -193,6 +193,7 @@ __device__ __forceinline__ uint32_t sat_rect(const uint32_t *__restrict__ s, int
 //    keeps (the kept tiles and their row-major order are unchanged).
 constexpr int COUNT_THREADS = 1024;
 constexpr int COUNT_ITEMS = SCAN_THREADS * SCAN_ITEMS / COUNT_THREADS;
+template <bool FILT>
 __global__ void __launch_bounds__(COUNT_THREADS)
 k_count(const gs_splat *__restrict__ splats, int n, const gs_camera *__restrict__ cams, int V, int T,
         const int64_t *__restrict__ vtab, const uint32_t *__restrict__ sat, const int32_t *__restrict__ bbox, int L, int64_t n_tiles,
@@ -204,15 +205,73 @@ k_count(const gs_splat *__restrict__ splats, int n, const gs_camera *__restrict_
     __syncthreads();
     const int64_t E = (int64_t)V * n;
     const int64_t base = (int64_t)blockIdx.x * (COUNT_THREADS * COUNT_ITEMS);
-    // the splat fields of every item first (mean, radius, depth), then the work
+    // Three rounds of loads over all items, each round issued before any of
+    // its values is used: (1) splat fields, quality bound, view sizes; (2)
+    // the level's bounding box; (3) the four summed-area corners.  Indices
+    // are clamped in bounds (items past E read entry 0, empty rectangles
+    // read corner (0, 0)) and the results selected afterwards, so no load
+    // sits behind a branch.
     float4 a[COUNT_ITEMS], c[COUNT_ITEMS];
+    int vq[COUNT_ITEMS], iq[COUNT_ITEMS], mq[COUNT_ITEMS], Wq[COUNT_ITEMS], Hq[COUNT_ITEMS];
+    int64_t toffq[COUNT_ITEMS];
+    int txq[COUNT_ITEMS];
 #pragma unroll
     for (int j = 0; j < COUNT_ITEMS; ++j) {
         const int64_t e = base + (int64_t)j * COUNT_THREADS + threadIdx.x;
-        if (e < E) {
-            const float4 *s4 = reinterpret_cast<const float4 *>(splats + e);
-            a[j] = s4[0];
-            c[j] = s4[2];
+        const int64_t ec = e < E ? e : 0;
+        const float4 *s4 = reinterpret_cast<const float4 *>(splats + ec);
+        a[j] = s4[0];
+        c[j] = s4[2];
+        vq[j] = (int)(ec / n);
+        iq[j] = (int)(ec - (int64_t)vq[j] * n);
+        Wq[j] = cams[vq[j]].width;
+        Hq[j] = cams[vq[j]].height;
+        mq[j] = FILT ? (int)qbound[iq[j]] : 255;
+        toffq[j] = FILT ? vtab[2 * vq[j]] : 0;
+        txq[j] = FILT ? (int)vtab[2 * vq[j] + 1] : 0;
+    }
+    TileRect r[COUNT_ITEMS];
+    bool has[COUNT_ITEMS];
+    int mlq[COUNT_ITEMS];
+    int4 bb[COUNT_ITEMS];
+#pragma unroll
+    for (int j = 0; j < COUNT_ITEMS; ++j) {
+        const int64_t e = base + (int64_t)j * COUNT_THREADS + threadIdx.x;
+        has[j] = e < E && tile_rect(a[j].x, a[j].y, __float_as_int(c[j].z), Wq[j], Hq[j], T, r[j]);
+        if (!has[j]) r[j].tx0 = r[j].tx1 = r[j].ty0 = r[j].ty1 = 0;
+        mlq[j] = mq[j] < 1 ? 1 : (mq[j] < L ? mq[j] : L);
+        if (FILT) bb[j] = reinterpret_cast<const int4 *>(bbox)[(int64_t)vq[j] * L + mlq[j] - 1];
+    }
+    uint32_t cnt[COUNT_ITEMS];
+    if (!FILT) {
+#pragma unroll
+        for (int j = 0; j < COUNT_ITEMS; ++j)
+            cnt[j] = has[j] ? (uint32_t)(r[j].tx1 - r[j].tx0 + 1) * (uint32_t)(r[j].ty1 - r[j].ty0 + 1) : 0u;
+    } else {
+        // kept tiles lie in the level's bounding box: clip to it
+        bool ne[COUNT_ITEMS];
+        uint32_t s11[COUNT_ITEMS], s01[COUNT_ITEMS], s10[COUNT_ITEMS], s00[COUNT_ITEMS];
+#pragma unroll
+        for (int j = 0; j < COUNT_ITEMS; ++j) {
+            r[j].tx0 = r[j].tx0 > bb[j].x ? r[j].tx0 : bb[j].x;
+            r[j].ty0 = r[j].ty0 > bb[j].y ? r[j].ty0 : bb[j].y;
+            r[j].tx1 = r[j].tx1 < bb[j].z ? r[j].tx1 : bb[j].z;
+            r[j].ty1 = r[j].ty1 < bb[j].w ? r[j].ty1 : bb[j].w;
+            ne[j] = has[j] && mq[j] >= 1 && r[j].tx0 <= r[j].tx1 && r[j].ty0 <= r[j].ty1;
+            const uint32_t *sp = sat + (int64_t)(mlq[j] - 1) * n_tiles + toffq[j];
+            const int x1 = ne[j] ? r[j].tx1 : 0, y1 = ne[j] ? r[j].ty1 : 0;
+            const int x0 = ne[j] && r[j].tx0 > 0 ? r[j].tx0 - 1 : 0;
+            const int y0 = ne[j] && r[j].ty0 > 0 ? r[j].ty0 - 1 : 0;
+            s11[j] = sp[(int64_t)y1 * txq[j] + x1];
+            s01[j] = sp[(int64_t)y1 * txq[j] + x0];
+            s10[j] = sp[(int64_t)y0 * txq[j] + x1];
+            s00[j] = sp[(int64_t)y0 * txq[j] + x0];
+        }
+#pragma unroll
+        for (int j = 0; j < COUNT_ITEMS; ++j) {
+            // sat_rect: corners left of column 0 or above row 0 count zero
+            const bool lx = r[j].tx0 > 0, ly = r[j].ty0 > 0;
+            cnt[j] = ne[j] ? s11[j] - (lx ? s01[j] : 0u) - (ly ? s10[j] : 0u) + (lx && ly ? s00[j] : 0u) : 0u;
         }
     }
     uint32_t vis = 0;
@@ -220,39 +279,14 @@ k_count(const gs_splat *__restrict__ splats, int n, const gs_camera *__restrict_
     for (int j = 0; j < COUNT_ITEMS; ++j) {
         const int64_t e = base + (int64_t)j * COUNT_THREADS + threadIdx.x;
         if (e >= E) break;
-        const int v = (int)(e / n);
-        const int i = (int)(e - (int64_t)v * n);
-        const int W = cams[v].width, H = cams[v].height;
-        TileRect r;
-        uint32_t cnt = 0;
-        int m = 255;
-        if (tile_rect(a[j].x, a[j].y, __float_as_int(c[j].z), W, H, T, r)) {
-            if (!sat) {
-                cnt = (uint32_t)(r.tx1 - r.tx0 + 1) * (uint32_t)(r.ty1 - r.ty0 + 1);
-            } else {
-                m = qbound[i];
-                if (m >= 1) {
-                    // kept tiles lie in the level's bounding box: clip to it
-                    const int ml = m < L ? m : L;
-                    const int4 b = reinterpret_cast<const int4 *>(bbox)[(int64_t)v * L + ml - 1];
-                    r.tx0 = r.tx0 > b.x ? r.tx0 : b.x;
-                    r.ty0 = r.ty0 > b.y ? r.ty0 : b.y;
-                    r.tx1 = r.tx1 < b.z ? r.tx1 : b.z;
-                    r.ty1 = r.ty1 < b.w ? r.ty1 : b.w;
-                    if (r.tx0 <= r.tx1 && r.ty0 <= r.ty1) {
-                        const uint32_t *s = sat + (int64_t)(ml - 1) * n_tiles + vtab[2 * v];
-                        cnt = sat_rect(s, (int)vtab[2 * v + 1], r.tx0, r.tx1, r.ty0, r.ty1);
-                    }
-                }
-            }
-        }
-        hits[e] = cnt;
-        if (cnt)
-            rec[e] = make_uint4((uint32_t)r.tx0 | ((uint32_t)r.ty0 << 16), (uint32_t)r.tx1 | ((uint32_t)r.ty1 << 16),
-                                cnt, (uint32_t)m);
-        if (hits_out) hits_out[e] = cnt;
+        hits[e] = cnt[j];
+        if (cnt[j])
+            rec[e] = make_uint4((uint32_t)r[j].tx0 | ((uint32_t)r[j].ty0 << 16),
+                                (uint32_t)r[j].tx1 | ((uint32_t)r[j].ty1 << 16), cnt[j],
+                                (uint32_t)(FILT ? mq[j] : 255));
+        if (hits_out) hits_out[e] = cnt[j];
         dkey_all[e] = __float_as_uint(c[j].y);
-        vis += cnt > 0;
+        vis += cnt[j] > 0;
     }
     for (int off = 32; off > 0; off >>= 1) vis += __shfl_xor(vis, off);
     if ((threadIdx.x & 63) == 0) atomicAdd(&s_cnt, vis);
@@ -1113,8 +1147,14 @@ hipError_t launch_bin_sort(const gs_splat *splats, int n, const gs_camera *cams_
                            L, tile_level, bs.st_cls);
     const int64_t nb = (E + SCAN_THREADS * SCAN_ITEMS - 1) / (SCAN_THREADS * SCAN_ITEMS);
     // 1-2: counts, then stable compaction of entries with keys (depth digits counted)
-    hipLaunchKernelGGL(k_count, dim3((unsigned)nb), dim3(COUNT_THREADS), 0, st, splats, n, cams_dev, V, T, bs.vtab,
-                       sat, bs.bbox, L, n_tiles, qbound, bs.hits, bs.rec, bs.dkey_b, hits_out, bs.block_vis);
+    if (filt)
+        hipLaunchKernelGGL(k_count<true>, dim3((unsigned)nb), dim3(COUNT_THREADS), 0, st, splats, n, cams_dev, V, T,
+                           bs.vtab, sat, bs.bbox, L, n_tiles, qbound, bs.hits, bs.rec, bs.dkey_b, hits_out,
+                           bs.block_vis);
+    else
+        hipLaunchKernelGGL(k_count<false>, dim3((unsigned)nb), dim3(COUNT_THREADS), 0, st, splats, n, cams_dev, V, T,
+                           bs.vtab, sat, bs.bbox, L, n_tiles, qbound, bs.hits, bs.rec, bs.dkey_b, hits_out,
+                           bs.block_vis);
     hipLaunchKernelGGL(k_scan_blocks, dim3(1), dim3(1024), 0, st, bs.block_sums, bs.block_vis, nb, bs.counts);
     if ((err = radix_sort_prepare(bs.rs, bs.counts, (uint64_t)E, 4, 32, st)) != hipSuccess) return err;
     hipLaunchKernelGGL(k_compact, dim3((unsigned)nb), dim3(COUNT_THREADS), 0, st, bs.hits, bs.dkey_b, E,
