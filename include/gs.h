@@ -389,6 +389,11 @@ int gs_graph_destroy(gs_graph *graph);
  *                   (chunks whose pixels reach the stop threshold are
  *                   composited again from the running state, so the result
  *                   is the sequential one up to float reassociation).
+ *   "coarse_packed": 1 (default): coarse (super-tile, entry) pairs carry
+ *                   their tile rectangle in the sort key above the
+ *                   super-tile id when the ids fit in 17 bits; 0: always in
+ *                   an 8-byte value (the form used above 2^17 super-tiles).
+ *                   The keys and ranges are identical either way.
  * Workspace sizes returned by gs_workspace_bytes / gs_render_workspace_bytes
  * depend on these settings: size workspaces after setting them.
  * The GS_RADIX_PART environment variable sets the same default. */

@@ -711,6 +711,11 @@ int gs_set_tuning(const char *name, int64_t value)
         g_raster_beta = (uint32_t)value;
         return ok();
     }
+    if (k == "coarse_packed") {
+        if (value != 0 && value != 1) return fail(GS_ERR_INVALID, "coarse_packed must be 0 or 1");
+        bin_set_coarse_packed(value != 0);
+        return ok();
+    }
     if (k == "radix_part") {
         if (!radix_set_part((int)value))
             return fail(GS_ERR_INVALID, "radix_part must be 4096, 8192 or 16384");

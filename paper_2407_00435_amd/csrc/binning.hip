@@ -1106,6 +1106,9 @@ inline int grid_for(uint64_t work, int per_block, int cap_blocks)
 
 }  // namespace
 
+static bool g_coarse_packed = true;
+void bin_set_coarse_packed(bool packed) { g_coarse_packed = packed; }
+
 hipError_t launch_fill_u32(uint32_t *p, uint32_t value, uint64_t count, hipStream_t st)
 {
     if (count == 0) return hipSuccess;
@@ -1172,7 +1175,7 @@ hipError_t launch_bin_sort(const gs_splat *splats, int n, const gs_camera *cams_
     int st_bits = 1;
     while ((int64_t(1) << st_bits) < n_st) ++st_bits;
     // the pair's info rides in the sort key when the super-tile ids leave room
-    const bool packed = st_bits <= ST_ID_BITS;
+    const bool packed = g_coarse_packed && st_bits <= ST_ID_BITS;
     const bool even = radix_pass_count(st_bits, packed ? 4 : 8) % 2 == 0;
     if (packed) {
         hipLaunchKernelGGL(k_coarse_emit<true>, dim3((unsigned)nb), dim3(GATHER_THREADS), 0, st, bs.rec_s, bs.cc_s,

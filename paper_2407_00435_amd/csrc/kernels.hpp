@@ -103,6 +103,9 @@ struct BinScratch {
     int32_t *bbox;                                // [V][4][4] bounding box of each level's kept tiles
     RadixScratch rs;
 };
+// coarse pairs with the rectangle in the sort key where the ids leave room
+// (default) or always with an 8-byte value
+void bin_set_coarse_packed(bool packed);
 hipError_t launch_bin_sort(const gs_splat *splats, int n, const gs_camera *cams_dev,
                            const gs_camera *cams_host, int V, int64_t n_tiles, int T,
                            const uint8_t *tile_level, const uint8_t *qbound, int n_levels,

@@ -63,6 +63,8 @@ def test_version_and_host_errors(L):
     assert lib.gs_sort_pairs(None, None, None, None, 10, 40, None, 0, None) == L.GS_ERR_INVALID
     assert lib.gs_set_tuning(b"radix_part", 1000) == L.GS_ERR_INVALID
     assert lib.gs_set_tuning(b"no_such_knob", 1) == L.GS_ERR_INVALID
+    assert lib.gs_set_tuning(b"coarse_packed", 2) == L.GS_ERR_INVALID
+    assert lib.gs_set_tuning(b"coarse_packed", 1) == 0
 
 
 def test_package_fails_loudly_without_library(tmp_path, monkeypatch):

@@ -94,6 +94,45 @@ def test_binning_bit_exact(tile):
     np.testing.assert_array_equal(out["hits"].cpu().numpy().view(np.uint32), ref["hits"])
 
 
+# coarse pairs carry their rectangle in the sort key (ids below 2^17) or in an
+# 8-byte value (the form used above 2^17 super-tiles); both give the oracle's
+# keys, with and without the level filter (whose bound rides in the pair)
+@pytest.mark.parametrize("packed", [1, 0])
+@pytest.mark.parametrize("filtered", [False, True])
+def test_binning_coarse_pair_forms(packed, filtered):
+    g = gs()
+    tile = 16
+    sc = scene_small(seed=53, n=4000, fr=4)
+    cams = [scenegen.pinhole(300, 170, scenegen.FR_FOV_DEG, t=(0.03, 0.0, 2.0)),
+            scenegen.pinhole(280, 190, scenegen.FR_FOV_DEG, t=(-0.03, 0.0, 2.0))]
+    say("coarse pairs", packed, filtered)
+    C = g.Cameras(cams)
+    S = g.SceneTensors(sc)
+    splats = g.gs_project(S, C, tile)
+    kw = {}
+    tl = None
+    if filtered:
+        fov = [scenegen.Fovea(150.0, 85.0)] * 2
+        t = g.gs_fovea_prep(C, fov, tile, 4)
+        kw = dict(tile_level=t["tile_level"], qbound=S.t["qbound"])
+        tl = t["tile_level"][:, 0].cpu().numpy()
+    g.gs_set_tuning("coarse_packed", packed)
+    try:
+        bs = g.gs_bin_sort(splats, sc.n, C, tile, want_keys=True, want_hits=True, **kw)
+        torch.cuda.synchronize()
+    finally:
+        g.gs_set_tuning("coarse_packed", 1)
+    sp = splat_np(splats)
+    ref = oracle.bin_f32(sp["mean2d"], sp["radius"], sp["depth"], [c.width for c in cams],
+                         [c.height for c in cams], tile,
+                         **(dict(tile_level_lo=tl, qbound=sc.qbound) if filtered else {}))
+    nk = int(bs["num_keys"].item())
+    assert nk == ref["num_keys"] > 1000
+    np.testing.assert_array_equal(bs["keys"].cpu().numpy()[:nk].view(np.uint64), ref["keys"])
+    np.testing.assert_array_equal(bs["vals"].cpu().numpy()[:nk].view(np.uint32), ref["vals"])
+    np.testing.assert_array_equal(bs["ranges"].cpu().numpy().view(np.uint32), ref["ranges"])
+
+
 def _raster_case(g, sc, cams, tile, bg=(0.0, 0.0, 0.0), dominated=True):
     C = g.Cameras(cams)
     S = g.SceneTensors(sc)
