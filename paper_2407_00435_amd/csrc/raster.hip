@@ -877,7 +877,10 @@ k_raster_bwd(const gs_splat *__restrict__ splats, int n, const gs_camera *__rest
     constexpr int SUB = T / 8;
     constexpr int NG = 9;  // sums of w, w dx, w dy, w dx^2, w dx dy, w dy^2, colour r, g, b
     __shared__ BwdRec s_rec[WAVES][64];
-    __shared__ float2 s_m[WAVES][8][64];  // (w, alpha T) of 8 records x 64 pixels per wave
+    // (w, alpha T) of 8 records x 64 pixels per wave; record r's row is
+    // rotated by r pairs so that the regrouped reads (lanes 8 r + y, column
+    // x) of the 8 records fall in different LDS banks
+    __shared__ float2 s_m[WAVES][8][64];
     __shared__ float s_grad[NG][64];
     __shared__ uint32_t s_id[64];
     __shared__ uint32_t s_maxnc;
@@ -989,7 +992,7 @@ k_raster_bwd(const gs_splat *__restrict__ splats, int n, const gs_camera *__rest
                     gB = fmaf(gc, wT, gB);
                     Tr = contrib ? Tn : Tr;
                     const float w = (contrib && araw <= GS_ALPHA_MAX) ? alpha * dLda : 0.f;
-                    s_m[wave][r][lane] = make_float2(w, wT);
+                    s_m[wave][r][(lane + r) & 63] = make_float2(w, wT);
                     any = any || contrib;
                 }
                 if (ballot64(any) == 0) continue;  // none of the 8 reaches the wave's pixels
@@ -1008,7 +1011,7 @@ k_raster_bwd(const gs_splat *__restrict__ splats, int n, const gs_camera *__rest
                     for (int k = 0; k < NG; ++k) S[k] = 0.f;
 #pragma unroll
                     for (int x = 0; x < 8; ++x) {
-                        const float2 m = s_m[wave][r][8 * y + x];
+                        const float2 m = s_m[wave][r][(8 * y + x + r) & 63];
                         const float dx = (rx0 + (float)x) - a.x;
                         const float wdx = m.x * dx, wdy = m.x * dy;
                         S[0] += m.x;
