@@ -118,8 +118,10 @@ class Foveated:
 
     def project(self):
         L, B = self.g.lib(), self.g.binding
+        # the constructor's first projection runs before the stream is set
+        st = getattr(self, "stream", None) or B._stream()
         B._check(L.gs_project(ctypes.byref(self.scene_struct), self.C.hp, self.C.dp, self.C.n, self.tile,
-                              B._ptr(self.splats), B._ptr(self.lvl), B._stream()))
+                              B._ptr(self.splats), B._ptr(self.lvl), st))
 
     def binsort(self):
         L, B, g = self.g.lib(), self.g.binding, self
@@ -329,6 +331,37 @@ def cpu_baseline(fr, wl, n_gauss_sample=12000, px_sample=(3000, 9000), threads=1
                 frame_s=frame)
 
 
+def pipelined_frames(g, wl, tile, frames=40, warmup=6):
+    """Throughput of consecutive stereo frames issued alternately to two
+    streams with two buffer sets: a frame's binning overlaps the previous
+    frame's compositing (a GPU analogue of the paper's incremental
+    pipelining).  Every frame still runs all four stages; per-frame latency
+    is the sequential frame time, not this figure."""
+    import torch
+    sts = [torch.cuda.Stream(), torch.cuda.Stream()]
+    frs = []
+    for st in sts:
+        with torch.cuda.stream(st):
+            frs.append(Foveated(g, wl, tile))
+    torch.cuda.synchronize()
+
+    def frame(f):
+        for s in f.STAGES:
+            getattr(f, s)()
+
+    for k in range(warmup):
+        frame(frs[k % 2])
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(frames):
+        frame(frs[k % 2])
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / frames
+    same = bool(torch.equal(frs[0].image, frs[1].image))
+    return {"streams": 2, "frames": frames, "ms_per_frame": dt * 1e3, "fps": 1.0 / dt,
+            "mpix_s": frs[0].n_px / dt / 1e6, "frames_identical": same}
+
+
 def hbm_bandwidth(g, fr, stage_ms, reps=10):
     """Achieved HBM bandwidth of the projection and of the radix sort, against a
     plain device copy on the same GPU (the achievable reference) and the
@@ -457,6 +490,8 @@ def main():
     if not args.no_extras:
         log("HBM bandwidth of projection and sort ...")
         line["hbm"] = hbm_bandwidth(g, fr, stage_ms)
+        log("consecutive frames on two streams ...")
+        line["pipelined_frames"] = pipelined_frames(g, wl, args.tile)
         log("plain forward, 500k Gaussians, 1280x720 ...")
         line["plain_fwd_720p_500k"] = plain_fwd_rate(g, scenegen.config2(), 20, 3)
         log("forward+backward, 1M Gaussians, 1280x720 ...")

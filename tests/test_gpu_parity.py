@@ -315,6 +315,46 @@ def test_render_foveated_one_call_equals_stages():
     assert torch.equal(img, img2)
 
 
+def test_concurrent_streams_give_the_sequential_frames():
+    """Two stereo frames (different gazes) rendered at the same time on two
+    streams, each with its own workspace and image, equal the same frames
+    rendered one after the other: no entry point shares device state between
+    calls (the frame pipelining of bench.py relies on this)."""
+    g = gs()
+    sc = scene_small(seed=61, n=6000, fr=4)
+    cams = [scenegen.pinhole(320, 180, scenegen.FR_FOV_DEG, t=(0.03, 0.0, 2.0)),
+            scenegen.pinhole(320, 180, scenegen.FR_FOV_DEG, t=(-0.03, 0.0, 2.0))]
+    gazes = [[scenegen.Fovea(150.0, 90.0)] * 2, [scenegen.Fovea(60.0, 120.0)] * 2]
+    say("two streams")
+    C = g.Cameras(cams)
+    S = g.SceneTensors(sc)
+    cap = 400_000
+    refs = []
+    for fov in gazes:
+        img, num, _ = g.gs_render_foveated(S, C, fov, 16, key_capacity=cap)
+        torch.cuda.synchronize()
+        assert 0 < int(num.item()) <= cap
+        refs.append(img.clone())
+    assert not torch.equal(refs[0], refs[1])
+    streams = [torch.cuda.Stream(), torch.cuda.Stream()]
+    imgs = [torch.empty_like(refs[0]), torch.empty_like(refs[1])]
+    wss = [None, None]
+    for rep in range(3):
+        cur = torch.cuda.current_stream()
+        for k, st in enumerate(streams):
+            st.wait_stream(cur)
+            with torch.cuda.stream(st):
+                _, _, wss[k] = g.gs_render_foveated(S, C, gazes[k], 16, key_capacity=cap, image=imgs[k],
+                                                    workspace=wss[k])
+        for st in streams:
+            cur.wait_stream(st)
+        torch.cuda.synchronize()
+        assert torch.equal(imgs[0], refs[0]) and torch.equal(imgs[1], refs[1]), rep
+        imgs[0].fill_(float("nan"))
+        imgs[1].fill_(float("nan"))
+        torch.cuda.synchronize()
+
+
 def test_backward_stagewise_matches_oracle():
     g = gs()
     sc = scene_small(seed=61, n=1500)
