@@ -125,6 +125,9 @@ class BatchedStep:
                     self.grads[k] = torch.empty_like(scene.t[k]) if scene.t.get(k) is not None else None
         else:
             self.eye_train = False
+        # eyes rendered forward only depend on the scene, not on the views'
+        # forward and reverse: they run on a second stream beside them
+        self.eye_stream = (torch.cuda.Stream(device=dev) if self.eye_groups and not self.eye_train else None)
         self.graph = None
 
     def _enqueue(self):
@@ -169,6 +172,18 @@ class BatchedStep:
                                                  P(gr.get("lvl_opacity_logits")), P(gr.get("lvl_sh_dc")),
                                                  0 if first else 1, st))
                 first = False
+        if self.eye_stream is not None:
+            # fork: the eyes' forward renders beside the views' work
+            es = self.eye_stream
+            es.wait_stream(self.stream)
+            est = ctypes.c_void_p(es.cuda_stream)
+            for k, e in enumerate(self.eye_groups):
+                o, npx = e["px_off"], e["n_px"]
+                B._check(L.gs_render_foveated(ctypes.byref(self.eye_struct), e["C"].hp, e["C"].dp,
+                                              ctypes.cast(e["fov"], B._PF), e["C"].n, g.tile,
+                                              ctypes.cast(g.bg, B._VP), P(self.eye_image[3 * o:3 * (o + npx)]),
+                                              e["cap"], P(self.eye_num[k:k + 1]), self.eye_ws[1], self.eye_ws[2],
+                                              est))
         for k, grp in enumerate(self.groups):
             C, o, npx = grp["C"], grp["px_off"], grp["n_px"]
             img = self.image[3 * o:3 * (o + npx)]
@@ -189,14 +204,9 @@ class BatchedStep:
                                       P(g.sgrads), P(gr["means"]), P(gr["log_scales"]), P(gr["quats"]),
                                       P(gr["opacity_logits"]), P(gr["sh"]), 0 if first else 1, st))
             first = False
-        if not self.eye_train:
-            for k, e in enumerate(self.eye_groups):
-                o, npx = e["px_off"], e["n_px"]
-                B._check(L.gs_render_foveated(ctypes.byref(self.eye_struct), e["C"].hp, e["C"].dp,
-                                              ctypes.cast(e["fov"], B._PF), e["C"].n, g.tile,
-                                              ctypes.cast(g.bg, B._VP), P(self.eye_image[3 * o:3 * (o + npx)]),
-                                              e["cap"], P(self.eye_num[k:k + 1]), self.eye_ws[1], self.eye_ws[2],
-                                              st))
+        if self.eye_stream is not None:
+            # join the eyes' branch
+            self.stream.wait_stream(self.eye_stream)
 
     def step(self):
         """Run one step eagerly on this object's stream."""
