@@ -251,7 +251,7 @@ def batched_vs_plain(g, steps=3, log=None, fixed=None, plain_too=True):
         g.gs_set_tuning("raster_queue", best.get("raster_queue", 0))
     else:
         best, tried = autotune.tune(S, cams, target, eyes, fov, reps=2, log=log)
-    step = BatchedStep(S, cams, target, best["tile"], best["batch_views"], eyes, fov)
+    step = BatchedStep(S, cams, target, best["tile"], best["batch_views"], eyes, fov, lanes=best.get("lanes", 1))
     ms_b = autotune.time_step(step, steps)
     keys_b = int(step.num_keys.sum().item())
     ok_b = step.keys_ok()
@@ -425,8 +425,9 @@ def main():
     ap.add_argument("--no-extras", action="store_true")
     ap.add_argument("--batched-only", action="store_true",
                     help="only the batched step (3M Gaussians, 32 views + 2 eyes) at a fixed schedule: "
-                         "--tile, --batch-views, --radix-part; for profiling")
+                         "--tile, --batch-views, --lanes, --radix-part; for profiling")
     ap.add_argument("--batch-views", type=int, default=32)
+    ap.add_argument("--lanes", type=int, default=1, help="streams the sub-batches alternate over")
     ap.add_argument("--radix-part", type=int, default=16384)
     ap.add_argument("--copy-probe", action="store_true",
                     help="only run a plain 1 GiB device copy (memory-counter calibration)")
@@ -445,7 +446,8 @@ def main():
 
     if args.batched_only:
         r = batched_vs_plain(g, args.steps, log, fixed=dict(tile=args.tile, batch_views=args.batch_views,
-                                                             radix_part=args.radix_part, raster_queue=0),
+                                                             lanes=args.lanes, radix_part=args.radix_part,
+                                                             raster_queue=0),
                              plain_too=False)
         print(json.dumps(r), flush=True)
         return

@@ -1,13 +1,14 @@
 """Autotuner for the batched step: tile size, views per sub-batch, the
-sort's partition size and the compositor's scheduling (one workgroup per
-tile or the persistent work queue).
+number of streams the sub-batches alternate over, the sort's partition size
+and the compositor's scheduling (one workgroup per tile or the persistent
+work queue).
 
 Candidates are measured, not modelled: each is built (buffers, a recorded
 graph), replayed a few times on the device, and timed with events on its
 stream.  The search is coordinate descent from (tile 16, all views in one
-sub-batch, partition 8192, one workgroup per tile): first the tile size,
-then the sub-batch size at the best tile, then the partition size, then the
-persistent work-queue compositor.  A candidate that does not fit in
+sub-batch, one stream, partition 8192, one workgroup per tile): first the
+tile size, then the sub-batch size (on one and on two streams) at the best
+tile, then the partition size, then the persistent work-queue compositor.  A candidate that does not fit in
 device memory is skipped.  Results can be cached in a JSON file keyed by the
 workload's shape (point count, SH degree, view sizes, device name).
 """
@@ -65,7 +66,8 @@ def tune(scene, cams, target, eyes=None, foveae=None, tiles=(16, 32, 8), reps=3,
         B.gs_set_tuning("raster_queue", cfg["raster_queue"])
         step = None
         try:
-            step = BatchedStep(scene, cams, target, cfg["tile"], cfg["batch_views"], eyes, foveae)
+            step = BatchedStep(scene, cams, target, cfg["tile"], cfg["batch_views"], eyes, foveae,
+                               lanes=cfg.get("lanes", 1))
             ms = time_step(step, reps)
             if not step.keys_ok():
                 ms = math.inf
@@ -81,7 +83,7 @@ def tune(scene, cams, target, eyes=None, foveae=None, tiles=(16, 32, 8), reps=3,
             log(f"  {cfg}: {ms:.3f} ms")
         return ms
 
-    best = dict(tile=16, batch_views=V, radix_part=8192, raster_queue=0)
+    best = dict(tile=16, batch_views=V, lanes=1, radix_part=8192, raster_queue=0)
     best_ms = measure(best)
     for t in tiles:
         c = dict(best, tile=t)
@@ -89,10 +91,11 @@ def tune(scene, cams, target, eyes=None, foveae=None, tiles=(16, 32, 8), reps=3,
         if ms < best_ms:
             best, best_ms = c, ms
     for bv in sorted({max(1, math.ceil(V / 2)), max(1, math.ceil(V / 4))}):
-        c = dict(best, batch_views=bv)
-        ms = measure(c)
-        if ms < best_ms:
-            best, best_ms = c, ms
+        for ln in (1, 2):
+            c = dict(best, batch_views=bv, lanes=ln)
+            ms = measure(c)
+            if ms < best_ms:
+                best, best_ms = c, ms
     for key, alt in (("radix_part", 16384), ("raster_queue", 1)):
         c = dict(best, **{key: alt})
         ms = measure(c)

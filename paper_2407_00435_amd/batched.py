@@ -32,7 +32,7 @@ class BatchedStep:
     def __init__(self, scene: B.SceneTensors, cams: list, target: torch.Tensor, tile_size: int = 16,
                  batch_views: int | None = None, eyes: list | None = None, foveae: list | None = None,
                  key_margin: float = 1.05, stream: torch.cuda.Stream | None = None,
-                 eye_batch: int | None = None, eye_target: torch.Tensor | None = None):
+                 eye_batch: int | None = None, eye_target: torch.Tensor | None = None, lanes: int = 1):
         dev = scene.t["means"].device
         self.scene, self.tile = scene, tile_size
         self.stream = stream or torch.cuda.Stream(device=dev)
@@ -60,13 +60,26 @@ class BatchedStep:
         n, Vb = scene.n, bv
         f32 = dict(dtype=torch.float32, device=dev)
         i32 = dict(dtype=torch.int32, device=dev)
-        # per-sub-batch scratch, reused by every sub-batch
-        self.splats = torch.empty((Vb, n, 12), **f32)
-        self.sgrads = torch.empty((Vb, n, 12), **f32)
-        self.vals = torch.empty(cap_max, **i32)
-        self.ranges = torch.empty((tiles_max, 2), **i32)
+        # lanes: sub-batches alternate over this many streams, each with its
+        # own scratch, so that one sub-batch's binning runs beside another's
+        # compositing (the eyes' reverse, when trained, keeps one lane)
+        nl = 1 if (eyes and eye_target is not None) else max(1, min(int(lanes), len(self.groups)))
+        self.lanes = nl
+        self.lane_streams = [self.stream] + [torch.cuda.Stream(device=dev) for _ in range(nl - 1)]
+        # per-sub-batch scratch of each lane, reused by the lane's sub-batches
+        self.lane_bufs = []
+        for _ in range(nl):
+            ws_t, ws, wsn = B._ws(ws_max)
+            self.lane_bufs.append(dict(splats=torch.empty((Vb, n, 12), **f32), sgrads=torch.empty((Vb, n, 12), **f32),
+                                       vals=torch.empty(cap_max, **i32), ranges=torch.empty((tiles_max, 2), **i32),
+                                       ws_t=ws_t, ws=ws, wsn=wsn))
+        self.splats, self.sgrads = self.lane_bufs[0]["splats"], self.lane_bufs[0]["sgrads"]
+        self.vals, self.ranges = self.lane_bufs[0]["vals"], self.lane_bufs[0]["ranges"]
+        self.ws_t, self.ws, self.wsn = self.lane_bufs[0]["ws_t"], self.lane_bufs[0]["ws"], self.lane_bufs[0]["wsn"]
+        # a sub-batch's projection reverse accumulates into the parameter
+        # gradients after the previous sub-batch's (one event per sub-batch)
+        self.pb_events = [torch.cuda.Event() for _ in self.groups]
         self.num_keys = torch.zeros(len(self.groups), dtype=torch.int64, device=dev)
-        self.ws_t, self.ws, self.wsn = B._ws(ws_max)
         # whole-step outputs
         self.image = torch.empty(3 * self.n_px, **f32)
         self.final_T = torch.empty(self.n_px, **f32)
@@ -184,6 +197,13 @@ class BatchedStep:
                                               ctypes.cast(g.bg, B._VP), P(self.eye_image[3 * o:3 * (o + npx)]),
                                               e["cap"], P(self.eye_num[k:k + 1]), self.eye_ws[1], self.eye_ws[2],
                                               est))
+        multi = self.lanes > 1
+        if multi:
+            # the loss is cleared before the lanes add to it
+            if first:
+                B._check(L.gs_l1_grad(None, None, 0, ctypes.c_float(g.scale), None, P(g.loss), 1, st))
+            for ls in self.lane_streams[1:]:
+                ls.wait_stream(self.stream)
         for k, grp in enumerate(self.groups):
             C, o, npx = grp["C"], grp["px_off"], grp["n_px"]
             img = self.image[3 * o:3 * (o + npx)]
@@ -191,19 +211,30 @@ class BatchedStep:
             nc = self.n_contrib[o:o + npx]
             dL = self.dL[3 * o:3 * (o + npx)]
             tg = self.target[3 * o:3 * (o + npx)]
+            lane = k % self.lanes
+            lb = self.lane_bufs[lane]
+            lst = self.lane_streams[lane]
+            sl = ctypes.c_void_p(lst.cuda_stream)
             B._check(L.gs_render_fwd(ctypes.byref(self.scene_struct), C.hp, C.dp, C.n, g.tile,
-                                     ctypes.cast(g.bg, B._VP), P(g.splats), P(g.vals), P(g.ranges),
-                                     grp["cap"], P(g.num_keys[k:k + 1]), P(img), P(fT), P(nc), g.ws, g.wsn,
-                                     st))
+                                     ctypes.cast(g.bg, B._VP), P(lb["splats"]), P(lb["vals"]), P(lb["ranges"]),
+                                     grp["cap"], P(g.num_keys[k:k + 1]), P(img), P(fT), P(nc), lb["ws"],
+                                     lb["wsn"], sl))
             B._check(L.gs_l1_grad(P(img), P(tg), 3 * npx, ctypes.c_float(g.scale), P(dL), P(g.loss),
-                                  1 if first and k == 0 else 0, st))
-            B._check(L.gs_rasterize_bwd(P(g.splats), g.scene.n, C.hp, C.dp, C.n, g.tile, P(g.vals),
-                                        P(g.ranges), ctypes.cast(g.bg, B._VP), P(fT), P(nc), P(dL),
-                                        P(g.sgrads), None, 0, st))
-            B._check(L.gs_project_bwd(ctypes.byref(self.scene_struct), C.hp, C.dp, C.n, P(g.splats),
-                                      P(g.sgrads), P(gr["means"]), P(gr["log_scales"]), P(gr["quats"]),
-                                      P(gr["opacity_logits"]), P(gr["sh"]), 0 if first else 1, st))
+                                  1 if first and k == 0 and not multi else 0, sl))
+            B._check(L.gs_rasterize_bwd(P(lb["splats"]), g.scene.n, C.hp, C.dp, C.n, g.tile, P(lb["vals"]),
+                                        P(lb["ranges"]), ctypes.cast(g.bg, B._VP), P(fT), P(nc), P(dL),
+                                        P(lb["sgrads"]), None, 0, sl))
+            if multi and k > 0 and (k - 1) % self.lanes != lane:
+                lst.wait_event(self.pb_events[k - 1])
+            B._check(L.gs_project_bwd(ctypes.byref(self.scene_struct), C.hp, C.dp, C.n, P(lb["splats"]),
+                                      P(lb["sgrads"]), P(gr["means"]), P(gr["log_scales"]), P(gr["quats"]),
+                                      P(gr["opacity_logits"]), P(gr["sh"]), 0 if first else 1, sl))
+            if multi:
+                self.pb_events[k].record(lst)
             first = False
+        if multi:
+            for ls in self.lane_streams[1:]:
+                self.stream.wait_stream(ls)
         if self.eye_stream is not None:
             # join the eyes' branch
             self.stream.wait_stream(self.eye_stream)

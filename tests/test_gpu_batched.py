@@ -120,13 +120,13 @@ def test_batched_step_matches_separate_calls():
         assert rel_l2(pg[k].cpu().numpy(), a["grads"][k].cpu().numpy()) < GRAD_RTOL, k
 
 
-@pytest.mark.parametrize("bv", [None, 2])
-def test_graph_replays_match_eager(bv):
+@pytest.mark.parametrize("bv,lanes", [(None, 1), (2, 1), (2, 2), (1, 2)])
+def test_graph_replays_match_eager(bv, lanes):
     g = gs()
     from paper_2407_00435_amd.batched import BatchedStep
     sc, S, cams, target, eyes, fov = setup(g, seed=25)
-    say("graph replay", bv)
-    step = BatchedStep(S, cams, target, 16, bv, eyes, fov)
+    say("graph replay", bv, lanes)
+    step = BatchedStep(S, cams, target, 16, bv, eyes, fov, lanes=lanes)
     step.step()
     eager = snapshot(step)
     step.capture()
@@ -147,6 +147,27 @@ def test_graph_replays_match_eager(bv):
     assert_same(eager2, got2)
     assert not torch.equal(eager2["dL"], eager["dL"]) or not torch.equal(eager2["loss"], eager["loss"])
     step.graph.close()
+
+
+@pytest.mark.parametrize("bv", [1, 2])
+def test_two_lanes_equal_one_lane(bv):
+    """Sub-batches alternating over two streams (one's binning beside the
+    other's compositing) give the one-stream step: the same images and
+    compositing state, the same loss and, up to the order of float atomics,
+    the same parameter gradients (the projection reverses accumulate in
+    sub-batch order)."""
+    g = gs()
+    from paper_2407_00435_amd.batched import BatchedStep
+    sc, S, cams, target, eyes, fov = setup(g, seed=27)
+    say("two lanes", bv)
+    one = BatchedStep(S, cams, target, 16, bv, eyes, fov, lanes=1)
+    one.step()
+    a = snapshot(one)
+    two = BatchedStep(S, cams, target, 16, bv, eyes, fov, lanes=2)
+    assert two.lanes == 2
+    for rep in range(2):
+        two.step()
+        assert_same(a, snapshot(two))
 
 
 def test_autotune_small():
