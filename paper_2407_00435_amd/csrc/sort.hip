@@ -29,18 +29,23 @@ constexpr int MIN_PART = 4096;
 constexpr uint64_t SWEEP_BLOCKS = 1024;  // persistent onesweep workgroups (at most)
 
 // Digit counts of every pass.  Each thread takes HIST_RUN consecutive keys
-// and adds runs of equal digits with one LDS atomic (key lists built in
-// depth order hold long runs of neighbouring tile ids).
+// and adds one per key and digit into its wave's own LDS counters (the
+// waves' counters are summed once at the end); a plain increment is a few
+// instructions, where detecting runs of equal digits cost about 24 per key
+// and digit and the keys sorted here rarely repeat.
 constexpr int HIST_RUN = 16;
+constexpr int HIST_THREADS = 1024;
 
-__global__ void __launch_bounds__(1024)
+__global__ void __launch_bounds__(HIST_THREADS)
 k_radix_hist(const uint32_t *__restrict__ keys, const uint64_t *__restrict__ d_count, uint64_t cap,
              int passes, int dbits, int radix, uint32_t *__restrict__ hist)
 {
-    // counts of pass p at sh[p * radix + digit] (radix 256, or 512 for one 9-bit pass)
-    __shared__ uint32_t sh[4 * 256];
-    for (int j = threadIdx.x; j < 4 * 256; j += blockDim.x) sh[j] = 0;
+    // counts of pass p at shw[wave][p * radix + digit] (radix 256, or 512 for one 9-bit pass)
+    constexpr int WAVES = HIST_THREADS / 64;
+    __shared__ uint32_t shw[WAVES][4 * 256];
+    for (int j = threadIdx.x; j < WAVES * 4 * 256; j += blockDim.x) (&shw[0][0])[j] = 0;
     __syncthreads();
+    uint32_t *sh = shw[threadIdx.x >> 6];
     uint64_t count = *d_count;
     count = count < cap ? count : cap;
     const uint32_t mask = (1u << dbits) - 1u;
@@ -64,25 +69,16 @@ k_radix_hist(const uint32_t *__restrict__ keys, const uint64_t *__restrict__ d_c
         }
         for (int p = 0; p < passes; ++p) {
             const int sh_p = dbits * p;
-            uint32_t prev = (k[0] >> sh_p) & mask, run = 1;
 #pragma unroll
-            for (int j = 1; j < HIST_RUN; ++j) {
-                if (j >= (int)nk) break;
-                const uint32_t d = (k[j] >> sh_p) & mask;
-                if (d == prev) {
-                    ++run;
-                } else {
-                    atomicAdd(&sh[p * radix + prev], run);
-                    prev = d;
-                    run = 1;
-                }
-            }
-            atomicAdd(&sh[p * radix + prev], run);
+            for (int j = 0; j < HIST_RUN; ++j)
+                if (j < (int)nk) atomicAdd(&sh[p * radix + ((k[j] >> sh_p) & mask)], 1u);
         }
     }
     __syncthreads();
     for (int j = threadIdx.x; j < passes * radix; j += blockDim.x) {
-        uint32_t c = sh[j];
+        uint32_t c = 0;
+#pragma unroll
+        for (int w = 0; w < WAVES; ++w) c += shw[w][j];
         if (c) atomicAdd(&hist[j], c);
     }
 }
@@ -336,7 +332,7 @@ static hipError_t sort_pairs_impl(uint32_t *ka, VT *va, uint32_t *kb, VT *vb,
         int hist_blocks = (int)((cap + 1024 * HIST_RUN * 4 - 1) / (1024 * HIST_RUN * 4));
         if (hist_blocks > 256) hist_blocks = 256;
         if (hist_blocks < 1) hist_blocks = 1;
-        hipLaunchKernelGGL(k_radix_hist, dim3(hist_blocks), dim3(1024), 0, st, ka, d_count, cap, passes,
+        hipLaunchKernelGGL(k_radix_hist, dim3(hist_blocks), dim3(HIST_THREADS), 0, st, ka, d_count, cap, passes,
                            dbits, R, rs.hist);
     }
     uint32_t *src_k = ka, *dst_k = kb;
