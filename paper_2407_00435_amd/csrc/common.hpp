@@ -45,27 +45,6 @@ __device__ __forceinline__ ViewInfo view_of_tile(const gs_camera *__restrict__ c
     return vi;
 }
 
-__device__ __forceinline__ ViewInfo view_of_pixel(const gs_camera *__restrict__ cams, int V, int T,
-                                                  int64_t gpix)
-{
-    ViewInfo vi;
-    int64_t toff = 0, poff = 0;
-    for (int v = 0; v < V; ++v) {
-        int W = cams[v].width, H = cams[v].height;
-        int tx = div_up(W, T), ty = div_up(H, T);
-        int64_t np = (int64_t)W * H;
-        if (gpix < poff + np || v == V - 1) {
-            vi.v = v; vi.W = W; vi.H = H; vi.tiles_x = tx; vi.tiles_y = ty;
-            vi.tile_off = toff; vi.pix_off = poff;
-            return vi;
-        }
-        toff += (int64_t)tx * ty;
-        poff += np;
-    }
-    vi.v = 0; vi.W = vi.H = vi.tiles_x = vi.tiles_y = 0; vi.tile_off = vi.pix_off = 0;
-    return vi;
-}
-
 // ---------------------------------------------------------------------------
 // Pixel rectangle of a splat in float32: [ceil(x - r), floor(x + r)] clipped
 // to the image, likewise in y; tile rectangle = pixel rectangle / T.  Only
@@ -203,36 +182,6 @@ __device__ __forceinline__ float row_sum16(float x)
     x += dpp_f<0x141>(x);  // row_half_mirror
     x += dpp_f<0x140>(x);  // row_mirror
     return x;
-}
-
-// Reduce-scatter of eight per-lane values over each 16-lane DPP row: on
-// return lane L holds the row sum of value scatter_q(L) = 4 bit2(L) +
-// 2 bit0(L) + bit1(L) (lanes L and L ^ 8 hold the same sum).  Each step
-// keeps half of the values and adds the partner's copy of them: partner
-// L ^ 7 within the half row (row half mirror), then L ^ 1 and L ^ 2 (quad
-// permutations), then L ^ 8 (row rotate by 8) -- 22 DPP-fed adds and selects
-// instead of 8 x 4 for eight row sums.  Every lane of the wave must be
-// active.
-__device__ __forceinline__ int scatter_q(int lane) { return 4 * ((lane >> 2) & 1) + 2 * (lane & 1) + ((lane >> 1) & 1); }
-
-__device__ __forceinline__ float row_scatter_sum8(const float (&v)[8], int lane)
-{
-    const bool h = (lane >> 2) & 1, b0 = lane & 1, b1 = (lane >> 1) & 1;
-    float a[4], b[2];
-#pragma unroll
-    for (int k = 0; k < 4; ++k) {
-        const float keep = h ? v[k + 4] : v[k], send = h ? v[k] : v[k + 4];
-        a[k] = keep + dpp_f<0x141>(send);  // row_half_mirror: L <-> 7 - L
-    }
-#pragma unroll
-    for (int k = 0; k < 2; ++k) {
-        const float keep = b0 ? a[k + 2] : a[k], send = b0 ? a[k] : a[k + 2];
-        b[k] = keep + dpp_f<0xB1>(send);   // quad_perm [1,0,3,2]: L <-> L ^ 1
-    }
-    const float keep = b1 ? b[1] : b[0], send = b1 ? b[0] : b[1];
-    float c = keep + dpp_f<0x4E>(send);    // quad_perm [2,3,0,1]: L <-> L ^ 2
-    c += dpp_f<0x128>(c);                  // row_ror:8: L <-> L ^ 8
-    return c;
 }
 
 // Inclusive prefix sum over the 64 lanes of a wave: shifts by 1, 2, 4 and 8
