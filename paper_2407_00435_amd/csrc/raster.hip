@@ -866,7 +866,7 @@ __device__ __forceinline__ float octet_sum(float x)
 }
 
 template <int T>
-__global__ void __launch_bounds__(T *T)
+__global__ void __launch_bounds__(T *T) __attribute__((amdgpu_waves_per_eu(5)))
 k_raster_bwd(const gs_splat *__restrict__ splats, int n, const gs_camera *__restrict__ cams, int V,
              const uint32_t *__restrict__ vals, const uint32_t *__restrict__ ranges, float bg0,
              float bg1, float bg2, const float *__restrict__ final_T,
@@ -881,7 +881,7 @@ k_raster_bwd(const gs_splat *__restrict__ splats, int n, const gs_camera *__rest
     // rotated by r pairs so that the regrouped reads (lanes 8 r + y, column
     // x) of the 8 records fall in different LDS banks
     __shared__ float2 s_m[WAVES][8][64];
-    __shared__ float s_grad[NG][64];
+    __shared__ float s_grad[NG][73];  // row stride 73: the flush reads 9 rows of 7 positions with few bank conflicts
     __shared__ uint32_t s_id[64];
     __shared__ uint32_t s_maxnc;
     const int64_t gtile = blockIdx.x;
@@ -900,7 +900,7 @@ k_raster_bwd(const gs_splat *__restrict__ splats, int n, const gs_camera *__rest
     const int64_t vbase = (int64_t)vi.v * n;
 
     if (threadIdx.x == 0) s_maxnc = 0;
-    for (int q = threadIdx.x; q < NG * 64; q += T * T) (&s_grad[0][0])[q] = 0.f;
+    for (int q = threadIdx.x; q < NG * 73; q += T * T) (&s_grad[0][0])[q] = 0.f;
     uint32_t nc = 0;
     float Tr = 1.0f, g0 = 0.f, g1 = 0.f, g2 = 0.f;
     if (inside) {
@@ -998,36 +998,41 @@ k_raster_bwd(const gs_splat *__restrict__ splats, int n, const gs_camera *__rest
                 if (ballot64(any) == 0) continue;  // none of the 8 reaches the wave's pixels
                 wave_lds_sync();
                 // (2) lane 8 r + y sums record j0 + r over pixel row y in
-                // registers (w and its moments in (dx, dy); colour as g alpha
-                // T), then the 8 rows of a record add up by DPP within the
-                // lane octet, and one lane per record adds the nine sums to
-                // the tile's slots of the record's list position
+                // registers: w and its moments in the pixel offsets (x, y)
+                // from the block corner, colour as g alpha T.  The 8 rows
+                // of a record add up by DPP within the lane octet; one lane
+                // per record moves the moments to the record's mean,
+                //   sum w dx = Mx - u M, sum w dx^2 = (Mxx - u Mx) - u sum w dx,
+                //   sum w dx dy = (Mxy - v Mx) - u sum w dy, ...
+                // with (u, v) the mean's offset from the corner, and adds the
+                // nine sums to the tile's slots of the record's list position
                 {
                     const int r = lane >> 3, y = lane & 7;
-                    const float4 a = s_rec[wave][j0 + r].a;
-                    const float dy = (ry0 + (float)y) - a.y;
-                    float S[NG];
-#pragma unroll
-                    for (int k = 0; k < NG; ++k) S[k] = 0.f;
+                    float M0 = 0.f, Mx = 0.f, Mxx = 0.f, C0 = 0.f, C1 = 0.f, C2 = 0.f;
 #pragma unroll
                     for (int x = 0; x < 8; ++x) {
                         const float2 m = s_m[wave][r][(8 * y + x + r) & 63];
-                        const float dx = (rx0 + (float)x) - a.x;
-                        const float wdx = m.x * dx, wdy = m.x * dy;
-                        S[0] += m.x;
-                        S[1] += wdx;
-                        S[2] += wdy;
-                        S[3] = fmaf(wdx, dx, S[3]);
-                        S[4] = fmaf(wdx, dy, S[4]);
-                        S[5] = fmaf(wdy, dy, S[5]);
-                        S[6] = fmaf(grow0[x], m.y, S[6]);
-                        S[7] = fmaf(grow1[x], m.y, S[7]);
-                        S[8] = fmaf(grow2[x], m.y, S[8]);
+                        M0 += m.x;
+                        Mx = fmaf(m.x, (float)x, Mx);
+                        Mxx = fmaf(m.x, (float)(x * x), Mxx);
+                        C0 = fmaf(grow0[x], m.y, C0);
+                        C1 = fmaf(grow1[x], m.y, C1);
+                        C2 = fmaf(grow2[x], m.y, C2);
                     }
+                    const float fy = (float)y;
+                    float S[NG] = {M0, Mx, fy * M0, Mxx, fy * Mx, fy * fy * M0, C0, C1, C2};
 #pragma unroll
                     for (int k = 0; k < NG; ++k) S[k] = octet_sum(S[k]);
                     if (y == 0 && j0 + r < cnt) {
+                        const float4 a = s_rec[wave][j0 + r].a;
                         const int q = (int)(__float_as_uint(s_rec[wave][j0 + r].b.w) - (uint32_t)p0);
+                        const float u = a.x - rx0, v = a.y - ry0;
+                        const float sdx = fmaf(-u, S[0], S[1]), sdy = fmaf(-v, S[0], S[2]);
+                        S[3] = fmaf(-u, sdx, fmaf(-u, S[1], S[3]));
+                        S[4] = fmaf(-u, sdy, fmaf(-v, S[1], S[4]));
+                        S[5] = fmaf(-v, sdy, fmaf(-v, S[2], S[5]));
+                        S[1] = sdx;
+                        S[2] = sdy;
 #pragma unroll
                         for (int k = 0; k < NG; ++k) atomicAdd(&s_grad[k][q], S[k]);
                     }
@@ -1036,39 +1041,40 @@ k_raster_bwd(const gs_splat *__restrict__ splats, int n, const gs_camera *__rest
             }
         }
         __syncthreads();
-        // the tile's sums of this chunk leave with one atomic per quantity:
-        // with q = the Mahalanobis form and dL/dq = -w / 2,
+        // the tile's sums of this chunk leave with global atomics: with q =
+        // the Mahalanobis form and dL/dq = -w / 2,
         //   dL/dmean = (A S_wdx + B S_wdy, B S_wdx + C S_wdy),
         //   dL/d(A, B, C) = (-S_wdx2 / 2, -S_wdxdy, -S_wdy2 / 2),
-        //   dL/dopacity = S_w / opacity
-        if (threadIdx.x < 64) {
-            const int jj = threadIdx.x;
-            float S[NG];
-            bool any = false;
-#pragma unroll
-            for (int k = 0; k < NG; ++k) {
-                S[k] = s_grad[k][jj];
-                s_grad[k][jj] = 0.f;
-                any = any || S[k] != 0.f;
-            }
-            if (any) {
-                const gs_splat *sp = splats + vbase + s_id[jj];
-                const float4 s0 = reinterpret_cast<const float4 *>(sp)[0];
-                const float4 s1 = reinterpret_cast<const float4 *>(sp)[1];
-                float out[NG];
-                out[0] = fmaf(s0.z, S[1], s0.w * S[2]);
-                out[1] = fmaf(s0.w, S[1], s1.x * S[2]);
-                out[2] = -0.5f * S[3];
-                out[3] = -S[4];
-                out[4] = -0.5f * S[5];
-                out[5] = S[0] * __builtin_amdgcn_rcpf(s1.y);
-                out[6] = S[6];
-                out[7] = S[7];
-                out[8] = S[8];
-                float *gp = reinterpret_cast<float *>(grads + vbase + s_id[jj]);
-#pragma unroll
-                for (int k = 0; k < NG; ++k)
-                    if (out[k] != 0.f) atomicAdd(gp + k, out[k]);
+        //   dL/dopacity = S_w / opacity.
+        // Lane 9 i + k of an instruction adds quantity k of position 7 rnd + i,
+        // so the lanes of one position add to one 36-byte run of its
+        // gradient record; the ten rounds of 7 positions go round the waves
+        {
+            // recomputed per chunk rather than held across the record loop
+            int ln = lane;
+            asm volatile("" : "+v"(ln));
+            const int pl = (ln * 57) >> 9;  // ln / 9 for ln < 64
+            const int k = ln - 9 * pl;
+            for (int rnd = wave; rnd < 10; rnd += WAVES) {
+                const int q = 7 * rnd + pl;
+                if (ln < 63 && q < 64) {
+                    // quantities 2..4 (the conic) come from the second moments 3..5
+                    const float v = s_grad[k >= 2 && k <= 4 ? k + 1 : k][q];
+                    const float S0 = s_grad[0][q], S1 = s_grad[1][q], S2 = s_grad[2][q];
+                    float out = k == 2 || k == 4 ? -0.5f * v : (k == 3 ? -v : v);
+                    if (k == 0 || k == 1 || k == 5) {
+                        out = 0.f;
+                        if (S0 != 0.f || S1 != 0.f || S2 != 0.f) {
+                            const float *sp = reinterpret_cast<const float *>(splats + vbase + s_id[q]);
+                            const float2 ab = *reinterpret_cast<const float2 *>(sp + 2);
+                            const float2 co = *reinterpret_cast<const float2 *>(sp + 4);
+                            out = k == 0 ? fmaf(ab.x, S1, ab.y * S2)
+                                         : (k == 1 ? fmaf(ab.y, S1, co.x * S2) : S0 * __builtin_amdgcn_rcpf(co.y));
+                        }
+                    }
+                    s_grad[k][q] = 0.f;
+                    if (out != 0.f) atomicAdd(reinterpret_cast<float *>(grads + vbase + s_id[q]) + k, out);
+                }
             }
         }
         __syncthreads();
