@@ -191,7 +191,8 @@ def plain_fwd_rate(g, wl, steps, warmup, tile=16):
 
 
 def fwd_bwd_rate(g, wl, steps, warmup, tile=16):
-    """Forward + backward (L1 loss against a target render) through autograd."""
+    """Forward + backward (L1 loss against a target render, the fused loss
+    kernel) through autograd."""
     import torch
     S, C = g.SceneTensors(wl.scene), g.Cameras(wl.cams)
     tgt_S = g.SceneTensors(wl.extra["target_scene"])
@@ -205,7 +206,7 @@ def fwd_bwd_rate(g, wl, steps, warmup, tile=16):
 
     def it():
         img = g.render(*params, C, S.sh_degree, tile, key_capacity=cap)
-        loss = (img - target).abs().mean()
+        loss = g.l1_loss(img, target)
         loss.backward()
         for p in params:
             p.grad = None

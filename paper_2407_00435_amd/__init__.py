@@ -13,4 +13,4 @@ from .binding import (  # noqa: F401
     gs_l1_grad, gs_ce_score, gs_select_lowest, gs_weighted_scale, Graph,
     gs_rasterize_foveated_bwd, gs_project_bwd_levels,
 )
-from .render import GaussianRender, render, FoveatedRender, render_foveated  # noqa: F401
+from .render import GaussianRender, render, FoveatedRender, render_foveated, L1Loss, l1_loss  # noqa: F401

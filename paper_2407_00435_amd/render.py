@@ -90,3 +90,28 @@ def render_foveated(means, log_scales, quats, opacity_logits, sh, lvl_opacity_lo
     """Foveated render of the eyes in ``cams`` (planar image buffer)."""
     return FoveatedRender.apply(means, log_scales, quats, opacity_logits, sh, lvl_opacity_logits, lvl_sh_dc,
                                 qbound, cams, foveae, sh_degree, tile_size, tuple(bg), key_capacity)
+
+
+class L1Loss(torch.autograd.Function):
+    """Mean absolute error between a render and its target, the training
+    objective used with the reverse pass, through the library's fused kernel:
+    one pass over both images gives the loss and dL/dimage = sign / n."""
+
+    @staticmethod
+    def forward(ctx, image, target):
+        image, target = image.detach().contiguous(), target.detach().contiguous()
+        grad = torch.empty_like(image)
+        loss = torch.empty(1, dtype=torch.float32, device=image.device)
+        B.gs_l1_grad(image, target, 1.0 / image.numel(), grad, loss, reset=True)
+        ctx.save_for_backward(grad)
+        return loss.reshape(())
+
+    @staticmethod
+    def backward(ctx, g):
+        (grad,) = ctx.saved_tensors
+        return grad * g, None
+
+
+def l1_loss(image, target):
+    """Mean |image - target| (a 0-d tensor) with its reverse."""
+    return L1Loss.apply(image, target)
