@@ -34,3 +34,35 @@ def test_sort_pairs_bit_exact(part, bits, n):
     np.testing.assert_array_equal(kt.cpu().numpy().view(np.uint32), keys[order])
     np.testing.assert_array_equal(vt.cpu().numpy().view(np.uint32), vals[order])
     g.gs_set_tuning("radix_part", 8192)
+
+
+@pytest.mark.parametrize("part", [4096, 8192])
+@pytest.mark.parametrize("pattern", ["top", "middle_and_top", "all_equal", "bottom"])
+def test_sort_pairs_constant_digits(part, pattern):
+    """Keys whose 8-bit digits are the same for every key in some passes
+    (every key lands in one digit of those passes) sort like any others."""
+    need_gpu()
+    import paper_2407_00435_amd as g
+    say("sort constant digits", part, pattern)
+    g.gs_set_tuning("radix_part", part)
+    n = 300_007
+    rng = np.random.default_rng(len(pattern) * 7 + part)
+    r = rng.integers(0, 1 << 32, n, dtype=np.uint64).astype(np.uint32)
+    if pattern == "top":
+        keys = (r & 0x00FFFFFF) | 0x40000000
+    elif pattern == "middle_and_top":
+        keys = (r & 0x00FF00FF) | 0x12003400
+    elif pattern == "all_equal":
+        keys = np.full(n, 0x3F8000AB, dtype=np.uint32)
+    else:
+        keys = (r & 0xFFFFFF00) | 0x7
+    keys = keys.astype(np.uint32)
+    vals = rng.permutation(n).astype(np.uint32)
+    kt = torch.from_numpy(keys.view(np.int32)).cuda()
+    vt = torch.from_numpy(vals.view(np.int32)).cuda()
+    g.gs_sort_pairs(kt, vt, 32)
+    torch.cuda.synchronize()
+    order = np.argsort(keys, kind="stable")
+    np.testing.assert_array_equal(kt.cpu().numpy().view(np.uint32), keys[order])
+    np.testing.assert_array_equal(vt.cpu().numpy().view(np.uint32), vals[order])
+    g.gs_set_tuning("radix_part", 8192)
