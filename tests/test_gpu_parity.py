@@ -355,18 +355,19 @@ def test_concurrent_streams_give_the_sequential_frames():
         torch.cuda.synchronize()
 
 
-def test_backward_stagewise_matches_oracle():
+@pytest.mark.parametrize("tile", [8, 16, 32])
+def test_backward_stagewise_matches_oracle(tile):
     g = gs()
     sc = scene_small(seed=61, n=1500)
     cams = two_views()
     bg = (0.2, 0.1, 0.3)
-    say("backward stage-wise")
-    C, splats, bs, out = _raster_case(g, sc, cams, 16, bg, dominated=False)
+    say(f"backward stage-wise tile {tile}")
+    C, splats, bs, out = _raster_case(g, sc, cams, tile, bg, dominated=False)
     sizes = [(c.width, c.height) for c in cams]
     rng = np.random.default_rng(0)
     dimg = rng.uniform(-1.0, 1.0, out["image"].shape[0]).astype(np.float32)
     dimg_t = torch.from_numpy(dimg).cuda()
-    grads = g.gs_rasterize_bwd(splats, sc.n, C, 16, bs["vals"], bs["ranges"], out["final_T"],
+    grads = g.gs_rasterize_bwd(splats, sc.n, C, tile, bs["vals"], bs["ranges"], out["final_T"],
                                out["n_contrib"], dimg_t, bg)
     S = g.SceneTensors(sc)
     pg = g.gs_project_bwd(S, C, splats, grads)
