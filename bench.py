@@ -26,7 +26,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 METRIC = "FPS & Mpix/s fwd, 1080p 1.5M Gaussians; fwd+bwd it/s; batched vs plain"
-# dense fp32 vector peak of MI355X (256 CUs, 2.4 GHz); see the design doc
+# published dense fp32 vector peak of MI355X (256 CUs, 2.4 GHz, packed fp32 counted as two)
 FP32_PEAK_TFLOPS = 157.3
 # algorithmic fp32 flops of one blended (pixel, point) pair (FMA = 2): offsets 2,
 # quadratic falloff 8, exp2 1, clamp 1, cut-off test 1, transmittance 2, stop
@@ -434,8 +434,8 @@ def main():
                     help="only run a plain 1 GiB device copy (memory-counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
-        print("bench.py runs on exactly one GPU: this build has no multi-GPU path "
-              "(see DESIGN.md for how the render would shard).", file=sys.stderr)
+        print("bench.py runs on exactly one GPU: the renderer has no multi-GPU path "
+              "(its views would shard across GPUs with one gradient all-reduce).", file=sys.stderr)
         sys.exit(2)
     import torch
 
