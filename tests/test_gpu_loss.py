@@ -12,15 +12,18 @@ from gpu_util import need_gpu, say
 pytestmark = pytest.mark.gpu
 
 
-@pytest.mark.parametrize("n", [1, 1000, 3 * 1280 * 720 + 7])
-def test_l1_loss_and_grad_match_definition(n):
+@pytest.mark.parametrize("offset", [0, 1])
+@pytest.mark.parametrize("n", [1, 3, 4, 1000, 4099, 3 * 1280 * 720 + 7])
+def test_l1_loss_and_grad_match_definition(n, offset):
+    """offset 1 starts the images one float into their buffers (the
+    unaligned path; aligned buffers take four floats per load)."""
     need_gpu()
     import paper_2407_00435_amd as g
-    say(f"l1 loss n={n}")
+    say(f"l1 loss n={n} offset={offset}")
     gen = torch.Generator(device="cuda")
     gen.manual_seed(n)
-    img = torch.rand(n, device="cuda", generator=gen)
-    tgt = torch.rand(n, device="cuda", generator=gen)
+    img = torch.rand(n + offset, device="cuda", generator=gen)[offset:]
+    tgt = torch.rand(n + offset, device="cuda", generator=gen)[offset:]
     tgt[::5] = img[::5]  # ties take a zero gradient
     a = img.clone().requires_grad_(True)
     b = img.clone().requires_grad_(True)
