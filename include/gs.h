@@ -200,7 +200,8 @@ int gs_rasterize_fwd(const gs_splat *splats, int32_t n, const gs_camera *cams_ho
  * forward's final_T and n_contrib, writes grads [n_views][n] (device,
  * overwritten): the gradient of L with respect to each splat's mean, conic,
  * opacity and colour.  The per-pixel decisions (extent, skip, stop, the alpha
- * clamp) are held constant. */
+ * clamp) are held constant.  A splat's sums over the tiles it reaches are
+ * added with float atomics, so their last bits depend on scheduling. */
 int gs_rasterize_bwd(const gs_splat *splats, int32_t n, const gs_camera *cams_host,
                      const gs_camera *cams_dev, int n_views, int tile_size,
                      const uint32_t *vals, const uint32_t *tile_ranges, const float *bg,
