@@ -68,6 +68,17 @@ def sh_basis(degree: int, direction) -> np.ndarray:
     return Y
 
 
+def sh_basis_grad(degree: int, direction):
+    """(Y [K], dY/d dir [K, 3]) of the real SH basis at a unit direction, from
+    the polynomial form of the basis (the reverse pass's derivative)."""
+    d = _f64(direction)
+    K = (degree + 1) ** 2
+    Y = np.zeros(K)
+    dY = np.zeros((K, 3))
+    lib().oc_sh_basis_grad(ctypes.c_int(degree), _p(d), _p(Y), _p(dY))
+    return Y, dY
+
+
 def project(scene, cam, levels: bool = False) -> dict:
     """FP64 projection of every Gaussian for one camera."""
     n = scene.n

@@ -119,23 +119,79 @@ void oc_sh_basis(int degree, const double dir[3], double *Y)
     }
 }
 
-/* d Y_k / d dir (3 partials each), by central differences of the analytic
- * basis along each axis of R^3 with the basis extended as a homogeneous-free
- * function of the normalised direction.  Used only by the reverse pass. */
-static void sh_basis_grad(int degree, const double dir[3], double *dY /* [K][3] */)
+/* Legendre polynomial P_l (l <= 3) as coefficients c[j] of z^j, from
+ * Bonnet's recurrence (k + 1) P_{k+1} = (2k + 1) z P_k - k P_{k-1}. */
+static void legendre_coeffs(int l, double c[4])
 {
-    int K = (degree + 1) * (degree + 1);
-    const double h = 1e-6;
-    double Yp[16], Ym[16], d[3];
-    for (int a = 0; a < 3; a++) {
-        for (int s = 0; s < 2; s++) {
-            for (int j = 0; j < 3; j++) d[j] = dir[j];
-            d[a] += s ? -h : h;
-            double n = sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
-            for (int j = 0; j < 3; j++) d[j] /= n;
-            oc_sh_basis(degree, d, s ? Ym : Yp);
+    double pm[4] = {1, 0, 0, 0}, p[4] = {0, 1, 0, 0};
+    if (l == 0) { memcpy(c, pm, sizeof(pm)); return; }
+    for (int k = 1; k < l; k++) {
+        double nx[4] = {0, 0, 0, 0};
+        for (int j = 0; j < 3; j++) nx[j + 1] += (2.0 * k + 1.0) * p[j];
+        for (int j = 0; j < 4; j++) nx[j] = (nx[j] - k * pm[j]) / (k + 1.0);
+        memcpy(pm, p, sizeof(p));
+        memcpy(p, nx, sizeof(nx));
+    }
+    memcpy(c, p, sizeof(p));
+}
+
+/* d^m/dz^m of the polynomial sum_j c[j] z^j, evaluated at z */
+static double poly_deriv(const double c[4], int m, double z)
+{
+    double s = 0.0;
+    for (int j = m; j < 4; j++) {
+        double f = c[j];
+        for (int k = 0; k < m; k++) f *= (double)(j - k);
+        double zp = 1.0;
+        for (int k = 0; k < j - m; k++) zp *= z;
+        s += f * zp;
+    }
+    return s;
+}
+
+/* Analytic derivative of Y_k(d / |d|) with respect to d at a unit d (3
+ * partials per basis function).  On the unit sphere the basis above equals
+ * the polynomial N_lm Q(z) A(x, y) with Q = d^|m| P_l / dz^|m| and A =
+ * sqrt2 Re (x + iy)^m for m > 0, 1 for m = 0, sqrt2 Im (x + iy)^|m| for
+ * m < 0, because (1 - z^2)^(|m|/2) e^(i |m| phi) = (x + iy)^|m| there.  The
+ * derivative of Y(d / |d|) is that polynomial's Euclidean gradient with its
+ * radial part removed, (I - d d^T) grad.  Used by the reverse pass.
+ * Y (nullable) receives the polynomial form's values. */
+void oc_sh_basis_grad(int degree, const double dir[3], double *Y, double *dY /* [K][3] */)
+{
+    double x = dir[0], y = dir[1], z = dir[2];
+    for (int l = 0; l <= degree; l++) {
+        double pc[4] = {0, 0, 0, 0};
+        legendre_coeffs(l, pc);
+        for (int m = -l; m <= l; m++) {
+            int am = m < 0 ? -m : m;
+            double N = sqrt((2.0 * l + 1.0) / (4.0 * OC_PI) * factorial(l - am) / factorial(l + am));
+            double Q = poly_deriv(pc, am, z), dQ = poly_deriv(pc, am + 1, z);
+            /* (x + iy)^am and (x + iy)^(am - 1) */
+            double re = 1.0, im = 0.0, re1 = 1.0, im1 = 0.0;
+            for (int k = 0; k < am; k++) {
+                re1 = re; im1 = im;
+                double r2 = re * x - im * y, i2 = re * y + im * x;
+                re = r2; im = i2;
+            }
+            double A, Ax, Ay;
+            if (m > 0) {
+                A = sqrt(2.0) * re;
+                Ax = sqrt(2.0) * am * re1;    /* d/dx (x+iy)^m = m (x+iy)^(m-1) */
+                Ay = -sqrt(2.0) * am * im1;   /* d/dy = i m (x+iy)^(m-1) */
+            } else if (m < 0) {
+                A = sqrt(2.0) * im;
+                Ax = sqrt(2.0) * am * im1;
+                Ay = sqrt(2.0) * am * re1;
+            } else {
+                A = 1.0; Ax = 0.0; Ay = 0.0;
+            }
+            int k = l * l + l + m;
+            double g[3] = {N * Ax * Q, N * Ay * Q, N * A * dQ};
+            double rad = g[0] * x + g[1] * y + g[2] * z;
+            for (int a = 0; a < 3; a++) dY[k * 3 + a] = g[a] - dir[a] * rad;
+            if (Y) Y[k] = N * A * Q;
         }
-        for (int k = 0; k < K; k++) dY[k * 3 + a] = (Yp[k] - Ym[k]) / (2.0 * h);
     }
 }
 
@@ -987,7 +1043,7 @@ int oc_project_bwd(int n, int sh_degree, const double *means, const double *log_
         /* colour -> SH and direction */
         double Y[16], dY[48];
         oc_sh_basis(sh_degree, o.dir, Y);
-        sh_basis_grad(sh_degree, o.dir, dY);
+        oc_sh_basis_grad(sh_degree, o.dir, NULL, dY);
         double ddir[3] = {0, 0, 0};
         for (int ch = 0; ch < 3; ch++) {
             if (!(o.color_raw[ch] > 0.0)) continue;

@@ -10,6 +10,8 @@ Section 4.2 nested subsets and multi-versioning, Section 6 ring layout).
   the plain render; a single level reduces to a plain render of the subset
   {i : m_i >= t}.
 """
+import math
+
 import numpy as np
 
 import scenegen
@@ -119,3 +121,49 @@ def test_blend_is_weighted_sum_of_levels(oracle_lib):
     b = stack[np.minimum(lo, 3), yy, xx]
     np.testing.assert_allclose(fr["rgb"], (1 - w) * a + w * b, rtol=1e-12, atol=1e-14)
     assert (f["pix_w"] > 0).any()
+
+
+def test_eccentricity_about_an_off_centre_gaze(oracle_lib):
+    # rays through one image row (or one image column) lie in a plane
+    # through the camera centre, so their angles add there.  On the gaze's
+    # row, in the plane y_cam = b z_cam with b = (gy - cy)/f, the in-plane
+    # distance to the axis is f sqrt(1 + b^2), so
+    # ecc = |atan((x - cx)/(f sqrt(1 + b^2))) - atan((gx - cx)/(f sqrt(1 + b^2)))|;
+    # on the gaze's column likewise with a = (gx - cx)/f.  On the principal
+    # row (odd height puts it on a pixel row) b = 0.
+    cam = scenegen.pinhole(321, 181, scenegen.FR_FOV_DEG, t=(0.0, 0.0, 2.0))
+    gx, gy = 251.0, 40.0
+    f = oracle_lib.fovea(cam, scenegen.Fovea(gx, gy), 4, 16)
+    ecc = f["ecc"].reshape(181, 321)
+    assert ecc[int(gy), int(gx)] < 1e-9
+    xs = np.arange(321)
+    b = (gy - cam.cy) / cam.fy
+    fx = cam.fx * math.sqrt(1 + b * b)
+    row = np.degrees(np.abs(np.arctan((xs - cam.cx) / fx) - np.arctan((gx - cam.cx) / fx)))
+    np.testing.assert_allclose(ecc[int(gy)], row, atol=1e-9)
+    f0 = oracle_lib.fovea(cam, scenegen.Fovea(gx, cam.cy), 4, 16)
+    row0 = np.degrees(np.abs(np.arctan((xs - cam.cx) / cam.fx) - np.arctan((gx - cam.cx) / cam.fx)))
+    np.testing.assert_allclose(f0["ecc"].reshape(181, 321)[int(cam.cy)], row0, atol=1e-9)
+    a = (gx - cam.cx) / cam.fx
+    fy = cam.fy * math.sqrt(1 + a * a)
+    ys = np.arange(181)
+    col = np.degrees(np.abs(np.arctan((ys - cam.cy) / fy) - np.arctan((gy - cam.cy) / fy)))
+    np.testing.assert_allclose(ecc[:, int(gx)], col, atol=1e-9)
+    # any pixel: rotate the gaze ray onto the optical axis, the eccentricity
+    # is then the polar angle of the rotated pixel ray
+    g = np.array([(gx - cam.cx) / cam.fx, (gy - cam.cy) / cam.fy, 1.0])
+    e3 = g / np.linalg.norm(g)
+    e1 = np.cross([0.0, 1.0, 0.0], e3)
+    e1 /= np.linalg.norm(e1)
+    e2 = np.cross(e3, e1)
+    Rg = np.stack([e1, e2, e3])
+    rng = np.random.default_rng(2)
+    for x, y in zip(rng.integers(0, 321, 50), rng.integers(0, 181, 50)):
+        r = Rg @ np.array([(x - cam.cx) / cam.fx, (y - cam.cy) / cam.fy, 1.0])
+        assert abs(ecc[y, x] - math.degrees(math.atan2(math.hypot(r[0], r[1]), r[2]))) < 1e-9
+    # the levels follow the gaze: the gaze pixel is in the fovea and the
+    # pixel farthest from it is in the outer ring
+    lo = f["pix_lo"].reshape(181, 321)
+    assert lo[int(gy), int(gx)] == 1
+    far = np.unravel_index(np.argmax(ecc), ecc.shape)
+    assert far == (180, 0) and lo[far] == 4

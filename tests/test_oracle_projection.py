@@ -162,3 +162,79 @@ def test_level_versions_replace_dc_and_opacity(oracle_lib):
         np.testing.assert_allclose(pr["lvl_color"][t][ok], (raw + delta)[ok], rtol=1e-9, atol=1e-12)
         op = 1.0 / (1.0 + np.exp(-sc.lvl_opacity_logits[t].astype(np.float64)))
         np.testing.assert_allclose(pr["lvl_opacity"][t], op, rtol=1e-13)
+
+
+def test_sh_basis_gradient_is_the_derivative(oracle_lib):
+    # the reverse pass's analytic derivative of Y(d / |d|) against central
+    # differences of the basis itself, at random directions and near and at
+    # the poles (where the angle form of the basis has no derivative in phi)
+    # (the angle form takes sqrt(1 - z^2), which keeps few digits within
+    # 1e-4 of a pole, so the differences there are only good to about 1e-5,
+    # and at the pole itself to about 1e-4: still far below any wrong sign,
+    # factor or dropped term, which are of order 0.1)
+    rng = np.random.default_rng(4)
+    dirs = [(rng.standard_normal(3), 2e-8) for _ in range(12)]
+    dirs += [(np.array([1e-4, -2e-4, 1.0]), 1e-5), (np.array([3e-5, 1e-5, -1.0]), 1e-5),
+             (np.array([0.0, 0.0, 1.0]), 1e-4), (np.array([1.0, 0.0, 0.0]), 2e-8),
+             (np.array([0.0, -1.0, 0.0]), 2e-8)]
+    h = 1e-6
+    for d, tol in dirs:
+        d = d / np.linalg.norm(d)
+        Y, dY = oracle_lib.sh_basis_grad(3, d)
+        np.testing.assert_allclose(Y, oracle_lib.sh_basis(3, d), atol=1e-13)
+        fd = np.zeros((16, 3))
+        for a in range(3):
+            e = np.zeros(3)
+            e[a] = h
+            yp = oracle_lib.sh_basis(3, (d + e) / np.linalg.norm(d + e))
+            ym = oracle_lib.sh_basis(3, (d - e) / np.linalg.norm(d - e))
+            fd[:, a] = (yp - ym) / (2 * h)
+        np.testing.assert_allclose(dY, fd, atol=tol)
+        # a radial change of d does not change Y(d / |d|)
+        np.testing.assert_allclose(dY @ d, 0.0, atol=1e-13)
+
+
+def test_tangent_clamp_closed_form(oracle_lib):
+    # a small isotropic Gaussian beyond the Jacobian's tangent limits: with
+    # R = I, Sigma = s^2 I, J = [[f/z, 0, -f tx/z], [0, f/z, -f ty/z]] and the
+    # tangents tx, ty clamped to 1.3 tan(fov/2) on each axis, the 2D
+    # covariance is (f s / z)^2 [[1 + tx^2, tx ty], [tx ty, 1 + ty^2]] + 0.3 I
+    s = 0.05
+    f = CAM.fx
+    limx = 1.3 * (CAM.width / 2.0) / CAM.fx
+    limy = 1.3 * (CAM.height / 2.0) / CAM.fy
+    for mean, tx, ty in (((4.5, 3.0, 0.0), limx, limy),       # both clamped
+                         ((-4.5, 0.8, 0.0), -limx, 0.2),      # x clamped only
+                         ((0.4, -3.2, 0.0), 0.1, -limy)):     # y clamped only
+        z = mean[2] + 4.0
+        pr = oracle_lib.project(one(mean, [math.log(s)] * 3), CAM)
+        k = (f * s / z) ** 2
+        expect = [k * (1 + tx * tx) + 0.3, k * tx * ty, k * (1 + ty * ty) + 0.3]
+        np.testing.assert_allclose(pr["cov2d"][0], expect, rtol=1e-12, atol=1e-14)
+        # the unclamped tangents would give a clearly different covariance
+        ux, uy = mean[0] / z, mean[1] / z
+        free = [k * (1 + ux * ux) + 0.3, k * ux * uy, k * (1 + uy * uy) + 0.3]
+        assert np.max(np.abs(np.subtract(free, expect))) > 0.05 * k
+        # the mean is not clamped
+        np.testing.assert_allclose(pr["mean2d"][0], [f * ux + CAM.cx, f * uy + CAM.cy], rtol=1e-13)
+
+
+def test_sh_direction_from_the_camera_centre(oracle_lib):
+    # rotated cameras: the colour direction runs from the camera centre (the
+    # eye position the camera was built from, not its translation vector) to
+    # the mean, in world space; the degree-1 basis is c1 (y, z, x) there
+    c0 = 0.5 / math.sqrt(math.pi)
+    c1 = math.sqrt(3.0 / (4.0 * math.pi))
+    rng = np.random.default_rng(11)
+    for eye in ((1.2, -0.6, -3.3), (-2.5, 1.5, 2.0), (0.0, 3.5, 0.5)):
+        cam = scenegen.look_at(eye, (0.1, 0.0, 0.0), 64, 48, 60.0)
+        assert np.abs(np.asarray(cam.t) + np.asarray(eye)).max() > 0.1  # -t is not the centre
+        mu = np.array([0.3, -0.2, 0.4])
+        sh = rng.normal(0.0, 0.3, (4, 3))
+        sh[0] = 1.0
+        pr = oracle_lib.project(one(mu, [-3.0] * 3, sh=sh, deg=1), cam)
+        assert pr["visible"][0]
+        d = (mu - np.asarray(eye)) / np.linalg.norm(mu - np.asarray(eye))
+        expect = 0.5 + c0 * sh[0] + c1 * (sh[1] * d[1] + sh[2] * d[2] + sh[3] * d[0])
+        assert np.all(expect > 0)
+        np.testing.assert_allclose(pr["color"][0], expect, rtol=1e-12)

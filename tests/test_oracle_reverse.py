@@ -102,3 +102,34 @@ def test_single_gaussian_opacity_and_colour_derivative(oracle_lib):
     Y00 = 0.5 / math.sqrt(math.pi)
     np.testing.assert_allclose(g["sh"][0, 0], Y00 * sum_a * np.ones(3), rtol=1e-12)
     assert g["opacity_logits"][0] == pytest.approx(c.sum() * sum_a * (1 - o), rel=1e-12)
+
+
+def test_reverse_beyond_the_tangent_clamp_matches_finite_differences(oracle_lib):
+    # two large Gaussians whose centres lie beyond the Jacobian's tangent
+    # limit (one horizontally, one vertically) but whose extents reach the
+    # image: the clamped tangent makes the covariance independent of the
+    # clamped coordinate, and the reverse must agree with the forward there
+    cam = scenegen.pinhole(64, 48, 60.0, t=(0.0, 0.0, 4.0))
+    limx = 1.3 * 32.0 / cam.fx
+    limy = 1.3 * 24.0 / cam.fy
+    means = np.array([[3.3, 0.1, 0.0], [0.2, 2.6, 0.0]])
+    assert means[0, 0] / 4.0 > limx and means[1, 1] / 4.0 > limy
+    sc = scenegen.Scene(means, np.array([[-0.8, -0.9, -0.85], [-0.85, -0.8, -0.9]]),
+                        np.array([[0.9, 0.1, -0.2, 0.3], [0.8, -0.3, 0.2, 0.1]]), np.array([0.6, 0.9]),
+                        np.random.default_rng(3).normal(0.0, 0.3, (2, 16, 3)) + 0.2, 3)
+    rng = np.random.default_rng(5)
+    wts = rng.uniform(-1.0, 1.0, (3, cam.height, cam.width))
+    g = oracle_lib.reverse(sc, [cam], [wts])
+    out = oracle_lib.render(sc, cam, nthreads=1)
+    assert (out["n_blend"] > 0).sum() > 40
+    picks = []
+    for i in range(2):
+        assert abs(g["opacity_logits"][i]) > 1e-6
+        for a in range(3):
+            picks += [("means", (i, a)), ("log_scales", (i, a))]
+        for a in range(4):
+            picks.append(("quats", (i, a)))
+        picks.append(("opacity_logits", (i,)))
+        picks += [("sh", (i, k, k % 3)) for k in (0, 3, 9, 15)]
+    checked, dropped = fd_check(oracle_lib, sc, cam, wts, g, picks)
+    assert checked >= len(picks) - 2, (checked, dropped)
