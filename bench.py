@@ -109,6 +109,9 @@ class Foveated:
         self.ws_t, self.ws, self.wsn = g.binding._ws(nb)
         self.bg = (ctypes.c_float * 3)(0.0, 0.0, 0.0)
         self.stream = g.binding._stream()
+        # per-point filtered hit counts ([views][n] uint32): off in the timed
+        # step, set to a buffer by the full-size parity test
+        self.hits = None
 
     def fovea(self):
         L, B, g = self.g.lib(), self.g.binding, self
@@ -127,7 +130,8 @@ class Foveated:
         L, B, g = self.g.lib(), self.g.binding, self
         B._check(L.gs_bin_sort(B._ptr(g.splats), g.n, g.C.hp, g.C.dp, g.C.n, g.tile,
                                B._ptr(g.tile_level), B._ptr(g.S.t["qbound"]), B._ptr(g.vals), None,
-                               g.cap, B._ptr(g.ranges), None, B._ptr(g.num), g.ws, g.wsn, g.stream))
+                               g.cap, B._ptr(g.ranges), B._ptr(g.hits), B._ptr(g.num), g.ws, g.wsn,
+                               g.stream))
 
     def raster(self, stats=None):
         L, B, g = self.g.lib(), self.g.binding, self

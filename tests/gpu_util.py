@@ -75,3 +75,17 @@ def rel_l2(a, b):
     a = np.asarray(a, np.float64).ravel()
     b = np.asarray(b, np.float64).ravel()
     return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-30))
+
+
+def per_point_check(gpu, ref, rtol=1e-2, floor=1e-3):
+    """Per-point gradient check beside a relative L2 bar: point i (a row of
+    the [n, ...] arrays) passes if ||g_i - r_i|| <= rtol ||r_i|| + floor *
+    rms_i ||r_i||.  Returns (number of failing points, the largest ratio of
+    error to bound)."""
+    g = np.asarray(gpu, np.float64).reshape(len(gpu), -1)
+    r = np.asarray(ref, np.float64).reshape(len(ref), -1)
+    nr = np.linalg.norm(r, axis=1)
+    rms = float(np.sqrt(np.mean(nr * nr))) if len(nr) else 0.0
+    bound = rtol * nr + floor * rms + 1e-30
+    ratio = np.linalg.norm(g - r, axis=1) / bound
+    return int((ratio > 1.0).sum()), float(ratio.max(initial=0.0))

@@ -8,9 +8,10 @@ projection on a random sample of Gaussians, and its image on sampled pixels
 (random ones, every pixel of each eye's heaviest tile, and pixels of the blend
 bands) against the FP64 oracle's per-pixel compositing.  Config 2 (the plain
 forward: 500k Gaussians, 1280x720) is checked the same way.  Config 5 (3M
-Gaussians, 32 views + 2 eyes) checks that the batched schedule the bench
-times gives the one-view-per-call schedule's results: images bit for bit,
-gradients within the run-to-run spread of float atomics.  Config 4 (1M
+Gaussians, 32 views + 2 eyes) checks the batched schedule the bench times:
+its projection reverse against the oracle's on sampled points (fed with the
+step's own splat gradients), and against the one-view-per-call schedule:
+images bit for bit, gradients within the 1e-3 relative L2 gradient bar.  Config 4 (1M
 Gaussians, forward + backward through autograd) checks sampled pixels and
 that autograd equals the reverse passes called one by one.
 """
@@ -20,7 +21,8 @@ import torch
 
 import oracle
 import scenegen
-from gpu_util import check_envelope, need_gpu, pixel_views, rel_l2, say, splat_np, view_slice
+from gpu_util import (check_envelope, need_gpu, per_point_check, pixel_views, rel_l2, say, splat_np,
+                      view_slice)
 
 pytestmark = pytest.mark.gpu
 
@@ -75,6 +77,7 @@ def test_config3_foveated_frame_full_size():
     say("config 3 full size: bench stages")
     wl = scenegen.config3()
     fr = Foveated(g, wl, 16)
+    fr.hits = torch.empty((fr.C.n, fr.n), dtype=torch.int32, device=fr.image.device)
     for s in fr.STAGES:
         getattr(fr, s)()
     torch.cuda.synchronize()
@@ -92,6 +95,8 @@ def test_config3_foveated_frame_full_size():
     np.testing.assert_array_equal(fr.vals[:nk].cpu().numpy().view(np.uint32), ref_b["vals"])
     ranges = fr.ranges.cpu().numpy().view(np.uint32)
     np.testing.assert_array_equal(ranges, ref_b["ranges"])
+    # per-point hit counts after the level filter, every point of both eyes
+    np.testing.assert_array_equal(fr.hits.cpu().numpy().view(np.uint32), ref_b["hits"])
     del ref_b
     # projection on a sample of Gaussians
     say("config 3: projection sample")
@@ -151,10 +156,10 @@ def test_config2_plain_forward_full_size():
     say(f"config 2: max err {err:.3g}, ambiguous {namb}")
 
 
-def test_config5_batched_equals_one_view_per_call():
+def test_config5_batched_matches_oracle_and_one_view_per_call():
     g = gs()
     from paper_2407_00435_amd.batched import BatchedStep
-    say("config 5 full size: batched vs one view per call")
+    say("config 5 full size: batched step")
     wl = scenegen.config5()
     S = g.SceneTensors(wl.scene)
     cams, eyes, fov = wl.cams, wl.extra["eyes"], wl.extra["eye_foveae"]
@@ -168,15 +173,30 @@ def test_config5_batched_equals_one_view_per_call():
     assert step.keys_ok()
     a = dict(image=step.image.clone(), loss=step.loss.clone(), eyes=step.eye_image.clone(),
              grads={k: v.clone() for k, v in step.grads.items() if v is not None})
-    # the same schedule again: float32 atomics make the gradients vary from run
-    # to run; that spread is the floor for comparing two schedules
-    step.step()
-    torch.cuda.synchronize()
-    assert torch.equal(a["image"], step.image)
-    noise = {k: rel_l2(step.grads[k].cpu().numpy(), a["grads"][k].cpu().numpy()) for k in a["grads"]}
+    # the projection reverse of all 32 views in one call against the oracle's,
+    # fed with the step's own float32 splat gradients, on sampled points (the
+    # stage-wise gradient check: atomics in the compositing reverse do not
+    # enter it)
+    say("config 5: projection reverse of the batched step against the oracle")
+    idx = np.sort(rng.choice(wl.scene.n, 2000, replace=False))
+    sg = step.lane_bufs[0]["sgrads"][:, torch.from_numpy(idx).cuda(), :].cpu().numpy().astype(np.float64)
+    sub = wl.scene.subset(idx)
+    acc = None
+    for v, cam in enumerate(cams):
+        gsplat = dict(mean2d=sg[v][:, 0:2], conic=sg[v][:, 2:5], opacity=sg[v][:, 5], color=sg[v][:, 6:9])
+        acc = oracle.project_bwd(sub, cam, gsplat, acc)
+    for name in ("means", "log_scales", "quats", "opacity_logits", "sh"):
+        gpu = a["grads"][name][torch.from_numpy(idx).cuda()].cpu().numpy()
+        r = rel_l2(gpu, acc[name])
+        nbad, worst = per_point_check(gpu, acc[name], rtol=1e-2, floor=1e-3)
+        say(f"config 5 project_bwd {name}: rel L2 {r:.2e}, points over the per-point bar {nbad}, worst {worst:.2e}")
+        assert r < 1e-3, (name, r)
+        assert nbad <= 2, (name, nbad)
+    del sg
     del step
     torch.cuda.empty_cache()
     g.gs_set_tuning("radix_part", 8192)
+    say("config 5: one view per call")
     plain = BatchedStep(S, cams, target, 16, 1, eyes, fov, eye_batch=1)
     plain.step()
     torch.cuda.synchronize()
@@ -186,19 +206,17 @@ def test_config5_batched_equals_one_view_per_call():
     # the loss is a float32 atomic sum over about 1e8 pixel channels: its
     # rounding depends on the order of the additions
     assert abs(a["loss"].item() - plain.loss.item()) <= 1e-5 * abs(a["loss"].item())
-    # gradients: both schedules run the same kernels, but float32 atomics add in
-    # a different order and the batched projection reverse sums the views'
+    # gradients: both schedules run the same kernels, but float32 atomics add
+    # in a different order and the batched projection reverse sums the views'
     # covariance gradients before mapping them to scales and rotations (one
-    # view per call maps each view's, then adds); over 32 views cancellation
-    # in the small shape gradients amplifies that rounding.  The schedules must
-    # agree within a few times the run-to-run spread of one schedule, and far
-    # below the oracle parity bar for gradients (1e-3 relative L2).
+    # view per call maps each view's, then adds).  Each schedule is held to
+    # the oracle above; between them the bar is the gradient parity bar
+    # (1e-3 relative L2 per parameter group), not a multiple of one sample of
+    # atomic noise.
     errs = {k: rel_l2(a["grads"][k].cpu().numpy(), plain.grads[k].cpu().numpy()) for k in a["grads"]}
     say("config 5: gradient rel L2 between schedules " + ", ".join(f"{k} {e:.2e}" for k, e in errs.items()))
-    say("config 5: run-to-run spread " + ", ".join(f"{k} {e:.2e}" for k, e in noise.items()))
     for k, e in errs.items():
-        assert e <= 4.0 * noise[k] + 1e-5, k
-        assert e < 1e-3, k
+        assert e <= 1e-3, k
 
 
 def test_config4_forward_backward_full_size():

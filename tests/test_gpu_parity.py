@@ -131,6 +131,9 @@ def test_binning_coarse_pair_forms(packed, filtered):
     np.testing.assert_array_equal(bs["keys"].cpu().numpy()[:nk].view(np.uint64), ref["keys"])
     np.testing.assert_array_equal(bs["vals"].cpu().numpy()[:nk].view(np.uint32), ref["vals"])
     np.testing.assert_array_equal(bs["ranges"].cpu().numpy().view(np.uint32), ref["ranges"])
+    # per-point hit counts after the level filter (Comp_i of Eq. 3 after the
+    # Section 4.2 filter) are bit-exact too
+    np.testing.assert_array_equal(bs["hits"].cpu().numpy().view(np.uint32), ref["hits"])
 
 
 def _raster_case(g, sc, cams, tile, bg=(0.0, 0.0, 0.0), dominated=True):
@@ -278,6 +281,8 @@ def test_foveated_matches_oracle(tile, rings, band):
     np.testing.assert_array_equal(bs["keys"].cpu().numpy()[:nk].view(np.uint64), ref_b["keys"])
     np.testing.assert_array_equal(bs["vals"].cpu().numpy()[:nk].view(np.uint32), ref_b["vals"])
     np.testing.assert_array_equal(bs["ranges"].cpu().numpy().view(np.uint32), ref_b["ranges"])
+    # filtered per-point hit counts (Comp_i after the level filter) bit for bit
+    np.testing.assert_array_equal(bs["hits"].cpu().numpy().view(np.uint32), ref_b["hits"])
     # fewer keys than the unfiltered rectangle count
     assert nk < int(sp["tiles_touched"].sum())
     imgs = image_views(img, sizes)
