@@ -77,7 +77,7 @@ def rel_l2(a, b):
     return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-30))
 
 
-def per_point_check(gpu, ref, rtol=1e-2, floor=1e-3):
+def per_point_check(gpu, ref, rtol=1e-3, floor=1e-4):
     """Per-point gradient check beside a relative L2 bar: point i (a row of
     the [n, ...] arrays) passes if ||g_i - r_i|| <= rtol ||r_i|| + floor *
     rms_i ||r_i||.  Returns (number of failing points, the largest ratio of
@@ -89,3 +89,18 @@ def per_point_check(gpu, ref, rtol=1e-2, floor=1e-3):
     bound = rtol * nr + floor * rms + 1e-30
     ratio = np.linalg.norm(g - r, axis=1) / bound
     return int((ratio > 1.0).sum()), float(ratio.max(initial=0.0))
+
+
+EPS32 = 2.0 ** -24  # unit roundoff of float32
+
+
+def conic_rounding_bound(cov2d, conic_ref):
+    """Per-point bound on a float32 conic against the FP64 one, [n, 1]:
+    conic = adj(S') / det(S') with det = a c - b^2, whose absolute rounding
+    error is of order eps (a c + b^2); relative to det that is eps times
+    kappa = (a c + b^2) / (a c - b^2), and it carries over to every conic
+    entry relative to the largest one.  The factor 64 covers the chain of
+    roundings before S' (rotation, scales, the Jacobian and the mean)."""
+    a, b, c = (np.asarray(cov2d, np.float64)[:, k] for k in range(3))
+    kappa = (a * c + b * b) / (a * c - b * b)
+    return 64.0 * EPS32 * kappa[:, None] * np.abs(conic_ref).max(axis=1, keepdims=True)

@@ -10,7 +10,7 @@ import torch
 
 import oracle
 import scenegen
-from gpu_util import need_gpu, pixel_views, rel_l2, say, splat_np, view_slice
+from gpu_util import need_gpu, per_point_check, pixel_views, rel_l2, say, splat_np, view_slice
 
 pytestmark = pytest.mark.gpu
 
@@ -118,9 +118,17 @@ def test_fr_reverse_parameters_match_oracle():
                           np.asarray(sc.lvl_sh_dc, np.float64))
     ref = oracle.fr_reverse(sc64, cams, tabs, dls)
     for k in ("means", "log_scales", "quats", "sh", "lvl_opacity_logits", "lvl_sh_dc"):
-        e = rel_l2(pg[k].cpu().numpy().astype(np.float64), ref[k])
-        say(f"{k}: rel L2 {e:.2e}")
+        gpu, r = pg[k].cpu().numpy().astype(np.float64), ref[k]
+        e = rel_l2(gpu, r)
+        if k.startswith("lvl_"):  # [L][n][...] -> points first
+            gpu, r = np.moveaxis(gpu, 1, 0), np.moveaxis(r, 1, 0)
+        # point by point: at most 0.2 % of the points beyond 1e-3 of their
+        # own norm + 1e-4 of the rms norm (threshold flips between float32
+        # and float64 move a point's gradient by a whole pair's contribution)
+        nbad, worst = per_point_check(gpu, r)
+        say(f"{k}: rel L2 {e:.2e}, points over the per-point bar {nbad}, worst {worst:.2e}")
         assert e < 1e-3, k
+        assert nbad <= 0.002 * sc.n, (k, nbad)
     # base logit and DC are unused when every level has its own version
     assert float(pg["opacity_logits"].abs().max()) == 0.0
     assert float(pg["sh"][:, 0, :].abs().max()) == 0.0

@@ -21,7 +21,7 @@ import torch
 
 import oracle
 import scenegen
-from gpu_util import (check_envelope, need_gpu, per_point_check, pixel_views, rel_l2, say, splat_np,
+from gpu_util import (check_envelope, conic_rounding_bound, need_gpu, per_point_check, pixel_views, rel_l2, say, splat_np,
                       view_slice)
 
 pytestmark = pytest.mark.gpu
@@ -49,7 +49,7 @@ def check_projection(sp, lvl, scene, cams, idx, levels):
         m = ref["mean2d"][vis]
         assert np.all(np.abs(s["mean2d"][vis] - m) <= 1e-4 * (1 + np.abs(m))), "mean2d"
         cn = ref["conic"][vis]
-        assert np.all(np.abs(s["conic"][vis] - cn) <= 2e-3 * np.abs(cn).max(axis=1, keepdims=True)), "conic"
+        assert np.all(np.abs(s["conic"][vis] - cn) <= conic_rounding_bound(ref["cov2d"][vis], cn)), "conic"
         np.testing.assert_allclose(s["depth"][vis], ref["depth"][vis], rtol=2e-6)
         np.testing.assert_allclose(s["opacity"], ref["opacity"], atol=2e-6)
         np.testing.assert_allclose(s["color"][vis], ref["color"][vis], atol=2e-5)
@@ -107,24 +107,18 @@ def test_config3_foveated_frame_full_size():
     pl = pixel_views(fr.pix_level, sizes)
     pw = pixel_views(fr.pix_weight, sizes)
     img = fr.image.cpu().numpy()
-    off_px, off_t = 0, 0
+    off_px = 0
     for v, (W, H) in enumerate(sizes):
-        tiles_x, tiles_y = (W + T - 1) // T, (H + T - 1) // T
-        band = np.argwhere(pw[v] > 0)
-        band = band[rng.choice(len(band), min(800, len(band)), replace=False)][:, ::-1]
-        pix = sample_pixels(rng, W, H, T, ranges[off_t:off_t + tiles_x * tiles_y], tiles_x, band)
-        say(f"config 3: eye {v}, {len(pix)} sampled pixels")
+        say(f"config 3: eye {v}, all {W * H} pixels against the oracle")
         proj = oracle.splats_to_proj(view_slice(sp, v))
         proj["lvl_opacity"] = lvl[v, :, :, 3].T.astype(np.float64).copy()
         proj["lvl_color"] = lvl[v, :, :, 0:3].transpose(1, 0, 2).astype(np.float64).copy()
         ref = oracle.composite(proj, W, H, qbound=wl.scene.qbound, pix_lo=pl[v].ravel(),
-                               pix_w=pw[v].ravel().astype(np.float64), levels=True, pixels=pix, nthreads=16)
-        plane = img[3 * off_px:3 * (off_px + W * H)].reshape(3, H, W)
-        gpu = plane[:, pix[:, 1], pix[:, 0]].T
+                               pix_w=pw[v].ravel().astype(np.float64), levels=True, nthreads=16)
+        gpu = img[3 * off_px:3 * (off_px + W * H)].reshape(3, H, W).transpose(1, 2, 0)
         err, namb = check_envelope(gpu, ref, max_unresolved_frac=1e-3)
         say(f"config 3: eye {v}, max err {err:.3g}, ambiguous {namb}")
         off_px += W * H
-        off_t += tiles_x * tiles_y
 
 
 def test_config2_plain_forward_full_size():
@@ -149,9 +143,11 @@ def test_config2_plain_forward_full_size():
     rng = np.random.default_rng(2)
     idx = np.sort(rng.choice(wl.scene.n, 3000, replace=False))
     check_projection(sp, None, wl.scene, wl.cams, idx, levels=False)
-    pix = sample_pixels(rng, W, H, T, ranges, (W + T - 1) // T, n_random=3000)
-    ref = oracle.composite(oracle.splats_to_proj(view_slice(sp, 0)), W, H, pixels=pix, nthreads=16)
-    gpu = out["image"].cpu().numpy().reshape(3, H, W)[:, pix[:, 1], pix[:, 0]].T
+    # every pixel of the frame against the oracle's per-pixel compositing of
+    # the same splats
+    say("config 2: all 921600 pixels against the oracle")
+    ref = oracle.composite(oracle.splats_to_proj(view_slice(sp, 0)), W, H, nthreads=16)
+    gpu = out["image"].cpu().numpy().reshape(3, H, W).transpose(1, 2, 0)
     err, namb = check_envelope(gpu, ref, max_unresolved_frac=1e-3)
     say(f"config 2: max err {err:.3g}, ambiguous {namb}")
 
@@ -188,10 +184,10 @@ def test_config5_batched_matches_oracle_and_one_view_per_call():
     for name in ("means", "log_scales", "quats", "opacity_logits", "sh"):
         gpu = a["grads"][name][torch.from_numpy(idx).cuda()].cpu().numpy()
         r = rel_l2(gpu, acc[name])
-        nbad, worst = per_point_check(gpu, acc[name], rtol=1e-2, floor=1e-3)
+        nbad, worst = per_point_check(gpu, acc[name])
         say(f"config 5 project_bwd {name}: rel L2 {r:.2e}, points over the per-point bar {nbad}, worst {worst:.2e}")
         assert r < 1e-3, (name, r)
-        assert nbad <= 2, (name, nbad)
+        assert nbad == 0, (name, nbad)
     del sg
     del step
     torch.cuda.empty_cache()

@@ -15,8 +15,8 @@ import torch
 
 import oracle
 import scenegen
-from gpu_util import (IMG_TOL, check_envelope, image_views, need_gpu, pixel_views, rel_l2, say,
-                      splat_np, view_slice)
+from gpu_util import (IMG_TOL, check_envelope, conic_rounding_bound, image_views, need_gpu, per_point_check,
+                      pixel_views, rel_l2, say, splat_np, view_slice)
 
 pytestmark = pytest.mark.gpu
 
@@ -63,7 +63,13 @@ def test_projection_matches_oracle(deg):
         assert np.all(np.abs(s["mean2d"][vis] - m) <= 1e-4 * (1 + np.abs(m))), "mean2d"
         cn = ref["conic"][vis]
         scale = np.abs(cn).max(axis=1, keepdims=True)
-        assert np.all(np.abs(s["conic"][vis] - cn) <= 2e-3 * scale), "conic"
+        # conic: within float32 rounding of the FP64 inverse, as propagated
+        # through the determinant's cancellation
+        dc = np.abs(s["conic"][vis] - cn)
+        bound = conic_rounding_bound(ref["cov2d"][vis], cn)
+        say(f"view {v}: conic error / row max {float((dc / scale).max()):.2e}, "
+            f"/ rounding bound {float((dc / bound).max()):.3f}")
+        assert np.all(dc <= bound), "conic"
         np.testing.assert_allclose(s["depth"][vis], ref["depth"][vis], rtol=2e-6)
         np.testing.assert_allclose(s["opacity"], ref["opacity"], atol=2e-6)
         np.testing.assert_allclose(s["color"][vis], ref["color"][vis], atol=2e-5)
@@ -389,16 +395,24 @@ def test_backward_stagewise_matches_oracle(tile):
         for name, sl in (("mean2d", slice(0, 2)), ("conic", slice(2, 5)), ("opacity", slice(5, 6)),
                          ("color", slice(6, 9))):
             r = rel_l2(gn[v][:, sl], ref[name].reshape(sc.n, -1))
-            say(f"view {v} {name}: rel L2 {r:.2e}")
+            # point by point as well: at most 0.2 % of the points may differ
+            # by more than 1e-3 of their own norm + 1e-4 of the rms norm (a
+            # pair at a cut-off flips between float32 and float64 and moves
+            # its point by a whole contribution)
+            nbad, worst = per_point_check(gn[v][:, sl], ref[name].reshape(sc.n, -1))
+            say(f"view {v} {name}: rel L2 {r:.2e}, points over the per-point bar {nbad}, worst {worst:.2e}")
             assert r < 1e-3, (v, name, r)
+            assert nbad <= 0.002 * sc.n, (v, name, nbad)
         # projection reverse fed with the same (GPU) splat gradients
         gsplat = dict(mean2d=gn[v][:, 0:2].astype(np.float64), conic=gn[v][:, 2:5].astype(np.float64),
                       opacity=gn[v][:, 5].astype(np.float64), color=gn[v][:, 6:9].astype(np.float64))
         acc = oracle.project_bwd(sc, cam, gsplat, acc)
     for name in ("means", "log_scales", "quats", "opacity_logits", "sh"):
         r = rel_l2(pg[name].cpu().numpy(), acc[name])
-        say(f"project_bwd {name}: rel L2 {r:.2e}")
+        nbad, worst = per_point_check(pg[name].cpu().numpy(), acc[name])
+        say(f"project_bwd {name}: rel L2 {r:.2e}, points over the per-point bar {nbad}, worst {worst:.2e}")
         assert r < 1e-4, (name, r)
+        assert nbad == 0, (name, nbad)
 
 
 def test_autograd_matches_oracle_reverse_fd_subcase():
@@ -422,8 +436,10 @@ def test_autograd_matches_oracle_reverse_fd_subcase():
     ref = oracle.reverse(sc, [cam], [gimg])
     for name in ("means", "log_scales", "quats", "opacity_logits", "sh"):
         r = rel_l2(params[name].grad.cpu().numpy(), ref[name])
-        say(f"autograd {name}: rel L2 {r:.2e}")
+        nbad, worst = per_point_check(params[name].grad.cpu().numpy(), ref[name])
+        say(f"autograd {name}: rel L2 {r:.2e}, points over the per-point bar {nbad}, worst {worst:.2e}")
         assert r < 1e-3, (name, r)
+        assert nbad <= 0.002 * sc.n, (name, nbad)
 
 
 def test_empty_and_culled_scenes_give_background():
