@@ -10,6 +10,12 @@
  * colour and blends the rings at their borders.
  *
  * Conventions shared by every entry point
+ *   - Calls that launch work, or whose result depends on launch choices,
+ *     take a context (gs_ctx, from gs_create) first.  A context holds host
+ *     state only: the device it was made for and its tuning (launch choices
+ *     that never change results).  Use one context per host thread; calls
+ *     with different contexts may run concurrently on different threads.
+ *     The context's device must be the calling thread's current device.
  *   - All arrays named "device" are device (HBM) pointers owned by the
  *     caller; the library never allocates, frees or retains them.  Scratch
  *     memory comes in through `workspace` (device, 256-byte aligned, at least
@@ -21,6 +27,10 @@
  *     error a negative status is returned, nothing is enqueued, and
  *     gs_last_error() returns a message (thread-local, valid until the next
  *     call on the same thread).
+ *   - Every workspace begins with a 256-byte status header: the key count
+ *     the last binning that used the workspace required and the capacity it
+ *     had.  A capacity overflow is found on the device, so it cannot be a
+ *     return status of the (asynchronous) call; gs_poll_status reads it.
  *   - Views: `cams_host` and `cams_dev` hold the same `n_views` cameras, on
  *     the host (read for validation and launch sizes) and on the device
  *     (read by kernels).  Tiles of all views form one global tile space:
@@ -44,11 +54,14 @@ extern "C" {
 
 enum {
     GS_OK = 0,
-    GS_ERR_INVALID = -1,     /* bad argument (null pointer, size, alignment) */
+    GS_ERR_INVALID = -1,     /* bad argument (null pointer, size, alignment, context) */
     GS_ERR_UNSUPPORTED = -2, /* valid but unsupported (SH degree > 3, tile size) */
-    GS_ERR_CAPACITY = -3,    /* workspace too small */
+    GS_ERR_CAPACITY = -3,    /* workspace too small, or (gs_poll_status) key capacity exceeded */
     GS_ERR_HIP = -4          /* a HIP runtime call or launch failed */
 };
+
+/* Library context (opaque; host state only). */
+typedef struct gs_ctx gs_ctx;
 
 /* Pinhole camera, OpenCV frame (x right, y down, z forward).  A world point x
  * maps to camera space as R x + t (R row-major).  Pixel (i, j) is sampled at
@@ -132,13 +145,35 @@ const char *gs_last_error(void);
 /* ABI version (bumped on any layout change). */
 int gs_version(void);
 
+/* Creates a context for HIP device `device` with the default tuning (the
+ * GS_RADIX_PART environment variable, if 4096, 8192 or 16384, sets the sort
+ * partition).  *out is owned by the caller and released with gs_destroy.
+ * Fails with GS_ERR_INVALID for a device that does not exist.  Without a
+ * usable HIP runtime the context still serves host-only calls (workspace
+ * sizes, argument checks); calls that launch work then fail. */
+int gs_create(gs_ctx **out, int device);
+
+/* Releases a context (NULL is a no-op).  Calls already enqueued with it are
+ * unaffected: a context holds no device state. */
+int gs_destroy(gs_ctx *ctx);
+
+/* Status of the last binning (gs_bin_sort, gs_render_fwd,
+ * gs_render_foveated) that used `workspace` (device, the call's workspace):
+ * *status = GS_OK, or GS_ERR_CAPACITY if it needed more keys than its
+ * key_capacity (its outputs are then invalid: ranges are empty and images
+ * show the background); *required_keys (nullable) = the keys it needed.
+ * Reads the workspace's header with a blocking copy: call it after the
+ * stream that ran the binning has been synchronised, outside graph capture.
+ * The header of a workspace no binning has used is undefined. */
+int gs_poll_status(gs_ctx *ctx, const void *workspace, int *status, uint64_t *required_keys);
+
 /* Host helper: total tiles and pixels of the global spaces. */
 int gs_tile_count(const gs_camera *cams_host, int n_views, int tile_size,
                   int64_t *n_tiles, int64_t *n_pixels);
 
 /* Bytes of workspace needed by gs_bin_sort / gs_rasterize_* / gs_render_*
  * for these views, n points and a key capacity. */
-size_t gs_workspace_bytes(const gs_camera *cams_host, int n_views, int32_t n,
+size_t gs_workspace_bytes(gs_ctx *ctx, const gs_camera *cams_host, int n_views, int32_t n,
                           int tile_size, uint64_t key_capacity);
 
 /* Projection (Section 2.1 "Projection"; Eq. 1b, 1c).
@@ -150,7 +185,7 @@ size_t gs_workspace_bytes(const gs_camera *cams_host, int n_views, int32_t n,
  * orthonormal SH basis of the unit direction from the camera centre to mu.
  * lvl_rgba (device, nullable) [n_views][n][n_levels][4]: per-level colour
  * and opacity (rgb, opacity) when the scene has n_levels > 0. */
-int gs_project(const gs_scene *scene, const gs_camera *cams_host, const gs_camera *cams_dev,
+int gs_project(gs_ctx *ctx, const gs_scene *scene, const gs_camera *cams_host, const gs_camera *cams_dev,
                int n_views, int tile_size, gs_splat *splats, float *lvl_rgba, void *stream);
 
 /* Tile binning and (tile, depth) sort (Section 2.1 "Sorting"; Section 4.2
@@ -165,11 +200,13 @@ int gs_project(const gs_scene *scene, const gs_camera *cams_host, const gs_camer
  *   tile_ranges [n_tiles][2]   [begin, end) of each tile's run in vals
  *   hits [n_views][n]          nullable; keys emitted per point (Comp_i)
  *   num_keys [1] (uint64)      total keys required.  If it exceeds
- *                              key_capacity the outputs are truncated and
- *                              invalid; the caller re-runs with a larger
- *                              capacity (read num_keys after synchronising).
+ *                              key_capacity the outputs are invalid (no
+ *                              tile has keys); the caller re-runs with a
+ *                              larger capacity (read num_keys, or
+ *                              gs_poll_status on the workspace, after
+ *                              synchronising).
  * key_capacity must be < 2^32. */
-int gs_bin_sort(const gs_splat *splats, int32_t n, const gs_camera *cams_host,
+int gs_bin_sort(gs_ctx *ctx, const gs_splat *splats, int32_t n, const gs_camera *cams_host,
                 const gs_camera *cams_dev, int n_views, int tile_size,
                 const uint8_t *tile_level, const uint8_t *qbound,
                 uint32_t *vals, uint64_t *keys, uint64_t key_capacity,
@@ -190,7 +227,7 @@ int gs_bin_sort(const gs_splat *splats, int32_t n, const gs_camera *cams_host,
  * (pixel, point) pairs, evaluated pairs, staged list entries and entries kept
  * by the per-wave footprint test; a separate instrumented kernel runs when
  * stats is non-NULL. */
-int gs_rasterize_fwd(const gs_splat *splats, int32_t n, const gs_camera *cams_host,
+int gs_rasterize_fwd(gs_ctx *ctx, const gs_splat *splats, int32_t n, const gs_camera *cams_host,
                      const gs_camera *cams_dev, int n_views, int tile_size,
                      const uint32_t *vals, const uint32_t *tile_ranges, const float *bg,
                      float *image, float *final_T, uint32_t *n_contrib, uint32_t *dominated_px,
@@ -202,7 +239,7 @@ int gs_rasterize_fwd(const gs_splat *splats, int32_t n, const gs_camera *cams_ho
  * opacity and colour.  The per-pixel decisions (extent, skip, stop, the alpha
  * clamp) are held constant.  A splat's sums over the tiles it reaches are
  * added with float atomics, so their last bits depend on scheduling. */
-int gs_rasterize_bwd(const gs_splat *splats, int32_t n, const gs_camera *cams_host,
+int gs_rasterize_bwd(gs_ctx *ctx, const gs_splat *splats, int32_t n, const gs_camera *cams_host,
                      const gs_camera *cams_dev, int n_views, int tile_size,
                      const uint32_t *vals, const uint32_t *tile_ranges, const float *bg,
                      const float *final_T, const uint32_t *n_contrib, const float *dL_dimage,
@@ -217,7 +254,7 @@ int gs_rasterize_bwd(const gs_splat *splats, int32_t n, const gs_camera *cams_ho
  * scene; splats (the forward's output) is accepted for interface symmetry and
  * not read.  A (view, point) whose gradient record is all zero, or that the
  * forward culls (near plane, degenerate covariance), contributes nothing. */
-int gs_project_bwd(const gs_scene *scene, const gs_camera *cams_host, const gs_camera *cams_dev,
+int gs_project_bwd(gs_ctx *ctx, const gs_scene *scene, const gs_camera *cams_host, const gs_camera *cams_dev,
                    int n_views, const gs_splat *splats, const gs_splat_grad *grads,
                    float *d_means, float *d_log_scales, float *d_quats,
                    float *d_opacity_logits, float *d_sh, int accumulate, void *stream);
@@ -231,7 +268,7 @@ int gs_project_bwd(const gs_scene *scene, const gs_camera *cams_host, const gs_c
  * fov_host: n_eyes structs (host).  Outputs (device): pix_level [n_pixels]
  * uint8, pix_weight [n_pixels] float, tile_level [n_tiles][2] uint8 (lo, hi).
  * n_levels is 1..4. */
-int gs_fovea_prep(const gs_camera *cams_host, const gs_camera *cams_dev, const gs_fovea *fov_host,
+int gs_fovea_prep(gs_ctx *ctx, const gs_camera *cams_host, const gs_camera *cams_dev, const gs_fovea *fov_host,
                   int n_eyes, int tile_size, int n_levels, uint8_t *pix_level, float *pix_weight,
                   uint8_t *tile_level, void *stream);
 
@@ -248,7 +285,7 @@ int gs_fovea_prep(const gs_camera *cams_host, const gs_camera *cams_dev, const g
  * receive per pixel the final transmittance and the last blended run
  * position of the two accumulators (levels lo and lo + 1): the start of
  * gs_rasterize_foveated_bwd. */
-int gs_rasterize_foveated(const gs_splat *splats, const float *lvl_rgba, int32_t n,
+int gs_rasterize_foveated(gs_ctx *ctx, const gs_splat *splats, const float *lvl_rgba, int32_t n,
                           const uint8_t *qbound, int n_levels, const gs_camera *cams_host,
                           const gs_camera *cams_dev, int n_eyes, int tile_size,
                           const uint32_t *vals, const uint32_t *tile_ranges,
@@ -266,7 +303,7 @@ int gs_rasterize_foveated(const gs_splat *splats, const float *lvl_rgba, int32_t
  * [n_levels][4]: per level, the gradient with respect to its colour (r, g,
  * b) and opacity.  Decisions (extent, filter, skip, stop, clamp) are held
  * constant. */
-int gs_rasterize_foveated_bwd(const gs_splat *splats, const float *lvl_rgba, int32_t n,
+int gs_rasterize_foveated_bwd(gs_ctx *ctx, const gs_splat *splats, const float *lvl_rgba, int32_t n,
                               const uint8_t *qbound, int n_levels, const gs_camera *cams_host,
                               const gs_camera *cams_dev, int n_eyes, int tile_size,
                               const uint32_t *vals, const uint32_t *tile_ranges,
@@ -284,7 +321,7 @@ int gs_rasterize_foveated_bwd(const gs_splat *splats, const float *lvl_rgba, int
  * gradients sum over the levels.  Outputs as in gs_project_bwd, plus the two
  * level arrays (nullable when the scene has no level versions);
  * accumulate = 1 adds to the outputs. */
-int gs_project_bwd_levels(const gs_scene *scene, const gs_camera *cams_host, const gs_camera *cams_dev,
+int gs_project_bwd_levels(gs_ctx *ctx, const gs_scene *scene, const gs_camera *cams_host, const gs_camera *cams_dev,
                           int n_views, const gs_splat *splats, const gs_splat_grad *grads,
                           const float *lvl_grads, float *d_means, float *d_log_scales, float *d_quats,
                           float *d_opacity_logits, float *d_sh, float *d_lvl_opacity_logits,
@@ -296,9 +333,9 @@ int gs_project_bwd_levels(const gs_scene *scene, const gs_camera *cams_host, con
  * gs_render_workspace_bytes().  num_keys (device, uint64) receives the
  * required key count as in gs_bin_sort (outputs are invalid if it exceeds
  * key_capacity). */
-size_t gs_render_workspace_bytes(const gs_camera *cams_host, int n_views, int32_t n,
+size_t gs_render_workspace_bytes(gs_ctx *ctx, const gs_camera *cams_host, int n_views, int32_t n,
                                  int n_levels, int tile_size, uint64_t key_capacity);
-int gs_render_foveated(const gs_scene *scene, const gs_camera *cams_host,
+int gs_render_foveated(gs_ctx *ctx, const gs_scene *scene, const gs_camera *cams_host,
                        const gs_camera *cams_dev, const gs_fovea *fov_host, int n_eyes,
                        int tile_size, const float *bg, float *image, uint64_t key_capacity,
                        uint64_t *num_keys, void *workspace, size_t workspace_bytes,
@@ -308,7 +345,7 @@ int gs_render_foveated(const gs_scene *scene, const gs_camera *cams_host,
  * compositing.  Same workspace rule as gs_render_foveated (n_levels = 0).
  * splats, vals, tile_ranges, final_T, n_contrib are outputs kept for a
  * backward pass (device; n_contrib/final_T [n_pixels], vals [key_capacity]). */
-int gs_render_fwd(const gs_scene *scene, const gs_camera *cams_host, const gs_camera *cams_dev,
+int gs_render_fwd(gs_ctx *ctx, const gs_scene *scene, const gs_camera *cams_host, const gs_camera *cams_dev,
                   int n_views, int tile_size, const float *bg, gs_splat *splats,
                   uint32_t *vals, uint32_t *tile_ranges, uint64_t key_capacity,
                   uint64_t *num_keys, float *image, float *final_T, uint32_t *n_contrib,
@@ -322,7 +359,7 @@ int gs_render_fwd(const gs_scene *scene, const gs_camera *cams_host, const gs_ca
  * zeroes it first).  The sum is taken in float32 with block partials added
  * atomically, so its last bits depend on scheduling.  Launches kernels
  * only, so it may be captured in a graph. */
-int gs_l1_grad(const float *image, const float *target, uint64_t n, float scale, float *dL_dimage,
+int gs_l1_grad(gs_ctx *ctx, const float *image, const float *target, uint64_t n, float scale, float *dL_dimage,
                float *loss, int reset, void *stream);
 
 /* Computational efficiency of every point (Section 3.2, the CE equation):
@@ -332,7 +369,7 @@ int gs_l1_grad(const float *image, const float *target, uint64_t n, float scale,
  * CE = the maximum over the views (0 for views where it uses no tile).  The
  * ratio is a correctly rounded float32 division.  dominated, hits: device
  * uint32 [n_views][n]; ce: device float [n]. */
-int gs_ce_score(const uint32_t *dominated, const uint32_t *hits, int32_t n, int n_views, float *ce,
+int gs_ce_score(gs_ctx *ctx, const uint32_t *dominated, const uint32_t *hits, int32_t n, int n_views, float *ce,
                 void *stream);
 
 /* Selection of the k points with the lowest CE for removal (the pruning
@@ -343,7 +380,7 @@ int gs_ce_score(const uint32_t *dominated, const uint32_t *hits, int32_t n, int 
  * clamped to [0, n].  Workspace: gs_select_workspace_bytes(n) bytes, 256-byte
  * aligned (not needed when k = 0). */
 size_t gs_select_workspace_bytes(int32_t n);
-int gs_select_lowest(const float *ce, int32_t n, int32_t k, uint8_t *mask, uint32_t *idx, void *workspace,
+int gs_select_lowest(gs_ctx *ctx, const float *ce, int32_t n, int32_t k, uint8_t *mask, uint32_t *idx, void *workspace,
                      size_t workspace_bytes, void *stream);
 
 /* Weighted scale and its gradient (Section 3.3): ws = gamma / (N V) *
@@ -355,12 +392,12 @@ int gs_select_lowest(const float *ce, int32_t n, int32_t k, uint8_t *mask, uint3
  * (accumulate = 0) or added to (1), e.g. on top of the render's gradient to
  * form the composite loss of Section 3.3.  ws: device float, overwritten;
  * summed in float32 with atomics (last bits depend on scheduling). */
-int gs_weighted_scale(const float *log_scales, const uint32_t *hits, int32_t n, int n_views, float threshold,
+int gs_weighted_scale(gs_ctx *ctx, const float *log_scales, const uint32_t *hits, int32_t n, int n_views, float threshold,
                       float gamma, float *ws, float *d_log_scales, int accumulate, void *stream);
 
 /* Graph capture of a sequence of calls on one stream (every entry point
- * above except gs_sort_pairs launches kernels only: no allocation, host
- * synchronisation or host copies, so a fixed sequence of them on
+ * above except gs_sort_pairs and gs_poll_status launches kernels only: no
+ * allocation, host synchronisation or host copies, so a fixed sequence of them on
  * preallocated buffers can be recorded once and replayed).
  * gs_graph_begin starts capture on `stream` (not the legacy default
  * stream); the calls that follow on that stream are recorded, not run;
@@ -375,7 +412,7 @@ int gs_graph_end(void *stream, gs_graph **graph);
 int gs_graph_launch(gs_graph *graph, void *stream);
 int gs_graph_destroy(gs_graph *graph);
 
-/* Process-wide tuning knob (not thread-safe against concurrent calls):
+/* Tuning of a context (launch choices; results do not depend on them):
  *   "radix_part": keys per sort workgroup, 4096, 8192 (default) or 16384.
  *   "raster_queue": 0 (default): one workgroup per tile; 1: when the call
  *                   has a workspace, the forward compositors run as a
@@ -396,9 +433,11 @@ int gs_graph_destroy(gs_graph *graph);
  *                   an 8-byte value (the form used above 2^17 super-tiles).
  *                   The keys and ranges are identical either way.
  * Workspace sizes returned by gs_workspace_bytes / gs_render_workspace_bytes
- * depend on these settings: size workspaces after setting them.
- * The GS_RADIX_PART environment variable sets the same default. */
-int gs_set_tuning(const char *name, int64_t value);
+ * depend on these settings: size workspaces after setting them.  The
+ * setting applies to the calls made afterwards with this context (a graph
+ * keeps the launches it recorded). */
+int gs_set_tuning(gs_ctx *ctx, const char *name, int64_t value);
+int gs_get_tuning(gs_ctx *ctx, const char *name, int64_t *value);
 
 /* Stable LSD radix sort of n (uint32 key, uint32 value) pairs by the low
  * `bits` bits of the key (1..32) -- the sort of gs_bin_sort's depth and tile
@@ -406,7 +445,7 @@ int gs_set_tuning(const char *name, int64_t value);
  * place; keys_tmp, vals_tmp (device, [n]) are scratch; equal keys keep their
  * input order.  Key bits above `bits` must be zero.  n < 2^32. */
 size_t gs_sort_workspace_bytes(uint64_t n);
-int gs_sort_pairs(uint32_t *keys, uint32_t *vals, uint32_t *keys_tmp, uint32_t *vals_tmp,
+int gs_sort_pairs(gs_ctx *ctx, uint32_t *keys, uint32_t *vals, uint32_t *keys_tmp, uint32_t *vals_tmp,
                   uint64_t n, int bits, void *workspace, size_t workspace_bytes, void *stream);
 
 #ifdef __cplusplus

@@ -6,7 +6,7 @@ marshals torch device tensors into the C calls.  Importing it loads the
 library and fails loudly if it has not been built.
 """
 from .binding import (  # noqa: F401
-    Cameras, SceneTensors, GsError, lib, lib_path,
+    Cameras, SceneTensors, GsError, lib, raw_lib, lib_path, Context, context, gs_get_tuning,
     gs_project, gs_bin_sort, gs_rasterize_fwd, gs_rasterize_bwd, gs_project_bwd,
     gs_fovea_prep, gs_rasterize_foveated, gs_render_foveated, gs_render_fwd,
     gs_workspace_bytes, gs_render_workspace_bytes, gs_tile_count, splat_fields, gs_sort_pairs, gs_set_tuning,

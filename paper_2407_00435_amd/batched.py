@@ -239,11 +239,17 @@ class BatchedStep:
             # join the eyes' branch
             self.stream.wait_stream(self.eye_stream)
 
-    def step(self):
-        """Run one step eagerly on this object's stream."""
+    def step(self, check: bool = False):
+        """Run one step eagerly on this object's stream.  check: synchronise
+        and raise GsError if a sub-batch or eye group needed more keys than
+        its capacity (its images and gradients are then invalid)."""
         self.stream.wait_stream(torch.cuda.current_stream())
         self._enqueue()
         torch.cuda.current_stream().wait_stream(self.stream)
+        if check and not self.keys_ok():
+            raise B.GsError(B.GS_ERR_CAPACITY, "a sub-batch needed more keys than its capacity: "
+                                               f"required {self.num_keys.cpu().tolist()}, capacities "
+                                               f"{[g['cap'] for g in self.groups]}")
 
     def capture(self):
         """Record one step as a graph (nothing runs during the recording)."""
@@ -254,6 +260,9 @@ class BatchedStep:
         return self.graph
 
     def replay(self):
+        """Replay the recorded step.  Capacities are those of the recording:
+        callers whose scene moves read keys_ok() after synchronising (or
+        rebuild the step) to find an overflowed sub-batch."""
         self.stream.wait_stream(torch.cuda.current_stream())
         self.graph.launch(self.stream)
         torch.cuda.current_stream().wait_stream(self.stream)

@@ -3,11 +3,19 @@
 Argument marshalling only: torch tensors supply device pointers and the
 current HIP stream; every computation happens in ``libgsmi.so``.  Function
 names match the C entry points.
+
+Contexts: the C calls that launch work take a ``gs_ctx`` first.  Each host
+thread has a current :class:`Context` (one per thread and device, made on
+first use, or the one entered with ``with Context(...)``); :func:`lib`
+returns the library with that context bound as the first argument of every
+call that takes one, so the wrappers below and their callers pass the other
+arguments only.  :func:`raw_lib` is the unbound library.
 """
 from __future__ import annotations
 
 import ctypes
 import os
+import threading
 
 import numpy as np
 import torch
@@ -62,6 +70,10 @@ _PF = ctypes.POINTER(GsFovea)
 _SIGS = {
     "gs_last_error": ([], ctypes.c_char_p),
     "gs_version": ([], _I),
+    "gs_create": ([ctypes.POINTER(_VP), _I], _I),
+    "gs_destroy": ([_VP], _I),
+    "gs_poll_status": ([_VP, ctypes.POINTER(_I), ctypes.POINTER(_U64)], _I),
+    "gs_get_tuning": ([ctypes.c_char_p, ctypes.POINTER(ctypes.c_int64)], _I),
     "gs_tile_count": ([_PC, _I, _I, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64)], _I),
     "gs_workspace_bytes": ([_PC, _I, _I32, _I, _U64], _SZ),
     "gs_render_workspace_bytes": ([_PC, _I, _I32, _I, _I, _U64], _SZ),
@@ -96,10 +108,21 @@ _SIGS = {
     "gs_graph_launch": ([_VP, _VP], _I),
     "gs_graph_destroy": ([_VP], _I),
 }
+# calls whose first C argument is the context (the signatures above list the
+# other arguments; the context pointer is prepended here)
+CTX_FIRST = frozenset((
+    "gs_workspace_bytes", "gs_render_workspace_bytes", "gs_project", "gs_bin_sort", "gs_rasterize_fwd",
+    "gs_rasterize_bwd", "gs_project_bwd", "gs_fovea_prep", "gs_rasterize_foveated",
+    "gs_rasterize_foveated_bwd", "gs_project_bwd_levels", "gs_render_foveated", "gs_render_fwd",
+    "gs_l1_grad", "gs_ce_score", "gs_select_lowest", "gs_weighted_scale", "gs_sort_pairs",
+    "gs_set_tuning", "gs_get_tuning", "gs_poll_status"))
+for _name in CTX_FIRST:
+    _a, _r = _SIGS[_name]
+    _SIGS[_name] = ([_VP] + list(_a), _r)
 EXPORTED = tuple(_SIGS)
 
 
-def lib():
+def raw_lib():
     """Load libgsmi.so (raises if it has not been built: there is no fallback)."""
     global _lib
     if _lib is None:
@@ -115,9 +138,99 @@ def lib():
     return _lib
 
 
+class Context:
+    """A library context (``gs_ctx``) for one device: its tuning applies to
+    the calls made with it.  ``with Context(...) as c:`` makes it the calling
+    thread's current context for the block."""
+
+    def __init__(self, device: int | None = None):
+        if device is None:
+            device = torch.cuda.current_device() if torch.cuda.is_available() else 0
+        self.device = int(device)
+        h = _VP()
+        _check(raw_lib().gs_create(ctypes.byref(h), self.device))
+        self._h = h
+
+    @property
+    def handle(self):
+        return self._h
+
+    def set_tuning(self, name: str, value: int):
+        _check(raw_lib().gs_set_tuning(self._h, name.encode(), int(value)))
+
+    def get_tuning(self, name: str) -> int:
+        v = ctypes.c_int64()
+        _check(raw_lib().gs_get_tuning(self._h, name.encode(), ctypes.byref(v)))
+        return int(v.value)
+
+    def poll_status(self, workspace) -> tuple[int, int]:
+        """(status, required keys) of the last binning that used
+        ``workspace`` (a tuple from ``_ws``); synchronises the current
+        stream first."""
+        torch.cuda.current_stream().synchronize()
+        st, req = _I(), _U64()
+        _check(raw_lib().gs_poll_status(self._h, workspace[1], ctypes.byref(st), ctypes.byref(req)))
+        return int(st.value), int(req.value)
+
+    def close(self):
+        if getattr(self, "_h", None):
+            raw_lib().gs_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        _tls.__dict__.setdefault("stack", []).append(self)
+        return self
+
+    def __exit__(self, et, ev, tb):
+        _tls.stack.pop()
+        return False
+
+
+_tls = threading.local()
+
+
+def context() -> Context:
+    """The calling thread's current context: the innermost ``with Context``,
+    else the thread's own context for the current device (made on first
+    use)."""
+    stack = getattr(_tls, "stack", None)
+    if stack:
+        return stack[-1]
+    dev = torch.cuda.current_device() if torch.cuda.is_available() else 0
+    own = _tls.__dict__.setdefault("own", {})
+    if dev not in own:
+        own[dev] = Context(dev)
+    return own[dev]
+
+
+class _Bound:
+    """The library with the current context bound as the first argument of
+    the calls that take one."""
+
+    def __init__(self, L):
+        self._L = L
+
+    def __getattr__(self, name):
+        fn = getattr(self._L, name)
+        if name in CTX_FIRST:
+            h = context().handle
+            return lambda *a: fn(h, *a)
+        return fn
+
+
+def lib():
+    return _Bound(raw_lib())
+
+
 def _check(code: int):
     if code != GS_OK:
-        raise GsError(code, lib().gs_last_error().decode())
+        raise GsError(code, raw_lib().gs_last_error().decode())
 
 
 def _ptr(t):
@@ -135,9 +248,41 @@ def _dev():
 
 
 def _ws(nbytes: int):
+    """A workspace: (tensor, 256-byte aligned pointer, usable bytes).  Its
+    status header starts zeroed (no binning has used it)."""
     t = torch.empty(max(int(nbytes), 256) + 256, dtype=torch.uint8, device=_dev())
     off = (-t.data_ptr()) % 256
+    t[off:off + 256].zero_()
     return t, ctypes.c_void_p(t.data_ptr() + off), int(nbytes)
+
+
+def _grown(required: int) -> int:
+    """Key capacity after an overflow: the reported count plus a margin for
+    later calls whose scene has moved a little."""
+    return int(required * 1.25) + 1024
+
+
+class KeyWatch:
+    """Deferred overflow check of one binning call: its required key count is
+    copied to pinned host memory behind it on the stream, and read once that
+    copy has landed (never waiting for it)."""
+
+    def __init__(self, num_keys: torch.Tensor, capacity: int):
+        self.capacity = int(capacity)
+        self.host = torch.empty(1, dtype=torch.int64, pin_memory=True)
+        self.host.copy_(num_keys.view(1), non_blocking=True)
+        self.event = torch.cuda.Event()
+        self.event.record()
+
+    def required(self):
+        """The call's required key count, or None while not yet known."""
+        if not self.event.query():
+            return None
+        return int(self.host[0])
+
+    def overflowed(self) -> bool:
+        r = self.required()
+        return r is not None and r > self.capacity
 
 
 class Cameras:
@@ -159,6 +304,37 @@ class Cameras:
         raw = bytes(self.host)
         self.dev = torch.frombuffer(bytearray(raw), dtype=torch.uint8).to(device or _dev())
         self.sizes = [(int(c.width), int(c.height)) for c in self.host]
+        # key capacity planned per (form, points, tile size) for calls that
+        # do not give one, and the pending overflow checks of those calls
+        self.key_capacity = {}
+        self.key_watch = {}
+
+    def planned_capacity(self, key, splats: torch.Tensor) -> int:
+        """Key capacity for a binning of these cameras without a host sync:
+        the first call per key reads the rectangle tile count of ``splats``
+        once (an upper bound of the keys, exact without the level filter) and
+        keeps it with a margin; later calls reuse it.  A pending check that
+        has found an earlier call over its capacity raises GsError (that
+        call's outputs were invalid) after raising the planned capacity."""
+        pending = self.key_watch.get(key, [])
+        for w in pending:
+            if w.overflowed():
+                self.key_watch[key] = []
+                self.key_capacity[key] = max(self.key_capacity.get(key, 0), _grown(w.required()))
+                raise GsError(GS_ERR_CAPACITY,
+                              f"an earlier render of these cameras needed {w.required()} keys but had "
+                              f"capacity for {w.capacity}: its image and gradients are invalid; the "
+                              f"planned capacity is now {self.key_capacity[key]}")
+        self.key_watch[key] = [w for w in pending if w.required() is None]
+        if key not in self.key_capacity:
+            bound = int(splat_fields(splats)["tiles_touched"].to(torch.int64).sum().item())
+            self.key_capacity[key] = _grown(bound)
+        return self.key_capacity[key]
+
+    def watch(self, key, num_keys: torch.Tensor, capacity: int) -> KeyWatch:
+        w = KeyWatch(num_keys, capacity)
+        self.key_watch.setdefault(key, []).append(w)
+        return w
 
     @property
     def hp(self):
@@ -255,27 +431,48 @@ def gs_project(scene: SceneTensors, cams: Cameras, tile_size: int = 16, levels: 
 
 def gs_bin_sort(splats: torch.Tensor, n: int, cams: Cameras, tile_size: int = 16,
                 tile_level=None, qbound=None, key_capacity: int | None = None,
-                want_keys: bool = False, want_hits: bool = False):
+                want_keys: bool = False, want_hits: bool = False, check: bool = False):
     """Binning + (tile, depth) sort.  key_capacity defaults to the sum of the
     unfiltered rectangle tile counts (exact for the plain path, an upper bound
-    with the level filter); that default reads one scalar back from the device."""
-    dev = splats.device
-    n_tiles, _ = cams.tiles(tile_size)
+    with the level filter); that default reads one scalar back from the device.
+    check: synchronise, read the workspace status and, if the capacity was
+    too small, run once more with the reported count (GsError if that fails
+    too)."""
     if key_capacity is None:
         key_capacity = int(splat_fields(splats)["tiles_touched"].to(torch.int64).sum().item())
-    cap = max(int(key_capacity), 1)
-    vals = torch.empty(cap, dtype=torch.int32, device=dev)
-    keys = torch.empty(cap, dtype=torch.int64, device=dev) if want_keys else None
-    ranges = torch.empty((n_tiles, 2), dtype=torch.int32, device=dev)
-    hits = torch.empty((cams.n, n), dtype=torch.int32, device=dev) if want_hits else None
-    num = torch.zeros(1, dtype=torch.int64, device=dev)
-    wsb = gs_workspace_bytes(cams, n, tile_size, cap)
-    ws_t, ws, wsn = _ws(wsb)
-    _check(lib().gs_bin_sort(_ptr(splats), n, cams.hp, cams.dp, cams.n, tile_size, _ptr(tile_level),
-                             _ptr(qbound), _ptr(vals), _ptr(keys), cap, _ptr(ranges), _ptr(hits),
-                             _ptr(num), ws, wsn, _stream()))
-    return dict(vals=vals, keys=keys, ranges=ranges, hits=hits, num_keys=num, capacity=cap,
-                _ws=ws_t)
+
+    def once(cap):
+        dev = splats.device
+        n_tiles, _ = cams.tiles(tile_size)
+        cap = max(int(cap), 1)
+        vals = torch.empty(cap, dtype=torch.int32, device=dev)
+        keys = torch.empty(cap, dtype=torch.int64, device=dev) if want_keys else None
+        ranges = torch.empty((n_tiles, 2), dtype=torch.int32, device=dev)
+        hits = torch.empty((cams.n, n), dtype=torch.int32, device=dev) if want_hits else None
+        num = torch.zeros(1, dtype=torch.int64, device=dev)
+        ws = _ws(gs_workspace_bytes(cams, n, tile_size, cap))
+        _check(lib().gs_bin_sort(_ptr(splats), n, cams.hp, cams.dp, cams.n, tile_size, _ptr(tile_level),
+                                 _ptr(qbound), _ptr(vals), _ptr(keys), cap, _ptr(ranges), _ptr(hits),
+                                 _ptr(num), ws[1], ws[2], _stream()))
+        return dict(vals=vals, keys=keys, ranges=ranges, hits=hits, num_keys=num, capacity=cap, _ws=ws[0],
+                    workspace=ws)
+
+    return _checked(once, key_capacity, check)
+
+
+def _checked(once, cap, check: bool):
+    """Runs once(cap); with check, polls the status of its workspace and runs
+    once more with the reported key count after an overflow."""
+    out = once(cap)
+    if not check:
+        return out
+    st, need = context().poll_status(out["workspace"])
+    if st == GS_ERR_CAPACITY:
+        out = once(need)
+        st, need = context().poll_status(out["workspace"])
+        if st == GS_ERR_CAPACITY:
+            raise GsError(st, f"binning needs {need} keys, more than the capacity {out['capacity']} of the retry")
+    return out
 
 
 def gs_rasterize_fwd(splats, n, cams: Cameras, tile_size, vals, ranges, bg=(0.0, 0.0, 0.0),
@@ -486,27 +683,40 @@ def gs_project_bwd_levels(scene: SceneTensors, cams: Cameras, splats, grads, lvl
 
 
 def gs_render_foveated(scene: SceneTensors, cams: Cameras, foveae, tile_size: int = 16,
-                       bg=(0.0, 0.0, 0.0), key_capacity: int = 0, image=None, workspace=None):
-    """One-call foveated render; returns (image, num_keys tensor, workspace)."""
+                       bg=(0.0, 0.0, 0.0), key_capacity: int = 0, image=None, workspace=None,
+                       check: bool = False):
+    """One-call foveated render; returns (image, num_keys tensor, workspace).
+    check as in gs_bin_sort (a retry sizes a new workspace)."""
     dev = scene.t["means"].device
     _, n_px = cams.tiles(tile_size)
     if image is None:
         image = torch.empty(3 * n_px, dtype=torch.float32, device=dev)
     num = torch.zeros(1, dtype=torch.int64, device=dev)
-    need = gs_render_workspace_bytes(cams, scene.n, scene.n_levels, tile_size, key_capacity)
-    if workspace is None or workspace[2] < need:
-        workspace = _ws(need)
     fa = _foveae(foveae)
     bgc = (ctypes.c_float * 3)(*bg)
     st = scene.struct(levels=True)
-    _check(lib().gs_render_foveated(ctypes.byref(st), cams.hp, cams.dp, ctypes.cast(fa, _PF), cams.n,
-                                    tile_size, ctypes.cast(bgc, _VP), _ptr(image), key_capacity,
-                                    _ptr(num), workspace[1], workspace[2], _stream()))
-    return image, num, workspace
+
+    def once(cap):
+        nonlocal workspace
+        need = gs_render_workspace_bytes(cams, scene.n, scene.n_levels, tile_size, cap)
+        if workspace is None or workspace[2] < need:
+            workspace = _ws(need)
+        _check(lib().gs_render_foveated(ctypes.byref(st), cams.hp, cams.dp, ctypes.cast(fa, _PF), cams.n,
+                                        tile_size, ctypes.cast(bgc, _VP), _ptr(image), int(cap),
+                                        _ptr(num), workspace[1], workspace[2], _stream()))
+        return dict(workspace=workspace, capacity=int(cap))
+
+    out = _checked(once, key_capacity, check)
+    return image, num, out["workspace"]
 
 
 def gs_set_tuning(name: str, value: int):
-    _check(lib().gs_set_tuning(name.encode(), int(value)))
+    """Sets a tuning knob of the calling thread's current context."""
+    context().set_tuning(name, value)
+
+
+def gs_get_tuning(name: str) -> int:
+    return context().get_tuning(name)
 
 
 def gs_sort_pairs(keys: torch.Tensor, vals: torch.Tensor, bits: int, workspace=None):
@@ -522,26 +732,33 @@ def gs_sort_pairs(keys: torch.Tensor, vals: torch.Tensor, bits: int, workspace=N
 
 
 def gs_render_fwd(scene: SceneTensors, cams: Cameras, tile_size: int = 16, bg=(0.0, 0.0, 0.0),
-                  key_capacity: int = 0, workspace=None):
+                  key_capacity: int = 0, workspace=None, check: bool = False):
+    """One-call plain render; check as in gs_bin_sort (a retry allocates new
+    buffers and workspace)."""
     dev = scene.t["means"].device
     n_tiles, n_px = cams.tiles(tile_size)
-    cap = max(int(key_capacity), 1)
-    out = dict(splats=torch.empty((cams.n, scene.n, 12), dtype=torch.float32, device=dev),
-               vals=torch.empty(cap, dtype=torch.int32, device=dev),
-               ranges=torch.empty((n_tiles, 2), dtype=torch.int32, device=dev),
-               num_keys=torch.zeros(1, dtype=torch.int64, device=dev),
-               image=torch.empty(3 * n_px, dtype=torch.float32, device=dev),
-               final_T=torch.empty(n_px, dtype=torch.float32, device=dev),
-               n_contrib=torch.empty(n_px, dtype=torch.int32, device=dev))
-    need = gs_workspace_bytes(cams, scene.n, tile_size, cap)
-    if workspace is None or workspace[2] < need:
-        workspace = _ws(need)
-    bgc = (ctypes.c_float * 3)(*bg)
-    st = scene.struct(levels=False)
-    _check(lib().gs_render_fwd(ctypes.byref(st), cams.hp, cams.dp, cams.n, tile_size,
-                               ctypes.cast(bgc, _VP), _ptr(out["splats"]), _ptr(out["vals"]),
-                               _ptr(out["ranges"]), cap, _ptr(out["num_keys"]), _ptr(out["image"]),
-                               _ptr(out["final_T"]), _ptr(out["n_contrib"]), workspace[1], workspace[2],
-                               _stream()))
-    out["workspace"] = workspace
-    return out
+
+    def once(cap):
+        nonlocal workspace
+        cap = max(int(cap), 1)
+        out = dict(splats=torch.empty((cams.n, scene.n, 12), dtype=torch.float32, device=dev),
+                   vals=torch.empty(cap, dtype=torch.int32, device=dev),
+                   ranges=torch.empty((n_tiles, 2), dtype=torch.int32, device=dev),
+                   num_keys=torch.zeros(1, dtype=torch.int64, device=dev),
+                   image=torch.empty(3 * n_px, dtype=torch.float32, device=dev),
+                   final_T=torch.empty(n_px, dtype=torch.float32, device=dev),
+                   n_contrib=torch.empty(n_px, dtype=torch.int32, device=dev), capacity=cap)
+        need = gs_workspace_bytes(cams, scene.n, tile_size, cap)
+        if workspace is None or workspace[2] < need:
+            workspace = _ws(need)
+        bgc = (ctypes.c_float * 3)(*bg)
+        st = scene.struct(levels=False)
+        _check(lib().gs_render_fwd(ctypes.byref(st), cams.hp, cams.dp, cams.n, tile_size,
+                                   ctypes.cast(bgc, _VP), _ptr(out["splats"]), _ptr(out["vals"]),
+                                   _ptr(out["ranges"]), cap, _ptr(out["num_keys"]), _ptr(out["image"]),
+                                   _ptr(out["final_T"]), _ptr(out["n_contrib"]), workspace[1], workspace[2],
+                                   _stream()))
+        out["workspace"] = workspace
+        return out
+
+    return _checked(once, key_capacity, check)

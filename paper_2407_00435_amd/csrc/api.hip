@@ -4,6 +4,7 @@
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
+#include <cstdlib>
 #include <string>
 
 #include "common.hpp"
@@ -162,33 +163,29 @@ void carve_render(Carve &c, int64_t E, int L, uint64_t cap, int64_t tiles, int64
 // against 0.79 ms) -- and, when on, no split by default (tiles with the
 // longest runs saturate within their first chunks, so splitting composites
 // chunks that are then discarded).
-int g_raster_queue = 0;
-uint32_t g_raster_beta = 0;
-uint32_t g_raster_heavy = 0;
-uint32_t g_raster_grab = 1;
 
 // chunk partial per task: T*T pixels x 3 float4
-size_t queue_task_bytes(int T) { return 8 + 4 + (g_raster_beta ? (size_t)T * T * 48 : 0); }
+size_t queue_task_bytes(const Tuning &tn, int T) { return 8 + 4 + (tn.raster_beta ? (size_t)T * T * 48 : 0); }
 
 size_t queue_fixed_bytes(int64_t tiles) { return 256 + 8 * (size_t)tiles + 4 * 256; }
 
 // Workspace for the queue of a compositing call over `tiles` tiles and at
 // most `cap` keys (0 when the queue is switched off).
-size_t raster_queue_bytes(int64_t tiles, int T, uint64_t cap)
+size_t raster_queue_bytes(const Tuning &tn, int64_t tiles, int T, uint64_t cap)
 {
-    if (!g_raster_queue) return 0;
-    return queue_fixed_bytes(tiles) + raster_queue_heavy_cap(tiles, T, cap, g_raster_beta) * queue_task_bytes(T);
+    if (!tn.raster_queue) return 0;
+    return queue_fixed_bytes(tiles) + raster_queue_heavy_cap(tiles, T, cap, tn.raster_beta) * queue_task_bytes(tn, T);
 }
 
 // Lays the queue out in [base, base + bytes); the heavy-task capacity is what
 // fits (tiles that do not fit are queued unsplit).  False if the queue is off
 // or the space does not hold the fixed part.
-bool carve_queue(char *base, size_t bytes, int64_t tiles, int T, RasterQueueArgs &q)
+bool carve_queue(const Tuning &tn, char *base, size_t bytes, int64_t tiles, int T, RasterQueueArgs &q)
 {
-    if (!g_raster_queue || !base) return false;
+    if (!tn.raster_queue || !base) return false;
     const size_t fixed = queue_fixed_bytes(tiles);
     if (bytes < fixed) return false;
-    const size_t per = queue_task_bytes(T);
+    const size_t per = queue_task_bytes(tn, T);
     uint64_t hc = (bytes - fixed) / per;
     if (hc > (1u << 30)) hc = 1u << 30;
     for (;;) {
@@ -198,7 +195,7 @@ bool carve_queue(char *base, size_t bytes, int64_t tiles, int T, RasterQueueArgs
         q.light = c.take<uint32_t>(8 * tiles);
         q.heavy = c.take<uint32_t>(8 * hc);
         q.merge_cnt = c.take<uint32_t>(4 * hc);
-        q.part = g_raster_beta ? c.take<float>((size_t)T * T * 48 * hc) : nullptr;
+        q.part = tn.raster_beta ? c.take<float>((size_t)T * T * 48 * hc) : nullptr;
         if (c.off <= bytes || hc == 0) break;
         // alignment padding ate into the heavy part: shrink it
         const uint64_t over = (c.off - bytes + per - 1) / per;
@@ -206,18 +203,32 @@ bool carve_queue(char *base, size_t bytes, int64_t tiles, int T, RasterQueueArgs
     }
     q.heavy_cap = (uint32_t)hc;
     q.light_cap = (uint32_t)tiles;
-    q.beta = g_raster_beta;
-    q.heavy_min = g_raster_heavy;
-    q.grab = g_raster_grab;
+    q.beta = tn.raster_beta;
+    q.heavy_min = tn.raster_heavy;
+    q.grab = tn.raster_grab;
     return true;
 }
+
+// Every workspace starts with a status header (WS_HEADER bytes): the
+// required key count and the capacity of the last binning that used it,
+// read back by gs_poll_status.  A compositing call's work queue and every
+// scratch area come after it.
+constexpr size_t WS_HEADER = 256;
 
 size_t bin_bytes(int V_, int64_t E, uint64_t cap, int64_t tiles)
 {
     Carve c;
+    c.take<uint64_t>(WS_HEADER);
     BinScratch bs;
     carve_bin(c, V_, E, cap, tiles, bs);
     return c.off + 256;
+}
+
+// The queue of a compositing call sits after the header of its workspace.
+bool carve_queue_ws(const Tuning &tn, void *ws, size_t bytes, int64_t tiles, int T, RasterQueueArgs &q)
+{
+    if (!ws || bytes <= WS_HEADER) return false;
+    return carve_queue(tn, (char *)ws + WS_HEADER, bytes - WS_HEADER, tiles, T, q);
 }
 
 int check_ws(const void *ws, size_t have, size_t need)
@@ -231,11 +242,93 @@ int check_ws(const void *ws, size_t have, size_t need)
 
 }  // namespace
 
+// A library context: the device it was made for and the launch choices of
+// the calls made with it.  Host state only.
+struct gs_ctx {
+    uint32_t magic;
+    int device;
+    Tuning tn;
+};
+
+namespace {
+
+constexpr uint32_t CTX_MAGIC = 0x67736374u;  // "gsct"
+
+// The context is valid; checked before any other argument.
+int check_ctx(const gs_ctx *ctx)
+{
+    if (!ctx) return fail(GS_ERR_INVALID, "context is NULL");
+    if (ctx->magic != CTX_MAGIC) return fail(GS_ERR_INVALID, "not a live context (destroyed or corrupt)");
+    return GS_OK;
+}
+
+// The context's device is the calling thread's current device; checked
+// after the arguments, before anything is enqueued.
+int check_device(const gs_ctx *ctx)
+{
+    int d = -1;
+    hipError_t e = hipGetDevice(&d);
+    if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+    if (d != ctx->device)
+        return fail(GS_ERR_INVALID, "context is for device %d, the current device is %d", ctx->device, d);
+    return GS_OK;
+}
+
+}  // namespace
+
 extern "C" {
+
+int gs_create(gs_ctx **out, int device)
+{
+    if (!out) return fail(GS_ERR_INVALID, "out is NULL");
+    *out = nullptr;
+    if (device < 0) return fail(GS_ERR_INVALID, "device %d < 0", device);
+    int count = 0;
+    // without a usable runtime the context still serves host-only calls
+    // (workspace sizes, argument checks); a call that launches work checks
+    // the device then
+    if (hipGetDeviceCount(&count) == hipSuccess && device >= count)
+        return fail(GS_ERR_INVALID, "device %d does not exist (%d devices)", device, count);
+    gs_ctx *c = new (std::nothrow) gs_ctx;
+    if (!c) return fail(GS_ERR_INVALID, "out of host memory");
+    c->magic = CTX_MAGIC;
+    c->device = device;
+    if (const char *s = std::getenv("GS_RADIX_PART")) {
+        const int v = std::atoi(s);
+        if (radix_part_ok(v)) c->tn.radix_part = v;
+    }
+    *out = c;
+    return ok();
+}
+
+int gs_destroy(gs_ctx *ctx)
+{
+    if (!ctx) return ok();
+    int r;
+    if ((r = check_ctx(ctx))) return r;
+    ctx->magic = 0;
+    delete ctx;
+    return ok();
+}
+
+int gs_poll_status(gs_ctx *ctx, const void *workspace, int *status, uint64_t *required_keys)
+{
+    int r;
+    if ((r = check_ctx(ctx))) return r;
+    if (!workspace || !status) return fail(GS_ERR_INVALID, "NULL workspace or status");
+    if (!aligned(workspace, 256)) return fail(GS_ERR_INVALID, "workspace must be 256-byte aligned");
+    if ((r = check_device(ctx))) return r;
+    uint64_t h[2] = {0, 0};
+    hipError_t e = hipMemcpy(h, workspace, sizeof(h), hipMemcpyDeviceToHost);
+    if (e != hipSuccess) return hip_fail(e, "gs_poll_status");
+    *status = h[0] > h[1] ? GS_ERR_CAPACITY : GS_OK;
+    if (required_keys) *required_keys = h[0];
+    return ok();
+}
 
 const char *gs_last_error(void) { return g_err.c_str(); }
 
-int gs_version(void) { return 1; }
+int gs_version(void) { return 2; }
 
 int gs_tile_count(const gs_camera *cams_host, int n_views, int tile_size, int64_t *n_tiles,
                   int64_t *n_pixels)
@@ -244,33 +337,35 @@ int gs_tile_count(const gs_camera *cams_host, int n_views, int tile_size, int64_
     return r ? r : ok();
 }
 
-size_t gs_workspace_bytes(const gs_camera *cams_host, int n_views, int32_t n, int tile_size,
+size_t gs_workspace_bytes(gs_ctx *ctx, const gs_camera *cams_host, int n_views, int32_t n, int tile_size,
                           uint64_t key_capacity)
 {
     int64_t tiles = 0;
-    if (check_cams(cams_host, cams_host, n_views, tile_size, &tiles, nullptr)) return 0;
-    return bin_bytes(n_views, (int64_t)n_views * (n > 0 ? n : 0), key_capacity, tiles) + 256 +
-           raster_queue_bytes(tiles, tile_size, key_capacity);
+    if (check_ctx(ctx) || check_cams(cams_host, cams_host, n_views, tile_size, &tiles, nullptr)) return 0;
+    return bin_bytes(n_views, (int64_t)n_views * (n > 0 ? n : 0), key_capacity, tiles) + WS_HEADER +
+           raster_queue_bytes(ctx->tn, tiles, tile_size, key_capacity);
 }
 
-size_t gs_render_workspace_bytes(const gs_camera *cams_host, int n_views, int32_t n, int n_levels,
+size_t gs_render_workspace_bytes(gs_ctx *ctx, const gs_camera *cams_host, int n_views, int32_t n, int n_levels,
                                  int tile_size, uint64_t key_capacity)
 {
     int64_t tiles = 0, pixels = 0;
-    if (check_cams(cams_host, cams_host, n_views, tile_size, &tiles, &pixels)) return 0;
+    if (check_ctx(ctx) || check_cams(cams_host, cams_host, n_views, tile_size, &tiles, &pixels)) return 0;
     int64_t E = (int64_t)n_views * (n > 0 ? n : 0);
     Carve c;
+    c.take<uint64_t>(WS_HEADER);
     BinScratch bs;
     RenderBufs rb;
     carve_render(c, E, n_levels, key_capacity, tiles, pixels, rb);
     carve_bin(c, n_views, E, key_capacity, tiles, bs);
-    return c.off + 512 + raster_queue_bytes(tiles, tile_size, key_capacity);
+    return c.off + 512 + raster_queue_bytes(ctx->tn, tiles, tile_size, key_capacity);
 }
 
-int gs_project(const gs_scene *scene, const gs_camera *cams_host, const gs_camera *cams_dev,
+int gs_project(gs_ctx *ctx, const gs_scene *scene, const gs_camera *cams_host, const gs_camera *cams_dev,
                int n_views, int tile_size, gs_splat *splats, float *lvl_rgba, void *stream)
 {
     int r;
+    if ((r = check_ctx(ctx))) return r;
     if ((r = check_scene(scene, false))) return r;
     if ((r = check_cams(cams_host, cams_dev, n_views, tile_size, nullptr, nullptr))) return r;
     if ((int64_t)n_views * scene->n >= (1ll << 32))
@@ -280,19 +375,21 @@ int gs_project(const gs_scene *scene, const gs_camera *cams_host, const gs_camer
         return fail(GS_ERR_INVALID, "splats and lvl_rgba must be 16-byte aligned");
     if (lvl_rgba && (scene->n_levels < 1 || scene->n_levels > 4))
         return fail(GS_ERR_INVALID, "lvl_rgba given but n_levels = %d", scene->n_levels);
+    if ((r = check_device(ctx))) return r;
     hipError_t e = launch_project(*scene, cams_dev, n_views, tile_size, splats, lvl_rgba,
                                   (hipStream_t)stream);
     if (e != hipSuccess) return hip_fail(e, "gs_project");
     return ok();
 }
 
-int gs_bin_sort(const gs_splat *splats, int32_t n, const gs_camera *cams_host,
+int gs_bin_sort(gs_ctx *ctx, const gs_splat *splats, int32_t n, const gs_camera *cams_host,
                 const gs_camera *cams_dev, int n_views, int tile_size,
                 const uint8_t *tile_level, const uint8_t *qbound, uint32_t *vals,
                 uint64_t *keys, uint64_t key_capacity, uint32_t *tile_ranges, uint32_t *hits,
                 uint64_t *num_keys, void *workspace, size_t workspace_bytes, void *stream)
 {
     int r;
+    if ((r = check_ctx(ctx))) return r;
     int64_t tiles = 0;
     if ((r = check_cams(cams_host, cams_dev, n_views, tile_size, &tiles, nullptr))) return r;
     if (n < 0) return fail(GS_ERR_INVALID, "n must be >= 0");
@@ -307,23 +404,27 @@ int gs_bin_sort(const gs_splat *splats, int32_t n, const gs_camera *cams_host,
     if ((r = check_ws(workspace, workspace_bytes, bin_bytes(n_views, E, key_capacity, tiles)))) return r;
     Carve c;
     c.base = (char *)workspace;
+    uint64_t *status = c.take<uint64_t>(WS_HEADER);
     BinScratch bs;
     carve_bin(c, n_views, E, key_capacity, tiles, bs);
+    bs.rs.part = ctx->tn.radix_part;
+    if ((r = check_device(ctx))) return r;
     hipError_t e = launch_bin_sort(splats, n, cams_dev, cams_host, n_views, tiles,
                                    tile_size,
                                    tile_level, qbound, 4, vals, keys, key_capacity, tile_ranges,
-                                   hits, num_keys, bs, (hipStream_t)stream);
+                                   hits, num_keys, bs, ctx->tn.coarse_packed, status, (hipStream_t)stream);
     if (e != hipSuccess) return hip_fail(e, "gs_bin_sort");
     return ok();
 }
 
-int gs_rasterize_fwd(const gs_splat *splats, int32_t n, const gs_camera *cams_host,
+int gs_rasterize_fwd(gs_ctx *ctx, const gs_splat *splats, int32_t n, const gs_camera *cams_host,
                      const gs_camera *cams_dev, int n_views, int tile_size, const uint32_t *vals,
                      const uint32_t *tile_ranges, const float *bg, float *image, float *final_T,
                      uint32_t *n_contrib, uint32_t *dominated_px, uint64_t *stats,
                      void *workspace, size_t workspace_bytes, void *stream)
 {
     int r;
+    if ((r = check_ctx(ctx))) return r;
     int64_t tiles = 0;
     if ((r = check_cams(cams_host, cams_dev, n_views, tile_size, &tiles, nullptr))) return r;
     if (n < 0) return fail(GS_ERR_INVALID, "n must be >= 0");
@@ -332,8 +433,9 @@ int gs_rasterize_fwd(const gs_splat *splats, int32_t n, const gs_camera *cams_ho
     if (!aligned(splats, 16)) return fail(GS_ERR_INVALID, "splats must be 16-byte aligned");
     if (workspace && !aligned(workspace, 256)) return fail(GS_ERR_INVALID, "workspace must be 256-byte aligned");
     RasterQueueArgs q;
-    const bool queued = carve_queue((char *)workspace, workspace_bytes, tiles, tile_size, q);
+    const bool queued = carve_queue_ws(ctx->tn, workspace, workspace_bytes, tiles, tile_size, q);
     const float zero[3] = {0.f, 0.f, 0.f};
+    if ((r = check_device(ctx))) return r;
     hipError_t e = launch_raster_fwd(splats, n, cams_dev, n_views, tile_size, tiles, vals, tile_ranges,
                                      bg ? bg : zero, image, final_T, n_contrib, dominated_px, stats,
                                      queued ? &q : nullptr, (hipStream_t)stream);
@@ -341,7 +443,7 @@ int gs_rasterize_fwd(const gs_splat *splats, int32_t n, const gs_camera *cams_ho
     return ok();
 }
 
-int gs_rasterize_bwd(const gs_splat *splats, int32_t n, const gs_camera *cams_host,
+int gs_rasterize_bwd(gs_ctx *ctx, const gs_splat *splats, int32_t n, const gs_camera *cams_host,
                      const gs_camera *cams_dev, int n_views, int tile_size, const uint32_t *vals,
                      const uint32_t *tile_ranges, const float *bg, const float *final_T,
                      const uint32_t *n_contrib, const float *dL_dimage, gs_splat_grad *grads,
@@ -350,6 +452,7 @@ int gs_rasterize_bwd(const gs_splat *splats, int32_t n, const gs_camera *cams_ho
     (void)workspace;
     (void)workspace_bytes;
     int r;
+    if ((r = check_ctx(ctx))) return r;
     int64_t tiles = 0;
     if ((r = check_cams(cams_host, cams_dev, n_views, tile_size, &tiles, nullptr))) return r;
     if (n < 0) return fail(GS_ERR_INVALID, "n must be >= 0");
@@ -358,6 +461,7 @@ int gs_rasterize_bwd(const gs_splat *splats, int32_t n, const gs_camera *cams_ho
         return fail(GS_ERR_INVALID, "NULL output or input pointer");
     if (!aligned(splats, 16)) return fail(GS_ERR_INVALID, "splats must be 16-byte aligned");
     const float zero[3] = {0.f, 0.f, 0.f};
+    if ((r = check_device(ctx))) return r;
     hipError_t e = launch_raster_bwd(splats, n, cams_dev, n_views, tile_size, tiles, vals, tile_ranges,
                                      bg ? bg : zero, final_T, n_contrib, dL_dimage, grads,
                                      (hipStream_t)stream);
@@ -365,12 +469,13 @@ int gs_rasterize_bwd(const gs_splat *splats, int32_t n, const gs_camera *cams_ho
     return ok();
 }
 
-int gs_project_bwd(const gs_scene *scene, const gs_camera *cams_host, const gs_camera *cams_dev,
+int gs_project_bwd(gs_ctx *ctx, const gs_scene *scene, const gs_camera *cams_host, const gs_camera *cams_dev,
                    int n_views, const gs_splat *splats, const gs_splat_grad *grads, float *d_means,
                    float *d_log_scales, float *d_quats, float *d_opacity_logits, float *d_sh,
                    int accumulate, void *stream)
 {
     int r;
+    if ((r = check_ctx(ctx))) return r;
     if ((r = check_scene(scene, false))) return r;
     if (accumulate != 0 && accumulate != 1) return fail(GS_ERR_INVALID, "accumulate must be 0 or 1");
     if ((r = check_cams(cams_host, cams_dev, n_views, 16, nullptr, nullptr))) return r;
@@ -380,17 +485,19 @@ int gs_project_bwd(const gs_scene *scene, const gs_camera *cams_host, const gs_c
     if (!aligned(d_quats, 16)) return fail(GS_ERR_INVALID, "d_quats must be 16-byte aligned");
     if ((scene->sh_degree == 1 || scene->sh_degree == 3) && !aligned(d_sh, 16))
         return fail(GS_ERR_INVALID, "d_sh must be 16-byte aligned");
+    if ((r = check_device(ctx))) return r;
     hipError_t e = launch_project_bwd(*scene, cams_dev, n_views, splats, grads, d_means, d_log_scales,
                                       d_quats, d_opacity_logits, d_sh, accumulate, (hipStream_t)stream);
     if (e != hipSuccess) return hip_fail(e, "gs_project_bwd");
     return ok();
 }
 
-int gs_fovea_prep(const gs_camera *cams_host, const gs_camera *cams_dev, const gs_fovea *fov_host,
+int gs_fovea_prep(gs_ctx *ctx, const gs_camera *cams_host, const gs_camera *cams_dev, const gs_fovea *fov_host,
                   int n_eyes, int tile_size, int n_levels, uint8_t *pix_level, float *pix_weight,
                   uint8_t *tile_level, void *stream)
 {
     int r;
+    if ((r = check_ctx(ctx))) return r;
     int64_t tiles = 0, pixels = 0;
     if ((r = check_cams(cams_host, cams_dev, n_eyes, tile_size, &tiles, &pixels))) return r;
     if (n_eyes > 8) return fail(GS_ERR_UNSUPPORTED, "at most 8 eyes (got %d)", n_eyes);
@@ -408,13 +515,14 @@ int gs_fovea_prep(const gs_camera *cams_host, const gs_camera *cams_dev, const g
         if (n_levels > 1 && f.band_deg > 0.f && !(f.ring_deg[0] - 0.5f * f.band_deg >= 0.f))
             return fail(GS_ERR_INVALID, "eye %d: first band starts below 0 degrees", i);
     }
+    if ((r = check_device(ctx))) return r;
     hipError_t e = launch_fovea_prep(cams_host, cams_dev, fov_host, n_eyes, tile_size, n_levels, pixels, tiles,
                                      pix_level, pix_weight, tile_level, (hipStream_t)stream);
     if (e != hipSuccess) return hip_fail(e, "gs_fovea_prep");
     return ok();
 }
 
-int gs_rasterize_foveated(const gs_splat *splats, const float *lvl_rgba, int32_t n,
+int gs_rasterize_foveated(gs_ctx *ctx, const gs_splat *splats, const float *lvl_rgba, int32_t n,
                           const uint8_t *qbound, int n_levels, const gs_camera *cams_host,
                           const gs_camera *cams_dev, int n_eyes, int tile_size, const uint32_t *vals,
                           const uint32_t *tile_ranges, const uint8_t *pix_level,
@@ -423,6 +531,7 @@ int gs_rasterize_foveated(const gs_splat *splats, const float *lvl_rgba, int32_t
                           void *stream)
 {
     int r;
+    if ((r = check_ctx(ctx))) return r;
     int64_t tiles = 0;
     if ((r = check_cams(cams_host, cams_dev, n_eyes, tile_size, &tiles, nullptr))) return r;
     if (n < 0) return fail(GS_ERR_INVALID, "n must be >= 0");
@@ -434,12 +543,13 @@ int gs_rasterize_foveated(const gs_splat *splats, const float *lvl_rgba, int32_t
         return fail(GS_ERR_INVALID, "splats and lvl_rgba must be 16-byte aligned");
     if (workspace && !aligned(workspace, 256)) return fail(GS_ERR_INVALID, "workspace must be 256-byte aligned");
     RasterQueueArgs q;
-    const bool queued = carve_queue((char *)workspace, workspace_bytes, tiles, tile_size, q);
+    const bool queued = carve_queue_ws(ctx->tn, workspace, workspace_bytes, tiles, tile_size, q);
     const float zero[3] = {0.f, 0.f, 0.f};
     if ((final_T2 != nullptr) != (n_contrib2 != nullptr))
         return fail(GS_ERR_INVALID, "final_T2 and n_contrib2 go together");
     if (!aligned(final_T2, 8) || !aligned(n_contrib2, 8))
         return fail(GS_ERR_INVALID, "final_T2 and n_contrib2 must be 8-byte aligned");
+    if ((r = check_device(ctx))) return r;
     hipError_t e = launch_raster_fov(splats, lvl_rgba, n, qbound, n_levels, cams_dev, n_eyes, tile_size,
                                      tiles, vals, tile_ranges, pix_level, pix_weight, bg ? bg : zero,
                                      image, stats, final_T2, n_contrib2, queued ? &q : nullptr, (hipStream_t)stream);
@@ -447,7 +557,7 @@ int gs_rasterize_foveated(const gs_splat *splats, const float *lvl_rgba, int32_t
     return ok();
 }
 
-int gs_rasterize_foveated_bwd(const gs_splat *splats, const float *lvl_rgba, int32_t n, const uint8_t *qbound,
+int gs_rasterize_foveated_bwd(gs_ctx *ctx, const gs_splat *splats, const float *lvl_rgba, int32_t n, const uint8_t *qbound,
                               int n_levels, const gs_camera *cams_host, const gs_camera *cams_dev, int n_eyes,
                               int tile_size, const uint32_t *vals, const uint32_t *tile_ranges,
                               const uint8_t *pix_level, const float *pix_weight, const float *bg,
@@ -455,6 +565,7 @@ int gs_rasterize_foveated_bwd(const gs_splat *splats, const float *lvl_rgba, int
                               gs_splat_grad *grads, float *lvl_grads, void *stream)
 {
     int r;
+    if ((r = check_ctx(ctx))) return r;
     int64_t tiles = 0;
     if ((r = check_cams(cams_host, cams_dev, n_eyes, tile_size, &tiles, nullptr))) return r;
     if (n < 0) return fail(GS_ERR_INVALID, "n must be >= 0");
@@ -467,6 +578,7 @@ int gs_rasterize_foveated_bwd(const gs_splat *splats, const float *lvl_rgba, int
     if (!aligned(final_T2, 8) || !aligned(n_contrib2, 8))
         return fail(GS_ERR_INVALID, "final_T2 and n_contrib2 must be 8-byte aligned");
     const float zero[3] = {0.f, 0.f, 0.f};
+    if ((r = check_device(ctx))) return r;
     hipError_t e = launch_raster_fov_bwd(splats, lvl_rgba, n, qbound, n_levels, cams_dev, n_eyes, tile_size, tiles,
                                          vals, tile_ranges, pix_level, pix_weight, bg ? bg : zero, final_T2,
                                          n_contrib2, dL_dimage, grads, lvl_grads, (hipStream_t)stream);
@@ -474,13 +586,14 @@ int gs_rasterize_foveated_bwd(const gs_splat *splats, const float *lvl_rgba, int
     return ok();
 }
 
-int gs_project_bwd_levels(const gs_scene *scene, const gs_camera *cams_host, const gs_camera *cams_dev,
+int gs_project_bwd_levels(gs_ctx *ctx, const gs_scene *scene, const gs_camera *cams_host, const gs_camera *cams_dev,
                           int n_views, const gs_splat *splats, const gs_splat_grad *grads, const float *lvl_grads,
                           float *d_means, float *d_log_scales, float *d_quats, float *d_opacity_logits,
                           float *d_sh, float *d_lvl_opacity_logits, float *d_lvl_sh_dc, int accumulate,
                           void *stream)
 {
     int r;
+    if ((r = check_ctx(ctx))) return r;
     if ((r = check_scene(scene, true))) return r;
     if ((r = check_cams(cams_host, cams_dev, n_views, 16, nullptr, nullptr))) return r;
     if (accumulate != 0 && accumulate != 1) return fail(GS_ERR_INVALID, "accumulate must be 0 or 1");
@@ -496,6 +609,7 @@ int gs_project_bwd_levels(const gs_scene *scene, const gs_camera *cams_host, con
     if (!aligned(d_quats, 16) || !aligned(lvl_grads, 16)) return fail(GS_ERR_INVALID, "d_quats and lvl_grads must be 16-byte aligned");
     if ((scene->sh_degree == 1 || scene->sh_degree == 3) && !aligned(d_sh, 16))
         return fail(GS_ERR_INVALID, "d_sh must be 16-byte aligned");
+    if ((r = check_device(ctx))) return r;
     hipError_t e = launch_project_bwd(*scene, cams_dev, n_views, splats, grads, d_means, d_log_scales, d_quats,
                                       d_opacity_logits, d_sh, accumulate, (hipStream_t)stream, lvl_grads,
                                       scene->lvl_opacity_logits ? d_lvl_opacity_logits : nullptr,
@@ -504,12 +618,13 @@ int gs_project_bwd_levels(const gs_scene *scene, const gs_camera *cams_host, con
     return ok();
 }
 
-int gs_render_foveated(const gs_scene *scene, const gs_camera *cams_host, const gs_camera *cams_dev,
+int gs_render_foveated(gs_ctx *ctx, const gs_scene *scene, const gs_camera *cams_host, const gs_camera *cams_dev,
                        const gs_fovea *fov_host, int n_eyes, int tile_size, const float *bg,
                        float *image, uint64_t key_capacity, uint64_t *num_keys, void *workspace,
                        size_t workspace_bytes, void *stream)
 {
     int r;
+    if ((r = check_ctx(ctx))) return r;
     int64_t tiles = 0, pixels = 0;
     if ((r = check_scene(scene, true))) return r;
     if ((r = check_cams(cams_host, cams_dev, n_eyes, tile_size, &tiles, &pixels))) return r;
@@ -519,31 +634,33 @@ int gs_render_foveated(const gs_scene *scene, const gs_camera *cams_host, const 
     int64_t E = (int64_t)n_eyes * scene->n;
     if (E >= (1ll << 32)) return fail(GS_ERR_UNSUPPORTED, "n_eyes * n must be < 2^32");
     int L = scene->n_levels;
-    size_t need = gs_render_workspace_bytes(cams_host, n_eyes, scene->n, L, tile_size, key_capacity);
+    size_t need = gs_render_workspace_bytes(ctx, cams_host, n_eyes, scene->n, L, tile_size, key_capacity);
     if ((r = check_ws(workspace, workspace_bytes, need))) return r;
     Carve c;
     c.base = (char *)workspace;
+    uint64_t *status = c.take<uint64_t>(WS_HEADER);
     RenderBufs rb;
     carve_render(c, E, L, key_capacity, tiles, pixels, rb);
     const size_t scratch_off = (c.off + 255) & ~size_t(255);  // binning scratch, then the compositing queue
     BinScratch bs;
     carve_bin(c, n_eyes, E, key_capacity, tiles, bs);
-    if ((r = gs_fovea_prep(cams_host, cams_dev, fov_host, n_eyes, tile_size, L, rb.pix_level,
+    bs.rs.part = ctx->tn.radix_part;
+    if ((r = gs_fovea_prep(ctx, cams_host, cams_dev, fov_host, n_eyes, tile_size, L, rb.pix_level,
                            rb.pix_weight, rb.tile_level, stream)))
         return r;
     hipStream_t st = (hipStream_t)stream;
     hipError_t e;
-    if ((r = gs_project(scene, cams_host, cams_dev, n_eyes, tile_size, rb.splats, rb.lvl, stream)))
+    if ((r = gs_project(ctx, scene, cams_host, cams_dev, n_eyes, tile_size, rb.splats, rb.lvl, stream)))
         return r;
     e = launch_bin_sort(rb.splats, scene->n, cams_dev, cams_host, n_eyes, tiles,
                         tile_size,
                         rb.tile_level, scene->qbound, L, rb.vals, nullptr, key_capacity, rb.ranges, nullptr,
-                        num_keys, bs, st);
+                        num_keys, bs, ctx->tn.coarse_packed, status, st);
     if (e != hipSuccess) return hip_fail(e, "gs_render_foveated (binning)");
     const float zero[3] = {0.f, 0.f, 0.f};
     RasterQueueArgs q;
-    const bool queued = carve_queue((char *)workspace + scratch_off, workspace_bytes - scratch_off, tiles,
-                                    tile_size, q);
+    const bool queued = carve_queue(ctx->tn, (char *)workspace + scratch_off, workspace_bytes - scratch_off,
+                                    tiles, tile_size, q);
     e = launch_raster_fov(rb.splats, rb.lvl, scene->n, scene->qbound, L, cams_dev, n_eyes, tile_size,
                           tiles, rb.vals, rb.ranges, rb.pix_level, rb.pix_weight, bg ? bg : zero, image,
                           nullptr, nullptr, nullptr, queued ? &q : nullptr, st);
@@ -551,35 +668,39 @@ int gs_render_foveated(const gs_scene *scene, const gs_camera *cams_host, const 
     return ok();
 }
 
-int gs_render_fwd(const gs_scene *scene, const gs_camera *cams_host, const gs_camera *cams_dev,
+int gs_render_fwd(gs_ctx *ctx, const gs_scene *scene, const gs_camera *cams_host, const gs_camera *cams_dev,
                   int n_views, int tile_size, const float *bg, gs_splat *splats, uint32_t *vals,
                   uint32_t *tile_ranges, uint64_t key_capacity, uint64_t *num_keys, float *image,
                   float *final_T, uint32_t *n_contrib, void *workspace, size_t workspace_bytes,
                   void *stream)
 {
     int r;
+    if ((r = check_ctx(ctx))) return r;
     int64_t tiles = 0;
     if ((r = check_scene(scene, false))) return r;
     if ((r = check_cams(cams_host, cams_dev, n_views, tile_size, &tiles, nullptr))) return r;
-    if ((r = gs_project(scene, cams_host, cams_dev, n_views, tile_size, splats, nullptr, stream)))
+    if ((r = gs_project(ctx, scene, cams_host, cams_dev, n_views, tile_size, splats, nullptr, stream)))
         return r;
-    if ((r = gs_bin_sort(splats, scene->n, cams_host, cams_dev, n_views, tile_size, nullptr, nullptr,
+    if ((r = gs_bin_sort(ctx, splats, scene->n, cams_host, cams_dev, n_views, tile_size, nullptr, nullptr,
                          vals, nullptr, key_capacity, tile_ranges, nullptr, num_keys, workspace,
                          workspace_bytes, stream)))
         return r;
-    return gs_rasterize_fwd(splats, scene->n, cams_host, cams_dev, n_views, tile_size, vals, tile_ranges,
+    return gs_rasterize_fwd(ctx, splats, scene->n, cams_host, cams_dev, n_views, tile_size, vals, tile_ranges,
                             bg, image, final_T, n_contrib, nullptr, nullptr, workspace, workspace_bytes,
                             stream);
 }
 
 size_t gs_sort_workspace_bytes(uint64_t n) { return radix_sort_scratch_bytes(n); }
 
-int gs_l1_grad(const float *image, const float *target, uint64_t n, float scale, float *dL_dimage,
+int gs_l1_grad(gs_ctx *ctx, const float *image, const float *target, uint64_t n, float scale, float *dL_dimage,
                float *loss, int reset, void *stream)
 {
+    int r;
+    if ((r = check_ctx(ctx))) return r;
     if (!loss || (n > 0 && (!image || !target || !dL_dimage)))
         return fail(GS_ERR_INVALID, "NULL output or input pointer");
     if (reset != 0 && reset != 1) return fail(GS_ERR_INVALID, "reset must be 0 or 1");
+    if ((r = check_device(ctx))) return r;
     hipError_t e;
     if (reset && (e = launch_fill_u32(reinterpret_cast<uint32_t *>(loss), 0u, 1, (hipStream_t)stream)) !=
                      hipSuccess)
@@ -589,11 +710,14 @@ int gs_l1_grad(const float *image, const float *target, uint64_t n, float scale,
     return ok();
 }
 
-int gs_ce_score(const uint32_t *dominated, const uint32_t *hits, int32_t n, int n_views, float *ce, void *stream)
+int gs_ce_score(gs_ctx *ctx, const uint32_t *dominated, const uint32_t *hits, int32_t n, int n_views, float *ce, void *stream)
 {
+    int r;
+    if ((r = check_ctx(ctx))) return r;
     if (n < 0 || n_views < 1) return fail(GS_ERR_INVALID, "n must be >= 0 and n_views >= 1");
     if ((int64_t)n * n_views >= (1ll << 32)) return fail(GS_ERR_UNSUPPORTED, "n_views * n must be < 2^32");
     if (n > 0 && (!dominated || !hits || !ce)) return fail(GS_ERR_INVALID, "NULL output or input pointer");
+    if ((r = check_device(ctx))) return r;
     hipError_t e = launch_ce_score(dominated, hits, n, n_views, ce, (hipStream_t)stream);
     if (e != hipSuccess) return hip_fail(e, "gs_ce_score");
     return ok();
@@ -601,32 +725,37 @@ int gs_ce_score(const uint32_t *dominated, const uint32_t *hits, int32_t n, int 
 
 size_t gs_select_workspace_bytes(int32_t n) { return select_scratch_bytes(n > 0 ? n : 0) + 256; }
 
-int gs_select_lowest(const float *ce, int32_t n, int32_t k, uint8_t *mask, uint32_t *idx, void *workspace,
+int gs_select_lowest(gs_ctx *ctx, const float *ce, int32_t n, int32_t k, uint8_t *mask, uint32_t *idx, void *workspace,
                      size_t workspace_bytes, void *stream)
 {
     int r;
+    if ((r = check_ctx(ctx))) return r;
     if (n < 0) return fail(GS_ERR_INVALID, "n must be >= 0");
     if (n > 0 && (!ce || !mask)) return fail(GS_ERR_INVALID, "NULL output or input pointer");
     if (k < 0) k = 0;
     if (k > n) k = n;
+    if (k > 0 && (r = check_ws(workspace, workspace_bytes, gs_select_workspace_bytes(n)))) return r;
+    if ((r = check_device(ctx))) return r;
     if (k == 0) {
         hipError_t e = launch_fill_u8(mask, 0, n, (hipStream_t)stream);
         if (e != hipSuccess) return hip_fail(e, "gs_select_lowest");
         return ok();
     }
-    if ((r = check_ws(workspace, workspace_bytes, gs_select_workspace_bytes(n)))) return r;
     hipError_t e = launch_select_lowest(ce, n, k, mask, idx, workspace, (hipStream_t)stream);
     if (e != hipSuccess) return hip_fail(e, "gs_select_lowest");
     return ok();
 }
 
-int gs_weighted_scale(const float *log_scales, const uint32_t *hits, int32_t n, int n_views, float threshold,
+int gs_weighted_scale(gs_ctx *ctx, const float *log_scales, const uint32_t *hits, int32_t n, int n_views, float threshold,
                       float gamma, float *ws, float *d_log_scales, int accumulate, void *stream)
 {
+    int r;
+    if ((r = check_ctx(ctx))) return r;
     if (n < 0 || n_views < 1) return fail(GS_ERR_INVALID, "n must be >= 0 and n_views >= 1");
     if ((int64_t)n * n_views >= (1ll << 32)) return fail(GS_ERR_UNSUPPORTED, "n_views * n must be < 2^32");
     if (!ws || (n > 0 && (!log_scales || !hits))) return fail(GS_ERR_INVALID, "NULL output or input pointer");
     if (accumulate != 0 && accumulate != 1) return fail(GS_ERR_INVALID, "accumulate must be 0 or 1");
+    if ((r = check_device(ctx))) return r;
     hipError_t e = launch_weighted_scale(log_scales, hits, n, n_views, threshold, gamma, ws, d_log_scales,
                                          accumulate, (hipStream_t)stream);
     if (e != hipSuccess) return hip_fail(e, "gs_weighted_scale");
@@ -686,57 +815,80 @@ int gs_graph_destroy(gs_graph *graph)
     return ok();
 }
 
-int gs_set_tuning(const char *name, int64_t value)
+int gs_set_tuning(gs_ctx *ctx, const char *name, int64_t value)
 {
+    int r;
+    if ((r = check_ctx(ctx))) return r;
     if (!name) return fail(GS_ERR_INVALID, "tuning name is NULL");
+    Tuning &tn = ctx->tn;
     std::string k(name);
     if (k == "raster_queue") {
         if (value != 0 && value != 1) return fail(GS_ERR_INVALID, "raster_queue must be 0 or 1");
-        g_raster_queue = (int)value;
+        tn.raster_queue = (int)value;
         return ok();
     }
     if (k == "raster_grab") {
         if (value < 1 || value > 64) return fail(GS_ERR_INVALID, "raster_grab must be in 1..64");
-        g_raster_grab = (uint32_t)value;
+        tn.raster_grab = (uint32_t)value;
         return ok();
     }
     if (k == "raster_heavy") {
         if (value < 0 || value > (1ll << 31)) return fail(GS_ERR_INVALID, "raster_heavy must be in 0..2^31");
-        g_raster_heavy = (uint32_t)value;
+        tn.raster_heavy = (uint32_t)value;
         return ok();
     }
     if (k == "raster_split") {
         if (value != 0 && (value < 256 || value > (1 << 24)))
             return fail(GS_ERR_INVALID, "raster_split must be 0 or in 256..2^24");
-        g_raster_beta = (uint32_t)value;
+        tn.raster_beta = (uint32_t)value;
         return ok();
     }
     if (k == "coarse_packed") {
         if (value != 0 && value != 1) return fail(GS_ERR_INVALID, "coarse_packed must be 0 or 1");
-        bin_set_coarse_packed(value != 0);
+        tn.coarse_packed = value != 0;
         return ok();
     }
     if (k == "radix_part") {
-        if (!radix_set_part((int)value))
-            return fail(GS_ERR_INVALID, "radix_part must be 4096, 8192 or 16384");
+        if (!radix_part_ok((int)value)) return fail(GS_ERR_INVALID, "radix_part must be 4096, 8192 or 16384");
+        tn.radix_part = (int)value;
         return ok();
     }
     return fail(GS_ERR_INVALID, "unknown tuning knob '%s'", name);
 }
 
-int gs_sort_pairs(uint32_t *keys, uint32_t *vals, uint32_t *keys_tmp, uint32_t *vals_tmp, uint64_t n,
+int gs_get_tuning(gs_ctx *ctx, const char *name, int64_t *value)
+{
+    int r;
+    if ((r = check_ctx(ctx))) return r;
+    if (!name || !value) return fail(GS_ERR_INVALID, "NULL name or value");
+    const Tuning &tn = ctx->tn;
+    std::string k(name);
+    if (k == "raster_queue") *value = tn.raster_queue;
+    else if (k == "raster_grab") *value = tn.raster_grab;
+    else if (k == "raster_heavy") *value = tn.raster_heavy;
+    else if (k == "raster_split") *value = tn.raster_beta;
+    else if (k == "coarse_packed") *value = tn.coarse_packed ? 1 : 0;
+    else if (k == "radix_part") *value = tn.radix_part;
+    else return fail(GS_ERR_INVALID, "unknown tuning knob '%s'", name);
+    return ok();
+}
+
+int gs_sort_pairs(gs_ctx *ctx, uint32_t *keys, uint32_t *vals, uint32_t *keys_tmp, uint32_t *vals_tmp, uint64_t n,
                   int bits, void *workspace, size_t workspace_bytes, void *stream)
 {
     int r;
+    if ((r = check_ctx(ctx))) return r;
     if (bits < 0 || bits > 32) return fail(GS_ERR_INVALID, "bits %d not in 0..32", bits);
     if (n >= (1ull << 32)) return fail(GS_ERR_UNSUPPORTED, "n must be < 2^32");
     if (n > 0 && (!keys || !vals || !keys_tmp || !vals_tmp))
         return fail(GS_ERR_INVALID, "NULL key or value array");
     if ((r = check_ws(workspace, workspace_bytes, radix_sort_scratch_bytes(n)))) return r;
     if (n == 0 || bits == 0) return ok();
+    if ((r = check_device(ctx))) return r;
     hipStream_t st = (hipStream_t)stream;
     bool in_tmp = false;
-    hipError_t e = radix_sort_standalone(keys, vals, keys_tmp, vals_tmp, n, bits, workspace, &in_tmp, st);
+    hipError_t e = radix_sort_standalone(keys, vals, keys_tmp, vals_tmp, n, bits, workspace, ctx->tn.radix_part,
+                                         &in_tmp, st);
     if (e == hipSuccess && in_tmp) {
         e = hipMemcpyAsync(keys, keys_tmp, 4 * n, hipMemcpyDeviceToDevice, st);
         if (e == hipSuccess) e = hipMemcpyAsync(vals, vals_tmp, 4 * n, hipMemcpyDeviceToDevice, st);

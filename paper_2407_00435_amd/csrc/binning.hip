@@ -62,7 +62,8 @@ __device__ __forceinline__ int64_t view_tile_off(const gs_camera *__restrict__ c
 __global__ void __launch_bounds__(256)
 k_bin_setup(const gs_camera *__restrict__ cams, int V, int T, int64_t *__restrict__ vtab, int4 *__restrict__ stab,
             uint64_t *__restrict__ cap_out, uint64_t cap, uint32_t *__restrict__ ranges, int64_t n_tiles,
-            uint32_t *__restrict__ st_ranges, int64_t n_st, uint64_t *__restrict__ num_keys)
+            uint32_t *__restrict__ st_ranges, int64_t n_st, uint64_t *__restrict__ num_keys,
+            uint64_t *__restrict__ status)
 {
     const uint64_t i0 = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
@@ -71,6 +72,10 @@ k_bin_setup(const gs_camera *__restrict__ cams, int V, int T, int64_t *__restric
     if (i0 != 0) return;
     *cap_out = cap;
     if (num_keys) *num_keys = 0;
+    if (status) {
+        status[0] = 0;  // required keys (k_scan_pair writes the total)
+        status[1] = cap;
+    }
     int64_t toff = 0;
     int soff = 0;
     for (int v = 0; v < V; ++v) {
@@ -342,7 +347,7 @@ k_scan_blocks(uint64_t *__restrict__ block_sums, const uint32_t *__restrict__ bl
 __global__ void __launch_bounds__(1024)
 k_scan_pair(uint64_t *__restrict__ key_sums, uint64_t *__restrict__ pair_sums, int64_t nb,
             uint64_t *__restrict__ keys_total, const uint64_t *__restrict__ cap_ptr,
-            uint64_t *__restrict__ num_keys, uint64_t *__restrict__ pairs_total)
+            uint64_t *__restrict__ num_keys, uint64_t *__restrict__ pairs_total, uint64_t *__restrict__ status)
 {
     __shared__ uint64_t s[1024];
     const uint64_t kt = scan_blocks_body(s, key_sums, nullptr, nb);
@@ -351,6 +356,7 @@ k_scan_pair(uint64_t *__restrict__ key_sums, uint64_t *__restrict__ pair_sums, i
     if (threadIdx.x == 1023) {
         *keys_total = kc;
         if (num_keys) *num_keys = kt;
+        if (status) status[0] = kt;
         *pairs_total = pt <= kc ? pt : 0;
     }
 }
@@ -1106,9 +1112,6 @@ inline int grid_for(uint64_t work, int per_block, int cap_blocks)
 
 }  // namespace
 
-static bool g_coarse_packed = true;
-void bin_set_coarse_packed(bool packed) { g_coarse_packed = packed; }
-
 hipError_t launch_fill_u32(uint32_t *p, uint32_t value, uint64_t count, hipStream_t st)
 {
     if (count == 0) return hipSuccess;
@@ -1122,7 +1125,7 @@ hipError_t launch_bin_sort(const gs_splat *splats, int n, const gs_camera *cams_
                            const uint8_t *tile_level, const uint8_t *qbound, int n_levels,
                            uint32_t *vals, uint64_t *keys, uint64_t cap, uint32_t *ranges,
                            uint32_t *hits_out, uint64_t *num_keys, const BinScratch &bs,
-                           hipStream_t st)
+                           bool coarse_packed, uint64_t *status, hipStream_t st)
 {
     const int64_t E = (int64_t)V * n;
     hipError_t err;
@@ -1135,7 +1138,7 @@ hipError_t launch_bin_sort(const gs_splat *splats, int n, const gs_camera *cams_
     }
     hipLaunchKernelGGL(k_bin_setup, dim3(grid_for(2 * (uint64_t)(n_tiles > n_st ? n_tiles : n_st), 256 * 4, 256)),
                        dim3(256), 0, st, cams_dev, V, T, bs.vtab, bs.stab, bs.counts + 2, cap, ranges, n_tiles,
-                       bs.st_ranges, n_st, E == 0 ? num_keys : nullptr);
+                       bs.st_ranges, n_st, E == 0 ? num_keys : nullptr, status);
     if (E == 0) return hipGetLastError();
     const bool filt = tile_level != nullptr;
     const int L = n_levels < 1 ? 1 : (n_levels > 4 ? 4 : n_levels);
@@ -1170,13 +1173,13 @@ hipError_t launch_bin_sort(const gs_splat *splats, int n, const gs_camera *cams_
     hipLaunchKernelGGL(k_gather, dim3((unsigned)nb), dim3(GATHER_THREADS), 0, st, bs.dval_a, bs.rec, bs.counts, n,
                        bs.vtab, bs.stab, sat, bs.st_cls, L, n_tiles, bs.rec_s, bs.cc_s, bs.block_sums, bs.block_sums2);
     hipLaunchKernelGGL(k_scan_pair, dim3(1), dim3(1024), 0, st, bs.block_sums, bs.block_sums2, nb, bs.counts + 1,
-                       bs.counts + 2, num_keys, bs.counts + 3);
+                       bs.counts + 2, num_keys, bs.counts + 3, status);
     // 4b: coarse pairs with their payloads, stably sorted by super-tile
     int st_bits = 1;
     while ((int64_t(1) << st_bits) < n_st) ++st_bits;
     // the pair's info rides in the sort key when the super-tile ids leave room
-    const bool packed = g_coarse_packed && st_bits <= ST_ID_BITS;
-    const bool even = radix_pass_count(st_bits, packed ? 4 : 8) % 2 == 0;
+    const bool packed = coarse_packed && st_bits <= ST_ID_BITS;
+    const bool even = radix_pass_count(st_bits, packed ? 4 : 8, bs.rs.part) % 2 == 0;
     if (packed) {
         hipLaunchKernelGGL(k_coarse_emit<true>, dim3((unsigned)nb), dim3(GATHER_THREADS), 0, st, bs.rec_s, bs.cc_s,
                            bs.counts, bs.block_sums2, bs.vtab, bs.stab, sat, bs.st_cls, L, n_tiles, bs.tkey_a,

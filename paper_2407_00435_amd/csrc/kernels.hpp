@@ -29,20 +29,32 @@ hipError_t launch_weighted_scale(const float *log_scales, const uint32_t *hits, 
 hipError_t launch_l1_grad(const float *image, const float *target, uint64_t n, float scale,
                           float *dL_dimage, float *loss, hipStream_t st);
 
+// Launch choices of one library context (gs_ctx), read on the host while a
+// call enqueues its kernels; they change launch shapes, never results.
+struct Tuning {
+    int radix_part = 8192;       // keys per sort workgroup: 4096, 8192 or 16384
+    bool coarse_packed = true;   // coarse pairs carry their rectangle in the key
+    int raster_queue = 0;        // persistent work-queue compositors
+    uint32_t raster_beta = 0;    // heavy-tile split length (0: no split)
+    uint32_t raster_heavy = 0;   // without split: runs longer than this go first
+    uint32_t raster_grab = 1;    // tasks per pop
+};
+
 // radix sort of (u32 key, u32 value) pairs, LSD over bits [0, bits)
 struct RadixScratch {
     uint32_t *hist;     // [4][256] digit counts, then exclusive bases
     uint64_t *status;   // [2][status_words] lookback words, two buffers
     uint32_t *tickets;  // [4] partition tickets, one per pass
     uint64_t status_words;  // words per buffer (radix_status_words)
+    int part = 8192;        // keys per workgroup (4096, 8192 or 16384)
 };
 // partitions the lookback status must hold for `cap` keys (smallest partition)
 uint64_t radix_max_parts(uint64_t cap);
 // lookback words per buffer for sorts of up to `cap` keys (any radix)
 uint64_t radix_status_words(uint64_t cap);
-// passes a sort of `bits`-bit keys with vbytes-byte values runs (its result
-// is in the second buffer pair when odd)
-int radix_pass_count(int bits, int vbytes);
+// passes a sort of `bits`-bit keys with vbytes-byte values runs with
+// partitions of `part` keys (its result is in the second buffer pair when odd)
+int radix_pass_count(int bits, int vbytes, int part);
 inline int radix_passes(int bits) { return (bits + 7) / 8; }
 // digit width of each pass for a key of `bits` bits (equal widths, <= 8)
 int radix_digit_bits(int bits);
@@ -65,10 +77,11 @@ hipError_t radix_sort_pairs_v2(uint32_t *ka, uint2 *va, uint32_t *kb, uint2 *vb,
 hipError_t radix_sort_prepare(const RadixScratch &rs, const uint64_t *d_count, uint64_t cap, int vbytes, int bits,
                               hipStream_t st);
 size_t radix_sort_scratch_bytes(uint64_t n);
-bool radix_set_part(int p);
-// sorts n pairs with its own scratch at ws; *in_tmp tells where the result is
+inline bool radix_part_ok(int p) { return p == 4096 || p == 8192 || p == 16384; }
+// sorts n pairs with its own scratch at ws (radix_sort_scratch_bytes(n)
+// bytes) in partitions of `part` keys; *in_tmp tells where the result is
 hipError_t radix_sort_standalone(uint32_t *keys, uint32_t *vals, uint32_t *kt, uint32_t *vt, uint64_t n,
-                                 int bits, void *ws, bool *in_tmp, hipStream_t st);
+                                 int bits, void *ws, int part, bool *in_tmp, hipStream_t st);
 
 // binning
 constexpr int SCAN_THREADS = 256;
@@ -103,15 +116,16 @@ struct BinScratch {
     int32_t *bbox;                                // [V][4][4] bounding box of each level's kept tiles
     RadixScratch rs;
 };
-// coarse pairs with the rectangle in the sort key where the ids leave room
-// (default) or always with an 8-byte value
-void bin_set_coarse_packed(bool packed);
+// Binning and sort.  coarse_packed: coarse pairs carry their rectangle in
+// the sort key where the super-tile ids leave room, else an 8-byte value
+// (same keys either way).  status (device, nullable, 2 words): the required
+// key count and the capacity, for gs_poll_status.
 hipError_t launch_bin_sort(const gs_splat *splats, int n, const gs_camera *cams_dev,
                            const gs_camera *cams_host, int V, int64_t n_tiles, int T,
                            const uint8_t *tile_level, const uint8_t *qbound, int n_levels,
                            uint32_t *vals, uint64_t *keys, uint64_t cap,
                            uint32_t *ranges, uint32_t *hits_out, uint64_t *num_keys,
-                           const BinScratch &bs, hipStream_t st);
+                           const BinScratch &bs, bool coarse_packed, uint64_t *status, hipStream_t st);
 
 // compositing
 // Work-queue scratch of the persistent compositors (carved from a workspace).

@@ -256,18 +256,6 @@ k_radix_onesweep(const uint32_t *__restrict__ kin, const VT *__restrict__ vin,
 
 __global__ void k_set_count(uint64_t *__restrict__ p, uint64_t value) { *p = value; }
 
-int g_part = 0;
-
-int part_size()
-{
-    if (g_part == 0) {
-        const char *s = std::getenv("GS_RADIX_PART");
-        int v = s ? std::atoi(s) : 8192;
-        g_part = (v == 4096 || v == 8192 || v == 16384) ? v : 8192;
-    }
-    return g_part;
-}
-
 }  // namespace
 
 uint64_t radix_max_parts(uint64_t cap) { return (cap + MIN_PART - 1) / MIN_PART; }
@@ -281,23 +269,24 @@ int radix_digit_bits(int bits)
     return passes ? (bits + passes - 1) / passes : 0;
 }
 
-// partition size of a sort with values of vbytes bytes (the LDS holds keys
-// and values: 8-byte values take partitions of at most 8192 keys)
-static int part_for(int vbytes) { return vbytes > 4 && part_size() > 8192 ? 8192 : part_size(); }
+// partition size of a sort with values of vbytes bytes given the context's
+// choice (the LDS holds keys and values: 8-byte values take partitions of at
+// most 8192 keys)
+static int part_for(int vbytes, int part) { return vbytes > 4 && part > 8192 ? 8192 : part; }
 
 // A 9-bit key sorts in one pass of 512 digits where the workgroup has a
 // thread per digit (512 threads: partitions of 8192 keys).
 static bool one_wide_pass(int bits, int P) { return bits == 9 && P == 8192; }
 
-int radix_pass_count(int bits, int vbytes)
+int radix_pass_count(int bits, int vbytes, int part)
 {
-    return one_wide_pass(bits, part_for(vbytes)) ? 1 : radix_passes(bits);
+    return one_wide_pass(bits, part_for(vbytes, part)) ? 1 : radix_passes(bits);
 }
 
 hipError_t radix_sort_prepare(const RadixScratch &rs, const uint64_t *d_count, uint64_t cap, int vbytes, int bits,
                               hipStream_t st)
 {
-    const int P = part_for(vbytes);
+    const int P = part_for(vbytes, rs.part);
     const int R = one_wide_pass(bits, P) ? 512 : 256;
     const uint64_t words = ((cap + P - 1) / P) * R;
     if (words > rs.status_words) return hipErrorInvalidValue;
@@ -314,7 +303,7 @@ static hipError_t sort_pairs_impl(uint32_t *ka, VT *va, uint32_t *kb, VT *vb,
                             const RadixScratch &rs, hipStream_t st, bool hist_ready)
 {
     if (radix_passes(bits) == 0 || cap == 0) return hipSuccess;
-    const int P = part_for((int)sizeof(VT));
+    const int P = part_for((int)sizeof(VT), rs.part);
     const bool wide = one_wide_pass(bits, P);
     const int passes = wide ? 1 : radix_passes(bits);
     // equal digit widths <= 8 bits (fewer buckets give longer runs per
@@ -381,13 +370,6 @@ hipError_t radix_sort_pairs_v2(uint32_t *ka, uint2 *va, uint32_t *kb, uint2 *vb,
     return sort_pairs_impl<uint2>(ka, va, kb, vb, d_count, cap, bits, rs, st, false);
 }
 
-bool radix_set_part(int p)
-{
-    if (p != 4096 && p != 8192 && p != 16384) return false;
-    g_part = p;
-    return true;
-}
-
 size_t radix_sort_scratch_bytes(uint64_t n)
 {
     // hist [4][256] u32 | tickets [4] u32 | count u64 | status [2][status words] u64
@@ -395,7 +377,7 @@ size_t radix_sort_scratch_bytes(uint64_t n)
 }
 
 hipError_t radix_sort_standalone(uint32_t *keys, uint32_t *vals, uint32_t *kt, uint32_t *vt, uint64_t n,
-                                 int bits, void *ws, bool *in_tmp, hipStream_t st)
+                                 int bits, void *ws, int part, bool *in_tmp, hipStream_t st)
 {
     char *base = (char *)ws;
     RadixScratch rs;
@@ -405,7 +387,8 @@ hipError_t radix_sort_standalone(uint32_t *keys, uint32_t *vals, uint32_t *kt, u
     rs.status = (uint64_t *)(base + 4 * 256 * 4 + 4 * 4 + 8 + 256);
     rs.status = (uint64_t *)(((uintptr_t)rs.status + 255) & ~uintptr_t(255));
     rs.status_words = radix_status_words(n);
+    rs.part = part;
     hipLaunchKernelGGL(k_set_count, dim3(1), dim3(1), 0, st, count, n);
-    *in_tmp = radix_pass_count(bits, 4) % 2 == 1;
+    *in_tmp = radix_pass_count(bits, 4, part) % 2 == 1;
     return radix_sort_pairs(keys, vals, kt, vt, count, n, bits, rs, st, false);
 }

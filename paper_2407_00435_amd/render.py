@@ -5,6 +5,13 @@ and keeps what the reverse pass needs (splats, sorted ids, tile ranges,
 final transmittance and last-contributor index); backward runs the
 compositing reverse and the projection reverse in the library.  Torch only
 supplies memory and the stream.
+
+Key capacity: given, it is used as is; else it is planned per camera set
+(``Cameras.planned_capacity``: one host read the first time, none after) and
+every forward leaves a deferred overflow check behind it.  A check that has
+found an overflow raises GsError at the next forward with these cameras, or
+at this forward's backward if the count has landed by then, and the plan
+grows; no forward waits for the device.
 """
 from __future__ import annotations
 
@@ -21,21 +28,31 @@ class GaussianRender(torch.autograd.Function):
                                quats=quats.detach(), opacity_logits=opacity_logits.detach(),
                                sh=sh.detach(), sh_degree=sh_degree)
         splats = B.gs_project(scene, cams, tile_size)
-        bs = B.gs_bin_sort(splats, scene.n, cams, tile_size, key_capacity=key_capacity)
+        plan = ("plain", scene.n, tile_size)
+        cap = key_capacity if key_capacity is not None else cams.planned_capacity(plan, splats)
+        bs = B.gs_bin_sort(splats, scene.n, cams, tile_size, key_capacity=cap)
         out = B.gs_rasterize_fwd(splats, scene.n, cams, tile_size, bs["vals"], bs["ranges"], bg)
         ctx.scene, ctx.cams, ctx.tile, ctx.bg = scene, cams, tile_size, bg
         ctx.save_for_backward(splats, bs["vals"], bs["ranges"], out["final_T"], out["n_contrib"])
         ctx.num_keys, ctx.capacity = bs["num_keys"], bs["capacity"]
+        ctx.watch = cams.watch(plan, bs["num_keys"], bs["capacity"]) if key_capacity is None else None
         return out["image"]
 
     @staticmethod
     def backward(ctx, dL_dimage):
+        _raise_if_overflowed(ctx.watch)
         splats, vals, ranges, final_T, n_contrib = ctx.saved_tensors
         g = B.gs_rasterize_bwd(splats, ctx.scene.n, ctx.cams, ctx.tile, vals, ranges, final_T,
                                n_contrib, dL_dimage.contiguous(), ctx.bg)
         pg = B.gs_project_bwd(ctx.scene, ctx.cams, splats, g)
         return (pg["means"], pg["log_scales"], pg["quats"], pg["opacity_logits"], pg["sh"],
                 None, None, None, None, None)
+
+
+def _raise_if_overflowed(watch):
+    if watch is not None and watch.overflowed():
+        raise B.GsError(B.GS_ERR_CAPACITY, f"the forward needed {watch.required()} keys but had capacity for "
+                                           f"{watch.capacity}: its image is invalid (render again)")
 
 
 def render(means, log_scales, quats, opacity_logits, sh, cams, sh_degree, tile_size=16,
@@ -61,8 +78,10 @@ class FoveatedRender(torch.autograd.Function):
         L = scene.n_levels
         t = B.gs_fovea_prep(cams, foveae, tile_size, L)
         splats, lvl = B.gs_project(scene, cams, tile_size, levels=True)
+        plan = ("foveated", scene.n, tile_size, L)
+        cap = key_capacity if key_capacity is not None else cams.planned_capacity(plan, splats)
         bs = B.gs_bin_sort(splats, scene.n, cams, tile_size, tile_level=t["tile_level"], qbound=scene.t["qbound"],
-                           key_capacity=key_capacity)
+                           key_capacity=cap)
         _, n_px = cams.tiles(tile_size)
         fT2 = torch.empty((n_px, 2), dtype=torch.float32, device=means.device)
         nc2 = torch.empty((n_px, 2), dtype=torch.int32, device=means.device)
@@ -71,10 +90,12 @@ class FoveatedRender(torch.autograd.Function):
         ctx.scene, ctx.cams, ctx.tile, ctx.bg, ctx.tables = scene, cams, tile_size, bg, t
         ctx.save_for_backward(splats, lvl, bs["vals"], bs["ranges"], fT2, nc2)
         ctx.num_keys = bs["num_keys"]
+        ctx.watch = cams.watch(plan, bs["num_keys"], bs["capacity"]) if key_capacity is None else None
         return image
 
     @staticmethod
     def backward(ctx, dL_dimage):
+        _raise_if_overflowed(ctx.watch)
         splats, lvl, vals, ranges, fT2, nc2 = ctx.saved_tensors
         sc, t = ctx.scene, ctx.tables
         g, lg = B.gs_rasterize_foveated_bwd(splats, lvl, sc.n, sc.t["qbound"], sc.n_levels, ctx.cams, ctx.tile, vals,

@@ -35,7 +35,7 @@ def test_every_declared_symbol_is_exported(L):
 
 def test_version_and_host_errors(L):
     lib = L.lib()
-    assert lib.gs_version() == 1
+    assert lib.gs_version() == 2
     cams = (L.GsCamera * 1)()
     cams[0].width, cams[0].height, cams[0].fx, cams[0].fy = 64, 48, 50.0, 50.0
     nt, npx = ctypes.c_int64(), ctypes.c_int64()
@@ -73,3 +73,62 @@ def test_package_fails_loudly_without_library(tmp_path, monkeypatch):
     monkeypatch.setattr(binding, "_lib", None)
     with pytest.raises(RuntimeError, match="missing"):
         binding.lib()
+
+
+def test_contexts_hold_their_own_tuning(L):
+    raw = L.raw_lib()
+    h = ctypes.c_void_p()
+    assert raw.gs_create(None, 0) == L.GS_ERR_INVALID
+    assert raw.gs_create(ctypes.byref(h), -1) == L.GS_ERR_INVALID
+    assert not h.value
+    a, b = L.Context(0), L.Context(0)
+    a.set_tuning("radix_part", 4096)
+    b.set_tuning("radix_part", 16384)
+    a.set_tuning("coarse_packed", 0)
+    assert (a.get_tuning("radix_part"), b.get_tuning("radix_part")) == (4096, 16384)
+    assert (a.get_tuning("coarse_packed"), b.get_tuning("coarse_packed")) == (0, 1)
+    for k, v in (("raster_queue", 0), ("raster_grab", 1), ("raster_heavy", 0), ("raster_split", 0)):
+        assert b.get_tuning(k) == v
+    with pytest.raises(L.GsError, match="unknown tuning knob"):
+        a.get_tuning("no_such_knob")
+    with pytest.raises(L.GsError, match="radix_part"):
+        a.set_tuning("radix_part", 1000)
+    assert a.get_tuning("radix_part") == 4096  # a rejected value leaves the setting
+    # the thread's current context follows `with`
+    with b:
+        assert L.context() is b and L.gs_get_tuning("radix_part") == 16384
+        with a:
+            assert L.context() is a
+        assert L.context() is b
+    assert L.context() is not a and L.context() is not b
+    # workspace sizes depend on the context's tuning (the work queue)
+    cams = (L.GsCamera * 1)()
+    cams[0].width, cams[0].height, cams[0].fx, cams[0].fy = 640, 480, 500.0, 500.0
+    pc = ctypes.cast(cams, L._PC)
+    base = raw.gs_workspace_bytes(a.handle, pc, 1, 1000, 16, 100000)
+    a.set_tuning("raster_queue", 1)
+    assert raw.gs_workspace_bytes(a.handle, pc, 1, 1000, 16, 100000) > base
+    assert raw.gs_workspace_bytes(None, pc, 1, 1000, 16, 100000) == 0
+    a.close()
+    b.close()
+
+
+def test_calls_check_the_context_first(L):
+    raw = L.raw_lib()
+    cams = (L.GsCamera * 1)()
+    cams[0].width, cams[0].height, cams[0].fx, cams[0].fy = 64, 48, 50.0, 50.0
+    sc = L.GsScene()
+    sc.n, sc.sh_degree = 10, 0
+    assert raw.gs_project(None, ctypes.byref(sc), ctypes.cast(cams, L._PC), ctypes.c_void_p(256), 1, 16,
+                          ctypes.c_void_p(256), None, None) == L.GS_ERR_INVALID
+    assert b"context is NULL" in raw.gs_last_error()
+    assert raw.gs_set_tuning(None, b"radix_part", 8192) == L.GS_ERR_INVALID
+    assert raw.gs_l1_grad(None, None, None, 0, ctypes.c_float(1.0), None, ctypes.c_void_p(256), 1,
+                          None) == L.GS_ERR_INVALID
+    st, req = ctypes.c_int(), ctypes.c_uint64()
+    ctx = L.Context(0)
+    assert raw.gs_poll_status(ctx.handle, None, ctypes.byref(st), ctypes.byref(req)) == L.GS_ERR_INVALID
+    assert raw.gs_poll_status(ctx.handle, ctypes.c_void_p(8), ctypes.byref(st), None) == L.GS_ERR_INVALID
+    assert b"256-byte aligned" in raw.gs_last_error()
+    assert raw.gs_destroy(None) == 0
+    ctx.close()
