@@ -448,6 +448,22 @@ size_t gs_sort_workspace_bytes(uint64_t n);
 int gs_sort_pairs(gs_ctx *ctx, uint32_t *keys, uint32_t *vals, uint32_t *keys_tmp, uint32_t *vals_tmp,
                   uint64_t n, int bits, void *workspace, size_t workspace_bytes, void *stream);
 
+/* Largest n of gs_sort_pairs_static. */
+#define GS_SORT_STATIC_MAX_KEYS (1u << 24)
+
+/* gs_sort_pairs without a workspace, for callers that cannot allocate
+ * device memory (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid allocation).  Same sort, arguments and result as
+ * gs_sort_pairs; its scratch (digit counts, tickets, lookback words) is a
+ * static 17 MiB array in the library, one per device, held until the
+ * process ends, so n is at most GS_SORT_STATIC_MAX_KEYS (GS_ERR_CAPACITY
+ * beyond, found on the host).  It allocates and frees nothing.  Every call
+ * on a device uses that device's one array: calls that overlap on one
+ * device (other streams, other threads, other contexts) race and must be
+ * ordered by the caller; each call clears what it needs. */
+int gs_sort_pairs_static(gs_ctx *ctx, uint32_t *keys, uint32_t *vals, uint32_t *keys_tmp, uint32_t *vals_tmp,
+                         uint64_t n, int bits, void *stream);
+
 #ifdef __cplusplus
 }
 #endif

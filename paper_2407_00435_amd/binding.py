@@ -98,6 +98,7 @@ _SIGS = {
     "gs_sort_workspace_bytes": ([_U64], _SZ),
     "gs_set_tuning": ([ctypes.c_char_p, ctypes.c_int64], _I),
     "gs_sort_pairs": ([_VP, _VP, _VP, _VP, _U64, _I, _VP, _SZ, _VP], _I),
+    "gs_sort_pairs_static": ([_VP, _VP, _VP, _VP, _U64, _I, _VP], _I),
     "gs_l1_grad": ([_VP, _VP, _U64, ctypes.c_float, _VP, _VP, _I, _VP], _I),
     "gs_ce_score": ([_VP, _VP, _I32, _I, _VP, _VP], _I),
     "gs_select_workspace_bytes": ([_I32], _SZ),
@@ -115,7 +116,7 @@ CTX_FIRST = frozenset((
     "gs_rasterize_bwd", "gs_project_bwd", "gs_fovea_prep", "gs_rasterize_foveated",
     "gs_rasterize_foveated_bwd", "gs_project_bwd_levels", "gs_render_foveated", "gs_render_fwd",
     "gs_l1_grad", "gs_ce_score", "gs_select_lowest", "gs_weighted_scale", "gs_sort_pairs",
-    "gs_set_tuning", "gs_get_tuning", "gs_poll_status"))
+    "gs_sort_pairs_static", "gs_set_tuning", "gs_get_tuning", "gs_poll_status"))
 for _name in CTX_FIRST:
     _a, _r = _SIGS[_name]
     _SIGS[_name] = ([_VP] + list(_a), _r)
@@ -729,6 +730,18 @@ def gs_sort_pairs(keys: torch.Tensor, vals: torch.Tensor, bits: int, workspace=N
     _check(lib().gs_sort_pairs(_ptr(keys), _ptr(vals), _ptr(kt), _ptr(vt), n, bits, workspace[1],
                                workspace[2], _stream()))
     return workspace
+
+
+SORT_STATIC_MAX_KEYS = 1 << 24
+
+
+def gs_sort_pairs_static(keys: torch.Tensor, vals: torch.Tensor, bits: int, tmp=None):
+    """gs_sort_pairs without a workspace (the library's static scratch): in
+    place, n <= SORT_STATIC_MAX_KEYS.  ``tmp`` = (keys_tmp, vals_tmp)
+    preallocated by the caller, or None to allocate them here."""
+    n = keys.numel()
+    kt, vt = tmp if tmp is not None else (torch.empty_like(keys), torch.empty_like(vals))
+    _check(lib().gs_sort_pairs_static(_ptr(keys), _ptr(vals), _ptr(kt), _ptr(vt), n, bits, _stream()))
 
 
 def gs_render_fwd(scene: SceneTensors, cams: Cameras, tile_size: int = 16, bg=(0.0, 0.0, 0.0),

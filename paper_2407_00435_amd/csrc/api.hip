@@ -5,6 +5,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstdlib>
+#include <mutex>
 #include <string>
 
 #include "common.hpp"
@@ -242,6 +243,50 @@ int check_ws(const void *ws, size_t have, size_t need)
 
 }  // namespace
 
+// ---------------------------------------------------------------------------
+// Static scratch of gs_sort_pairs_static: the sort's digit counts, tickets,
+// key count and lookback words for up to GS_SORT_STATIC_MAX_KEYS keys live
+// in this array, one copy per device, held until the process ends.  Host code
+// never uses the array's name (a host-side stand-in): its device address on
+// each device is resolved once, when the first context for that device is
+// created, and kept in g_scratch_ptr.
+constexpr size_t SORT_STATIC_BYTES = 17u << 20;
+static __device__ __align__(256) unsigned char scratch[SORT_STATIC_BYTES];
+
+namespace {
+
+constexpr int MAX_DEVICES = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[MAX_DEVICES] = {};
+
+// Resolves the device address of `scratch` on `device` (once per device),
+// with that device current; restores the caller's current device.
+int setup_static_scratch(int device)
+{
+    if (device >= MAX_DEVICES) return fail(GS_ERR_UNSUPPORTED, "device %d: at most %d devices", device, MAX_DEVICES);
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (g_scratch_ptr[device]) return GS_OK;
+    int prev = 0;
+    hipError_t e = hipGetDevice(&prev);
+    if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+    if (prev != device && (e = hipSetDevice(device)) != hipSuccess) return hip_fail(e, "hipSetDevice");
+    void *ptr = nullptr;
+    e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (prev != device) hipSetDevice(prev);
+    if (e != hipSuccess) return hip_fail(e, "hipGetSymbolAddress (static sort scratch)");
+    g_scratch_ptr[device] = ptr;
+    return GS_OK;
+}
+
+void *static_scratch(int device)
+{
+    if (device < 0 || device >= MAX_DEVICES) return nullptr;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    return g_scratch_ptr[device];
+}
+
+}  // namespace
+
 // A library context: the device it was made for and the launch choices of
 // the calls made with it.  Host state only.
 struct gs_ctx {
@@ -287,8 +332,11 @@ int gs_create(gs_ctx **out, int device)
     // without a usable runtime the context still serves host-only calls
     // (workspace sizes, argument checks); a call that launches work checks
     // the device then
-    if (hipGetDeviceCount(&count) == hipSuccess && device >= count)
-        return fail(GS_ERR_INVALID, "device %d does not exist (%d devices)", device, count);
+    if (hipGetDeviceCount(&count) == hipSuccess) {
+        if (device >= count) return fail(GS_ERR_INVALID, "device %d does not exist (%d devices)", device, count);
+        int r;
+        if ((r = setup_static_scratch(device))) return r;
+    }
     gs_ctx *c = new (std::nothrow) gs_ctx;
     if (!c) return fail(GS_ERR_INVALID, "out of host memory");
     c->magic = CTX_MAGIC;
@@ -873,6 +921,30 @@ int gs_get_tuning(gs_ctx *ctx, const char *name, int64_t *value)
     return ok();
 }
 
+}  // extern "C"
+
+namespace {
+
+// The sort of gs_sort_pairs / gs_sort_pairs_static with its scratch at ws.
+int sort_pairs_with(gs_ctx *ctx, uint32_t *keys, uint32_t *vals, uint32_t *keys_tmp, uint32_t *vals_tmp, uint64_t n,
+                    int bits, void *ws, void *stream)
+{
+    hipStream_t st = (hipStream_t)stream;
+    bool in_tmp = false;
+    hipError_t e = radix_sort_standalone(keys, vals, keys_tmp, vals_tmp, n, bits, ws, ctx->tn.radix_part, &in_tmp,
+                                         st);
+    if (e == hipSuccess && in_tmp) {
+        e = hipMemcpyAsync(keys, keys_tmp, 4 * n, hipMemcpyDeviceToDevice, st);
+        if (e == hipSuccess) e = hipMemcpyAsync(vals, vals_tmp, 4 * n, hipMemcpyDeviceToDevice, st);
+    }
+    if (e != hipSuccess) return hip_fail(e, "sort");
+    return ok();
+}
+
+}  // namespace
+
+extern "C" {
+
 int gs_sort_pairs(gs_ctx *ctx, uint32_t *keys, uint32_t *vals, uint32_t *keys_tmp, uint32_t *vals_tmp, uint64_t n,
                   int bits, void *workspace, size_t workspace_bytes, void *stream)
 {
@@ -885,16 +957,29 @@ int gs_sort_pairs(gs_ctx *ctx, uint32_t *keys, uint32_t *vals, uint32_t *keys_tm
     if ((r = check_ws(workspace, workspace_bytes, radix_sort_scratch_bytes(n)))) return r;
     if (n == 0 || bits == 0) return ok();
     if ((r = check_device(ctx))) return r;
-    hipStream_t st = (hipStream_t)stream;
-    bool in_tmp = false;
-    hipError_t e = radix_sort_standalone(keys, vals, keys_tmp, vals_tmp, n, bits, workspace, ctx->tn.radix_part,
-                                         &in_tmp, st);
-    if (e == hipSuccess && in_tmp) {
-        e = hipMemcpyAsync(keys, keys_tmp, 4 * n, hipMemcpyDeviceToDevice, st);
-        if (e == hipSuccess) e = hipMemcpyAsync(vals, vals_tmp, 4 * n, hipMemcpyDeviceToDevice, st);
-    }
-    if (e != hipSuccess) return hip_fail(e, "gs_sort_pairs");
-    return ok();
+    return sort_pairs_with(ctx, keys, vals, keys_tmp, vals_tmp, n, bits, workspace, stream);
+}
+
+int gs_sort_pairs_static(gs_ctx *ctx, uint32_t *keys, uint32_t *vals, uint32_t *keys_tmp, uint32_t *vals_tmp,
+                         uint64_t n, int bits, void *stream)
+{
+    int r;
+    if ((r = check_ctx(ctx))) return r;
+    if (bits < 0 || bits > 32) return fail(GS_ERR_INVALID, "bits %d not in 0..32", bits);
+    if (n > GS_SORT_STATIC_MAX_KEYS)
+        return fail(GS_ERR_CAPACITY, "n = %llu keys exceeds the static scratch's maximum of %llu keys",
+                    (unsigned long long)n, (unsigned long long)GS_SORT_STATIC_MAX_KEYS);
+    if (n > 0 && (!keys || !vals || !keys_tmp || !vals_tmp))
+        return fail(GS_ERR_INVALID, "NULL key or value array");
+    if (n == 0 || bits == 0) return ok();
+    if ((r = check_device(ctx))) return r;
+    void *ws = static_scratch(ctx->device);
+    if (!ws)
+        return fail(GS_ERR_HIP, "no static scratch on device %d (its context was made without a HIP runtime)",
+                    ctx->device);
+    if (radix_sort_scratch_bytes(n) > SORT_STATIC_BYTES)
+        return fail(GS_ERR_CAPACITY, "static scratch too small for %llu keys", (unsigned long long)n);
+    return sort_pairs_with(ctx, keys, vals, keys_tmp, vals_tmp, n, bits, ws, stream);
 }
 
 }  // extern "C"
