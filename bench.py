@@ -28,10 +28,15 @@ sys.path.insert(0, ROOT)
 METRIC = "FPS & Mpix/s fwd, 1080p 1.5M Gaussians; fwd+bwd it/s; batched vs plain"
 # published dense fp32 vector peak of MI355X (256 CUs, 2.4 GHz, packed fp32 counted as two)
 FP32_PEAK_TFLOPS = 157.3
-# algorithmic fp32 flops of one blended (pixel, point) pair (FMA = 2): offsets 2,
-# quadratic falloff 8, exp2 1, clamp 1, cut-off test 1, transmittance 2, stop
-# test 1, weight 1, colour 6
+# algorithmic fp32 flops of one (pixel, point) pair of the forward compositing
+# (FMA = 2): offsets 2, quadratic falloff 8, exp2 1, clamp 1, cut-off test 1,
+# transmittance 2, stop test 1, weight 1, colour 6
 FLOPS_PER_BLEND = 23
+# ... and of one blended pair of its reverse: offsets 2, quadratic falloff 8,
+# exp2 1, clamp 1, 1/(1 - alpha) 2, transmittance recovery 1, blend weight 1,
+# g . colour 5, dL/dalpha 3, light-behind update 2, w = alpha dL/dalpha 1,
+# the six moments of w in the pixel offset 11, colour gradients 6
+FLOPS_PER_BLEND_BWD = 44
 
 
 # HBM traffic of one k_raster_fov launch on this workload, from two
@@ -39,9 +44,11 @@ FLOPS_PER_BLEND = 23
 # averaged over the dispatches), each scaled by the ratio of known bytes to
 # the same counter on a plain device copy (bench.py --copy-probe).  Valid
 # only for the kernel sources they were taken on (sha256 below).
-TRAFFIC = {"kernel": "k_raster_fov", "fetch_kib": 439994.9, "write_kib": 57104.5, "fetch_scale": 1.9999,
-           "write_scale": 1.0,
-           "sha256": "8dc52825230a6d6427f7a81a506e4310f265f26f8605bc256ba71b75b9528e09"}
+TRAFFIC = {"kernel": "k_raster_fov", "fetch_kib": 440614.0, "write_kib": 57135.8, "fetch_scale": 2.0,
+           "write_scale": 1.0, "sha256": "8dc52825230a6d6427f7a81a506e4310f265f26f8605bc256ba71b75b9528e09"}
+# The same for the compositing reverse on the 1280x720 1M-Gaussian frame.
+TRAFFIC_BWD = {"kernel": "k_raster_bwd", "fetch_kib": 55523.7, "write_kib": 29395.7, "fetch_scale": 2.0,
+               "write_scale": 1.0, "sha256": "8dc52825230a6d6427f7a81a506e4310f265f26f8605bc256ba71b75b9528e09"}
 
 
 def kernel_sha():
@@ -53,10 +60,11 @@ def kernel_sha():
     return h.hexdigest()
 
 
-def traffic_bytes():
-    if not TRAFFIC or TRAFFIC["sha256"] != kernel_sha():
+def traffic_bytes(t=None):
+    t = t or TRAFFIC
+    if not t or t["sha256"] != kernel_sha():
         return None
-    return (TRAFFIC["fetch_kib"] * TRAFFIC["fetch_scale"] + TRAFFIC["write_kib"] * TRAFFIC["write_scale"]) * 1024
+    return (t["fetch_kib"] * t["fetch_scale"] + t["write_kib"] * t["write_scale"]) * 1024
 
 
 def copy_probe(mib=1024, reps=5):
@@ -174,24 +182,47 @@ def raster_stats(fr):
     return [int(x) for x in st.cpu().tolist()]
 
 
+def timed_windows(fn, steps, warmup, windows=5, min_warm_s=0.3):
+    """Seconds per call of fn: `warmup` calls and at least `min_warm_s` of
+    calls untimed (the GPU has idled while the host built the workload),
+    then `windows` timed windows of `steps` calls each; returns (median,
+    fastest, slowest) window averages."""
+    import statistics
+
+    import torch
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    while time.perf_counter() - t0 < min_warm_s:
+        fn()
+        torch.cuda.synchronize()
+    per = []
+    for _ in range(windows):
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            fn()
+        torch.cuda.synchronize()
+        per.append((time.perf_counter() - t0) / steps)
+    return statistics.median(per), min(per), max(per)
+
+
 def plain_fwd_rate(g, wl, steps, warmup, tile=16):
     """Plain forward (projection, binning/sort, compositing) of one view."""
     import torch
     S, C = g.SceneTensors(wl.scene), g.Cameras(wl.cams)
     splats = g.gs_project(S, C, tile)
     cap = int(splats[..., 11].view(torch.int32).to(torch.int64).sum().item())
-    ws = None
-    for _ in range(warmup):
-        out = g.gs_render_fwd(S, C, tile, key_capacity=cap, workspace=ws)
-        ws = out["workspace"]
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(steps):
-        out = g.gs_render_fwd(S, C, tile, key_capacity=cap, workspace=ws)
-    torch.cuda.synchronize()
-    dt = (time.perf_counter() - t0) / steps
+    state = {"ws": None}
+
+    def frame():
+        state["out"] = g.gs_render_fwd(S, C, tile, key_capacity=cap, workspace=state["ws"])
+        state["ws"] = state["out"]["workspace"]
+
+    dt, lo, hi = timed_windows(frame, steps, warmup)
     px = sum(w * h for w, h in C.sizes)
-    return dict(fps=1.0 / dt, mpix_s=px / dt / 1e6, ms=dt * 1e3, keys=int(out["num_keys"].item()))
+    return dict(fps=1.0 / dt, mpix_s=px / dt / 1e6, ms=dt * 1e3, ms_range=[lo * 1e3, hi * 1e3],
+                keys=int(state["out"]["num_keys"].item()), timing=f"median of 5 windows of {steps} frames")
 
 
 def fwd_bwd_rate(g, wl, steps, warmup, tile=16):
@@ -215,15 +246,45 @@ def fwd_bwd_rate(g, wl, steps, warmup, tile=16):
         for p in params:
             p.grad = None
 
-    for _ in range(warmup):
-        it()
+    dt, lo, hi = timed_windows(it, steps, warmup)
+    out = dict(it_s=1.0 / dt, ms=dt * 1e3, ms_range=[lo * 1e3, hi * 1e3],
+               timing=f"median of 5 windows of {steps} iterations")
+    # the compositing reverse on its own, timed live with events on the
+    # stream it runs on, against the blended pairs of the forward (the
+    # reverse takes the forward's decisions, pair for pair)
+    fw = g.gs_render_fwd(S, C, tile, key_capacity=cap)
+    st = torch.zeros(4, dtype=torch.int64, device="cuda")
+    g.gs_rasterize_fwd(fw["splats"], S.n, C, tile, fw["vals"], fw["ranges"], stats=st)
+    img = fw["image"]
+    dL = torch.sign(img - target) / img.numel()
+    grads = torch.empty((1, S.n, 12), dtype=torch.float32, device="cuda")
+    B = g.binding
+    L = g.lib()
+    bg = (ctypes.c_float * 3)(0.0, 0.0, 0.0)
+
+    def bwd():
+        B._check(L.gs_rasterize_bwd(B._ptr(fw["splats"]), S.n, C.hp, C.dp, C.n, tile, B._ptr(fw["vals"]),
+                                    B._ptr(fw["ranges"]), ctypes.cast(bg, B._VP), B._ptr(fw["final_T"]),
+                                    B._ptr(fw["n_contrib"]), B._ptr(dL), B._ptr(grads), None, 0, B._stream()))
+
+    for _ in range(3):
+        bwd()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    reps = 20
+    e0.record()
+    for _ in range(reps):
+        bwd()
+    e1.record()
     torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(steps):
-        it()
-    torch.cuda.synchronize()
-    dt = (time.perf_counter() - t0) / steps
-    return dict(it_s=1.0 / dt, ms=dt * 1e3)
+    t_b = e0.elapsed_time(e1) * 1e-3 / reps
+    blended = int(st[0].item())
+    ach = blended * FLOPS_PER_BLEND_BWD / t_b / 1e12
+    out["roofline_bwd"] = {"bound": "alu", "kernel": "k_raster_bwd", "unit": "TFLOP/s", "achieved": ach,
+                           "peak": FP32_PEAK_TFLOPS, "frac": ach / FP32_PEAK_TFLOPS,
+                           "frac_of_nonpacked": ach / (FP32_PEAK_TFLOPS / 2), "ms": t_b * 1e3,
+                           "traffic": traffic_bytes(TRAFFIC_BWD), "unit_of_work": "blended (pixel, point) pair",
+                           "blended_pairs": blended, "flops_per_pair": FLOPS_PER_BLEND_BWD}
+    return out
 
 
 def batched_vs_plain(g, steps=3, log=None, fixed=None, plain_too=True):
@@ -285,20 +346,32 @@ def batched_vs_plain(g, steps=3, log=None, fixed=None, plain_too=True):
                 tried=[dict(c, ms=round(m, 3)) for c, m in tried])
 
 
-def cpu_baseline(fr, wl, n_gauss_sample=12000, px_sample=(3000, 9000), threads=16):
+def host_threads():
+    """Threads the oracle runs on: the CPUs this process may use, at most the
+    16 a one-GPU machine shares out."""
+    return max(1, min(16, len(os.sched_getaffinity(0))))
+
+
+def cpu_baseline(fr, wl, n_gauss_sample=12000, px_sample=(3000, 9000), threads=None):
     """FP64 oracle on the host, on a bounded sample of the same workload:
     projection (with the four level versions) of a random subset of the
     Gaussians for both eyes, and per-pixel foveated compositing of random
-    pixels over the full projected splat set.  The per-Gaussian and per-pixel
-    costs are extrapolated to a whole stereo frame."""
+    pixels over the full projected splat set, each on `threads` threads.  The
+    per-Gaussian and per-pixel costs are extrapolated to a whole stereo
+    frame."""
+    import concurrent.futures as cf
+
     import numpy as np
     import oracle
-    threads = max(1, min(threads, os.cpu_count() or 1))
+    threads = threads or host_threads()
     rng = np.random.default_rng(0)
     sub = wl.scene.subset(rng.choice(wl.scene.n, n_gauss_sample, replace=False))
+    parts = [sub.subset(np.arange(a, min(a + -(-sub.n // threads), sub.n)))
+             for a in range(0, sub.n, -(-sub.n // threads))]
     t0 = time.perf_counter()
-    for cam in wl.cams:
-        oracle.project(sub, cam, levels=True)
+    with cf.ThreadPoolExecutor(threads) as ex:  # the oracle's C code runs without the GIL
+        for cam in wl.cams:
+            list(ex.map(lambda sc: oracle.project(sc, cam, levels=True), parts))
     t_proj = (time.perf_counter() - t0) / (n_gauss_sample * len(wl.cams))
     sp = fr.splats.cpu().numpy()
     spi = fr.splats.cpu().view(fr.torch.int32).numpy()
@@ -328,12 +401,48 @@ def cpu_baseline(fr, wl, n_gauss_sample=12000, px_sample=(3000, 9000), threads=1
         f + a * c.width * c.height for f, a, c in zip(fixed, per_px, wl.cams))
     px = sum(c.width * c.height for c in wl.cams)
     return dict(value=px / frame / 1e6, unit="Mpix/s", cores=threads, kind="oracle",
+                host_cpus=len(os.sched_getaffinity(0)),
                 sample=(f"projection of {n_gauss_sample} random Gaussians x {len(wl.cams)} eyes x "
-                        f"(base + {wl.scene.lvl_opacity_logits.shape[0]} levels) single-threaded, and "
-                        f"foveated compositing of {px_sample[0]}+{px_sample[1]} random pixels per eye over "
-                        f"all projected splats; extrapolated to one full stereo frame "
+                        f"(base + {wl.scene.lvl_opacity_logits.shape[0]} levels), and foveated compositing "
+                        f"of {px_sample[0]}+{px_sample[1]} random pixels per eye over all projected splats, "
+                        f"both on {threads} threads; extrapolated to one full stereo frame "
                         f"({frame:.1f} s/frame)"),
                 frame_s=frame)
+
+
+def cpu_full_frames(threads=None, reps=3):
+    """The oracle's full render (FP64 projection, then per-pixel compositing)
+    of whole frames of the two plain workloads: 4096 Gaussians at 128x128
+    and 500k Gaussians at 1280x720, on all the threads it may use and on one.
+    Median of `reps` runs, except that the single-threaded 1280x720 frame is
+    timed on every 8th pixel row and scaled by 8 (about 75 s whole)."""
+    import numpy as np
+    import oracle
+    import scenegen
+    threads = threads or host_threads()
+    out = {"host_cpus": len(os.sched_getaffinity(0)), "threads": threads}
+    for label, wl, r in (("128x128_4k", scenegen.config1(), reps), ("1280x720_500k", scenegen.config2(), 1)):
+        cam = wl.cams[0]
+        W, H = cam.width, cam.height
+        rec = {}
+        for th in (threads, 1):
+            sub_rows = th == 1 and H > 128
+            pix = None
+            if sub_rows:
+                ys = np.arange(0, H, 8)
+                pix = np.stack(np.meshgrid(np.arange(W), ys), -1).reshape(-1, 2).astype(np.int32)
+            ts = []
+            for _ in range(r):
+                t0 = time.perf_counter()
+                oracle.render(wl.scene, cam, pixels=pix, nthreads=th)
+                ts.append(time.perf_counter() - t0)
+            t = float(np.median(ts))
+            if sub_rows:
+                t *= H / len(np.arange(0, H, 8))
+            rec[f"{th}_threads"] = {"s_per_frame": t, "fps": 1.0 / t, "mpix_s": W * H / t / 1e6,
+                                    "measured_on": "every 8th row, scaled" if sub_rows else "full frame"}
+        out[label] = rec
+    return out
 
 
 def pipelined_frames(g, wl, tile, frames=40, warmup=6):
@@ -436,6 +545,9 @@ def main():
     ap.add_argument("--radix-part", type=int, default=16384)
     ap.add_argument("--copy-probe", action="store_true",
                     help="only run a plain 1 GiB device copy (memory-counter calibration)")
+    ap.add_argument("--only", choices=("fwdbwd", "plain"),
+                    help="only the 1280x720 1M-Gaussian forward+backward, or only the 1280x720 500k plain "
+                         "forward (for profiling one kernel)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py runs on exactly one GPU: the renderer has no multi-GPU path "
@@ -449,6 +561,12 @@ def main():
     import paper_2407_00435_amd as g
     import scenegen
 
+    if args.only == "fwdbwd":
+        print(json.dumps(fwd_bwd_rate(g, scenegen.config4(), args.steps, args.warmup)), flush=True)
+        return
+    if args.only == "plain":
+        print(json.dumps(plain_fwd_rate(g, scenegen.config2(), args.steps, args.warmup)), flush=True)
+        return
     if args.batched_only:
         r = batched_vs_plain(g, args.steps, log, fixed=dict(tile=args.tile, batch_views=args.batch_views,
                                                              lanes=args.lanes, radix_part=args.radix_part,
@@ -468,7 +586,10 @@ def main():
     keys = int(fr.num.item())
     stats = raster_stats(fr)
     t_r = stage_ms["raster"] * 1e-3
-    achieved = stats[0] * FLOPS_PER_BLEND / t_r / 1e12
+    # the algorithmic unit is the evaluated (pixel, point) pair; the
+    # blended pairs (those that change the pixel) are reported beside it
+    achieved = stats[1] * FLOPS_PER_BLEND / t_r / 1e12
+    achieved_bl = stats[0] * FLOPS_PER_BLEND / t_r / 1e12
     line = {
         "metric": METRIC,
         "value": px / (wall / args.steps) / 1e6,
@@ -492,13 +613,18 @@ def main():
         "raster_pairs": {"blended": stats[0], "evaluated": stats[1], "staged": stats[2], "kept": stats[3]},
         "roofline": {"bound": "alu", "kernel": "k_raster_fov", "achieved": achieved,
                      "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s", "frac": achieved / FP32_PEAK_TFLOPS,
-                     "traffic": traffic_bytes()},
+                     "traffic": traffic_bytes(), "unit_of_work": "evaluated (pixel, point) pair",
+                     "flops_per_pair": FLOPS_PER_BLEND, "pairs": stats[1], "ms": stage_ms["raster"],
+                     "frac_of_nonpacked": achieved / (FP32_PEAK_TFLOPS / 2),
+                     "achieved_blended": achieved_bl, "frac_blended": achieved_bl / FP32_PEAK_TFLOPS},
     }
     if not args.no_extras:
         log("HBM bandwidth of projection and sort ...")
         line["hbm"] = hbm_bandwidth(g, fr, stage_ms)
         log("consecutive frames on two streams ...")
         line["pipelined_frames"] = pipelined_frames(g, wl, args.tile)
+        log("plain forward, 4096 Gaussians, 128x128 ...")
+        line["plain_fwd_128_4k"] = plain_fwd_rate(g, scenegen.config1(), 50, 5)
         log("plain forward, 500k Gaussians, 1280x720 ...")
         line["plain_fwd_720p_500k"] = plain_fwd_rate(g, scenegen.config2(), 20, 3)
         log("forward+backward, 1M Gaussians, 1280x720 ...")
@@ -508,6 +634,8 @@ def main():
     if not args.no_cpu_baseline:
         log("oracle on the host (bounded sample) ...")
         line["cpu_baseline"] = cpu_baseline(fr, wl)
+        log("oracle on whole 128x128 and 1280x720 frames ...")
+        line["cpu_oracle_frames"] = cpu_full_frames()
     print(json.dumps(line), flush=True)
 
 
