@@ -393,3 +393,45 @@ def fr_render(scene, cam, pix_lo, pix_w, bg=(0.0, 0.0, 0.0)) -> np.ndarray:
     out = composite(pr, int(cam.width), int(cam.height), bg=bg, qbound=scene.qbound, pix_lo=pix_lo,
                     pix_w=np.asarray(pix_w, dtype=np.float64), levels=True, nthreads=1)
     return out["rgb"]
+
+
+# ---------------------------------------------------------------------------
+# HVSQ (Section 2.2, Eq. 2) on the stated feature reading (colour channels,
+# square windows whose half-width grows linearly with eccentricity).
+
+def hvsq_radius(cam, fov, rho: float, eps: float = 1e-4):
+    """Pooling half-width of every pixel: floor(rho * eccentricity in
+    degrees), with the eccentricity of Section 4.1 (the angle between the
+    pixel's and the gaze pixel's rays).  Returns (radius int32 [H*W],
+    ambiguous uint8 [H*W]: rho * ecc within eps of an integer, where a
+    float32 evaluation may land on the other side)."""
+    f = fovea(cam, fov, 1, 16)
+    x = rho * f["ecc"]
+    rad = np.floor(x).astype(np.int32)
+    frac = x - np.floor(x)
+    amb = ((frac < eps) | (frac > 1.0 - eps)).astype(np.uint8)
+    return rad, amb
+
+
+def hvsq(img_a, img_r, radius, W: int, H: int, region=None, n_regions: int = 0, grad_region=None,
+         want_terms: bool = False) -> dict:
+    """HVSQ of altered image img_a against reference img_r, both [3][H][W]
+    (any array shape with 3*H*W elements), radius [H*W] pooling half-widths,
+    region [H*W] (1..n_regions, optional).  Returns per-region sums and
+    counts of the per-pixel terms (index n_regions = the whole image), the
+    means ("hvsq"), optionally per-pixel terms and the gradient of the mean
+    over region grad_region (0 = whole image) with respect to img_a."""
+    a = _f64(img_a).reshape(3, H, W)
+    r = _f64(img_r).reshape(3, H, W)
+    rad = np.ascontiguousarray(radius, np.int32).reshape(-1)
+    reg = None if region is None else np.ascontiguousarray(region, np.uint8).reshape(-1)
+    sums = np.zeros(n_regions + 1)
+    counts = np.zeros(n_regions + 1)
+    terms = np.zeros(W * H) if want_terms else None
+    grad = np.zeros((3, H, W)) if grad_region is not None else None
+    lib().oc_hvsq(ctypes.c_int(W), ctypes.c_int(H), _p(a), _p(r), _p(rad), _p(reg), ctypes.c_int(n_regions),
+                  ctypes.c_int(0 if grad_region is None else int(grad_region)), _p(sums), _p(counts), _p(terms),
+                  _p(grad))
+    with np.errstate(invalid="ignore", divide="ignore"):
+        means = np.where(counts > 0, sums / np.maximum(counts, 1), 0.0)
+    return dict(sums=sums, counts=counts, hvsq=means, terms=terms, grad=grad)

@@ -1142,4 +1142,102 @@ int oc_project_bwd(int n, int sh_degree, const double *means, const double *log_
     return 0;
 }
 
+/* ------------------------------------------------------------------------ */
+/* HVSQ (Section 2.2, Eq. 2): mean over the pixels of a region of
+ * (M(I^a_i) - M(I^r_i))^2 + (sigma(I^a_i) - sigma(I^r_i))^2, the pooled
+ * statistics of the altered and reference images around each pixel i.
+ * The paper takes the features and the pooling shape from the cited HVSQ
+ * work; the readings here: the features are the three colour channels (the
+ * term is averaged over them); the pooling of pixel i is the square window
+ * of half-width radius[i] centred on it, clipped to the image (its area
+ * grows quadratically when the radius grows linearly with eccentricity);
+ * M is the mean and sigma the population standard deviation over the
+ * window.  Region restriction (Section 4.3): the mean runs over the pixels
+ * of one quality region.  Every window is summed directly, two passes
+ * (mean, then squared deviations).
+ *
+ * a, r: [3][H][W]; radius: [H*W] (>= 0); region (nullable): [H*W] in
+ * 1..n_regions.  sums[t - 1], counts[t - 1]: the sum of the per-pixel terms
+ * and the pixel count of region t; sums[n_regions], counts[n_regions]: the
+ * whole image.  terms (nullable): [H*W] per-pixel term.  grad (nullable):
+ * [3][H][W], d(mean over region grad_region, or the whole image when 0, of
+ * the per-pixel terms) / d a; where sigma(I^a_i) = 0 its term contributes
+ * only through the mean (the square root has no derivative there). */
+static void window_stats(int W, int H, const double *img, int x, int y, int rad, double mu[3], double sd[3], int *n)
+{
+    int x0 = x - rad < 0 ? 0 : x - rad, x1 = x + rad > W - 1 ? W - 1 : x + rad;
+    int y0 = y - rad < 0 ? 0 : y - rad, y1 = y + rad > H - 1 ? H - 1 : y + rad;
+    int cnt = (x1 - x0 + 1) * (y1 - y0 + 1);
+    for (int c = 0; c < 3; c++) {
+        const double *pl = img + (size_t)c * W * H;
+        double s = 0.0;
+        for (int yy = y0; yy <= y1; yy++)
+            for (int xx = x0; xx <= x1; xx++) s += pl[(size_t)yy * W + xx];
+        double m = s / cnt, v = 0.0;
+        for (int yy = y0; yy <= y1; yy++)
+            for (int xx = x0; xx <= x1; xx++) {
+                double d = pl[(size_t)yy * W + xx] - m;
+                v += d * d;
+            }
+        mu[c] = m;
+        sd[c] = sqrt(v / cnt);
+    }
+    *n = cnt;
+}
+
+int oc_hvsq(int W, int H, const double *a, const double *r, const int32_t *radius, const uint8_t *region,
+            int n_regions, int grad_region, double *sums, double *counts, double *terms, double *grad)
+{
+    for (int t = 0; t <= n_regions; t++) sums[t] = counts[t] = 0.0;
+    if (grad) memset(grad, 0, sizeof(double) * 3 * (size_t)W * H);
+    for (int y = 0; y < H; y++)
+        for (int x = 0; x < W; x++) {
+            size_t i = (size_t)y * W + x;
+            double ma[3], sa[3], mr[3], sr[3];
+            int n;
+            window_stats(W, H, a, x, y, radius[i], ma, sa, &n);
+            window_stats(W, H, r, x, y, radius[i], mr, sr, &n);
+            double term = 0.0;
+            for (int c = 0; c < 3; c++) term += (ma[c] - mr[c]) * (ma[c] - mr[c]) + (sa[c] - sr[c]) * (sa[c] - sr[c]);
+            term /= 3.0;
+            int t = region ? region[i] : 0;
+            if (t >= 1 && t <= n_regions) {
+                sums[t - 1] += term;
+                counts[t - 1] += 1.0;
+            }
+            sums[n_regions] += term;
+            counts[n_regions] += 1.0;
+            if (terms) terms[i] = term;
+        }
+    if (!grad) return 0;
+    double N = grad_region == 0 ? counts[n_regions] : counts[grad_region - 1];
+    if (N <= 0.0) return 0;
+    for (int y = 0; y < H; y++)
+        for (int x = 0; x < W; x++) {
+            size_t i = (size_t)y * W + x;
+            if (grad_region != 0 && (!region || region[i] != grad_region)) continue;
+            double ma[3], sa[3], mr[3], sr[3];
+            int n;
+            window_stats(W, H, a, x, y, radius[i], ma, sa, &n);
+            window_stats(W, H, r, x, y, radius[i], mr, sr, &n);
+            int rad = radius[i];
+            int x0 = x - rad < 0 ? 0 : x - rad, x1 = x + rad > W - 1 ? W - 1 : x + rad;
+            int y0 = y - rad < 0 ? 0 : y - rad, y1 = y + rad > H - 1 ? H - 1 : y + rad;
+            for (int c = 0; c < 3; c++) {
+                /* d term / d a_j = (1/3) [2 (ma - mr) / n + 2 (sa - sr) (a_j - ma) / (n sa)] */
+                double k = 1.0 / (3.0 * N);
+                double gm = k * 2.0 * (ma[c] - mr[c]) / n;
+                double gs = sa[c] > 0.0 ? k * 2.0 * (sa[c] - sr[c]) / (n * sa[c]) : 0.0;
+                const double *pl = a + (size_t)c * W * H;
+                double *gp = grad + (size_t)c * W * H;
+                for (int yy = y0; yy <= y1; yy++)
+                    for (int xx = x0; xx <= x1; xx++) {
+                        size_t j = (size_t)yy * W + xx;
+                        gp[j] += gm + gs * (pl[j] - ma[c]);
+                    }
+            }
+        }
+    return 0;
+}
+
 int oc_version(void) { return 1; }
