@@ -529,6 +529,34 @@ def hbm_bandwidth(g, fr, stage_ms, reps=10):
     return out
 
 
+def hvsq_rate(g, fr, wl, reps=10):
+    """HVSQ (Eq. 2) of the foveated stereo frame against the full render of
+    the same eyes, per ring, with the gradient of the whole-frame metric
+    (pooling half-width 0.25 x eccentricity in degrees, in pixels), timed
+    with events on the library's stream."""
+    import numpy as np
+    import torch
+    ref = g.gs_render_fwd(fr.S, fr.C, fr.tile, key_capacity=fr.cap, check=True)["image"]
+    rho = 0.25 * float(wl.cams[0].fx) * np.pi / 180.0
+    rad = g.gs_hvsq_pooling(fr.C, wl.foveae, rho)
+    out = g.gs_hvsq(fr.image, ref, fr.C, rad, region=fr.pix_level, n_regions=fr.L, grad_region=0)
+    ws = out["workspace"]
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    res = {}
+    for label, gr in (("metric", -1), ("metric_and_gradient", 0)):
+        g.gs_hvsq(fr.image, ref, fr.C, rad, region=fr.pix_level, n_regions=fr.L, grad_region=gr, workspace=ws)
+        e0.record()
+        for _ in range(reps):
+            out = g.gs_hvsq(fr.image, ref, fr.C, rad, region=fr.pix_level, n_regions=fr.L, grad_region=gr,
+                            workspace=ws)
+        e1.record()
+        torch.cuda.synchronize()
+        res[label + "_ms"] = e0.elapsed_time(e1) / reps
+    res["hvsq_per_ring"] = [[round(float(x), 7) for x in row] for row in out["hvsq"].cpu().numpy()]
+    res["max_radius_px"] = int(rad.max().item())
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -629,6 +657,8 @@ def main():
         line["plain_fwd_720p_500k"] = plain_fwd_rate(g, scenegen.config2(), 20, 3)
         log("forward+backward, 1M Gaussians, 1280x720 ...")
         line["fwd_bwd_720p_1M"] = fwd_bwd_rate(g, scenegen.config4(), 10, 3)
+        log("HVSQ of the stereo frame ...")
+        line["hvsq_stereo_1080p"] = hvsq_rate(g, fr, wl)
         log("batched vs plain, 3M Gaussians, 32 views + 2 eyes ...")
         line["batched_vs_plain"] = batched_vs_plain(g, 3, log)
     if not args.no_cpu_baseline:

@@ -448,6 +448,43 @@ size_t gs_sort_workspace_bytes(uint64_t n);
 int gs_sort_pairs(gs_ctx *ctx, uint32_t *keys, uint32_t *vals, uint32_t *keys_tmp, uint32_t *vals_tmp,
                   uint64_t n, int bits, void *workspace, size_t workspace_bytes, void *stream);
 
+/* HVSQ, the eccentricity-aware quality metric (Section 2.2, Eq. 2), per
+ * quality region as the foveated training uses it (Section 4.3).  The
+ * paper takes the features and pooling from the cited HVSQ work; this
+ * library reads them as: features = the three colour channels; the pooling
+ * of pixel i = the square window of half-width radius[i] centred on it,
+ * clipped to the image; statistics = mean and population standard deviation
+ * per channel.  term_i = (1/3) sum over channels of (M_a - M_r)^2 +
+ * (S_a - S_r)^2; the HVSQ of a region = the mean of term_i over its pixels.
+ *
+ * gs_hvsq_pooling: radius[p] = floor(rho * eccentricity of p in degrees)
+ * (the eccentricity of gs_fovea_prep; a pooling whose area grows
+ * quadratically with eccentricity) for the n_views (<= 8) views and their
+ * gazes; radius: device int32 [n_pixels].
+ *
+ * gs_hvsq: img_a (altered), img_r (reference): device planar float images
+ * as everywhere in this library; radius: device int32 [n_pixels] (negative
+ * values count as 0); region: device uint8 [n_pixels] in 1..n_regions
+ * (nullable when n_regions = 0), e.g. the pix_level of gs_fovea_prep.
+ * Outputs (device, overwritten): sums, counts: double [n_views][n_regions + 1],
+ * per view the sum of term_i and the pixel count of each region (index
+ * t - 1) and of the whole view (index n_regions); terms (nullable): double
+ * [n_pixels], term_i.  grad_region = -1: no gradient; 0 or t in
+ * 1..n_regions: dL_da (device float, planar like img_a) receives the
+ * gradient of L = sum over views of the view's HVSQ over the whole view (0)
+ * or over region t, with respect to img_a (where the altered window's
+ * standard deviation is 0 only its mean contributes).  Double-precision
+ * accumulations use atomics, so the last bits depend on scheduling.
+ * Workspace: gs_hvsq_workspace_bytes(want_grad) bytes, 256-byte aligned.
+ * At most GS_HVSQ_MAX_REGIONS (8) regions. */
+int gs_hvsq_pooling(gs_ctx *ctx, const gs_camera *cams_host, const gs_camera *cams_dev, const gs_fovea *fov_host,
+                    int n_views, float rho, int32_t *radius, void *stream);
+size_t gs_hvsq_workspace_bytes(gs_ctx *ctx, const gs_camera *cams_host, int n_views, int want_grad);
+int gs_hvsq(gs_ctx *ctx, const gs_camera *cams_host, const gs_camera *cams_dev, int n_views, const float *img_a,
+            const float *img_r, const int32_t *radius, const uint8_t *region, int n_regions, double *sums,
+            double *counts, double *terms, int grad_region, float *dL_da, void *workspace, size_t workspace_bytes,
+            void *stream);
+
 /* Largest n of gs_sort_pairs_static. */
 #define GS_SORT_STATIC_MAX_KEYS (1u << 24)
 

@@ -435,3 +435,15 @@ def hvsq(img_a, img_r, radius, W: int, H: int, region=None, n_regions: int = 0, 
     with np.errstate(invalid="ignore", divide="ignore"):
         means = np.where(counts > 0, sums / np.maximum(counts, 1), 0.0)
     return dict(sums=sums, counts=counts, hvsq=means, terms=terms, grad=grad)
+
+
+def hvsq_at(img_a, img_r, radius, W: int, H: int, pixels) -> np.ndarray:
+    """Per-pixel HVSQ terms at the (x, y) rows of ``pixels`` only."""
+    a = _f64(img_a).reshape(3, H, W)
+    r = _f64(img_r).reshape(3, H, W)
+    rad = np.ascontiguousarray(radius, np.int32).reshape(-1)
+    px = np.ascontiguousarray(pixels, np.int32)
+    out = np.zeros(px.shape[0])
+    lib().oc_hvsq_at(ctypes.c_int(W), ctypes.c_int(H), _p(a), _p(r), _p(rad), ctypes.c_int(px.shape[0]), _p(px),
+                     _p(out))
+    return out

@@ -1240,4 +1240,23 @@ int oc_hvsq(int W, int H, const double *a, const double *r, const int32_t *radiu
     return 0;
 }
 
+/* Per-pixel HVSQ terms at listed pixels px [npx][2] = (x, y) only (for
+ * sampled checks of large images). */
+int oc_hvsq_at(int W, int H, const double *a, const double *r, const int32_t *radius, int npx, const int32_t *px,
+               double *terms)
+{
+    for (int k = 0; k < npx; k++) {
+        int x = px[2 * k], y = px[2 * k + 1];
+        double ma[3], sa[3], mr[3], sr[3];
+        int n;
+        int rad = radius[(size_t)y * W + x];
+        window_stats(W, H, a, x, y, rad, ma, sa, &n);
+        window_stats(W, H, r, x, y, rad, mr, sr, &n);
+        double term = 0.0;
+        for (int c = 0; c < 3; c++) term += (ma[c] - mr[c]) * (ma[c] - mr[c]) + (sa[c] - sr[c]) * (sa[c] - sr[c]);
+        terms[k] = term / 3.0;
+    }
+    return 0;
+}
+
 int oc_version(void) { return 1; }

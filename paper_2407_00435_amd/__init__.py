@@ -10,7 +10,7 @@ from .binding import (  # noqa: F401
     gs_project, gs_bin_sort, gs_rasterize_fwd, gs_rasterize_bwd, gs_project_bwd,
     gs_fovea_prep, gs_rasterize_foveated, gs_render_foveated, gs_render_fwd,
     gs_workspace_bytes, gs_render_workspace_bytes, gs_tile_count, splat_fields, gs_sort_pairs, gs_set_tuning,
-    gs_sort_pairs_static,
+    gs_sort_pairs_static, gs_hvsq_pooling, gs_hvsq,
     gs_l1_grad, gs_ce_score, gs_select_lowest, gs_weighted_scale, Graph,
     gs_rasterize_foveated_bwd, gs_project_bwd_levels,
 )

@@ -104,6 +104,9 @@ _SIGS = {
     "gs_select_workspace_bytes": ([_I32], _SZ),
     "gs_select_lowest": ([_VP, _I32, _I32, _VP, _VP, _VP, _SZ, _VP], _I),
     "gs_weighted_scale": ([_VP, _VP, _I32, _I, ctypes.c_float, ctypes.c_float, _VP, _VP, _I, _VP], _I),
+    "gs_hvsq_pooling": ([_PC, _VP, _PF, _I, ctypes.c_float, _VP, _VP], _I),
+    "gs_hvsq_workspace_bytes": ([_PC, _I, _I], _SZ),
+    "gs_hvsq": ([_PC, _VP, _I, _VP, _VP, _VP, _VP, _I, _VP, _VP, _VP, _I, _VP, _VP, _SZ, _VP], _I),
     "gs_graph_begin": ([_VP], _I),
     "gs_graph_end": ([_VP, ctypes.POINTER(_VP)], _I),
     "gs_graph_launch": ([_VP, _VP], _I),
@@ -116,7 +119,8 @@ CTX_FIRST = frozenset((
     "gs_rasterize_bwd", "gs_project_bwd", "gs_fovea_prep", "gs_rasterize_foveated",
     "gs_rasterize_foveated_bwd", "gs_project_bwd_levels", "gs_render_foveated", "gs_render_fwd",
     "gs_l1_grad", "gs_ce_score", "gs_select_lowest", "gs_weighted_scale", "gs_sort_pairs",
-    "gs_sort_pairs_static", "gs_set_tuning", "gs_get_tuning", "gs_poll_status"))
+    "gs_sort_pairs_static", "gs_set_tuning", "gs_get_tuning", "gs_poll_status", "gs_hvsq_pooling",
+    "gs_hvsq_workspace_bytes", "gs_hvsq"))
 for _name in CTX_FIRST:
     _a, _r = _SIGS[_name]
     _SIGS[_name] = ([_VP] + list(_a), _r)
@@ -730,6 +734,39 @@ def gs_sort_pairs(keys: torch.Tensor, vals: torch.Tensor, bits: int, workspace=N
     _check(lib().gs_sort_pairs(_ptr(keys), _ptr(vals), _ptr(kt), _ptr(vt), n, bits, workspace[1],
                                workspace[2], _stream()))
     return workspace
+
+
+def gs_hvsq_pooling(cams: Cameras, foveae, rho: float):
+    """Pooling half-widths floor(rho * eccentricity) of every pixel (int32 [n_pixels])."""
+    _, n_px = cams.tiles(16)
+    radius = torch.empty(n_px, dtype=torch.int32, device=cams.dev.device)
+    fa = _foveae(foveae)
+    _check(lib().gs_hvsq_pooling(cams.hp, cams.dp, ctypes.cast(fa, _PF), cams.n, float(rho), _ptr(radius),
+                                 _stream()))
+    return radius
+
+
+def gs_hvsq(img_a, img_r, cams: Cameras, radius, region=None, n_regions: int = 0, grad_region: int = -1,
+            want_terms: bool = False, workspace=None):
+    """HVSQ of img_a against img_r (planar float images of ``cams``): per view
+    and region the sums and counts of the per-pixel terms, their means
+    ("hvsq", [n_views][n_regions + 1], the last column the whole view),
+    optionally the per-pixel terms and, for grad_region >= 0, the gradient of
+    the sum over views of the region's HVSQ with respect to img_a."""
+    dev = img_a.device
+    _, n_px = cams.tiles(16)
+    sums = torch.empty((cams.n, n_regions + 1), dtype=torch.float64, device=dev)
+    counts = torch.empty_like(sums)
+    terms = torch.empty(n_px, dtype=torch.float64, device=dev) if want_terms else None
+    grad = torch.empty_like(img_a) if grad_region >= 0 else None
+    need = int(lib().gs_hvsq_workspace_bytes(cams.hp, cams.n, int(grad_region >= 0)))
+    if workspace is None or workspace[2] < need:
+        workspace = _ws(need)
+    _check(lib().gs_hvsq(cams.hp, cams.dp, cams.n, _ptr(img_a.contiguous()), _ptr(img_r.contiguous()),
+                         _ptr(radius), _ptr(region), int(n_regions), _ptr(sums), _ptr(counts), _ptr(terms),
+                         int(grad_region), _ptr(grad), workspace[1], workspace[2], _stream()))
+    return dict(sums=sums, counts=counts, hvsq=sums / counts.clamp(min=1), terms=terms, grad=grad,
+                workspace=workspace)
 
 
 SORT_STATIC_MAX_KEYS = 1 << 24

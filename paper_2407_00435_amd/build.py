@@ -16,7 +16,8 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libgsmi.so")
-SOURCES = ["api.hip", "project.hip", "sort.hip", "binning.hip", "raster.hip", "loss.hip", "prune.hip"]
+SOURCES = ["api.hip", "project.hip", "sort.hip", "binning.hip", "raster.hip", "loss.hip", "prune.hip",
+           "hvsq.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 FLAGS = [

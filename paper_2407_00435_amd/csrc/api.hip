@@ -863,6 +863,51 @@ int gs_graph_destroy(gs_graph *graph)
     return ok();
 }
 
+int gs_hvsq_pooling(gs_ctx *ctx, const gs_camera *cams_host, const gs_camera *cams_dev, const gs_fovea *fov_host,
+                    int n_views, float rho, int32_t *radius, void *stream)
+{
+    int r;
+    if ((r = check_ctx(ctx))) return r;
+    if ((r = check_cams(cams_host, cams_dev, n_views, 16, nullptr, nullptr))) return r;
+    if (n_views > 8) return fail(GS_ERR_UNSUPPORTED, "at most 8 views (got %d)", n_views);
+    if (!fov_host || !radius) return fail(GS_ERR_INVALID, "NULL output or input pointer");
+    if (!(rho >= 0.f) || !std::isfinite(rho)) return fail(GS_ERR_INVALID, "rho must be finite and >= 0");
+    if ((r = check_device(ctx))) return r;
+    hipError_t e = launch_hvsq_radius(cams_host, cams_dev, fov_host, n_views, rho, radius, (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(e, "gs_hvsq_pooling");
+    return ok();
+}
+
+size_t gs_hvsq_workspace_bytes(gs_ctx *ctx, const gs_camera *cams_host, int n_views, int want_grad)
+{
+    if (check_ctx(ctx) || check_cams(cams_host, cams_host, n_views, 16, nullptr, nullptr)) return 0;
+    return hvsq_scratch_bytes(cams_host, n_views, want_grad != 0);
+}
+
+int gs_hvsq(gs_ctx *ctx, const gs_camera *cams_host, const gs_camera *cams_dev, int n_views, const float *img_a,
+            const float *img_r, const int32_t *radius, const uint8_t *region, int n_regions, double *sums,
+            double *counts, double *terms, int grad_region, float *dL_da, void *workspace, size_t workspace_bytes,
+            void *stream)
+{
+    int r;
+    if ((r = check_ctx(ctx))) return r;
+    if ((r = check_cams(cams_host, cams_dev, n_views, 16, nullptr, nullptr))) return r;
+    if (n_regions < 0 || n_regions > GS_HVSQ_MAX_REGIONS)
+        return fail(GS_ERR_UNSUPPORTED, "n_regions %d not in 0..%d", n_regions, GS_HVSQ_MAX_REGIONS);
+    if (!img_a || !img_r || !radius || !sums || !counts) return fail(GS_ERR_INVALID, "NULL output or input pointer");
+    if (n_regions > 0 && !region) return fail(GS_ERR_INVALID, "n_regions > 0 needs the region map");
+    if (grad_region < -1 || grad_region > n_regions)
+        return fail(GS_ERR_INVALID, "grad_region %d not in -1..n_regions", grad_region);
+    if (grad_region >= 0 && !dL_da) return fail(GS_ERR_INVALID, "grad_region >= 0 needs dL_da");
+    const bool grad = grad_region >= 0;
+    if ((r = check_ws(workspace, workspace_bytes, hvsq_scratch_bytes(cams_host, n_views, grad)))) return r;
+    if ((r = check_device(ctx))) return r;
+    hipError_t e = launch_hvsq(cams_host, cams_dev, n_views, img_a, img_r, radius, region, n_regions, sums, counts,
+                               terms, grad ? grad_region : -1, grad ? dL_da : nullptr, workspace, (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(e, "gs_hvsq");
+    return ok();
+}
+
 int gs_set_tuning(gs_ctx *ctx, const char *name, int64_t value)
 {
     int r;

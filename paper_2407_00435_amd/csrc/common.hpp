@@ -23,6 +23,20 @@ struct ViewInfo {
 
 __device__ __forceinline__ int div_up(int a, int b) { return (a + b - 1) / b; }
 
+// Eccentricity of pixel (x, y) in degrees (Section 4.1): the angle between
+// the pinhole rays through the pixel and through the gaze pixel.
+__device__ __forceinline__ float pixel_ecc_deg(const gs_camera &c, float gaze_x, float gaze_y, int x, int y)
+{
+    const float ifx = 1.0f / c.fx, ify = 1.0f / c.fy;
+    const float rx = ((float)x - c.cx) * ifx, ry = ((float)y - c.cy) * ify;
+    const float gx = (gaze_x - c.cx) * ifx, gy = (gaze_y - c.cy) * ify;
+    // angle between (rx, ry, 1) and (gx, gy, 1)
+    const float cx_ = ry - gy, cy_ = gx - rx, cz_ = rx * gy - ry * gx;
+    const float cn = sqrtf(cx_ * cx_ + cy_ * cy_ + cz_ * cz_);
+    const float dt = rx * gx + ry * gy + 1.0f;
+    return atan2f(cn, dt) * 57.29577951308232f;
+}
+
 // Linear walk over the (few) views; every lane of a block does the same walk.
 __device__ __forceinline__ ViewInfo view_of_tile(const gs_camera *__restrict__ cams, int V, int T,
                                                  int64_t gtile)

@@ -165,5 +165,18 @@ hipError_t launch_raster_fov(const gs_splat *splats, const float *lvl_rgba, int 
                              float *image, uint64_t *stats, float *final_T2, uint32_t *n_contrib2,
                              const RasterQueueArgs *qa, hipStream_t st);
 
+// HVSQ (hvsq.hip)
+constexpr int GS_HVSQ_MAX_REGIONS = 8;
+struct FoveaGazes {
+    float x[8], y[8];
+};
+int64_t hvsq_padded_pixels(const gs_camera *cams_host, int V);
+size_t hvsq_scratch_bytes(const gs_camera *cams_host, int V, bool grad);
+hipError_t launch_hvsq_radius(const gs_camera *cams_host, const gs_camera *cams_dev, const gs_fovea *fov_host, int V,
+                              float rho, int32_t *radius, hipStream_t st);
+hipError_t launch_hvsq(const gs_camera *cams_host, const gs_camera *cams_dev, int V, const float *img_a,
+                       const float *img_r, const int32_t *radius, const uint8_t *region, int R, double *sums,
+                       double *counts, double *terms, int grad_region, float *dL_da, void *ws, hipStream_t st);
+
 // utilities
 hipError_t launch_fill_u32(uint32_t *p, uint32_t value, uint64_t count, hipStream_t st);

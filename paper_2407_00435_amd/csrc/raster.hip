@@ -1325,14 +1325,7 @@ struct FovArgs {
 __device__ __forceinline__ void fovea_level(const gs_camera &c, const gs_fovea &f, int L, int x, int y, int &lo,
                                             float &w)
 {
-    const float ifx = 1.0f / c.fx, ify = 1.0f / c.fy;
-    const float rx = ((float)x - c.cx) * ifx, ry = ((float)y - c.cy) * ify;
-    const float gx = (f.gaze_x - c.cx) * ifx, gy = (f.gaze_y - c.cy) * ify;
-    // angle between (rx, ry, 1) and (gx, gy, 1)
-    const float cx_ = ry - gy, cy_ = gx - rx, cz_ = rx * gy - ry * gx;
-    const float cn = sqrtf(cx_ * cx_ + cy_ * cy_ + cz_ * cz_);
-    const float dt = rx * gx + ry * gy + 1.0f;
-    const float ecc = atan2f(cn, dt) * 57.29577951308232f;
+    const float ecc = pixel_ecc_deg(c, f.gaze_x, f.gaze_y, x, y);
     lo = 1;
     w = 0.0f;
     const float hb = 0.5f * f.band_deg;
