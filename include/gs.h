@@ -427,6 +427,12 @@ int gs_graph_destroy(gs_graph *graph);
  *                   (chunks whose pixels reach the stop threshold are
  *                   composited again from the running state, so the result
  *                   is the sequential one up to float reassociation).
+ *   "raster_merge": 0 (default) or beta >= 1: with the queue off and a
+ *                   workspace, consecutive tiles are merged while their keys
+ *                   total at most beta (a tile with more stands alone; the
+ *                   Tile Merging of Section 5.2), and the workgroups of a
+ *                   persistent forward compositor take merged tiles whole;
+ *                   results are those of one workgroup per tile.
  *   "coarse_packed": 1 (default): coarse (super-tile, entry) pairs carry
  *                   their tile rectangle in the sort key above the
  *                   super-tile id when the ids fit in 17 bits; 0: always in

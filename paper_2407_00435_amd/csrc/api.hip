@@ -174,8 +174,18 @@ size_t queue_fixed_bytes(int64_t tiles) { return 256 + 8 * (size_t)tiles + 4 * 2
 // most `cap` keys (0 when the queue is switched off).
 size_t raster_queue_bytes(const Tuning &tn, int64_t tiles, int T, uint64_t cap)
 {
-    if (!tn.raster_queue) return 0;
+    if (!tn.raster_queue) return tn.raster_merge ? 4 * merge_scratch_words(tiles) + 256 : 0;
     return queue_fixed_bytes(tiles) + raster_queue_heavy_cap(tiles, T, cap, tn.raster_beta) * queue_task_bytes(tn, T);
+}
+
+// Tile-merging scratch at [base, base + bytes) (false when merging is off,
+// the queue is on, or the space is too small).
+bool carve_merge(const Tuning &tn, char *base, size_t bytes, int64_t tiles, MergeArgs &ma)
+{
+    if (tn.raster_queue || !tn.raster_merge || !base || bytes < 4 * merge_scratch_words(tiles)) return false;
+    ma.scratch = reinterpret_cast<uint32_t *>(base);
+    ma.beta = tn.raster_merge;
+    return true;
 }
 
 // Lays the queue out in [base, base + bytes); the heavy-task capacity is what
@@ -230,6 +240,12 @@ bool carve_queue_ws(const Tuning &tn, void *ws, size_t bytes, int64_t tiles, int
 {
     if (!ws || bytes <= WS_HEADER) return false;
     return carve_queue(tn, (char *)ws + WS_HEADER, bytes - WS_HEADER, tiles, T, q);
+}
+
+bool carve_merge_ws(const Tuning &tn, void *ws, size_t bytes, int64_t tiles, MergeArgs &ma)
+{
+    if (!ws || bytes <= WS_HEADER) return false;
+    return carve_merge(tn, (char *)ws + WS_HEADER, bytes - WS_HEADER, tiles, ma);
 }
 
 int check_ws(const void *ws, size_t have, size_t need)
@@ -482,11 +498,13 @@ int gs_rasterize_fwd(gs_ctx *ctx, const gs_splat *splats, int32_t n, const gs_ca
     if (workspace && !aligned(workspace, 256)) return fail(GS_ERR_INVALID, "workspace must be 256-byte aligned");
     RasterQueueArgs q;
     const bool queued = carve_queue_ws(ctx->tn, workspace, workspace_bytes, tiles, tile_size, q);
+    MergeArgs ma;
+    const bool merged = carve_merge_ws(ctx->tn, workspace, workspace_bytes, tiles, ma);
     const float zero[3] = {0.f, 0.f, 0.f};
     if ((r = check_device(ctx))) return r;
     hipError_t e = launch_raster_fwd(splats, n, cams_dev, n_views, tile_size, tiles, vals, tile_ranges,
                                      bg ? bg : zero, image, final_T, n_contrib, dominated_px, stats,
-                                     queued ? &q : nullptr, (hipStream_t)stream);
+                                     queued ? &q : nullptr, (hipStream_t)stream, merged ? &ma : nullptr);
     if (e != hipSuccess) return hip_fail(e, "gs_rasterize_fwd");
     return ok();
 }
@@ -592,6 +610,8 @@ int gs_rasterize_foveated(gs_ctx *ctx, const gs_splat *splats, const float *lvl_
     if (workspace && !aligned(workspace, 256)) return fail(GS_ERR_INVALID, "workspace must be 256-byte aligned");
     RasterQueueArgs q;
     const bool queued = carve_queue_ws(ctx->tn, workspace, workspace_bytes, tiles, tile_size, q);
+    MergeArgs ma;
+    const bool merged = carve_merge_ws(ctx->tn, workspace, workspace_bytes, tiles, ma);
     const float zero[3] = {0.f, 0.f, 0.f};
     if ((final_T2 != nullptr) != (n_contrib2 != nullptr))
         return fail(GS_ERR_INVALID, "final_T2 and n_contrib2 go together");
@@ -600,7 +620,8 @@ int gs_rasterize_foveated(gs_ctx *ctx, const gs_splat *splats, const float *lvl_
     if ((r = check_device(ctx))) return r;
     hipError_t e = launch_raster_fov(splats, lvl_rgba, n, qbound, n_levels, cams_dev, n_eyes, tile_size,
                                      tiles, vals, tile_ranges, pix_level, pix_weight, bg ? bg : zero,
-                                     image, stats, final_T2, n_contrib2, queued ? &q : nullptr, (hipStream_t)stream);
+                                     image, stats, final_T2, n_contrib2, queued ? &q : nullptr, (hipStream_t)stream,
+                                     merged ? &ma : nullptr);
     if (e != hipSuccess) return hip_fail(e, "gs_rasterize_foveated");
     return ok();
 }
@@ -709,9 +730,11 @@ int gs_render_foveated(gs_ctx *ctx, const gs_scene *scene, const gs_camera *cams
     RasterQueueArgs q;
     const bool queued = carve_queue(ctx->tn, (char *)workspace + scratch_off, workspace_bytes - scratch_off,
                                     tiles, tile_size, q);
+    MergeArgs ma;
+    const bool merged = carve_merge(ctx->tn, (char *)workspace + scratch_off, workspace_bytes - scratch_off, tiles, ma);
     e = launch_raster_fov(rb.splats, rb.lvl, scene->n, scene->qbound, L, cams_dev, n_eyes, tile_size,
                           tiles, rb.vals, rb.ranges, rb.pix_level, rb.pix_weight, bg ? bg : zero, image,
-                          nullptr, nullptr, nullptr, queued ? &q : nullptr, st);
+                          nullptr, nullptr, nullptr, queued ? &q : nullptr, st, merged ? &ma : nullptr);
     if (e != hipSuccess) return hip_fail(e, "gs_render_foveated (compositing)");
     return ok();
 }
@@ -936,6 +959,11 @@ int gs_set_tuning(gs_ctx *ctx, const char *name, int64_t value)
         tn.raster_beta = (uint32_t)value;
         return ok();
     }
+    if (k == "raster_merge") {
+        if (value < 0 || value > (1ll << 31)) return fail(GS_ERR_INVALID, "raster_merge must be in 0..2^31");
+        tn.raster_merge = (uint32_t)value;
+        return ok();
+    }
     if (k == "coarse_packed") {
         if (value != 0 && value != 1) return fail(GS_ERR_INVALID, "coarse_packed must be 0 or 1");
         tn.coarse_packed = value != 0;
@@ -960,6 +988,7 @@ int gs_get_tuning(gs_ctx *ctx, const char *name, int64_t *value)
     else if (k == "raster_grab") *value = tn.raster_grab;
     else if (k == "raster_heavy") *value = tn.raster_heavy;
     else if (k == "raster_split") *value = tn.raster_beta;
+    else if (k == "raster_merge") *value = tn.raster_merge;
     else if (k == "coarse_packed") *value = tn.coarse_packed ? 1 : 0;
     else if (k == "radix_part") *value = tn.radix_part;
     else return fail(GS_ERR_INVALID, "unknown tuning knob '%s'", name);

@@ -38,6 +38,7 @@ struct Tuning {
     uint32_t raster_beta = 0;    // heavy-tile split length (0: no split)
     uint32_t raster_heavy = 0;   // without split: runs longer than this go first
     uint32_t raster_grab = 1;    // tasks per pop
+    uint32_t raster_merge = 0;   // tile merging threshold beta (0: one workgroup per tile)
 };
 
 // radix sort of (u32 key, u32 value) pairs, LSD over bits [0, bits)
@@ -141,10 +142,19 @@ struct RasterQueueArgs {
     uint32_t grab;       // consecutive tasks a workgroup takes per pop
 };
 uint64_t raster_queue_heavy_cap(int64_t n_tiles, int T, uint64_t cap, uint32_t beta);
+// Tile merging (carved from a workspace): groups of consecutive tiles whose
+// intersections total at most beta (a heavier tile alone), popped whole by
+// the workgroups of a persistent compositor.
+struct MergeArgs {
+    uint32_t *scratch;  // merge_scratch_words(n_tiles) words
+    uint32_t beta;
+};
+inline size_t merge_scratch_words(int64_t n_tiles) { return 16 + 8 * (size_t)(n_tiles + 1); }
 hipError_t launch_raster_fwd(const gs_splat *splats, int n, const gs_camera *cams_dev, int V, int T,
                              int64_t n_tiles, const uint32_t *vals, const uint32_t *ranges,
                              const float bg[3], float *image, float *final_T, uint32_t *n_contrib,
-                             uint32_t *dominated, uint64_t *stats, const RasterQueueArgs *qa, hipStream_t st);
+                             uint32_t *dominated, uint64_t *stats, const RasterQueueArgs *qa, hipStream_t st,
+                             const MergeArgs *ma = nullptr);
 hipError_t launch_raster_bwd(const gs_splat *splats, int n, const gs_camera *cams_dev, int V, int T,
                              int64_t n_tiles, const uint32_t *vals, const uint32_t *ranges,
                              const float bg[3], const float *final_T, const uint32_t *n_contrib,
@@ -163,7 +173,7 @@ hipError_t launch_raster_fov(const gs_splat *splats, const float *lvl_rgba, int 
                              int T, int64_t n_tiles, const uint32_t *vals, const uint32_t *ranges,
                              const uint8_t *pix_level, const float *pix_weight, const float bg[3],
                              float *image, uint64_t *stats, float *final_T2, uint32_t *n_contrib2,
-                             const RasterQueueArgs *qa, hipStream_t st);
+                             const RasterQueueArgs *qa, hipStream_t st, const MergeArgs *ma = nullptr);
 
 // HVSQ (hvsq.hip)
 constexpr int GS_HVSQ_MAX_REGIONS = 8;

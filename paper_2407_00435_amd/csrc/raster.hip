@@ -832,6 +832,164 @@ k_raster_fov_q(const gs_splat *__restrict__ splats, const float4 *__restrict__ l
 }
 
 // ---------------------------------------------------------------------------
+// Tile merging (the Tile Merge Unit of Section 5.2, on the GPU): consecutive
+// tiles are merged while their intersections (keys) total at most beta; a
+// tile with more stands alone.  Greedy from the first tile: the group that
+// starts at tile i ends before next(i), the last j with S(j) - S(i) <= beta
+// (S the exclusive prefix of the tile loads; at least i + 1).  The group
+// starts are the chain 0, next(0), next(next(0)), ...: found by pointer
+// doubling (round r marks the chain nodes 2^r steps beyond the marked ones),
+// then compacted in order.  One workgroup does it all; a persistent
+// compositor's workgroups then pop whole groups and composite their tiles
+// one after another (per pixel exactly as one workgroup per tile).
+struct MergeView {
+    uint32_t *counts;  // [16]: groups, pop head
+    uint32_t *S, *nxt, *J0, *J1, *mark;  // [n_tiles + 1]
+    uint2 *groups;     // [n_tiles + 1] (first tile, end tile)
+};
+
+__host__ __device__ __forceinline__ MergeView merge_view(uint32_t *base, int64_t n_tiles)
+{
+    MergeView m;
+    const int64_t n1 = n_tiles + 1;
+    m.counts = base;
+    m.S = base + 16;
+    m.nxt = m.S + n1;
+    m.J0 = m.nxt + n1;
+    m.J1 = m.J0 + n1;
+    m.mark = m.J1 + n1;
+    m.groups = reinterpret_cast<uint2 *>(m.mark + n1 + ((n1 & 1) ? 1 : 0));
+    return m;
+}
+
+constexpr int MERGE_THREADS = 1024;
+
+// Exclusive scan of f(i), i < n, into out[0..n] (out[n] = total), by the
+// whole workgroup: contiguous segments per thread, segment totals in LDS.
+template <class F>
+__device__ __forceinline__ void block_exclusive_scan(int64_t n, F f, uint32_t *__restrict__ out, uint32_t *s_tot)
+{
+    const int t = threadIdx.x;
+    const int64_t seg = (n + MERGE_THREADS - 1) / MERGE_THREADS;
+    const int64_t b = t * seg, e = min(b + seg, n);
+    uint32_t acc = 0;
+    for (int64_t i = b; i < e; ++i) acc += f(i);
+    s_tot[t] = acc;
+    __syncthreads();
+    for (int off = 1; off < MERGE_THREADS; off <<= 1) {
+        const uint32_t add = t >= off ? s_tot[t - off] : 0u;
+        __syncthreads();
+        s_tot[t] += add;
+        __syncthreads();
+    }
+    uint32_t run = t ? s_tot[t - 1] : 0u;
+    for (int64_t i = b; i < e; ++i) {
+        out[i] = run;
+        run += f(i);
+    }
+    if (t == MERGE_THREADS - 1) out[n] = s_tot[t];
+    __syncthreads();
+}
+
+__global__ void __launch_bounds__(MERGE_THREADS)
+k_merge_groups(const uint32_t *__restrict__ ranges, int64_t n_tiles, uint32_t beta, uint32_t *scratch)
+{
+    __shared__ uint32_t s_tot[MERGE_THREADS];
+    const MergeView m = merge_view(scratch, n_tiles);
+    const int64_t T = n_tiles;
+    block_exclusive_scan(T, [&](int64_t i) { return ranges[2 * i + 1] - ranges[2 * i]; }, m.S, s_tot);
+    for (int64_t i = threadIdx.x; i < T; i += MERGE_THREADS) {
+        const uint64_t target = (uint64_t)m.S[i] + beta;
+        int64_t lo = i + 1, hi = T;
+        if ((uint64_t)m.S[lo] <= target) {
+            // last j in [lo, T] with S(j) <= target
+            while (lo < hi) {
+                const int64_t mid = (lo + hi + 1) >> 1;
+                if ((uint64_t)m.S[mid] <= target) lo = mid;
+                else hi = mid - 1;
+            }
+        }
+        m.nxt[i] = (uint32_t)lo;
+        m.J0[i] = (uint32_t)lo;
+        m.mark[i] = i == 0 ? 1u : 0u;
+    }
+    __syncthreads();
+    uint32_t *J = m.J0, *Jn = m.J1;
+    for (int64_t span = 1; span <= T; span <<= 1) {
+        for (int64_t i = threadIdx.x; i < T; i += MERGE_THREADS)
+            if (m.mark[i] && J[i] < (uint32_t)T) m.mark[J[i]] = 1u;
+        __syncthreads();
+        for (int64_t i = threadIdx.x; i < T; i += MERGE_THREADS) Jn[i] = J[i] < (uint32_t)T ? J[J[i]] : (uint32_t)T;
+        __syncthreads();
+        uint32_t *tmp = J;
+        J = Jn;
+        Jn = tmp;
+    }
+    // group starts in order: the exclusive scan of the marks reuses J0 / J1
+    block_exclusive_scan(T, [&](int64_t i) { return m.mark[i]; }, Jn, s_tot);
+    for (int64_t i = threadIdx.x; i < T; i += MERGE_THREADS)
+        if (m.mark[i]) m.groups[Jn[i]] = make_uint2((uint32_t)i, m.nxt[i]);
+    if (threadIdx.x == 0) {
+        m.counts[0] = Jn[T];
+        m.counts[1] = 0u;
+    }
+}
+
+template <int T, bool DOM>
+__global__ void __launch_bounds__(T *T)
+k_raster_fwd_m(const gs_splat *__restrict__ splats, int n, const gs_camera *__restrict__ cams, int V,
+               const uint32_t *__restrict__ vals, const uint32_t *__restrict__ ranges, float bg0, float bg1,
+               float bg2, float *__restrict__ image, float *__restrict__ final_T,
+               uint32_t *__restrict__ n_contrib, uint32_t *__restrict__ dominated, uint32_t *merge, int64_t n_tiles)
+{
+    constexpr int WAVES = T * T / 64;
+    __shared__ FwdRec s_rec[WAVES][64];
+    __shared__ uint32_t s_slot;
+    const MergeView m = merge_view(merge, n_tiles);
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const uint32_t ng = m.counts[0];
+    uint32_t g = pop_task(m.counts + 1, &s_slot, 1);
+    while (g < ng) {
+        const uint2 gr = m.groups[g];
+        for (uint32_t t = gr.x; t < gr.y; ++t) {
+            const WaveCtx w = wave_ctx<T>(cams, V, t, wave, lane, ranges);
+            FwdState s = fwd_init(w.inside);
+            fwd_walk<DOM, false>(splats + (int64_t)w.vi.v * n, vals, w, w.start, w.end, s_rec[wave], s, nullptr);
+            fwd_finish<DOM>(w, s, n, bg0, bg1, bg2, image, final_T, n_contrib, dominated);
+        }
+        g = pop_task(m.counts + 1, &s_slot, 1);
+    }
+}
+
+template <int T>
+__global__ void __launch_bounds__(T *T)
+k_raster_fov_m(const gs_splat *__restrict__ splats, const float4 *__restrict__ lvl, int n,
+               const uint8_t *__restrict__ qbound, int L, const gs_camera *__restrict__ cams, int V,
+               const uint32_t *__restrict__ vals, const uint32_t *__restrict__ ranges,
+               const uint8_t *__restrict__ pix_level, const float *__restrict__ pix_weight, float bg0, float bg1,
+               float bg2, float *__restrict__ image, uint32_t *merge, int64_t n_tiles)
+{
+    constexpr int WAVES = T * T / 64;
+    __shared__ FovRec s_rec[WAVES][64];
+    __shared__ uint32_t s_slot;
+    const MergeView m = merge_view(merge, n_tiles);
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const uint32_t ng = m.counts[0];
+    uint32_t g = pop_task(m.counts + 1, &s_slot, 1);
+    while (g < ng) {
+        const uint2 gr = m.groups[g];
+        for (uint32_t t = gr.x; t < gr.y; ++t) {
+            const WaveCtx w = wave_ctx<T>(cams, V, t, wave, lane, ranges);
+            const FovPix f = fov_pix(w, pix_level, pix_weight);
+            FovState s = fov_init(w.inside, f.two);
+            fov_walk<false>(splats, lvl, n, qbound, L, vals, w, f, w.start, w.end, s_rec[wave], s, nullptr);
+            fov_finish(w, f, s, bg0, bg1, bg2, image);
+        }
+        g = pop_task(m.counts + 1, &s_slot, 1);
+    }
+}
+
+// ---------------------------------------------------------------------------
 // Reverse of the forward compositing.  Per pixel, back to front from its last
 // blended splat: T_i = T_(i+1) / (1 - alpha_i) starting from final_T, and the
 // light behind i (including the background) is accumulated on the way, so
@@ -1438,12 +1596,40 @@ uint64_t raster_queue_heavy_cap(int64_t n_tiles, int T, uint64_t cap, uint32_t b
 hipError_t launch_raster_fwd(const gs_splat *splats, int n, const gs_camera *cams_dev, int V, int T,
                              int64_t n_tiles, const uint32_t *vals, const uint32_t *ranges,
                              const float bg[3], float *image, float *final_T, uint32_t *n_contrib,
-                             uint32_t *dominated, uint64_t *stats, const RasterQueueArgs *qa, hipStream_t st)
+                             uint32_t *dominated, uint64_t *stats, const RasterQueueArgs *qa, hipStream_t st,
+                             const MergeArgs *ma)
 {
     if (n_tiles == 0) return hipSuccess;
     hipError_t e;
     if (dominated && (e = launch_fill_u32(dominated, 0u, (uint64_t)V * n, st)) != hipSuccess) return e;
     unsigned long long *sp = reinterpret_cast<unsigned long long *>(stats);
+    if (ma && !qa && !stats) {
+        hipLaunchKernelGGL(k_merge_groups, dim3(1), dim3(MERGE_THREADS), 0, st, ranges, n_tiles, ma->beta,
+                           ma->scratch);
+#define GS_RM(TS, DM)                                                                                  \
+    {                                                                                                  \
+        static unsigned blocks = 0;                                                                    \
+        if (!blocks) blocks = persistent_blocks(k_raster_fwd_m<TS, DM>, TS * TS);                     \
+        hipLaunchKernelGGL((k_raster_fwd_m<TS, DM>), dim3(blocks), dim3(TS * TS), 0, st, splats, n, cams_dev, \
+                           V, vals, ranges, bg[0], bg[1], bg[2], image, final_T, n_contrib, dominated,  \
+                           ma->scratch, n_tiles);                                                      \
+    }
+        if (dominated) {
+            switch (T) {
+            case 8: GS_RM(8, true); break;
+            case 16: GS_RM(16, true); break;
+            default: GS_RM(32, true); break;
+            }
+        } else {
+            switch (T) {
+            case 8: GS_RM(8, false); break;
+            case 16: GS_RM(16, false); break;
+            default: GS_RM(32, false); break;
+            }
+        }
+#undef GS_RM
+        return hipGetLastError();
+    }
     if (qa && !stats) {
         RasterQueue q;
         if ((e = build_queue(ranges, n_tiles, T, *qa, q, st)) != hipSuccess) return e;
@@ -1566,7 +1752,7 @@ hipError_t launch_raster_fov(const gs_splat *splats, const float *lvl_rgba, int 
                              int T, int64_t n_tiles, const uint32_t *vals, const uint32_t *ranges,
                              const uint8_t *pix_level, const float *pix_weight, const float bg[3],
                              float *image, uint64_t *stats, float *final_T2, uint32_t *n_contrib2,
-                             const RasterQueueArgs *qa, hipStream_t st)
+                             const RasterQueueArgs *qa, hipStream_t st, const MergeArgs *ma)
 {
     if (n_tiles == 0) return hipSuccess;
     const float4 *lv = reinterpret_cast<const float4 *>(lvl_rgba);
@@ -1585,6 +1771,25 @@ hipError_t launch_raster_fov(const gs_splat *splats, const float *lvl_rgba, int 
         default: GS_RK(32); break;
         }
 #undef GS_RK
+        return hipGetLastError();
+    }
+    if (ma && !qa && !stats) {
+        hipLaunchKernelGGL(k_merge_groups, dim3(1), dim3(MERGE_THREADS), 0, st, ranges, n_tiles, ma->beta,
+                           ma->scratch);
+#define GS_RM(TS)                                                                                      \
+    {                                                                                                  \
+        static unsigned blocks = 0;                                                                    \
+        if (!blocks) blocks = persistent_blocks(k_raster_fov_m<TS>, TS * TS);                         \
+        hipLaunchKernelGGL((k_raster_fov_m<TS>), dim3(blocks), dim3(TS * TS), 0, st, splats, lv, n, qbound, \
+                           n_levels, cams_dev, V, vals, ranges, pix_level, pix_weight, bg[0], bg[1],    \
+                           bg[2], image, ma->scratch, n_tiles);                                        \
+    }
+        switch (T) {
+        case 8: GS_RM(8); break;
+        case 16: GS_RM(16); break;
+        default: GS_RM(32); break;
+        }
+#undef GS_RM
         return hipGetLastError();
     }
     if (qa && !stats) {
