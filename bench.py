@@ -287,6 +287,99 @@ def fwd_bwd_rate(g, wl, steps, warmup, tile=16):
     return out
 
 
+TILE_SCHEDULES = (
+    ("per_tile", {}),
+    ("merge_256", {"raster_merge": 256}),
+    ("merge_1024", {"raster_merge": 1024}),
+    ("merge_4096", {"raster_merge": 4096}),
+    ("merge_16384", {"raster_merge": 16384}),
+    ("queue", {"raster_queue": 1}),
+    ("queue_split_4096", {"raster_queue": 1, "raster_split": 4096}),
+)
+
+
+def greedy_group_count(ranges, beta):
+    """Merged tiles of the greedy rule (consecutive tiles while their keys
+    total at most beta) over a [tiles, 2] range table."""
+    import numpy as np
+    loads = (ranges[:, 1] - ranges[:, 0]).astype(np.int64)
+    groups, tot = 0, None
+    for x in loads:
+        if tot is None or tot + x > beta:
+            groups += 1
+            tot = int(x)
+        else:
+            tot += int(x)
+    return groups
+
+
+def tile_schedules(g, fr, wl2, tile=16, reps=20):
+    """Compositing time of the foveated stereo frame and of the 1280x720
+    500k-Gaussian plain frame under each tile schedule: one workgroup per
+    tile, light tiles merged up to beta keys, the persistent work queue, and
+    the queue with runs longer than 4096 keys split.  Events around the
+    compositing call, on the stream it runs on (median over calls); each
+    image is compared with the per-tile one (merged and queued: bit for bit;
+    split: reassociated)."""
+    import torch
+    B = g.binding
+    S2, C2 = g.SceneTensors(wl2.scene), g.Cameras(wl2.cams)
+    splats2 = g.gs_project(S2, C2, tile)
+    bs2 = g.gs_bin_sort(splats2, S2.n, C2, tile, check=True)
+    saved = (fr.ws_t, fr.ws, fr.wsn)
+    cases = {"foveated_stereo_1080p_1.5M": {}, "plain_720p_500k": {}}
+    ranges = {"foveated_stereo_1080p_1.5M": fr.ranges.cpu().numpy(),
+              "plain_720p_500k": bs2["ranges"].cpu().numpy()}
+    refs = {}
+
+    def ev_ms(fn):
+        # per-call event pairs, median: a host stall (allocator, collector)
+        # inside the window would otherwise count as compositing time
+        import statistics
+        for _ in range(3):
+            fn()
+        ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(reps)]
+        torch.cuda.synchronize()
+        for e0, e1 in ev:
+            e0.record()
+            fn()
+            e1.record()
+        torch.cuda.synchronize()
+        return statistics.median(e0.elapsed_time(e1) for e0, e1 in ev)
+
+    try:
+        for name, knobs in TILE_SCHEDULES:
+            for k, v in knobs.items():
+                g.gs_set_tuning(k, v)
+            try:
+                fr.ws_t, fr.ws, fr.wsn = B._ws(g.gs_workspace_bytes(fr.C, fr.n, tile, fr.cap))
+                ws2 = B._ws(g.gs_workspace_bytes(C2, S2.n, tile, bs2["capacity"]))
+                st = {}
+
+                def plain():
+                    st["out"] = g.gs_rasterize_fwd(splats2, S2.n, C2, tile, bs2["vals"], bs2["ranges"],
+                                                   workspace=ws2)
+
+                for case, fn, img in (("foveated_stereo_1080p_1.5M", fr.raster, lambda: fr.image),
+                                      ("plain_720p_500k", plain, lambda: st["out"]["image"])):
+                    ms = ev_ms(fn)
+                    im = img().clone()
+                    if name == "per_tile":
+                        refs[case] = im
+                    r = {"ms": ms, "bit_equal": bool(torch.equal(im, refs[case])),
+                         "max_abs_diff": float((im - refs[case]).abs().max().item())}
+                    if "raster_merge" in knobs:
+                        r["merged_tiles"] = greedy_group_count(ranges[case], knobs["raster_merge"])
+                        r["tiles"] = int(len(ranges[case]))
+                    cases[case][name] = r
+            finally:
+                for k in knobs:
+                    g.gs_set_tuning(k, 0)
+    finally:
+        fr.ws_t, fr.ws, fr.wsn = saved
+    return cases
+
+
 def batched_vs_plain(g, steps=3, log=None, fixed=None, plain_too=True):
     """3M Gaussians, 32 orbit views at mixed resolutions (forward + L1 loss +
     backward) plus the foveated forward of two eyes, as one step.  Batched:
@@ -573,9 +666,9 @@ def main():
     ap.add_argument("--radix-part", type=int, default=16384)
     ap.add_argument("--copy-probe", action="store_true",
                     help="only run a plain 1 GiB device copy (memory-counter calibration)")
-    ap.add_argument("--only", choices=("fwdbwd", "plain"),
-                    help="only the 1280x720 1M-Gaussian forward+backward, or only the 1280x720 500k plain "
-                         "forward (for profiling one kernel)")
+    ap.add_argument("--only", choices=("fwdbwd", "plain", "schedules"),
+                    help="only the 1280x720 1M-Gaussian forward+backward, only the 1280x720 500k plain "
+                         "forward (for profiling one kernel), or only the tile-schedule comparison")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py runs on exactly one GPU: the renderer has no multi-GPU path "
@@ -594,6 +687,12 @@ def main():
         return
     if args.only == "plain":
         print(json.dumps(plain_fwd_rate(g, scenegen.config2(), args.steps, args.warmup)), flush=True)
+        return
+    if args.only == "schedules":
+        torch.cuda.set_device(0)
+        fr = Foveated(g, scenegen.config3(), args.tile)
+        time_foveated(fr, 3, 2)
+        print(json.dumps(tile_schedules(g, fr, scenegen.config2(), args.tile)), flush=True)
         return
     if args.batched_only:
         r = batched_vs_plain(g, args.steps, log, fixed=dict(tile=args.tile, batch_views=args.batch_views,
@@ -655,6 +754,8 @@ def main():
         line["plain_fwd_128_4k"] = plain_fwd_rate(g, scenegen.config1(), 50, 5)
         log("plain forward, 500k Gaussians, 1280x720 ...")
         line["plain_fwd_720p_500k"] = plain_fwd_rate(g, scenegen.config2(), 20, 3)
+        log("tile schedules: per tile, merged, queue, split ...")
+        line["tile_schedules"] = tile_schedules(g, fr, scenegen.config2(), args.tile)
         log("forward+backward, 1M Gaussians, 1280x720 ...")
         line["fwd_bwd_720p_1M"] = fwd_bwd_rate(g, scenegen.config4(), 10, 3)
         log("HVSQ of the stereo frame ...")

@@ -892,7 +892,7 @@ __device__ __forceinline__ void block_exclusive_scan(int64_t n, F f, uint32_t *_
 }
 
 __global__ void __launch_bounds__(MERGE_THREADS)
-k_merge_groups(const uint32_t *__restrict__ ranges, int64_t n_tiles, uint32_t beta, uint32_t *scratch)
+k_merge_groups_global(const uint32_t *__restrict__ ranges, int64_t n_tiles, uint32_t beta, uint32_t *scratch)
 {
     __shared__ uint32_t s_tot[MERGE_THREADS];
     const MergeView m = merge_view(scratch, n_tiles);
@@ -931,6 +931,136 @@ k_merge_groups(const uint32_t *__restrict__ ranges, int64_t n_tiles, uint32_t be
         if (m.mark[i]) m.groups[Jn[i]] = make_uint2((uint32_t)i, m.nxt[i]);
     if (threadIdx.x == 0) {
         m.counts[0] = Jn[T];
+        m.counts[1] = 0u;
+    }
+}
+
+// Inclusive prefix sum over the 64 lanes of a wave.
+__device__ __forceinline__ uint32_t wave_incl_scan(uint32_t v)
+{
+    const int lane = threadIdx.x & 63;
+    for (int off = 1; off < 64; off <<= 1) {
+        const uint32_t a = __shfl_up(v, off);
+        if (lane >= off) v += a;
+    }
+    return v;
+}
+
+// Exclusive prefix, over the workgroup, of x (one value per thread, in
+// thread order) after `carry`; carry becomes carry + the workgroup's total.
+__device__ __forceinline__ uint32_t block_scan_step(uint32_t x, uint32_t &carry, uint32_t *s_tot)
+{
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const uint32_t incl = wave_incl_scan(x);
+    if (lane == 63) s_tot[wave] = incl;
+    __syncthreads();
+    uint32_t off = carry, all = carry;
+    for (int w = 0; w < MERGE_THREADS / 64; ++w) {
+        const uint32_t y = s_tot[w];
+        off += w < wave ? y : 0u;
+        all += y;
+    }
+    carry = all;
+    __syncthreads();
+    return off + incl - x;
+}
+
+// The grouping of k_merge_groups_global with every array in LDS (up to
+// MERGE_LDS_TILES tiles): the loads are staged in LDS and scanned in place
+// a workgroup-width chunk at a time, each tile's reach is found by a
+// galloping search of the prefix, and the doubling rounds stop once a round
+// marks no new group start.  The jump arrays are 16-bit; the second reuses
+// the prefix's space, and so do the group starts at the end.
+constexpr int MERGE_LDS_TILES = 16384;
+
+__global__ void __launch_bounds__(MERGE_THREADS)
+k_merge_groups(const uint32_t *__restrict__ ranges, int T, uint32_t beta, uint32_t *scratch)
+{
+    __shared__ uint32_t s_S[MERGE_LDS_TILES + 2];
+    __shared__ uint16_t s_J[MERGE_LDS_TILES];
+    __shared__ uint8_t s_mark[MERGE_LDS_TILES];
+    __shared__ uint32_t s_tot[MERGE_THREADS / 64];
+    const MergeView m = merge_view(scratch, T);
+    const int t = threadIdx.x;
+    const uint2 *rg = reinterpret_cast<const uint2 *>(ranges);
+#pragma unroll 4
+    for (int i = t; i < T; i += MERGE_THREADS) {
+        const uint2 r = rg[i];
+        s_S[i] = r.y - r.x;
+    }
+    __syncthreads();
+    uint32_t carry = 0;
+    for (int base = 0; base < T; base += MERGE_THREADS) {
+        const int i = base + t;
+        const uint32_t x = i < T ? s_S[i] : 0u;
+        const uint32_t ex = block_scan_step(x, carry, s_tot);
+        if (i < T) s_S[i] = ex;
+    }
+    if (t == 0) s_S[T] = carry;
+    __syncthreads();
+    // reach: the last j in [i + 1, T] with S(j) <= S(i) + beta
+    for (int i = t; i < T; i += MERGE_THREADS) {
+        const uint64_t target = (uint64_t)s_S[i] + beta;
+        int lo = i + 1;
+        if ((uint64_t)s_S[lo] <= target) {
+            int step = 1, hi;
+            for (;;) {
+                const int nx = lo + step;
+                if (nx > T || (uint64_t)s_S[nx] > target) {
+                    hi = min(nx, T + 1) - 1;
+                    break;
+                }
+                lo = nx;
+                step <<= 1;
+            }
+            while (lo < hi) {
+                const int mid = (lo + hi + 1) >> 1;
+                if ((uint64_t)s_S[mid] <= target) lo = mid;
+                else hi = mid - 1;
+            }
+        }
+        s_J[i] = (uint16_t)lo;
+        s_mark[i] = i == 0 ? 1u : 0u;
+    }
+    __syncthreads();
+    uint16_t *J = s_J, *Jn = reinterpret_cast<uint16_t *>(s_S);
+    for (int span = 1; span < T; span <<= 1) {
+        int fresh = 0;
+#pragma unroll 4
+        for (int i = t; i < T; i += MERGE_THREADS) {
+            const int j = J[i];
+            if (s_mark[i] && j < T && !s_mark[j]) {
+                s_mark[j] = 1u;
+                fresh = 1;
+            }
+        }
+        if (!__syncthreads_or(fresh)) break;
+#pragma unroll 4
+        for (int i = t; i < T; i += MERGE_THREADS) {
+            const int j = J[i];
+            Jn[i] = j < T ? J[j] : (uint16_t)T;
+        }
+        __syncthreads();
+        uint16_t *tmp = J;
+        J = Jn;
+        Jn = tmp;
+    }
+    // group starts in order; a group ends where the next one starts
+    uint16_t *start = s_J;
+    __syncthreads();
+    carry = 0;
+    for (int base = 0; base < T; base += MERGE_THREADS) {
+        const int i = base + t;
+        const uint32_t x = i < T ? s_mark[i] : 0u;
+        const uint32_t pos = block_scan_step(x, carry, s_tot);
+        if (x) start[pos] = (uint16_t)i;
+    }
+    const uint32_t ng = carry;
+    __syncthreads();
+    for (uint32_t g = t; g < ng; g += MERGE_THREADS)
+        m.groups[g] = make_uint2(start[g], g + 1 < ng ? (uint32_t)start[g + 1] : (uint32_t)T);
+    if (t == 0) {
+        m.counts[0] = ng;
         m.counts[1] = 0u;
     }
 }
@@ -1549,16 +1679,32 @@ k_fovea_prep(const gs_camera *__restrict__ cams, int V, int L, FovArgs fa, uint8
 
 namespace {
 
-// Persistent grid: resident workgroups of the kernel on every CU.
+// Persistent grid: as many workgroups per CU as its thread slots hold, on
+// every CU.  No workgroup of a persistent compositor waits on another, so
+// workgroups beyond what registers or LDS let reside only start late and find
+// the task list drained; asking for fewer (the occupancy query's answer is
+// conservative here) would leave slots idle for the whole launch.
 template <class K>
 unsigned persistent_blocks(K kernel, int threads)
 {
+    (void)kernel;
     int dev = 0, cus = 0, per_cu = 0;
-    if (hipGetDevice(&dev) != hipSuccess) return 1024;
-    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) cus = 256;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, threads, 0) != hipSuccess || per_cu < 1)
-        per_cu = 1;
-    return (unsigned)(cus * per_cu);
+    if (hipGetDevice(&dev) != hipSuccess) return 2048;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus < 1) cus = 256;
+    if (hipDeviceGetAttribute(&per_cu, hipDeviceAttributeMaxThreadsPerMultiProcessor, dev) != hipSuccess ||
+        per_cu < threads)
+        per_cu = 2048;
+    return (unsigned)(cus * std::max(1, per_cu / threads));
+}
+
+void launch_merge_groups(const uint32_t *ranges, int64_t n_tiles, const MergeArgs *ma, hipStream_t st)
+{
+    if (n_tiles <= MERGE_LDS_TILES)
+        hipLaunchKernelGGL(k_merge_groups, dim3(1), dim3(MERGE_THREADS), 0, st, ranges, (int)n_tiles, ma->beta,
+                           ma->scratch);
+    else
+        hipLaunchKernelGGL(k_merge_groups_global, dim3(1), dim3(MERGE_THREADS), 0, st, ranges, n_tiles, ma->beta,
+                           ma->scratch);
 }
 
 hipError_t build_queue(const uint32_t *ranges, int64_t n_tiles, int T, const RasterQueueArgs &qa, RasterQueue &q,
@@ -1604,8 +1750,7 @@ hipError_t launch_raster_fwd(const gs_splat *splats, int n, const gs_camera *cam
     if (dominated && (e = launch_fill_u32(dominated, 0u, (uint64_t)V * n, st)) != hipSuccess) return e;
     unsigned long long *sp = reinterpret_cast<unsigned long long *>(stats);
     if (ma && !qa && !stats) {
-        hipLaunchKernelGGL(k_merge_groups, dim3(1), dim3(MERGE_THREADS), 0, st, ranges, n_tiles, ma->beta,
-                           ma->scratch);
+        launch_merge_groups(ranges, n_tiles, ma, st);
 #define GS_RM(TS, DM)                                                                                  \
     {                                                                                                  \
         static unsigned blocks = 0;                                                                    \
@@ -1774,8 +1919,7 @@ hipError_t launch_raster_fov(const gs_splat *splats, const float *lvl_rgba, int 
         return hipGetLastError();
     }
     if (ma && !qa && !stats) {
-        hipLaunchKernelGGL(k_merge_groups, dim3(1), dim3(MERGE_THREADS), 0, st, ranges, n_tiles, ma->beta,
-                           ma->scratch);
+        launch_merge_groups(ranges, n_tiles, ma, st);
 #define GS_RM(TS)                                                                                      \
     {                                                                                                  \
         static unsigned blocks = 0;                                                                    \
