@@ -569,6 +569,40 @@ def pipelined_frames(g, wl, tile, frames=40, warmup=6):
             "mpix_s": frs[0].n_px / dt / 1e6, "frames_identical": same}
 
 
+def one_call_frames(g, fr, wl, tile, steps=20, warmup=5):
+    """The stereo frame through the one-call gs_render_foveated: joint (both
+    eyes per stage) and eye by eye on two streams (stream_views: eye 0's
+    compositing overlaps eye 1's binning), with one workspace sized for
+    each, median of timed windows; the two images are compared bit for
+    bit."""
+    import torch
+    B = g.binding
+    out = {}
+    imgs = {}
+    for name, on in (("joint", 0), ("eye_streamed", 1)):
+        g.gs_set_tuning("stream_views", on)
+        try:
+            state = {"ws": None}
+
+            def frame():
+                img, num, ws = g.gs_render_foveated(fr.S, fr.C, wl.foveae, tile, key_capacity=fr.cap,
+                                                    workspace=state["ws"])
+                state.update(ws=ws, img=img, num=num)
+
+            frame()
+            torch.cuda.synchronize()
+            st, need = g.context().poll_status(state["ws"])
+            dt, lo, hi = timed_windows(frame, steps, warmup)
+            imgs[name] = state["img"].clone()
+            out[name] = {"ms": dt * 1e3, "ms_range": [lo * 1e3, hi * 1e3], "mpix_s": fr.n_px / dt / 1e6,
+                         "keys": int(state["num"].item()), "capacity_ok": st == B.GS_OK}
+        finally:
+            g.gs_set_tuning("stream_views", 0)
+    out["bit_equal"] = bool(torch.equal(imgs["joint"], imgs["eye_streamed"]))
+    out["timing"] = f"median of 5 windows of {steps} frames"
+    return out
+
+
 def hbm_bandwidth(g, fr, stage_ms, reps=10):
     """Achieved HBM bandwidth of the projection and of the radix sort, against a
     plain device copy on the same GPU (the achievable reference) and the
@@ -666,9 +700,10 @@ def main():
     ap.add_argument("--radix-part", type=int, default=16384)
     ap.add_argument("--copy-probe", action="store_true",
                     help="only run a plain 1 GiB device copy (memory-counter calibration)")
-    ap.add_argument("--only", choices=("fwdbwd", "plain", "schedules"),
+    ap.add_argument("--only", choices=("fwdbwd", "plain", "schedules", "streamed"),
                     help="only the 1280x720 1M-Gaussian forward+backward, only the 1280x720 500k plain "
-                         "forward (for profiling one kernel), or only the tile-schedule comparison")
+                         "forward (for profiling one kernel), only the tile-schedule comparison, or only the one-call "
+                         "frame joint and eye by eye")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py runs on exactly one GPU: the renderer has no multi-GPU path "
@@ -687,6 +722,12 @@ def main():
         return
     if args.only == "plain":
         print(json.dumps(plain_fwd_rate(g, scenegen.config2(), args.steps, args.warmup)), flush=True)
+        return
+    if args.only == "streamed":
+        torch.cuda.set_device(0)
+        wl = scenegen.config3()
+        fr = Foveated(g, wl, args.tile)
+        print(json.dumps(one_call_frames(g, fr, wl, args.tile)), flush=True)
         return
     if args.only == "schedules":
         torch.cuda.set_device(0)
@@ -748,6 +789,8 @@ def main():
     if not args.no_extras:
         log("HBM bandwidth of projection and sort ...")
         line["hbm"] = hbm_bandwidth(g, fr, stage_ms)
+        log("one-call frame: joint and eye by eye on two streams ...")
+        line["one_call_frames"] = one_call_frames(g, fr, wl, args.tile)
         log("consecutive frames on two streams ...")
         line["pipelined_frames"] = pipelined_frames(g, wl, args.tile)
         log("plain forward, 4096 Gaussians, 128x128 ...")

@@ -433,6 +433,20 @@ int gs_graph_destroy(gs_graph *graph);
  *                   Tile Merging of Section 5.2), and the workgroups of a
  *                   persistent forward compositor take merged tiles whole;
  *                   results are those of one workgroup per tile.
+ *   "stream_views": 0 (default) or 1: gs_render_foveated with two or more
+ *                   eyes bins and composites eye by eye, the binning on the
+ *                   caller's stream and the compositing on a second stream
+ *                   of the context, so that eye e's compositing overlaps eye
+ *                   e + 1's binning (the incremental pipelining of Section
+ *                   5.2 at view granularity).  Each eye gets key_capacity /
+ *                   n_eyes keys; gs_poll_status then reports n_eyes times the
+ *                   largest per-eye requirement and *num_keys the total.
+ *                   Images are those of the joint call.  The second stream
+ *                   (default priority) and its two events are made on the
+ *                   first such call and bound to that device until
+ *                   gs_destroy; the caller's stream waits for them, so a
+ *                   graph captured on it records both branches.  The
+ *                   compositing queue and tile merging are not used here.
  *   "coarse_packed": 1 (default): coarse (super-tile, entry) pairs carry
  *                   their tile rectangle in the sort key above the
  *                   super-tile id when the ids fit in 17 bits; 0: always in

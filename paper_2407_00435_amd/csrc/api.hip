@@ -309,6 +309,11 @@ struct gs_ctx {
     uint32_t magic;
     int device;
     Tuning tn;
+    // view-by-view rendering: the second stream and its two events, made on
+    // the first such call (on `side_device`), released by gs_destroy
+    hipStream_t side = nullptr;
+    hipEvent_t ev_bin = nullptr, ev_join = nullptr;
+    int side_device = -1;
 };
 
 namespace {
@@ -371,6 +376,17 @@ int gs_destroy(gs_ctx *ctx)
     int r;
     if ((r = check_ctx(ctx))) return r;
     ctx->magic = 0;
+    if (ctx->side) {
+        int cur = 0;
+        const bool have = hipGetDevice(&cur) == hipSuccess;
+        if (hipSetDevice(ctx->side_device) == hipSuccess) {
+            (void)hipStreamSynchronize(ctx->side);
+            (void)hipStreamDestroy(ctx->side);
+            (void)hipEventDestroy(ctx->ev_bin);
+            (void)hipEventDestroy(ctx->ev_join);
+        }
+        if (have) (void)hipSetDevice(cur);
+    }
     delete ctx;
     return ok();
 }
@@ -687,6 +703,93 @@ int gs_project_bwd_levels(gs_ctx *ctx, const gs_scene *scene, const gs_camera *c
     return ok();
 }
 
+namespace {
+
+// The context's second stream and events, made on the first call that needs
+// them; a context keeps them on that device.
+int side_stream(gs_ctx *ctx)
+{
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+    if (ctx->side) {
+        if (dev != ctx->side_device)
+            return fail(GS_ERR_INVALID, "view-by-view rendering of one context stays on device %d (now on %d)",
+                        ctx->side_device, dev);
+        return GS_OK;
+    }
+    hipStream_t s = nullptr;
+    hipEvent_t a = nullptr, b = nullptr;
+    if ((e = hipStreamCreateWithFlags(&s, hipStreamNonBlocking)) != hipSuccess) return hip_fail(e, "hipStreamCreate");
+    if ((e = hipEventCreateWithFlags(&a, hipEventDisableTiming)) != hipSuccess ||
+        (e = hipEventCreateWithFlags(&b, hipEventDisableTiming)) != hipSuccess) {
+        (void)hipStreamDestroy(s);
+        if (a) (void)hipEventDestroy(a);
+        return hip_fail(e, "hipEventCreate");
+    }
+    ctx->side = s;
+    ctx->ev_bin = a;
+    ctx->ev_join = b;
+    ctx->side_device = dev;
+    return GS_OK;
+}
+
+// Per-view slots of the workspace status header (in 8-byte words): the
+// (required, capacity) pair each view's binning writes, then its key count.
+constexpr int STATUS_VIEW_REQ = 4;
+constexpr int STATUS_VIEW_NUM = 20;
+
+// The incremental pipelining of Section 5.2 at view granularity: each view is
+// binned on the caller's stream into its own cap / V slice of the keys, and
+// composited on the context's second stream once its binning is done, so
+// that view v's compositing overlaps view v + 1's binning.  Each view's keys,
+// ranges and pixels are exactly those of the joint call (bit-identical
+// images); the caller's stream waits for the last compositing.  The
+// compositing work queue and tile merging are not used here (their scratch
+// would be shared by the concurrent binning).
+int render_views_streamed(gs_ctx *ctx, const gs_scene *scene, const gs_camera *cams_host, const gs_camera *cams_dev,
+                          int V, int T, const float *bg, float *image, uint64_t key_capacity, uint64_t *num_keys,
+                          uint64_t *status, const RenderBufs &rb, BinScratch &bs, hipStream_t st)
+{
+    int r;
+    if ((r = side_stream(ctx))) return r;
+    const int n = scene->n, L = scene->n_levels;
+    const uint64_t cap_v = key_capacity / (uint64_t)V;
+    const float zero[3] = {0.f, 0.f, 0.f};
+    int64_t toff = 0, poff = 0;
+    hipError_t e;
+    for (int v = 0; v < V; ++v) {
+        const int W = cams_host[v].width, H = cams_host[v].height;
+        const int64_t tv = (int64_t)((W + T - 1) / T) * ((H + T - 1) / T);
+        const gs_splat *sp = rb.splats + (int64_t)v * n;
+        const float *lv = rb.lvl + (int64_t)v * n * L * 4;
+        uint32_t *vals = rb.vals + (int64_t)v * cap_v;
+        uint32_t *ranges = rb.ranges + 2 * toff;
+        e = launch_bin_sort(sp, n, cams_dev + v, cams_host + v, 1, tv, T, rb.tile_level + 2 * toff, scene->qbound, L,
+                            vals, nullptr, cap_v, ranges, nullptr, status + STATUS_VIEW_NUM + v, bs,
+                            ctx->tn.coarse_packed, status + STATUS_VIEW_REQ + 2 * v, st);
+        if (e != hipSuccess) return hip_fail(e, "gs_render_foveated (binning of a view)");
+        if ((e = hipEventRecord(ctx->ev_bin, st)) != hipSuccess ||
+            (e = hipStreamWaitEvent(ctx->side, ctx->ev_bin, 0)) != hipSuccess)
+            return hip_fail(e, "gs_render_foveated (stream order)");
+        e = launch_raster_fov(sp, lv, n, scene->qbound, L, cams_dev + v, 1, T, tv, vals, ranges, rb.pix_level + poff,
+                              rb.pix_weight + poff, bg ? bg : zero, image + 3 * poff, nullptr, nullptr, nullptr,
+                              nullptr, ctx->side, nullptr);
+        if (e != hipSuccess) return hip_fail(e, "gs_render_foveated (compositing of a view)");
+        toff += tv;
+        poff += (int64_t)W * H;
+    }
+    if ((e = launch_status_views(status + STATUS_VIEW_REQ, status + STATUS_VIEW_NUM, V, key_capacity, status,
+                                 num_keys, st)) != hipSuccess)
+        return hip_fail(e, "gs_render_foveated (status)");
+    if ((e = hipEventRecord(ctx->ev_join, ctx->side)) != hipSuccess ||
+        (e = hipStreamWaitEvent(st, ctx->ev_join, 0)) != hipSuccess)
+        return hip_fail(e, "gs_render_foveated (stream join)");
+    return ok();
+}
+
+}  // namespace
+
 int gs_render_foveated(gs_ctx *ctx, const gs_scene *scene, const gs_camera *cams_host, const gs_camera *cams_dev,
                        const gs_fovea *fov_host, int n_eyes, int tile_size, const float *bg,
                        float *image, uint64_t key_capacity, uint64_t *num_keys, void *workspace,
@@ -721,6 +824,9 @@ int gs_render_foveated(gs_ctx *ctx, const gs_scene *scene, const gs_camera *cams
     hipError_t e;
     if ((r = gs_project(ctx, scene, cams_host, cams_dev, n_eyes, tile_size, rb.splats, rb.lvl, stream)))
         return r;
+    if (ctx->tn.stream_views && n_eyes > 1)
+        return render_views_streamed(ctx, scene, cams_host, cams_dev, n_eyes, tile_size, bg, image, key_capacity,
+                                     num_keys, status, rb, bs, st);
     e = launch_bin_sort(rb.splats, scene->n, cams_dev, cams_host, n_eyes, tiles,
                         tile_size,
                         rb.tile_level, scene->qbound, L, rb.vals, nullptr, key_capacity, rb.ranges, nullptr,
@@ -964,6 +1070,11 @@ int gs_set_tuning(gs_ctx *ctx, const char *name, int64_t value)
         tn.raster_merge = (uint32_t)value;
         return ok();
     }
+    if (k == "stream_views") {
+        if (value != 0 && value != 1) return fail(GS_ERR_INVALID, "stream_views must be 0 or 1");
+        tn.stream_views = (int)value;
+        return ok();
+    }
     if (k == "coarse_packed") {
         if (value != 0 && value != 1) return fail(GS_ERR_INVALID, "coarse_packed must be 0 or 1");
         tn.coarse_packed = value != 0;
@@ -990,6 +1101,7 @@ int gs_get_tuning(gs_ctx *ctx, const char *name, int64_t *value)
     else if (k == "raster_split") *value = tn.raster_beta;
     else if (k == "raster_merge") *value = tn.raster_merge;
     else if (k == "coarse_packed") *value = tn.coarse_packed ? 1 : 0;
+    else if (k == "stream_views") *value = tn.stream_views;
     else if (k == "radix_part") *value = tn.radix_part;
     else return fail(GS_ERR_INVALID, "unknown tuning knob '%s'", name);
     return ok();

@@ -1120,6 +1120,30 @@ hipError_t launch_fill_u32(uint32_t *p, uint32_t value, uint64_t count, hipStrea
     return hipGetLastError();
 }
 
+namespace {
+
+__global__ void k_status_views(const uint64_t *__restrict__ req_cap, const uint64_t *__restrict__ nums, int V,
+                               uint64_t cap, uint64_t *__restrict__ status, uint64_t *__restrict__ num_keys)
+{
+    uint64_t most = 0, total = 0;
+    for (int v = 0; v < V; ++v) {
+        most = max(most, req_cap[2 * v]);
+        total += nums[v];
+    }
+    status[0] = most * (uint64_t)V;
+    status[1] = cap;
+    if (num_keys) *num_keys = total;
+}
+
+}  // namespace
+
+hipError_t launch_status_views(const uint64_t *req_cap, const uint64_t *nums, int V, uint64_t cap,
+                               uint64_t *status, uint64_t *num_keys, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_status_views, dim3(1), dim3(1), 0, st, req_cap, nums, V, cap, status, num_keys);
+    return hipGetLastError();
+}
+
 hipError_t launch_bin_sort(const gs_splat *splats, int n, const gs_camera *cams_dev,
                            const gs_camera *cams_host, int V, int64_t n_tiles, int T,
                            const uint8_t *tile_level, const uint8_t *qbound, int n_levels,

@@ -39,6 +39,7 @@ struct Tuning {
     uint32_t raster_heavy = 0;   // without split: runs longer than this go first
     uint32_t raster_grab = 1;    // tasks per pop
     uint32_t raster_merge = 0;   // tile merging threshold beta (0: one workgroup per tile)
+    int stream_views = 0;        // one-call foveated render: bin and composite view by view on two streams
 };
 
 // radix sort of (u32 key, u32 value) pairs, LSD over bits [0, bits)
@@ -127,6 +128,13 @@ hipError_t launch_bin_sort(const gs_splat *splats, int n, const gs_camera *cams_
                            uint32_t *vals, uint64_t *keys, uint64_t cap,
                            uint32_t *ranges, uint32_t *hits_out, uint64_t *num_keys,
                            const BinScratch &bs, bool coarse_packed, uint64_t *status, hipStream_t st);
+
+// Status of a binning done view by view: status[0] = V * the largest per-view
+// required key count (the capacity that fits every view when each has
+// cap / V), status[1] = cap, *num_keys = the total; req_cap: [V][2] (required,
+// capacity) as each binning wrote it, nums: [V] per-view key counts.
+hipError_t launch_status_views(const uint64_t *req_cap, const uint64_t *nums, int V, uint64_t cap,
+                               uint64_t *status, uint64_t *num_keys, hipStream_t st);
 
 // compositing
 // Work-queue scratch of the persistent compositors (carved from a workspace).
