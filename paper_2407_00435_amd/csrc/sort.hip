@@ -27,6 +27,10 @@ constexpr uint64_t FLAG_INC = 2ull << 62;
 constexpr uint64_t VAL_MASK = (1ull << 62) - 1;
 constexpr int MIN_PART = 4096;
 constexpr uint64_t SWEEP_BLOCKS = 1024;  // persistent onesweep workgroups (at most)
+// lookback words read per round (1024-thread workgroups have no registers
+// to spare for more than one)
+template <int THREADS>
+constexpr int lookback_batch() { return THREADS >= 1024 ? 1 : 8; }
 
 // Digit counts of every pass.  Each thread takes HIST_RUN consecutive keys
 // and adds one per key and digit into its wave's own LDS counters (the
@@ -200,18 +204,36 @@ k_radix_onesweep(const uint32_t *__restrict__ kin, const VT *__restrict__ vin,
                 __hip_atomic_store(my, FLAG_AGG | (uint64_t)total, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             }
             if (part > 0 && (uint32_t)t <= mask) {
+                // a batch of predecessors' words is read at once and taken in
+                // order (aggregates added until an inclusive prefix); an
+                // unpublished word ends the batch and is read again next
+                // round.  Partition 0 always ends the walk, so words before
+                // it are never taken.
+                constexpr int LOOKBACK = lookback_batch<THREADS>();
                 int64_t q = (int64_t)part - 1;
                 for (;;) {
-                    uint64_t st = __hip_atomic_load(status + q * R + t, __ATOMIC_RELAXED,
-                                                    __HIP_MEMORY_SCOPE_AGENT);
-                    uint64_t flag = st & ~VAL_MASK;
-                    if (flag == 0) {
-                        __builtin_amdgcn_s_sleep(1);
-                        continue;
+                    uint64_t w[LOOKBACK];
+#pragma unroll
+                    for (int j = 0; j < LOOKBACK; ++j)
+                        w[j] = q - j >= 0 ? __hip_atomic_load(status + (q - j) * R + t, __ATOMIC_RELAXED,
+                                                              __HIP_MEMORY_SCOPE_AGENT)
+                                          : FLAG_INC;
+                    int used = LOOKBACK;
+                    bool done = false;
+#pragma unroll
+                    for (int j = 0; j < LOOKBACK; ++j) {
+                        if (used < LOOKBACK || done) continue;
+                        const uint64_t flag = w[j] & ~VAL_MASK;
+                        if (flag == 0) {
+                            used = j;
+                            continue;
+                        }
+                        prefix += w[j] & VAL_MASK;
+                        if (flag == FLAG_INC) done = true;
                     }
-                    prefix += st & VAL_MASK;
-                    if (flag == FLAG_INC) break;
-                    --q;
+                    if (done) break;
+                    if (used == 0) __builtin_amdgcn_s_sleep(1);
+                    q -= used;
                 }
                 __hip_atomic_store(my, FLAG_INC | (prefix + total), __ATOMIC_RELAXED,
                                    __HIP_MEMORY_SCOPE_AGENT);
