@@ -294,6 +294,8 @@ TILE_SCHEDULES = (
     ("merge_4096", {"raster_merge": 4096}),
     ("merge_16384", {"raster_merge": 16384}),
     ("queue", {"raster_queue": 1}),
+    ("queue_heavy_4096", {"raster_queue": 1, "raster_heavy": 4096}),
+    ("queue_heavy_16384", {"raster_queue": 1, "raster_heavy": 16384}),
     ("queue_split_4096", {"raster_queue": 1, "raster_split": 4096}),
 )
 

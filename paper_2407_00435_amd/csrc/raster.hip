@@ -338,6 +338,41 @@ __device__ __forceinline__ FovState fov_init(bool inside, bool two)
     return s;
 }
 
+// One lane's share of a chunk's staging loads: the point's geometry, quality
+// bound and (two-level waves) the two level records the wave uses.
+struct FovFetch {
+    uint32_t id;
+    int m;
+    float4 s0, l0, l1;
+    float c;  // the conic's third coefficient (first word of the second vector)
+};
+
+template <bool WIDE>
+__device__ __forceinline__ FovFetch fov_fetch(const gs_splat *__restrict__ splats, const float4 *__restrict__ lvl,
+                                              const uint8_t *__restrict__ qbound, int L, int64_t vbase, uint32_t id,
+                                              bool ok, int wave_lo)
+{
+    FovFetch r;
+    r.id = id;
+    r.m = 0;
+    r.s0 = r.l0 = r.l1 = make_float4(0.f, 0.f, 0.f, 0.f);
+    r.c = 0.0f;
+    if (ok) {
+        r.m = qbound[id];
+        // only the words the compositor uses: a wider load would hold
+        // registers that the compiler reuses at once, waiting for the load
+        const float4 *s4 = reinterpret_cast<const float4 *>(splats + vbase + id);
+        r.s0 = s4[0];
+        r.c = reinterpret_cast<const float *>(s4 + 1)[0];
+        if (!WIDE) {
+            const float4 *lp = lvl + (vbase + id) * L;
+            r.l0 = lp[min(max(wave_lo - 1, 0), L - 1)];
+            r.l1 = lp[min(wave_lo, L - 1)];
+        }
+    }
+    return r;
+}
+
 template <bool STATS, bool KEEP, bool WIDE>
 __device__ __forceinline__ void fov_walk_impl(const gs_splat *__restrict__ splats, const float4 *__restrict__ lvl,
                                          int n, const uint8_t *__restrict__ qbound, int L,
@@ -347,26 +382,35 @@ __device__ __forceinline__ void fov_walk_impl(const gs_splat *__restrict__ splat
 {
     const int lane = __lane_id();
     const int64_t vbase = (int64_t)w.vi.v * n;
+    // the next chunk's point indices are loaded while this chunk is
+    // composited, so that staging a chunk waits for one memory latency (its
+    // records) instead of two dependent ones; prefetching the records too
+    // holds more registers than the occupancy it costs is worth
+    // (the index load is unconditional -- clamped to the run's last entry,
+    // in bounds whenever the run is not empty -- so that waiting for the
+    // records never has to wait for it)
+    uint32_t id_next = b < e ? vals[min(b + lane, e - 1)] : 0u;
     for (uint32_t c0 = b; c0 < e; c0 += 64) {
         if (ballot64(!(s.done_a && s.done_b)) == 0) break;
         const uint32_t idx = c0 + lane;
+        const FovFetch cur = fov_fetch<WIDE>(splats, lvl, qbound, L, vbase, id_next, idx < e, f.wave_lo);
+        id_next = vals[min(c0 + 64 + lane, e - 1)];
         bool keep = false;
         // the record is fully defined on every lane before the cull decision
         FovRec rec;
         rec.a = rec.b = rec.lv[0] = rec.lv[1] = make_float4(0.f, 0.f, 0.f, 0.f);
         if (idx < e) {
-            const uint32_t id = vals[idx];
-            const int m = qbound[id];
-            const float4 *s4 = reinterpret_cast<const float4 *>(splats + vbase + id);
-            const float4 s0 = s4[0], s1 = s4[1];
+            const uint32_t id = cur.id;
+            const int m = cur.m;
+            const float4 s0 = cur.s0;
+            const float c = cur.c;
             rec.a = make_float4(s0.x, s0.y, NEG_HALF_LOG2E * s0.z, -GS_LOG2E * s0.w);
-            rec.b = make_float4(NEG_HALF_LOG2E * s1.x, __uint_as_float(id), __int_as_float(m),
+            rec.b = make_float4(NEG_HALF_LOG2E * c, __uint_as_float(id), __int_as_float(m),
                                 __uint_as_float(idx - w.start + 1));
             float qcull = 9.001f;
             if (!WIDE) {
-                const float4 *lp = lvl + (vbase + id) * L;
-                rec.lv[0] = lp[min(max(f.wave_lo - 1, 0), L - 1)];
-                rec.lv[1] = lp[min(f.wave_lo, L - 1)];
+                rec.lv[0] = cur.l0;
+                rec.lv[1] = cur.l1;
                 // level wave_lo + 1 above the splat's quality bound: zero
                 // opacity, which no alpha test passes (so the loop needs no
                 // level test)
@@ -376,7 +420,7 @@ __device__ __forceinline__ void fov_walk_impl(const gs_splat *__restrict__ splat
                 qcull = qmax_of(fmaxf(rec.lv[0].w, rec.lv[1].w));
             }
             keep = m >= f.wave_lo &&
-                   reaches_rect(s0.x, s0.y, s0.z, s0.w, s1.x, qcull, w.rx0, w.rx1, w.ry0, w.ry1);
+                   reaches_rect(s0.x, s0.y, s0.z, s0.w, c, qcull, w.rx0, w.rx1, w.ry0, w.ry1);
         }
         const uint64_t msk = ballot64(keep);
         const int cnt = __popcll(msk);
