@@ -15,6 +15,8 @@ the mean over a region's pixels (Section 4.3).
 - The gradient agrees with central finite differences of the metric.
 - Regions partition the image: their sums and counts add up to the whole.
 - The pooling radius is zero at the gaze pixel and grows with eccentricity.
+- The terms at sampled pixels equal brute-force windows with numpy's
+  population statistics (borders, and a window over the whole image).
 """
 import math
 
@@ -113,3 +115,22 @@ def test_pooling_radius_grows_with_eccentricity(oracle_lib):
     np.testing.assert_array_equal(rad, np.floor(rho * ecc).astype(np.int32))
     row = rad[45, 40:]
     assert np.all(np.diff(row) >= 0) and row[-1] > 20
+
+
+def test_sampled_terms_match_brute_force_windows(oracle_lib):
+    # hvsq_at (the per-pixel terms at chosen pixels) against windows sliced
+    # out by hand and numpy's population statistics, including windows
+    # clipped at every border and one covering the whole image
+    rng = np.random.default_rng(11)
+    H, W = 9, 13
+    a, r = rnd(rng, H, W), rnd(rng, H, W)
+    rad = rng.integers(0, 5, H * W).astype(np.int32)
+    rad[4 * W + 6] = 20
+    pix = np.array([[0, 0], [12, 8], [6, 4], [12, 0], [0, 8], [3, 5], [9, 2]], np.int32)
+    got = oracle_lib.hvsq_at(a, r, rad, W, H, pix)
+    for k, (x, y) in enumerate(pix):
+        h = int(rad[y * W + x])
+        ys, xs = slice(max(0, y - h), min(H, y + h + 1)), slice(max(0, x - h), min(W, x + h + 1))
+        wa, wr = a[:, ys, xs].reshape(3, -1), r[:, ys, xs].reshape(3, -1)
+        term = np.mean((wa.mean(1) - wr.mean(1)) ** 2 + (wa.std(1) - wr.std(1)) ** 2)
+        assert got[k] == pytest.approx(term, rel=1e-12, abs=1e-15), (x, y)
