@@ -104,7 +104,6 @@ void carve_bin(Carve &c, int V, int64_t E, uint64_t cap, int64_t tiles, BinScrat
     bs.dval_a = c.take<uint32_t>(4 * E);
     bs.dkey_b = c.take<uint32_t>(4 * E);
     bs.dval_b = c.take<uint32_t>(4 * E);
-    bs.hits = c.take<uint32_t>(4 * E);
     bs.rec = c.take<uint4>(16 * E);
     bs.rec_s = c.take<uint4>(16 * E);
     bs.cc_s = c.take<uint32_t>(4 * E);

@@ -16,6 +16,8 @@
 //      position and yields the tile ranges from per-tile counts.
 // Sorting by depth over the points (millions) and counting per tile over the
 // keys (tens of millions) moves far fewer bytes than a 64-bit key sort.
+#include <algorithm>
+
 #include "common.hpp"
 #include "kernels.hpp"
 
@@ -59,16 +61,34 @@ __device__ __forceinline__ int64_t view_tile_off(const gs_camera *__restrict__ c
 // per row, tiles_x, tiles_y}; the key capacity in *cap_out; zeroed tile and
 // super-tile ranges (a tile without keys keeps (0, 0)); and, when given,
 // *num_keys = 0 (no entries at all).
+// Also cleared here: the lookback words and ticket of the counting pass
+// (lb[nb], *tick) and the depth sort's digit counts, tickets and first-pass
+// lookback words (what radix_sort_prepare would clear).
+struct SetupClears {
+    uint64_t *lb;
+    int64_t nb;
+    uint32_t *tick;
+    uint32_t *hist;     // [4][256]
+    uint32_t *tickets;  // [4]
+    uint64_t *status;
+    uint64_t status_words;
+};
+
 __global__ void __launch_bounds__(256)
 k_bin_setup(const gs_camera *__restrict__ cams, int V, int T, int64_t *__restrict__ vtab, int4 *__restrict__ stab,
             uint64_t *__restrict__ cap_out, uint64_t cap, uint32_t *__restrict__ ranges, int64_t n_tiles,
             uint32_t *__restrict__ st_ranges, int64_t n_st, uint64_t *__restrict__ num_keys,
-            uint64_t *__restrict__ status)
+            uint64_t *__restrict__ status, SetupClears z)
 {
     const uint64_t i0 = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
     for (uint64_t i = i0; i < 2 * (uint64_t)n_tiles; i += stride) ranges[i] = 0;
     for (uint64_t i = i0; i < 2 * (uint64_t)n_st; i += stride) st_ranges[i] = 0;
+    for (uint64_t i = i0; i < (uint64_t)z.nb; i += stride) z.lb[i] = 0;
+    for (uint64_t i = i0; i < z.status_words; i += stride) z.status[i] = 0;
+    for (uint64_t i = i0; i < 4 * 256; i += stride) z.hist[i] = 0;
+    if (i0 < 4) z.tickets[i0] = 0;
+    if (i0 == 4) *z.tick = 0;
     if (i0 != 0) return;
     *cap_out = cap;
     if (num_keys) *num_keys = 0;
@@ -191,25 +211,81 @@ __device__ __forceinline__ uint32_t sat_rect(const uint32_t *__restrict__ s, int
            sat_at(s, tiles_x, x0 - 1, y0 - 1);
 }
 
-// 1. per-entry counts; culled / empty entries get 0.  Also the float32 depth
-//    bits (dkey_all), a per-block count of entries with keys and, for those
-//    entries, rec[e] = {x0 | y0 << 16, x1 | y1 << 16, count, quality bound}
-//    with the rectangle clipped to the bounding box of the tiles its level
-//    keeps (the kept tiles and their row-major order are unchanged).
+// 1-2. per-entry counts (culled / empty entries count 0, to hits_out when
+//    given) and, for the entries with keys, rec[e] = {x0 | y0 << 16,
+//    x1 | y1 << 16, count, quality bound} with the rectangle clipped to the
+//    bounding box of the tiles its level keeps (the kept tiles and their
+//    row-major order are unchanged); then the stable compaction of those
+//    entries, (float32 depth bits, entry) to (dkey, dval), counting the depth
+//    digits of every sort pass into hist.  Workgroups take their blocks of
+//    entries in ticket order and find their output offset by decoupled
+//    lookback over the blocks before (lb: flag | count words); the block with
+//    the last ticket writes the total to *total.
 constexpr int COUNT_THREADS = 1024;
 constexpr int COUNT_ITEMS = SCAN_THREADS * SCAN_ITEMS / COUNT_THREADS;
+constexpr uint64_t LB_AGG = 1ull << 62;
+constexpr uint64_t LB_INC = 2ull << 62;
+constexpr uint64_t LB_VAL = (1ull << 62) - 1;
+constexpr int LB_BATCH = 8;  // lookback words read per round
+
+// Exclusive prefix of `tot` over the blocks before `blk` (ticket order), by
+// decoupled lookback: a batch of predecessors' words is read at once and
+// taken in order until an inclusive prefix; an unpublished word ends the
+// batch.  One thread.
+__device__ __forceinline__ uint64_t block_lookback(uint64_t *__restrict__ lb, int64_t blk, uint64_t tot)
+{
+    if (blk == 0) {
+        __hip_atomic_store(lb, LB_INC | tot, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        return 0;
+    }
+    __hip_atomic_store(lb + blk, LB_AGG | tot, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    uint64_t prefix = 0;
+    int64_t q = blk - 1;
+    for (;;) {
+        uint64_t w[LB_BATCH];
+#pragma unroll
+        for (int k = 0; k < LB_BATCH; ++k)
+            w[k] = q - k >= 0 ? __hip_atomic_load(lb + (q - k), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) : LB_INC;
+        int used = LB_BATCH;
+        bool done = false;
+#pragma unroll
+        for (int k = 0; k < LB_BATCH; ++k) {
+            if (used < LB_BATCH || done) continue;
+            const uint64_t flag = w[k] & ~LB_VAL;
+            if (flag == 0) {
+                used = k;
+                continue;
+            }
+            prefix += w[k] & LB_VAL;
+            if (flag == LB_INC) done = true;
+        }
+        if (done) break;
+        if (used == 0) __builtin_amdgcn_s_sleep(1);
+        q -= used;
+    }
+    __hip_atomic_store(lb + blk, LB_INC | (prefix + tot), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    return prefix;
+}
+
 template <bool FILT>
 __global__ void __launch_bounds__(COUNT_THREADS)
 k_count(const gs_splat *__restrict__ splats, int n, const gs_camera *__restrict__ cams, int V, int T,
         const int64_t *__restrict__ vtab, const uint32_t *__restrict__ sat, const int32_t *__restrict__ bbox, int L, int64_t n_tiles,
-        const uint8_t *__restrict__ qbound, uint32_t *__restrict__ hits, uint4 *__restrict__ rec,
-        uint32_t *__restrict__ dkey_all, uint32_t *__restrict__ hits_out, uint32_t *__restrict__ block_vis)
+        const uint8_t *__restrict__ qbound, uint4 *__restrict__ rec, uint32_t *__restrict__ hits_out,
+        uint32_t *__restrict__ tick, uint64_t *__restrict__ lb, uint64_t *__restrict__ total,
+        uint32_t *__restrict__ dkey, uint32_t *__restrict__ dval, uint32_t *__restrict__ hist)
 {
-    __shared__ uint32_t s_cnt;
-    if (threadIdx.x == 0) s_cnt = 0;
+    constexpr int W = COUNT_THREADS / 64;
+    __shared__ uint32_t s_blk;
+    __shared__ uint32_t s_w[COUNT_ITEMS][W];
+    __shared__ uint32_t s_h[4][256];
+    __shared__ uint64_t s_off;
+    if (threadIdx.x == 0) s_blk = atomicAdd(tick, 1u);
+    for (int q = threadIdx.x; q < 4 * 256; q += COUNT_THREADS) (&s_h[0][0])[q] = 0;
     __syncthreads();
+    const int64_t blk = s_blk;
     const int64_t E = (int64_t)V * n;
-    const int64_t base = (int64_t)blockIdx.x * (COUNT_THREADS * COUNT_ITEMS);
+    const int64_t base = blk * (COUNT_THREADS * COUNT_ITEMS);
     // Three rounds of loads over all items, each round issued before any of
     // its values is used: (1) splat fields, quality bound, view sizes; (2)
     // the level's bounding box; (3) the four summed-area corners.  Indices
@@ -279,24 +355,58 @@ k_count(const gs_splat *__restrict__ splats, int n, const gs_camera *__restrict_
             cnt[j] = ne[j] ? s11[j] - (lx ? s01[j] : 0u) - (ly ? s10[j] : 0u) + (lx && ly ? s00[j] : 0u) : 0u;
         }
     }
-    uint32_t vis = 0;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    uint64_t bal[COUNT_ITEMS];
 #pragma unroll
     for (int j = 0; j < COUNT_ITEMS; ++j) {
         const int64_t e = base + (int64_t)j * COUNT_THREADS + threadIdx.x;
-        if (e >= E) break;
-        hits[e] = cnt[j];
-        if (cnt[j])
-            rec[e] = make_uint4((uint32_t)r[j].tx0 | ((uint32_t)r[j].ty0 << 16),
-                                (uint32_t)r[j].tx1 | ((uint32_t)r[j].ty1 << 16), cnt[j],
-                                (uint32_t)(FILT ? mq[j] : 255));
-        if (hits_out) hits_out[e] = cnt[j];
-        dkey_all[e] = __float_as_uint(c[j].y);
-        vis += cnt[j] > 0;
+        if (e < E) {
+            if (cnt[j])
+                rec[e] = make_uint4((uint32_t)r[j].tx0 | ((uint32_t)r[j].ty0 << 16),
+                                    (uint32_t)r[j].tx1 | ((uint32_t)r[j].ty1 << 16), cnt[j],
+                                    (uint32_t)(FILT ? mq[j] : 255));
+            if (hits_out) hits_out[e] = cnt[j];
+        }
+        bal[j] = ballot64(e < E && cnt[j] > 0);
+        if (lane == 0) s_w[j][wave] = (uint32_t)__popcll(bal[j]);
     }
-    for (int off = 32; off > 0; off >>= 1) vis += __shfl_xor(vis, off);
-    if ((threadIdx.x & 63) == 0) atomicAdd(&s_cnt, vis);
     __syncthreads();
-    if (threadIdx.x == 0) block_vis[blockIdx.x] = s_cnt;
+    if (threadIdx.x == 0) {
+        uint64_t tot = 0;
+        for (int j = 0; j < COUNT_ITEMS; ++j)
+            for (int w = 0; w < W; ++w) tot += s_w[j][w];
+        const uint64_t pre = block_lookback(lb, blk, tot);
+        s_off = pre;
+        if (blk == (int64_t)gridDim.x - 1) *total = pre + tot;
+    }
+    __syncthreads();
+    // entries with keys in entry order: item-major within the block (item j
+    // of thread t is entry base + j * COUNT_THREADS + t)
+    uint64_t run = s_off;
+#pragma unroll
+    for (int j = 0; j < COUNT_ITEMS; ++j) {
+        uint32_t wpre = 0, tot = 0;
+        for (int w = 0; w < W; ++w) {
+            const uint32_t x = s_w[j][w];
+            if (w < wave) wpre += x;
+            tot += x;
+        }
+        if ((bal[j] >> lane) & 1ull) {
+            const int64_t e = base + (int64_t)j * COUNT_THREADS + threadIdx.x;
+            const uint64_t pos = run + wpre + (uint32_t)__popcll(bal[j] & lanemask_lt());
+            const uint32_t k = __float_as_uint(c[j].y);
+            dkey[pos] = k;
+            dval[pos] = (uint32_t)e;
+#pragma unroll
+            for (int p = 0; p < 4; ++p) atomicAdd(&s_h[p][(k >> (8 * p)) & 255u], 1u);
+        }
+        run += tot;
+    }
+    __syncthreads();
+    for (int q = threadIdx.x; q < 4 * 256; q += COUNT_THREADS) {
+        const uint32_t x = (&s_h[0][0])[q];
+        if (x) atomicAdd(&hist[q], x);
+    }
 }
 
 // Exclusive scan of nb block values in place by one workgroup of 1024
@@ -358,55 +468,6 @@ k_scan_pair(uint64_t *__restrict__ key_sums, uint64_t *__restrict__ pair_sums, i
         if (num_keys) *num_keys = kt;
         if (status) status[0] = kt;
         *pairs_total = pt <= kc ? pt : 0;
-    }
-}
-
-// 2. stable compaction of the entries with keys, counting depth digits.
-__global__ void __launch_bounds__(COUNT_THREADS)
-k_compact(const uint32_t *__restrict__ hits, const uint32_t *__restrict__ dkey_all, int64_t E,
-          const uint64_t *__restrict__ block_off, uint32_t *__restrict__ dkey,
-          uint32_t *__restrict__ dval, uint32_t *__restrict__ hist)
-{
-    constexpr int W = COUNT_THREADS / 64;
-    __shared__ uint32_t s_w[COUNT_ITEMS][W];
-    __shared__ uint32_t s_h[4][256];
-    for (int q = threadIdx.x; q < 4 * 256; q += COUNT_THREADS) (&s_h[0][0])[q] = 0;
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const int64_t base = (int64_t)blockIdx.x * (COUNT_THREADS * COUNT_ITEMS);
-    bool vis[COUNT_ITEMS];
-    uint64_t bal[COUNT_ITEMS];
-#pragma unroll
-    for (int j = 0; j < COUNT_ITEMS; ++j) {
-        const int64_t e = base + (int64_t)j * COUNT_THREADS + threadIdx.x;
-        vis[j] = e < E && hits[e] > 0;
-        bal[j] = ballot64(vis[j]);
-        if (lane == 0) s_w[j][wave] = (uint32_t)__popcll(bal[j]);
-    }
-    __syncthreads();
-    uint64_t run = block_off[blockIdx.x];
-#pragma unroll
-    for (int j = 0; j < COUNT_ITEMS; ++j) {
-        uint32_t wpre = 0, tot = 0;
-        for (int w = 0; w < W; ++w) {
-            const uint32_t c = s_w[j][w];
-            if (w < wave) wpre += c;
-            tot += c;
-        }
-        if (vis[j]) {
-            const int64_t e = base + (int64_t)j * COUNT_THREADS + threadIdx.x;
-            const uint64_t pos = run + wpre + (uint32_t)__popcll(bal[j] & lanemask_lt());
-            const uint32_t k = dkey_all[e];
-            dkey[pos] = k;
-            dval[pos] = (uint32_t)e;
-#pragma unroll
-            for (int p = 0; p < 4; ++p) atomicAdd(&s_h[p][(k >> (8 * p)) & 255u], 1u);
-        }
-        run += tot;
-    }
-    __syncthreads();
-    for (int q = threadIdx.x; q < 4 * 256; q += COUNT_THREADS) {
-        const uint32_t c = (&s_h[0][0])[q];
-        if (c) atomicAdd(&hist[q], c);
     }
 }
 
@@ -1160,9 +1221,22 @@ hipError_t launch_bin_sort(const gs_splat *splats, int n, const gs_camera *cams_
         n_st += (int64_t)((tx + ST - 1) / ST) * ((ty + ST - 1) / ST);
         max_view_tiles = tx * ty > max_view_tiles ? tx * ty : max_view_tiles;
     }
-    hipLaunchKernelGGL(k_bin_setup, dim3(grid_for(2 * (uint64_t)(n_tiles > n_st ? n_tiles : n_st), 256 * 4, 256)),
-                       dim3(256), 0, st, cams_dev, V, T, bs.vtab, bs.stab, bs.counts + 2, cap, ranges, n_tiles,
-                       bs.st_ranges, n_st, E == 0 ? num_keys : nullptr, status);
+    const int64_t nb = (E + SCAN_THREADS * SCAN_ITEMS - 1) / (SCAN_THREADS * SCAN_ITEMS);
+    // the counting pass's ticket and lookback words, and the depth sort's
+    // state for all E entries, are cleared with the rest of the set-up
+    SetupClears z;
+    z.lb = bs.block_sums;
+    z.nb = nb;
+    z.tick = bs.block_vis;
+    z.hist = bs.rs.hist;
+    z.tickets = bs.rs.tickets;
+    z.status = bs.rs.status;
+    z.status_words = radix_prepare_words(bs.rs, (uint64_t)E, 4, 32);
+    if (z.status_words > bs.rs.status_words) return hipErrorInvalidValue;
+    const uint64_t setup_n = std::max<uint64_t>(2 * (uint64_t)(n_tiles > n_st ? n_tiles : n_st), z.status_words);
+    hipLaunchKernelGGL(k_bin_setup, dim3(grid_for(setup_n, 256 * 4, 256)), dim3(256), 0, st, cams_dev, V, T, bs.vtab,
+                       bs.stab, bs.counts + 2, cap, ranges, n_tiles, bs.st_ranges, n_st,
+                       E == 0 ? num_keys : nullptr, status, z);
     if (E == 0) return hipGetLastError();
     const bool filt = tile_level != nullptr;
     const int L = n_levels < 1 ? 1 : (n_levels > 4 ? 4 : n_levels);
@@ -1175,20 +1249,16 @@ hipError_t launch_bin_sort(const gs_splat *splats, int n, const gs_camera *cams_
     if (filt)
         hipLaunchKernelGGL(k_st_class, dim3((unsigned)((n_st + 3) / 4)), dim3(256), 0, st, bs.vtab, bs.stab, V, n_st,
                            L, tile_level, bs.st_cls);
-    const int64_t nb = (E + SCAN_THREADS * SCAN_ITEMS - 1) / (SCAN_THREADS * SCAN_ITEMS);
-    // 1-2: counts, then stable compaction of entries with keys (depth digits counted)
+    // 1-2: counts, and the stable compaction of the entries with keys (depth
+    // digits counted, the total to counts[0])
     if (filt)
         hipLaunchKernelGGL(k_count<true>, dim3((unsigned)nb), dim3(COUNT_THREADS), 0, st, splats, n, cams_dev, V, T,
-                           bs.vtab, sat, bs.bbox, L, n_tiles, qbound, bs.hits, bs.rec, bs.dkey_b, hits_out,
-                           bs.block_vis);
+                           bs.vtab, sat, bs.bbox, L, n_tiles, qbound, bs.rec, hits_out, bs.block_vis,
+                           bs.block_sums, bs.counts, bs.dkey_a, bs.dval_a, bs.rs.hist);
     else
         hipLaunchKernelGGL(k_count<false>, dim3((unsigned)nb), dim3(COUNT_THREADS), 0, st, splats, n, cams_dev, V, T,
-                           bs.vtab, sat, bs.bbox, L, n_tiles, qbound, bs.hits, bs.rec, bs.dkey_b, hits_out,
-                           bs.block_vis);
-    hipLaunchKernelGGL(k_scan_blocks, dim3(1), dim3(1024), 0, st, bs.block_sums, bs.block_vis, nb, bs.counts);
-    if ((err = radix_sort_prepare(bs.rs, bs.counts, (uint64_t)E, 4, 32, st)) != hipSuccess) return err;
-    hipLaunchKernelGGL(k_compact, dim3((unsigned)nb), dim3(COUNT_THREADS), 0, st, bs.hits, bs.dkey_b, E,
-                       bs.block_sums, bs.dkey_a, bs.dval_a, bs.rs.hist);
+                           bs.vtab, sat, bs.bbox, L, n_tiles, qbound, bs.rec, hits_out, bs.block_vis,
+                           bs.block_sums, bs.counts, bs.dkey_a, bs.dval_a, bs.rs.hist);
     // 3: depth sort of the entries with keys (4 x 8-bit passes), result back in (dkey_a, dval_a)
     if ((err = radix_sort_pairs(bs.dkey_a, bs.dval_a, bs.dkey_b, bs.dval_b, bs.counts, (uint64_t)E, 32, bs.rs, st,
                                 true)) != hipSuccess)

@@ -78,6 +78,10 @@ hipError_t radix_sort_pairs_v2(uint32_t *ka, uint2 *va, uint32_t *kb, uint2 *vb,
 // the digit counts itself (hist_ready) calls it first
 hipError_t radix_sort_prepare(const RadixScratch &rs, const uint64_t *d_count, uint64_t cap, int vbytes, int bits,
                               hipStream_t st);
+// the lookback words radix_sort_prepare clears for a sort of `count` pairs
+// (a caller clearing them itself, with the digit counts and tickets, may
+// skip radix_sort_prepare)
+uint64_t radix_prepare_words(const RadixScratch &rs, uint64_t count, int vbytes, int bits);
 size_t radix_sort_scratch_bytes(uint64_t n);
 inline bool radix_part_ok(int p) { return p == 4096 || p == 8192 || p == 16384; }
 // sorts n pairs with its own scratch at ws (radix_sort_scratch_bytes(n)
@@ -96,12 +100,11 @@ constexpr uint32_t BIN_CHUNK = 256; // coarse pairs per chunk of the per-tile co
 inline uint64_t bin_max_chunks(uint64_t cap, int64_t n_tiles) { return cap / BIN_CHUNK + (uint64_t)n_tiles + 1; }
 struct BinScratch {
     uint32_t *dkey_a, *dval_a, *dkey_b, *dval_b;  // [E] depth sort ping-pong
-    uint32_t *hits;                               // [E]
     uint4 *rec;                                   // [E] rectangle, count, quality bound (entries with keys)
     uint4 *rec_s;                                 // [E] rectangle, entry, view and quality bound in depth order
     uint32_t *cc_s;                               // [E] coarse pairs of each entry in depth order
-    uint32_t *block_vis;                          // [E / SCAN_ITEMS + 1] entries with keys per block
-    uint64_t *block_sums, *block_sums2;           // [E / SCAN_ITEMS + 1]
+    uint32_t *block_vis;                          // [0]: ticket of the counting pass
+    uint64_t *block_sums, *block_sums2;           // [E / SCAN_ITEMS + 1] (block_sums: the counting pass's lookback words first)
     int64_t *vtab;                                // [2V] first tile and tiles_x of each view
     int4 *stab;                                   // [V] first super-tile, super-tiles per row, tiles_x, tiles_y
     uint32_t *tkey_a, *tkey_b;                    // [cap] coarse-pair sort keys (super-tile ids), ping-pong

@@ -305,6 +305,13 @@ int radix_pass_count(int bits, int vbytes, int part)
     return one_wide_pass(bits, part_for(vbytes, part)) ? 1 : radix_passes(bits);
 }
 
+uint64_t radix_prepare_words(const RadixScratch &rs, uint64_t count, int vbytes, int bits)
+{
+    const int P = part_for(vbytes, rs.part);
+    const int R = one_wide_pass(bits, P) ? 512 : 256;
+    return ((count + P - 1) / P) * R;
+}
+
 hipError_t radix_sort_prepare(const RadixScratch &rs, const uint64_t *d_count, uint64_t cap, int vbytes, int bits,
                               hipStream_t st)
 {
