@@ -290,6 +290,9 @@ struct FovRec {
     float4 a, b;
     float4 lv[2];
 };
+// staging slots per wave: a chunk's 64 records after up to 3 carried ones,
+// padded to a group of 4
+constexpr int FOV_SLOTS = 68;
 
 struct FovPix {
     int lo;          // lower level of the pixel
@@ -390,6 +393,7 @@ __device__ __forceinline__ void fov_walk_impl(const gs_splat *__restrict__ splat
     // in bounds whenever the run is not empty -- so that waiting for the
     // records never has to wait for it)
     uint32_t id_next = b < e ? vals[min(b + lane, e - 1)] : 0u;
+    int carry = 0;  // records carried over from the chunk before, at srec[0, carry)
     for (uint32_t c0 = b; c0 < e; c0 += 64) {
         if (ballot64(!(s.done_a && s.done_b)) == 0) break;
         const uint32_t idx = c0 + lane;
@@ -424,28 +428,33 @@ __device__ __forceinline__ void fov_walk_impl(const gs_splat *__restrict__ splat
         }
         const uint64_t msk = ballot64(keep);
         const int cnt = __popcll(msk);
-        // the list is padded to a multiple of 4 with null records (opacity 0,
-        // level -1: no pixel uses them) so that the loop below runs in groups
-        // of 4 with one exit test per group
-        const int cnt4 = (cnt + 3) & ~3;
-        if (keep) srec[__popcll(msk & lanemask_lt())] = rec;
-        if (lane >= cnt && lane < cnt4) {
+        // kept records go after the 0-3 carried from the chunk before; the
+        // loop below runs in groups of 4 with one exit test per group, and
+        // the records past the last full group wait for the next chunk --
+        // after the last chunk they are padded to a group with null records
+        // (opacity 0, level -1: no pixel uses them)
+        if (keep) srec[carry + __popcll(msk & lanemask_lt())] = rec;
+        const int total = carry + cnt;
+        const bool last_chunk = c0 + 64 >= e;
+        const int full = total & ~3;
+        const int upto = last_chunk ? (total + 3) & ~3 : full;
+        if (last_chunk && lane < 4 && full + lane >= total && full + lane < upto) {
             FovRec z;
             z.a = z.lv[0] = z.lv[1] = make_float4(0.f, 0.f, 0.f, 0.f);
             z.b = make_float4(0.f, 0.f, __int_as_float(-1), 0.f);
-            srec[lane] = z;
+            srec[full + lane] = z;
         }
         wave_lds_sync();
         if (STATS) {
             st[2] += (float)min(64u, e - c0);
             st[3] += (float)cnt;
         }
-        for (int j0 = 0; j0 < cnt4; j0 += 4) {
+        for (int j0 = 0; j0 < upto; j0 += 4) {
 #pragma unroll
             for (int j = j0; j < j0 + 4; ++j) {
                 // branch-free: every lane evaluates, selects take the decisions
                 const float4 a = srec[j].a, bb = srec[j].b;
-                if (STATS) st[1] += (j >= cnt || (s.done_a && s.done_b)) ? 0.0f : 1.0f;
+                if (STATS) st[1] += (j >= total || (s.done_a && s.done_b)) ? 0.0f : 1.0f;
                 const float p2 = pair_e2(a, make_float4(bb.x, 0.f, 0.f, 0.f), w.fpx, w.fpy);  // falloff only
                 const int m = __float_as_int(bb.z);
                 const float G = fast_exp2(p2);
@@ -496,6 +505,19 @@ __device__ __forceinline__ void fov_walk_impl(const gs_splat *__restrict__ splat
             if (ballot64(!(s.done_a && s.done_b)) == 0) break;
         }
         wave_lds_sync();
+        // the records past the last full group move to the front (they do
+        // not overlap their new place when there was a full group)
+        const int left = total - full;
+        if (!last_chunk && full > 0) {
+            // one float4 per lane: lane k moves part k % 4 of record k / 4
+            float4 *v4 = reinterpret_cast<float4 *>(srec);
+            const bool mv = lane < 4 * left;
+            const float4 t = v4[mv ? 4 * full + lane : 0];
+            wave_lds_sync();
+            if (mv) v4[lane] = t;
+            wave_lds_sync();
+        }
+        carry = left;
     }
 }
 
@@ -548,7 +570,7 @@ k_raster_fov(const gs_splat *__restrict__ splats, const float4 *__restrict__ lvl
 {
     float st[4] = {0.f, 0.f, 0.f, 0.f};
     constexpr int WAVES = T * T / 64;
-    __shared__ FovRec s_rec[WAVES][64];
+    __shared__ FovRec s_rec[WAVES][FOV_SLOTS];
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const WaveCtx w = wave_ctx<T>(cams, V, blockIdx.x, wave, lane, ranges);
     const FovPix f = fov_pix(w, pix_level, pix_weight);
@@ -860,7 +882,7 @@ k_raster_fov_q(const gs_splat *__restrict__ splats, const float4 *__restrict__ l
                float bg2, float *__restrict__ image, RasterQueue q)
 {
     constexpr int WAVES = T * T / 64;
-    __shared__ FovRec s_rec[WAVES][64];
+    __shared__ FovRec s_rec[WAVES][FOV_SLOTS];
     __shared__ uint32_t s_slot;
     const uint32_t nh = min(q.counts[1], q.heavy_cap), total = nh + min(q.counts[2], q.light_cap);
     // q.grab consecutive tasks per pop (neighbouring tiles share splats in cache)
@@ -1144,7 +1166,7 @@ k_raster_fov_m(const gs_splat *__restrict__ splats, const float4 *__restrict__ l
                float bg2, float *__restrict__ image, uint32_t *merge, int64_t n_tiles)
 {
     constexpr int WAVES = T * T / 64;
-    __shared__ FovRec s_rec[WAVES][64];
+    __shared__ FovRec s_rec[WAVES][FOV_SLOTS];
     __shared__ uint32_t s_slot;
     const MergeView m = merge_view(merge, n_tiles);
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
