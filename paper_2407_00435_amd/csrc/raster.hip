@@ -30,6 +30,9 @@ constexpr float EXTENT_LOG2 = -4.5f * GS_LOG2E;         // log2 exp(-9/2)
 struct FwdRec {
     float4 a, b, c;
 };
+// staging slots per wave: a chunk's 64 records after up to 3 carried ones,
+// padded to a group of 4
+constexpr int FWD_SLOTS = 68;
 
 __device__ __forceinline__ FwdRec make_rec(const float4 s0, const float4 s1, const float4 s2,
                                            uint32_t pos, uint32_t id)
@@ -180,14 +183,20 @@ __device__ __forceinline__ void fwd_walk(const gs_splat *__restrict__ vsp, const
                                          FwdState &s, float *st)
 {
     const int lane = __lane_id();
+    // the next chunk's point indices load while this chunk composites (an
+    // unconditional load clamped to the run's last entry, so that waiting
+    // for the records never waits for it)
+    uint32_t id_next = b < e ? vals[min(b + lane, e - 1)] : 0u;
+    int carry = 0;  // records carried over from the chunk before, at srec[0, carry)
     for (uint32_t c0 = b; c0 < e; c0 += 64) {
         if (ballot64(!s.done) == 0) break;
         const uint32_t idx = c0 + lane;
+        const uint32_t id = id_next;
+        id_next = vals[min(c0 + 64 + lane, e - 1)];
         bool keep = false;
         // the record is fully defined on every lane before the cull decision
         FwdRec rec = zero_rec();
         if (idx < e) {
-            const uint32_t id = vals[idx];
             const float4 *s4 = reinterpret_cast<const float4 *>(vsp + id);
             const float4 s0 = s4[0], s1 = s4[1], s2 = s4[2];
             rec = make_rec(s0, s1, s2, idx - w.start + 1, id);
@@ -195,27 +204,32 @@ __device__ __forceinline__ void fwd_walk(const gs_splat *__restrict__ vsp, const
         }
         const uint64_t m = ballot64(keep);
         const int cnt = __popcll(m);
-        // padded to a multiple of 4 with null records (an infinite alpha
-        // threshold: no pixel uses them): the loop runs in groups of 4 with
-        // one exit test per group
-        const int cnt4 = (cnt + 3) & ~3;
-        if (keep) srec[__popcll(m & lanemask_lt())] = rec;
-        if (lane >= cnt && lane < cnt4) {
+        // kept records go after the 0-3 carried from the chunk before; the
+        // loop below runs in groups of 4 with one exit test per group, and
+        // the records past the last full group wait for the next chunk --
+        // after the last chunk they are padded to a group with null records
+        // (an infinite alpha threshold: no pixel uses them)
+        if (keep) srec[carry + __popcll(m & lanemask_lt())] = rec;
+        const int total = carry + cnt;
+        const bool last_chunk = c0 + 64 >= e;
+        const int full = total & ~3;
+        const int upto = last_chunk ? (total + 3) & ~3 : full;
+        if (last_chunk && lane < 4 && full + lane >= total && full + lane < upto) {
             FwdRec z = zero_rec();
             z.b.z = __builtin_inff();
-            srec[lane] = z;
+            srec[full + lane] = z;
         }
         wave_lds_sync();
         if (STATS) {
             st[2] += (float)min(64u, e - c0);
             st[3] += (float)cnt;
         }
-        for (int j0 = 0; j0 < cnt4; j0 += 4) {
+        for (int j0 = 0; j0 < upto; j0 += 4) {
 #pragma unroll
             for (int j = j0; j < j0 + 4; ++j) {
                 // branch-free: every lane evaluates, selects take the decisions
                 const float4 a = srec[j].a, bb = srec[j].b, c = srec[j].c;
-                if (STATS) st[1] += (j >= cnt || s.done) ? 0.0f : 1.0f;
+                if (STATS) st[1] += (j >= total || s.done) ? 0.0f : 1.0f;
                 const float e2 = pair_e2(a, bb, w.fpx, w.fpy);
                 const float alpha = fminf(GS_ALPHA_MAX, fast_exp2(e2));
                 const bool use = !s.done && e2 >= bb.z;
@@ -238,6 +252,19 @@ __device__ __forceinline__ void fwd_walk(const gs_splat *__restrict__ vsp, const
             if (ballot64(!s.done) == 0) break;
         }
         wave_lds_sync();
+        // the records past the last full group move to the front (they do
+        // not overlap their new place when there was a full group): lane k
+        // moves part k % 3 of record k / 3
+        const int left = total - full;
+        if (!last_chunk && full > 0) {
+            float4 *v4 = reinterpret_cast<float4 *>(srec);
+            const bool mv = lane < 3 * left;
+            const float4 t = v4[mv ? 3 * full + lane : 0];
+            wave_lds_sync();
+            if (mv) v4[lane] = t;
+            wave_lds_sync();
+        }
+        carry = left;
     }
 }
 
@@ -267,7 +294,7 @@ k_raster_fwd(const gs_splat *__restrict__ splats, int n, const gs_camera *__rest
 {
     float st[4] = {0.f, 0.f, 0.f, 0.f};
     constexpr int WAVES = T * T / 64;
-    __shared__ FwdRec s_rec[WAVES][64];
+    __shared__ FwdRec s_rec[WAVES][FWD_SLOTS];
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const WaveCtx w = wave_ctx<T>(cams, V, blockIdx.x, wave, lane, ranges);
     FwdState s = fwd_init(w.inside);
@@ -778,7 +805,7 @@ k_raster_fwd_q(const gs_splat *__restrict__ splats, int n, const gs_camera *__re
                uint32_t *__restrict__ n_contrib, uint32_t *__restrict__ dominated, RasterQueue q)
 {
     constexpr int WAVES = T * T / 64;
-    __shared__ FwdRec s_rec[WAVES][64];
+    __shared__ FwdRec s_rec[WAVES][FWD_SLOTS];
     __shared__ uint32_t s_slot;
     const uint32_t nh = min(q.counts[1], q.heavy_cap), total = nh + min(q.counts[2], q.light_cap);
     // q.grab consecutive tasks per pop (neighbouring tiles share splats in cache)
@@ -1139,7 +1166,7 @@ k_raster_fwd_m(const gs_splat *__restrict__ splats, int n, const gs_camera *__re
                uint32_t *__restrict__ n_contrib, uint32_t *__restrict__ dominated, uint32_t *merge, int64_t n_tiles)
 {
     constexpr int WAVES = T * T / 64;
-    __shared__ FwdRec s_rec[WAVES][64];
+    __shared__ FwdRec s_rec[WAVES][FWD_SLOTS];
     __shared__ uint32_t s_slot;
     const MergeView m = merge_view(merge, n_tiles);
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
