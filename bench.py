@@ -44,12 +44,11 @@ FLOPS_PER_BLEND_BWD = 44
 # averaged over the dispatches), each scaled by the ratio of known bytes to
 # the same counter on a plain device copy (bench.py --copy-probe).  Valid
 # only for the kernel sources they were taken on (sha256 below).
-TRAFFIC = {"kernel": "k_raster_fov", "fetch_kib": 440614.0, "write_kib": 57135.8, "fetch_scale": 2.0,
-           "write_scale": 1.0, "sha256": "8dc52825230a6d6427f7a81a506e4310f265f26f8605bc256ba71b75b9528e09"}
+TRAFFIC = {"kernel": "k_raster_fov", "fetch_kib": 480851.2, "write_kib": 57409.3, "fetch_scale": 2.0,
+           "write_scale": 1.0, "sha256": "b5067fc528e6bb4f9ed7b4ba312babb1d164889a3b00b9b956bb73f656778da9"}
 # The same for the compositing reverse on the 1280x720 1M-Gaussian frame.
-TRAFFIC_BWD = {"kernel": "k_raster_bwd", "fetch_kib": 55523.7, "write_kib": 29395.7, "fetch_scale": 2.0,
-               "write_scale": 1.0, "sha256": "8dc52825230a6d6427f7a81a506e4310f265f26f8605bc256ba71b75b9528e09"}
-
+TRAFFIC_BWD = {"kernel": "k_raster_bwd", "fetch_kib": 55544.4, "write_kib": 29395.7, "fetch_scale": 2.0,
+               "write_scale": 1.0, "sha256": "b5067fc528e6bb4f9ed7b4ba312babb1d164889a3b00b9b956bb73f656778da9"}
 
 def kernel_sha():
     import hashlib
