@@ -371,7 +371,7 @@ static hipError_t sort_pairs_impl(uint32_t *ka, VT *va, uint32_t *kb, VT *vb,
         if (wide) {
             GS_OS(512, 16, 9);
         } else if (P == 4096) {
-            GS_OS(256, 16, 8);
+            GS_OS(512, 8, 8);
         } else if (P == 16384) {
             if constexpr (sizeof(VT) == 4) GS_OS(1024, 16, 8);
         } else {
