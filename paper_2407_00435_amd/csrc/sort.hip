@@ -27,10 +27,10 @@ constexpr uint64_t FLAG_INC = 2ull << 62;
 constexpr uint64_t VAL_MASK = (1ull << 62) - 1;
 constexpr int MIN_PART = 4096;
 constexpr uint64_t SWEEP_BLOCKS = 1024;  // persistent onesweep workgroups (at most)
-// lookback words read per round (1024-thread workgroups have no registers
-// to spare for more than one)
-template <int THREADS>
-constexpr int lookback_batch() { return THREADS >= 1024 ? 1 : 8; }
+// lookback words read per round (1024-thread workgroups holding 16 keys a
+// thread have no registers to spare for more than one)
+template <int THREADS, int ITEMS>
+constexpr int lookback_batch() { return THREADS >= 1024 && ITEMS >= 16 ? 1 : 8; }
 
 // Digit counts of every pass.  Each thread takes HIST_RUN consecutive keys
 // and adds one per key and digit into its wave's own LDS counters (the
@@ -209,7 +209,7 @@ k_radix_onesweep(const uint32_t *__restrict__ kin, const VT *__restrict__ vin,
                 // unpublished word ends the batch and is read again next
                 // round.  Partition 0 always ends the walk, so words before
                 // it are never taken.
-                constexpr int LOOKBACK = lookback_batch<THREADS>();
+                constexpr int LOOKBACK = lookback_batch<THREADS, ITEMS>();
                 int64_t q = (int64_t)part - 1;
                 for (;;) {
                     uint64_t w[LOOKBACK];
@@ -375,7 +375,7 @@ static hipError_t sort_pairs_impl(uint32_t *ka, VT *va, uint32_t *kb, VT *vb,
         } else if (P == 16384) {
             if constexpr (sizeof(VT) == 4) GS_OS(1024, 16, 8);
         } else {
-            GS_OS(512, 16, 8);
+            GS_OS(1024, 8, 8);
         }
 #undef GS_OS
         uint32_t *tk = src_k;
