@@ -369,7 +369,7 @@ static hipError_t sort_pairs_impl(uint32_t *ka, VT *va, uint32_t *kb, VT *vb,
                        src_v, dst_k, dst_v, d_count, cap, dbits * p, mask, dbits,                  \
                        rs.hist + R * p, cur, next, rs.tickets + p)
         if (wide) {
-            GS_OS(512, 16, 9);
+            GS_OS(1024, 8, 9);
         } else if (P == 4096) {
             GS_OS(512, 8, 8);
         } else if (P == 16384) {
