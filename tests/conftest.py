@@ -12,7 +12,7 @@ if ROOT not in sys.path:
 # so that a failure late in the list (under -x) hides as few oracle checks as
 # possible.  Files not listed keep their place after these (the allocation-free
 # entry point's test, test_zz_*, is collected last by name).
-GPU_ORDER = ("test_gpu_parity.py", "test_gpu_sort.py", "test_gpu_prune.py", "test_gpu_loss.py",
+GPU_ORDER = ("test_gpu_parity.py", "test_gpu_edge.py", "test_gpu_sort.py", "test_gpu_prune.py", "test_gpu_loss.py",
              "test_gpu_queue.py", "test_gpu_merge.py", "test_gpu_streamed.py", "test_gpu_fr_bwd.py", "test_gpu_ctx.py",
              "test_gpu_hvsq.py", "test_gpu_batched_oracle.py", "test_gpu_batched.py",
              "test_gpu_fullsize.py")
