@@ -132,3 +132,37 @@ def test_calls_check_the_context_first(L):
     assert b"256-byte aligned" in raw.gs_last_error()
     assert raw.gs_destroy(None) == 0
     ctx.close()
+
+
+def test_size_limits_and_scheduling_knobs_on_the_host(L):
+    raw = L.raw_lib()
+    ctx = L.Context(0)
+    h = ctx.handle
+    # the allocation-free sort refuses more keys than its static scratch holds,
+    # and accepts empty or zero-bit sorts without touching a device
+    big = ctypes.c_uint64(L.SORT_STATIC_MAX_KEYS + 1)
+    p = ctypes.c_void_p(256)
+    assert raw.gs_sort_pairs_static(h, p, p, p, p, big, 16, None) == L.GS_ERR_CAPACITY
+    assert b"maximum" in raw.gs_last_error()
+    assert raw.gs_sort_pairs_static(h, p, p, p, p, ctypes.c_uint64(10), 33, None) == L.GS_ERR_INVALID
+    assert raw.gs_sort_pairs_static(h, None, None, None, None, ctypes.c_uint64(0), 16, None) == 0
+    assert raw.gs_sort_pairs_static(h, p, p, p, p, ctypes.c_uint64(10), 0, None) == 0
+    # scheduling knobs: defaults, accepted values, rejected values leave the setting
+    for k, v in (("raster_merge", 0), ("stream_views", 0)):
+        assert ctx.get_tuning(k) == v
+    ctx.set_tuning("raster_merge", 4096)
+    ctx.set_tuning("stream_views", 1)
+    assert (ctx.get_tuning("raster_merge"), ctx.get_tuning("stream_views")) == (4096, 1)
+    for k, v in (("raster_merge", -1), ("raster_merge", 1 << 32), ("stream_views", 2), ("stream_views", -1)):
+        with pytest.raises(L.GsError):
+            ctx.set_tuning(k, v)
+    assert (ctx.get_tuning("raster_merge"), ctx.get_tuning("stream_views")) == (4096, 1)
+    # merging needs workspace for its groups
+    cams = (L.GsCamera * 1)()
+    cams[0].width, cams[0].height, cams[0].fx, cams[0].fy = 640, 480, 500.0, 500.0
+    pc = ctypes.cast(cams, L._PC)
+    merged = raw.gs_workspace_bytes(h, pc, 1, 1000, 16, 100000)
+    ctx.set_tuning("raster_merge", 0)
+    plain = raw.gs_workspace_bytes(h, pc, 1, 1000, 16, 100000)
+    assert merged > plain
+    ctx.close()
