@@ -731,10 +731,10 @@ def main():
     ap.add_argument("--radix-part", type=int, default=16384)
     ap.add_argument("--copy-probe", action="store_true",
                     help="only run a plain 1 GiB device copy (memory-counter calibration)")
-    ap.add_argument("--only", choices=("fwdbwd", "plain", "schedules", "streamed"),
+    ap.add_argument("--only", choices=("fwdbwd", "plain", "schedules", "streamed", "hvsq"),
                     help="only the 1280x720 1M-Gaussian forward+backward, only the 1280x720 500k plain "
-                         "forward (for profiling one kernel), only the tile-schedule comparison, or only the one-call "
-                         "frame joint and eye by eye")
+                         "forward (for profiling one kernel), only the tile-schedule comparison, only the one-call "
+                         "frame joint and eye by eye, or only the HVSQ of the stereo frame")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py runs on exactly one GPU: the renderer has no multi-GPU path "
@@ -753,6 +753,13 @@ def main():
         return
     if args.only == "plain":
         print(json.dumps(plain_fwd_rate(g, scenegen.config2(), args.steps, args.warmup)), flush=True)
+        return
+    if args.only == "hvsq":
+        torch.cuda.set_device(0)
+        wl = scenegen.config3()
+        fr = Foveated(g, wl, args.tile)
+        time_foveated(fr, 1, 1)
+        print(json.dumps(hvsq_rate(g, fr, wl)), flush=True)
         return
     if args.only == "streamed":
         torch.cuda.set_device(0)

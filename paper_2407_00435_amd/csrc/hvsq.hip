@@ -102,17 +102,24 @@ k_hvsq_radius(const gs_camera *__restrict__ cams, int V, FoveaGazes gz, float rh
 constexpr int PLANES = 12;  // image (a, r) x channel (3) x power (x, x^2)
 constexpr int ROW_THREADS = 256;
 
-// Row pass of the summed-area tables: block (row g of all views, plane p)
-// writes the inclusive prefix of its row into table row y + 1, columns
-// 1..W (column 0 is zero).  Each thread sums a contiguous segment, the
-// segment totals are scanned in LDS, then each thread writes its prefixes.
+// Row pass: one workgroup per (view row, image, channel) makes the row of
+// both powers' tables (x and x^2).  The row is read in chunks of
+// 4 * ROW_THREADS values, four consecutive ones per thread (coalesced); each
+// chunk is scanned in double-double -- within the thread, across the wave by
+// shuffles, across the workgroup through LDS -- after the running total of
+// the chunks before, and stored as contiguous runs; table column 0 is zero.
+__device__ __forceinline__ dd dd_shfl_up(dd x, int off)
+{
+    return {__shfl_up(x.hi, off), __shfl_up(x.lo, off)};
+}
+
 __global__ void __launch_bounds__(ROW_THREADS)
 k_hvsq_sat_rows(const gs_camera *__restrict__ cams, int V, const float *__restrict__ img_a,
                 const float *__restrict__ img_r, int64_t P, double *__restrict__ hi, double *__restrict__ lo)
 {
-    __shared__ dd s_tot[ROW_THREADS];
-    const int p = blockIdx.y;
-    const int img = p / 6, ch = (p / 2) % 3, sq = p & 1;
+    constexpr int WAVES = ROW_THREADS / 64;
+    __shared__ dd s_w[2][WAVES];
+    const int q = blockIdx.y, img = q / 3, ch = q % 3;
     // the view of global row blockIdx.x
     int v = 0;
     int64_t rows = 0;
@@ -123,33 +130,66 @@ k_hvsq_sat_rows(const gs_camera *__restrict__ cams, int V, const float *__restri
     const HvView h = hv_view(cams, V, v);
     const int y = (int)(blockIdx.x - h.row_off);
     const float *src = (img ? img_r : img_a) + 3 * h.pix_off + (int64_t)ch * h.W * h.H + (int64_t)y * h.W;
-    const int seg = (h.W + ROW_THREADS - 1) / ROW_THREADS;
-    const int x0 = threadIdx.x * seg, x1 = min(x0 + seg, h.W);
-    dd acc = {0.0, 0.0};
-    for (int x = x0; x < x1; ++x) {
-        const double e = (double)src[x];
-        acc = dd_add(acc, {sq ? e * e : e, 0.0});  // a float's square is exact in a double
-    }
-    s_tot[threadIdx.x] = acc;
-    __syncthreads();
-    // inclusive scan of the segment totals (Hillis-Steele)
-    for (int off = 1; off < ROW_THREADS; off <<= 1) {
-        const dd add = threadIdx.x >= off ? s_tot[threadIdx.x - off] : dd{0.0, 0.0};
-        __syncthreads();
-        s_tot[threadIdx.x] = dd_add(s_tot[threadIdx.x], add);
-        __syncthreads();
-    }
-    dd run = threadIdx.x ? s_tot[threadIdx.x - 1] : dd{0.0, 0.0};
-    const int64_t row = (int64_t)p * P + h.pad_off + (int64_t)(y + 1) * (h.W + 1);
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    // planes img * 6 + ch * 2 + power
+    const int64_t row0 = (int64_t)(img * 6 + ch * 2) * P + h.pad_off + (int64_t)(y + 1) * (h.W + 1);
+    const int64_t row1 = row0 + P;
     if (threadIdx.x == 0) {
-        hi[row] = 0.0;
-        lo[row] = 0.0;
+        hi[row0] = lo[row0] = 0.0;
+        hi[row1] = lo[row1] = 0.0;
     }
-    for (int x = x0; x < x1; ++x) {
-        const double e = (double)src[x];
-        run = dd_add(run, {sq ? e * e : e, 0.0});
-        hi[row + x + 1] = run.hi;
-        lo[row + x + 1] = run.lo;
+    dd carry0 = {0.0, 0.0}, carry1 = {0.0, 0.0};
+    for (int c0 = 0; c0 < h.W; c0 += 4 * ROW_THREADS) {
+        const int x = c0 + 4 * (int)threadIdx.x;
+        dd a[4], b[4];  // the thread's inclusive prefixes of x and x^2
+        dd s0 = {0.0, 0.0}, s1 = {0.0, 0.0};
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            const double e = x + k < h.W ? (double)src[x + k] : 0.0;
+            s0 = dd_add(s0, {e, 0.0});
+            s1 = dd_add(s1, {e * e, 0.0});  // a float's square is exact in a double
+            a[k] = s0;
+            b[k] = s1;
+        }
+        dd t0 = s0, t1 = s1;
+        for (int off = 1; off < 64; off <<= 1) {
+            const dd u0 = dd_shfl_up(t0, off), u1 = dd_shfl_up(t1, off);
+            if (lane >= off) {
+                t0 = dd_add(t0, u0);
+                t1 = dd_add(t1, u1);
+            }
+        }
+        if (lane == 63) {
+            s_w[0][wave] = t0;
+            s_w[1][wave] = t1;
+        }
+        __syncthreads();
+        dd w0 = carry0, w1 = carry1, n0 = carry0, n1 = carry1;
+        for (int k = 0; k < WAVES; ++k) {
+            if (k < wave) {
+                w0 = dd_add(w0, s_w[0][k]);
+                w1 = dd_add(w1, s_w[1][k]);
+            }
+            n0 = dd_add(n0, s_w[0][k]);
+            n1 = dd_add(n1, s_w[1][k]);
+        }
+        dd e0 = dd_shfl_up(t0, 1), e1 = dd_shfl_up(t1, 1);
+        if (lane == 0) e0 = e1 = {0.0, 0.0};
+        w0 = dd_add(w0, e0);
+        w1 = dd_add(w1, e1);
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            if (x + k < h.W) {
+                const dd r0 = dd_add(w0, a[k]), r1 = dd_add(w1, b[k]);
+                hi[row0 + x + k + 1] = r0.hi;
+                lo[row0 + x + k + 1] = r0.lo;
+                hi[row1 + x + k + 1] = r1.hi;
+                lo[row1 + x + k + 1] = r1.lo;
+            }
+        }
+        carry0 = n0;
+        carry1 = n1;
+        __syncthreads();  // s_w is written again by the next chunk
     }
 }
 
@@ -173,8 +213,41 @@ k_hvsq_sat_cols(const gs_camera *__restrict__ cams, int V, int64_t P, double *__
     hi[base] = 0.0;
     lo[base] = 0.0;
     dd acc = {0.0, 0.0};
-#pragma unroll 8
-    for (int y = 1; y <= h.H; ++y) {
+    // rows in batches of CB: the next batch's loads are issued before this
+    // batch's stores (a load waits for every store issued before it), then
+    // the rows left over one by one
+    constexpr int CB = 8;
+    const int full = h.H / CB * CB;
+    double nh[CB], nl[CB];
+    if (full > 0) {
+#pragma unroll
+        for (int k = 0; k < CB; ++k) {
+            nh[k] = hi[base + (int64_t)(1 + k) * W1];
+            nl[k] = lo[base + (int64_t)(1 + k) * W1];
+        }
+    }
+    for (int y0 = 1; y0 <= full; y0 += CB) {
+        double ch[CB], cl[CB];
+#pragma unroll
+        for (int k = 0; k < CB; ++k) {
+            ch[k] = nh[k];
+            cl[k] = nl[k];
+        }
+        if (y0 + CB <= full) {
+#pragma unroll
+            for (int k = 0; k < CB; ++k) {
+                nh[k] = hi[base + (int64_t)(y0 + CB + k) * W1];
+                nl[k] = lo[base + (int64_t)(y0 + CB + k) * W1];
+            }
+        }
+#pragma unroll
+        for (int k = 0; k < CB; ++k) {
+            acc = dd_add(acc, {ch[k], cl[k]});
+            hi[base + (int64_t)(y0 + k) * W1] = acc.hi;
+            lo[base + (int64_t)(y0 + k) * W1] = acc.lo;
+        }
+    }
+    for (int y = full + 1; y <= h.H; ++y) {
         const int64_t q = base + (int64_t)y * W1;
         acc = dd_add(acc, {hi[q], lo[q]});
         hi[q] = acc.hi;
@@ -319,7 +392,8 @@ k_hvsq_scatter(const gs_camera *__restrict__ cams, int V, int64_t P, const doubl
 __global__ void __launch_bounds__(ROW_THREADS)
 k_hvsq_prefix_rows(const gs_camera *__restrict__ cams, int V, int64_t P, double *__restrict__ D)
 {
-    __shared__ double s_tot[ROW_THREADS];
+    constexpr int WAVES = ROW_THREADS / 64;
+    __shared__ double s_w[WAVES];
     int v = 0;
     int64_t rows = 0;
     for (; v < V - 1; ++v) {
@@ -329,22 +403,37 @@ k_hvsq_prefix_rows(const gs_camera *__restrict__ cams, int V, int64_t P, double 
     const HvView h = hv_view(cams, V, v);
     const int y = (int)(blockIdx.x - h.row_off);
     double *row = D + (int64_t)blockIdx.y * P + h.pad_off + (int64_t)y * (h.W + 1);
-    const int seg = (h.W + ROW_THREADS - 1) / ROW_THREADS;
-    const int x0 = threadIdx.x * seg, x1 = min(x0 + seg, h.W);
-    double acc = 0.0;
-    for (int x = x0; x < x1; ++x) acc += row[x];
-    s_tot[threadIdx.x] = acc;
-    __syncthreads();
-    for (int off = 1; off < ROW_THREADS; off <<= 1) {
-        const double add = threadIdx.x >= off ? s_tot[threadIdx.x - off] : 0.0;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    // chunks of 4 * ROW_THREADS values, four consecutive ones per thread, as
+    // in the table's row pass
+    double carry = 0.0;
+    for (int c0 = 0; c0 < h.W; c0 += 4 * ROW_THREADS) {
+        const int x = c0 + 4 * (int)threadIdx.x;
+        double a[4], t = 0.0;
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            t += x + k < h.W ? row[x + k] : 0.0;
+            a[k] = t;
+        }
+        double wt = t;
+        for (int off = 1; off < 64; off <<= 1) {
+            const double u = __shfl_up(wt, off);
+            if (lane >= off) wt += u;
+        }
+        if (lane == 63) s_w[wave] = wt;
         __syncthreads();
-        s_tot[threadIdx.x] += add;
-        __syncthreads();
-    }
-    double run = threadIdx.x ? s_tot[threadIdx.x - 1] : 0.0;
-    for (int x = x0; x < x1; ++x) {
-        run += row[x];
-        row[x] = run;
+        double w = carry, n = carry;
+        for (int k = 0; k < WAVES; ++k) {
+            if (k < wave) w += s_w[k];
+            n += s_w[k];
+        }
+        const double ex = __shfl_up(wt, 1);
+        w += lane ? ex : 0.0;
+#pragma unroll
+        for (int k = 0; k < 4; ++k)
+            if (x + k < h.W) row[x + k] = w + a[k];
+        carry = n;
+        __syncthreads();  // s_w is written again by the next chunk
     }
 }
 
@@ -362,8 +451,30 @@ k_hvsq_prefix_cols(const gs_camera *__restrict__ cams, int V, int64_t P, double 
     double *col = D + (int64_t)blockIdx.y * P + h.pad_off + c;
     const int64_t W1 = h.W + 1;
     double acc = 0.0;
-#pragma unroll 8
-    for (int y = 0; y < h.H; ++y) {
+    // batches of CB rows, the next batch's loads issued before this batch's
+    // stores (as in the table's column pass), then the rows left over
+    constexpr int CB = 8;
+    const int full = h.H / CB * CB;
+    double nx[CB];
+    if (full > 0) {
+#pragma unroll
+        for (int k = 0; k < CB; ++k) nx[k] = col[(int64_t)k * W1];
+    }
+    for (int y0 = 0; y0 < full; y0 += CB) {
+        double cx[CB];
+#pragma unroll
+        for (int k = 0; k < CB; ++k) cx[k] = nx[k];
+        if (y0 + CB < full) {
+#pragma unroll
+            for (int k = 0; k < CB; ++k) nx[k] = col[(int64_t)(y0 + CB + k) * W1];
+        }
+#pragma unroll
+        for (int k = 0; k < CB; ++k) {
+            acc += cx[k];
+            col[(int64_t)(y0 + k) * W1] = acc;
+        }
+    }
+    for (int y = full; y < h.H; ++y) {
         acc += col[(int64_t)y * W1];
         col[(int64_t)y * W1] = acc;
     }
@@ -435,7 +546,7 @@ hipError_t launch_hvsq(const gs_camera *cams_host, const gs_camera *cams_dev, in
     const int64_t nsum = (int64_t)V * (R + 1);
     hipLaunchKernelGGL(k_fill_f64, dim3(1), dim3(256), 0, st, sums, nsum);
     hipLaunchKernelGGL(k_fill_f64, dim3(1), dim3(256), 0, st, counts, nsum);
-    hipLaunchKernelGGL(k_hvsq_sat_rows, dim3((unsigned)rows, PLANES), dim3(ROW_THREADS), 0, st, cams_dev, V, img_a,
+    hipLaunchKernelGGL(k_hvsq_sat_rows, dim3((unsigned)rows, PLANES / 2), dim3(ROW_THREADS), 0, st, cams_dev, V, img_a,
                        img_r, P, hi, lo);
     hipLaunchKernelGGL(k_hvsq_sat_cols, dim3((unsigned)((cols + 255) / 256), PLANES), dim3(256), 0, st, cams_dev, V,
                        P, hi, lo);
