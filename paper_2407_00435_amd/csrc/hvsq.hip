@@ -20,7 +20,8 @@
 // (B_i = 0 where S_a = 0, where the square root has no derivative), is a
 // sum of per-window constants over rectangles: each window adds A_i and B_i
 // at its four corners of a difference array (double atomics), and a 2D
-// prefix sum of that array gives every pixel's sums.
+// prefix sum of that array gives every pixel's sums (k is applied last: it
+// needs the region's pixel count, which the scatter's own pass counts).
 #include <algorithm>
 
 #include "common.hpp"
@@ -307,13 +308,32 @@ __device__ __forceinline__ double pixel_term(const WinStats &w)
     return t / 3.0;
 }
 
+__device__ __forceinline__ double wave_sum_d(double x)
+{
+    for (int off = 32; off > 0; off >>= 1) x += __shfl_xor(x, off);
+    return x;
+}
+
 // Per pixel: the term; per view: sums and counts per region and over the
-// whole view (block partials in LDS, one double atomic per region and block).
-// terms (nullable): the per-pixel terms.
+// whole view (wave sums, one LDS atomic per wave and region, one double
+// atomic per block and region).  terms (nullable): the per-pixel terms.
+// With GRAD, the pixels of grad_region (0: every pixel) also add their
+// window's gradient constants, without the factor 1 / (3 N) (N the region's
+// pixel count, known only when every block is done; k_hvsq_grad applies it),
+// at the four corners of the window in the view's difference arrays D
+// ([channel][A, B] planes of (H + 1) x (W + 1) doubles): the metric over a
+// region is (1 / N) sum_i t_i, and for pixel j of window i and channel c,
+//   d t_i / d a_jc = (1 / 3) (2 (M_a - M_r) / n + 2 (S_a - S_r) (a_jc - M_a) / (n S_a))
+//                  = (1 / 3) (A + B a_jc),
+// B = 2 (S_a - S_r) / (n S_a) (0 where S_a = 0), A = 2 (M_a - M_r) / n - B M_a,
+// the statistics being those of channel c; summed over the windows that
+// contain j.
+template <bool GRAD>
 __global__ void __launch_bounds__(256)
 k_hvsq_terms(const gs_camera *__restrict__ cams, int V, int64_t P, const double *__restrict__ hi,
              const double *__restrict__ lo, const int32_t *__restrict__ radius, const uint8_t *__restrict__ region,
-             int R, double *__restrict__ sums, double *__restrict__ counts, double *__restrict__ terms)
+             int R, double *__restrict__ sums, double *__restrict__ counts, double *__restrict__ terms,
+             int grad_region, double *__restrict__ D)
 {
     __shared__ double s_sum[GS_HVSQ_MAX_REGIONS + 1], s_cnt[GS_HVSQ_MAX_REGIONS + 1];
     if (threadIdx.x <= R) {
@@ -323,20 +343,59 @@ k_hvsq_terms(const gs_camera *__restrict__ cams, int V, int64_t P, const double 
     __syncthreads();
     const HvView h = hv_view(cams, V, blockIdx.y);
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < (int64_t)h.W * h.H) {
+    const int lane = threadIdx.x & 63;
+    const bool valid = i < (int64_t)h.W * h.H;
+    double t = 0.0;
+    int rg = 0;  // the pixel's region (0: none)
+    if (valid) {
         const int x = (int)(i % h.W), y = (int)(i / h.W);
         const WinStats w = win_stats(h, P, hi, lo, x, y, max(radius[h.pix_off + i], 0));
-        const double t = pixel_term(w);
+        t = pixel_term(w);
         if (terms) terms[h.pix_off + i] = t;
-        atomicAdd(&s_sum[R], t);
-        atomicAdd(&s_cnt[R], 1.0);
         if (region) {
             const int r = region[h.pix_off + i];
-            if (r >= 1 && r <= R) {
-                atomicAdd(&s_sum[r - 1], t);
-                atomicAdd(&s_cnt[r - 1], 1.0);
+            rg = r >= 1 && r <= R ? r : 0;
+        }
+        if (GRAD && (grad_region == 0 || rg == grad_region)) {
+            const double n = (double)w.n;
+            const int64_t W1 = h.W + 1;
+            const int64_t c00 = (int64_t)w.y0 * W1 + w.x0, c10 = (int64_t)w.y0 * W1 + w.x1 + 1;
+            const int64_t c01 = (int64_t)(w.y1 + 1) * W1 + w.x0, c11 = (int64_t)(w.y1 + 1) * W1 + w.x1 + 1;
+            for (int ch = 0; ch < 3; ++ch) {
+                const double dm = w.mu[0][ch] - w.mu[1][ch], ds = w.sd[0][ch] - w.sd[1][ch];
+                const double B = w.sd[0][ch] > 0.0 ? 2.0 * ds / (n * w.sd[0][ch]) : 0.0;
+                const double A = 2.0 * dm / n - B * w.mu[0][ch];
+                for (int q = 0; q < 2; ++q) {
+                    const double val = q ? B : A;
+                    double *pl = D + (int64_t)(ch * 2 + q) * P + h.pad_off;
+                    atomicAdd(pl + c00, val);
+                    atomicAdd(pl + c10, -val);
+                    atomicAdd(pl + c01, -val);
+                    atomicAdd(pl + c11, val);
+                }
             }
         }
+    }
+    // the whole view
+    const uint64_t vm = ballot64(valid);
+    const double tv = wave_sum_d(t);
+    if (lane == 0 && vm) {
+        atomicAdd(&s_sum[R], tv);
+        atomicAdd(&s_cnt[R], (double)__popcll(vm));
+    }
+    // each region present in the wave
+    uint64_t left = ballot64(rg != 0);
+    while (left) {
+        const int leader = __ffsll((unsigned long long)left) - 1;
+        const int cur = __shfl(rg, leader);
+        const bool mine = rg == cur;
+        const uint64_t m = ballot64(mine);
+        const double x = wave_sum_d(mine ? t : 0.0);
+        if (lane == leader) {
+            atomicAdd(&s_sum[cur - 1], x);
+            atomicAdd(&s_cnt[cur - 1], (double)__popcll(m));
+        }
+        left &= ~m;
     }
     __syncthreads();
     if (threadIdx.x <= R && s_cnt[threadIdx.x] > 0.0) {
@@ -349,41 +408,6 @@ __global__ void __launch_bounds__(256) k_fill_f64(double *__restrict__ p, int64_
 {
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
         p[i] = 0.0;
-}
-
-// Gradient scatter: every pixel of the region adds A and B of each channel
-// at the four corners of its window in the view's difference arrays D
-// ([channel][A, B] planes of (H + 1) x (W + 1) doubles).
-__global__ void __launch_bounds__(256)
-k_hvsq_scatter(const gs_camera *__restrict__ cams, int V, int64_t P, const double *__restrict__ hi,
-               const double *__restrict__ lo, const int32_t *__restrict__ radius, const uint8_t *__restrict__ region,
-               int R, int grad_region, const double *__restrict__ counts, double *__restrict__ D)
-{
-    const HvView h = hv_view(cams, V, blockIdx.y);
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= (int64_t)h.W * h.H) return;
-    if (grad_region > 0 && (!region || region[h.pix_off + i] != grad_region)) return;
-    const double N = counts[(int64_t)h.v * (R + 1) + (grad_region > 0 ? grad_region - 1 : R)];
-    if (!(N > 0.0)) return;
-    const int x = (int)(i % h.W), y = (int)(i / h.W);
-    const WinStats w = win_stats(h, P, hi, lo, x, y, max(radius[h.pix_off + i], 0));
-    const double k = 1.0 / (3.0 * N), n = (double)w.n;
-    const int64_t W1 = h.W + 1;
-    const int64_t c00 = (int64_t)w.y0 * W1 + w.x0, c10 = (int64_t)w.y0 * W1 + w.x1 + 1;
-    const int64_t c01 = (int64_t)(w.y1 + 1) * W1 + w.x0, c11 = (int64_t)(w.y1 + 1) * W1 + w.x1 + 1;
-    for (int ch = 0; ch < 3; ++ch) {
-        const double dm = w.mu[0][ch] - w.mu[1][ch], ds = w.sd[0][ch] - w.sd[1][ch];
-        const double B = w.sd[0][ch] > 0.0 ? k * 2.0 * ds / (n * w.sd[0][ch]) : 0.0;
-        const double A = k * 2.0 * dm / n - B * w.mu[0][ch];
-        for (int q = 0; q < 2; ++q) {
-            const double val = q ? B : A;
-            double *pl = D + (int64_t)(ch * 2 + q) * P + h.pad_off;
-            atomicAdd(pl + c00, val);
-            atomicAdd(pl + c10, -val);
-            atomicAdd(pl + c01, -val);
-            atomicAdd(pl + c11, val);
-        }
-    }
 }
 
 // In-place inclusive prefix of the difference arrays along rows (block per
@@ -483,17 +507,21 @@ k_hvsq_prefix_cols(const gs_camera *__restrict__ cams, int V, int64_t P, double 
 // dL/da = G_A + a G_B per pixel and channel (float).
 __global__ void __launch_bounds__(256)
 k_hvsq_grad(const gs_camera *__restrict__ cams, int V, int64_t P, const double *__restrict__ D,
-            const float *__restrict__ img_a, float *__restrict__ dL_da)
+            const float *__restrict__ img_a, const double *__restrict__ counts, int R, int grad_region,
+            float *__restrict__ dL_da)
 {
     const HvView h = hv_view(cams, V, blockIdx.y);
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= (int64_t)h.W * h.H) return;
+    // the factor 1 / (3 N) of the view's region, left out of the scatter
+    const double N = counts[(int64_t)h.v * (R + 1) + (grad_region > 0 ? grad_region - 1 : R)];
+    const double k = N > 0.0 ? 1.0 / (3.0 * N) : 0.0;
     const int x = (int)(i % h.W), y = (int)(i / h.W);
     const int64_t q = h.pad_off + (int64_t)y * (h.W + 1) + x;
     for (int ch = 0; ch < 3; ++ch) {
         const int64_t px = 3 * h.pix_off + (int64_t)ch * h.W * h.H + i;
         const double g = D[(int64_t)(ch * 2) * P + q] + (double)img_a[px] * D[(int64_t)(ch * 2 + 1) * P + q];
-        dL_da[px] = (float)g;
+        dL_da[px] = (float)(k * g);
     }
 }
 
@@ -551,18 +579,21 @@ hipError_t launch_hvsq(const gs_camera *cams_host, const gs_camera *cams_dev, in
     hipLaunchKernelGGL(k_hvsq_sat_cols, dim3((unsigned)((cols + 255) / 256), PLANES), dim3(256), 0, st, cams_dev, V,
                        P, hi, lo);
     const dim3 pgrid((unsigned)((maxpx + 255) / 256), V);
-    hipLaunchKernelGGL(k_hvsq_terms, pgrid, dim3(256), 0, st, cams_dev, V, P, hi, lo, radius, region, R, sums, counts,
-                       terms);
-    if (grad_region >= 0 && dL_da) {
+    const bool grad = grad_region >= 0 && dL_da;
+    if (grad) {
         const int64_t nD = 6 * P;
         const int64_t fb = (nD + 255) / 256 < 8192 ? (nD + 255) / 256 : 8192;
         hipLaunchKernelGGL(k_fill_f64, dim3((unsigned)fb), dim3(256), 0, st, D, nD);
-        hipLaunchKernelGGL(k_hvsq_scatter, pgrid, dim3(256), 0, st, cams_dev, V, P, hi, lo, radius, region, R,
-                           grad_region, counts, D);
+        hipLaunchKernelGGL(k_hvsq_terms<true>, pgrid, dim3(256), 0, st, cams_dev, V, P, hi, lo, radius, region, R,
+                           sums, counts, terms, grad_region, D);
         hipLaunchKernelGGL(k_hvsq_prefix_rows, dim3((unsigned)rows, 6), dim3(ROW_THREADS), 0, st, cams_dev, V, P, D);
         hipLaunchKernelGGL(k_hvsq_prefix_cols, dim3((unsigned)((colsD + 255) / 256), 6), dim3(256), 0, st, cams_dev,
                            V, P, D);
-        hipLaunchKernelGGL(k_hvsq_grad, pgrid, dim3(256), 0, st, cams_dev, V, P, D, img_a, dL_da);
+        hipLaunchKernelGGL(k_hvsq_grad, pgrid, dim3(256), 0, st, cams_dev, V, P, D, img_a, counts, R, grad_region,
+                           dL_da);
+    } else {
+        hipLaunchKernelGGL(k_hvsq_terms<false>, pgrid, dim3(256), 0, st, cams_dev, V, P, hi, lo, radius, region, R,
+                           sums, counts, terms, -1, nullptr);
     }
     return hipGetLastError();
 }
