@@ -184,7 +184,10 @@ size_t gs_workspace_bytes(gs_ctx *ctx, const gs_camera *cams_host, int n_views, 
  * field of view); colour max(0, sum_k sh_k Y_k(dir) + 1/2) with Y the real
  * orthonormal SH basis of the unit direction from the camera centre to mu.
  * lvl_rgba (device, nullable) [n_views][n][n_levels][4]: per-level colour
- * and opacity (rgb, opacity) when the scene has n_levels > 0. */
+ * and opacity (rgb, opacity) when the scene has n_levels > 0.  A point has no
+ * version at the levels above its quality bound (Section 4.2): where the
+ * scene gives qbound, level t's opacity is 0 for the points with
+ * qbound < t. */
 int gs_project(gs_ctx *ctx, const gs_scene *scene, const gs_camera *cams_host, const gs_camera *cams_dev,
                int n_views, int tile_size, gs_splat *splats, float *lvl_rgba, void *stream);
 
@@ -278,7 +281,9 @@ int gs_fovea_prep(gs_ctx *ctx, const gs_camera *cams_host, const gs_camera *cams
  * the superset of its other levels).  Each pixel composites level lo and, if its
  * weight is non-zero, level lo + 1; level t uses only points with
  * qbound >= t and their level-t colour and opacity (lvl_rgba from
- * gs_project); output (1 - w) I_lo + w I_(lo+1).  Same cut-offs as
+ * gs_project of a scene with these quality bounds: the filter relies on its
+ * zero opacity above each point's bound, qbound is read only where a pixel
+ * block spans more than two levels); output (1 - w) I_lo + w I_(lo+1).  Same cut-offs as
  * gs_rasterize_fwd, applied per level; stats as in gs_rasterize_fwd
  * (blended pairs count each level's blend).  final_T2 (float [n_pixels][2])
  * and n_contrib2 (uint32 [n_pixels][2]), both nullable and given together,

@@ -102,6 +102,12 @@ def project(scene, cam, levels: bool = False) -> dict:
                      _p(out["depth"]), _p(out["opacity"]), _p(out["color"]), _p(out["radius"]),
                      _p(out["visible"]), ctypes.c_int(L), _p(lvl_logits if L else None),
                      _p(lvl_dc if L else None), _p(lo), _p(lc))
+    if L:
+        # Section 4.2: a point has a version only at the levels t <= m_i (its
+        # quality bound); at the levels above, its opacity is zero
+        qb = np.asarray(scene.qbound).astype(np.int64)
+        for t in range(1, L + 1):
+            lo[t - 1][qb < t] = 0.0
     return out
 
 

@@ -91,8 +91,9 @@ __global__ void __launch_bounds__(256)
 k_project(const float *__restrict__ means, const float *__restrict__ log_scales,
           const float *__restrict__ quats, const float *__restrict__ logits,
           const float *__restrict__ sh, const float *__restrict__ lvl_logits,
-          const float *__restrict__ lvl_dc, int L, const gs_camera *__restrict__ cams, int V,
-          int T, int n, gs_splat *__restrict__ out, float4 *__restrict__ lvl_out)
+          const float *__restrict__ lvl_dc, int L, const uint8_t *__restrict__ qbound,
+          const gs_camera *__restrict__ cams, int V, int T, int n, gs_splat *__restrict__ out,
+          float4 *__restrict__ lvl_out)
 {
     constexpr int K = (DEG + 1) * (DEG + 1);
     int i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -129,9 +130,12 @@ k_project(const float *__restrict__ means, const float *__restrict__ log_scales,
                 for (int ch = 0; ch < 3; ++ch) rdc[t][ch] = hd ? lvl_dc[tl * 3 + ch] : 0.f;
             }
         }
+        // a point has no version at the levels above its quality bound
+        // (Section 4.2): there its level opacity is zero
+        const int qm = qbound ? (int)qbound[i] : 255;
 #pragma unroll
         for (int t = 0; t < 4; ++t) {
-            lvl_op[t] = (hl && t < L) ? sigmoidf(raw[t]) : opacity;
+            lvl_op[t] = t + 1 > qm ? 0.0f : ((hl && t < L) ? sigmoidf(raw[t]) : opacity);
 #pragma unroll
             for (int ch = 0; ch < 3; ++ch) lvl_dcv[t][ch] = (hd && t < L) ? rdc[t][ch] : coef[ch];
         }
@@ -240,7 +244,8 @@ k_project_bwd(const float *__restrict__ means, const float *__restrict__ log_sca
               float *__restrict__ g_means, float *__restrict__ g_ls, float *__restrict__ g_q,
               float *__restrict__ g_logit, float *__restrict__ g_sh, int acc,
               const float *__restrict__ lvl_logits, const float *__restrict__ lvl_dc, int L,
-              const float4 *__restrict__ lvl_g, float *__restrict__ g_lvl_logit, float *__restrict__ g_lvl_dc)
+              const uint8_t *__restrict__ qbound, const float4 *__restrict__ lvl_g,
+              float *__restrict__ g_lvl_logit, float *__restrict__ g_lvl_dc)
 {
     constexpr int K = (DEG + 1) * (DEG + 1);
     int i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -268,6 +273,7 @@ k_project_bwd(const float *__restrict__ means, const float *__restrict__ log_sca
     load_sh<DEG>(sh, i, coef);
     float opacity = sigmoidf(logits[i]);
     // level versions (LEVELS only)
+    const int qm = (LEVELS && qbound) ? (int)qbound[i] : 255;
     constexpr int ML = LEVELS ? 4 : 1;
     float lvl_op[ML], lvl_dcv[ML][3], g_lop[ML], g_ldc[ML][3];
 #pragma unroll
@@ -375,7 +381,7 @@ k_project_bwd(const float *__restrict__ means, const float *__restrict__ log_sca
         } else {
 #pragma unroll
             for (int t = 0; t < ML; ++t)
-                if (t < L) {
+                if (t < L && t + 1 <= qm) {  // zero opacity above the quality bound
                     const float d = lg[t].w * lvl_op[t] * (1.0f - lvl_op[t]);
                     if (lvl_logits)
                         g_lop[t] += d;
@@ -591,11 +597,11 @@ hipError_t launch_project(const gs_scene &sc, const gs_camera *cams_dev, int V, 
     if (lv)                                                                                            \
         hipLaunchKernelGGL((k_project<DEG, true>), grid, block, 0, st, sc.means, sc.log_scales,       \
                            sc.quats, sc.opacity_logits, sc.sh, sc.lvl_opacity_logits, sc.lvl_sh_dc,  \
-                           L, cams_dev, V, T, n, out, lo);                                             \
+                           L, sc.qbound, cams_dev, V, T, n, out, lo);                                  \
     else                                                                                               \
         hipLaunchKernelGGL((k_project<DEG, false>), grid, block, 0, st, sc.means, sc.log_scales,      \
-                           sc.quats, sc.opacity_logits, sc.sh, nullptr, nullptr, 0, cams_dev, V, T,   \
-                           n, out, nullptr);
+                           sc.quats, sc.opacity_logits, sc.sh, nullptr, nullptr, 0, nullptr, cams_dev, \
+                           V, T, n, out, nullptr);
     switch (sc.sh_degree) {
     case 0: GS_PROJ(0); break;
     case 1: GS_PROJ(1); break;
@@ -621,12 +627,12 @@ hipError_t launch_project_bwd(const gs_scene &sc, const gs_camera *cams_dev, int
         hipLaunchKernelGGL((k_project_bwd<DEG, true>), grid, block, 0, st, sc.means, sc.log_scales,   \
                            sc.quats, sc.opacity_logits, sc.sh, cams_dev, V, n, splats, grads, g_means, \
                            g_ls, g_q, g_logit, g_sh, accumulate, sc.lvl_opacity_logits, sc.lvl_sh_dc, L, \
-                           lg, g_lvl_logit, g_lvl_dc);                                                \
+                           sc.qbound, lg, g_lvl_logit, g_lvl_dc);                                     \
     else                                                                                               \
         hipLaunchKernelGGL((k_project_bwd<DEG, false>), grid, block, 0, st, sc.means, sc.log_scales,  \
                            sc.quats, sc.opacity_logits, sc.sh, cams_dev, V, n, splats, grads, g_means, \
                            g_ls, g_q, g_logit, g_sh, accumulate, nullptr, nullptr, 0, nullptr, nullptr, \
-                           nullptr);
+                           nullptr, nullptr);
     switch (sc.sh_degree) {
     case 0: GS_PB(0); break;
     case 1: GS_PB(1); break;

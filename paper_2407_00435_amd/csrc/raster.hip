@@ -61,6 +61,40 @@ __device__ __forceinline__ float pair_e2(const float4 &a, const float4 &b, float
     return fmaf(u, dx, w);
 }
 
+// The same falloff exponent qa dx^2 + qb dx dy + qc dy^2 expanded about the
+// centre (cx, cy) of a wave's 8 x 8 block.  With (mu, mv) the mean's offset
+// from the centre and (u, v) the pixel's,
+//   e = F + u (D + qa u + qb v) + v (E + qc v),
+//   D = -(2 qa mu + qb mv),  E = -(2 qc mv + qb mu),
+//   F = qa mu^2 + qb mu mv + qc mv^2,
+// five FMAs per pair instead of the two differences and five products and
+// sums of the direct form (the mean is folded into F, D, E once per splat).
+// The cancellation between the terms is the one the direct form has between
+// qa dx^2, qb dx dy and qc dy^2: both lose accuracy with the conic's
+// condition, not with the expansion.  Explicit fmaf throughout, so that
+// every kernel that evaluates a pair this way rounds identically.
+struct Quad {
+    float F, D, E;
+};
+
+__device__ __forceinline__ Quad quad_about(float mx, float my, float qa, float qb, float qc, float cx, float cy)
+{
+    const float mu = mx - cx, mv = my - cy;
+    Quad q;
+    q.D = -fmaf(qb, mv, (2.0f * qa) * mu);
+    q.E = -fmaf(qb, mu, (2.0f * qc) * mv);
+    q.F = fmaf(mu, fmaf(qa, mu, qb * mv), (qc * mv) * mv);
+    return q;
+}
+
+__device__ __forceinline__ float quad_eval(float F, float D, float E, float qa, float qb, float qc, float u,
+                                           float v)
+{
+    const float t1 = fmaf(qa, u, fmaf(qb, v, D));
+    const float t2 = fmaf(v, fmaf(qc, v, E), F);
+    return fmaf(u, t1, t2);
+}
+
 // Conservative test: can the splat (conic A, B, C; mean m; extent q <= qmax)
 // reach any point of the pixel rectangle [x0, x1] x [y0, y1]?  Minimises
 // q(d) = A dx^2 + 2 B dx dy + C dy^2 over the rectangle (continuous), which
@@ -304,9 +338,11 @@ k_raster_fwd(const gs_splat *__restrict__ splats, int n, const gs_camera *__rest
 }
 
 // ---------------------------------------------------------------------------
-// Foveated compositing.  Record: geometry (mean, qa, qb | qc, point index,
-// quality bound, list position) and (r, g, b, opacity) of the two levels the
-// wave's pixels use (wave_lo and wave_lo + 1).  Each pixel runs the
+// Foveated compositing.  Record: the falloff about the wave's block centre
+// (F, D, E, qa | qb, qc, point index, list position) and (r, g, b, opacity)
+// of the two levels the wave's pixels use (wave_lo and wave_lo + 1); a wave
+// that reads its levels from memory keeps the quality bound in the first
+// level slot instead.  Each pixel runs the
 // accumulator of its lower level and, if blended, of the next one; level t
 // takes a splat only if its quality bound is >= t and uses that level's
 // opacity and colour.  An 8 x 8 block needs more than two levels only when
@@ -327,6 +363,7 @@ struct FovPix {
     bool two;        // the pixel blends two levels
     int wave_lo;     // lowest level any pixel of the wave needs
     bool any_two;    // some pixel of the wave blends two levels
+    bool one;        // every pixel of the wave uses level wave_lo alone
     bool wide;       // the wave's pixels need more than two levels
 };
 
@@ -347,6 +384,7 @@ __device__ __forceinline__ FovPix fov_pix(const WaveCtx &w, const uint8_t *__res
     for (int off = 32; off > 0; off >>= 1) wh = max(wh, __shfl_xor(wh, off));
     f.wave_lo = wl;
     f.any_two = ballot64(f.two) != 0;
+    f.one = wh == wl;
     f.wide = wh - wl >= 2;
     return f;
 }
@@ -368,8 +406,11 @@ __device__ __forceinline__ FovState fov_init(bool inside, bool two)
     return s;
 }
 
-// One lane's share of a chunk's staging loads: the point's geometry, quality
-// bound and (two-level waves) the two level records the wave uses.
+// One lane's share of a chunk's staging loads: the point's geometry and the
+// level records the wave uses (one or two).  A level above the point's
+// quality bound has zero opacity in the level records, which no cull or
+// alpha test passes, so the quality bound itself is loaded only by a wave
+// that reads its levels from memory.
 struct FovFetch {
     uint32_t id;
     int m;
@@ -380,7 +421,7 @@ struct FovFetch {
 template <bool WIDE>
 __device__ __forceinline__ FovFetch fov_fetch(const gs_splat *__restrict__ splats, const float4 *__restrict__ lvl,
                                               const uint8_t *__restrict__ qbound, int L, int64_t vbase, uint32_t id,
-                                              bool ok, int wave_lo)
+                                              bool ok, int wave_lo, bool one)
 {
     FovFetch r;
     r.id = id;
@@ -388,16 +429,17 @@ __device__ __forceinline__ FovFetch fov_fetch(const gs_splat *__restrict__ splat
     r.s0 = r.l0 = r.l1 = make_float4(0.f, 0.f, 0.f, 0.f);
     r.c = 0.0f;
     if (ok) {
-        r.m = qbound[id];
         // only the words the compositor uses: a wider load would hold
         // registers that the compiler reuses at once, waiting for the load
         const float4 *s4 = reinterpret_cast<const float4 *>(splats + vbase + id);
         r.s0 = s4[0];
         r.c = reinterpret_cast<const float *>(s4 + 1)[0];
-        if (!WIDE) {
+        if (WIDE) {
+            r.m = qbound[id];
+        } else {
             const float4 *lp = lvl + (vbase + id) * L;
             r.l0 = lp[min(max(wave_lo - 1, 0), L - 1)];
-            r.l1 = lp[min(wave_lo, L - 1)];
+            if (!one) r.l1 = lp[min(wave_lo, L - 1)];
         }
     }
     return r;
@@ -420,11 +462,14 @@ __device__ __forceinline__ void fov_walk_impl(const gs_splat *__restrict__ splat
     // in bounds whenever the run is not empty -- so that waiting for the
     // records never has to wait for it)
     uint32_t id_next = b < e ? vals[min(b + lane, e - 1)] : 0u;
+    // the block centre, and the pixel's offset from it (exact in float)
+    const float cx = w.rx0 + 3.5f, cy = w.ry0 + 3.5f;
+    const float pu = (float)(lane & 7) - 3.5f, pv = (float)(lane >> 3) - 3.5f;
     int carry = 0;  // records carried over from the chunk before, at srec[0, carry)
     for (uint32_t c0 = b; c0 < e; c0 += 64) {
         if (ballot64(!(s.done_a && s.done_b)) == 0) break;
         const uint32_t idx = c0 + lane;
-        const FovFetch cur = fov_fetch<WIDE>(splats, lvl, qbound, L, vbase, id_next, idx < e, f.wave_lo);
+        const FovFetch cur = fov_fetch<WIDE>(splats, lvl, qbound, L, vbase, id_next, idx < e, f.wave_lo, f.one);
         id_next = vals[min(c0 + 64 + lane, e - 1)];
         bool keep = false;
         // the record is fully defined on every lane before the cull decision
@@ -435,22 +480,23 @@ __device__ __forceinline__ void fov_walk_impl(const gs_splat *__restrict__ splat
             const int m = cur.m;
             const float4 s0 = cur.s0;
             const float c = cur.c;
-            rec.a = make_float4(s0.x, s0.y, NEG_HALF_LOG2E * s0.z, -GS_LOG2E * s0.w);
-            rec.b = make_float4(NEG_HALF_LOG2E * c, __uint_as_float(id), __int_as_float(m),
-                                __uint_as_float(idx - w.start + 1));
+            const float qa = NEG_HALF_LOG2E * s0.z, qb = -GS_LOG2E * s0.w, qc = NEG_HALF_LOG2E * c;
+            const Quad q = quad_about(s0.x, s0.y, qa, qb, qc, cx, cy);
+            rec.a = make_float4(q.F, q.D, q.E, qa);
+            rec.b = make_float4(qb, qc, __uint_as_float(id), __uint_as_float(idx - w.start + 1));
             float qcull = 9.001f;
+            if (WIDE) rec.lv[0].x = __int_as_float(m);
             if (!WIDE) {
+                // (a level above the splat's quality bound has zero opacity:
+                // no alpha test passes, so the loop needs no level test)
                 rec.lv[0] = cur.l0;
                 rec.lv[1] = cur.l1;
-                // level wave_lo + 1 above the splat's quality bound: zero
-                // opacity, which no alpha test passes (so the loop needs no
-                // level test)
-                if (m < f.wave_lo + 1) rec.lv[1].w = 0.0f;
                 // no pixel of the wave blends the splat where opacity * G
-                // stays below the alpha floor
+                // stays below the alpha floor (at every level the wave uses;
+                // a splat filtered out of them has no reach at all)
                 qcull = qmax_of(fmaxf(rec.lv[0].w, rec.lv[1].w));
             }
-            keep = m >= f.wave_lo &&
+            keep = (!WIDE || m >= f.wave_lo) &&
                    reaches_rect(s0.x, s0.y, s0.z, s0.w, c, qcull, w.rx0, w.rx1, w.ry0, w.ry1);
         }
         const uint64_t msk = ballot64(keep);
@@ -459,7 +505,7 @@ __device__ __forceinline__ void fov_walk_impl(const gs_splat *__restrict__ splat
         // loop below runs in groups of 4 with one exit test per group, and
         // the records past the last full group wait for the next chunk --
         // after the last chunk they are padded to a group with null records
-        // (opacity 0, level -1: no pixel uses them)
+        // (opacity 0, quality bound -1: no pixel uses them)
         if (keep) srec[carry + __popcll(msk & lanemask_lt())] = rec;
         const int total = carry + cnt;
         const bool last_chunk = c0 + 64 >= e;
@@ -467,8 +513,8 @@ __device__ __forceinline__ void fov_walk_impl(const gs_splat *__restrict__ splat
         const int upto = last_chunk ? (total + 3) & ~3 : full;
         if (last_chunk && lane < 4 && full + lane >= total && full + lane < upto) {
             FovRec z;
-            z.a = z.lv[0] = z.lv[1] = make_float4(0.f, 0.f, 0.f, 0.f);
-            z.b = make_float4(0.f, 0.f, __int_as_float(-1), 0.f);
+            z.a = z.b = z.lv[1] = make_float4(0.f, 0.f, 0.f, 0.f);
+            z.lv[0] = make_float4(WIDE ? __int_as_float(-1) : 0.f, 0.f, 0.f, 0.f);
             srec[full + lane] = z;
         }
         wave_lds_sync();
@@ -482,17 +528,18 @@ __device__ __forceinline__ void fov_walk_impl(const gs_splat *__restrict__ splat
                 // branch-free: every lane evaluates, selects take the decisions
                 const float4 a = srec[j].a, bb = srec[j].b;
                 if (STATS) st[1] += (j >= total || (s.done_a && s.done_b)) ? 0.0f : 1.0f;
-                const float p2 = pair_e2(a, make_float4(bb.x, 0.f, 0.f, 0.f), w.fpx, w.fpy);  // falloff only
-                const int m = __float_as_int(bb.z);
+                const float p2 = quad_eval(a.x, a.y, a.z, a.w, bb.x, bb.y, pu, pv);  // falloff only
                 const float G = fast_exp2(p2);
                 const bool incl = p2 >= EXTENT_LOG2;
                 float4 lva, lvb;
+                int m = 0;
                 if (!WIDE) {
                     // 0 or 1 inside the image; pixels outside (level 1, done) are clamped
                     lva = srec[j].lv[min(max(f.lo - f.wave_lo, 0), 1)];
                     lvb = srec[j].lv[1];
                 } else {
-                    const float4 *lp = lvl + (vbase + __float_as_uint(bb.y)) * L;
+                    m = __float_as_int(srec[j].lv[0].x);
+                    const float4 *lp = lvl + (vbase + __float_as_uint(bb.z)) * L;
                     lva = lp[f.lo - 1];
                     lvb = lp[f.lo < L ? f.lo : L - 1];
                 }
@@ -1496,6 +1543,8 @@ k_raster_fov_bwd(const gs_splat *__restrict__ splats, const float4 *__restrict__
     const WaveCtx w = wave_ctx<T>(cams, V, blockIdx.x, wave, lane, ranges);
     const FovPix f = fov_pix(w, pix_level, pix_weight);
     const int64_t vbase = (int64_t)w.vi.v * n;
+    const float cx = w.rx0 + 3.5f, cy = w.ry0 + 3.5f;
+    const float pu = (float)(lane & 7) - 3.5f, pv = (float)(lane >> 3) - 3.5f;
 
     if (threadIdx.x == 0) s_maxnc = 0;
     for (int q = threadIdx.x; q < NG * 64; q += T * T) (&s_grad[0][0])[q] = 0.f;
@@ -1569,7 +1618,10 @@ k_raster_fov_bwd(const gs_splat *__restrict__ splats, const float4 *__restrict__
                 const float4 a = s_rec[wave][j].a, b = s_rec[wave][j].b;
                 const uint32_t ppos = __float_as_uint(b.w);
                 const int m = __float_as_int(b.z);
-                const float p2 = pair_e2(a, b, w.fpx, w.fpy);
+                // the forward's falloff, bit for bit: the same expansion
+                // about the block centre
+                const Quad qd = quad_about(a.x, a.y, a.z, a.w, b.x, cx, cy);
+                const float p2 = quad_eval(qd.F, qd.D, qd.E, a.z, a.w, b.x, pu, pv);
                 const float G = fast_exp2(p2);
                 const bool incl = p2 >= EXTENT_LOG2;
                 const float4 raw = s_rec[wave][j].raw;

@@ -9,6 +9,8 @@ Section 4.2 nested subsets and multi-versioning, Section 6 ring layout).
 - All quality bounds at the top level with no per-level versions reduces to
   the plain render; a single level reduces to a plain render of the subset
   {i : m_i >= t}.
+- A point has no version above its quality bound (Section 4.2): its level
+  opacity there is zero, elsewhere the logistic of its level logit.
 """
 import math
 
@@ -100,6 +102,18 @@ def test_single_level_is_plain_render_of_subset(oracle_lib):
         sub["color"] = pr["lvl_color"][t - 1][keep]
         plain = oracle_lib.composite(sub, 48, 32)
         np.testing.assert_allclose(fr["rgb"], plain["rgb"], rtol=1e-12, atol=1e-14)
+
+
+def test_level_opacity_is_zero_above_the_quality_bound(oracle_lib):
+    sc, cam, _ = _fr_scene(24)
+    pr = oracle_lib.project(sc, cam, levels=True)
+    logits = np.asarray(sc.lvl_opacity_logits, np.float64)
+    qb = np.asarray(sc.qbound).astype(np.int64)
+    vis = pr["radius"] > 0
+    assert vis.sum() > 50 and len(set(qb[vis].tolist())) >= 3
+    for t in range(1, 5):
+        want = np.where(qb >= t, 1.0 / (1.0 + np.exp(-logits[t - 1])), 0.0)
+        np.testing.assert_allclose(pr["lvl_opacity"][t - 1][vis], want[vis], rtol=1e-13, atol=0.0)
 
 
 def test_blend_is_weighted_sum_of_levels(oracle_lib):

@@ -160,7 +160,10 @@ def test_level_versions_replace_dc_and_opacity(oracle_lib):
         delta = (sc.lvl_sh_dc[t].astype(np.float64) - sc.sh[:, 0, :]) * 0.28209479177387814
         ok = (raw > 0) & (pr["lvl_color"][t] > 0)
         np.testing.assert_allclose(pr["lvl_color"][t][ok], (raw + delta)[ok], rtol=1e-9, atol=1e-12)
+        # the logistic of the level logit where the point has a level-(t + 1)
+        # version (quality bound >= t + 1, Section 4.2), zero above its bound
         op = 1.0 / (1.0 + np.exp(-sc.lvl_opacity_logits[t].astype(np.float64)))
+        op = np.where(np.asarray(sc.qbound) >= t + 1, op, 0.0)
         np.testing.assert_allclose(pr["lvl_opacity"][t], op, rtol=1e-13)
 
 
