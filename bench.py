@@ -44,11 +44,11 @@ FLOPS_PER_BLEND_BWD = 44
 # averaged over the dispatches), each scaled by the ratio of known bytes to
 # the same counter on a plain device copy (bench.py --copy-probe).  Valid
 # only for the kernel sources they were taken on (sha256 below).
-TRAFFIC = {"kernel": "k_raster_fov", "fetch_kib": 480851.2, "write_kib": 57409.3, "fetch_scale": 2.0,
-           "write_scale": 1.0, "sha256": "b5067fc528e6bb4f9ed7b4ba312babb1d164889a3b00b9b956bb73f656778da9"}
+TRAFFIC = {"kernel": "k_raster_fov", "fetch_kib": 273031.1, "write_kib": 54881.7, "fetch_scale": 2.0,
+           "write_scale": 1.0, "sha256": "2b2482baf6237915e126680caaa02af493d3d62fd02ee37101220c41640cc2d7"}
 # The same for the compositing reverse on the 1280x720 1M-Gaussian frame.
-TRAFFIC_BWD = {"kernel": "k_raster_bwd", "fetch_kib": 55544.4, "write_kib": 29395.7, "fetch_scale": 2.0,
-               "write_scale": 1.0, "sha256": "b5067fc528e6bb4f9ed7b4ba312babb1d164889a3b00b9b956bb73f656778da9"}
+TRAFFIC_BWD = {"kernel": "k_raster_bwd", "fetch_kib": 55524.5, "write_kib": 29395.7, "fetch_scale": 2.0,
+               "write_scale": 1.0, "sha256": "2b2482baf6237915e126680caaa02af493d3d62fd02ee37101220c41640cc2d7"}
 
 def kernel_sha():
     import hashlib
