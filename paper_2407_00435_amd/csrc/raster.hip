@@ -633,12 +633,15 @@ __device__ __forceinline__ void fov_finish(const WaveCtx &w, const FovPix &f, co
     img[2 * plane] = ba;
 }
 
-// Seven waves per SIMD (at most 72 registers, no spills) composite faster than
-// the six the compiler's own choice of 73 allows: 0.484 -> 0.463 ms on the
-// stereo 1080p frame.  The statistics and reverse-state instantiations keep
-// the compiler's choice.
+// Eight waves per SIMD (at most 64 registers) composite faster than the six
+// the compiler's own choice of 73 allows: 0.484 -> 0.463 ms at seven waves,
+// 0.451 ms at eight, on the stereo 1080p frame.  At eight, one 64-bit value
+// is kept in scratch across the chunk loop (and one record per chunk in the
+// rare walk that reads levels from memory); the record loop itself spills
+// nothing.  The statistics and reverse-state instantiations keep the
+// compiler's choice.
 template <int T, bool STATS, bool KEEP>
-__global__ void __launch_bounds__(T *T) __attribute__((amdgpu_waves_per_eu(STATS || KEEP ? 1 : 7)))
+__global__ void __launch_bounds__(T *T) __attribute__((amdgpu_waves_per_eu(STATS || KEEP ? 1 : 8)))
 k_raster_fov(const gs_splat *__restrict__ splats, const float4 *__restrict__ lvl, int n,
              const uint8_t *__restrict__ qbound, int L, const gs_camera *__restrict__ cams, int V,
              const uint32_t *__restrict__ vals, const uint32_t *__restrict__ ranges,
