@@ -109,6 +109,28 @@ k_bin_setup(const gs_camera *__restrict__ cams, int V, int T, int64_t *__restric
     }
 }
 
+// Class of every (super-tile, level): 0 if the level keeps none of the
+// super-tile's tiles, 1 if it keeps all of them, 2 otherwise.  One wave per
+// super-tile s, lane = tile.
+__device__ __forceinline__ void st_class(const int64_t *__restrict__ vtab, const int4 *__restrict__ stab, int V,
+                                         int64_t s, int L, const uint8_t *__restrict__ tl,
+                                         uint8_t *__restrict__ cls)
+{
+    const int lane = threadIdx.x & 63;
+    int v = 0;
+    while (v + 1 < V && stab[v + 1].x <= (int)s) ++v;
+    const int4 sb = stab[v];
+    const int sl = (int)s - sb.x, sy = sl / sb.y, sx = sl - sy * sb.y;
+    const int tx = sx * ST + lane % ST, ty = sy * ST + lane / ST;
+    const bool valid = lane < TST && tx < sb.z && ty < sb.w;
+    const uint32_t lvl = valid ? tl[2 * (vtab[2 * v] + (int64_t)ty * sb.z + tx)] : 255u;
+    const int nv = __popcll(ballot64(valid));
+    for (int m = 1; m <= L; ++m) {
+        const int nk = __popcll(ballot64(valid && lvl <= (uint32_t)m));
+        if (lane == 0) cls[s * 4 + m - 1] = (uint8_t)(nk == 0 ? 0 : (nk == nv ? 1 : 2));
+    }
+}
+
 // Summed-area table of [lower level of tile <= m] over each view's tile grid,
 // one table per level m = 1..L: sat[(m-1) * n_tiles + g] counts the tiles
 // (x', y') <= (x, y) of g's view.  One workgroup per (view, level), built in
@@ -116,13 +138,21 @@ k_bin_setup(const gs_camera *__restrict__ cams, int V, int T, int64_t *__restric
 // view's grid fits, else in place in memory: row sums (a wave per row), then
 // column sums (a wave per column).
 // Also the bounding box of those tiles, bbox[(v * L + m - 1) * 4 +
-// {x0, y0, x1, y1}] (x0 > x1 when there are none).
+// {x0, y0, x1, y1}] (x0 > x1 when there are none).  The workgroups after the
+// first V * L classify the super-tiles, 16 per workgroup (st_class).
 __global__ void __launch_bounds__(1024)
 k_level_sat(const gs_camera *__restrict__ cams, int V, int T, int L, int64_t n_tiles,
-            const uint8_t *__restrict__ tl, uint32_t *__restrict__ sat, int32_t *__restrict__ bbox, int use_lds)
+            const uint8_t *__restrict__ tl, uint32_t *__restrict__ sat, int32_t *__restrict__ bbox, int use_lds,
+            const int64_t *__restrict__ vtab, const int4 *__restrict__ stab, int64_t n_st,
+            uint8_t *__restrict__ cls)
 {
     extern __shared__ uint32_t s_sat[];
     __shared__ int s_box[4];
+    if ((int)blockIdx.x >= V * L) {
+        const int64_t st_id = (int64_t)(blockIdx.x - V * L) * 16 + (threadIdx.x >> 6);
+        if (st_id < n_st) st_class(vtab, stab, V, st_id, L, tl, cls);
+        return;
+    }
     const int v = blockIdx.x / L, m = blockIdx.x % L + 1;
     const int64_t toff = view_tile_off(cams, v, T);
     const int tx = div_up(cams[v].width, T), ty = div_up(cams[v].height, T);
@@ -489,30 +519,6 @@ k_scan_pair(uint64_t *__restrict__ key_sums, uint64_t *__restrict__ pair_sums, i
 //      start + chunk prefix + running count: the (tile, depth, view, point)
 //      order, with every key written once at its final position.
 
-// Class of every (super-tile, level): 0 if the level keeps none of the
-// super-tile's tiles, 1 if it keeps all of them, 2 otherwise.  One wave per
-// super-tile, lane = tile.
-__global__ void __launch_bounds__(256)
-k_st_class(const int64_t *__restrict__ vtab, const int4 *__restrict__ stab, int V, int64_t n_st, int L,
-           const uint8_t *__restrict__ tl, uint8_t *__restrict__ cls)
-{
-    const int lane = threadIdx.x & 63;
-    const int64_t s = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
-    if (s >= n_st) return;
-    int v = 0;
-    while (v + 1 < V && stab[v + 1].x <= (int)s) ++v;
-    const int4 sb = stab[v];
-    const int sl = (int)s - sb.x, sy = sl / sb.y, sx = sl - sy * sb.y;
-    const int tx = sx * ST + lane % ST, ty = sy * ST + lane / ST;
-    const bool valid = lane < TST && tx < sb.z && ty < sb.w;
-    const uint32_t lvl = valid ? tl[2 * (vtab[2 * v] + (int64_t)ty * sb.z + tx)] : 255u;
-    const int nv = __popcll(ballot64(valid));
-    for (int m = 1; m <= L; ++m) {
-        const int nk = __popcll(ballot64(valid && lvl <= (uint32_t)m));
-        if (lane == 0) cls[s * 4 + m - 1] = (uint8_t)(nk == 0 ? 0 : (nk == nv ? 1 : 2));
-    }
-}
-
 // What a coarse pair carries besides its entry (view * n + point): relative
 // to super-tile (sx, sy), the entry's clipped tile rectangle (3 bits per
 // bound) and min(quality bound, 4) (3 bits; the tile pass tells no higher
@@ -640,15 +646,22 @@ __device__ __forceinline__ uint32_t coarse_code(uint32_t rx, uint32_t ry, uint32
 // pairs (count, or count and mask, as coarse_code); per-block sums of key counts and
 // coarse pairs.  A block takes SCAN_THREADS * SCAN_ITEMS entries with
 // GATHER_THREADS threads, each issuing its loads for all its entries first.
+// The depth sort is done by now: the first block zeroes the sort's digit
+// counts and tickets for the super-tile sort (see k_coarse_emit).
 constexpr int GATHER_THREADS = 1024;
 constexpr int GATHER_ITEMS = SCAN_THREADS * SCAN_ITEMS / GATHER_THREADS;
 __global__ void __launch_bounds__(GATHER_THREADS)
 k_gather(const uint32_t *__restrict__ order, const uint4 *__restrict__ rec, const uint64_t *__restrict__ d_count,
          int n, const int64_t *__restrict__ vtab, const int4 *__restrict__ stab, const uint32_t *__restrict__ sat,
          const uint8_t *__restrict__ cls, int L, int64_t n_tiles, uint4 *__restrict__ rec_s,
-         uint32_t *__restrict__ cc_s, uint64_t *__restrict__ bsum_h, uint64_t *__restrict__ bsum_c)
+         uint32_t *__restrict__ cc_s, uint64_t *__restrict__ bsum_h, uint64_t *__restrict__ bsum_c,
+         uint32_t *__restrict__ sort_hist, uint32_t *__restrict__ sort_tickets)
 {
     __shared__ uint64_t s_h[GATHER_THREADS / 64], s_c[GATHER_THREADS / 64];
+    if (blockIdx.x == 0) {
+        sort_hist[threadIdx.x] = 0u;  // [4][256]: one word per thread
+        if (threadIdx.x < 4) sort_tickets[threadIdx.x] = 0u;
+    }
     const uint64_t E = *d_count;
     const int64_t base = (int64_t)blockIdx.x * (GATHER_THREADS * GATHER_ITEMS);
     uint32_t e[GATHER_ITEMS];
@@ -694,16 +707,26 @@ k_gather(const uint32_t *__restrict__ order, const uint4 *__restrict__ rec, cons
 }
 
 // 4b. coarse pairs of every depth-ordered entry at its scanned offset (from
-// the mask when there is one).
+// the mask when there is one).  The grid also zeroes the first-pass lookback
+// words of the super-tile sort for the pairs' count, counts[3] (clamped to
+// cap): ceil(count / part) * radix words.
 template <bool PACKED>
 __global__ void __launch_bounds__(GATHER_THREADS)
 k_coarse_emit(const uint4 *__restrict__ rec_s, const uint32_t *__restrict__ cc_s, const uint64_t *__restrict__ counts,
               const uint64_t *__restrict__ boff, const int64_t *__restrict__ vtab, const int4 *__restrict__ stab,
               const uint32_t *__restrict__ sat, const uint8_t *__restrict__ cls, int L, int64_t n_tiles,
-              uint32_t *__restrict__ ck, void *__restrict__ cv)
+              uint32_t *__restrict__ ck, void *__restrict__ cv, uint64_t *__restrict__ sort_status, uint64_t cap,
+              int part, int radix)
 {
     constexpr int W = GATHER_THREADS / 64;
     __shared__ uint32_t s_w[GATHER_ITEMS][W];
+    {
+        const uint64_t np = counts[3] < cap ? counts[3] : cap;
+        const uint64_t words = ((np + part - 1) / part) * (uint64_t)radix;
+        const uint64_t stride = (uint64_t)gridDim.x * GATHER_THREADS;
+        for (uint64_t i = (uint64_t)blockIdx.x * GATHER_THREADS + threadIdx.x; i < words; i += stride)
+            sort_status[i] = 0;
+    }
     const uint64_t E = counts[0];
     if (counts[1] == 0) return;  // no keys, or more than the capacity
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -1242,13 +1265,12 @@ hipError_t launch_bin_sort(const gs_splat *splats, int n, const gs_camera *cams_
     const int L = n_levels < 1 ? 1 : (n_levels > 4 ? 4 : n_levels);
     if (filt) {
         const int lds = max_view_tiles <= SAT_LDS_TILES;
-        hipLaunchKernelGGL(k_level_sat, dim3(V * L), dim3(1024), lds ? 5 * max_view_tiles + 16 : 0, st, cams_dev,
-                           V, T, L, n_tiles, tile_level, bs.sat, bs.bbox, lds);
+        const unsigned cls_blocks = (unsigned)((n_st + 15) / 16);
+        hipLaunchKernelGGL(k_level_sat, dim3(V * L + cls_blocks), dim3(1024), lds ? 5 * max_view_tiles + 16 : 0,
+                           st, cams_dev, V, T, L, n_tiles, tile_level, bs.sat, bs.bbox, lds, bs.vtab, bs.stab, n_st,
+                           bs.st_cls);
     }
     const uint32_t *sat = filt ? bs.sat : nullptr;
-    if (filt)
-        hipLaunchKernelGGL(k_st_class, dim3((unsigned)((n_st + 3) / 4)), dim3(256), 0, st, bs.vtab, bs.stab, V, n_st,
-                           L, tile_level, bs.st_cls);
     // 1-2: counts, and the stable compaction of the entries with keys (depth
     // digits counted, the total to counts[0])
     if (filt)
@@ -1264,8 +1286,10 @@ hipError_t launch_bin_sort(const gs_splat *splats, int n, const gs_camera *cams_
                                 true)) != hipSuccess)
         return err;
     // 4a: records in depth order; totals of keys (capacity rule) and coarse pairs
+    static_assert(GATHER_THREADS == 4 * 256, "k_gather zeroes the sort's digit counts with a word per thread");
     hipLaunchKernelGGL(k_gather, dim3((unsigned)nb), dim3(GATHER_THREADS), 0, st, bs.dval_a, bs.rec, bs.counts, n,
-                       bs.vtab, bs.stab, sat, bs.st_cls, L, n_tiles, bs.rec_s, bs.cc_s, bs.block_sums, bs.block_sums2);
+                       bs.vtab, bs.stab, sat, bs.st_cls, L, n_tiles, bs.rec_s, bs.cc_s, bs.block_sums, bs.block_sums2,
+                       bs.rs.hist, bs.rs.tickets);
     hipLaunchKernelGGL(k_scan_pair, dim3(1), dim3(1024), 0, st, bs.block_sums, bs.block_sums2, nb, bs.counts + 1,
                        bs.counts + 2, num_keys, bs.counts + 3, status);
     // 4b: coarse pairs with their payloads, stably sorted by super-tile
@@ -1274,20 +1298,24 @@ hipError_t launch_bin_sort(const gs_splat *splats, int n, const gs_camera *cams_
     // the pair's info rides in the sort key when the super-tile ids leave room
     const bool packed = coarse_packed && st_bits <= ST_ID_BITS;
     const bool even = radix_pass_count(st_bits, packed ? 4 : 8, bs.rs.part) % 2 == 0;
+    // the super-tile sort's digit counts and tickets were zeroed by k_gather
+    // and its first-pass lookback words are zeroed by k_coarse_emit
+    const RadixShape shape = radix_shape(bs.rs, packed ? 4 : 8, st_bits);
+    if (radix_prepare_words(bs.rs, cap, packed ? 4 : 8, st_bits) > bs.rs.status_words) return hipErrorInvalidValue;
     if (packed) {
         hipLaunchKernelGGL(k_coarse_emit<true>, dim3((unsigned)nb), dim3(GATHER_THREADS), 0, st, bs.rec_s, bs.cc_s,
                            bs.counts, bs.block_sums2, bs.vtab, bs.stab, sat, bs.st_cls, L, n_tiles, bs.tkey_a,
-                           (void *)bs.cpay_a);
+                           (void *)bs.cpay_a, bs.rs.status, cap, shape.part, shape.radix);
         if ((err = radix_sort_pairs(bs.tkey_a, reinterpret_cast<uint32_t *>(bs.cpay_a), bs.tkey_b,
                                     reinterpret_cast<uint32_t *>(bs.cpay_b), bs.counts + 3, cap, st_bits, bs.rs, st,
-                                    false)) != hipSuccess)
+                                    false, true)) != hipSuccess)
             return err;
     } else {
         hipLaunchKernelGGL(k_coarse_emit<false>, dim3((unsigned)nb), dim3(GATHER_THREADS), 0, st, bs.rec_s, bs.cc_s,
                            bs.counts, bs.block_sums2, bs.vtab, bs.stab, sat, bs.st_cls, L, n_tiles, bs.tkey_a,
-                           (void *)bs.cpay_a);
+                           (void *)bs.cpay_a, bs.rs.status, cap, shape.part, shape.radix);
         if ((err = radix_sort_pairs_v2(bs.tkey_a, bs.cpay_a, bs.tkey_b, bs.cpay_b, bs.counts + 3, cap, st_bits, bs.rs,
-                                       st)) != hipSuccess)
+                                       st, true)) != hipSuccess)
             return err;
     }
     const uint32_t *sk = even ? bs.tkey_a : bs.tkey_b;

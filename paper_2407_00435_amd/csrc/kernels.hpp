@@ -65,13 +65,26 @@ int radix_digit_bits(int bits);
 // vb).  With hist_ready (keys of more than 9 bits) the caller has called
 // radix_sort_prepare and accumulated the per-pass digit counts into rs.hist
 // ([pass][256], pass p = bits [p d, (p + 1) d) with d = radix_digit_bits(bits)).
+// With `cleared` (and not hist_ready) the caller has zeroed what
+// radix_sort_prepare would (digit counts, tickets, first-pass lookback words)
+// and the sort only counts the digits.
 hipError_t radix_sort_pairs(uint32_t *ka, uint32_t *va, uint32_t *kb, uint32_t *vb,
                             const uint64_t *d_count, uint64_t cap, int bits,
-                            const RadixScratch &rs, hipStream_t st, bool hist_ready);
+                            const RadixScratch &rs, hipStream_t st, bool hist_ready, bool cleared = false);
 
 // The same with 8-byte values (partitions of at most 8192 keys).
 hipError_t radix_sort_pairs_v2(uint32_t *ka, uint2 *va, uint32_t *kb, uint2 *vb, const uint64_t *d_count,
-                               uint64_t cap, int bits, const RadixScratch &rs, hipStream_t st);
+                               uint64_t cap, int bits, const RadixScratch &rs, hipStream_t st,
+                               bool cleared = false);
+
+// Partition size and digits of the first pass of a sort of `bits`-bit keys
+// with vbytes-byte values: its lookback words for `count` pairs are
+// ceil(count / part) * radix (what radix_prepare_words returns).
+struct RadixShape {
+    int part;
+    int radix;
+};
+RadixShape radix_shape(const RadixScratch &rs, int vbytes, int bits);
 
 // zeroes the digit counts, tickets and first-pass lookback words of a sort
 // of min(*d_count, cap) pairs with vbytes-byte values; a caller that builds

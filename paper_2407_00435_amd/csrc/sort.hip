@@ -305,11 +305,16 @@ int radix_pass_count(int bits, int vbytes, int part)
     return one_wide_pass(bits, part_for(vbytes, part)) ? 1 : radix_passes(bits);
 }
 
-uint64_t radix_prepare_words(const RadixScratch &rs, uint64_t count, int vbytes, int bits)
+RadixShape radix_shape(const RadixScratch &rs, int vbytes, int bits)
 {
     const int P = part_for(vbytes, rs.part);
-    const int R = one_wide_pass(bits, P) ? 512 : 256;
-    return ((count + P - 1) / P) * R;
+    return RadixShape{P, one_wide_pass(bits, P) ? 512 : 256};
+}
+
+uint64_t radix_prepare_words(const RadixScratch &rs, uint64_t count, int vbytes, int bits)
+{
+    const RadixShape sh = radix_shape(rs, vbytes, bits);
+    return ((count + sh.part - 1) / sh.part) * sh.radix;
 }
 
 hipError_t radix_sort_prepare(const RadixScratch &rs, const uint64_t *d_count, uint64_t cap, int vbytes, int bits,
@@ -329,7 +334,7 @@ hipError_t radix_sort_prepare(const RadixScratch &rs, const uint64_t *d_count, u
 template <typename VT>
 static hipError_t sort_pairs_impl(uint32_t *ka, VT *va, uint32_t *kb, VT *vb,
                             const uint64_t *d_count, uint64_t cap, int bits,
-                            const RadixScratch &rs, hipStream_t st, bool hist_ready)
+                            const RadixScratch &rs, hipStream_t st, bool hist_ready, bool cleared)
 {
     if (radix_passes(bits) == 0 || cap == 0) return hipSuccess;
     const int P = part_for((int)sizeof(VT), rs.part);
@@ -343,7 +348,8 @@ static hipError_t sort_pairs_impl(uint32_t *ka, VT *va, uint32_t *kb, VT *vb,
     hipError_t e;
     const uint64_t parts = (cap + P - 1) / P;
     if (!hist_ready) {
-        if ((e = radix_sort_prepare(rs, d_count, cap, (int)sizeof(VT), bits, st)) != hipSuccess) return e;
+        if (!cleared && (e = radix_sort_prepare(rs, d_count, cap, (int)sizeof(VT), bits, st)) != hipSuccess)
+            return e;
         // few large blocks: each adds its counts to the global histogram
         // with one atomic per digit, and same-address atomics from
         // thousands of blocks would serialise in L2
@@ -388,15 +394,15 @@ static hipError_t sort_pairs_impl(uint32_t *ka, VT *va, uint32_t *kb, VT *vb,
 
 hipError_t radix_sort_pairs(uint32_t *ka, uint32_t *va, uint32_t *kb, uint32_t *vb,
                             const uint64_t *d_count, uint64_t cap, int bits,
-                            const RadixScratch &rs, hipStream_t st, bool hist_ready)
+                            const RadixScratch &rs, hipStream_t st, bool hist_ready, bool cleared)
 {
-    return sort_pairs_impl<uint32_t>(ka, va, kb, vb, d_count, cap, bits, rs, st, hist_ready);
+    return sort_pairs_impl<uint32_t>(ka, va, kb, vb, d_count, cap, bits, rs, st, hist_ready, cleared);
 }
 
 hipError_t radix_sort_pairs_v2(uint32_t *ka, uint2 *va, uint32_t *kb, uint2 *vb, const uint64_t *d_count,
-                               uint64_t cap, int bits, const RadixScratch &rs, hipStream_t st)
+                               uint64_t cap, int bits, const RadixScratch &rs, hipStream_t st, bool cleared)
 {
-    return sort_pairs_impl<uint2>(ka, va, kb, vb, d_count, cap, bits, rs, st, false);
+    return sort_pairs_impl<uint2>(ka, va, kb, vb, d_count, cap, bits, rs, st, false, cleared);
 }
 
 size_t radix_sort_scratch_bytes(uint64_t n)
