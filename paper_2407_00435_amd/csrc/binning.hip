@@ -536,10 +536,24 @@ __device__ __forceinline__ uint32_t coarse_info(uint32_t rx, uint32_t ry, uint32
     return cx0 | (cy0 << 3) | (cx1 << 6) | (cy1 << 9) | (min(m, 4u) << 12);
 }
 
+// The super-tile sort's digit counts of the pairs a workgroup emits, in LDS
+// (sh[p * radix + digit], pass p's digit of the super-tile id: the packed
+// info above the id lies past every digit).
+struct DigitCount {
+    uint32_t *sh;
+    int passes, dbits, radix;
+    __device__ __forceinline__ void add(uint32_t st_id) const
+    {
+        const uint32_t mask = (1u << dbits) - 1u;
+        for (int p = 0; p < passes; ++p) atomicAdd(&sh[p * radix + ((st_id >> (dbits * p)) & mask)], 1u);
+    }
+};
+
 template <bool PACKED>
 __device__ __forceinline__ void coarse_put(uint32_t *__restrict__ ck, void *__restrict__ cv, uint64_t pos,
-                                           uint32_t st_id, uint32_t info, uint32_t e)
+                                           uint32_t st_id, uint32_t info, uint32_t e, const DigitCount &dc)
 {
+    dc.add(st_id);
     if (PACKED) {
         ck[pos] = st_id | (info << ST_ID_BITS);
         reinterpret_cast<uint32_t *>(cv)[pos] = e;
@@ -560,7 +574,7 @@ __device__ __forceinline__ uint32_t coarse_walk(uint32_t rx, uint32_t ry, uint32
                                                 const int64_t *__restrict__ vtab, const int4 *__restrict__ stab,
                                                 const uint32_t *__restrict__ sat, const uint8_t *__restrict__ cls,
                                                 int L, int64_t n_tiles, uint32_t *__restrict__ ck,
-                                                void *__restrict__ cv, uint64_t pos)
+                                                void *__restrict__ cv, uint64_t pos, const DigitCount *dc)
 {
     const int x0 = (int)(rx & 0xffffu), y0 = (int)(rx >> 16), x1 = (int)(ry & 0xffffu), y1 = (int)(ry >> 16);
     const int sx0 = x0 / ST, sx1 = x1 / ST, sy0 = y0 / ST, sy1 = y1 / ST;
@@ -568,7 +582,8 @@ __device__ __forceinline__ uint32_t coarse_walk(uint32_t rx, uint32_t ry, uint32
     if (sx0 == sx1 && sy0 == sy1) {
         // one super-tile: it holds all the entry's kept tiles (there is one)
         if (EMIT)
-            coarse_put<PACKED>(ck, cv, pos, (uint32_t)(sb.x + sy0 * sb.y + sx0), coarse_info(rx, ry, m, sx0, sy0), e);
+            coarse_put<PACKED>(ck, cv, pos, (uint32_t)(sb.x + sy0 * sb.y + sx0), coarse_info(rx, ry, m, sx0, sy0), e,
+                               *dc);
         return 1u;
     }
     const uint32_t *s = nullptr;
@@ -591,7 +606,7 @@ __device__ __forceinline__ uint32_t coarse_walk(uint32_t rx, uint32_t ry, uint32
                 }
             }
             if (keep) {
-                if (EMIT) coarse_put<PACKED>(ck, cv, pos + c, st_id, coarse_info(rx, ry, m, sx, sy), e);
+                if (EMIT) coarse_put<PACKED>(ck, cv, pos + c, st_id, coarse_info(rx, ry, m, sx, sy), e, *dc);
                 ++c;
             }
         }
@@ -613,7 +628,7 @@ __device__ __forceinline__ uint32_t coarse_code(uint32_t rx, uint32_t ry, uint32
     const int x0 = (int)(rx & 0xffffu), y0 = (int)(rx >> 16), x1 = (int)(ry & 0xffffu), y1 = (int)(ry >> 16);
     const int sx0 = x0 / ST, sx1 = x1 / ST, sy0 = y0 / ST, sy1 = y1 / ST;
     if (sx1 - sx0 >= MS || sy1 - sy0 >= MS)
-        return coarse_walk<false>(rx, ry, m, v, 0u, vtab, stab, sat, cls, L, n_tiles, nullptr, nullptr, 0);
+        return coarse_walk<false>(rx, ry, m, v, 0u, vtab, stab, sat, cls, L, n_tiles, nullptr, nullptr, 0, nullptr);
     if (sx0 == sx1 && sy0 == sy1) return 0x80000000u | (1u << 16) | 1u;
     const int4 sb = stab[v];
     const int ml = (int)m < L ? (int)m : L;
@@ -707,19 +722,25 @@ k_gather(const uint32_t *__restrict__ order, const uint4 *__restrict__ rec, cons
 }
 
 // 4b. coarse pairs of every depth-ordered entry at its scanned offset (from
-// the mask when there is one).  The grid also zeroes the first-pass lookback
-// words of the super-tile sort for the pairs' count, counts[3] (clamped to
-// cap): ceil(count / part) * radix words.
+// the mask when there is one).  The super-tile sort needs no set-up launch of
+// its own: each workgroup counts the digits of the super-tile ids it emits
+// into the sort's digit counts (zeroed by k_gather), and the grid zeroes the
+// sort's first-pass lookback words for the pairs' count, counts[3] (clamped
+// to cap): ceil(count / part) * radix words.
 template <bool PACKED>
 __global__ void __launch_bounds__(GATHER_THREADS)
 k_coarse_emit(const uint4 *__restrict__ rec_s, const uint32_t *__restrict__ cc_s, const uint64_t *__restrict__ counts,
               const uint64_t *__restrict__ boff, const int64_t *__restrict__ vtab, const int4 *__restrict__ stab,
               const uint32_t *__restrict__ sat, const uint8_t *__restrict__ cls, int L, int64_t n_tiles,
               uint32_t *__restrict__ ck, void *__restrict__ cv, uint64_t *__restrict__ sort_status, uint64_t cap,
-              int part, int radix)
+              RadixShape shape, uint32_t *__restrict__ sort_hist)
 {
     constexpr int W = GATHER_THREADS / 64;
     __shared__ uint32_t s_w[GATHER_ITEMS][W];
+    __shared__ uint32_t s_dig[4 * 256];
+    const int part = shape.part, radix = shape.radix;
+    for (int q = threadIdx.x; q < 4 * 256; q += GATHER_THREADS) s_dig[q] = 0u;  // (visible after the barrier below)
+    const DigitCount dc{s_dig, shape.passes, shape.dbits, radix};
     {
         const uint64_t np = counts[3] < cap ? counts[3] : cap;
         const uint64_t words = ((np + part - 1) / part) * (uint64_t)radix;
@@ -770,16 +791,19 @@ k_coarse_emit(const uint4 *__restrict__ rec_s, const uint32_t *__restrict__ cc_s
                     mask &= mask - 1u;
                     const int sx = sx0 + bit % MS, sy = sy0 + bit / MS;
                     coarse_put<PACKED>(ck, cv, pos + k, (uint32_t)(sb.x + sy * sb.y + sx),
-                                       coarse_info(q[j].x, q[j].y, q[j].w & 255u, sx, sy), q[j].z);
+                                       coarse_info(q[j].x, q[j].y, q[j].w & 255u, sx, sy), q[j].z, dc);
                     ++k;
                 }
             } else {
                 coarse_walk<true, PACKED>(q[j].x, q[j].y, q[j].w & 255u, v, q[j].z, vtab, stab, sat, cls, L,
-                                          n_tiles, ck, cv, pos);
+                                          n_tiles, ck, cv, pos, &dc);
             }
         }
         run += tw;
     }
+    __syncthreads();
+    for (int q = threadIdx.x; q < shape.passes * radix; q += GATHER_THREADS)
+        if (s_dig[q]) atomicAdd(&sort_hist[q], s_dig[q]);
 }
 
 // View of a super-tile: the last view whose first super-tile is <= s.
@@ -1296,26 +1320,30 @@ hipError_t launch_bin_sort(const gs_splat *splats, int n, const gs_camera *cams_
     int st_bits = 1;
     while ((int64_t(1) << st_bits) < n_st) ++st_bits;
     // the pair's info rides in the sort key when the super-tile ids leave room
-    const bool packed = coarse_packed && st_bits <= ST_ID_BITS;
+    // (and only while every digit of the sort lies below the packed info:
+    // three 6-bit digits of a 17-bit id would reach its lowest bit)
+    const bool packed = coarse_packed && st_bits <= 16;
     const bool even = radix_pass_count(st_bits, packed ? 4 : 8, bs.rs.part) % 2 == 0;
-    // the super-tile sort's digit counts and tickets were zeroed by k_gather
-    // and its first-pass lookback words are zeroed by k_coarse_emit
+    // the super-tile sort's digit counts and tickets were zeroed by k_gather;
+    // k_coarse_emit zeroes its first-pass lookback words and counts its digits
     const RadixShape shape = radix_shape(bs.rs, packed ? 4 : 8, st_bits);
-    if (radix_prepare_words(bs.rs, cap, packed ? 4 : 8, st_bits) > bs.rs.status_words) return hipErrorInvalidValue;
+    if (radix_prepare_words(bs.rs, cap, packed ? 4 : 8, st_bits) > bs.rs.status_words ||
+        shape.passes * shape.radix > 4 * 256)
+        return hipErrorInvalidValue;
     if (packed) {
         hipLaunchKernelGGL(k_coarse_emit<true>, dim3((unsigned)nb), dim3(GATHER_THREADS), 0, st, bs.rec_s, bs.cc_s,
                            bs.counts, bs.block_sums2, bs.vtab, bs.stab, sat, bs.st_cls, L, n_tiles, bs.tkey_a,
-                           (void *)bs.cpay_a, bs.rs.status, cap, shape.part, shape.radix);
+                           (void *)bs.cpay_a, bs.rs.status, cap, shape, bs.rs.hist);
         if ((err = radix_sort_pairs(bs.tkey_a, reinterpret_cast<uint32_t *>(bs.cpay_a), bs.tkey_b,
                                     reinterpret_cast<uint32_t *>(bs.cpay_b), bs.counts + 3, cap, st_bits, bs.rs, st,
-                                    false, true)) != hipSuccess)
+                                    true)) != hipSuccess)
             return err;
     } else {
         hipLaunchKernelGGL(k_coarse_emit<false>, dim3((unsigned)nb), dim3(GATHER_THREADS), 0, st, bs.rec_s, bs.cc_s,
                            bs.counts, bs.block_sums2, bs.vtab, bs.stab, sat, bs.st_cls, L, n_tiles, bs.tkey_a,
-                           (void *)bs.cpay_a, bs.rs.status, cap, shape.part, shape.radix);
+                           (void *)bs.cpay_a, bs.rs.status, cap, shape, bs.rs.hist);
         if ((err = radix_sort_pairs_v2(bs.tkey_a, bs.cpay_a, bs.tkey_b, bs.cpay_b, bs.counts + 3, cap, st_bits, bs.rs,
-                                       st, true)) != hipSuccess)
+                                       st, true, true)) != hipSuccess)
             return err;
     }
     const uint32_t *sk = even ? bs.tkey_a : bs.tkey_b;

@@ -75,14 +75,18 @@ hipError_t radix_sort_pairs(uint32_t *ka, uint32_t *va, uint32_t *kb, uint32_t *
 // The same with 8-byte values (partitions of at most 8192 keys).
 hipError_t radix_sort_pairs_v2(uint32_t *ka, uint2 *va, uint32_t *kb, uint2 *vb, const uint64_t *d_count,
                                uint64_t cap, int bits, const RadixScratch &rs, hipStream_t st,
-                               bool cleared = false);
+                               bool hist_ready = false, bool cleared = false);
 
-// Partition size and digits of the first pass of a sort of `bits`-bit keys
-// with vbytes-byte values: its lookback words for `count` pairs are
-// ceil(count / part) * radix (what radix_prepare_words returns).
+// How a sort of `bits`-bit keys with vbytes-byte values runs: partitions of
+// `part` keys, `passes` passes of `dbits`-bit digits (pass p sorts on the
+// digit (key >> (dbits * p)) & ((1 << dbits) - 1), counted at
+// hist[p * radix + digit]); its first pass's lookback words for `count` pairs
+// are ceil(count / part) * radix (what radix_prepare_words returns).
 struct RadixShape {
     int part;
     int radix;
+    int passes;
+    int dbits;
 };
 RadixShape radix_shape(const RadixScratch &rs, int vbytes, int bits);
 

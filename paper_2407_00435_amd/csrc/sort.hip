@@ -308,7 +308,10 @@ int radix_pass_count(int bits, int vbytes, int part)
 RadixShape radix_shape(const RadixScratch &rs, int vbytes, int bits)
 {
     const int P = part_for(vbytes, rs.part);
-    return RadixShape{P, one_wide_pass(bits, P) ? 512 : 256};
+    const bool wide = one_wide_pass(bits, P);
+    // equal digit widths <= 8 bits (fewer buckets give longer runs per
+    // digit), or one 9-bit digit
+    return RadixShape{P, wide ? 512 : 256, wide ? 1 : radix_passes(bits), wide ? 9 : radix_digit_bits(bits)};
 }
 
 uint64_t radix_prepare_words(const RadixScratch &rs, uint64_t count, int vbytes, int bits)
@@ -337,13 +340,12 @@ static hipError_t sort_pairs_impl(uint32_t *ka, VT *va, uint32_t *kb, VT *vb,
                             const RadixScratch &rs, hipStream_t st, bool hist_ready, bool cleared)
 {
     if (radix_passes(bits) == 0 || cap == 0) return hipSuccess;
-    const int P = part_for((int)sizeof(VT), rs.part);
-    const bool wide = one_wide_pass(bits, P);
-    const int passes = wide ? 1 : radix_passes(bits);
-    // equal digit widths <= 8 bits (fewer buckets give longer runs per
-    // digit), or one 9-bit digit
-    const int dbits = wide ? 9 : radix_digit_bits(bits);
-    const int R = wide ? 512 : 256;
+    const RadixShape shape = radix_shape(rs, (int)sizeof(VT), bits);
+    const int P = shape.part;
+    const bool wide = shape.radix == 512;
+    const int passes = shape.passes;
+    const int dbits = shape.dbits;
+    const int R = shape.radix;
     const uint32_t mask = (1u << dbits) - 1u;
     hipError_t e;
     const uint64_t parts = (cap + P - 1) / P;
@@ -400,9 +402,10 @@ hipError_t radix_sort_pairs(uint32_t *ka, uint32_t *va, uint32_t *kb, uint32_t *
 }
 
 hipError_t radix_sort_pairs_v2(uint32_t *ka, uint2 *va, uint32_t *kb, uint2 *vb, const uint64_t *d_count,
-                               uint64_t cap, int bits, const RadixScratch &rs, hipStream_t st, bool cleared)
+                               uint64_t cap, int bits, const RadixScratch &rs, hipStream_t st, bool hist_ready,
+                               bool cleared)
 {
-    return sort_pairs_impl<uint2>(ka, va, kb, vb, d_count, cap, bits, rs, st, false, cleared);
+    return sort_pairs_impl<uint2>(ka, va, kb, vb, d_count, cap, bits, rs, st, hist_ready, cleared);
 }
 
 size_t radix_sort_scratch_bytes(uint64_t n)
