@@ -44,11 +44,11 @@ FLOPS_PER_BLEND_BWD = 44
 # averaged over the dispatches), each scaled by the ratio of known bytes to
 # the same counter on a plain device copy (bench.py --copy-probe).  Valid
 # only for the kernel sources they were taken on (sha256 below).
-TRAFFIC = {"kernel": "k_raster_fov", "fetch_kib": 273031.1, "write_kib": 54881.7, "fetch_scale": 2.0,
-           "write_scale": 1.0, "sha256": "2b2482baf6237915e126680caaa02af493d3d62fd02ee37101220c41640cc2d7"}
+TRAFFIC = {"kernel": "k_raster_fov", "fetch_kib": 361648.5, "write_kib": 88893.9, "fetch_scale": 2.0,
+           "write_scale": 1.0, "sha256": "1fc057b4607568bcd7147fabb8ac4542369577c4753818c6138d5c824d87fac4"}
 # The same for the compositing reverse on the 1280x720 1M-Gaussian frame.
-TRAFFIC_BWD = {"kernel": "k_raster_bwd", "fetch_kib": 55524.5, "write_kib": 29395.7, "fetch_scale": 2.0,
-               "write_scale": 1.0, "sha256": "2b2482baf6237915e126680caaa02af493d3d62fd02ee37101220c41640cc2d7"}
+TRAFFIC_BWD = {"kernel": "k_raster_bwd", "fetch_kib": 55498.0, "write_kib": 29395.7, "fetch_scale": 2.0,
+               "write_scale": 1.0, "sha256": "1fc057b4607568bcd7147fabb8ac4542369577c4753818c6138d5c824d87fac4"}
 
 def kernel_sha():
     import hashlib
