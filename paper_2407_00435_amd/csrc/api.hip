@@ -107,7 +107,7 @@ void carve_bin(Carve &c, int V, int64_t E, uint64_t cap, int64_t tiles, BinScrat
     bs.rec = c.take<uint4>(16 * E);
     bs.rec_s = c.take<uint4>(16 * E);
     bs.cc_s = c.take<uint32_t>(4 * E);
-    int64_t nb = (E + SCAN_THREADS * SCAN_ITEMS - 1) / (SCAN_THREADS * SCAN_ITEMS) + 1;
+    int64_t nb = (E + ENTRY_BLOCK - 1) / ENTRY_BLOCK + 1;
     bs.block_sums = c.take<uint64_t>(8 * nb);
     bs.block_sums2 = c.take<uint64_t>(8 * nb);
     bs.block_vis = c.take<uint32_t>(4 * nb);

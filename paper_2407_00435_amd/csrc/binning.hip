@@ -252,7 +252,7 @@ __device__ __forceinline__ uint32_t sat_rect(const uint32_t *__restrict__ s, int
 //    lookback over the blocks before (lb: flag | count words); the block with
 //    the last ticket writes the total to *total.
 constexpr int COUNT_THREADS = 1024;
-constexpr int COUNT_ITEMS = SCAN_THREADS * SCAN_ITEMS / COUNT_THREADS;
+constexpr int COUNT_ITEMS = ENTRY_BLOCK / COUNT_THREADS;
 constexpr uint64_t LB_AGG = 1ull << 62;
 constexpr uint64_t LB_INC = 2ull << 62;
 constexpr uint64_t LB_VAL = (1ull << 62) - 1;
@@ -659,12 +659,12 @@ __device__ __forceinline__ uint32_t coarse_code(uint32_t rx, uint32_t ry, uint32
 // 4a. gather the records in depth order: rec_s[r] = {x0 | y0 << 16,
 // x1 | y1 << 16, entry, view << 8 | quality bound}; cc_s[r] = its coarse
 // pairs (count, or count and mask, as coarse_code); per-block sums of key counts and
-// coarse pairs.  A block takes SCAN_THREADS * SCAN_ITEMS entries with
+// coarse pairs.  A block takes ENTRY_BLOCK entries with
 // GATHER_THREADS threads, each issuing its loads for all its entries first.
 // The depth sort is done by now: the first block zeroes the sort's digit
 // counts and tickets for the super-tile sort (see k_coarse_emit).
 constexpr int GATHER_THREADS = 1024;
-constexpr int GATHER_ITEMS = SCAN_THREADS * SCAN_ITEMS / GATHER_THREADS;
+constexpr int GATHER_ITEMS = ENTRY_BLOCK / GATHER_THREADS;
 __global__ void __launch_bounds__(GATHER_THREADS)
 k_gather(const uint32_t *__restrict__ order, const uint4 *__restrict__ rec, const uint64_t *__restrict__ d_count,
          int n, const int64_t *__restrict__ vtab, const int4 *__restrict__ stab, const uint32_t *__restrict__ sat,
@@ -1268,7 +1268,7 @@ hipError_t launch_bin_sort(const gs_splat *splats, int n, const gs_camera *cams_
         n_st += (int64_t)((tx + ST - 1) / ST) * ((ty + ST - 1) / ST);
         max_view_tiles = tx * ty > max_view_tiles ? tx * ty : max_view_tiles;
     }
-    const int64_t nb = (E + SCAN_THREADS * SCAN_ITEMS - 1) / (SCAN_THREADS * SCAN_ITEMS);
+    const int64_t nb = (E + ENTRY_BLOCK - 1) / ENTRY_BLOCK;
     // the counting pass's ticket and lookback words, and the depth sort's
     // state for all E entries, are cleared with the rest of the set-up
     SetupClears z;

@@ -109,6 +109,12 @@ hipError_t radix_sort_standalone(uint32_t *keys, uint32_t *vals, uint32_t *kt, u
 // binning
 constexpr int SCAN_THREADS = 256;
 constexpr int SCAN_ITEMS = 16;
+// (view, point) entries per block of the counting, gather and coarse-emission
+// passes (1024-thread workgroups, two entries a thread): blocks of 4096 kept
+// one 1024-thread workgroup per CU for the gather and the emission, whose
+// latency then set their time (binning of the stereo 1080p frame 0.478 ->
+// 0.444 ms at 2048; 1024 was slower again, 0.463 ms)
+constexpr int ENTRY_BLOCK = 2048;
 constexpr int BIN_SUPER_TILE = 8;   // super-tile side in tiles (BIN_SUPER_TILE^2 <= 64)
 constexpr uint32_t BIN_CHUNK = 256; // coarse pairs per chunk of the per-tile counting passes
 // chunks of the counting passes: each super-tile's run of coarse pairs (at
@@ -121,7 +127,7 @@ struct BinScratch {
     uint4 *rec_s;                                 // [E] rectangle, entry, view and quality bound in depth order
     uint32_t *cc_s;                               // [E] coarse pairs of each entry in depth order
     uint32_t *block_vis;                          // [0]: ticket of the counting pass
-    uint64_t *block_sums, *block_sums2;           // [E / SCAN_ITEMS + 1] (block_sums: the counting pass's lookback words first)
+    uint64_t *block_sums, *block_sums2;           // [E / ENTRY_BLOCK + 1] (block_sums: the counting pass's lookback words first)
     int64_t *vtab;                                // [2V] first tile and tiles_x of each view
     int4 *stab;                                   // [V] first super-tile, super-tiles per row, tiles_x, tiles_y
     uint32_t *tkey_a, *tkey_b;                    // [cap] coarse-pair sort keys (super-tile ids), ping-pong
