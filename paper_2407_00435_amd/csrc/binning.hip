@@ -252,7 +252,13 @@ __device__ __forceinline__ uint32_t sat_rect(const uint32_t *__restrict__ s, int
 //    lookback over the blocks before (lb: flag | count words); the block with
 //    the last ticket writes the total to *total.
 constexpr int COUNT_THREADS = 1024;
-constexpr int COUNT_ITEMS = ENTRY_BLOCK / COUNT_THREADS;
+// The counting pass keeps blocks of 4096 entries: its blocks find their
+// output offsets by a lookback chain over the blocks before and add their
+// digit counts with global atomics, and twice as many blocks made it slower
+// (78 -> 88 us on the stereo 1080p frame) where the gather and the emission
+// gained from blocks of ENTRY_BLOCK.
+constexpr int COUNT_BLOCK = 4096;
+constexpr int COUNT_ITEMS = COUNT_BLOCK / COUNT_THREADS;
 constexpr uint64_t LB_AGG = 1ull << 62;
 constexpr uint64_t LB_INC = 2ull << 62;
 constexpr uint64_t LB_VAL = (1ull << 62) - 1;
@@ -1268,12 +1274,13 @@ hipError_t launch_bin_sort(const gs_splat *splats, int n, const gs_camera *cams_
         n_st += (int64_t)((tx + ST - 1) / ST) * ((ty + ST - 1) / ST);
         max_view_tiles = tx * ty > max_view_tiles ? tx * ty : max_view_tiles;
     }
-    const int64_t nb = (E + ENTRY_BLOCK - 1) / ENTRY_BLOCK;
+    const int64_t nb = (E + ENTRY_BLOCK - 1) / ENTRY_BLOCK;  // gather and emission blocks
+    const int64_t nbc = (E + COUNT_BLOCK - 1) / COUNT_BLOCK;  // counting-pass blocks
     // the counting pass's ticket and lookback words, and the depth sort's
     // state for all E entries, are cleared with the rest of the set-up
     SetupClears z;
     z.lb = bs.block_sums;
-    z.nb = nb;
+    z.nb = nbc;
     z.tick = bs.block_vis;
     z.hist = bs.rs.hist;
     z.tickets = bs.rs.tickets;
@@ -1298,11 +1305,11 @@ hipError_t launch_bin_sort(const gs_splat *splats, int n, const gs_camera *cams_
     // 1-2: counts, and the stable compaction of the entries with keys (depth
     // digits counted, the total to counts[0])
     if (filt)
-        hipLaunchKernelGGL(k_count<true>, dim3((unsigned)nb), dim3(COUNT_THREADS), 0, st, splats, n, cams_dev, V, T,
+        hipLaunchKernelGGL(k_count<true>, dim3((unsigned)nbc), dim3(COUNT_THREADS), 0, st, splats, n, cams_dev, V, T,
                            bs.vtab, sat, bs.bbox, L, n_tiles, qbound, bs.rec, hits_out, bs.block_vis,
                            bs.block_sums, bs.counts, bs.dkey_a, bs.dval_a, bs.rs.hist);
     else
-        hipLaunchKernelGGL(k_count<false>, dim3((unsigned)nb), dim3(COUNT_THREADS), 0, st, splats, n, cams_dev, V, T,
+        hipLaunchKernelGGL(k_count<false>, dim3((unsigned)nbc), dim3(COUNT_THREADS), 0, st, splats, n, cams_dev, V, T,
                            bs.vtab, sat, bs.bbox, L, n_tiles, qbound, bs.rec, hits_out, bs.block_vis,
                            bs.block_sums, bs.counts, bs.dkey_a, bs.dval_a, bs.rs.hist);
     // 3: depth sort of the entries with keys (4 x 8-bit passes), result back in (dkey_a, dval_a)
