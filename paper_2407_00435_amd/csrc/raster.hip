@@ -1781,49 +1781,72 @@ __device__ __forceinline__ void fovea_level(const gs_camera &c, const gs_fovea &
     }
 }
 
-// One workgroup per tile, a thread per pixel: the pixel's level and weight,
-// and the tile's lowest level and highest level with non-zero weight
-// (tile_level[2 g], tile_level[2 g + 1]).
+// One workgroup per strip of G = 64 / T horizontally adjacent tiles of one
+// view (64 pixels wide, T rows): its four waves take the strip's rows in
+// turn, a lane per pixel, so each row's levels and weights are written as 64
+// contiguous pixels.  Each lane keeps the lowest level and the highest level
+// with non-zero weight of its column; the T lanes of a tile's columns and the
+// four waves then give the tile's (tile_level[2 g], tile_level[2 g + 1]).
 template <int T>
-__global__ void __launch_bounds__(T * T)
+__global__ void __launch_bounds__(256)
 k_fovea_prep(const gs_camera *__restrict__ cams, int V, int L, FovArgs fa, uint8_t *__restrict__ pix_level,
              float *__restrict__ pix_weight, uint8_t *__restrict__ tile_level)
 {
-    constexpr int WAVES = (T * T + 63) / 64;
-    __shared__ int s_lo[WAVES], s_hi[WAVES];
-    const int64_t gt = blockIdx.x;
-    const ViewInfo vi = view_of_tile(cams, V, T, gt);
-    const int64_t lt = gt - vi.tile_off;
-    const int tx = (int)(lt % vi.tiles_x), ty = (int)(lt / vi.tiles_x);
-    const int x = tx * T + (int)(threadIdx.x % T), y = ty * T + (int)(threadIdx.x / T);
-    int lo = 255, hi = 0;
-    if (x < vi.W && y < vi.H) {
-        int l;
-        float w;
-        fovea_level(cams[vi.v], fa.f[vi.v], L, x, y, l, w);
-        const int64_t p = vi.pix_off + (int64_t)y * vi.W + x;
-        pix_level[p] = (uint8_t)l;
-        pix_weight[p] = w;
-        lo = l;
-        hi = l + (w > 0.0f ? 1 : 0);
+    constexpr int G = 64 / T;
+    static_assert(G * T == 64 && T >= 4, "a strip is 64 pixels wide");
+    __shared__ int s_lo[4][G], s_hi[4][G];
+    // the strip's view: strips are numbered view by view, row-major within one
+    const int64_t gs = blockIdx.x;
+    int v = 0, W = 0, H = 0, ntx = 0;
+    int64_t soff = 0, toff = 0, poff = 0;
+    for (;; ++v) {
+        W = cams[v].width;
+        H = cams[v].height;
+        ntx = div_up(W, T);
+        const int nty = div_up(H, T);
+        const int64_t ns = (int64_t)div_up(ntx, G) * nty;
+        if (gs < soff + ns || v == V - 1) break;
+        soff += ns;
+        toff += (int64_t)ntx * nty;
+        poff += (int64_t)W * H;
     }
-    for (int off = 32; off > 0; off >>= 1) {
+    const int nsx = div_up(ntx, G);
+    const int sx = (int)((gs - soff) % nsx), ty = (int)((gs - soff) / nsx);
+    const int col = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int x = sx * 64 + col;
+    int lo = 255, hi = 0;
+    for (int r = wave; r < T; r += 4) {
+        const int y = ty * T + r;
+        if (x < W && y < H) {
+            int l;
+            float w;
+            fovea_level(cams[v], fa.f[v], L, x, y, l, w);
+            const int64_t p = poff + (int64_t)y * W + x;
+            pix_level[p] = (uint8_t)l;
+            pix_weight[p] = w;
+            lo = min(lo, l);
+            hi = max(hi, l + (w > 0.0f ? 1 : 0));
+        }
+    }
+    for (int off = T / 2; off > 0; off >>= 1) {
         lo = min(lo, __shfl_xor(lo, off));
         hi = max(hi, __shfl_xor(hi, off));
     }
-    const int wave = threadIdx.x >> 6;
-    if ((threadIdx.x & 63) == 0) {
-        s_lo[wave] = lo;
-        s_hi[wave] = hi;
+    if (col % T == 0) {
+        s_lo[wave][col / T] = lo;
+        s_hi[wave][col / T] = hi;
     }
     __syncthreads();
-    if (threadIdx.x == 0) {
-        for (int q = 1; q < WAVES; ++q) {
-            lo = min(lo, s_lo[q]);
-            hi = max(hi, s_hi[q]);
+    const int t = threadIdx.x;
+    if (t < G && sx * G + t < ntx) {
+        int a = s_lo[0][t], b = s_hi[0][t];
+        for (int q = 1; q < 4; ++q) {
+            a = min(a, s_lo[q][t]);
+            b = max(b, s_hi[q][t]);
         }
-        tile_level[2 * gt] = (uint8_t)lo;
-        tile_level[2 * gt + 1] = (uint8_t)hi;
+        const int64_t gt = toff + (int64_t)ty * ntx + sx * G + t;
+        tile_level[2 * gt] = (uint8_t)a;
+        tile_level[2 * gt + 1] = (uint8_t)b;
     }
 }
 
@@ -2027,13 +2050,20 @@ hipError_t launch_fovea_prep(const gs_camera *cams_host, const gs_camera *cams_d
                              int n_eyes, int T, int n_levels, int64_t n_pixels, int64_t n_tiles,
                              uint8_t *pix_level, float *pix_weight, uint8_t *tile_level, hipStream_t st)
 {
-    (void)cams_host;
     (void)n_pixels;
     if (n_tiles == 0) return hipSuccess;
     FovArgs fa;
     for (int i = 0; i < 8; ++i) fa.f[i] = fov_host[i < n_eyes ? i : 0];
+    // strips of 64 / T tiles, view by view
+    const int Tc = T == 8 || T == 16 ? T : 32;
+    int64_t strips = 0;
+    for (int v = 0; v < n_eyes; ++v) {
+        const int64_t ntx = (cams_host[v].width + Tc - 1) / Tc, nty = (cams_host[v].height + Tc - 1) / Tc;
+        strips += (ntx + 64 / Tc - 1) / (64 / Tc) * nty;
+    }
+    if (strips == 0) return hipSuccess;
 #define GS_FP(TS)                                                                                      \
-    hipLaunchKernelGGL((k_fovea_prep<TS>), dim3((unsigned)n_tiles), dim3(TS * TS), 0, st, cams_dev, n_eyes,  \
+    hipLaunchKernelGGL((k_fovea_prep<TS>), dim3((unsigned)strips), dim3(256), 0, st, cams_dev, n_eyes,     \
                        n_levels, fa, pix_level, pix_weight, tile_level)
     switch (T) {
     case 8: GS_FP(8); break;

@@ -214,21 +214,26 @@ def test_end_to_end_image_matches_fp64_oracle():
         say(f"view {v}: max err vs fp64 {err:.3g}, ambiguous {namb}")
 
 
-def test_foveation_tables():
+@pytest.mark.parametrize("tile", [8, 16, 32])
+def test_foveation_tables(tile):
+    """Per-pixel levels and weights and per-tile level ranges; the widths
+    leave a partial strip of tiles at the right edge at every tile size (the
+    kernel takes 64-pixel-wide strips of tiles) and partial tiles below."""
     g = gs()
     cams = [scenegen.pinhole(320, 180, scenegen.FR_FOV_DEG, t=(0.03, 0.0, 2.0)),
-            scenegen.pinhole(250, 170, scenegen.FR_FOV_DEG, t=(-0.03, 0.0, 2.0))]
-    fov = [scenegen.Fovea(140.0, 95.0), scenegen.Fovea(120.3, 70.7)]
-    say("fovea tables")
+            scenegen.pinhole(232, 170, scenegen.FR_FOV_DEG, t=(-0.03, 0.0, 2.0)),
+            scenegen.pinhole(200, 90, scenegen.FR_FOV_DEG, t=(0.0, 0.02, 2.0))]
+    fov = [scenegen.Fovea(140.0, 95.0), scenegen.Fovea(120.3, 70.7), scenegen.Fovea(90.0, 40.0)]
+    say(f"fovea tables, tile {tile}")
     C = g.Cameras(cams)
-    t = g.gs_fovea_prep(C, fov, 16, 4)
+    t = g.gs_fovea_prep(C, fov, tile, 4)
     sizes = [(c.width, c.height) for c in cams]
     lv = pixel_views(t["pix_level"], sizes)
     wt = pixel_views(t["pix_weight"], sizes)
     tl = t["tile_level"].cpu().numpy()
     off = 0
     for v, cam in enumerate(cams):
-        ref = oracle.fovea(cam, fov[v], 4, 16, eps=1e-3)
+        ref = oracle.fovea(cam, fov[v], 4, tile, eps=1e-3)
         amb = ref["pix_amb"].reshape(cam.height, cam.width) > 0
         np.testing.assert_array_equal(lv[v][~amb], ref["pix_lo"].reshape(cam.height, cam.width)[~amb])
         np.testing.assert_allclose(wt[v], ref["pix_w"].reshape(cam.height, cam.width), atol=2e-3 / 3.5)
