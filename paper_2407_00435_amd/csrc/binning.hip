@@ -836,37 +836,58 @@ __global__ void __launch_bounds__(1024)
 k_chunk_table(const uint32_t *__restrict__ st_ranges, int64_t n_st, uint32_t *__restrict__ chunk_off,
               uint64_t *__restrict__ n_chunks, const int4 *__restrict__ stab, int V, uint4 *__restrict__ chunk)
 {
+    // with FILL, each thread's super-tile run (first, end pair) and view stay
+    // in LDS for the fill, so no wave waits on a global load per super-tile
     __shared__ uint32_t s[1024];
-    const int t = threadIdx.x;
+    __shared__ uint32_t s_w[16];
+    __shared__ uint32_t s_b[FILL ? 1024 : 1], s_e[FILL ? 1024 : 1], s_v[FILL ? 1024 : 1];
+    const int t = threadIdx.x, wave = t >> 6, lane = t & 63;
     const int64_t per = (n_st + 1023) / 1024;
     const int64_t b0 = t * per < n_st ? t * per : n_st, b1 = b0 + per < n_st ? b0 + per : n_st;
     uint32_t local = 0;
-    for (int64_t q = b0; q < b1; ++q) local += (st_ranges[2 * q + 1] - st_ranges[2 * q] + CHUNK - 1) / CHUNK;
-    s[t] = local;
-    __syncthreads();
-    for (int off = 1; off < 1024; off <<= 1) {
-        const uint32_t add = t >= off ? s[t - off] : 0u;
-        __syncthreads();
-        s[t] += add;
-        __syncthreads();
+    if constexpr (FILL) {
+        // per == 1: super-tile t
+        if (b0 < b1) {
+            const uint32_t bq = st_ranges[2 * b0], eq = st_ranges[2 * b0 + 1];
+            s_b[t] = bq;
+            s_e[t] = eq;
+            s_v[t] = (uint32_t)view_of_st(stab, V, (int)b0);
+            local = (eq - bq + CHUNK - 1) / CHUNK;
+        }
+    } else {
+        for (int64_t q = b0; q < b1; ++q) local += (st_ranges[2 * q + 1] - st_ranges[2 * q] + CHUNK - 1) / CHUNK;
     }
-    uint32_t run = s[t] - local;
-    for (int64_t q = b0; q < b1; ++q) {
-        chunk_off[q] = run;
-        run += (st_ranges[2 * q + 1] - st_ranges[2 * q] + CHUNK - 1) / CHUNK;
+    // inclusive prefix over the threads: a scan per wave, then the wave totals
+    const uint32_t x = wave_incl_scan(local);
+    if (lane == 63) s_w[wave] = x;
+    __syncthreads();
+    uint32_t add = 0, all = 0;
+    for (int w = 0; w < 16; ++w) {
+        const uint32_t y = s_w[w];
+        if (w < wave) add += y;
+        all += y;
+    }
+    s[t] = add + x;
+    uint32_t run = add + x - local;
+    if constexpr (FILL) {
+        if (b0 < b1) chunk_off[b0] = run;
+    } else {
+        for (int64_t q = b0; q < b1; ++q) {
+            chunk_off[q] = run;
+            run += (st_ranges[2 * q + 1] - st_ranges[2 * q] + CHUNK - 1) / CHUNK;
+        }
     }
     if (t == 1023) {
-        chunk_off[n_st] = s[1023];
-        *n_chunks = s[1023];
+        chunk_off[n_st] = all;
+        *n_chunks = all;
     }
     if constexpr (FILL) {
-        // s[q] is the inclusive chunk prefix of super-tile q (per == 1)
-        const int wave = t >> 6, lane = t & 63;
+        __syncthreads();
+        // s[q] is the inclusive chunk prefix of super-tile q; a wave per super-tile
         for (int64_t q = wave; q < n_st; q += 1024 / 64) {
             const uint32_t c1 = s[q], c0 = q > 0 ? s[q - 1] : 0u;
             if (c1 == c0) continue;
-            const uint32_t bq = st_ranges[2 * q], eq = st_ranges[2 * q + 1];
-            const uint32_t v = (uint32_t)view_of_st(stab, V, (int)q);
+            const uint32_t bq = s_b[q], eq = s_e[q], v = s_v[q];
             for (uint32_t c = c0 + lane; c < c1; c += 64) {
                 const uint32_t bb = bq + (c - c0) * CHUNK;
                 chunk[c] = make_uint4(bb, eq < bb + CHUNK ? eq : bb + CHUNK, (uint32_t)q, v);
