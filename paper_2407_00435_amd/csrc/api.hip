@@ -821,15 +821,27 @@ int gs_render_foveated(gs_ctx *ctx, const gs_scene *scene, const gs_camera *cams
         return r;
     hipStream_t st = (hipStream_t)stream;
     hipError_t e;
-    if ((r = gs_project(ctx, scene, cams_host, cams_dev, n_eyes, tile_size, rb.splats, rb.lvl, stream)))
-        return r;
-    if (ctx->tn.stream_views && n_eyes > 1)
+    if (ctx->tn.stream_views && n_eyes > 1) {
+        if ((r = gs_project(ctx, scene, cams_host, cams_dev, n_eyes, tile_size, rb.splats, rb.lvl, stream)))
+            return r;
         return render_views_streamed(ctx, scene, cams_host, cams_dev, n_eyes, tile_size, bg, image, key_capacity,
                                      num_keys, status, rb, bs, st);
-    e = launch_bin_sort(rb.splats, scene->n, cams_dev, cams_host, n_eyes, tiles,
-                        tile_size,
-                        rb.tile_level, scene->qbound, L, rb.vals, nullptr, key_capacity, rb.ranges, nullptr,
-                        num_keys, bs, ctx->tn.coarse_packed, status, st);
+    }
+    // The binning's set-up and level-filter tables go first, so that the
+    // projection counts each entry's kept tiles while it has the splat in
+    // registers; the binning then compacts the key words it wrote instead of
+    // reading the splat records again.  Keys and ranges are those of the
+    // separate stages.
+    e = launch_bin_sort(rb.splats, scene->n, cams_dev, cams_host, n_eyes, tiles, tile_size, rb.tile_level,
+                        scene->qbound, L, rb.vals, nullptr, key_capacity, rb.ranges, nullptr, num_keys, bs,
+                        ctx->tn.coarse_packed, status, st, BIN_SETUP);
+    if (e != hipSuccess) return hip_fail(e, "gs_render_foveated (binning set-up)");
+    const ProjBin pb = bin_counting_args(bs, tiles, nullptr);
+    e = launch_project(*scene, cams_dev, n_eyes, tile_size, rb.splats, rb.lvl, st, &pb);
+    if (e != hipSuccess) return hip_fail(e, "gs_render_foveated (projection)");
+    e = launch_bin_sort(rb.splats, scene->n, cams_dev, cams_host, n_eyes, tiles, tile_size, rb.tile_level,
+                        scene->qbound, L, rb.vals, nullptr, key_capacity, rb.ranges, nullptr, num_keys, bs,
+                        ctx->tn.coarse_packed, status, st, BIN_COUNTED);
     if (e != hipSuccess) return hip_fail(e, "gs_render_foveated (binning)");
     const float zero[3] = {0.f, 0.f, 0.f};
     RasterQueueArgs q;

@@ -303,6 +303,62 @@ __device__ __forceinline__ uint64_t block_lookback(uint64_t *__restrict__ lb, in
     return prefix;
 }
 
+// The stable compaction of one block's entries with keys (item j of thread t
+// is entry base + j * COUNT_THREADS + t; bal[j] = the wave's ballot of item j
+// having keys): (depth bits, entry) to (dkey, dval) at the block's offset,
+// found by lookback, and the depth digits of every sort pass into hist.
+// Called by every thread of the block after s_h is zeroed.
+__device__ __forceinline__ void compact_block(const uint64_t (&bal)[COUNT_ITEMS], const uint32_t (&key)[COUNT_ITEMS],
+                                              int64_t base, int64_t blk, uint64_t *__restrict__ lb,
+                                              uint64_t *__restrict__ total, uint32_t *__restrict__ dkey,
+                                              uint32_t *__restrict__ dval, uint32_t *__restrict__ hist,
+                                              uint32_t (*s_w)[COUNT_THREADS / 64], uint32_t (*s_h)[256],
+                                              uint64_t *s_off)
+{
+    constexpr int W = COUNT_THREADS / 64;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    if (lane == 0) {
+#pragma unroll
+        for (int j = 0; j < COUNT_ITEMS; ++j) s_w[j][wave] = (uint32_t)__popcll(bal[j]);
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        uint64_t tot = 0;
+        for (int j = 0; j < COUNT_ITEMS; ++j)
+            for (int w = 0; w < W; ++w) tot += s_w[j][w];
+        const uint64_t pre = block_lookback(lb, blk, tot);
+        *s_off = pre;
+        if (blk == (int64_t)gridDim.x - 1) *total = pre + tot;
+    }
+    __syncthreads();
+    // entries with keys in entry order: item-major within the block
+    uint64_t run = *s_off;
+#pragma unroll
+    for (int j = 0; j < COUNT_ITEMS; ++j) {
+        uint32_t wpre = 0, tot = 0;
+        for (int w = 0; w < W; ++w) {
+            const uint32_t x = s_w[j][w];
+            if (w < wave) wpre += x;
+            tot += x;
+        }
+        if ((bal[j] >> lane) & 1ull) {
+            const int64_t e = base + (int64_t)j * COUNT_THREADS + threadIdx.x;
+            const uint64_t pos = run + wpre + (uint32_t)__popcll(bal[j] & lanemask_lt());
+            const uint32_t k = key[j];
+            dkey[pos] = k;
+            dval[pos] = (uint32_t)e;
+#pragma unroll
+            for (int p = 0; p < 4; ++p) atomicAdd(&s_h[p][(k >> (8 * p)) & 255u], 1u);
+        }
+        run += tot;
+    }
+    __syncthreads();
+    for (int q = threadIdx.x; q < 4 * 256; q += COUNT_THREADS) {
+        const uint32_t x = (&s_h[0][0])[q];
+        if (x) atomicAdd(&hist[q], x);
+    }
+}
+
 template <bool FILT>
 __global__ void __launch_bounds__(COUNT_THREADS)
 k_count(const gs_splat *__restrict__ splats, int n, const gs_camera *__restrict__ cams, int V, int T,
@@ -391,8 +447,8 @@ k_count(const gs_splat *__restrict__ splats, int n, const gs_camera *__restrict_
             cnt[j] = ne[j] ? s11[j] - (lx ? s01[j] : 0u) - (ly ? s10[j] : 0u) + (lx && ly ? s00[j] : 0u) : 0u;
         }
     }
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     uint64_t bal[COUNT_ITEMS];
+    uint32_t key[COUNT_ITEMS];
 #pragma unroll
     for (int j = 0; j < COUNT_ITEMS; ++j) {
         const int64_t e = base + (int64_t)j * COUNT_THREADS + threadIdx.x;
@@ -404,45 +460,38 @@ k_count(const gs_splat *__restrict__ splats, int n, const gs_camera *__restrict_
             if (hits_out) hits_out[e] = cnt[j];
         }
         bal[j] = ballot64(e < E && cnt[j] > 0);
-        if (lane == 0) s_w[j][wave] = (uint32_t)__popcll(bal[j]);
+        key[j] = __float_as_uint(c[j].y);
     }
+    compact_block(bal, key, base, blk, lb, total, dkey, dval, hist, s_w, s_h, &s_off);
+}
+
+// The compaction alone, over the key words a counting projection wrote
+// (kw[e] = depth bits, or KEY_NONE for an entry without keys): the same
+// blocks, tickets, lookback and outputs as the counting pass.
+__global__ void __launch_bounds__(COUNT_THREADS)
+k_compact_keys(const uint32_t *__restrict__ kw, int64_t E, uint32_t *__restrict__ tick, uint64_t *__restrict__ lb,
+               uint64_t *__restrict__ total, uint32_t *__restrict__ dkey, uint32_t *__restrict__ dval,
+               uint32_t *__restrict__ hist)
+{
+    __shared__ uint32_t s_blk;
+    __shared__ uint32_t s_w[COUNT_ITEMS][COUNT_THREADS / 64];
+    __shared__ uint32_t s_h[4][256];
+    __shared__ uint64_t s_off;
+    if (threadIdx.x == 0) s_blk = atomicAdd(tick, 1u);
+    for (int q = threadIdx.x; q < 4 * 256; q += COUNT_THREADS) (&s_h[0][0])[q] = 0;
     __syncthreads();
-    if (threadIdx.x == 0) {
-        uint64_t tot = 0;
-        for (int j = 0; j < COUNT_ITEMS; ++j)
-            for (int w = 0; w < W; ++w) tot += s_w[j][w];
-        const uint64_t pre = block_lookback(lb, blk, tot);
-        s_off = pre;
-        if (blk == (int64_t)gridDim.x - 1) *total = pre + tot;
-    }
-    __syncthreads();
-    // entries with keys in entry order: item-major within the block (item j
-    // of thread t is entry base + j * COUNT_THREADS + t)
-    uint64_t run = s_off;
+    const int64_t blk = s_blk;
+    const int64_t base = blk * (COUNT_THREADS * COUNT_ITEMS);
+    uint64_t bal[COUNT_ITEMS];
+    uint32_t key[COUNT_ITEMS];
 #pragma unroll
     for (int j = 0; j < COUNT_ITEMS; ++j) {
-        uint32_t wpre = 0, tot = 0;
-        for (int w = 0; w < W; ++w) {
-            const uint32_t x = s_w[j][w];
-            if (w < wave) wpre += x;
-            tot += x;
-        }
-        if ((bal[j] >> lane) & 1ull) {
-            const int64_t e = base + (int64_t)j * COUNT_THREADS + threadIdx.x;
-            const uint64_t pos = run + wpre + (uint32_t)__popcll(bal[j] & lanemask_lt());
-            const uint32_t k = __float_as_uint(c[j].y);
-            dkey[pos] = k;
-            dval[pos] = (uint32_t)e;
+        const int64_t e = base + (int64_t)j * COUNT_THREADS + threadIdx.x;
+        key[j] = e < E ? kw[e] : KEY_NONE;
+    }
 #pragma unroll
-            for (int p = 0; p < 4; ++p) atomicAdd(&s_h[p][(k >> (8 * p)) & 255u], 1u);
-        }
-        run += tot;
-    }
-    __syncthreads();
-    for (int q = threadIdx.x; q < 4 * 256; q += COUNT_THREADS) {
-        const uint32_t x = (&s_h[0][0])[q];
-        if (x) atomicAdd(&hist[q], x);
-    }
+    for (int j = 0; j < COUNT_ITEMS; ++j) bal[j] = ballot64(key[j] != KEY_NONE);
+    compact_block(bal, key, base, blk, lb, total, dkey, dval, hist, s_w, s_h, &s_off);
 }
 
 // Exclusive scan of nb block values in place by one workgroup of 1024
@@ -1279,12 +1328,17 @@ hipError_t launch_status_views(const uint64_t *req_cap, const uint64_t *nums, in
     return hipGetLastError();
 }
 
+ProjBin bin_counting_args(const BinScratch &bs, int64_t n_tiles, uint32_t *hits_out)
+{
+    return ProjBin{bs.sat, bs.bbox, bs.vtab, n_tiles, bs.rec, bs.dkey_b, hits_out};
+}
+
 hipError_t launch_bin_sort(const gs_splat *splats, int n, const gs_camera *cams_dev,
                            const gs_camera *cams_host, int V, int64_t n_tiles, int T,
                            const uint8_t *tile_level, const uint8_t *qbound, int n_levels,
                            uint32_t *vals, uint64_t *keys, uint64_t cap, uint32_t *ranges,
                            uint32_t *hits_out, uint64_t *num_keys, const BinScratch &bs,
-                           bool coarse_packed, uint64_t *status, hipStream_t st)
+                           bool coarse_packed, uint64_t *status, hipStream_t st, BinMode mode)
 {
     const int64_t E = (int64_t)V * n;
     hipError_t err;
@@ -1309,23 +1363,33 @@ hipError_t launch_bin_sort(const gs_splat *splats, int n, const gs_camera *cams_
     z.status_words = radix_prepare_words(bs.rs, (uint64_t)E, 4, 32);
     if (z.status_words > bs.rs.status_words) return hipErrorInvalidValue;
     const uint64_t setup_n = std::max<uint64_t>(2 * (uint64_t)(n_tiles > n_st ? n_tiles : n_st), z.status_words);
-    hipLaunchKernelGGL(k_bin_setup, dim3(grid_for(setup_n, 256 * 4, 256)), dim3(256), 0, st, cams_dev, V, T, bs.vtab,
-                       bs.stab, bs.counts + 2, cap, ranges, n_tiles, bs.st_ranges, n_st,
-                       E == 0 ? num_keys : nullptr, status, z);
-    if (E == 0) return hipGetLastError();
     const bool filt = tile_level != nullptr;
     const int L = n_levels < 1 ? 1 : (n_levels > 4 ? 4 : n_levels);
-    if (filt) {
-        const int lds = max_view_tiles <= SAT_LDS_TILES;
-        const unsigned cls_blocks = (unsigned)((n_st + 15) / 16);
-        hipLaunchKernelGGL(k_level_sat, dim3(V * L + cls_blocks), dim3(1024), lds ? 5 * max_view_tiles + 16 : 0,
-                           st, cams_dev, V, T, L, n_tiles, tile_level, bs.sat, bs.bbox, lds, bs.vtab, bs.stab, n_st,
-                           bs.st_cls);
+    if (mode == BIN_COUNTED && !filt) return hipErrorInvalidValue;  // the projection counts after the level filter
+    if (mode != BIN_COUNTED) {
+        hipLaunchKernelGGL(k_bin_setup, dim3(grid_for(setup_n, 256 * 4, 256)), dim3(256), 0, st, cams_dev, V, T,
+                           bs.vtab, bs.stab, bs.counts + 2, cap, ranges, n_tiles, bs.st_ranges, n_st,
+                           E == 0 ? num_keys : nullptr, status, z);
+        if (E == 0) return hipGetLastError();
+        if (filt) {
+            const int lds = max_view_tiles <= SAT_LDS_TILES;
+            const unsigned cls_blocks = (unsigned)((n_st + 15) / 16);
+            hipLaunchKernelGGL(k_level_sat, dim3(V * L + cls_blocks), dim3(1024), lds ? 5 * max_view_tiles + 16 : 0,
+                               st, cams_dev, V, T, L, n_tiles, tile_level, bs.sat, bs.bbox, lds, bs.vtab, bs.stab,
+                               n_st, bs.st_cls);
+        }
+        if (mode == BIN_SETUP) return hipGetLastError();
+    } else if (E == 0) {
+        return hipSuccess;
     }
     const uint32_t *sat = filt ? bs.sat : nullptr;
     // 1-2: counts, and the stable compaction of the entries with keys (depth
-    // digits counted, the total to counts[0])
-    if (filt)
+    // digits counted, the total to counts[0]); after a counting projection
+    // only the compaction of its key words
+    if (mode == BIN_COUNTED)
+        hipLaunchKernelGGL(k_compact_keys, dim3((unsigned)nbc), dim3(COUNT_THREADS), 0, st, bs.dkey_b, E,
+                           bs.block_vis, bs.block_sums, bs.counts, bs.dkey_a, bs.dval_a, bs.rs.hist);
+    else if (filt)
         hipLaunchKernelGGL(k_count<true>, dim3((unsigned)nbc), dim3(COUNT_THREADS), 0, st, splats, n, cams_dev, V, T,
                            bs.vtab, sat, bs.bbox, L, n_tiles, qbound, bs.rec, hits_out, bs.block_vis,
                            bs.block_sums, bs.counts, bs.dkey_a, bs.dval_a, bs.rs.hist);

@@ -7,8 +7,23 @@
 #include "gs.h"
 
 // projection
+// The binning's counting step folded into the projection (the one-call
+// foveated render): per entry e = v n + i, the count of kept tiles after the
+// level filter, its rectangle record (rec[e], entries with keys only), its
+// depth key or KEY_NONE (kw[e]), and optionally the count (hits[e]).  The
+// tables (sat, bbox, vtab) are the level filter's, built before.
+constexpr uint32_t KEY_NONE = 0xFFFFFFFFu;  // no keys: never the bits of a positive depth
+struct ProjBin {
+    const uint32_t *sat;
+    const int32_t *bbox;
+    const int64_t *vtab;
+    int64_t n_tiles;
+    uint4 *rec;
+    uint32_t *kw;
+    uint32_t *hits;
+};
 hipError_t launch_project(const gs_scene &sc, const gs_camera *cams_dev, int V, int T,
-                          gs_splat *out, float *lvl_rgba, hipStream_t st);
+                          gs_splat *out, float *lvl_rgba, hipStream_t st, const ProjBin *pb = nullptr);
 hipError_t launch_project_bwd(const gs_scene &sc, const gs_camera *cams_dev, int V,
                               const gs_splat *splats, const gs_splat_grad *grads, float *g_means,
                               float *g_ls, float *g_q, float *g_logit, float *g_sh, int accumulate,
@@ -148,12 +163,21 @@ struct BinScratch {
 // the sort key where the super-tile ids leave room, else an 8-byte value
 // (same keys either way).  status (device, nullable, 2 words): the required
 // key count and the capacity, for gs_poll_status.
+// mode: BIN_ALL runs every step; BIN_SETUP only the set-up and the level
+// filter's tables (before a projection that counts, launch_project with
+// bin_counting_args); BIN_COUNTED the rest, compacting the key words that
+// projection wrote instead of counting from the splat records.
+enum BinMode { BIN_ALL = 0, BIN_SETUP = 1, BIN_COUNTED = 2 };
 hipError_t launch_bin_sort(const gs_splat *splats, int n, const gs_camera *cams_dev,
                            const gs_camera *cams_host, int V, int64_t n_tiles, int T,
                            const uint8_t *tile_level, const uint8_t *qbound, int n_levels,
                            uint32_t *vals, uint64_t *keys, uint64_t cap,
                            uint32_t *ranges, uint32_t *hits_out, uint64_t *num_keys,
-                           const BinScratch &bs, bool coarse_packed, uint64_t *status, hipStream_t st);
+                           const BinScratch &bs, bool coarse_packed, uint64_t *status, hipStream_t st,
+                           BinMode mode = BIN_ALL);
+// The projection's counting arguments over a binning scratch (kw in the depth
+// sort's second key buffer, free until the sort's first pass).
+ProjBin bin_counting_args(const BinScratch &bs, int64_t n_tiles, uint32_t *hits_out);
 
 // Status of a binning done view by view: status[0] = V * the largest per-view
 // required key count (the capacity that fits every view when each has

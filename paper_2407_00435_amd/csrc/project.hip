@@ -86,15 +86,21 @@ __device__ __forceinline__ void load_sh(const float *__restrict__ sh, int64_t i,
 
 __device__ __forceinline__ float sigmoidf(float x) { return 1.0f / (1.0f + __expf(-x)); }
 
-template <int DEG, bool LEVELS>
+// BIN: also the binning's count of each entry after the level filter (the
+// tile rectangle clipped to the bounding box of the tiles whose lower level
+// is at most the point's quality bound, then that level's summed-area table
+// over the clipped rectangle), written as the counting pass of the binning
+// writes it.
+template <int DEG, bool LEVELS, bool BIN>
 __global__ void __launch_bounds__(256)
 k_project(const float *__restrict__ means, const float *__restrict__ log_scales,
           const float *__restrict__ quats, const float *__restrict__ logits,
           const float *__restrict__ sh, const float *__restrict__ lvl_logits,
           const float *__restrict__ lvl_dc, int L, const uint8_t *__restrict__ qbound,
           const gs_camera *__restrict__ cams, int V, int T, int n, gs_splat *__restrict__ out,
-          float4 *__restrict__ lvl_out)
+          float4 *__restrict__ lvl_out, ProjBin pb)
 {
+    static_assert(!BIN || LEVELS, "the level filter needs the quality bounds");
     constexpr int K = (DEG + 1) * (DEG + 1);
     int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
@@ -107,6 +113,7 @@ k_project(const float *__restrict__ means, const float *__restrict__ log_scales,
     float coef[K * 3];
     load_sh<DEG>(sh, i, coef);
     float lvl_op[4], lvl_dcv[4][3];
+    const int qm = LEVELS && qbound ? (int)qbound[i] : 255;
     if (LEVELS) {
         // every level's loads first, unconditional (levels past L read level
         // L - 1, which is in bounds) so that they are in flight together,
@@ -132,7 +139,6 @@ k_project(const float *__restrict__ means, const float *__restrict__ log_scales,
         }
         // a point has no version at the levels above its quality bound
         // (Section 4.2): there its level opacity is zero
-        const int qm = qbound ? (int)qbound[i] : 255;
 #pragma unroll
         for (int t = 0; t < 4; ++t) {
             lvl_op[t] = t + 1 > qm ? 0.0f : ((hl && t < L) ? sigmoidf(raw[t]) : opacity);
@@ -140,10 +146,13 @@ k_project(const float *__restrict__ means, const float *__restrict__ log_scales,
             for (int ch = 0; ch < 3; ++ch) lvl_dcv[t][ch] = (hd && t < L) ? rdc[t][ch] : coef[ch];
         }
     }
+    const int mlq = qm < 1 ? 1 : (qm < L ? qm : L);  // the level filter's table for this point
     for (int v = 0; v < V; ++v) {
         CamF c = load_cam(cams, v);
         int64_t e = (int64_t)v * n + i;
         float4 *o4 = reinterpret_cast<float4 *>(out + e);
+        // the level's bounding box, loaded before the projection needs it
+        const int4 bb = BIN ? reinterpret_cast<const int4 *>(pb.bbox)[(int64_t)v * L + mlq - 1] : int4{};
         float ux = c.R[0] * mx + c.R[1] * my + c.R[2] * mz + c.t[0];
         float uy = c.R[3] * mx + c.R[4] * my + c.R[5] * mz + c.t[1];
         float uz = c.R[6] * mx + c.R[7] * my + c.R[8] * mz + c.t[2];
@@ -180,6 +189,10 @@ k_project(const float *__restrict__ means, const float *__restrict__ log_scales,
             o4[2] = z;
             if (LEVELS)
                 for (int t = 0; t < L; ++t) lvl_out[e * L + t] = z;
+            if (BIN) {
+                pb.kw[e] = KEY_NONE;
+                if (pb.hits) pb.hits[e] = 0u;
+            }
             continue;
         }
         float idet = 1.0f / det;
@@ -188,10 +201,32 @@ k_project(const float *__restrict__ means, const float *__restrict__ log_scales,
         int radius = (int)ceilf(3.0f * sqrtf(lmax));
         float px = c.fx * ux / uz + c.cx;
         float py = c.fy * uy / uz + c.cy;
-        TileRect rect;
+        TileRect rect{};
         uint32_t tiles = 0;
         if (tile_rect(px, py, radius, c.W, c.H, T, rect))
             tiles = (uint32_t)(rect.tx1 - rect.tx0 + 1) * (uint32_t)(rect.ty1 - rect.ty0 + 1);
+        // the filtered count: the level's summed-area table over the
+        // rectangle clipped to that level's bounding box (the four corners
+        // are loaded here and used after the colour)
+        bool ne = false, lx = false, ly = false;
+        uint32_t s11 = 0, s01 = 0, s10 = 0, s00 = 0;
+        if (BIN) {
+            rect.tx0 = rect.tx0 > bb.x ? rect.tx0 : bb.x;
+            rect.ty0 = rect.ty0 > bb.y ? rect.ty0 : bb.y;
+            rect.tx1 = rect.tx1 < bb.z ? rect.tx1 : bb.z;
+            rect.ty1 = rect.ty1 < bb.w ? rect.ty1 : bb.w;
+            ne = tiles && qm >= 1 && rect.tx0 <= rect.tx1 && rect.ty0 <= rect.ty1;
+            const int64_t ntx = pb.vtab[2 * v + 1];
+            const uint32_t *sp = pb.sat + (int64_t)(mlq - 1) * pb.n_tiles + pb.vtab[2 * v];
+            lx = rect.tx0 > 0;
+            ly = rect.ty0 > 0;
+            const int x1 = ne ? rect.tx1 : 0, y1 = ne ? rect.ty1 : 0;
+            const int x0 = ne && lx ? rect.tx0 - 1 : 0, y0 = ne && ly ? rect.ty0 - 1 : 0;
+            s11 = sp[(int64_t)y1 * ntx + x1];
+            s01 = sp[(int64_t)y1 * ntx + x0];
+            s10 = sp[(int64_t)y0 * ntx + x1];
+            s00 = sp[(int64_t)y0 * ntx + x0];
+        }
         // colour from the unit direction camera -> mean
         float dx = mx - c.pos[0], dy = my - c.pos[1], dz = mz - c.pos[2];
         float inv = rsqrtf(dx * dx + dy * dy + dz * dz);
@@ -219,6 +254,14 @@ k_project(const float *__restrict__ means, const float *__restrict__ log_scales,
                                                  fmaxf(0.0f, lvl_dcv[t][2] * SH_C0 + rest[2]),
                                                  lvl_op[t]);
             }
+        }
+        if (BIN) {
+            const uint32_t cnt = ne ? s11 - (lx ? s01 : 0u) - (ly ? s10 : 0u) + (lx && ly ? s00 : 0u) : 0u;
+            if (cnt)
+                pb.rec[e] = make_uint4((uint32_t)rect.tx0 | ((uint32_t)rect.ty0 << 16),
+                                       (uint32_t)rect.tx1 | ((uint32_t)rect.ty1 << 16), cnt, (uint32_t)qm);
+            pb.kw[e] = cnt ? __float_as_uint(uz) : KEY_NONE;
+            if (pb.hits) pb.hits[e] = cnt;
         }
     }
 }
@@ -585,23 +628,29 @@ k_project_bwd(const float *__restrict__ means, const float *__restrict__ log_sca
 }  // namespace
 
 hipError_t launch_project(const gs_scene &sc, const gs_camera *cams_dev, int V, int T,
-                          gs_splat *out, float *lvl_rgba, hipStream_t st)
+                          gs_splat *out, float *lvl_rgba, hipStream_t st, const ProjBin *pb)
 {
     int n = sc.n;
     if (n == 0) return hipSuccess;
     dim3 grid((n + 255) / 256), block(256);
     int L = sc.n_levels;
     bool lv = lvl_rgba != nullptr && L > 0;
+    if (pb && (!lv || !sc.qbound)) return hipErrorInvalidValue;
     float4 *lo = reinterpret_cast<float4 *>(lvl_rgba);
+    const ProjBin none{};
 #define GS_PROJ(DEG)                                                                                   \
-    if (lv)                                                                                            \
-        hipLaunchKernelGGL((k_project<DEG, true>), grid, block, 0, st, sc.means, sc.log_scales,       \
+    if (pb)                                                                                            \
+        hipLaunchKernelGGL((k_project<DEG, true, true>), grid, block, 0, st, sc.means, sc.log_scales, \
                            sc.quats, sc.opacity_logits, sc.sh, sc.lvl_opacity_logits, sc.lvl_sh_dc,  \
-                           L, sc.qbound, cams_dev, V, T, n, out, lo);                                  \
+                           L, sc.qbound, cams_dev, V, T, n, out, lo, *pb);                             \
+    else if (lv)                                                                                       \
+        hipLaunchKernelGGL((k_project<DEG, true, false>), grid, block, 0, st, sc.means, sc.log_scales,\
+                           sc.quats, sc.opacity_logits, sc.sh, sc.lvl_opacity_logits, sc.lvl_sh_dc,  \
+                           L, sc.qbound, cams_dev, V, T, n, out, lo, none);                            \
     else                                                                                               \
-        hipLaunchKernelGGL((k_project<DEG, false>), grid, block, 0, st, sc.means, sc.log_scales,      \
+        hipLaunchKernelGGL((k_project<DEG, false, false>), grid, block, 0, st, sc.means, sc.log_scales,\
                            sc.quats, sc.opacity_logits, sc.sh, nullptr, nullptr, 0, nullptr, cams_dev, \
-                           V, T, n, out, nullptr);
+                           V, T, n, out, nullptr, none);
     switch (sc.sh_degree) {
     case 0: GS_PROJ(0); break;
     case 1: GS_PROJ(1); break;

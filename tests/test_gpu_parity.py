@@ -317,15 +317,20 @@ def test_foveated_matches_oracle(tile, rings, band):
     np.testing.assert_allclose(lvn[0, vis, :, 0:3], ref_p["lvl_color"].transpose(1, 0, 2)[vis], atol=2e-5)
 
 
-def test_render_foveated_one_call_equals_stages():
+@pytest.mark.parametrize("tile,eyes", [(16, 2), (8, 3), (32, 3)])
+def test_render_foveated_one_call_equals_stages(tile, eyes):
+    """The one-call render (its projection counts each entry's kept tiles and
+    the binning compacts what it wrote) gives the image and key count of the
+    separate stages (counting pass over the splat records)."""
     g = gs()
     sc = scene_small(seed=52, n=3000, fr=4)
     cams = [scenegen.pinhole(300, 170, scenegen.FR_FOV_DEG, t=(0.03, 0.0, 2.0)),
-            scenegen.pinhole(300, 170, scenegen.FR_FOV_DEG, t=(-0.03, 0.0, 2.0))]
-    fov = [scenegen.Fovea(150.0, 90.0)] * 2
-    say("render_foveated one call")
-    C, S, t, splats, lvl, bs, img = _fr_case(g, sc, cams, fov, 16)
-    img2, num, _ = g.gs_render_foveated(S, C, fov, 16, key_capacity=int(bs["num_keys"].item()) + 7)
+            scenegen.pinhole(300, 170, scenegen.FR_FOV_DEG, t=(-0.03, 0.0, 2.0)),
+            scenegen.pinhole(213, 121, scenegen.FR_FOV_DEG, t=(0.0, 0.05, 1.8))][:eyes]
+    fov = [scenegen.Fovea(150.0, 90.0), scenegen.Fovea(150.0, 90.0), scenegen.Fovea(60.0, 100.0)][:eyes]
+    say(f"render_foveated one call, tile {tile}, {eyes} eyes")
+    C, S, t, splats, lvl, bs, img = _fr_case(g, sc, cams, fov, tile)
+    img2, num, _ = g.gs_render_foveated(S, C, fov, tile, key_capacity=int(bs["num_keys"].item()) + 7)
     torch.cuda.synchronize()
     assert int(num.item()) == int(bs["num_keys"].item())
     assert torch.equal(img, img2)
