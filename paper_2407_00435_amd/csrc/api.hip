@@ -867,12 +867,35 @@ int gs_render_fwd(gs_ctx *ctx, const gs_scene *scene, const gs_camera *cams_host
     int64_t tiles = 0;
     if ((r = check_scene(scene, false))) return r;
     if ((r = check_cams(cams_host, cams_dev, n_views, tile_size, &tiles, nullptr))) return r;
-    if ((r = gs_project(ctx, scene, cams_host, cams_dev, n_views, tile_size, splats, nullptr, stream)))
-        return r;
-    if ((r = gs_bin_sort(ctx, splats, scene->n, cams_host, cams_dev, n_views, tile_size, nullptr, nullptr,
-                         vals, nullptr, key_capacity, tile_ranges, nullptr, num_keys, workspace,
-                         workspace_bytes, stream)))
-        return r;
+    const int64_t E = (int64_t)n_views * scene->n;
+    if (E >= (1ll << 32)) return fail(GS_ERR_UNSUPPORTED, "n_views * n must be < 2^32");
+    if (key_capacity >= (1ull << 32)) return fail(GS_ERR_UNSUPPORTED, "key_capacity must be < 2^32");
+    if ((scene->n > 0 && !splats) || !tile_ranges || !num_keys || (key_capacity > 0 && !vals))
+        return fail(GS_ERR_INVALID, "NULL output or input pointer");
+    if (!aligned(splats, 16)) return fail(GS_ERR_INVALID, "splats must be 16-byte aligned");
+    if ((r = check_ws(workspace, workspace_bytes, bin_bytes(n_views, E, key_capacity, tiles)))) return r;
+    if ((r = check_device(ctx))) return r;
+    Carve c;
+    c.base = (char *)workspace;
+    uint64_t *status = c.take<uint64_t>(WS_HEADER);
+    BinScratch bs;
+    carve_bin(c, n_views, E, key_capacity, tiles, bs);
+    bs.rs.part = ctx->tn.radix_part;
+    hipStream_t st = (hipStream_t)stream;
+    // as in gs_render_foveated: the binning's set-up first, the projection
+    // counts each entry's tiles, the binning compacts its key words (keys
+    // and ranges are those of gs_project + gs_bin_sort)
+    hipError_t e = launch_bin_sort(splats, scene->n, cams_dev, cams_host, n_views, tiles, tile_size, nullptr,
+                                   nullptr, 4, vals, nullptr, key_capacity, tile_ranges, nullptr, num_keys, bs,
+                                   ctx->tn.coarse_packed, status, st, BIN_SETUP);
+    if (e != hipSuccess) return hip_fail(e, "gs_render_fwd (binning set-up)");
+    const ProjBin pb = bin_counting_args(bs, tiles, nullptr);
+    e = launch_project(*scene, cams_dev, n_views, tile_size, splats, nullptr, st, &pb);
+    if (e != hipSuccess) return hip_fail(e, "gs_render_fwd (projection)");
+    e = launch_bin_sort(splats, scene->n, cams_dev, cams_host, n_views, tiles, tile_size, nullptr, nullptr, 4, vals,
+                        nullptr, key_capacity, tile_ranges, nullptr, num_keys, bs, ctx->tn.coarse_packed, status, st,
+                        BIN_COUNTED);
+    if (e != hipSuccess) return hip_fail(e, "gs_render_fwd (binning)");
     return gs_rasterize_fwd(ctx, splats, scene->n, cams_host, cams_dev, n_views, tile_size, vals, tile_ranges,
                             bg, image, final_T, n_contrib, nullptr, nullptr, workspace, workspace_bytes,
                             stream);

@@ -259,11 +259,12 @@ constexpr int COUNT_THREADS = 1024;
 // gained from blocks of ENTRY_BLOCK.
 constexpr int COUNT_BLOCK = 4096;
 constexpr int COUNT_ITEMS = COUNT_BLOCK / COUNT_THREADS;
-// The compaction of a counting projection's key words takes blocks of 16384
-// entries (one-call stereo 1080p frame: 1.041 ms at 4096, 1.037 at 8192,
-// 1.034 at 16384).
-constexpr int KEYW_BLOCK = 16384;
-static_assert(KEYW_BLOCK % COUNT_BLOCK == 0, "the set-up clears lookback words for COUNT_BLOCK blocks");
+// The compaction of a counting projection's key words takes blocks of up to
+// 16384 entries while that leaves at least KEYW_MIN_BLOCKS of them (one-call
+// stereo 1080p frame, 3M entries: 1.041 ms at 4096, 1.037 at 8192, 1.034 at
+// 16384; a 500k-entry view was slower at 16384 than at 4096, with 31 blocks).
+constexpr int KEYW_MIN_BLOCKS = 160;
+static_assert(COUNT_BLOCK == 4096, "the set-up clears lookback words for blocks of at least 4096 entries");
 constexpr uint64_t LB_AGG = 1ull << 62;
 constexpr uint64_t LB_INC = 2ull << 62;
 constexpr uint64_t LB_VAL = (1ull << 62) - 1;
@@ -1375,7 +1376,6 @@ hipError_t launch_bin_sort(const gs_splat *splats, int n, const gs_camera *cams_
     const uint64_t setup_n = std::max<uint64_t>(2 * (uint64_t)(n_tiles > n_st ? n_tiles : n_st), z.status_words);
     const bool filt = tile_level != nullptr;
     const int L = n_levels < 1 ? 1 : (n_levels > 4 ? 4 : n_levels);
-    if (mode == BIN_COUNTED && !filt) return hipErrorInvalidValue;  // the projection counts after the level filter
     if (mode != BIN_COUNTED) {
         hipLaunchKernelGGL(k_bin_setup, dim3(grid_for(setup_n, 256 * 4, 256)), dim3(256), 0, st, cams_dev, V, T,
                            bs.vtab, bs.stab, bs.counts + 2, cap, ranges, n_tiles, bs.st_ranges, n_st,
@@ -1396,18 +1396,27 @@ hipError_t launch_bin_sort(const gs_splat *splats, int n, const gs_camera *cams_
     // 1-2: counts, and the stable compaction of the entries with keys (depth
     // digits counted, the total to counts[0]); after a counting projection
     // only the compaction of its key words
-    if (mode == BIN_COUNTED)
-        hipLaunchKernelGGL(k_compact_keys<KEYW_BLOCK / COUNT_THREADS>, dim3((unsigned)((E + KEYW_BLOCK - 1) / KEYW_BLOCK)),
-                           dim3(COUNT_THREADS), 0, st, bs.dkey_b, E, bs.block_vis, bs.block_sums, bs.counts, bs.dkey_a,
-                           bs.dval_a, bs.rs.hist);
-    else if (filt)
+#define GS_CK(IT)                                                                                         \
+    hipLaunchKernelGGL(k_compact_keys<IT>, dim3((unsigned)((E + IT * COUNT_THREADS - 1) / (IT * COUNT_THREADS))), \
+                       dim3(COUNT_THREADS), 0, st, bs.dkey_b, E, bs.block_vis, bs.block_sums, bs.counts, bs.dkey_a,  \
+                       bs.dval_a, bs.rs.hist)
+    if (mode == BIN_COUNTED) {
+        if (E >= (int64_t)KEYW_MIN_BLOCKS * 16 * COUNT_THREADS)
+            GS_CK(16);
+        else if (E >= (int64_t)KEYW_MIN_BLOCKS * 8 * COUNT_THREADS)
+            GS_CK(8);
+        else
+            GS_CK(4);
+    } else if (filt) {
         hipLaunchKernelGGL(k_count<true>, dim3((unsigned)nbc), dim3(COUNT_THREADS), 0, st, splats, n, cams_dev, V, T,
                            bs.vtab, sat, bs.bbox, L, n_tiles, qbound, bs.rec, hits_out, bs.block_vis,
                            bs.block_sums, bs.counts, bs.dkey_a, bs.dval_a, bs.rs.hist);
-    else
+    } else {
         hipLaunchKernelGGL(k_count<false>, dim3((unsigned)nbc), dim3(COUNT_THREADS), 0, st, splats, n, cams_dev, V, T,
                            bs.vtab, sat, bs.bbox, L, n_tiles, qbound, bs.rec, hits_out, bs.block_vis,
                            bs.block_sums, bs.counts, bs.dkey_a, bs.dval_a, bs.rs.hist);
+    }
+#undef GS_CK
     // 3: depth sort of the entries with keys (4 x 8-bit passes), result back in (dkey_a, dval_a)
     if ((err = radix_sort_pairs(bs.dkey_a, bs.dval_a, bs.dkey_b, bs.dval_b, bs.counts, (uint64_t)E, 32, bs.rs, st,
                                 true)) != hipSuccess)

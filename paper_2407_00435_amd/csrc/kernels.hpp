@@ -8,10 +8,11 @@
 
 // projection
 // The binning's counting step folded into the projection (the one-call
-// foveated render): per entry e = v n + i, the count of kept tiles after the
-// level filter, its rectangle record (rec[e], entries with keys only), its
-// depth key or KEY_NONE (kw[e]), and optionally the count (hits[e]).  The
-// tables (sat, bbox, vtab) are the level filter's, built before.
+// renders): per entry e = v n + i, the count of its tiles (with level
+// versions: kept after the level filter), its rectangle record (rec[e],
+// entries with keys only), its depth key or KEY_NONE (kw[e]), and optionally
+// the count (hits[e]).  The tables (sat, bbox, vtab) are the binning's,
+// built before.
 constexpr uint32_t KEY_NONE = 0xFFFFFFFFu;  // no keys: never the bits of a positive depth
 struct ProjBin {
     const uint32_t *sat;

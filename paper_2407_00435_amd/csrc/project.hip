@@ -86,11 +86,11 @@ __device__ __forceinline__ void load_sh(const float *__restrict__ sh, int64_t i,
 
 __device__ __forceinline__ float sigmoidf(float x) { return 1.0f / (1.0f + __expf(-x)); }
 
-// BIN: also the binning's count of each entry after the level filter (the
-// tile rectangle clipped to the bounding box of the tiles whose lower level
-// is at most the point's quality bound, then that level's summed-area table
-// over the clipped rectangle), written as the counting pass of the binning
-// writes it.
+// BIN: also the binning's count of each entry, written as the counting pass
+// of the binning writes it: with LEVELS, after the level filter (the tile
+// rectangle clipped to the bounding box of the tiles whose lower level is at
+// most the point's quality bound, then that level's summed-area table over
+// the clipped rectangle); without, the rectangle's tiles.
 template <int DEG, bool LEVELS, bool BIN>
 __global__ void __launch_bounds__(256)
 k_project(const float *__restrict__ means, const float *__restrict__ log_scales,
@@ -100,7 +100,6 @@ k_project(const float *__restrict__ means, const float *__restrict__ log_scales,
           const gs_camera *__restrict__ cams, int V, int T, int n, gs_splat *__restrict__ out,
           float4 *__restrict__ lvl_out, ProjBin pb)
 {
-    static_assert(!BIN || LEVELS, "the level filter needs the quality bounds");
     constexpr int K = (DEG + 1) * (DEG + 1);
     int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
@@ -152,7 +151,7 @@ k_project(const float *__restrict__ means, const float *__restrict__ log_scales,
         int64_t e = (int64_t)v * n + i;
         float4 *o4 = reinterpret_cast<float4 *>(out + e);
         // the level's bounding box, loaded before the projection needs it
-        const int4 bb = BIN ? reinterpret_cast<const int4 *>(pb.bbox)[(int64_t)v * L + mlq - 1] : int4{};
+        const int4 bb = BIN && LEVELS ? reinterpret_cast<const int4 *>(pb.bbox)[(int64_t)v * L + mlq - 1] : int4{};
         float ux = c.R[0] * mx + c.R[1] * my + c.R[2] * mz + c.t[0];
         float uy = c.R[3] * mx + c.R[4] * my + c.R[5] * mz + c.t[1];
         float uz = c.R[6] * mx + c.R[7] * my + c.R[8] * mz + c.t[2];
@@ -210,7 +209,7 @@ k_project(const float *__restrict__ means, const float *__restrict__ log_scales,
         // are loaded here and used after the colour)
         bool ne = false, lx = false, ly = false;
         uint32_t s11 = 0, s01 = 0, s10 = 0, s00 = 0;
-        if (BIN) {
+        if (BIN && LEVELS) {
             rect.tx0 = rect.tx0 > bb.x ? rect.tx0 : bb.x;
             rect.ty0 = rect.ty0 > bb.y ? rect.ty0 : bb.y;
             rect.tx1 = rect.tx1 < bb.z ? rect.tx1 : bb.z;
@@ -256,7 +255,8 @@ k_project(const float *__restrict__ means, const float *__restrict__ log_scales,
             }
         }
         if (BIN) {
-            const uint32_t cnt = ne ? s11 - (lx ? s01 : 0u) - (ly ? s10 : 0u) + (lx && ly ? s00 : 0u) : 0u;
+            const uint32_t cnt =
+                !LEVELS ? tiles : (ne ? s11 - (lx ? s01 : 0u) - (ly ? s10 : 0u) + (lx && ly ? s00 : 0u) : 0u);
             if (cnt)
                 pb.rec[e] = make_uint4((uint32_t)rect.tx0 | ((uint32_t)rect.ty0 << 16),
                                        (uint32_t)rect.tx1 | ((uint32_t)rect.ty1 << 16), cnt, (uint32_t)qm);
@@ -635,14 +635,18 @@ hipError_t launch_project(const gs_scene &sc, const gs_camera *cams_dev, int V, 
     dim3 grid((n + 255) / 256), block(256);
     int L = sc.n_levels;
     bool lv = lvl_rgba != nullptr && L > 0;
-    if (pb && (!lv || !sc.qbound)) return hipErrorInvalidValue;
+    if (pb && lv && !sc.qbound) return hipErrorInvalidValue;  // the level filter needs the quality bounds
     float4 *lo = reinterpret_cast<float4 *>(lvl_rgba);
     const ProjBin none{};
 #define GS_PROJ(DEG)                                                                                   \
-    if (pb)                                                                                            \
+    if (pb && lv)                                                                                      \
         hipLaunchKernelGGL((k_project<DEG, true, true>), grid, block, 0, st, sc.means, sc.log_scales, \
                            sc.quats, sc.opacity_logits, sc.sh, sc.lvl_opacity_logits, sc.lvl_sh_dc,  \
                            L, sc.qbound, cams_dev, V, T, n, out, lo, *pb);                             \
+    else if (pb)                                                                                       \
+        hipLaunchKernelGGL((k_project<DEG, false, true>), grid, block, 0, st, sc.means, sc.log_scales,\
+                           sc.quats, sc.opacity_logits, sc.sh, nullptr, nullptr, 0, nullptr, cams_dev, \
+                           V, T, n, out, nullptr, *pb);                                                \
     else if (lv)                                                                                       \
         hipLaunchKernelGGL((k_project<DEG, true, false>), grid, block, 0, st, sc.means, sc.log_scales,\
                            sc.quats, sc.opacity_logits, sc.sh, sc.lvl_opacity_logits, sc.lvl_sh_dc,  \

@@ -317,6 +317,29 @@ def test_foveated_matches_oracle(tile, rings, band):
     np.testing.assert_allclose(lvn[0, vis, :, 0:3], ref_p["lvl_color"].transpose(1, 0, 2)[vis], atol=2e-5)
 
 
+@pytest.mark.parametrize("tile", [8, 16, 32])
+def test_render_fwd_one_call_equals_stages(tile):
+    """The plain one-call render (its projection counts each entry's tiles and
+    the binning compacts what it wrote) gives exactly the splats, keys, tile
+    ranges, image, final T and contributor counts of gs_project +
+    gs_bin_sort + gs_rasterize_fwd, over views of mixed sizes."""
+    g = gs()
+    sc = scene_small(seed=57, n=4000)
+    cams = two_views() + [scenegen.pinhole(213, 121, 60.0, t=(0.0, 0.05, 1.8))]
+    say(f"render_fwd one call, tile {tile}")
+    C, splats, bs, out = _raster_case(g, sc, cams, tile, dominated=False)
+    S = g.SceneTensors(sc)
+    one = g.gs_render_fwd(S, C, tile, key_capacity=int(bs["num_keys"].item()) + 5)
+    torch.cuda.synchronize()
+    nk = int(bs["num_keys"].item())
+    assert int(one["num_keys"].item()) == nk
+    assert torch.equal(one["splats"], splats)
+    assert torch.equal(one["vals"][:nk], bs["vals"][:nk])
+    assert torch.equal(one["ranges"], bs["ranges"])
+    for k in ("image", "final_T", "n_contrib"):
+        assert torch.equal(one[k], out[k]), k
+
+
 @pytest.mark.parametrize("tile,eyes", [(16, 2), (8, 3), (32, 3)])
 def test_render_foveated_one_call_equals_stages(tile, eyes):
     """The one-call render (its projection counts each entry's kept tiles and
