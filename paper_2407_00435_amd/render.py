@@ -27,15 +27,18 @@ class GaussianRender(torch.autograd.Function):
         scene = B.SceneTensors(means=means.detach(), log_scales=log_scales.detach(),
                                quats=quats.detach(), opacity_logits=opacity_logits.detach(),
                                sh=sh.detach(), sh_degree=sh_degree)
-        splats = B.gs_project(scene, cams, tile_size)
         plan = ("plain", scene.n, tile_size)
-        cap = key_capacity if key_capacity is not None else cams.planned_capacity(plan, splats)
-        bs = B.gs_bin_sort(splats, scene.n, cams, tile_size, key_capacity=cap)
-        out = B.gs_rasterize_fwd(splats, scene.n, cams, tile_size, bs["vals"], bs["ranges"], bg)
+        if key_capacity is not None:
+            cap = key_capacity
+        else:
+            # the first render of these cameras projects once to size the capacity
+            planned = plan in cams.key_capacity
+            cap = cams.planned_capacity(plan, None if planned else B.gs_project(scene, cams, tile_size))
+        out = B.gs_render_fwd(scene, cams, tile_size, bg, key_capacity=cap)
         ctx.scene, ctx.cams, ctx.tile, ctx.bg = scene, cams, tile_size, bg
-        ctx.save_for_backward(splats, bs["vals"], bs["ranges"], out["final_T"], out["n_contrib"])
-        ctx.num_keys, ctx.capacity = bs["num_keys"], bs["capacity"]
-        ctx.watch = cams.watch(plan, bs["num_keys"], bs["capacity"]) if key_capacity is None else None
+        ctx.save_for_backward(out["splats"], out["vals"], out["ranges"], out["final_T"], out["n_contrib"])
+        ctx.num_keys, ctx.capacity = out["num_keys"], out["capacity"]
+        ctx.watch = cams.watch(plan, out["num_keys"], out["capacity"]) if key_capacity is None else None
         return out["image"]
 
     @staticmethod
