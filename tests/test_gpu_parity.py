@@ -340,6 +340,25 @@ def test_render_fwd_one_call_equals_stages(tile):
         assert torch.equal(one[k], out[k]), k
 
 
+@pytest.mark.parametrize("n", [700_000, 1_400_000, 2_700_000])
+def test_render_fwd_one_call_compaction_block_sizes(n):
+    """Entry counts on each side of the compaction's block-size thresholds
+    (4096, 8192 and 16384 entries per block): the one-call keys, ranges and
+    image equal those of the counting pass (blocks of 4096)."""
+    g = gs()
+    sc = scene_small(seed=59, n=n, deg=0)
+    cams = [scenegen.pinhole(320, 240, 60.0, t=(0.0, 0.0, 4.0))]
+    say(f"render_fwd one call, {n} entries")
+    C, splats, bs, out = _raster_case(g, sc, cams, 16, dominated=False)
+    one = g.gs_render_fwd(g.SceneTensors(sc), C, 16, key_capacity=int(bs["num_keys"].item()) + 5)
+    torch.cuda.synchronize()
+    nk = int(bs["num_keys"].item())
+    assert int(one["num_keys"].item()) == nk
+    assert torch.equal(one["vals"][:nk], bs["vals"][:nk])
+    assert torch.equal(one["ranges"], bs["ranges"])
+    assert torch.equal(one["image"], out["image"])
+
+
 @pytest.mark.parametrize("tile,eyes", [(16, 2), (8, 3), (32, 3)])
 def test_render_foveated_one_call_equals_stages(tile, eyes):
     """The one-call render (its projection counts each entry's kept tiles and
