@@ -312,8 +312,10 @@ __device__ __forceinline__ uint64_t block_lookback(uint64_t *__restrict__ lb, in
 // The stable compaction of one block's entries with keys (item j of thread t
 // is entry base + j * COUNT_THREADS + t; bal[j] = the wave's ballot of item j
 // having keys): (depth bits, entry) to (dkey, dval) at the block's offset,
-// found by lookback, and the depth digits of every sort pass into hist.
-// Called by every thread of the block after s_h is zeroed.
+// found by lookback, and the depth digits of every sort pass into hist.  The
+// per-(item, wave) counts are scanned once in entry order (item-major) by
+// the first IT waves, so each item's offset is one LDS read.  Called by
+// every thread of the block after s_h is zeroed.
 template <int IT>
 __device__ __forceinline__ void compact_block(const uint64_t (&bal)[IT], const uint32_t (&key)[IT],
                                               int64_t base, int64_t blk, uint64_t *__restrict__ lb,
@@ -323,41 +325,49 @@ __device__ __forceinline__ void compact_block(const uint64_t (&bal)[IT], const u
                                               uint64_t *s_off)
 {
     constexpr int W = COUNT_THREADS / 64;
+    constexpr int NF = IT * W;  // (item, wave) counts
+    static_assert(NF % 64 == 0 && NF <= COUNT_THREADS, "whole waves scan the counts");
+    __shared__ uint32_t s_wp[NF / 64];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     if (lane == 0) {
 #pragma unroll
         for (int j = 0; j < IT; ++j) s_w[j][wave] = (uint32_t)__popcll(bal[j]);
     }
     __syncthreads();
+    uint32_t *flat = &s_w[0][0];  // index j * W + w
+    if (threadIdx.x < NF) {
+        const uint32_t x = flat[threadIdx.x];
+        const uint32_t inc = wave_incl_scan(x);
+        flat[threadIdx.x] = inc - x;
+        if (lane == 63) s_wp[wave] = inc;
+    }
+    __syncthreads();
     if (threadIdx.x == 0) {
         uint64_t tot = 0;
-        for (int j = 0; j < IT; ++j)
-            for (int w = 0; w < W; ++w) tot += s_w[j][w];
+        for (int q = 0; q < NF / 64; ++q) {
+            const uint32_t c = s_wp[q];
+            s_wp[q] = (uint32_t)tot;
+            tot += c;
+        }
         const uint64_t pre = block_lookback(lb, blk, tot);
         *s_off = pre;
         if (blk == (int64_t)gridDim.x - 1) *total = pre + tot;
     }
     __syncthreads();
-    // entries with keys in entry order: item-major within the block
-    uint64_t run = *s_off;
+    // entries with keys in entry order
+    const uint64_t off = *s_off;
 #pragma unroll
     for (int j = 0; j < IT; ++j) {
-        uint32_t wpre = 0, tot = 0;
-        for (int w = 0; w < W; ++w) {
-            const uint32_t x = s_w[j][w];
-            if (w < wave) wpre += x;
-            tot += x;
-        }
         if ((bal[j] >> lane) & 1ull) {
+            const int f = j * W + wave;
             const int64_t e = base + (int64_t)j * COUNT_THREADS + threadIdx.x;
-            const uint64_t pos = run + wpre + (uint32_t)__popcll(bal[j] & lanemask_lt());
+            const uint64_t pos = off + s_wp[f >> 6] + flat[f] + (uint32_t)__popcll(bal[j] & lanemask_lt());
             const uint32_t k = key[j];
             dkey[pos] = k;
             dval[pos] = (uint32_t)e;
 #pragma unroll
             for (int p = 0; p < 4; ++p) atomicAdd(&s_h[p][(k >> (8 * p)) & 255u], 1u);
         }
-        run += tot;
     }
     __syncthreads();
     for (int q = threadIdx.x; q < 4 * 256; q += COUNT_THREADS) {
