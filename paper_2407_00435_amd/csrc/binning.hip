@@ -844,18 +844,22 @@ k_coarse_emit(const uint4 *__restrict__ rec_s, const uint32_t *__restrict__ cc_s
         if (lane == 63) s_w[j][wave] = x[j];
     }
     __syncthreads();
-    uint64_t run = boff[blockIdx.x];
+    // the (item, wave) totals scanned once in entry order (item-major) by
+    // the first wave, so that an item's offset is one LDS read
+    static_assert(GATHER_ITEMS * W <= 64, "one wave scans the (item, wave) totals");
+    uint32_t *flat = &s_w[0][0];  // index j * W + w
+    if (wave == 0) {
+        const uint32_t v = lane < GATHER_ITEMS * W ? flat[lane] : 0u;
+        const uint32_t inc = wave_incl_scan(v);
+        if (lane < GATHER_ITEMS * W) flat[lane] = inc - v;
+    }
+    __syncthreads();
+    const uint64_t run = boff[blockIdx.x];
 #pragma unroll
     for (int j = 0; j < GATHER_ITEMS; ++j) {
-        uint64_t pw = 0, tw = 0;
-        for (int w = 0; w < W; ++w) {
-            const uint32_t vw = s_w[j][w];
-            if (w < wave) pw += vw;
-            tw += vw;
-        }
         const int64_t r = base + (int64_t)j * GATHER_THREADS + threadIdx.x;
         const uint32_t cnt = cc_count(c[j]);
-        const uint64_t pos = run + pw + x[j] - cnt;
+        const uint64_t pos = run + flat[j * W + wave] + x[j] - cnt;
         if (cnt) {
             const int v = (int)(q[j].w >> 8);
             if (c[j] >> 31) {
@@ -875,7 +879,6 @@ k_coarse_emit(const uint4 *__restrict__ rec_s, const uint32_t *__restrict__ cc_s
                                           n_tiles, ck, cv, pos, &dc);
             }
         }
-        run += tw;
     }
     __syncthreads();
     for (int q = threadIdx.x; q < shape.passes * radix; q += GATHER_THREADS)
