@@ -470,10 +470,10 @@ k_count(const gs_splat *__restrict__ splats, int n, const gs_camera *__restrict_
     for (int j = 0; j < COUNT_ITEMS; ++j) {
         const int64_t e = base + (int64_t)j * COUNT_THREADS + threadIdx.x;
         if (e < E) {
-            if (cnt[j])
-                rec[e] = make_uint4((uint32_t)r[j].tx0 | ((uint32_t)r[j].ty0 << 16),
-                                    (uint32_t)r[j].tx1 | ((uint32_t)r[j].ty1 << 16), cnt[j],
-                                    (uint32_t)(FILT ? mq[j] : 255));
+            // every entry's record is written (whole cache lines), read only for entries with keys
+            rec[e] = make_uint4((uint32_t)r[j].tx0 | ((uint32_t)r[j].ty0 << 16),
+                                (uint32_t)r[j].tx1 | ((uint32_t)r[j].ty1 << 16), cnt[j],
+                                (uint32_t)(FILT ? mq[j] : 255));
             if (hits_out) hits_out[e] = cnt[j];
         }
         bal[j] = ballot64(e < E && cnt[j] > 0);

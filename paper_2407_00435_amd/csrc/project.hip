@@ -189,6 +189,7 @@ k_project(const float *__restrict__ means, const float *__restrict__ log_scales,
             if (LEVELS)
                 for (int t = 0; t < L; ++t) lvl_out[e * L + t] = z;
             if (BIN) {
+                pb.rec[e] = make_uint4(0u, 0u, 0u, 0u);
                 pb.kw[e] = KEY_NONE;
                 if (pb.hits) pb.hits[e] = 0u;
             }
@@ -257,9 +258,9 @@ k_project(const float *__restrict__ means, const float *__restrict__ log_scales,
         if (BIN) {
             const uint32_t cnt =
                 !LEVELS ? tiles : (ne ? s11 - (lx ? s01 : 0u) - (ly ? s10 : 0u) + (lx && ly ? s00 : 0u) : 0u);
-            if (cnt)
-                pb.rec[e] = make_uint4((uint32_t)rect.tx0 | ((uint32_t)rect.ty0 << 16),
-                                       (uint32_t)rect.tx1 | ((uint32_t)rect.ty1 << 16), cnt, (uint32_t)qm);
+            // every entry's record is written (whole cache lines), read only for entries with keys
+            pb.rec[e] = make_uint4((uint32_t)rect.tx0 | ((uint32_t)rect.ty0 << 16),
+                                   (uint32_t)rect.tx1 | ((uint32_t)rect.ty1 << 16), cnt, (uint32_t)qm);
             pb.kw[e] = cnt ? __float_as_uint(uz) : KEY_NONE;
             if (pb.hits) pb.hits[e] = cnt;
         }
