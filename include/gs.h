@@ -337,7 +337,9 @@ int gs_project_bwd_levels(gs_ctx *ctx, const gs_scene *scene, const gs_camera *c
  * Intermediate buffers live in the workspace; size it with
  * gs_render_workspace_bytes().  num_keys (device, uint64) receives the
  * required key count as in gs_bin_sort (outputs are invalid if it exceeds
- * key_capacity). */
+ * key_capacity).  The projection also counts each entry's kept tiles, so
+ * the binning does not read the splat records again; image and key count
+ * equal those of the stage calls. */
 size_t gs_render_workspace_bytes(gs_ctx *ctx, const gs_camera *cams_host, int n_views, int32_t n,
                                  int n_levels, int tile_size, uint64_t key_capacity);
 int gs_render_foveated(gs_ctx *ctx, const gs_scene *scene, const gs_camera *cams_host,
@@ -349,7 +351,9 @@ int gs_render_foveated(gs_ctx *ctx, const gs_scene *scene, const gs_camera *cams
 /* One-call plain render of n_views views: projection, binning and sort,
  * compositing.  Same workspace rule as gs_render_foveated (n_levels = 0).
  * splats, vals, tile_ranges, final_T, n_contrib are outputs kept for a
- * backward pass (device; n_contrib/final_T [n_pixels], vals [key_capacity]). */
+ * backward pass (device; n_contrib/final_T [n_pixels], vals [key_capacity]),
+ * equal to those of gs_project + gs_bin_sort + gs_rasterize_fwd (the
+ * projection also counts each entry's tiles). */
 int gs_render_fwd(gs_ctx *ctx, const gs_scene *scene, const gs_camera *cams_host, const gs_camera *cams_dev,
                   int n_views, int tile_size, const float *bg, gs_splat *splats,
                   uint32_t *vals, uint32_t *tile_ranges, uint64_t key_capacity,
