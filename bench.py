@@ -44,10 +44,10 @@ FLOPS_PER_BLEND_BWD = 44
 # averaged over the dispatches), each scaled by the ratio of known bytes to
 # the same counter on a plain device copy (bench.py --copy-probe).  Valid
 # only for the kernel sources they were taken on (sha256 below).
-TRAFFIC = {"kernel": "k_raster_fov", "fetch_kib": 360096.1, "write_kib": 88894.3, "fetch_scale": 2.0,
+TRAFFIC = {"kernel": "k_raster_fov", "fetch_kib": 360724.9, "write_kib": 88878.7, "fetch_scale": 2.0,
            "write_scale": 1.0, "sha256": "66dce30ac61ade92b2d34b0355baebc59c3d18623c6fb84d8f264e095baaf491"}
 # The same for the compositing reverse on the 1280x720 1M-Gaussian frame.
-TRAFFIC_BWD = {"kernel": "k_raster_bwd", "fetch_kib": 55523.0, "write_kib": 29395.7, "fetch_scale": 2.0,
+TRAFFIC_BWD = {"kernel": "k_raster_bwd", "fetch_kib": 55507.6, "write_kib": 29395.7, "fetch_scale": 2.0,
                "write_scale": 1.0, "sha256": "66dce30ac61ade92b2d34b0355baebc59c3d18623c6fb84d8f264e095baaf491"}
 
 def kernel_sha():
