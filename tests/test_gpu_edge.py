@@ -9,6 +9,8 @@
 - The foveated path on the tiny views (the gaze inside each), binning
   bit-exact with the level filter, images within the envelope; and an empty
   foveated scene renders the background.
+- Points that are all behind the cameras: both one-call renders give no
+  keys and the background.
 """
 import numpy as np
 import pytest
@@ -150,3 +152,27 @@ def test_foveated_tiny_views_and_empty_scene():
     assert int(num0.item()) == 0
     for im in image_views(img0, TINY):
         np.testing.assert_array_equal(im, np.broadcast_to(np.float32(bg), im.shape))
+
+
+def test_one_call_renders_with_every_point_behind_the_camera():
+    """Points exist but none is in front of any camera: the one-call renders
+    (whose projection writes every entry's key word as 'no keys') give zero
+    keys and the background, as the stage calls do."""
+    g = gs()
+    sc = scene(97, fr=4)
+    cams = [scenegen.pinhole(40, 30, 60.0, t=(0.0, 0.0, -10.0)), scenegen.pinhole(33, 17, 60.0, t=(0.1, 0.0, -12.0))]
+    C, S = g.Cameras(cams), g.SceneTensors(sc)
+    bg = (0.2, 0.4, 0.6)
+    say("every point behind the camera")
+    plain = g.gs_render_fwd(S, C, 16, bg=bg, key_capacity=64)
+    fov = [scenegen.Fovea(20.0, 15.0), scenegen.Fovea(16.0, 8.0)]
+    img, num, _ = g.gs_render_foveated(S, C, fov, 16, bg=bg, key_capacity=64)
+    torch.cuda.synchronize()
+    assert int(plain["num_keys"].item()) == 0 and int(num.item()) == 0
+    sizes = [(c.width, c.height) for c in cams]
+    for im in image_views(plain["image"], sizes):
+        np.testing.assert_array_equal(im, np.broadcast_to(np.float32(bg), im.shape))
+    # band pixels blend two background values, (1 - w) bg + w bg: within an ulp of bg
+    for im in image_views(img, sizes):
+        np.testing.assert_allclose(im, np.broadcast_to(np.float32(bg), im.shape), rtol=0, atol=2e-7)
+    assert torch.all(plain["final_T"] == 1.0) and torch.all(plain["n_contrib"] == 0)
