@@ -836,7 +836,7 @@ int gs_render_foveated(gs_ctx *ctx, const gs_scene *scene, const gs_camera *cams
                         scene->qbound, L, rb.vals, nullptr, key_capacity, rb.ranges, nullptr, num_keys, bs,
                         ctx->tn.coarse_packed, status, st, BIN_SETUP);
     if (e != hipSuccess) return hip_fail(e, "gs_render_foveated (binning set-up)");
-    const ProjBin pb = bin_counting_args(bs, tiles, nullptr);
+    const ProjBin pb = bin_counting_args(bs, tiles);
     e = launch_project(*scene, cams_dev, n_eyes, tile_size, rb.splats, rb.lvl, st, &pb);
     if (e != hipSuccess) return hip_fail(e, "gs_render_foveated (projection)");
     e = launch_bin_sort(rb.splats, scene->n, cams_dev, cams_host, n_eyes, tiles, tile_size, rb.tile_level,
@@ -889,7 +889,7 @@ int gs_render_fwd(gs_ctx *ctx, const gs_scene *scene, const gs_camera *cams_host
                                    nullptr, 4, vals, nullptr, key_capacity, tile_ranges, nullptr, num_keys, bs,
                                    ctx->tn.coarse_packed, status, st, BIN_SETUP);
     if (e != hipSuccess) return hip_fail(e, "gs_render_fwd (binning set-up)");
-    const ProjBin pb = bin_counting_args(bs, tiles, nullptr);
+    const ProjBin pb = bin_counting_args(bs, tiles);
     e = launch_project(*scene, cams_dev, n_views, tile_size, splats, nullptr, st, &pb);
     if (e != hipSuccess) return hip_fail(e, "gs_render_fwd (projection)");
     e = launch_bin_sort(splats, scene->n, cams_dev, cams_host, n_views, tiles, tile_size, nullptr, nullptr, 4, vals,

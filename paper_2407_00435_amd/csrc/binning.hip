@@ -1352,9 +1352,9 @@ hipError_t launch_status_views(const uint64_t *req_cap, const uint64_t *nums, in
     return hipGetLastError();
 }
 
-ProjBin bin_counting_args(const BinScratch &bs, int64_t n_tiles, uint32_t *hits_out)
+ProjBin bin_counting_args(const BinScratch &bs, int64_t n_tiles)
 {
-    return ProjBin{bs.sat, bs.bbox, bs.vtab, n_tiles, bs.rec, bs.dkey_b, hits_out};
+    return ProjBin{bs.sat, bs.bbox, bs.vtab, n_tiles, bs.rec, bs.dkey_b};
 }
 
 hipError_t launch_bin_sort(const gs_splat *splats, int n, const gs_camera *cams_dev,

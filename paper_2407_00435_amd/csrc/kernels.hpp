@@ -9,10 +9,9 @@
 // projection
 // The binning's counting step folded into the projection (the one-call
 // renders): per entry e = v n + i, the count of its tiles (with level
-// versions: kept after the level filter), its rectangle record (rec[e],
-// entries with keys only), its depth key or KEY_NONE (kw[e]), and optionally
-// the count (hits[e]).  The tables (sat, bbox, vtab) are the binning's,
-// built before.
+// versions: kept after the level filter) in its rectangle record (rec[e]),
+// and its depth key or KEY_NONE (kw[e]).  The tables (sat, bbox, vtab) are
+// the binning's, built before.
 constexpr uint32_t KEY_NONE = 0xFFFFFFFFu;  // no keys: never the bits of a positive depth
 struct ProjBin {
     const uint32_t *sat;
@@ -21,7 +20,6 @@ struct ProjBin {
     int64_t n_tiles;
     uint4 *rec;
     uint32_t *kw;
-    uint32_t *hits;
 };
 hipError_t launch_project(const gs_scene &sc, const gs_camera *cams_dev, int V, int T,
                           gs_splat *out, float *lvl_rgba, hipStream_t st, const ProjBin *pb = nullptr);
@@ -178,7 +176,7 @@ hipError_t launch_bin_sort(const gs_splat *splats, int n, const gs_camera *cams_
                            BinMode mode = BIN_ALL);
 // The projection's counting arguments over a binning scratch (kw in the depth
 // sort's second key buffer, free until the sort's first pass).
-ProjBin bin_counting_args(const BinScratch &bs, int64_t n_tiles, uint32_t *hits_out);
+ProjBin bin_counting_args(const BinScratch &bs, int64_t n_tiles);
 
 // Status of a binning done view by view: status[0] = V * the largest per-view
 // required key count (the capacity that fits every view when each has

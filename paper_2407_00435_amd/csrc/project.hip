@@ -191,7 +191,6 @@ k_project(const float *__restrict__ means, const float *__restrict__ log_scales,
             if (BIN) {
                 pb.rec[e] = make_uint4(0u, 0u, 0u, 0u);
                 pb.kw[e] = KEY_NONE;
-                if (pb.hits) pb.hits[e] = 0u;
             }
             continue;
         }
@@ -262,7 +261,6 @@ k_project(const float *__restrict__ means, const float *__restrict__ log_scales,
             pb.rec[e] = make_uint4((uint32_t)rect.tx0 | ((uint32_t)rect.ty0 << 16),
                                    (uint32_t)rect.tx1 | ((uint32_t)rect.ty1 << 16), cnt, (uint32_t)qm);
             pb.kw[e] = cnt ? __float_as_uint(uz) : KEY_NONE;
-            if (pb.hits) pb.hits[e] = cnt;
         }
     }
 }
